@@ -1,0 +1,16 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/benchmark and the CPU oracle.
+
+This package holds input data only: simplicial meshes of the unit square / unit cube,
+vertex jitter, per-element material coefficients, polynomial degrees and point-source
+locations.  It contains none of the discretisation's arithmetic (no basis, quadrature,
+local matrices or solves), so that the oracle and the GPU library stay independent.
+"""
+from .meshes import (  # noqa: F401
+    Problem,
+    unit_square_tris,
+    kuhn_cube_tets,
+    five_tet_box,
+    jitter_vertices,
+    make_problem,
+    CONFIGS,
+)
