@@ -1,0 +1,233 @@
+/*
+ * hdg.h -- C ABI of the MI355X (gfx950) HDG condensation library (libhdg.so).
+ *
+ * The library implements the element-local part of an implicit hybridised DG stage
+ * (Fernandez, Christophe, Terrana, Nguyen, Peraire, "Hybridized discontinuous Galerkin
+ * methods for wave propagation", arXiv:1807.00086):
+ *
+ *   section 2.3   the semi-discrete problem is an index-1 DAE  M du/dt + f(u,v,t) = 0,
+ *                 g(u,v,t) = 0, advanced by DIRK stages (section 2.3.2);
+ *   section 2.4.1 every stage is a linear system [A B; C D] (u, lam) = (f, g) whose block
+ *                 A is block-diagonal over elements; the local unknowns are eliminated,
+ *                 K = D - C A^{-1} B, r = g - C A^{-1} f, the global trace system
+ *                 K lam = r is solved, and u is recovered from the first block row.
+ *
+ * Physics: acoustics (velocity v, pressure p; trace p_hat), linear elastodynamics
+ * (velocity, symmetric stress; trace v_hat; section 4.1), Maxwell (E, H; tangential
+ * trace E_hat^t; section 5.2).  The orderings are listed below; the local equations and
+ * sign conventions of each physics are stated in csrc/physics.h.
+ *
+ * Conventions shared by every entry point
+ *  - Reference simplex: vertices 0, e_1, .., e_d; local face f is opposite local vertex f.
+ *  - Basis: orthonormal PKD (Dubiner) polynomials of degree k on the reference simplex,
+ *    ordered by total degree; trace basis: the same on the reference face, mapped from the
+ *    face's vertices sorted by global id (so both neighbours share it).
+ *  - Global faces are numbered in lexicographic order of their sorted global vertex ids.
+ *  - Local dofs: element-major, then field component, then basis index, then rhs (r
+ *    innermost when nrhs > 1).  Component orders:
+ *      acoustic [v_1..v_d, p];  elastic [s11,s22,s33,s23,s13,s12, v_1,v_2,v_3];
+ *      maxwell [H_1,H_2,H_3, E_1,E_2,E_3].
+ *  - Trace dofs: face-major, then component, then face basis index, then rhs.
+ *    Maxwell trace components are coefficients along the face frame (t1, t2):
+ *    t1 = unit(X_g1 - X_g0), t2 = n_F x t1, n_F = unit((X_g1-X_g0) x (X_g2-X_g0)).
+ *  - Device pointers are borrowed for the duration of the call (stream-ordered on the
+ *    context's stream).  Host pointers are read during the call only.
+ *  - Every entry point returns an hdg_status; no exception crosses the ABI.  A failed call
+ *    leaves a message retrievable with hdg_last_error().
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int hdg_status;
+enum {
+    HDG_OK = 0,
+    HDG_E_ARG = 1,         /* invalid argument (null pointer, size or enum out of range)   */
+    HDG_E_MESH = 2,        /* inverted element, non-manifold face, degree out of range      */
+    HDG_E_ALLOC = 3,       /* device allocation failed                                      */
+    HDG_E_HIP = 4,         /* a HIP runtime call failed                                     */
+    HDG_E_SINGULAR = 5,    /* zero / non-finite pivot in a local factorisation              */
+    HDG_E_NOCONV = 6,      /* Krylov solve or refinement did not reach its tolerance        */
+    HDG_E_STATE = 7,       /* call order violated (e.g. recover before condense)            */
+    HDG_E_UNSUPPORTED = 8  /* configuration not built into this library                     */
+};
+
+enum hdg_physics { HDG_ACOUSTIC = 0, HDG_ELASTIC = 1, HDG_MAXWELL = 2 };
+enum hdg_precision {
+    HDG_FP64 = 0,          /* local factorisations, Z and K_e in FP64                       */
+    HDG_MIXED_FP32 = 1     /* local factorisations, Z and K_e in FP32, FP64 refinement      */
+};
+enum hdg_scheme { HDG_BACKWARD_EULER = 0, HDG_DIRK33 = 1 };
+
+typedef struct hdg_ctx hdg_ctx;
+
+typedef struct {
+    int dim;                    /* 2 (triangles) or 3 (tetrahedra)                            */
+    int64_t n_vert;
+    const double* xyz;          /* host [n_vert][dim]                                         */
+    int64_t n_elem;
+    const int64_t* elem_vert;   /* host [n_elem][dim+1], positively oriented                  */
+    const int8_t* degree;       /* host [n_elem] polynomial degree (1..5); NULL: options.k     */
+} hdg_mesh_desc;
+
+typedef struct {
+    int physics;                /* enum hdg_physics                                           */
+    const double* elem_par;     /* host [n_elem][3]: acoustic (rho, c, -), elastic
+                                   (rho, lambda, mu), maxwell (eps, mu, sigma)               */
+    double stab_scale;          /* multiplies tau = 1/(rho c) | S = 2 rho c_s | tau = 2       */
+} hdg_phys_desc;
+
+typedef struct {
+    int precision;              /* enum hdg_precision                                         */
+    int k;                      /* uniform degree when mesh.degree == NULL                    */
+    int nrhs;                   /* right-hand sides solved together (1..32)                   */
+    double krylov_tol;          /* relative residual of the FP64 trace solve                  */
+    int krylov_maxit;
+    double refine_tol;          /* mixed precision: relative FP64 residual of the full system */
+    int refine_maxit;
+} hdg_options;
+
+/* Query keys for hdg_query. */
+enum hdg_query_key {
+    HDG_Q_N_ELEM = 0, HDG_Q_N_FACES = 1, HDG_Q_N_BFACES = 2,
+    HDG_Q_N_LOCAL_DOFS = 3,     /* sum over elements of n_e (without the nrhs factor)        */
+    HDG_Q_N_TRACE_DOFS = 4,     /* sum over faces of m_hat dim P_kF(face)                   */
+    HDG_Q_N_VOL_POINTS = 5,     /* total volume quadrature points (projection helper)       */
+    HDG_Q_N_BND_POINTS = 6,     /* total boundary-face quadrature points                    */
+    HDG_Q_LAST_ITERS = 7,       /* Krylov iterations of the last trace solve                 */
+    HDG_Q_LAST_REFINE = 8,      /* refinement iterations of the last mixed recover          */
+    HDG_Q_M_LOCAL = 9,          /* field components per element                             */
+    HDG_Q_M_TRACE = 10          /* trace components per face                                */
+};
+
+/*
+ * hdg_init_mesh -- build the mesh skeleton and reference tables and upload them.
+ * Sections 2.1-2.2 (mesh, faces E_h^I / E_h^B, spaces V_h^k and M_h^k).  All host arrays
+ * are copied; the context owns every device buffer it allocates.  Validation (|J| <= 0,
+ * a face shared by more than two elements, degree outside 1..5, nrhs outside 1..32)
+ * fails with HDG_E_MESH / HDG_E_ARG before any device work.  `stream` is a hipStream_t
+ * (NULL: the default stream); every later call is ordered on it.  Faces with one
+ * neighbour are Dirichlet faces.
+ */
+hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* mesh, const hdg_phys_desc* phys,
+                         const hdg_options* opts, void* stream);
+
+/* hdg_query -- integer facts about the discretisation (see enum hdg_query_key). */
+hdg_status hdg_query(const hdg_ctx* ctx, int key, int64_t* value);
+
+/*
+ * hdg_condense -- element-local Galerkin solve and static condensation (section 2.4.1).
+ * For every element: form A, B, C, D of the stage system with stage coefficient `a`
+ * (A = a*Mw + L), factor A without pivoting (the flux-like leading block is
+ * block-diagonal and is eliminated in closed form, the rest by a dense LU), compute
+ * Z = A^{-1} B, z = A^{-1} f, K_e = D - C Z, r_e = -C z, and assemble the global trace
+ * system in face-block sparse rows with the Dirichlet faces eliminated.
+ *   a        stage coefficient d_ii / dt (> 0)
+ *   f_loc    device [n_local_dofs][nrhs] FP64 local right-hand side (a Mw u* + sources)
+ *   lam_bnd  device [n_trace_dofs][nrhs] FP64; only boundary-face entries are read
+ *            (L2 projection of the Dirichlet data, see hdg_project_boundary)
+ * Asynchronous; a zero or non-finite pivot is reported by the next synchronising call
+ * (hdg_trace_solve / hdg_recover) as HDG_E_SINGULAR.
+ */
+hdg_status hdg_condense(hdg_ctx* ctx, double a, const double* f_loc, const double* lam_bnd);
+
+/*
+ * hdg_trace_solve -- solve the assembled trace system K lam = r in FP64 (section 2.4.2;
+ * K is symmetric and definite for every physics here, so preconditioned conjugate
+ * gradients replace GMRES; block-Jacobi preconditioner).
+ *   lambda   device [n_trace_dofs][nrhs] in: initial guess (boundary entries are reset to
+ *            the Dirichlet values), out: solution
+ *   iters    host, may be NULL: iterations used
+ *   relres   host, may be NULL: final max over rhs of ||r - K lam|| / ||r||
+ * Synchronises the stream.  HDG_E_NOCONV if krylov_tol is not met within krylov_maxit.
+ */
+hdg_status hdg_trace_solve(hdg_ctx* ctx, double* lambda, int* iters, double* relres);
+
+/*
+ * hdg_recover -- local fields from the trace: u_e = z_e - Z_e lam_e (first block row of
+ * the stage system).  In HDG_MIXED_FP32 mode the result is then refined: the residual of
+ * the full uncondensed system is evaluated in FP64 from the element operators, corrected
+ * through the FP32 factors and a new FP64 trace solve, until it is below refine_tol
+ * relative to the right-hand side (lambda is refined in place as well).
+ *   lambda   device [n_trace_dofs][nrhs] FP64 (in; in/out in mixed mode)
+ *   u_loc    device [n_local_dofs][nrhs] FP64 out
+ * HDG_E_NOCONV when refinement stalls.
+ */
+hdg_status hdg_recover(hdg_ctx* ctx, double* lambda, double* u_loc);
+
+/*
+ * hdg_step -- advance u^n -> u^{n+1} by backward Euler or DIRK(3,3) (section 2.3.2,
+ * stiffly accurate, so u^{n+1} is the last stage).  Per stage i:
+ * u*_i = u^n - (1/d_ii) sum_{j<i} d_ij (U_j - u^n), f = a Mw u*_i with a = d_ii / dt, then
+ * condense, trace solve, recover.
+ *   u          device [n_local_dofs][nrhs] in: u^n, out: u^{n+1}
+ *   lambda     device [n_trace_dofs][nrhs] in: initial guess, out: trace of the last stage
+ *   lam_bnd    device [n_stages][n_trace_dofs][nrhs] Dirichlet data at t + c_i dt
+ *   src        device [n_local_dofs][nrhs] or NULL: time-independent tested source
+ */
+hdg_status hdg_step(hdg_ctx* ctx, double t, double dt, int scheme, double* u, double* lambda,
+                    const double* lam_bnd, const double* src);
+
+/* Stage glue: f = a * Mw * u element by element (device pointers, FP64). */
+hdg_status hdg_apply_mass(hdg_ctx* ctx, double a, const double* u, double* f);
+
+/*
+ * Projection helpers (L2 projections that fix initial data and Dirichlet traces).
+ * hdg_volume_points: host out [n_vol_points][dim] physical quadrature points, element-major.
+ * hdg_project_volume: vals host [n_vol_points][m_local] field values at those points ->
+ *   u host [n_local_dofs] (nrhs = 1 layout) coefficients u_i = (val, phi_i)_K / |J_K|.
+ * hdg_boundary_points: host out [n_bnd_points][dim], boundary faces in face order.
+ * hdg_project_boundary: vals host [n_bnd_points][dim or 1] -> lam host [n_trace_dofs]
+ *   (zero on interior faces); Maxwell takes the full E vector and keeps its tangential
+ *   part along (t1, t2).
+ */
+hdg_status hdg_volume_points(const hdg_ctx* ctx, double* pts);
+hdg_status hdg_project_volume(const hdg_ctx* ctx, const double* vals, double* u);
+hdg_status hdg_boundary_points(const hdg_ctx* ctx, double* pts);
+hdg_status hdg_project_boundary(const hdg_ctx* ctx, const double* vals, double* lam);
+
+/*
+ * hdg_point_sources: host pts [n_src][dim] -> host f [n_local_dofs][n_src]: column s holds
+ * phi_i(x_s) in the pressure block of the element containing x_s (acoustics only).
+ */
+hdg_status hdg_point_sources(const hdg_ctx* ctx, int n_src, const double* pts, double* f);
+
+/*
+ * hdg_element_data -- copy per-element results of the last condense to the host as FP64
+ * (inspection / parity testing).  which: 0 = K_e [t][t], 1 = r_e [t][nrhs],
+ * 2 = Z [n][t], 3 = z [n][nrhs].  Elements [e0, e0+count) must share one degree;
+ * out holds count * block doubles.
+ */
+hdg_status hdg_element_data(hdg_ctx* ctx, int which, int64_t e0, int64_t count, double* out);
+
+/* Timing of the last call of each kind, milliseconds (HIP events on the context stream):
+ * which: 0 condense, 1 assemble, 2 trace solve, 3 recover, 4 refinement element work,
+ * 5 refinement trace solves. */
+hdg_status hdg_last_timing(const hdg_ctx* ctx, int which, double* ms);
+
+/*
+ * hdg_reference_table -- host-only copy of a reference-element table (no device needed):
+ * which = 0: Sr[r][i][j] = int phi_i d phi_j / d xi_r (dim x N x N); 1: Mf[f][i][j] =
+ * int_{face f} phi_i phi_j per unit reference-face measure ((dim+1) x N x N); 2: the symmetric
+ * products Sr_r Sr_s^T (+ transpose for r < s); 3: E[f][p][i][l] = int_{face f} phi_i psi_l
+ * with the face parametrised from vertex permutation p, face degree kF.  Writes at most cap
+ * doubles; returns the count written or minus an hdg_status.
+ */
+int64_t hdg_reference_table(int dim, int k, int kF, int which, double* out, int64_t cap);
+
+/* hdg_destroy -- free every buffer the context owns.  NULL-safe. */
+void hdg_destroy(hdg_ctx* ctx);
+
+/* Message of the last failed call on this context ("" if none); ctx may be NULL for
+ * failures of hdg_init_mesh, which are kept per thread. */
+const char* hdg_last_error(const hdg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDG_H */

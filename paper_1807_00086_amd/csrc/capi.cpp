@@ -1,0 +1,590 @@
+// C ABI entry points (host).  Argument validation, device buffers, call ordering and the
+// FP64 refinement / time-stepping loops; every arithmetic step on the element and trace data
+// runs in the HIP kernels of condense_*.hip, trace.hip and stage.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace hdg {
+int launch_condense_acoustic(hdg_ctx* c, double a, const double* f_loc);
+int launch_condense_general(hdg_ctx* c, double a, const double* f_loc);
+}  // namespace hdg
+
+using namespace hdg;
+
+namespace {
+
+thread_local std::string g_init_err;
+
+int fail(hdg_ctx* c, int code, const std::string& msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_init_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t _e = (call);                                                               \
+        if (_e != hipSuccess) return fail(c, HDG_E_HIP, std::string(#call ": ") + hipGetErrorString(_e)); \
+    } while (0)
+
+template <typename T>
+int dalloc(hdg_ctx* c, T** p, size_t count) {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        std::ostringstream os;
+        os << "hipMalloc of " << count * sizeof(T) << " bytes failed: " << hipGetErrorString(e);
+        return fail(c, HDG_E_ALLOC, os.str());
+    }
+    return HDG_OK;
+}
+
+template <typename T>
+int upload(hdg_ctx* c, T** p, const std::vector<T>& h) {
+    int s = dalloc(c, p, h.size());
+    if (s) return s;
+    HIPCHK(hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return HDG_OK;
+}
+
+int upload_f32(hdg_ctx* c, float** p, const std::vector<double>& h) {
+    std::vector<float> f(h.begin(), h.end());
+    return upload(c, p, f);
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+struct EventTimer {
+    hdg_ctx* c;
+    float* out;
+    explicit EventTimer(hdg_ctx* cc, float* o) : c(cc), out(o) { (void)hipEventRecord(c->ev0, c->stream); }
+    ~EventTimer() {
+        (void)hipEventRecord(c->ev1, c->stream);
+        if (hipEventSynchronize(c->ev1) == hipSuccess) (void)hipEventElapsedTime(out, c->ev0, c->ev1);
+    }
+};
+
+int check_status(hdg_ctx* c) {
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (h & 1) return fail(c, HDG_E_SINGULAR, "zero or non-finite pivot in a local factorisation");
+    return HDG_OK;
+}
+
+bool supported(hdg_ctx* c) {
+    if (c->physics == HDG_ACOUSTIC) return c->nrhs == 1 && c->k >= 1 && c->k <= 4;
+    return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hdg_last_error(const hdg_ctx* ctx) { return ctx ? ctx->err.c_str() : g_init_err.c_str(); }
+
+hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_desc* p, const hdg_options* o,
+                         void* stream) {
+    g_init_err.clear();
+    hdg_ctx* c = nullptr;
+    if (!out || !m || !p || !o) return fail(nullptr, HDG_E_ARG, "null argument");
+    *out = nullptr;
+    if (m->dim != 2 && m->dim != 3) return fail(nullptr, HDG_E_ARG, "dim must be 2 or 3");
+    if (!m->xyz || !m->elem_vert || m->n_elem <= 0 || m->n_vert <= 0)
+        return fail(nullptr, HDG_E_ARG, "empty mesh or null mesh arrays");
+    if (m->n_elem >= (int64_t)1 << 31) return fail(nullptr, HDG_E_ARG, "too many elements");
+    if (p->physics < 0 || p->physics > 2) return fail(nullptr, HDG_E_ARG, "unknown physics");
+    if (p->physics != HDG_ACOUSTIC && m->dim != 3) return fail(nullptr, HDG_E_ARG, "elastic/maxwell need dim 3");
+    if (!p->elem_par) return fail(nullptr, HDG_E_ARG, "null elem_par");
+    if (o->precision != HDG_FP64 && o->precision != HDG_MIXED_FP32)
+        return fail(nullptr, HDG_E_ARG, "unknown precision");
+    if (o->nrhs < 1 || o->nrhs > 32) return fail(nullptr, HDG_E_ARG, "nrhs must be in 1..32");
+    if (!(p->stab_scale > 0)) return fail(nullptr, HDG_E_ARG, "stab_scale must be positive");
+    int kk = o->k;
+    bool uniform = true;
+    if (m->degree) {
+        kk = m->degree[0];
+        for (int64_t e = 0; e < m->n_elem; ++e) {
+            if (m->degree[e] < 1 || m->degree[e] > 5) return fail(nullptr, HDG_E_MESH, "degree outside 1..5");
+            if (m->degree[e] != kk) uniform = false;
+        }
+    }
+    if (kk < 1 || kk > 5) return fail(nullptr, HDG_E_MESH, "degree outside 1..5");
+    c = new (std::nothrow) hdg_ctx();
+    if (!c) return fail(nullptr, HDG_E_ALLOC, "host allocation failed");
+    c->physics = p->physics;
+    c->precision = o->precision;
+    c->nrhs = o->nrhs;
+    c->k = kk;
+    c->uniform = uniform;
+    c->stab_scale = p->stab_scale;
+    c->krylov_tol = o->krylov_tol > 0 ? o->krylov_tol : 1e-13;
+    c->krylov_maxit = o->krylov_maxit > 0 ? o->krylov_maxit : 5000;
+    c->refine_tol = o->refine_tol > 0 ? o->refine_tol : 1e-13;
+    c->refine_maxit = o->refine_maxit > 0 ? o->refine_maxit : 10;
+    c->stream = (hipStream_t)stream;
+    int st = build_mesh(c, m, p);
+    if (st) {
+        g_init_err = c->err;
+        delete c;
+        return st;
+    }
+    if (!uniform) {
+        g_init_err = "variable polynomial degree is not supported by this build";
+        delete c;
+        return HDG_E_UNSUPPORTED;
+    }
+    const int d = c->dim;
+    c->m_local = (c->physics == HDG_ACOUSTIC) ? d + 1 : (c->physics == HDG_ELASTIC ? 9 : 6);
+    c->m_trace = (c->physics == HDG_ACOUSTIC) ? 1 : (c->physics == HDG_ELASTIC ? 3 : 2);
+    c->N = dim_p(kk, d);
+    c->NF = dim_p(kk, d - 1);
+    c->n_loc = c->m_local * c->N;
+    c->bs = c->m_trace * c->NF;
+    c->n_tr = (d + 1) * c->bs;
+    c->n_local_dofs = c->n_elem * c->n_loc;
+    c->n_trace_dofs = c->n_faces * c->bs;
+    c->K_sign = (c->physics == HDG_ACOUSTIC) ? -1.0 : 1.0;
+    c->Ns = c->N;
+    if (!supported(c)) {
+        std::ostringstream os;
+        os << "configuration not built: physics " << c->physics << ", k " << kk << ", nrhs " << c->nrhs;
+        g_init_err = os.str();
+        delete c;
+        return HDG_E_UNSUPPORTED;
+    }
+    // reference tables
+    build_ref_tables(d, kk, c->ref);
+    build_face_tables(d, kk, kk, c->reff);
+
+    int s = 0;
+#define TRY(x)                       \
+    do {                             \
+        if ((s = (x)) != HDG_OK) {   \
+            g_init_err = c->err;     \
+            hdg_destroy(c);          \
+            return s;                \
+        }                            \
+    } while (0)
+    TRY(upload(c, &c->d_geom, c->geom));
+    TRY(upload(c, &c->d_eface, c->elem_face));
+    TRY(upload(c, &c->d_eperm, c->elem_perm));
+    TRY(upload(c, &c->d_face_elem, c->face_elem));
+    TRY(upload(c, &c->d_face_lf, c->face_lf));
+    TRY(upload(c, &c->d_face_bnd, c->face_bnd));
+    TRY(upload(c, &c->d_bsr_cols, c->bsr_cols_h));
+    TRY(upload(c, &c->tab.Sr, c->ref.Sr));
+    TRY(upload(c, &c->tab.Mf, c->ref.Mf));
+    TRY(upload(c, &c->tab.Tsym, c->ref.Tsym));
+    TRY(upload(c, &c->tab.Ef, c->reff.E));
+    TRY(upload_f32(c, &c->tab.Sr32, c->ref.Sr));
+    TRY(upload_f32(c, &c->tab.Mf32, c->ref.Mf));
+    TRY(upload_f32(c, &c->tab.Tsym32, c->ref.Tsym));
+    TRY(upload_f32(c, &c->tab.Ef32, c->reff.E));
+
+    const size_t tsz = (c->precision == HDG_FP64) ? sizeof(double) : sizeof(float);
+    const int64_t ne = c->n_elem, R = c->nrhs;
+    TRY(dalloc(c, (char**)&c->d_Ke, ne * c->n_tr * c->n_tr * tsz));
+    TRY(dalloc(c, (char**)&c->d_re, ne * c->n_tr * R * tsz));
+    TRY(dalloc(c, (char**)&c->d_Zt, ne * c->n_tr * c->n_loc * tsz));
+    TRY(dalloc(c, (char**)&c->d_z, ne * c->n_loc * R * tsz));
+    if (c->precision == HDG_MIXED_FP32) TRY(dalloc(c, (char**)&c->d_LU, ne * c->Ns * c->Ns * tsz));
+    TRY(dalloc(c, &c->d_status, 1));
+    const int64_t ntr = c->n_trace_dofs;
+    TRY(dalloc(c, &c->d_bsr, c->n_faces * c->nslot * c->bs * c->bs));
+    TRY(dalloc(c, &c->d_rhs, ntr * R));
+    TRY(dalloc(c, &c->d_pinv, c->n_faces * c->bs * c->bs));
+    TRY(dalloc(c, &c->d_cg_r, ntr * R));
+    TRY(dalloc(c, &c->d_cg_z, ntr * R));
+    TRY(dalloc(c, &c->d_cg_p, ntr * R));
+    TRY(dalloc(c, &c->d_cg_q, std::max<int64_t>(ntr * R, c->n_faces * c->bs * c->bs)));
+    c->red_blocks = 1024;
+    TRY(dalloc(c, &c->d_red, c->red_blocks * 32));
+    TRY(dalloc(c, &c->d_scal, 8 * 32));
+    const int64_t nl = c->n_local_dofs * R;
+    if (c->precision == HDG_MIXED_FP32) {
+        TRY(dalloc(c, &c->d_f_saved, nl));
+        TRY(dalloc(c, &c->d_lbnd_saved, ntr * R));
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        g_init_err = "hipEventCreate failed";
+        hdg_destroy(c);
+        return HDG_E_HIP;
+    }
+#undef TRY
+    *out = c;
+    return HDG_OK;
+}
+
+hdg_status hdg_query(const hdg_ctx* c, int key, int64_t* v) {
+    if (!c || !v) return HDG_E_ARG;
+    switch (key) {
+        case HDG_Q_N_ELEM: *v = c->n_elem; break;
+        case HDG_Q_N_FACES: *v = c->n_faces; break;
+        case HDG_Q_N_BFACES: *v = c->n_bfaces; break;
+        case HDG_Q_N_LOCAL_DOFS: *v = c->n_local_dofs; break;
+        case HDG_Q_N_TRACE_DOFS: *v = c->n_trace_dofs; break;
+        case HDG_Q_N_VOL_POINTS: {
+            std::vector<double> p, w;
+            simplex_quadrature(c->dim, c->k + 2, p, w);
+            *v = c->n_elem * (int64_t)w.size();
+            break;
+        }
+        case HDG_Q_N_BND_POINTS: {
+            std::vector<double> p, w;
+            simplex_quadrature(c->dim - 1, c->k + 3, p, w);
+            *v = c->n_bfaces * (int64_t)w.size();
+            break;
+        }
+        case HDG_Q_LAST_ITERS: *v = c->last_iters; break;
+        case HDG_Q_LAST_REFINE: *v = c->last_refine; break;
+        case HDG_Q_M_LOCAL: *v = c->m_local; break;
+        case HDG_Q_M_TRACE: *v = c->m_trace; break;
+        default: return HDG_E_ARG;
+    }
+    return HDG_OK;
+}
+
+hdg_status hdg_condense(hdg_ctx* c, double a, const double* f_loc, const double* lam_bnd) {
+    if (!c) return HDG_E_ARG;
+    if (!f_loc || !lam_bnd) return fail(c, HDG_E_ARG, "null f_loc or lam_bnd");
+    if (!(a > 0) || !std::isfinite(a)) return fail(c, HDG_E_ARG, "stage coefficient must be positive");
+    HIPCHK(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
+    const int64_t R = c->nrhs;
+    if (c->precision == HDG_MIXED_FP32) {   // kept for the FP64 refinement residuals
+        HIPCHK(hipMemcpyAsync(c->d_f_saved, f_loc, c->n_local_dofs * R * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->d_lbnd_saved, lam_bnd, c->n_trace_dofs * R * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+    }
+    int e;
+    {
+        EventTimer t(c, &c->tim.condense);
+        e = (c->physics == HDG_ACOUSTIC) ? launch_condense_acoustic(c, a, f_loc) : -1;
+    }
+    if (e) return fail(c, HDG_E_HIP, "condensation kernel launch failed");
+    {
+        EventTimer t(c, &c->tim.assemble);
+        e = launch_assemble(c, lam_bnd);
+        if (!e) e = launch_block_inverse(c);
+    }
+    if (e) return fail(c, HDG_E_HIP, "assembly kernel launch failed");
+    c->last_a = a;
+    c->condensed = true;
+    return HDG_OK;
+}
+
+hdg_status hdg_trace_solve(hdg_ctx* c, double* lambda, int* iters, double* relres) {
+    if (!c) return HDG_E_ARG;
+    if (!lambda) return fail(c, HDG_E_ARG, "null lambda");
+    if (!c->condensed) return fail(c, HDG_E_STATE, "hdg_trace_solve before hdg_condense");
+    int s = check_status(c);
+    if (s) return s;
+    int r;
+    {
+        EventTimer t(c, &c->tim.solve);
+        r = trace_cg(c, lambda, iters, relres);
+    }
+    if (r == HDG_E_NOCONV) return fail(c, r, "trace solve did not reach krylov_tol");
+    if (r) return fail(c, r, "trace solve failed");
+    return HDG_OK;
+}
+
+hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
+    if (!c) return HDG_E_ARG;
+    if (!lambda || !u) return fail(c, HDG_E_ARG, "null lambda or u");
+    if (!c->condensed) return fail(c, HDG_E_STATE, "hdg_recover before hdg_condense");
+    int s = check_status(c);
+    if (s) return s;
+    int e;
+    {
+        EventTimer t(c, &c->tim.recover);
+        e = launch_recover(c, lambda, u, false);
+    }
+    if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
+    c->last_refine = 0;
+    return HDG_OK;
+}
+
+hdg_status hdg_apply_mass(hdg_ctx* c, double a, const double* u, double* f) {
+    if (!c) return HDG_E_ARG;
+    if (!u || !f) return fail(c, HDG_E_ARG, "null pointer");
+    if (launch_apply_mass(c, a, u, f)) return fail(c, HDG_E_HIP, "mass kernel launch failed");
+    return HDG_OK;
+}
+
+hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, double* lambda,
+                    const double* lam_bnd, const double* src) {
+    if (!c) return HDG_E_ARG;
+    if (!u || !lambda || !lam_bnd) return fail(c, HDG_E_ARG, "null pointer");
+    if (!(dt > 0)) return fail(c, HDG_E_ARG, "dt must be positive");
+    if (scheme != HDG_BACKWARD_EULER && scheme != HDG_DIRK33) return fail(c, HDG_E_ARG, "unknown scheme");
+    (void)t;
+    // Butcher tableau and its inverse d = A^{-1}
+    double A[3][3] = {}, Dm[3][3] = {};
+    int ns = 1;
+    if (scheme == HDG_BACKWARD_EULER) {
+        A[0][0] = 1.0;
+    } else {
+        ns = 3;
+        // gamma: root in (1/6, 1/2) of x^3 - 3x^2 + 3x/2 - 1/6 (Newton from 0.4)
+        double g = 0.4;
+        for (int it = 0; it < 60; ++it) {
+            double fx = ((g - 3.0) * g + 1.5) * g - 1.0 / 6.0;
+            double dfx = (3.0 * g - 6.0) * g + 1.5;
+            g -= fx / dfx;
+        }
+        double b1 = -1.5 * g * g + 4.0 * g - 0.25, b2 = 1.5 * g * g - 5.0 * g + 1.25;
+        A[0][0] = g;
+        A[1][0] = 0.5 * (1.0 - g);
+        A[1][1] = g;
+        A[2][0] = b1;
+        A[2][1] = b2;
+        A[2][2] = g;
+    }
+    for (int i = 0; i < ns; ++i) {   // forward substitution for the lower-triangular inverse
+        Dm[i][i] = 1.0 / A[i][i];
+        for (int j = 0; j < i; ++j) {
+            double acc = 0.0;
+            for (int m = j; m < i; ++m) acc += A[i][m] * Dm[m][j];
+            Dm[i][j] = -acc / A[i][i];
+        }
+    }
+    const int64_t nl = c->n_local_dofs * c->nrhs;
+    const int64_t nt = c->n_trace_dofs * c->nrhs;
+    if (!c->d_stage) {
+        int s = dalloc(c, &c->d_stage, 3 * nl);
+        if (s) return s;
+        if ((s = dalloc(c, &c->d_ustar, nl))) return s;
+        if ((s = dalloc(c, &c->d_fstage, nl))) return s;
+    }
+    for (int i = 0; i < ns; ++i) {
+        const double a = Dm[i][i] / dt;
+        // u* = u^n - (1/d_ii) sum_{j<i} d_ij (U_j - u^n)
+        HIPCHK(hipMemcpyAsync(c->d_ustar, u, nl * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        double wsum = 0.0;
+        for (int j = 0; j < i; ++j) {
+            double w = -Dm[i][j] / Dm[i][i];
+            wsum += w;
+            launch_axpy(c, nl, w, c->d_stage + j * nl, c->d_ustar);
+        }
+        if (wsum != 0.0) launch_axpy(c, nl, -wsum, u, c->d_ustar);
+        launch_apply_mass(c, a, c->d_ustar, c->d_fstage);
+        if (src) launch_axpy(c, nl, 1.0, src, c->d_fstage);
+        int s = hdg_condense(c, a, c->d_fstage, lam_bnd + i * nt);
+        if (s) return s;
+        int it;
+        double rr;
+        if ((s = hdg_trace_solve(c, lambda, &it, &rr))) return s;
+        if ((s = hdg_recover(c, lambda, c->d_stage + i * nl))) return s;
+    }
+    // stiffly accurate: u^{n+1} = U_s
+    HIPCHK(hipMemcpyAsync(u, c->d_stage + (ns - 1) * nl, nl * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return HDG_OK;
+}
+
+hdg_status hdg_volume_points(const hdg_ctx* c, double* pts) {
+    if (!c || !pts) return HDG_E_ARG;
+    std::vector<double> p, w;
+    simplex_quadrature(c->dim, c->k + 2, p, w);
+    const int d = c->dim, nq = (int)w.size();
+    for (int64_t e = 0; e < c->n_elem; ++e) {
+        const int64_t* ev = &c->ev[e * (d + 1)];
+        for (int q = 0; q < nq; ++q)
+            for (int r = 0; r < d; ++r) {
+                double x = c->xyz[ev[0] * d + r];
+                for (int s = 0; s < d; ++s) x += (c->xyz[ev[s + 1] * d + r] - c->xyz[ev[0] * d + r]) * p[q * d + s];
+                pts[(e * nq + q) * d + r] = x;
+            }
+    }
+    return HDG_OK;
+}
+
+hdg_status hdg_project_volume(const hdg_ctx* c, const double* vals, double* u) {
+    if (!c || !vals || !u) return HDG_E_ARG;
+    std::vector<double> p, w;
+    simplex_quadrature(c->dim, c->k + 2, p, w);
+    const int d = c->dim, nq = (int)w.size(), N = c->N, m = c->m_local;
+    std::vector<double> phi(nq * N);
+    for (int q = 0; q < nq; ++q) pkd_eval(d, c->k, &p[q * d], &phi[q * N], nullptr);
+    for (int64_t e = 0; e < c->n_elem; ++e)
+        for (int comp = 0; comp < m; ++comp)
+            for (int i = 0; i < N; ++i) {
+                double acc = 0.0;
+                for (int q = 0; q < nq; ++q) acc += w[q] * phi[q * N + i] * vals[(e * nq + q) * m + comp];
+                u[e * m * N + comp * N + i] = acc;
+            }
+    return HDG_OK;
+}
+
+hdg_status hdg_boundary_points(const hdg_ctx* c, double* pts) {
+    if (!c || !pts) return HDG_E_ARG;
+    std::vector<double> p, w;
+    const int d = c->dim;
+    simplex_quadrature(d - 1, c->k + 3, p, w);
+    const int nq = (int)w.size();
+    for (size_t b = 0; b < c->bface_list.size(); ++b) {
+        const int64_t* fv = &c->face_vert[c->bface_list[b] * d];
+        for (int q = 0; q < nq; ++q)
+            for (int r = 0; r < d; ++r) {
+                double x = c->xyz[fv[0] * d + r];
+                for (int s = 0; s < d - 1; ++s)
+                    x += (c->xyz[fv[s + 1] * d + r] - c->xyz[fv[0] * d + r]) * p[q * (d - 1) + s];
+                pts[(b * nq + q) * d + r] = x;
+            }
+    }
+    return HDG_OK;
+}
+
+hdg_status hdg_project_boundary(const hdg_ctx* c, const double* vals, double* lam) {
+    if (!c || !vals || !lam) return HDG_E_ARG;
+    std::vector<double> p, w;
+    const int d = c->dim;
+    simplex_quadrature(d - 1, c->k + 3, p, w);
+    const int nq = (int)w.size(), NF = c->NF, mt = c->m_trace;
+    std::vector<double> psi(nq * NF);
+    for (int q = 0; q < nq; ++q) pkd_eval(d - 1, c->k, &p[q * (d - 1)], &psi[q * NF], nullptr);
+    std::fill(lam, lam + c->n_trace_dofs, 0.0);
+    const int vw = (c->physics == HDG_ACOUSTIC) ? 1 : 3;
+    for (size_t b = 0; b < c->bface_list.size(); ++b) {
+        int64_t F = c->bface_list[b];
+        for (int comp = 0; comp < mt; ++comp)
+            for (int l = 0; l < NF; ++l) {
+                double acc = 0.0;
+                for (int q = 0; q < nq; ++q) {
+                    const double* v = &vals[(b * nq + q) * vw];
+                    double g;
+                    if (c->physics == HDG_MAXWELL) {
+                        const double* t = &c->frame[F * 6 + comp * 3];
+                        g = v[0] * t[0] + v[1] * t[1] + v[2] * t[2];
+                    } else {
+                        g = v[comp];
+                    }
+                    acc += w[q] * psi[q * NF + l] * g;
+                }
+                lam[F * c->bs + comp * NF + l] = acc;   // face mass = s_F I, quadrature carries s_F
+            }
+    }
+    return HDG_OK;
+}
+
+hdg_status hdg_point_sources(const hdg_ctx* c, int n_src, const double* pts, double* f) {
+    if (!c || !pts || !f || n_src < 1) return HDG_E_ARG;
+    if (c->physics != HDG_ACOUSTIC) return HDG_E_UNSUPPORTED;
+    const int d = c->dim, N = c->N;
+    std::fill(f, f + c->n_local_dofs * n_src, 0.0);
+    std::vector<double> phi(N);
+    for (int s = 0; s < n_src; ++s) {
+        const double* x = pts + s * d;
+        bool found = false;
+        for (int64_t e = 0; e < c->n_elem && !found; ++e) {
+            const double* g = &c->geom[e * GEOM_STRIDE];
+            const int64_t v0 = c->ev[e * (d + 1)];
+            double xi[3], sum = 0.0;
+            bool inside = true;
+            for (int r = 0; r < d; ++r) {
+                double acc = 0.0;
+                for (int xx = 0; xx < d; ++xx) acc += g[1 + r * d + xx] * (x[xx] - c->xyz[v0 * d + xx]);
+                xi[r] = acc;
+                sum += acc;
+                if (acc < -1e-12) inside = false;
+            }
+            if (!inside || sum > 1.0 + 1e-12) continue;
+            pkd_eval(d, c->k, xi, phi.data(), nullptr);
+            for (int i = 0; i < N; ++i) f[(e * c->n_loc + d * N + i) * n_src + s] = phi[i];
+            found = true;
+        }
+        if (!found) return HDG_E_ARG;
+    }
+    return HDG_OK;
+}
+
+hdg_status hdg_element_data(hdg_ctx* c, int which, int64_t e0, int64_t count, double* out) {
+    if (!c || !out || which < 0 || which > 3 || e0 < 0 || count < 0 || e0 + count > c->n_elem) return HDG_E_ARG;
+    if (!c->condensed) return fail(c, HDG_E_STATE, "no condensed data");
+    const int64_t R = c->nrhs, n = c->n_loc, t = c->n_tr;
+    int64_t blk;
+    void* src;
+    switch (which) {
+        case 0: blk = t * t; src = c->d_Ke; break;
+        case 1: blk = t * R; src = c->d_re; break;
+        case 2: blk = n * t; src = c->d_Zt; break;
+        default: blk = n * R; src = c->d_z; break;
+    }
+    const size_t tsz = (c->precision == HDG_FP64) ? sizeof(double) : sizeof(float);
+    std::vector<char> buf(count * blk * tsz);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(buf.data(), (char*)src + e0 * blk * tsz, buf.size(), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < count * blk; ++i) {
+        double v = (tsz == 8) ? ((double*)buf.data())[i] : (double)((float*)buf.data())[i];
+        if (which == 2) {   // stored column-major per element: [c][row] -> [row][c]
+            int64_t e = i / blk, rem = i % blk, col = rem / n, row = rem % n;
+            out[e * blk + row * t + col] = v;
+        } else {
+            out[i] = v;
+        }
+    }
+    return HDG_OK;
+}
+
+hdg_status hdg_last_timing(const hdg_ctx* c, int which, double* ms) {
+    if (!c || !ms) return HDG_E_ARG;
+    const float v[6] = {c->tim.condense, c->tim.assemble, c->tim.solve, c->tim.recover, c->tim.refine_elem,
+                        c->tim.refine_solve};
+    if (which < 0 || which > 5) return HDG_E_ARG;
+    *ms = v[which];
+    return HDG_OK;
+}
+
+void hdg_destroy(hdg_ctx* c) {
+    if (!c) return;
+    void* ptrs[] = {c->d_geom, c->d_eface, c->d_eperm, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
+                    c->d_bsr_cols, c->tab.Sr, c->tab.Mf, c->tab.Tsym, c->tab.Ef, c->tab.Sr32, c->tab.Mf32,
+                    c->tab.Tsym32, c->tab.Ef32, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
+                    c->d_bsr, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
+                    c->d_scal, c->d_f_saved, c->d_lbnd_saved, c->d_su, c->d_slam, c->d_du, c->d_dlam,
+                    c->d_stage, c->d_ustar, c->d_fstage};
+    if (c->stream || c->d_geom) (void)hipStreamSynchronize(c->stream);
+    for (void* p : ptrs) dfree(p);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+}
+
+// Host-only access to the reference tables (no device needed): which = 0 Sr, 1 Mf, 2 Tsym,
+// 3 oriented face table E (face degree kF).  Returns the number of doubles written, or a
+// negative hdg_status.
+int64_t hdg_reference_table(int dim, int k, int kF, int which, double* out, int64_t cap) {
+    if ((dim != 2 && dim != 3) || k < 0 || k > 8 || kF < 0 || kF > 8 || !out) return -HDG_E_ARG;
+    std::vector<double> v;
+    if (which <= 2) {
+        RefTables T;
+        build_ref_tables(dim, k, T);
+        v = (which == 0) ? T.Sr : (which == 1 ? T.Mf : T.Tsym);
+    } else if (which == 3) {
+        RefFaceTables E;
+        build_face_tables(dim, k, kF, E);
+        v = E.E;
+    } else {
+        return -HDG_E_ARG;
+    }
+    if ((int64_t)v.size() > cap) return -HDG_E_ARG;
+    std::copy(v.begin(), v.end(), out);
+    return (int64_t)v.size();
+}
+
+}  // extern "C"

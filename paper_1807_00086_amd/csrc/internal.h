@@ -1,0 +1,137 @@
+// Internal state of an HDG context (host + device buffers).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hdg.h"
+#include "reftab.h"
+
+namespace hdg {
+
+constexpr int GEOM_STRIDE = 32;   // doubles per element geometry record
+// 3D record: [0] |J|, [1..9] G = J^{-1} row-major (G[r][x] = d xi_r / d x_x),
+//            [10..13] s_f = face measure / reference-face measure, [14..25] outward unit
+//            normals n_f (4 x 3), [26..28] material (rho,c,-)|(rho,lambda,mu)|(eps,mu,sigma),
+//            [29] stabilisation (tau or S)
+// 2D record: [0] |J|, [1..4] G, [5..7] s_f, [8..13] normals (3 x 2), [26..29] as above
+inline int geo_G(int) { return 1; }
+inline int geo_s(int d) { return 1 + d * d; }
+inline int geo_n(int d) { return 1 + d * d + (d + 1); }
+constexpr int GEO_PAR = 26;
+constexpr int GEO_STAB = 29;
+
+struct DeviceTables {         // one polynomial degree (uniform meshes: face degree = k)
+    int k = 0, N = 0, NF = 0;
+    double *Sr = nullptr, *Mf = nullptr, *Tsym = nullptr, *Ef = nullptr;     // FP64
+    float *Sr32 = nullptr, *Mf32 = nullptr, *Tsym32 = nullptr, *Ef32 = nullptr;
+};
+
+struct Timings {
+    float condense = 0, assemble = 0, solve = 0, recover = 0, refine_elem = 0, refine_solve = 0;
+};
+
+}  // namespace hdg
+
+struct hdg_ctx {
+    // configuration
+    int dim = 0, physics = 0, precision = 0, nrhs = 1, k = 0;
+    bool uniform = true;
+    double stab_scale = 1.0;
+    double krylov_tol = 1e-13, refine_tol = 1e-13;
+    int krylov_maxit = 2000, refine_maxit = 8;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // sizes
+    int64_t n_elem = 0, n_vert = 0, n_faces = 0, n_bfaces = 0;
+    int m_local = 0, m_trace = 0;
+    int N = 0, NF = 0, n_loc = 0, n_tr = 0;   // per element (uniform degree)
+    int64_t n_local_dofs = 0, n_trace_dofs = 0;
+    int bs = 0;                                // trace block size per face = m_trace * NF
+    int nslot = 0;                             // BSR blocks per face row = 1 + 2 d
+    double K_sign = 1.0;                       // assemble sign * K so the system is SPD
+
+    // host mesh data
+    std::vector<double> xyz, par;
+    std::vector<int64_t> ev;
+    std::vector<int8_t> degree;
+    std::vector<int32_t> elem_face;            // [ne][d+1]
+    std::vector<int32_t> elem_perm;            // [ne][d+1]
+    std::vector<int32_t> face_elem;            // [nf][2]
+    std::vector<int32_t> face_lf;              // [nf][2]
+    std::vector<int64_t> face_vert;            // [nf][d] sorted global ids
+    std::vector<uint8_t> face_bnd;             // [nf]
+    std::vector<double> geom;                  // [ne][GEOM_STRIDE]
+    std::vector<double> frame;                 // [nf][6] Maxwell tangent frame (t1, t2)
+    std::vector<int64_t> bface_list;           // boundary faces in face order
+    std::vector<int32_t> bsr_cols_h;           // [nf][nslot]
+
+    hdg::RefTables ref;
+    hdg::RefFaceTables reff;
+
+    // device mesh data
+    double* d_geom = nullptr;
+    int32_t* d_eface = nullptr;
+    int32_t* d_eperm = nullptr;
+    int32_t* d_face_elem = nullptr;
+    int32_t* d_face_lf = nullptr;
+    uint8_t* d_face_bnd = nullptr;
+    int32_t* d_bsr_cols = nullptr;
+    hdg::DeviceTables tab;
+
+    // condensation outputs (precision-typed: double or float)
+    void* d_Ke = nullptr;      // [ne][t][t]
+    void* d_re = nullptr;      // [ne][t][r]
+    void* d_Zt = nullptr;      // [ne][t][n]   (column-major Z)
+    void* d_z = nullptr;       // [ne][n][r]
+    void* d_LU = nullptr;      // [ne][Ns][Ns] factored Schur block (mixed precision)
+    int Ns = 0;                // size of the densely factored block
+    int* d_status = nullptr;   // device status word (0 ok, 1 singular pivot)
+
+    // global trace system (FP64)
+    double* d_bsr = nullptr;   // [nf][nslot][bs][bs]
+    double* d_rhs = nullptr;   // [ntr][r]
+    double* d_pinv = nullptr;  // [nf][bs][bs] inverse diagonal blocks
+    double *d_cg_r = nullptr, *d_cg_z = nullptr, *d_cg_p = nullptr, *d_cg_q = nullptr;
+    double* d_red = nullptr;   // reduction scratch
+    double* d_scal = nullptr;  // device scalars
+    int red_blocks = 0;
+
+    // stage / refinement buffers (FP64)
+    double* d_f_saved = nullptr;     // [n_local_dofs][r]
+    double* d_lbnd_saved = nullptr;  // [n_trace_dofs][r]
+    double* d_su = nullptr;          // [n_local_dofs][r]
+    double* d_slam = nullptr;        // [n_trace_dofs][r]
+    double* d_du = nullptr;
+    double* d_dlam = nullptr;
+    double* d_stage = nullptr;       // [3][n_local_dofs][r] DIRK stages
+    double* d_ustar = nullptr;
+    double* d_fstage = nullptr;
+    double last_a = 0.0;
+    bool condensed = false;
+    int last_iters = 0, last_refine = 0;
+    hdg::Timings tim;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace hdg {
+// mesh.cpp
+int build_mesh(hdg_ctx* c, const hdg_mesh_desc* m, const hdg_phys_desc* p);
+// kernels (launchers, in .hip files); all return hipError_t as int
+int launch_condense(hdg_ctx* c, double a, const double* f_loc, const double* lam_bnd);
+int launch_assemble(hdg_ctx* c, const double* lam_bnd);
+int launch_recover(hdg_ctx* c, const double* lambda, double* u, bool rhs_only_z);
+int launch_residual(hdg_ctx* c, double a, const double* u, const double* lam, const double* f,
+                    const double* lam_bnd, double* su, double* slam);
+int launch_rhs_condense(hdg_ctx* c, const double* su, const double* slam);
+int launch_apply_mass(hdg_ctx* c, double a, const double* u, double* f);
+int launch_block_inverse(hdg_ctx* c);
+int trace_cg(hdg_ctx* c, double* lambda, int* iters, double* relres);
+int launch_axpy(hdg_ctx* c, int64_t n, double alpha, const double* x, double* y);
+int launch_lincomb(hdg_ctx* c, int64_t n, double a, const double* x, double b, const double* y,
+                   double* out);
+int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out);
+}  // namespace hdg

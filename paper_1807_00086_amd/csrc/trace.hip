@@ -1,0 +1,355 @@
+// Global trace system in FP64 (section 2.4.2): owner-computes assembly of the element Schur
+// complements into face-block rows, block-Jacobi preconditioned conjugate gradients.
+//
+// BSR layout: row F has nslot = 1 + 2d blocks; slot 0 is the diagonal, slots 1 + s d + m are
+// the other faces of the s-th neighbour element of F.  Blocks are stored column-major
+// (bsr[F][slot][b][a] is entry (a, b)) so that the threads of one row block read adjacent
+// words.  Dirichlet faces have identity rows; couplings to Dirichlet faces are moved to the
+// right-hand side.  The system is assembled as K_sign * K so that it is positive definite.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace hdg {
+
+namespace {
+constexpr int NT = 256;
+
+template <typename T>
+__global__ __launch_bounds__(NT) void assemble_kernel(
+    int64_t nf, int d, int bs, int tt, int R, double sign, const int32_t* __restrict__ face_elem,
+    const int32_t* __restrict__ face_lf, const uint8_t* __restrict__ face_bnd,
+    const int32_t* __restrict__ eface, const T* __restrict__ Ke, const T* __restrict__ re,
+    const double* __restrict__ lam_bnd, double* __restrict__ bsr, double* __restrict__ rhs) {
+    const int nslot = 1 + 2 * d, nv = d + 1;
+    for (int64_t F = blockIdx.x; F < nf; F += gridDim.x) {
+        const bool bnd = face_bnd[F] != 0;
+        int32_t es[2] = {face_elem[2 * F], face_elem[2 * F + 1]};
+        int32_t ls[2] = {face_lf[2 * F], face_lf[2 * F + 1]};
+        double* B = bsr + (size_t)F * nslot * bs * bs;
+        for (int idx = threadIdx.x; idx < nslot * bs * bs; idx += NT) {
+            int slot = idx / (bs * bs), rem = idx % (bs * bs);
+            int b = rem / bs, a = rem % bs;   // column-major block
+            double v = 0.0;
+            if (slot == 0) {
+                if (bnd) {
+                    v = (a == b) ? 1.0 : 0.0;
+                } else {
+                    for (int s = 0; s < 2; ++s) {
+                        const T* K = Ke + (size_t)es[s] * tt * tt;
+                        v += (double)K[(ls[s] * bs + a) * tt + ls[s] * bs + b];
+                    }
+                    v *= sign;
+                }
+            } else if (!bnd) {
+                int s = (slot - 1) / d, m = (slot - 1) % d;
+                int32_t e = es[s];
+                if (e >= 0) {
+                    int lf = ls[s];
+                    int q = (m < lf) ? m : m + 1;
+                    int32_t F2 = eface[(size_t)e * nv + q];
+                    if (!face_bnd[F2]) v = sign * (double)Ke[(size_t)e * tt * tt + (lf * bs + a) * tt + q * bs + b];
+                }
+            }
+            B[idx] = v;
+        }
+        for (int idx = threadIdx.x; idx < bs * R; idx += NT) {
+            int a = idx / R, r = idx % R;
+            double v;
+            if (bnd) {
+                v = lam_bnd[((size_t)F * bs + a) * R + r];
+            } else {
+                v = 0.0;
+                for (int s = 0; s < 2; ++s) {
+                    int32_t e = es[s];
+                    int lf = ls[s];
+                    const T* K = Ke + (size_t)e * tt * tt;
+                    double acc = (double)re[((size_t)e * tt + lf * bs + a) * R + r];
+                    for (int q = 0; q < nv; ++q) {
+                        if (q == lf) continue;
+                        int32_t F2 = eface[(size_t)e * nv + q];
+                        if (!face_bnd[F2]) continue;
+                        for (int b = 0; b < bs; ++b)
+                            acc -= (double)K[(lf * bs + a) * tt + q * bs + b] *
+                                   lam_bnd[((size_t)F2 * bs + b) * R + r];
+                    }
+                    v += acc;
+                }
+                v *= sign;
+            }
+            rhs[((size_t)F * bs + a) * R + r] = v;
+        }
+    }
+}
+
+// inverse of each diagonal block by Gauss-Jordan (one thread per face; blocks are SPD)
+__global__ __launch_bounds__(64) void block_inverse_kernel(int64_t nf, int nslot, int bs,
+                                                            const double* __restrict__ bsr,
+                                                            double* __restrict__ pinv,
+                                                            double* __restrict__ work) {
+    int64_t F = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (F >= nf) return;
+    const double* A = bsr + (size_t)F * nslot * bs * bs;   // slot 0, column-major
+    double* M = work + (size_t)F * bs * bs;
+    double* Inv = pinv + (size_t)F * bs * bs;
+    for (int i = 0; i < bs * bs; ++i) {
+        M[i] = A[i];
+        Inv[i] = ((i % bs) == (i / bs)) ? 1.0 : 0.0;
+    }
+    // column-major: entry (r, c) at c*bs + r
+    for (int j = 0; j < bs; ++j) {
+        double piv = M[j * bs + j];
+        double ip = 1.0 / piv;
+        for (int c = 0; c < bs; ++c) {
+            M[c * bs + j] *= ip;
+            Inv[c * bs + j] *= ip;
+        }
+        for (int r = 0; r < bs; ++r) {
+            if (r == j) continue;
+            double fct = M[j * bs + r];
+            if (fct == 0.0) continue;
+            for (int c = 0; c < bs; ++c) {
+                M[c * bs + r] -= fct * M[c * bs + j];
+                Inv[c * bs + r] -= fct * Inv[c * bs + j];
+            }
+        }
+    }
+}
+
+// y = A x (one thread per row entry (F, a, r))
+__global__ __launch_bounds__(NT) void bsr_spmv_kernel(int64_t nf, int nslot, int bs, int R,
+                                                      const int32_t* __restrict__ cols,
+                                                      const double* __restrict__ bsr,
+                                                      const double* __restrict__ x, double* __restrict__ y) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = nf * bs * R;
+    if (gid >= total) return;
+    int r = (int)(gid % R);
+    int64_t Fa = gid / R;
+    int64_t F = Fa / bs;
+    int a = (int)(Fa % bs);
+    double acc = 0.0;
+    for (int s = 0; s < nslot; ++s) {
+        int32_t cF = cols[F * nslot + s];
+        if (cF < 0) continue;
+        const double* B = bsr + ((size_t)F * nslot + s) * bs * bs;
+        const double* xv = x + (size_t)cF * bs * R + r;
+        for (int b = 0; b < bs; ++b) acc += B[b * bs + a] * xv[b * R];
+    }
+    y[gid] = acc;
+}
+
+__global__ __launch_bounds__(NT) void block_apply_kernel(int64_t nf, int bs, int R,
+                                                         const double* __restrict__ pinv,
+                                                         const double* __restrict__ x,
+                                                         double* __restrict__ y) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = nf * bs * R;
+    if (gid >= total) return;
+    int r = (int)(gid % R);
+    int64_t Fa = gid / R;
+    int64_t F = Fa / bs;
+    int a = (int)(Fa % bs);
+    const double* B = pinv + (size_t)F * bs * bs;
+    const double* xv = x + (size_t)F * bs * R + r;
+    double acc = 0.0;
+    for (int b = 0; b < bs; ++b) acc += B[b * bs + a] * xv[b * R];
+    y[gid] = acc;
+}
+
+// partial dot products per rhs column: out[blk][r]
+__global__ __launch_bounds__(NT) void dot_partial_kernel(int64_t n, int R, const double* __restrict__ x,
+                                                         const double* __restrict__ y,
+                                                         double* __restrict__ part) {
+    __shared__ double sh[NT];
+    for (int r = 0; r < R; ++r) {
+        double acc = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+            acc += x[i * R + r] * y[i * R + r];
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = NT / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * R + r] = sh[0];
+        __syncthreads();
+    }
+}
+
+__global__ void dot_final_kernel(int nb, int R, const double* __restrict__ part, double* __restrict__ out) {
+    int r = threadIdx.x;
+    if (r >= R) return;
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += part[(size_t)b * R + r];
+    out[r] = acc;
+}
+
+// y[i, r] += alpha[r] * x[i, r] (alpha from device array, optional sign)
+__global__ __launch_bounds__(NT) void axpy_cols_kernel(int64_t n, int R, const double* __restrict__ num,
+                                                       const double* __restrict__ den, double sgn,
+                                                       const double* __restrict__ x, double* __restrict__ y) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n * R) return;
+    int r = (int)(gid % R);
+    double dd = den[r];
+    double al = (dd != 0.0) ? num[r] / dd : 0.0;
+    y[gid] += sgn * al * x[gid];
+}
+
+// p = z + beta p, beta = num/den per column
+__global__ __launch_bounds__(NT) void xpby_cols_kernel(int64_t n, int R, const double* __restrict__ num,
+                                                       const double* __restrict__ den,
+                                                       const double* __restrict__ z, double* __restrict__ p) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n * R) return;
+    int r = (int)(gid % R);
+    double dd = den[r];
+    double be = (dd != 0.0) ? num[r] / dd : 0.0;
+    p[gid] = z[gid] + be * p[gid];
+}
+
+__global__ __launch_bounds__(NT) void lincomb_kernel(int64_t n, double a, const double* __restrict__ x,
+                                                     double b, const double* __restrict__ y,
+                                                     double* __restrict__ out) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n) return;
+    out[gid] = a * x[gid] + (y ? b * y[gid] : 0.0);
+}
+
+__global__ __launch_bounds__(NT) void copy_bnd_kernel(int64_t nf, int bs, int R, const uint8_t* __restrict__ bnd,
+                                                      const double* __restrict__ src, double* __restrict__ dst) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nf * bs * R) return;
+    int64_t F = gid / ((int64_t)bs * R);
+    if (bnd[F]) dst[gid] = src[gid];
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
+
+}  // namespace
+
+int launch_assemble(hdg_ctx* c, const double* lam_bnd) {
+    int grid = (int)std::min<int64_t>(c->n_faces, 65536);
+    if (c->precision == HDG_FP64)
+        hipLaunchKernelGGL((assemble_kernel<double>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
+                           c->bs, c->n_tr, c->nrhs, c->K_sign, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
+                           c->d_eface, (const double*)c->d_Ke, (const double*)c->d_re, lam_bnd, c->d_bsr,
+                           c->d_rhs);
+    else
+        hipLaunchKernelGGL((assemble_kernel<float>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
+                           c->bs, c->n_tr, c->nrhs, c->K_sign, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
+                           c->d_eface, (const float*)c->d_Ke, (const float*)c->d_re, lam_bnd, c->d_bsr,
+                           c->d_rhs);
+    return (int)hipGetLastError();
+}
+
+int launch_block_inverse(hdg_ctx* c) {
+    // the CG direction buffer doubles as Gauss-Jordan scratch (nf * bs * bs <= its size is
+    // guaranteed at allocation)
+    hipLaunchKernelGGL(block_inverse_kernel, dim3((unsigned)((c->n_faces + 63) / 64)), dim3(64), 0, c->stream,
+                       c->n_faces, c->nslot, c->bs, c->d_bsr, c->d_pinv, c->d_cg_q);
+    return (int)hipGetLastError();
+}
+
+static void spmv(hdg_ctx* c, const double* x, double* y) {
+    int64_t n = c->n_faces * c->bs * c->nrhs;
+    hipLaunchKernelGGL(bsr_spmv_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->nslot, c->bs,
+                       c->nrhs, c->d_bsr_cols, c->d_bsr, x, y);
+}
+
+static void precond(hdg_ctx* c, const double* x, double* y) {
+    int64_t n = c->n_faces * c->bs * c->nrhs;
+    hipLaunchKernelGGL(block_apply_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->bs, c->nrhs,
+                       c->d_pinv, x, y);
+}
+
+static void dot(hdg_ctx* c, const double* x, const double* y, double* out_dev) {
+    int64_t n = c->n_faces * c->bs;
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, c->nrhs, x, y,
+                       c->d_red);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(64), 0, c->stream, c->red_blocks, c->nrhs, c->d_red,
+                       out_dev);
+}
+
+int launch_lincomb(hdg_ctx* c, int64_t n, double a, const double* x, double b, const double* y, double* out) {
+    hipLaunchKernelGGL(lincomb_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, n, a, x, b, y, out);
+    return (int)hipGetLastError();
+}
+
+int launch_axpy(hdg_ctx* c, int64_t n, double alpha, const double* x, double* y) {
+    return launch_lincomb(c, n, alpha, x, 1.0, y, y);
+}
+
+int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out) {
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, 1, x, x, c->d_red);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(64), 0, c->stream, c->red_blocks, 1, c->d_red,
+                       c->d_scal + 7 * 32);
+    hipError_t e = hipMemcpyAsync(host_out, c->d_scal + 7 * 32, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return (int)e;
+    e = hipStreamSynchronize(c->stream);
+    *host_out = std::sqrt(*host_out);
+    return (int)e;
+}
+
+// Preconditioned CG on the assembled (sign-adjusted) system; all rhs columns iterate
+// together with their own scalars.  Convergence is checked on the host every iteration.
+int trace_cg(hdg_ctx* c, double* x, int* iters, double* relres) {
+    const int R = c->nrhs;
+    const int64_t n = c->n_faces * c->bs;
+    double* rr = c->d_cg_r;
+    double* zz = c->d_cg_z;
+    double* pp = c->d_cg_p;
+    double* qq = c->d_cg_q;
+    double* s_rz = c->d_scal;            // [R]
+    double* s_rz_new = c->d_scal + 32;   // [R]
+    double* s_pq = c->d_scal + 64;       // [R]
+    double* s_rr = c->d_scal + 96;       // [R]
+    double* s_bb = c->d_scal + 128;      // [R]
+    // boundary entries of x are the Dirichlet values (identity rows)
+    hipLaunchKernelGGL(copy_bnd_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, c->n_faces, c->bs, R,
+                       c->d_face_bnd, c->d_rhs, x);
+    spmv(c, x, qq);
+    launch_lincomb(c, n * R, 1.0, c->d_rhs, -1.0, qq, rr);
+    precond(c, rr, zz);
+    hipMemcpyAsync(pp, zz, n * R * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    dot(c, rr, zz, s_rz);
+    dot(c, c->d_rhs, c->d_rhs, s_bb);
+    std::vector<double> hb(R), hr(R);
+    hipMemcpyAsync(hb.data(), s_bb, R * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    hipStreamSynchronize(c->stream);
+    for (int r = 0; r < R; ++r) hb[r] = std::sqrt(hb[r]) > 0 ? std::sqrt(hb[r]) : 1.0;
+    int it = 0;
+    double worst = 0.0;
+    for (it = 0; it <= c->krylov_maxit; ++it) {
+        dot(c, rr, rr, s_rr);
+        hipMemcpyAsync(hr.data(), s_rr, R * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return HDG_E_HIP;
+        worst = 0.0;
+        for (int r = 0; r < R; ++r) worst = std::max(worst, std::sqrt(hr[r]) / hb[r]);
+        if (!(worst == worst)) break;
+        if (worst <= c->krylov_tol || it == c->krylov_maxit) break;
+        spmv(c, pp, qq);
+        dot(c, pp, qq, s_pq);
+        hipLaunchKernelGGL(axpy_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, 1.0,
+                           pp, x);
+        hipLaunchKernelGGL(axpy_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, -1.0,
+                           qq, rr);
+        precond(c, rr, zz);
+        dot(c, rr, zz, s_rz_new);
+        hipLaunchKernelGGL(xpby_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz_new, s_rz, zz,
+                           pp);
+        hipMemcpyAsync(s_rz, s_rz_new, R * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = worst;
+    c->last_iters = it;
+    if (!(worst <= c->krylov_tol)) return HDG_E_NOCONV;
+    return HDG_OK;
+}
+
+}  // namespace hdg

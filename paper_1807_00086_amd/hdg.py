@@ -1,0 +1,234 @@
+"""Thin ctypes binding of libhdg.so (include/hdg.h).
+
+Argument marshalling only: torch supplies device memory (``tensor.data_ptr()``) and the
+stream (``torch.cuda.current_stream().cuda_stream``); every step of the condensation path runs
+in the library's HIP kernels.  Importing this module never falls back to anything else: if
+the shared library is missing, loading fails with an error that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhdg.so")
+
+ACOUSTIC, ELASTIC, MAXWELL = 0, 1, 2
+FP64, MIXED_FP32 = 0, 1
+BACKWARD_EULER, DIRK33 = 0, 1
+PHYSICS = {"acoustic": ACOUSTIC, "elastic": ELASTIC, "maxwell": MAXWELL}
+PRECISION = {"fp64": FP64, "mixed_fp32": MIXED_FP32}
+STATUS = {0: "HDG_OK", 1: "HDG_E_ARG", 2: "HDG_E_MESH", 3: "HDG_E_ALLOC", 4: "HDG_E_HIP",
+          5: "HDG_E_SINGULAR", 6: "HDG_E_NOCONV", 7: "HDG_E_STATE", 8: "HDG_E_UNSUPPORTED"}
+Q = dict(n_elem=0, n_faces=1, n_bfaces=2, n_local_dofs=3, n_trace_dofs=4, n_vol_points=5,
+         n_bnd_points=6, last_iters=7, last_refine=8, m_local=9, m_trace=10)
+
+# every function declared in include/hdg.h
+EXPORTS = ["hdg_init_mesh", "hdg_query", "hdg_condense", "hdg_trace_solve", "hdg_recover",
+           "hdg_step", "hdg_apply_mass", "hdg_volume_points", "hdg_project_volume",
+           "hdg_boundary_points", "hdg_project_boundary", "hdg_point_sources",
+           "hdg_element_data", "hdg_last_timing", "hdg_reference_table", "hdg_destroy",
+           "hdg_last_error"]
+
+
+class HDGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_vert", C.c_int64), ("xyz", C.c_void_p),
+                ("n_elem", C.c_int64), ("elem_vert", C.c_void_p), ("degree", C.c_void_p)]
+
+
+class PhysDesc(C.Structure):
+    _fields_ = [("physics", C.c_int), ("elem_par", C.c_void_p), ("stab_scale", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("k", C.c_int), ("nrhs", C.c_int),
+                ("krylov_tol", C.c_double), ("krylov_maxit", C.c_int),
+                ("refine_tol", C.c_double), ("refine_maxit", C.c_int)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhdg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_1807_00086_amd.build` "
+                          "(or __graft_entry__.build()); there is no fallback implementation")
+    lib = C.CDLL(path)
+    vp, i64, dbl, cint = C.c_void_p, C.c_int64, C.c_double, C.c_int
+    sig = {
+        "hdg_init_mesh": (cint, [C.POINTER(vp), C.POINTER(MeshDesc), C.POINTER(PhysDesc),
+                                 C.POINTER(Options), vp]),
+        "hdg_query": (cint, [vp, cint, C.POINTER(i64)]),
+        "hdg_condense": (cint, [vp, dbl, vp, vp]),
+        "hdg_trace_solve": (cint, [vp, vp, C.POINTER(cint), C.POINTER(dbl)]),
+        "hdg_recover": (cint, [vp, vp, vp]),
+        "hdg_step": (cint, [vp, dbl, dbl, cint, vp, vp, vp, vp]),
+        "hdg_apply_mass": (cint, [vp, dbl, vp, vp]),
+        "hdg_volume_points": (cint, [vp, vp]),
+        "hdg_project_volume": (cint, [vp, vp, vp]),
+        "hdg_boundary_points": (cint, [vp, vp]),
+        "hdg_project_boundary": (cint, [vp, vp, vp]),
+        "hdg_point_sources": (cint, [vp, cint, vp, vp]),
+        "hdg_element_data": (cint, [vp, cint, i64, i64, vp]),
+        "hdg_last_timing": (cint, [vp, cint, C.POINTER(dbl)]),
+        "hdg_reference_table": (i64, [cint, cint, cint, cint, vp, i64]),
+        "hdg_destroy": (None, [vp]),
+        "hdg_last_error": (C.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    """Device pointer of a torch tensor or host pointer of a contiguous numpy array."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def reference_table(dim, k, kF, which):
+    lib = load_library()
+    cap = 8 * 6 * 200000
+    out = np.zeros(cap)
+    n = lib.hdg_reference_table(dim, k, kF, which, _ptr(out), cap)
+    if n < 0:
+        raise HDGError(-n, "hdg_reference_table failed")
+    return out[:n].copy()
+
+
+class Solver:
+    """One HDG context (mesh + physics + options) bound to a HIP stream."""
+
+    def __init__(self, xyz, elem_vert, physics, elem_par, k=None, degree=None, precision="fp64",
+                 nrhs=1, stab_scale=1.0, krylov_tol=1e-13, krylov_maxit=5000, refine_tol=1e-13,
+                 refine_maxit=10, stream=None):
+        self.lib = load_library()
+        self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self._ev = np.ascontiguousarray(elem_vert, dtype=np.int64)
+        par = np.zeros((self._ev.shape[0], 3))
+        ep = np.asarray(elem_par, dtype=np.float64)
+        par[:, :ep.shape[1]] = ep
+        self._par = np.ascontiguousarray(par)
+        self._deg = None if degree is None else np.ascontiguousarray(degree, dtype=np.int8)
+        self.dim = self._xyz.shape[1]
+        self.physics = PHYSICS[physics] if isinstance(physics, str) else int(physics)
+        self.nrhs = int(nrhs)
+        md = MeshDesc(self.dim, self._xyz.shape[0], _ptr(self._xyz).value, self._ev.shape[0],
+                      _ptr(self._ev).value, None if self._deg is None else _ptr(self._deg).value)
+        pd = PhysDesc(self.physics, _ptr(self._par).value, float(stab_scale))
+        prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        od = Options(prec, int(k if k is not None else (int(degree[0]) if degree is not None else 1)),
+                     self.nrhs, float(krylov_tol), int(krylov_maxit), float(refine_tol),
+                     int(refine_maxit))
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        self.ctx = C.c_void_p()
+        st = self.lib.hdg_init_mesh(C.byref(self.ctx), C.byref(md), C.byref(pd), C.byref(od),
+                                    C.c_void_p(stream))
+        if st != 0:
+            raise HDGError(st, self.lib.hdg_last_error(None).decode())
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, st):
+        if st != 0:
+            raise HDGError(st, self.lib.hdg_last_error(self.ctx).decode())
+
+    def query(self, key):
+        v = C.c_int64()
+        self._check(self.lib.hdg_query(self.ctx, Q[key] if isinstance(key, str) else key, C.byref(v)))
+        return v.value
+
+    def close(self):
+        if self.ctx:
+            self.lib.hdg_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ path
+    def condense(self, a, f_loc, lam_bnd):
+        self._check(self.lib.hdg_condense(self.ctx, float(a), _ptr(f_loc), _ptr(lam_bnd)))
+
+    def trace_solve(self, lam):
+        it = C.c_int()
+        rr = C.c_double()
+        self._check(self.lib.hdg_trace_solve(self.ctx, _ptr(lam), C.byref(it), C.byref(rr)))
+        return it.value, rr.value
+
+    def recover(self, lam, u):
+        self._check(self.lib.hdg_recover(self.ctx, _ptr(lam), _ptr(u)))
+
+    def step(self, t, dt, scheme, u, lam, lam_bnd_stages, src=None):
+        sc = {"be": BACKWARD_EULER, "dirk33": DIRK33}.get(scheme, scheme)
+        self._check(self.lib.hdg_step(self.ctx, float(t), float(dt), int(sc), _ptr(u), _ptr(lam),
+                                      _ptr(lam_bnd_stages), _ptr(src)))
+
+    def apply_mass(self, a, u, f):
+        self._check(self.lib.hdg_apply_mass(self.ctx, float(a), _ptr(u), _ptr(f)))
+
+    # ------------------------------------------------------------------ host helpers
+    def volume_points(self):
+        n = self.query("n_vol_points")
+        out = np.zeros((n, self.dim))
+        self._check(self.lib.hdg_volume_points(self.ctx, _ptr(out)))
+        return out
+
+    def project_volume(self, vals):
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        u = np.zeros(self.query("n_local_dofs"))
+        self._check(self.lib.hdg_project_volume(self.ctx, _ptr(vals), _ptr(u)))
+        return u
+
+    def boundary_points(self):
+        n = self.query("n_bnd_points")
+        out = np.zeros((n, self.dim))
+        self._check(self.lib.hdg_boundary_points(self.ctx, _ptr(out)))
+        return out
+
+    def project_boundary(self, vals):
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        lam = np.zeros(self.query("n_trace_dofs"))
+        self._check(self.lib.hdg_project_boundary(self.ctx, _ptr(vals), _ptr(lam)))
+        return lam
+
+    def point_sources(self, pts):
+        pts = np.ascontiguousarray(pts, dtype=np.float64)
+        f = np.zeros((self.query("n_local_dofs"), pts.shape[0]))
+        self._check(self.lib.hdg_point_sources(self.ctx, pts.shape[0], _ptr(pts), _ptr(f)))
+        return f
+
+    def element_data(self, which, e0, count, block):
+        out = np.zeros(count * block)
+        w = {"K": 0, "r": 1, "Z": 2, "z": 3}.get(which, which)
+        self._check(self.lib.hdg_element_data(self.ctx, w, int(e0), int(count), _ptr(out)))
+        return out
+
+    def timing(self, which):
+        ms = C.c_double()
+        w = {"condense": 0, "assemble": 1, "solve": 2, "recover": 3, "refine_elem": 4,
+             "refine_solve": 5}.get(which, which)
+        self._check(self.lib.hdg_last_timing(self.ctx, w, C.byref(ms)))
+        return ms.value

@@ -5,6 +5,7 @@ vertex jitter, per-element material coefficients, polynomial degrees and point-s
 locations.  It contains none of the discretisation's arithmetic (no basis, quadrature,
 local matrices or solves), so that the oracle and the GPU library stay independent.
 """
+from .rhs import random_vector  # noqa: F401
 from .meshes import (  # noqa: F401
     Problem,
     unit_square_tris,

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle on the same
+seeded inputs.
+
+Tolerances (relative, per field, L2(Omega) norm = |J|-weighted coefficient norm):
+  FP64 mode              1e-12 (stage solution), 1e-11 element-wise (K_e, r_e, Z, z)
+  mixed FP32 + refinement 1e-10 (after refinement; the FP32 factors alone give ~1e-6)
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from synth import make_problem, random_vector
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle():
+    from oracle import hdg as ohdg
+    return ohdg
+
+
+def _solver(p, precision="fp64", **kw):
+    from paper_1807_00086_amd import Solver
+    return Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=int(p.degree[0]),
+                  precision=precision, nrhs=p.nrhs, **kw)
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _rel_field_errors(ohdg, d, u_gpu, u_ref):
+    out = []
+    groups = {"acoustic": [list(range(d.dim)), [d.dim]], "elastic": [list(range(6)), [6, 7, 8]],
+              "maxwell": [[0, 1, 2], [3, 4, 5]]}[d.physics]
+    for g in groups:
+        num = ohdg.l2_norm_fields(d, u_gpu - u_ref, g)
+        den = ohdg.l2_norm_fields(d, u_ref, g)
+        out.append(num / max(den, 1e-300))
+    return out
+
+
+def _gpu_stage(s, a, f, lb):
+    fd, lbd = _dev(f), _dev(lb)
+    s.condense(a, fd, lbd)
+    lam = torch.zeros_like(lbd)
+    it, rr = s.trace_solve(lam)
+    u = torch.zeros_like(fd)
+    s.recover(lam, u)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), lam.cpu().numpy(), it, rr
+
+
+CASES = [
+    (1, dict()),                     # 2D acoustic workload itself: 8x8 -> 128 triangles, k=2
+    (1, dict(n=5, k=3)),
+    (1, dict(n=3, k=1)),
+    (2, dict(n=2, k=1)),
+    (2, dict(n=2, k=2)),
+    (2, dict(n=3, k=3)),             # 162 tets: several workgroup waves, ragged
+    (2, dict(n=2, k=4)),
+]
+
+
+@pytest.mark.parametrize("cfg,kw", CASES)
+def test_stage_parity_fp64(cfg, kw):
+    _need_gpu()
+    ohdg = _oracle()
+    p = make_problem(cfg, **kw)
+    print(f"case cfg={cfg} {kw} n_elem={p.n_elem}", flush=True)
+    d = ohdg.make_discretisation(p)
+    a = 1.0 / (0.43586652150845899 * p.dt)
+    f = random_vector(d.loc_off[-1], cfg, 1)
+    lb = random_vector(d.tr_off[-1], cfg, 2) * ohdg.boundary_trace_mask(d)
+    u_ref, lam_ref, cond = ohdg.solve_stage(d, a, f, lb)
+    s = _solver(p)
+    u, lam, it, rr = _gpu_stage(s, a, f, lb)
+    assert rr <= 1e-13
+    errs = _rel_field_errors(ohdg, d, u, u_ref)
+    assert max(errs) <= 1e-12, errs
+    assert np.linalg.norm(lam - lam_ref) <= 1e-12 * np.linalg.norm(lam_ref)
+    # element-wise quantities of the condensation
+    n, t = s.query("n_local_dofs") // p.n_elem, (d.dim + 1) * d.m_trace * (d.tr_off[1] - d.tr_off[0]) // d.m_trace
+    ne = p.n_elem
+    Ke = s.element_data("K", 0, ne, t * t).reshape(ne, t, t)
+    re = s.element_data("r", 0, ne, t).reshape(ne, t)
+    Z = s.element_data("Z", 0, ne, n * t).reshape(ne, n, t)
+    z = s.element_data("z", 0, ne, n).reshape(ne, n)
+    for e in range(0, ne, max(1, ne // 17)):
+        sc = np.abs(cond.Ke[e]).max()
+        assert np.abs(Ke[e] - cond.Ke[e]).max() <= 1e-11 * sc
+        assert np.abs(re[e] - cond.re[e][:, 0]).max() <= 1e-11 * max(np.abs(cond.re[e]).max(), 1e-300)
+        assert np.abs(Z[e] - cond.Z[e]).max() <= 1e-11 * np.abs(cond.Z[e]).max()
+        assert np.abs(z[e] - cond.z[e][:, 0]).max() <= 1e-11 * np.abs(cond.z[e]).max()
+    s.close()
+
+
+def test_stage_parity_repeatable_bitwise():
+    """Owner-computes assembly and fixed reduction order: two runs give identical bits."""
+    _need_gpu()
+    p = make_problem(2, n=3, k=2)
+    s = _solver(p)
+    nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+    f = random_vector(nl, 2, 1)
+    lb = random_vector(nt, 2, 2)
+    u1, l1, _, _ = _gpu_stage(s, 50.0, f, lb)
+    u2, l2, _, _ = _gpu_stage(s, 50.0, f, lb)
+    assert np.array_equal(u1, u2) and np.array_equal(l1, l2)
+
+
+def test_full_size_acoustic3d_sampled():
+    """The 82,944-element acoustic workload at full size, as the benchmark runs it: sampled
+    element-level parity against the oracle, and the local equations A u + B lam = f of
+    sampled elements hold for the recovered fields."""
+    _need_gpu()
+    ohdg = _oracle()
+    p = make_problem(2)
+    d = ohdg.make_discretisation(p)
+    a = 1.0 / (0.43586652150845899 * p.dt)
+    s = _solver(p)
+    nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+    assert nl == d.loc_off[-1] and nt == d.tr_off[-1]
+    f = random_vector(nl, 2, 11)
+    lb = random_vector(nt, 2, 12)
+    u, lam, it, rr = _gpu_stage(s, a, f, lb)
+    assert rr <= 1e-13
+    n, t = 80, 40
+    rng = np.random.default_rng(5)
+    sample = np.unique(np.concatenate([[0, 1, p.n_elem - 1], rng.integers(0, p.n_elem, 300)]))
+    for e in sample:
+        A, B, Cm, Dm, _ = ohdg.element_system(d, int(e), a)
+        li, ti = d.elem_local_dofs(e), d.elem_trace_dofs(e)
+        Ke_ref = Dm - Cm @ np.linalg.solve(A, B)
+        Ke = s.element_data("K", int(e), 1, t * t).reshape(t, t)
+        assert np.abs(Ke - Ke_ref).max() <= 1e-11 * np.abs(Ke_ref).max()
+        res = A @ u[li] + B @ lam[ti] - f[li]
+        assert np.linalg.norm(res) <= 1e-11 * np.linalg.norm(f[li])
+    # trace equations on sampled interior faces: sum_K (C u + D lam) = 0
+    bm = ohdg.boundary_trace_mask(d)
+    faces = rng.integers(0, d.skel.n_faces, 200)
+    for F in faces:
+        if d.skel.is_boundary[F]:
+            sl = slice(d.tr_off[F], d.tr_off[F + 1])
+            assert np.allclose(lam[sl], lb[sl], rtol=0, atol=1e-14)
+            continue
+        acc = 0.0
+        scale = 0.0
+        for e in d.skel.face_elems[F]:
+            A, B, Cm, Dm, _ = ohdg.element_system(d, int(e), a)
+            li, ti = d.elem_local_dofs(e), d.elem_trace_dofs(e)
+            f_loc = list(d.skel.elem_faces[e]).index(F)
+            rows = slice(f_loc * 10, (f_loc + 1) * 10)
+            acc = acc + (Cm @ u[li] + Dm @ lam[ti])[rows]
+            scale = max(scale, np.abs(Cm[rows] @ u[li]).max())
+        assert np.abs(acc).max() <= 1e-10 * scale
+    s.close()
+
+
+def test_dirk_step_parity_fp64():
+    """Two DIRK(3,3) steps through hdg_step against the oracle's stage recursion."""
+    _need_gpu()
+    ohdg = _oracle()
+    p = make_problem(2, n=2, k=2)
+    d = ohdg.make_discretisation(p)
+    u0 = random_vector(d.loc_off[-1], 2, 21)
+    bm = ohdg.boundary_trace_mask(d)
+    _, _, c = ohdg.dirk33()
+    dt = 0.01
+    lbs = {}
+    for n in range(2):
+        for i in range(3):
+            lbs[round(n * dt + c[i] * dt, 12)] = random_vector(d.tr_off[-1], 2, 100 + 3 * n + i) * bm
+    u_ref = u0.copy()
+    for n in range(2):
+        u_ref = ohdg.dirk_step(d, u_ref, n * dt, dt, lambda t: lbs[round(t, 12)])
+    s = _solver(p)
+    u = _dev(u0)
+    lam = torch.zeros(d.tr_off[-1], dtype=torch.float64, device="cuda")
+    for n in range(2):
+        stages = np.stack([lbs[round(n * dt + c[i] * dt, 12)] for i in range(3)])
+        s.step(n * dt, dt, "dirk33", u, lam, _dev(stages))
+    torch.cuda.synchronize()
+    errs = _rel_field_errors(ohdg, d, u.cpu().numpy(), u_ref)
+    assert max(errs) <= 1e-12, errs
+    s.close()
+
+
+def test_apply_mass_and_projections():
+    """Stage-glue mass application and the projection helpers against the oracle (a
+    polynomial field, integrated exactly by both quadrature rules)."""
+    _need_gpu()
+    ohdg = _oracle()
+    p = make_problem(2, n=2, k=3)
+    d = ohdg.make_discretisation(p)
+    s = _solver(p)
+    u = random_vector(d.loc_off[-1], 2, 31)
+    f = torch.zeros(d.loc_off[-1], dtype=torch.float64, device="cuda")
+    s.apply_mass(7.0, _dev(u), f)
+    torch.cuda.synchronize()
+    ref = ohdg.apply_mass(d, u, 7.0)
+    assert np.abs(f.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+    def poly(x, t=0.0):
+        return np.stack([x[:, 0] ** 2, x[:, 1] * x[:, 2], x[:, 0] ** 3 - x[:, 2], 1 + x[:, 0] * x[:, 1]], 1)
+    up = s.project_volume(poly(s.volume_points()))
+    assert np.abs(up - ohdg.project_volume(d, poly)).max() <= 1e-12
+    bp = s.boundary_points()
+    lam = s.project_boundary(poly(bp)[:, 3])
+    lref = ohdg.project_boundary(d, lambda x, t: poly(x)[:, 3])
+    assert np.abs(lam - lref).max() <= 1e-12
+    s.close()
+
+
+def test_singular_pivot_reported():
+    """Local blocks that cannot be factored are reported as HDG_E_SINGULAR by the next
+    synchronising call (forced from the host with an infinite-impedance material, which
+    removes the mass and stabilisation terms from the Schur block; no device fault)."""
+    _need_gpu()
+    from paper_1807_00086_amd import HDGError
+    p = make_problem(2, n=1, k=2)
+    p.elem_par[:, 1] = 1e300
+    s = _solver(p)
+    nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+    s.condense(1.0, _dev(np.ones(nl)), _dev(np.zeros(nt)))
+    lam = torch.zeros(nt, dtype=torch.float64, device="cuda")
+    with pytest.raises(HDGError) as ei:
+        s.trace_solve(lam)
+    assert ei.value.code == 5
+    s.close()
+
+
+def test_nonfinite_rhs_reports_noconv():
+    _need_gpu()
+    from paper_1807_00086_amd import HDGError
+    p = make_problem(2, n=1, k=1)
+    s = _solver(p)
+    nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+    s.condense(1.0, _dev(np.full(nl, np.nan)), _dev(np.zeros(nt)))
+    lam = torch.zeros(nt, dtype=torch.float64, device="cuda")
+    with pytest.raises(HDGError) as ei:
+        s.trace_solve(lam)
+    assert ei.value.code == 6
+    s.close()
