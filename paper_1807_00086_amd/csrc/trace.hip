@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <limits>
 #include <vector>
 
 #include "internal.h"
@@ -330,8 +331,16 @@ int trace_cg(hdg_ctx* c, double* x, int* iters, double* relres) {
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return HDG_E_HIP;
         worst = 0.0;
-        for (int r = 0; r < R; ++r) worst = std::max(worst, std::sqrt(hr[r]) / hb[r]);
-        if (!(worst == worst)) break;
+        bool nonfinite = false;
+        for (int r = 0; r < R; ++r) {
+            double v = std::sqrt(hr[r]) / hb[r];
+            if (!(v - v == 0.0)) nonfinite = true;   // NaN or inf (std::max would drop a NaN)
+            else worst = std::max(worst, v);
+        }
+        if (nonfinite) {
+            worst = std::numeric_limits<double>::quiet_NaN();
+            break;
+        }
         if (worst <= c->krylov_tol || it == c->krylov_maxit) break;
         spmv(c, pp, qq);
         dot(c, pp, qq, s_pq);
