@@ -35,22 +35,30 @@ def dimp(k, d):
     return {1: k + 1, 2: (k + 1) * (k + 2) // 2, 3: (k + 1) * (k + 2) * (k + 3) // 6}[d]
 
 
-def acoustic_counts(D, K, R, elt_bytes):
+def acoustic_counts(D, K, R, elt_bytes, mixed=False):
     """Algorithmic HBM bytes and executed flops per element of the acoustic condensation
-    kernel (see condense_acoustic.hip) and bytes of the recovery GEMV."""
+    kernel (condense_acoustic.hip: closed-form velocity elimination, Cholesky of the pressure
+    Schur block, K = D - B_v^T B_v/(a rho |J|) + W^T W) and of the recovery kernel.  Reads of
+    the degree-dependent reference tables hit the caches and are not counted as HBM traffic."""
     N, NF, NFACE = dimp(K, D), dimp(K, D - 1), D + 1
     TT, NLOC = NFACE * NF, (D + 1) * N
     C = TT + R
     npair = D * (D + 1) // 2
-    fma = (N * N * (NFACE + npair) + NFACE * N * N * D + D * N * R * D + N * TT * N + N * R * D * N
-           + N ** 3 / 3 + N * N * C + D * N * C * N + TT * D * N * D + NFACE * N * C * 2 * D
-           + NFACE * NF * C * N)
-    flops = 2.0 * fma
+    fma = (N * R * D * N * (D + 1)          # condensed pressure rhs
+           + NFACE * N * N * D              # W_f = tau I + sum_r beta_fr Sr_r
+           + NFACE * N * NF * N             # B~_f = -s_f W_f E_f
+           + N * N * (NFACE + npair)        # S from reference tables
+           + N ** 3 / 6.0                   # Cholesky
+           + C * N * N / 2.0                # L^{-1} [B~ | f~]
+           + 2 * TT * TT * N                # W^T W and E^T E
+           + TT * R * N * (D + 2)           # r_e
+           + C * N * N / 2.0)               # L^{-T} [W | w]
     reads = NLOC * R * 8 + 32 * 8 + NFACE * 4
-    writes = (TT * TT + TT * R + NLOC * TT + NLOC * R) * elt_bytes
-    cond_bytes = reads + writes
-    rec_bytes = NLOC * TT * elt_bytes + NLOC * R * elt_bytes + TT * R * 8 + NLOC * R * 8 + NFACE * 4
-    return dict(cond_bytes=cond_bytes, cond_flops=flops, rec_bytes=rec_bytes, rec_flops=2.0 * NLOC * TT * R)
+    writes = (TT * TT + TT * R + N * TT + NLOC * R + (N * N if mixed else 0)) * elt_bytes
+    rec_bytes = (N * TT + NLOC * R) * elt_bytes + TT * R * 8 + 32 * 8 + 2 * NFACE * 4 + NLOC * R * 8
+    rec_fma = N * TT * R + D * N * R * (NFACE * NF + D * N)
+    return dict(cond_bytes=reads + writes, cond_flops=2.0 * fma, rec_bytes=rec_bytes,
+                rec_flops=2.0 * rec_fma)
 
 
 def cpu_baseline(problem, a, budget_s=15.0):
@@ -88,32 +96,17 @@ def cpu_baseline(problem, a, budget_s=15.0):
                        f"{el:.1f} s, 1 BLAS thread, per-element form+factor+Schur+recover")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed_fp32"])
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the element kernels shard "
-                                   "by element partition, see the design notes", "n_gpus": args.gpus}))
-        sys.exit(2)
-
+def run_precision(p, prec, steps, warmup, keep_solution=False):
+    """Time `steps` whole stages in one precision; returns timings and (optionally) the
+    final stage solution on the host."""
     import torch
 
     from paper_1807_00086_amd import Solver
-    from synth import make_problem
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    p = make_problem(2)
     k = int(p.degree[0])
     a = 1.0 / (GAMMA * p.dt)
-    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=k, precision=args.precision)
+    kw = dict(krylov_tol=1e-13) if prec == "fp64" else dict(krylov_tol=1e-8, refine_tol=1e-12)
+    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=k, precision=prec, **kw)
     nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
-
     # inputs: projected plane wave p0 = sin(2 pi x), v0 = (p0, 0, 0); Dirichlet p = sin 2pi(x - t)
     vp = s.volume_points()
     p0 = np.sin(2 * np.pi * vp[:, 0])
@@ -131,36 +124,99 @@ def main():
     def stage():
         s.condense(a, f_d, lb_d)
         lam.zero_()
-        it, rr = s.trace_solve(lam)
+        it, _ = s.trace_solve(lam)
         s.recover(lam, u)
-        return it, rr
+        return it
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         stage()
     torch.cuda.synchronize()
-    t_cond = t_rec = t_asm = t_sol = t_ref = 0.0
-    iters = []
+    tm = dict(condense=0.0, recover=0.0, assemble=0.0, solve=0.0, refine_elem=0.0, refine_solve=0.0)
+    iters, refs = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        it, rr = stage()
-        iters.append(it)
-        t_cond += s.timing("condense")
-        t_rec += s.timing("recover")
-        t_asm += s.timing("assemble")
-        t_sol += s.timing("solve")
-        t_ref += s.timing("refine_elem")
+    for _ in range(steps):
+        iters.append(stage())
+        refs.append(s.query("last_refine"))
+        for key in tm:
+            tm[key] += s.timing(key)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_step = 1e3 * wall / args.steps
-    elem_ms = t_cond + t_rec + t_ref
-    value = p.n_elem * args.steps / (elem_ms * 1e-3)
+    out = dict(ms_step=1e3 * wall / steps, iters=float(np.mean(iters)), refine=float(np.mean(refs)),
+               **{k2: v / steps for k2, v in tm.items()})
+    if keep_solution:
+        out["u"] = u.cpu().numpy()
+        out["lam"] = lam.cpu().numpy()
+    s.close()
+    del f_d, u0_d, lb_d, lam, u
+    torch.cuda.empty_cache()
+    return out
 
-    eb = 8 if args.precision == "fp64" else 4
-    cnt = acoustic_counts(3, k, 1, eb)
-    cond_avg_s = t_cond / args.steps * 1e-3
-    achieved_gbs = cnt["cond_bytes"] * p.n_elem / cond_avg_s / 1e9
-    achieved_tf = cnt["cond_flops"] * p.n_elem / cond_avg_s / 1e12
-    rec_gbs = cnt["rec_bytes"] * p.n_elem / (t_rec / args.steps * 1e-3) / 1e9
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed_fp32"])
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = 1 << 27                                   # 2^27 doubles = 1 GiB
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes_read": 8 * n, "calibration_copy_bytes_written": 8 * n}))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only (the element kernels shard by "
+                                   "element partition; nothing here uses a second GPU)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from synth import make_problem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    p = make_problem(2)
+    k = int(p.degree[0])
+    a = 1.0 / (GAMMA * p.dt)
+    precs = ["fp64", "mixed_fp32"] if args.precision == "both" else [args.precision]
+    res = {pr: run_precision(p, pr, args.steps, args.warmup, keep_solution=(len(precs) == 2))
+           for pr in precs}
+
+    def elem_rate(r):
+        return p.n_elem / ((r["condense"] + r["recover"] + r["refine_elem"]) * 1e-3)
+
+    equal_error = None
+    if len(precs) == 2:
+        u64, u32 = res["fp64"]["u"].reshape(p.n_elem, 4, -1), res["mixed_fp32"]["u"].reshape(p.n_elem, 4, -1)
+        X = p.xyz[p.elem_vert]
+        dj = np.abs(np.linalg.det(np.transpose(X[:, 1:, :] - X[:, :1, :], (0, 2, 1))))[:, None, None]
+        errs = {}
+        for name, comps in (("v", [0, 1, 2]), ("p", [3])):
+            num = np.sqrt(np.sum(dj * (u32[:, comps] - u64[:, comps]) ** 2))
+            den = np.sqrt(np.sum(dj * u64[:, comps] ** 2))
+            errs[name] = float(num / den)
+        equal_error = errs
+        ok = max(errs.values()) <= 1e-10
+        head = "mixed_fp32" if ok and elem_rate(res["mixed_fp32"]) > elem_rate(res["fp64"]) else "fp64"
+    else:
+        head = precs[0]
+    r = res[head]
+    value = elem_rate(r)
+    eb = 8 if head == "fp64" else 4
+    cnt = acoustic_counts(3, k, 1, eb, mixed=head != "fp64")
+    cond_s = r["condense"] * 1e-3
+    achieved_gbs = cnt["cond_bytes"] * p.n_elem / cond_s / 1e9
+    achieved_tf = cnt["cond_flops"] * p.n_elem / cond_s / 1e12
+    rec_gbs = cnt["rec_bytes"] * p.n_elem / (r["recover"] * 1e-3) / 1e9
     out = {
         "metric": "elements/s for batched HDG condensation+recovery, mixed vs FP64 at equal error",
         "value": value,
@@ -168,33 +224,28 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "acoustic3d_kuhn24_k3_dirk33_stage", "elements": p.n_elem, "k": k,
-                   "local_unknowns": 80, "trace_unknowns": 40, "precision": args.precision,
+                   "local_unknowns": 80, "trace_unknowns": 40, "precision": head,
                    "parallelism": "single GPU"},
-        "value_basis": "element kernels only (condense + recover [+ refinement element work]); "
-                       "ms_per_step includes assembly and the FP64 trace solve",
-        "ms_condense": t_cond / args.steps,
-        "ms_recover": t_rec / args.steps,
-        "ms_assemble": t_asm / args.steps,
-        "ms_trace_solve": t_sol / args.steps,
-        "ms_refine_elem": t_ref / args.steps,
-        "krylov_iters": float(np.mean(iters)),
-        "stage_elements_per_s": p.n_elem / (ms_step * 1e-3),
+        "value_basis": "element kernels only (condense + recover + refinement element work) per stage; "
+                       "ms_per_step is the whole stage including assembly and FP64 trace solves",
+        "per_precision": {pr: {kk: vv for kk, vv in rr.items() if kk not in ("u", "lam")} | {
+            "elements_per_s": elem_rate(rr)} for pr, rr in res.items()},
+        "mixed_vs_fp64_rel_l2": equal_error,
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "condense_acoustic_kernel<3,3,1>",
+                     "kernel": f"condense_acoustic_kernel<3,3,1,{'double' if head == 'fp64' else 'float'}>",
                      "bytes_per_element": cnt["cond_bytes"], "flops_per_element": cnt["cond_flops"],
-                     "flop_frac_fp64": achieved_tf / FP64_PEAK_TFLOPS},
+                     "flop_frac_fp64_peak": achieved_tf / FP64_PEAK_TFLOPS},
         "recover_roofline": {"bound": "hbm", "achieved": rec_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": rec_gbs / HBM_PEAK_GBS, "bytes_per_element": cnt["rec_bytes"]},
     }
-    s.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, a, args.cpu_budget)
     print(json.dumps(out))

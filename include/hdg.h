@@ -156,7 +156,9 @@ hdg_status hdg_trace_solve(hdg_ctx* ctx, double* lambda, int* iters, double* rel
  * relative to the right-hand side (lambda is refined in place as well).
  *   lambda   device [n_trace_dofs][nrhs] FP64 (in; in/out in mixed mode)
  *   u_loc    device [n_local_dofs][nrhs] FP64 out
- * HDG_E_NOCONV when refinement stalls.
+ * HDG_E_NOCONV when refinement stalls.  In mixed mode the refinement reuses the
+ * condensation buffers: a second hdg_recover needs a new hdg_condense (HDG_E_STATE).
+ * The inner trace solves of the refinement use krylov_tol.
  */
 hdg_status hdg_recover(hdg_ctx* ctx, double* lambda, double* u_loc);
 
@@ -200,8 +202,10 @@ hdg_status hdg_point_sources(const hdg_ctx* ctx, int n_src, const double* pts, d
 /*
  * hdg_element_data -- copy per-element results of the last condense to the host as FP64
  * (inspection / parity testing).  which: 0 = K_e [t][t], 1 = r_e [t][nrhs],
- * 2 = Z [n][t], 3 = z [n][nrhs].  Elements [e0, e0+count) must share one degree;
- * out holds count * block doubles.
+ * 2 = Z_s [n_s][t], 3 = z_s [n_s][nrhs]: the rows of Z = A^{-1} B and z = A^{-1} f that
+ * belong to the densely factored block (acoustic p, elastic v, maxwell E; n_s of them per
+ * element); the eliminated block is reconstructed in closed form at recovery.  Elements
+ * [e0, e0+count) must share one degree; out holds count * block doubles.
  */
 hdg_status hdg_element_data(hdg_ctx* ctx, int which, int64_t e0, int64_t count, double* out);
 

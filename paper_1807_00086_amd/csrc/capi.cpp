@@ -158,7 +158,9 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     c->n_local_dofs = c->n_elem * c->n_loc;
     c->n_trace_dofs = c->n_faces * c->bs;
     c->K_sign = (c->physics == HDG_ACOUSTIC) ? -1.0 : 1.0;
-    c->Ns = c->N;
+    // densely factored (Schur) block: acoustic p, elastic v, maxwell E
+    c->Ns = (c->physics == HDG_ACOUSTIC) ? c->N : 3 * c->N;
+    c->s_row0 = (c->physics == HDG_ACOUSTIC) ? d * c->N : (c->physics == HDG_ELASTIC ? 6 * c->N : 3 * c->N);
     if (!supported(c)) {
         std::ostringstream os;
         os << "configuration not built: physics " << c->physics << ", k " << kk << ", nrhs " << c->nrhs;
@@ -195,11 +197,12 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(upload_f32(c, &c->tab.Tsym32, c->ref.Tsym));
     TRY(upload_f32(c, &c->tab.Ef32, c->reff.E));
 
+
     const size_t tsz = (c->precision == HDG_FP64) ? sizeof(double) : sizeof(float);
     const int64_t ne = c->n_elem, R = c->nrhs;
     TRY(dalloc(c, (char**)&c->d_Ke, ne * c->n_tr * c->n_tr * tsz));
     TRY(dalloc(c, (char**)&c->d_re, ne * c->n_tr * R * tsz));
-    TRY(dalloc(c, (char**)&c->d_Zt, ne * c->n_tr * c->n_loc * tsz));
+    TRY(dalloc(c, (char**)&c->d_Zt, ne * c->n_tr * c->Ns * tsz));
     TRY(dalloc(c, (char**)&c->d_z, ne * c->n_loc * R * tsz));
     if (c->precision == HDG_MIXED_FP32) TRY(dalloc(c, (char**)&c->d_LU, ne * c->Ns * c->Ns * tsz));
     TRY(dalloc(c, &c->d_status, 1));
@@ -218,6 +221,10 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     if (c->precision == HDG_MIXED_FP32) {
         TRY(dalloc(c, &c->d_f_saved, nl));
         TRY(dalloc(c, &c->d_lbnd_saved, ntr * R));
+        TRY(dalloc(c, &c->d_du, nl));
+        TRY(dalloc(c, &c->d_dlam, ntr * R));
+        TRY(dalloc(c, &c->d_re64, ne * c->n_tr * R));
+        TRY(dalloc(c, &c->d_sq, ne));
     }
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         g_init_err = "hipEventCreate failed";
@@ -284,6 +291,7 @@ hdg_status hdg_condense(hdg_ctx* c, double a, const double* f_loc, const double*
     if (e) return fail(c, HDG_E_HIP, "assembly kernel launch failed");
     c->last_a = a;
     c->condensed = true;
+    c->z_consumed = false;
     return HDG_OK;
 }
 
@@ -307,6 +315,9 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
     if (!c) return HDG_E_ARG;
     if (!lambda || !u) return fail(c, HDG_E_ARG, "null lambda or u");
     if (!c->condensed) return fail(c, HDG_E_STATE, "hdg_recover before hdg_condense");
+    if (c->z_consumed)
+        return fail(c, HDG_E_STATE, "mixed precision: the refinement of the previous hdg_recover used the "
+                                    "condensation buffers; call hdg_condense again");
     int s = check_status(c);
     if (s) return s;
     int e;
@@ -316,7 +327,54 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
     }
     if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
     c->last_refine = 0;
-    return HDG_OK;
+    c->tim.refine_elem = 0.f;
+    c->tim.refine_solve = 0.f;
+    if (c->precision != HDG_MIXED_FP32) return HDG_OK;
+
+    // Iterative refinement of the full stage system: FP64 residual, correction through the
+    // FP32 factors and an FP64 trace solve, until the correction is below refine_tol.
+    c->z_consumed = true;
+    const int64_t nl = c->n_local_dofs * c->nrhs, nt = c->n_trace_dofs * c->nrhs;
+    double prev = 0.0;
+    for (int it = 1; it <= c->refine_maxit; ++it) {
+        float t_res = 0.f, t_sol = 0.f, t_rec = 0.f;
+        {
+            EventTimer t(c, &t_res);
+            e = launch_refine_residual(c, u, lambda, c->d_sq);
+            if (!e) e = launch_assemble_rhs64(c, c->d_re64);
+        }
+        if (e) return fail(c, HDG_E_HIP, "refinement kernel launch failed");
+        HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
+        int r;
+        {
+            EventTimer t(c, &t_sol);
+            int its;
+            double rr;
+            r = trace_cg(c, c->d_dlam, &its, &rr);
+        }
+        if (r && r != HDG_E_NOCONV) return fail(c, r, "refinement trace solve failed");
+        {
+            EventTimer t(c, &t_rec);
+            e = launch_recover(c, c->d_dlam, c->d_du, false);
+        }
+        if (e) return fail(c, HDG_E_HIP, "refinement recovery launch failed");
+        c->tim.refine_elem += t_res + t_rec;
+        c->tim.refine_solve += t_sol;
+        launch_axpy(c, nl, 1.0, c->d_du, u);
+        launch_axpy(c, nt, 1.0, c->d_dlam, lambda);
+        double ndu, nu, ndl, nlam;
+        launch_norm2(c, nl, c->d_du, &ndu);
+        launch_norm2(c, nl, u, &nu);
+        launch_norm2(c, nt, c->d_dlam, &ndl);
+        launch_norm2(c, nt, lambda, &nlam);
+        const double rel = std::max(ndu / (nu > 0 ? nu : 1.0), ndl / (nlam > 0 ? nlam : 1.0));
+        c->last_refine = it;
+        if (!(rel == rel)) return fail(c, HDG_E_NOCONV, "refinement produced a non-finite correction");
+        if (rel <= c->refine_tol) return HDG_OK;
+        if (it > 1 && rel > 0.5 * prev) return fail(c, HDG_E_NOCONV, "refinement stagnated");
+        prev = rel;
+    }
+    return fail(c, HDG_E_NOCONV, "refinement did not reach refine_tol within refine_maxit");
 }
 
 hdg_status hdg_apply_mass(hdg_ctx* c, double a, const double* u, double* f) {
@@ -519,25 +577,26 @@ hdg_status hdg_element_data(hdg_ctx* c, int which, int64_t e0, int64_t count, do
     const int64_t R = c->nrhs, n = c->n_loc, t = c->n_tr;
     int64_t blk;
     void* src;
+    const int64_t ns = c->Ns;
     switch (which) {
         case 0: blk = t * t; src = c->d_Ke; break;
         case 1: blk = t * R; src = c->d_re; break;
-        case 2: blk = n * t; src = c->d_Zt; break;
+        case 2: blk = ns * t; src = c->d_Zt; break;
         default: blk = n * R; src = c->d_z; break;
     }
     const size_t tsz = (c->precision == HDG_FP64) ? sizeof(double) : sizeof(float);
     std::vector<char> buf(count * blk * tsz);
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(buf.data(), (char*)src + e0 * blk * tsz, buf.size(), hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < count * blk; ++i) {
-        double v = (tsz == 8) ? ((double*)buf.data())[i] : (double)((float*)buf.data())[i];
-        if (which == 2) {   // stored column-major per element: [c][row] -> [row][c]
-            int64_t e = i / blk, rem = i % blk, col = rem / n, row = rem % n;
-            out[e * blk + row * t + col] = v;
-        } else {
-            out[i] = v;
+    const int64_t oblk = (which == 3) ? ns * R : blk;
+    for (int64_t e = 0; e < count; ++e)
+        for (int64_t i = 0; i < oblk; ++i) {
+            // which == 3: only the Schur-block rows of z are A^{-1} f (the eliminated rows hold
+            // the closed-form part applied at recovery)
+            int64_t src_i = (which == 3) ? c->s_row0 * R + i : i;
+            int64_t k = e * blk + src_i;
+            out[e * oblk + i] = (tsz == 8) ? ((double*)buf.data())[k] : (double)((float*)buf.data())[k];
         }
-    }
     return HDG_OK;
 }
 
@@ -557,6 +616,7 @@ void hdg_destroy(hdg_ctx* c) {
                     c->tab.Tsym32, c->tab.Ef32, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
                     c->d_bsr, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
                     c->d_scal, c->d_f_saved, c->d_lbnd_saved, c->d_su, c->d_slam, c->d_du, c->d_dlam,
+                    c->d_re64, c->d_sq,
                     c->d_stage, c->d_ustar, c->d_fstage};
     if (c->stream || c->d_geom) (void)hipStreamSynchronize(c->stream);
     for (void* p : ptrs) dfree(p);

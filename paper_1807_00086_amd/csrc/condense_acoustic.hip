@@ -5,15 +5,20 @@
 //   Q_x = |J| sum_r G_rx Sr_r  (Q_x[i][j] = (phi_i, d phi_j / d x_x)_K),
 //   B = [[n_fx s_f E_f], [-tau s_f E_f]],  C = [[n_fx s_f E_f^T, tau s_f E_f^T]],
 //   D = -tau s_f I on each face block,
-// where G = J^{-1}, s_f the face measure over the reference-face measure, E_f the oriented
-// volume-trace face table.  The velocity block is diagonal, so LU without pivoting reduces
-// to the pressure Schur block
-//   S = a|J|/(rho c^2) I + tau sum_f s_f Mf_f + (|J| / (a rho)) sum_{r,s} (G G^T)_rs Sr_r Sr_s^T,
-// (the last sum uses the precomputed symmetric products), followed by
-//   [Z_p | z_p] = S^{-1} [B~ | f~],  B~_f = -s_f (tau I + (1/(a rho)) sum_r beta_fr Sr_r) E_f,
-//   beta_fr = sum_x G_rx n_fx,  f~ = f_p - (1/(a rho)) sum_r Sr_r (sum_x G_rx f_vx),
-//   Z_v,x = (1/(a rho)) (n_fx s_f E_f / |J| + sum_r G_rx Sr_r^T Z_p)  (same for z_v),
-//   K_e = D - C Z,  r_e = -C z.
+// with G = J^{-1}, s_f the face measure over the reference-face measure, E_f the oriented
+// volume-trace face table.  LU without pivoting of A, velocity block first: the velocity
+// block is a rho |J| I, so its elimination is closed form and leaves the SPD pressure block
+//   S  = a|J|/(rho c^2) I + tau sum_f s_f Mf_f + (|J|/(a rho)) sum_{r,s} (G G^T)_rs Sr_r Sr_s^T
+//   B~ = [-s_f (tau I + (1/(a rho)) sum_r beta_fr Sr_r) E_f]_f,   beta_fr = sum_x G_rx n_fx
+//   f~ = f_p - (1/(a rho)) sum_r Sr_r (sum_x G_rx f_vx).
+// With S = L L^T (Cholesky), W = L^{-1} B~, w = L^{-1} f~:
+//   K_e = D - (1/(a rho |J|)) B_v^T B_v + W^T W,      r_e = -(1/(a rho |J|)) B_v^T f_v + W^T w,
+//   Z_p = L^{-T} W,  z_p = L^{-T} w   (pressure rows of Z = A^{-1} B and z = A^{-1} f),
+// where (B_v^T B_v)_{fg} = s_f s_g (n_f . n_g) E_f^T E_g.  Recovery (first block row):
+//   p = z_p - Z_p lam,   v_x = (f_vx - sum_f n_fx s_f E_f lam_f + Q_x^T p) / (a rho |J|).
+//
+// Execution: one element per wavefront, several wavefronts per workgroup sharing the
+// reference tables in LDS; all intra-element synchronisation is wavefront-local.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -23,9 +28,18 @@ namespace hdg {
 
 namespace {
 
-constexpr int NT = 256;
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-template <int D, int K, int R, typename T>
+template <typename T>
+__device__ __forceinline__ T eps_of() {
+    return sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7);
+}
+
+template <int D, int K, int R>
 struct AcDims {
     static constexpr int N = dimp(K, D);
     static constexpr int NF = dimp(K, D - 1);
@@ -35,318 +49,665 @@ struct AcDims {
     static constexpr int NLOC = (D + 1) * N;       // local unknowns per element
     static constexpr int NPERM = (D == 3) ? 6 : 2;
     static constexpr int NPAIR = D * (D + 1) / 2;
-    static constexpr int WSZ = NFACE * N * N;      // per-face W_f scratch
-    static constexpr int YSZ = D * N * C;
-    static constexpr int YW = (WSZ > YSZ) ? WSZ : YSZ;
 };
 
+// per-wavefront LDS scratch
 template <int D, int K, int R, typename T>
-__global__ __launch_bounds__(NT) void condense_acoustic_kernel(
+struct AcScratch {
+    using Dm = AcDims<D, K, R>;
+    T Sb[Dm::N * Dm::N];                 // S, then its Cholesky factor L
+    T X[Dm::N * Dm::C];                  // [B~ | f~] -> [W | w]
+    T El[Dm::NFACE * Dm::N * Dm::NF];    // oriented face tables of the element
+    T FV[D * Dm::N * R];                 // velocity right-hand side
+    double geo[GEOM_STRIDE];
+};
+
+template <int D, int K, int R, typename T, int WPB>
+__global__ __launch_bounds__(64 * WPB) void condense_acoustic_kernel(
     int64_t ne, double a_in, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
     const T* __restrict__ Sr, const T* __restrict__ Mf, const T* __restrict__ Tsym,
     const T* __restrict__ Ef, const double* __restrict__ f_loc, T* __restrict__ Ke,
-    T* __restrict__ re, T* __restrict__ Zt, T* __restrict__ zout, T* __restrict__ LUout,
+    T* __restrict__ re, T* __restrict__ Zs, T* __restrict__ zs, T* __restrict__ Lout,
     int* __restrict__ status) {
-    using Dm = AcDims<D, K, R, T>;
+    using Dm = AcDims<D, K, R>;
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT, C = Dm::C;
     constexpr int NLOC = Dm::NLOC, NPERM = Dm::NPERM, NPAIR = Dm::NPAIR;
 
-    __shared__ T S[N * N];
-    __shared__ T X[N * C];
-    __shared__ T YW[Dm::YW];          // W_f (phase 1) then Y_r = Sr_r^T X (phase 3)
-    __shared__ T P[N * C];
-    __shared__ T El[NFACE * N * NF];  // oriented face tables of this element
-    __shared__ T FV[D * N * R];       // velocity right-hand side
-    __shared__ T GRv[D * N * R];      // sum_x G_rx f_vx
-    __shared__ double geo[GEOM_STRIDE];
+    __shared__ T Srs[D * N * N];
+    __shared__ AcScratch<D, K, R, T> scr_all[WPB];
 
-    const int tid = threadIdx.x;
+    for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    AcScratch<D, K, R, T>& sc = scr_all[wave];
+    T* Sb = sc.Sb;
+    T* X = sc.X;
+    T* El = sc.El;
+    T* FV = sc.FV;
     const T a = (T)a_in;
 
-    for (int64_t e = blockIdx.x; e < ne; e += gridDim.x) {
-        // ------------------------------------------------------------------ load
-        if (tid < GEOM_STRIDE) geo[tid] = geom[e * GEOM_STRIDE + tid];
-        for (int idx = tid; idx < NFACE * N * NF; idx += NT) {
-            int f = idx / (N * NF), rem = idx % (N * NF);
-            int p = eperm[e * NFACE + f];
-            El[idx] = Ef[(size_t)(f * NPERM + p) * N * NF + rem];
+    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
+        // ------------------------------------------------------------ load
+        if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
+        for (int idx = lane; idx < NFACE * N * NF; idx += 64) {
+            const int f = idx / (N * NF);
+            const int p = eperm[e * NFACE + f];
+            El[idx] = Ef[(size_t)(f * NPERM + p) * N * NF + (idx - f * N * NF)];
         }
         const double* fe = f_loc + (size_t)e * NLOC * R;
-        for (int idx = tid; idx < D * N * R; idx += NT) FV[idx] = (T)fe[idx];
-        for (int idx = tid; idx < N * R; idx += NT) {
-            int i = idx / R, q = idx % R;
-            X[i * C + TT + q] = (T)fe[D * N * R + idx];
-        }
-        __syncthreads();
+        for (int idx = lane; idx < D * N * R; idx += 64) FV[idx] = (T)fe[idx];
+        for (int idx = lane; idx < N * R; idx += 64) X[(idx / R) * C + TT + idx % R] = (T)fe[D * N * R + idx];
+        wsync();
 
-        const T J = (T)geo[0];
-        T G[D][D];
+        const T J = (T)sc.geo[0];
+        T G[D][D], sf[NFACE], nf[NFACE][D];
+#pragma unroll
         for (int r = 0; r < D; ++r)
-            for (int x = 0; x < D; ++x) G[r][x] = (T)geo[1 + r * D + x];
-        T sf[NFACE], nf[NFACE][D];
+#pragma unroll
+            for (int x = 0; x < D; ++x) G[r][x] = (T)sc.geo[1 + r * D + x];
+#pragma unroll
         for (int f = 0; f < NFACE; ++f) {
-            sf[f] = (T)geo[1 + D * D + f];
-            for (int x = 0; x < D; ++x) nf[f][x] = (T)geo[1 + D * D + NFACE + f * D + x];
+            sf[f] = (T)sc.geo[1 + D * D + f];
+#pragma unroll
+            for (int x = 0; x < D; ++x) nf[f][x] = (T)sc.geo[1 + D * D + NFACE + f * D + x];
         }
-        const T rho = (T)geo[GEO_PAR], cc = (T)geo[GEO_PAR + 1];
-        const T tau = (T)geo[GEO_STAB];
-        const T arho = a * rho;
-        const T inv_arho = T(1) / arho;
+        const T rho = (T)sc.geo[GEO_PAR], cc = (T)sc.geo[GEO_PAR + 1];
+        const T tau = (T)sc.geo[GEO_STAB];
+        const T inv_arho = T(1) / (a * rho);
+        const T inv_av = inv_arho / J;          // 1 / (a rho |J|)
         const T alpha_p = a * J / (rho * cc * cc);
-        T gam[NPAIR];
-        {
-            int c = 0;
-            for (int r = 0; r < D; ++r)
-                for (int s = r; s < D; ++s, ++c) {
+
+        // ------------------------------------------------------------ f~ (pressure rhs)
+        for (int idx = lane; idx < N * R; idx += 64) {
+            const int i = idx / R, q = idx % R;
+            T acc = 0;
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                const T* Srow = &Srs[(r * N + i) * N];
+                for (int j = 0; j < N; ++j) {
                     T g = 0;
-                    for (int x = 0; x < D; ++x) g += G[r][x] * G[s][x];
-                    gam[c] = g;
+#pragma unroll
+                    for (int x = 0; x < D; ++x) g += G[r][x] * FV[(x * N + j) * R + q];
+                    acc += Srow[j] * g;
                 }
+            }
+            X[i * C + TT + q] -= inv_arho * acc;
         }
-        T beta[NFACE][D];
-        for (int f = 0; f < NFACE; ++f)
+
+        // ------------------------------------------------------------ B~ face by face
+#pragma unroll 1
+        for (int f = 0; f < NFACE; ++f) {
+            T beta[D];
+#pragma unroll
             for (int r = 0; r < D; ++r) {
                 T b = 0;
+#pragma unroll
                 for (int x = 0; x < D; ++x) b += G[r][x] * nf[f][x];
-                beta[f][r] = b;
+                beta[r] = b * inv_arho;
             }
+            // W_f = tau I + (1/(a rho)) sum_r beta_fr Sr_r  (in the S buffer, not yet in use)
+            for (int idx = lane; idx < N * N; idx += 64) {
+                T w = 0;
+#pragma unroll
+                for (int r = 0; r < D; ++r) w += beta[r] * Srs[r * N * N + idx];
+                if (idx / N == idx % N) w += tau;
+                Sb[idx] = w;
+            }
+            wsync();
+            // X[:, f NF + l] = -s_f W_f E_f   (2 x 2 register blocks)
+            constexpr int NBR = (N + 1) / 2, NBC = (NF + 1) / 2;
+            const T* Ef_ = &El[f * N * NF];
+            for (int blk = lane; blk < NBR * NBC; blk += 64) {
+                const int i0 = 2 * (blk / NBC), l0 = 2 * (blk % NBC);
+                const bool i1ok = i0 + 1 < N, l1ok = l0 + 1 < NF;
+                T a00 = 0, a01 = 0, a10 = 0, a11 = 0;
+                for (int j = 0; j < N; ++j) {
+                    const T w0 = Sb[i0 * N + j];
+                    const T w1 = i1ok ? Sb[(i0 + 1) * N + j] : T(0);
+                    const T e0 = Ef_[j * NF + l0];
+                    const T e1 = l1ok ? Ef_[j * NF + l0 + 1] : T(0);
+                    a00 += w0 * e0;
+                    a01 += w0 * e1;
+                    a10 += w1 * e0;
+                    a11 += w1 * e1;
+                }
+                const T s = -sf[f];
+                X[i0 * C + f * NF + l0] = s * a00;
+                if (l1ok) X[i0 * C + f * NF + l0 + 1] = s * a01;
+                if (i1ok) {
+                    X[(i0 + 1) * C + f * NF + l0] = s * a10;
+                    if (l1ok) X[(i0 + 1) * C + f * NF + l0 + 1] = s * a11;
+                }
+            }
+            wsync();
+        }
 
-        // ------------------------------------------------------------------ phase 1: form
-        const T cT = J * inv_arho;
-        for (int idx = tid; idx < N * N; idx += NT) {
-            int i = idx / N, j = idx % N;
-            T s = (i == j) ? alpha_p : T(0);
-            T fm = 0;
-            for (int f = 0; f < NFACE; ++f) fm += sf[f] * Mf[f * N * N + idx];
-            s += tau * fm;
-            T tt = 0;
-            for (int c = 0; c < NPAIR; ++c) tt += gam[c] * Tsym[c * N * N + idx];
-            S[idx] = s + cT * tt;
+        // ------------------------------------------------------------ S
+        {
+            T gam[NPAIR];
+            int c = 0;
+#pragma unroll
+            for (int r = 0; r < D; ++r)
+#pragma unroll
+                for (int s = r; s < D; ++s, ++c) {
+                    T g = 0;
+#pragma unroll
+                    for (int x = 0; x < D; ++x) g += G[r][x] * G[s][x];
+                    gam[c] = g * J * inv_arho;
+                }
+            for (int idx = lane; idx < N * N; idx += 64) {
+                T s = (idx / N == idx % N) ? alpha_p : T(0);
+                T fm = 0;
+#pragma unroll
+                for (int f = 0; f < NFACE; ++f) fm += sf[f] * Mf[f * N * N + idx];
+                s += tau * fm;
+#pragma unroll
+                for (int c2 = 0; c2 < NPAIR; ++c2) s += gam[c2] * Tsym[c2 * N * N + idx];
+                Sb[idx] = s;
+            }
         }
-        // W_f = tau I + (1/(a rho)) sum_r beta_fr Sr_r
-        for (int idx = tid; idx < NFACE * N * N; idx += NT) {
-            int f = idx / (N * N), ij = idx % (N * N);
-            T w = 0;
-            for (int r = 0; r < D; ++r) w += beta[f][r] * Sr[r * N * N + ij];
-            w *= inv_arho;
-            if (ij / N == ij % N) w += tau;
-            YW[idx] = w;
+        wsync();
+
+        // ------------------------------------------------------------ Cholesky S = L L^T
+        {
+            T dmax = 0;
+            for (int i = 0; i < N; ++i) dmax = fmax(dmax, fabs(Sb[i * N + i]));
+            const T ptol = T(64 * N) * eps_of<T>() * dmax;
+#pragma unroll 1
+            for (int j = 0; j < N; ++j) {
+                const T djj = Sb[j * N + j];
+                if (lane == 0 && !(djj > ptol && djj - djj == T(0))) atomicOr(status, 1);
+                const T ljj = sqrt(djj);
+                const T inv = T(1) / ljj;
+                wsync();
+                for (int i = j + 1 + lane; i < N; i += 64) Sb[i * N + j] *= inv;
+                if (lane == 0) Sb[j * N + j] = ljj;
+                wsync();
+                const int m = N - j - 1;
+                for (int idx = lane; idx < m * m; idx += 64) {
+                    const int ii = j + 1 + idx / m, mm = j + 1 + idx % m;
+                    if (mm <= ii) Sb[ii * N + mm] -= Sb[ii * N + j] * Sb[mm * N + j];
+                }
+                wsync();
+            }
         }
-        // g_r = sum_x G_rx f_vx
-        for (int idx = tid; idx < D * N * R; idx += NT) {
-            int r = idx / (N * R), iq = idx % (N * R);
-            T g = 0;
-            for (int x = 0; x < D; ++x) g += G[r][x] * FV[x * N * R + iq];
-            GRv[idx] = g;
+        if (Lout)
+            for (int idx = lane; idx < N * N; idx += 64) Lout[(size_t)e * N * N + idx] = Sb[idx];
+
+        // ------------------------------------------------------------ [W | w] = L^{-1} [B~ | f~]
+        for (int c = lane; c < C; c += 64) {
+            T x[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T s = X[i * C + c];
+#pragma unroll
+                for (int m = 0; m < i; ++m) s -= Sb[i * N + m] * x[m];
+                x[i] = s / Sb[i * N + i];
+                X[i * C + c] = x[i];
+            }
         }
-        __syncthreads();
-        // B~ columns and f~
-        for (int idx = tid; idx < N * C; idx += NT) {
-            int i = idx / C, c = idx % C;
+        wsync();
+
+        // ------------------------------------------------------------ K_e, r_e
+        {
+            // K = D - (1/(a rho |J|)) [s_f s_g (n_f.n_g) E_f^T E_g] + W^T W, 4 x 4 register blocks
+            constexpr int NBA = (TT + 3) / 4;
+            T* Kee = Ke + (size_t)e * TT * TT;
+            for (int blk = lane; blk < NBA * NBA; blk += 64) {
+                const int a0 = 4 * (blk / NBA), b0 = 4 * (blk % NBA);
+                T ww[4][4] = {}, ee[4][4] = {};
+                int fa[4], la[4], fb[4], lb[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int aa = min(a0 + u, TT - 1), bb = min(b0 + u, TT - 1);
+                    fa[u] = aa / NF;
+                    la[u] = aa % NF;
+                    fb[u] = bb / NF;
+                    lb[u] = bb % NF;
+                }
+                for (int i = 0; i < N; ++i) {
+                    T xa[4], xb[4], ea[4], eb[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int aa = min(a0 + u, TT - 1), bb = min(b0 + u, TT - 1);
+                        xa[u] = X[i * C + aa];
+                        xb[u] = X[i * C + bb];
+                        ea[u] = El[(fa[u] * N + i) * NF + la[u]];
+                        eb[u] = El[(fb[u] * N + i) * NF + lb[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            ww[u][v] += xa[u] * xb[v];
+                            ee[u][v] += ea[u] * eb[v];
+                        }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (a0 + u >= TT) continue;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        if (b0 + v >= TT) continue;
+                        T nn = 0;
+#pragma unroll
+                        for (int x = 0; x < D; ++x) nn += nf[fa[u]][x] * nf[fb[v]][x];
+                        T val = ww[u][v] - inv_av * sf[fa[u]] * sf[fb[v]] * nn * ee[u][v];
+                        if (a0 + u == b0 + v) val -= tau * sf[fa[u]];
+                        Kee[(a0 + u) * TT + b0 + v] = val;
+                    }
+                }
+            }
+            T* ree = re + (size_t)e * TT * R;
+            for (int idx = lane; idx < TT * R; idx += 64) {
+                const int aa = idx / R, q = idx % R;
+                const int f = aa / NF, l = aa % NF;
+                T acc = 0, accv = 0;
+                for (int i = 0; i < N; ++i) {
+                    acc += X[i * C + aa] * X[i * C + TT + q];
+                    T fvn = 0;
+#pragma unroll
+                    for (int x = 0; x < D; ++x) fvn += nf[f][x] * FV[(x * N + i) * R + q];
+                    accv += El[(f * N + i) * NF + l] * fvn;
+                }
+                ree[idx] = acc - inv_av * sf[f] * accv;
+            }
+        }
+        wsync();
+
+        // ------------------------------------------------------------ Z_p = L^{-T} W, z_p = L^{-T} w
+        T* Zse = Zs + (size_t)e * N * TT;
+        T* zse = zs + (size_t)e * NLOC * R;
+        for (int c = lane; c < C; c += 64) {
+            T x[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) x[i] = X[i * C + c];
+#pragma unroll
+            for (int i = N - 1; i >= 0; --i) {
+                T s = x[i];
+#pragma unroll
+                for (int m = i + 1; m < N; ++m) s -= Sb[m * N + i] * x[m];
+                x[i] = s / Sb[i * N + i];
+            }
             if (c < TT) {
-                int f = c / NF, l = c % NF;
-                const T* W = &YW[f * N * N + i * N];
-                const T* E = &El[f * N * NF + l];
-                T acc = 0;
-                for (int j = 0; j < N; ++j) acc += W[j] * E[j * NF];
-                X[idx] = -sf[f] * acc;
+#pragma unroll
+                for (int i = 0; i < N; ++i) Zse[i * TT + c] = x[i];
             } else {
-                int q = c - TT;
-                T acc = 0;
-                for (int r = 0; r < D; ++r) {
-                    const T* Srow = &Sr[r * N * N + i * N];
-                    for (int j = 0; j < N; ++j) acc += Srow[j] * GRv[(r * N + j) * R + q];
-                }
-                X[idx] = X[idx] - inv_arho * acc;
+#pragma unroll
+                for (int i = 0; i < N; ++i) zse[(D * N + i) * R + (c - TT)] = x[i];
             }
         }
-        __syncthreads();
-
-        // ------------------------------------------------------------------ phase 2: LU(S), solve
-        // pivots below 64 N eps of the largest diagonal entry, or non-finite, are reported
-        T dmax = 0;
-        for (int i = 0; i < N; ++i) dmax = fmax(dmax, fabs(S[i * N + i]));
-        const T ptol = T(64 * N) * (sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7)) * dmax;
-        for (int j = 0; j < N; ++j) {
-            const T piv = S[j * N + j];
-            if (tid == 0 && !(fabs(piv) > ptol && piv - piv == T(0))) atomicOr(status, 1);
-            const T ipiv = T(1) / piv;
-            for (int i = j + 1 + tid; i < N; i += NT) S[i * N + j] *= ipiv;
-            __syncthreads();
-            const int m = N - j - 1;
-            for (int idx = tid; idx < m * m; idx += NT) {
-                int i = j + 1 + idx / m, c = j + 1 + idx % m;
-                S[i * N + c] -= S[i * N + j] * S[j * N + c];
-            }
-            __syncthreads();
-        }
-        if (LUout) {
-            for (int idx = tid; idx < N * N; idx += NT) LUout[(size_t)e * N * N + idx] = S[idx];
-        }
-        // forward (unit lower)
-        for (int j = 0; j < N - 1; ++j) {
-            const int m = N - j - 1;
-            for (int idx = tid; idx < m * C; idx += NT) {
-                int i = j + 1 + idx / C, c = idx % C;
-                X[i * C + c] -= S[i * N + j] * X[j * C + c];
-            }
-            __syncthreads();
-        }
-        // backward
-        for (int j = N - 1; j >= 0; --j) {
-            if (tid < C) X[j * C + tid] /= S[j * N + j];
-            __syncthreads();
-            for (int idx = tid; idx < j * C; idx += NT) {
-                int i = idx / C, c = idx % C;
-                X[i * C + c] -= S[i * N + j] * X[j * C + c];
-            }
-            __syncthreads();
-        }
-
-        // ------------------------------------------------------------------ phase 3: Y_r = Sr_r^T X
-        for (int idx = tid; idx < D * N * C; idx += NT) {
-            int r = idx / (N * C), ic = idx % (N * C);
-            int i = ic / C, c = ic % C;
-            const T* Scol = &Sr[r * N * N + i];
-            T acc = 0;
-            for (int j = 0; j < N; ++j) acc += Scol[j * N] * X[j * C + c];
-            YW[idx] = acc;
-        }
-        __syncthreads();
-
-        // ------------------------------------------------------------------ phase 4: write Z, z
-        const T invJ = T(1) / J;
-        T* Zte = Zt + (size_t)e * TT * NLOC;
-        for (int idx = tid; idx < TT * NLOC; idx += NT) {
-            int c = idx / NLOC, row = idx % NLOC;
-            int x = row / N, i = row % N;
-            T v;
-            if (x < D) {
-                int f = c / NF, l = c % NF;
-                T acc = nf[f][x] * sf[f] * El[f * N * NF + i * NF + l] * invJ;
-                for (int r = 0; r < D; ++r) acc += G[r][x] * YW[(r * N + i) * C + c];
-                v = inv_arho * acc;
-            } else {
-                v = X[i * C + c];
-            }
-            Zte[idx] = v;
-        }
-        T* ze = zout + (size_t)e * NLOC * R;
-        for (int idx = tid; idx < NLOC * R; idx += NT) {
-            int row = idx / R, q = idx % R;
-            int x = row / N, i = row % N;
-            T v;
-            if (x < D) {
-                T acc = FV[(x * N + i) * R + q] * invJ;
-                for (int r = 0; r < D; ++r) acc += G[r][x] * YW[(r * N + i) * C + TT + q];
-                v = inv_arho * acc;
-            } else {
-                v = X[i * C + TT + q];
-            }
-            ze[idx] = v;
-        }
-
-        // ------------------------------------------------------------------ phase 5: K_e, r_e
-        T* Kee = Ke + (size_t)e * TT * TT;
-        T* ree = re + (size_t)e * TT * R;
-        for (int f = 0; f < NFACE; ++f) {
-            // P = sum_x n_fx Z_v,x + tau Z_p  (and the same for the z columns)
-            for (int idx = tid; idx < N * C; idx += NT) {
-                int i = idx / C, c = idx % C;
-                T acc = 0;
-                if (c < TT) {
-                    int g = c / NF, l = c % NF;
-                    T nn = 0;
-                    for (int x = 0; x < D; ++x) nn += nf[f][x] * nf[g][x];
-                    acc = nn * sf[g] * El[g * N * NF + i * NF + l] * invJ;
-                } else {
-                    int q = c - TT;
-                    for (int x = 0; x < D; ++x) acc += nf[f][x] * FV[(x * N + i) * R + q];
-                    acc *= invJ;
-                }
-                for (int r = 0; r < D; ++r) acc += beta[f][r] * YW[(r * N + i) * C + c];
-                P[idx] = inv_arho * acc + tau * X[idx];
-            }
-            __syncthreads();
-            for (int idx = tid; idx < NF * C; idx += NT) {
-                int l = idx / C, c = idx % C;
-                T acc = 0;
-                for (int i = 0; i < N; ++i) acc += El[f * N * NF + i * NF + l] * P[i * C + c];
-                T v = -sf[f] * acc;
-                if (c < TT) {
-                    if (c == f * NF + l) v -= tau * sf[f];
-                    Kee[(f * NF + l) * TT + c] = v;
-                } else {
-                    ree[(f * NF + l) * R + (c - TT)] = v;
-                }
-            }
-            __syncthreads();
-        }
+        // velocity rows of z: D1^{-1} f_v (the coupling to p is applied at recovery)
+        for (int idx = lane; idx < D * N * R; idx += 64) zse[idx] = FV[idx] * inv_av;
+        wsync();
     }
 }
 
-// u_e = z_e - Z_e lam_e ; Zt column-major per element
-template <int R, typename T>
-__global__ __launch_bounds__(NT) void recover_kernel(int64_t ne, int nloc, int tt, int nfe, int bs,
-                                                     const int32_t* __restrict__ eface,
-                                                     const T* __restrict__ Zt, const T* __restrict__ z,
-                                                     const double* __restrict__ lam,
-                                                     double* __restrict__ u, int epb) {
-    extern __shared__ double lsh[];   // [epb][tt][R]
-    const int tid = threadIdx.x;
-    const int64_t e0 = (int64_t)blockIdx.x * epb;
-    for (int idx = tid; idx < epb * tt * R; idx += NT) {
-        int s = idx / (tt * R), rem = idx % (tt * R);
-        int c = rem / R, q = rem % R;
-        int64_t e = e0 + s;
-        double v = 0.0;
-        if (e < ne) {
-            int f = c / bs, l = c % bs;
-            int32_t F = eface[e * nfe + f];
-            v = lam[((int64_t)F * bs + l) * R + q];
-        }
-        lsh[idx] = v;
-    }
+// Recovery: p = z_p - Z_p lam_e, v_x = z1_x - (sum_f n_fx s_f E_f lam_f - Q_x^T p)/(a rho |J|)
+template <int D, int K, int R, typename T, int WPB>
+__global__ __launch_bounds__(64 * WPB) void recover_acoustic_kernel(
+    int64_t ne, double a_in, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
+    const int32_t* __restrict__ eface, const T* __restrict__ Sr, const T* __restrict__ Ef,
+    const T* __restrict__ Zs, const T* __restrict__ zs, const double* __restrict__ lam,
+    double* __restrict__ u) {
+    using Dm = AcDims<D, K, R>;
+    constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT;
+    constexpr int NLOC = Dm::NLOC, NPERM = Dm::NPERM;
+    __shared__ T Srs[D * N * N];
+    __shared__ double lamsh[WPB][TT * R];
+    __shared__ double psh[WPB][N * R];
+    __shared__ double geo[WPB][GEOM_STRIDE];
+    for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
     __syncthreads();
-    const int s = tid / nloc, row = tid % nloc;
-    const int64_t e = e0 + s;
-    if (s >= epb || e >= ne) return;
-    const T* Ze = Zt + (size_t)e * tt * nloc;
-    const double* le = lsh + s * tt * R;
-    double acc[R];
-    for (int q = 0; q < R; ++q) acc[q] = (double)z[((size_t)e * nloc + row) * R + q];
-    for (int c = 0; c < tt; ++c) {
-        double zz = (double)Ze[(size_t)c * nloc + row];
-        for (int q = 0; q < R; ++q) acc[q] -= zz * le[c * R + q];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double a = a_in;
+    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
+        if (lane < GEOM_STRIDE) geo[wave][lane] = geom[e * GEOM_STRIDE + lane];
+        for (int idx = lane; idx < TT * R; idx += 64) {
+            const int c = idx / R, q = idx % R;
+            const int32_t F = eface[e * NFACE + c / NF];
+            lamsh[wave][idx] = lam[((int64_t)F * NF + c % NF) * R + q];
+        }
+        wsync();
+        const T* Zse = Zs + (size_t)e * N * TT;
+        const T* zse = zs + (size_t)e * NLOC * R;
+        double* ue = u + (size_t)e * NLOC * R;
+        for (int idx = lane; idx < N * R; idx += 64) {
+            const int i = idx / R, q = idx % R;
+            double acc = (double)zse[(D * N + i) * R + q];
+            const T* Zrow = Zse + i * TT;
+            for (int c = 0; c < TT; ++c) acc -= (double)Zrow[c] * lamsh[wave][c * R + q];
+            psh[wave][idx] = acc;
+            ue[(D * N + i) * R + q] = acc;
+        }
+        wsync();
+        const double J = geo[wave][0];
+        const double inv_av = 1.0 / (a * geo[wave][GEO_PAR] * J);
+        for (int idx = lane; idx < D * N * R; idx += 64) {
+            const int x = idx / (N * R), i = (idx / R) % N, q = idx % R;
+            double bl = 0.0;
+#pragma unroll
+            for (int f = 0; f < NFACE; ++f) {
+                const int p = eperm[e * NFACE + f];
+                const T* Er = Ef + (size_t)(f * NPERM + p) * N * NF + i * NF;
+                double s = 0.0;
+                for (int l = 0; l < NF; ++l) s += (double)Er[l] * lamsh[wave][(f * NF + l) * R + q];
+                bl += geo[wave][1 + D * D + NFACE + f * D + x] * geo[wave][1 + D * D + f] * s;
+            }
+            double qp = 0.0;
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                double s = 0.0;
+                for (int j = 0; j < N; ++j) s += (double)Srs[(r * N + j) * N + i] * psh[wave][j * R + q];
+                qp += geo[wave][1 + r * D + x] * s;
+            }
+            ue[idx] = (double)zse[idx] - inv_av * (bl - J * qp);
+        }
+        wsync();
     }
-    for (int q = 0; q < R; ++q) u[((size_t)e * nloc + row) * R + q] = acc[q];
+}
+
+// wavefronts per workgroup: as many as fit in 80 KB of LDS (two workgroups per CU), at most 4
+// Mixed-precision refinement step (FP64 residual, FP32 correction factors).
+// For the current iterate (u, lam) of the full uncondensed stage system:
+//   s_u = f - A u - B lam   (FP64, element operators applied from the FP64 tables)
+//   t_e = C u + D lam       (the element's contribution to the trace residual)
+// and the correction right-hand sides through the stored low-precision factors:
+//   s~_p = s_p - (1/(a rho)) sum_r Sr_r (sum_x G_rx s_vx)
+//   z'   = [ s_v / (a rho |J|) ;  L^{-T} L^{-1} s~_p ]     (stored in the z buffer)
+//   r'_e = -(1/(a rho |J|)) B_v^T s_v + Z_p^T s~_p          (= -C A~^{-1} s_u)
+//   re64 = r'_e - t_e                                         (FP64, assembled into the rhs)
+// Every operator application is staged as a short matrix-vector product with the lanes over
+// its outputs (one element per wavefront).
+template <int D, int K, int R, typename T, int WPB>
+__global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
+    int64_t ne, double a, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
+    const int32_t* __restrict__ eface, const double* __restrict__ Sr, const double* __restrict__ Mf,
+    const double* __restrict__ Ef, const T* __restrict__ Zs, const T* __restrict__ Lst,
+    const double* __restrict__ u, const double* __restrict__ lam, const double* __restrict__ f,
+    T* __restrict__ zout, double* __restrict__ re64, double* __restrict__ sq) {
+    using Dm = AcDims<D, K, R>;
+    constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT;
+    constexpr int NLOC = Dm::NLOC, NPERM = Dm::NPERM;
+    struct Scr {
+        double geo[GEOM_STRIDE];
+        double uu[NLOC * R];          // iterate u_e
+        double su[NLOC * R];          // f_e, then s_u
+        double lm[TT * R];            // lam_e
+        double ef[NFACE * N * R];     // E_f lam_f
+        double gv[D * N * R];         // sum_x G_rx v_x ; later sum_x G_rx s_vx
+        double yp[D * N * R];         // Sr_r^T p
+        double vn[NFACE * N * R];     // sum_x n_fx v_x + tau p ; later sum_x n_fx s_vx
+        double st[N * R];             // s~_p
+        double te[TT * R];            // t_e = C u + D lam
+        double El[NFACE * N * NF];
+        T L[N * N];
+    };
+    __shared__ double Srs[D * N * N];
+    __shared__ double Mfs[NFACE * N * N];
+    __shared__ Scr scr_all[WPB];
+    for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
+    for (int idx = threadIdx.x; idx < NFACE * N * N; idx += 64 * WPB) Mfs[idx] = Mf[idx];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Scr& sc = scr_all[wave];
+    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
+        if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
+        for (int idx = lane; idx < NLOC * R; idx += 64) {
+            sc.uu[idx] = u[(size_t)e * NLOC * R + idx];
+            sc.su[idx] = f[(size_t)e * NLOC * R + idx];
+        }
+        for (int idx = lane; idx < TT * R; idx += 64) {
+            const int c = idx / R, q = idx % R;
+            const int32_t F = eface[e * NFACE + c / NF];
+            sc.lm[idx] = lam[((int64_t)F * NF + c % NF) * R + q];
+        }
+        for (int idx = lane; idx < NFACE * N * NF; idx += 64) {
+            const int fc = idx / (N * NF);
+            const int p = eperm[e * NFACE + fc];
+            sc.El[idx] = Ef[(size_t)(fc * NPERM + p) * N * NF + (idx - fc * N * NF)];
+        }
+        for (int idx = lane; idx < N * N; idx += 64) sc.L[idx] = Lst[(size_t)e * N * N + idx];
+        wsync();
+        const double* g = sc.geo;
+        const double J = g[0];
+        const double rho = g[GEO_PAR], cc = g[GEO_PAR + 1], tau = g[GEO_STAB];
+        const double arho = a * rho, inv_av = 1.0 / (arho * J), alpha_p = a * J / (rho * cc * cc);
+        double G[D][D], sf[NFACE], nf[NFACE][D];
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+#pragma unroll
+            for (int x = 0; x < D; ++x) G[r][x] = g[1 + r * D + x];
+#pragma unroll
+        for (int fc = 0; fc < NFACE; ++fc) {
+            sf[fc] = g[1 + D * D + fc];
+#pragma unroll
+            for (int x = 0; x < D; ++x) nf[fc][x] = g[1 + D * D + NFACE + fc * D + x];
+        }
+        const double* v = sc.uu;
+        const double* pp = sc.uu + D * N * R;
+        // ---- stage 1: E_f lam_f, G v, Sr^T p, n.v + tau p
+        for (int idx = lane; idx < NFACE * N * R; idx += 64) {
+            const int fc = idx / (N * R), i = (idx / R) % N, q = idx % R;
+            double s = 0.0;
+#pragma unroll
+            for (int l = 0; l < NF; ++l) s += sc.El[(fc * N + i) * NF + l] * sc.lm[(fc * NF + l) * R + q];
+            sc.ef[idx] = s;
+            double vn = tau * pp[i * R + q];
+#pragma unroll
+            for (int x = 0; x < D; ++x) vn += nf[fc][x] * v[(x * N + i) * R + q];
+            sc.vn[idx] = vn;
+        }
+        for (int idx = lane; idx < D * N * R; idx += 64) {
+            const int r = idx / (N * R), i = (idx / R) % N, q = idx % R;
+            double s = 0.0, y = 0.0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) s += G[r][x] * v[(x * N + i) * R + q];
+            sc.gv[idx] = s;
+#pragma unroll
+            for (int j = 0; j < N; ++j) y += Srs[(r * N + j) * N + i] * pp[j * R + q];
+            sc.yp[idx] = y;
+        }
+        wsync();
+        // ---- stage 2: s_u = f - A u - B lam ; t_e part of re64
+        for (int idx = lane; idx < NLOC * R; idx += 64) {
+            const int row = idx / R, q = idx % R;
+            const int x = row / N, i = row % N;
+            double Au;
+            if (x < D) {
+                double qt = 0.0, bl = 0.0;
+#pragma unroll
+                for (int r = 0; r < D; ++r) qt += G[r][x] * sc.yp[(r * N + i) * R + q];
+#pragma unroll
+                for (int fc = 0; fc < NFACE; ++fc) bl += nf[fc][x] * sf[fc] * sc.ef[(fc * N + i) * R + q];
+                Au = arho * J * v[idx] - J * qt + bl;
+            } else {
+                double qv = 0.0, mp = 0.0, bp = 0.0;
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    const double* Srow = &Srs[(r * N + i) * N];
+#pragma unroll
+                    for (int j = 0; j < N; ++j) qv += Srow[j] * sc.gv[(r * N + j) * R + q];
+                }
+#pragma unroll
+                for (int fc = 0; fc < NFACE; ++fc) {
+                    const double* Mrow = &Mfs[(fc * N + i) * N];
+                    double s = 0.0;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) s += Mrow[j] * pp[j * R + q];
+                    mp += sf[fc] * s;
+                    bp += sf[fc] * sc.ef[(fc * N + i) * R + q];
+                }
+                Au = J * qv + alpha_p * pp[i * R + q] + tau * mp - tau * bp;
+            }
+            sc.su[idx] -= Au;
+        }
+        wsync();
+        const double* sv = sc.su;
+        const double* sp = sc.su + D * N * R;
+        // ---- stage 3: G s_v and n.s_v (reuse gv, ef buffers); t_e into re64 accumulator
+        for (int idx = lane; idx < TT * R; idx += 64) {
+            const int aa = idx / R, q = idx % R;
+            const int fc = aa / NF, l = aa % NF;
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) s += sc.El[(fc * N + i) * NF + l] * sc.vn[(fc * N + i) * R + q];
+            sc.te[idx] = sf[fc] * s - tau * sf[fc] * sc.lm[idx];
+        }
+        wsync();
+        for (int idx = lane; idx < D * N * R; idx += 64) {
+            const int r = idx / (N * R), iq = idx % (N * R);
+            double s = 0.0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) s += G[r][x] * sv[x * N * R + iq];
+            sc.gv[idx] = s;
+        }
+        for (int idx = lane; idx < NFACE * N * R; idx += 64) {
+            const int fc = idx / (N * R), iq = idx % (N * R);
+            double s = 0.0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) s += nf[fc][x] * sv[x * N * R + iq];
+            sc.vn[idx] = s;
+        }
+        wsync();
+        // ---- stage 4: s~_p
+        for (int idx = lane; idx < N * R; idx += 64) {
+            const int i = idx / R, q = idx % R;
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                const double* Srow = &Srs[(r * N + i) * N];
+#pragma unroll
+                for (int j = 0; j < N; ++j) acc += Srow[j] * sc.gv[(r * N + j) * R + q];
+            }
+            sc.st[idx] = sp[idx] - acc / arho;
+        }
+        wsync();
+        // ---- stage 5: re64 = -(1/(a rho |J|)) B_v^T s_v + Z_p^T s~_p - t_e
+        const T* Zse = Zs + (size_t)e * N * TT;
+        for (int idx = lane; idx < TT * R; idx += 64) {
+            const int aa = idx / R, q = idx % R;
+            const int fc = aa / NF, l = aa % NF;
+            double rv = 0.0, zt = 0.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                rv += sc.El[(fc * N + i) * NF + l] * sc.vn[(fc * N + i) * R + q];
+                zt += (double)Zse[i * TT + aa] * sc.st[i * R + q];
+            }
+            re64[(size_t)e * TT * R + idx] = -inv_av * sf[fc] * rv + zt - sc.te[idx];
+        }
+        // ---- stage 6: z' = [s_v/(a rho |J|); S^{-1} s~_p]
+        T* ze = zout + (size_t)e * NLOC * R;
+        for (int idx = lane; idx < D * N * R; idx += 64) ze[idx] = (T)(sv[idx] * inv_av);
+        for (int q = lane; q < R; q += 64) {
+            T x[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T s = (T)sc.st[i * R + q];
+#pragma unroll
+                for (int m = 0; m < i; ++m) s -= sc.L[i * N + m] * x[m];
+                x[i] = s / sc.L[i * N + i];
+            }
+#pragma unroll
+            for (int i = N - 1; i >= 0; --i) {
+                T s = x[i];
+#pragma unroll
+                for (int m = i + 1; m < N; ++m) s -= sc.L[m * N + i] * x[m];
+                x[i] = s / sc.L[i * N + i];
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) ze[(D * N + i) * R + q] = x[i];
+        }
+        // ---- squared residual norm of this element's local equations
+        double acc = 0.0;
+        for (int idx = lane; idx < NLOC * R; idx += 64) acc += sc.su[idx] * sc.su[idx];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (lane == 0) sq[e] = acc;
+        wsync();
+    }
+}
+
+template <int D, int K, typename T>
+constexpr int ac_wpb() {
+    constexpr int sb = (int)sizeof(AcScratch<D, K, 1, T>);
+    constexpr int tb = D * dimp(K, D) * dimp(K, D) * (int)sizeof(T);
+    return (4 * sb + tb <= 80 * 1024) ? 4 : ((2 * sb + tb <= 80 * 1024) ? 2 : 1);
 }
 
 template <int D, int K, int R, typename T>
 int launch_ac(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* Mf, const T* Tsym,
               const T* Ef) {
-    int grid = (int)std::min<int64_t>(c->n_elem, 256 * 64);
-    hipLaunchKernelGGL((condense_acoustic_kernel<D, K, R, T>), dim3(grid), dim3(NT), 0, c->stream,
+    constexpr int WPB = ac_wpb<D, K, T>();
+    int64_t groups = (c->n_elem + WPB - 1) / WPB;
+    int grid = (int)std::min<int64_t>(groups, 256 * 16);
+    hipLaunchKernelGGL((condense_acoustic_kernel<D, K, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream,
                        c->n_elem, a, c->d_geom, c->d_eperm, Sr, Mf, Tsym, Ef, f_loc, (T*)c->d_Ke,
                        (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
                        c->precision == HDG_MIXED_FP32 ? (T*)c->d_LU : (T*)nullptr, c->d_status);
     return (int)hipGetLastError();
 }
 
+template <int D, int K, int R, typename T>
+int launch_ac_rec(hdg_ctx* c, const T* Sr, const T* Ef, const double* lam, double* u) {
+    constexpr int WPB = 4;
+    int64_t groups = (c->n_elem + WPB - 1) / WPB;
+    int grid = (int)std::min<int64_t>(groups, 256 * 32);
+    hipLaunchKernelGGL((recover_acoustic_kernel<D, K, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream,
+                       c->n_elem, c->last_a, c->d_geom, c->d_eperm, c->d_eface, Sr, Ef, (const T*)c->d_Zt,
+                       (const T*)c->d_z, lam, u);
+    return (int)hipGetLastError();
+}
+
+template <int D, int K, int R, typename T>
+int launch_ac_ref(hdg_ctx* c, const double* u, const double* lam, double* sq) {
+    constexpr int WPB = 2;
+    int64_t groups = (c->n_elem + WPB - 1) / WPB;
+    int grid = (int)std::min<int64_t>(groups, 256 * 32);
+    hipLaunchKernelGGL((refine_acoustic_kernel<D, K, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream,
+                       c->n_elem, c->last_a, c->d_geom, c->d_eperm, c->d_eface, c->tab.Sr, c->tab.Mf, c->tab.Ef,
+                       (const T*)c->d_Zt, (const T*)c->d_LU, u, lam, c->d_f_saved, (T*)c->d_z, c->d_re64, sq);
+    return (int)hipGetLastError();
+}
+
+#define HDG_AC_CASES(X) X(2, 1, 1) X(2, 2, 1) X(2, 3, 1) X(2, 4, 1) X(3, 1, 1) X(3, 2, 1) X(3, 3, 1) X(3, 4, 1)
+
 template <typename T>
 int dispatch_ac(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* Mf, const T* Tsym,
                 const T* Ef) {
     const int D = c->dim, K = c->k, R = c->nrhs;
-#define HDG_AC_CASE(DD, KK, RR)                                                     \
-    if (D == DD && K == KK && R == RR)                                              \
-        return launch_ac<DD, KK, RR, T>(c, a, f_loc, Sr, Mf, Tsym, Ef);
-    HDG_AC_CASE(2, 1, 1) HDG_AC_CASE(2, 2, 1) HDG_AC_CASE(2, 3, 1) HDG_AC_CASE(2, 4, 1)
-    HDG_AC_CASE(3, 1, 1) HDG_AC_CASE(3, 2, 1) HDG_AC_CASE(3, 3, 1) HDG_AC_CASE(3, 4, 1)
-#undef HDG_AC_CASE
+#define HDG_CASE(DD, KK, RR) \
+    if (D == DD && K == KK && R == RR) return launch_ac<DD, KK, RR, T>(c, a, f_loc, Sr, Mf, Tsym, Ef);
+    HDG_AC_CASES(HDG_CASE)
+#undef HDG_CASE
+    return -1;
+}
+
+template <typename T>
+int dispatch_ac_rec(hdg_ctx* c, const T* Sr, const T* Ef, const double* lam, double* u) {
+    const int D = c->dim, K = c->k, R = c->nrhs;
+#define HDG_CASE(DD, KK, RR) \
+    if (D == DD && K == KK && R == RR) return launch_ac_rec<DD, KK, RR, T>(c, Sr, Ef, lam, u);
+    HDG_AC_CASES(HDG_CASE)
+#undef HDG_CASE
+    return -1;
+}
+
+int dispatch_ac_ref(hdg_ctx* c, const double* u, const double* lam, double* sq) {
+    const int D = c->dim, K = c->k, R = c->nrhs;
+#define HDG_CASE(DD, KK, RR) \
+    if (D == DD && K == KK && R == RR) return launch_ac_ref<DD, KK, RR, float>(c, u, lam, sq);
+    HDG_AC_CASES(HDG_CASE)
+#undef HDG_CASE
     return -1;
 }
 
 }  // namespace
+
+int launch_refine_residual(hdg_ctx* c, const double* u, const double* lam, double* sq) {
+    if (c->physics != HDG_ACOUSTIC || c->precision != HDG_MIXED_FP32) return -1;
+    return dispatch_ac_ref(c, u, lam, sq);
+}
 
 int launch_condense_acoustic(hdg_ctx* c, double a, const double* f_loc) {
     if (c->precision == HDG_FP64)
@@ -355,20 +716,9 @@ int launch_condense_acoustic(hdg_ctx* c, double a, const double* f_loc) {
 }
 
 int launch_recover(hdg_ctx* c, const double* lambda, double* u, bool) {
-    const int nloc = c->n_loc, tt = c->n_tr, R = c->nrhs;
-    int epb = std::max(1, NT / nloc);
-    int64_t grid = (c->n_elem + epb - 1) / epb;
-    size_t shm = (size_t)epb * tt * R * sizeof(double);
-    if (R != 1) return -1;
-    if (c->precision == HDG_FP64)
-        hipLaunchKernelGGL((recover_kernel<1, double>), dim3((unsigned)grid), dim3(NT), shm, c->stream,
-                           c->n_elem, nloc, tt, c->dim + 1, c->bs, c->d_eface, (const double*)c->d_Zt,
-                           (const double*)c->d_z, lambda, u, epb);
-    else
-        hipLaunchKernelGGL((recover_kernel<1, float>), dim3((unsigned)grid), dim3(NT), shm, c->stream,
-                           c->n_elem, nloc, tt, c->dim + 1, c->bs, c->d_eface, (const float*)c->d_Zt,
-                           (const float*)c->d_z, lambda, u, epb);
-    return (int)hipGetLastError();
+    if (c->physics != HDG_ACOUSTIC) return -1;
+    if (c->precision == HDG_FP64) return dispatch_ac_rec<double>(c, c->tab.Sr, c->tab.Ef, lambda, u);
+    return dispatch_ac_rec<float>(c, c->tab.Sr32, c->tab.Ef32, lambda, u);
 }
 
 }  // namespace hdg

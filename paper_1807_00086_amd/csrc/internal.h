@@ -85,10 +85,11 @@ struct hdg_ctx {
     // condensation outputs (precision-typed: double or float)
     void* d_Ke = nullptr;      // [ne][t][t]
     void* d_re = nullptr;      // [ne][t][r]
-    void* d_Zt = nullptr;      // [ne][t][n]   (column-major Z)
+    void* d_Zt = nullptr;      // [ne][Ns][t]  rows of Z = A^{-1} B for the Schur block
     void* d_z = nullptr;       // [ne][n][r]
     void* d_LU = nullptr;      // [ne][Ns][Ns] factored Schur block (mixed precision)
-    int Ns = 0;                // size of the densely factored block
+    int Ns = 0;                // size of the densely factored (Schur) block
+    int s_row0 = 0;            // first local row of that block
     int* d_status = nullptr;   // device status word (0 ok, 1 singular pivot)
 
     // global trace system (FP64)
@@ -105,13 +106,16 @@ struct hdg_ctx {
     double* d_lbnd_saved = nullptr;  // [n_trace_dofs][r]
     double* d_su = nullptr;          // [n_local_dofs][r]
     double* d_slam = nullptr;        // [n_trace_dofs][r]
-    double* d_du = nullptr;
-    double* d_dlam = nullptr;
+    double* d_du = nullptr;          // [n_local_dofs][r] correction
+    double* d_dlam = nullptr;        // [n_trace_dofs][r] correction
+    double* d_re64 = nullptr;        // [ne][t][r] FP64 correction trace right-hand side
+    double* d_sq = nullptr;          // [ne] squared local residual norms
     double* d_stage = nullptr;       // [3][n_local_dofs][r] DIRK stages
     double* d_ustar = nullptr;
     double* d_fstage = nullptr;
     double last_a = 0.0;
     bool condensed = false;
+    bool z_consumed = false;         // mixed: z buffer reused by the refinement corrections
     int last_iters = 0, last_refine = 0;
     hdg::Timings tim;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -126,7 +130,8 @@ int launch_assemble(hdg_ctx* c, const double* lam_bnd);
 int launch_recover(hdg_ctx* c, const double* lambda, double* u, bool rhs_only_z);
 int launch_residual(hdg_ctx* c, double a, const double* u, const double* lam, const double* f,
                     const double* lam_bnd, double* su, double* slam);
-int launch_rhs_condense(hdg_ctx* c, const double* su, const double* slam);
+int launch_refine_residual(hdg_ctx* c, const double* u, const double* lam, double* sq);
+int launch_assemble_rhs64(hdg_ctx* c, const double* re64);
 int launch_apply_mass(hdg_ctx* c, double a, const double* u, double* f);
 int launch_block_inverse(hdg_ctx* c);
 int trace_cg(hdg_ctx* c, double* lambda, int* iters, double* relres);

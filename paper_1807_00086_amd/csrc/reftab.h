@@ -46,6 +46,7 @@ struct RefFaceTables {
 void build_ref_tables(int d, int k, RefTables& T);
 void build_face_tables(int d, int k, int kF, RefFaceTables& E);
 
+
 // Sorted local vertex list of local face f of a d-simplex (the d vertices other than f).
 void local_face_vertices(int d, int f, int* lv);
 

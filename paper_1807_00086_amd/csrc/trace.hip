@@ -86,37 +86,69 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
     }
 }
 
-// inverse of each diagonal block by Gauss-Jordan (one thread per face; blocks are SPD)
-__global__ __launch_bounds__(64) void block_inverse_kernel(int64_t nf, int nslot, int bs,
-                                                            const double* __restrict__ bsr,
-                                                            double* __restrict__ pinv,
-                                                            double* __restrict__ work) {
-    int64_t F = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (F >= nf) return;
-    const double* A = bsr + (size_t)F * nslot * bs * bs;   // slot 0, column-major
-    double* M = work + (size_t)F * bs * bs;
-    double* Inv = pinv + (size_t)F * bs * bs;
-    for (int i = 0; i < bs * bs; ++i) {
-        M[i] = A[i];
-        Inv[i] = ((i % bs) == (i / bs)) ? 1.0 : 0.0;
+// right-hand side of a correction equation: sum over the face's elements of the FP64
+// per-element contributions; Dirichlet faces carry a zero correction
+__global__ __launch_bounds__(NT) void assemble_rhs64_kernel(int64_t nf, int bs, int tt, int R, double sign,
+                                                            const int32_t* __restrict__ face_elem,
+                                                            const int32_t* __restrict__ face_lf,
+                                                            const uint8_t* __restrict__ face_bnd,
+                                                            const double* __restrict__ re64,
+                                                            double* __restrict__ rhs) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nf * bs * R) return;
+    const int64_t F = gid / ((int64_t)bs * R);
+    const int rem = (int)(gid % ((int64_t)bs * R));
+    double v = 0.0;
+    if (!face_bnd[F]) {
+        for (int s = 0; s < 2; ++s) {
+            const int32_t e = face_elem[2 * F + s];
+            const int lf = face_lf[2 * F + s];
+            v += re64[((size_t)e * tt + lf * bs) * R + rem];
+        }
+        v *= sign;
     }
-    // column-major: entry (r, c) at c*bs + r
-    for (int j = 0; j < bs; ++j) {
-        double piv = M[j * bs + j];
-        double ip = 1.0 / piv;
-        for (int c = 0; c < bs; ++c) {
-            M[c * bs + j] *= ip;
-            Inv[c * bs + j] *= ip;
+    rhs[gid] = v;
+}
+
+// inverse of each diagonal block by Gauss-Jordan without pivoting (the blocks are SPD):
+// one wavefront per face, the block and its inverse in LDS (bs <= 48)
+constexpr int BI_MAX = 48;
+__global__ __launch_bounds__(64) void block_inverse_kernel(int64_t nf, int nslot, int bs,
+                                                           const double* __restrict__ bsr,
+                                                           double* __restrict__ pinv) {
+    __shared__ double M[BI_MAX * BI_MAX];
+    __shared__ double V[BI_MAX * BI_MAX];
+    __shared__ double fcol[BI_MAX];
+    const int lane = threadIdx.x;
+    for (int64_t F = blockIdx.x; F < nf; F += gridDim.x) {
+        const double* A = bsr + (size_t)F * nslot * bs * bs;   // slot 0, column-major
+        for (int i = lane; i < bs * bs; i += 64) {
+            M[i] = A[i];
+            V[i] = ((i % bs) == (i / bs)) ? 1.0 : 0.0;
         }
-        for (int r = 0; r < bs; ++r) {
-            if (r == j) continue;
-            double fct = M[j * bs + r];
-            if (fct == 0.0) continue;
-            for (int c = 0; c < bs; ++c) {
-                M[c * bs + r] -= fct * M[c * bs + j];
-                Inv[c * bs + r] -= fct * Inv[c * bs + j];
+        __syncthreads();
+        // column-major: entry (r, c) at c*bs + r
+        for (int j = 0; j < bs; ++j) {
+            const double ip = 1.0 / M[j * bs + j];
+            __syncthreads();
+            for (int c = lane; c < bs; c += 64) {
+                M[c * bs + j] *= ip;
+                V[c * bs + j] *= ip;
             }
+            for (int r = lane; r < bs; r += 64) fcol[r] = M[j * bs + r];   // column j before elimination
+            __syncthreads();
+            for (int idx = lane; idx < bs * bs; idx += 64) {
+                const int c = idx / bs, r = idx % bs;
+                if (r == j) continue;
+                const double fct = fcol[r];
+                M[c * bs + r] -= fct * M[c * bs + j];
+                V[c * bs + r] -= fct * V[c * bs + j];
+            }
+            __syncthreads();
         }
+        double* Inv = pinv + (size_t)F * bs * bs;
+        for (int i = lane; i < bs * bs; i += 64) Inv[i] = V[i];
+        __syncthreads();
     }
 }
 
@@ -181,12 +213,21 @@ __global__ __launch_bounds__(NT) void dot_partial_kernel(int64_t n, int R, const
     }
 }
 
-__global__ void dot_final_kernel(int nb, int R, const double* __restrict__ part, double* __restrict__ out) {
-    int r = threadIdx.x;
-    if (r >= R) return;
-    double acc = 0.0;
-    for (int b = 0; b < nb; ++b) acc += part[(size_t)b * R + r];
-    out[r] = acc;
+__global__ __launch_bounds__(NT) void dot_final_kernel(int nb, int R, const double* __restrict__ part,
+                                                       double* __restrict__ out) {
+    __shared__ double sh[NT];
+    for (int r = 0; r < R; ++r) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nb; b += NT) acc += part[(size_t)b * R + r];
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = NT / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[r] = sh[0];
+        __syncthreads();
+    }
 }
 
 // y[i, r] += alpha[r] * x[i, r] (alpha from device array, optional sign)
@@ -248,11 +289,18 @@ int launch_assemble(hdg_ctx* c, const double* lam_bnd) {
     return (int)hipGetLastError();
 }
 
+int launch_assemble_rhs64(hdg_ctx* c, const double* re64) {
+    const int64_t n = c->n_faces * c->bs * c->nrhs;
+    hipLaunchKernelGGL(assemble_rhs64_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->bs, c->n_tr,
+                       c->nrhs, c->K_sign, c->d_face_elem, c->d_face_lf, c->d_face_bnd, re64, c->d_rhs);
+    return (int)hipGetLastError();
+}
+
 int launch_block_inverse(hdg_ctx* c) {
-    // the CG direction buffer doubles as Gauss-Jordan scratch (nf * bs * bs <= its size is
-    // guaranteed at allocation)
-    hipLaunchKernelGGL(block_inverse_kernel, dim3((unsigned)((c->n_faces + 63) / 64)), dim3(64), 0, c->stream,
-                       c->n_faces, c->nslot, c->bs, c->d_bsr, c->d_pinv, c->d_cg_q);
+    if (c->bs > BI_MAX) return -1;
+    int grid = (int)std::min<int64_t>(c->n_faces, 65536);
+    hipLaunchKernelGGL(block_inverse_kernel, dim3(grid), dim3(64), 0, c->stream, c->n_faces, c->nslot, c->bs,
+                       c->d_bsr, c->d_pinv);
     return (int)hipGetLastError();
 }
 
@@ -272,7 +320,7 @@ static void dot(hdg_ctx* c, const double* x, const double* y, double* out_dev) {
     int64_t n = c->n_faces * c->bs;
     hipLaunchKernelGGL(dot_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, c->nrhs, x, y,
                        c->d_red);
-    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(64), 0, c->stream, c->red_blocks, c->nrhs, c->d_red,
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, c->nrhs, c->d_red,
                        out_dev);
 }
 
@@ -287,7 +335,7 @@ int launch_axpy(hdg_ctx* c, int64_t n, double alpha, const double* x, double* y)
 
 int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out) {
     hipLaunchKernelGGL(dot_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, 1, x, x, c->d_red);
-    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(64), 0, c->stream, c->red_blocks, 1, c->d_red,
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, 1, c->d_red,
                        c->d_scal + 7 * 32);
     hipError_t e = hipMemcpyAsync(host_out, c->d_scal + 7 * 32, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return (int)e;

@@ -48,6 +48,13 @@ def _rel_field_errors(ohdg, d, u_gpu, u_ref):
     return out
 
 
+def _schur_rows(d):
+    """(count, first row) of the densely factored block inside an element's local vector."""
+    from oracle.polynomials import dim_p
+    N = dim_p(int(d.degree[0]), d.dim)
+    return {"acoustic": (N, d.dim * N), "elastic": (3 * N, 6 * N), "maxwell": (3 * N, 3 * N)}[d.physics]
+
+
 def _gpu_stage(s, a, f, lb):
     fd, lbd = _dev(f), _dev(lb)
     s.condense(a, fd, lbd)
@@ -88,19 +95,92 @@ def test_stage_parity_fp64(cfg, kw):
     assert max(errs) <= 1e-12, errs
     assert np.linalg.norm(lam - lam_ref) <= 1e-12 * np.linalg.norm(lam_ref)
     # element-wise quantities of the condensation
-    n, t = s.query("n_local_dofs") // p.n_elem, (d.dim + 1) * d.m_trace * (d.tr_off[1] - d.tr_off[0]) // d.m_trace
+    t = cond.Ke[0].shape[0]
     ne = p.n_elem
+    ns, r0 = _schur_rows(d)
     Ke = s.element_data("K", 0, ne, t * t).reshape(ne, t, t)
     re = s.element_data("r", 0, ne, t).reshape(ne, t)
-    Z = s.element_data("Z", 0, ne, n * t).reshape(ne, n, t)
-    z = s.element_data("z", 0, ne, n).reshape(ne, n)
+    Z = s.element_data("Z", 0, ne, ns * t).reshape(ne, ns, t)
+    z = s.element_data("z", 0, ne, ns).reshape(ne, ns)
     for e in range(0, ne, max(1, ne // 17)):
         sc = np.abs(cond.Ke[e]).max()
         assert np.abs(Ke[e] - cond.Ke[e]).max() <= 1e-11 * sc
         assert np.abs(re[e] - cond.re[e][:, 0]).max() <= 1e-11 * max(np.abs(cond.re[e]).max(), 1e-300)
-        assert np.abs(Z[e] - cond.Z[e]).max() <= 1e-11 * np.abs(cond.Z[e]).max()
-        assert np.abs(z[e] - cond.z[e][:, 0]).max() <= 1e-11 * np.abs(cond.z[e]).max()
+        Zr, zr = cond.Z[e][r0:r0 + ns], cond.z[e][r0:r0 + ns, 0]
+        assert np.abs(Z[e] - Zr).max() <= 1e-11 * np.abs(Zr).max()
+        assert np.abs(z[e] - zr).max() <= 1e-11 * np.abs(zr).max()
     s.close()
+
+
+MIXED_CASES = [
+    (1, dict()),
+    (1, dict(n=4, k=4)),
+    (2, dict(n=2, k=2)),
+    (2, dict(n=3, k=3)),
+]
+
+
+@pytest.mark.parametrize("cfg,kw", MIXED_CASES)
+def test_stage_parity_mixed(cfg, kw):
+    """FP32 condensation + FP64 refinement reaches the FP64 oracle to 1e-10 per field."""
+    _need_gpu()
+    ohdg = _oracle()
+    p = make_problem(cfg, **kw)
+    print(f"case mixed cfg={cfg} {kw} n_elem={p.n_elem}", flush=True)
+    d = ohdg.make_discretisation(p)
+    a = 1.0 / (0.43586652150845899 * p.dt)
+    f = random_vector(d.loc_off[-1], cfg, 1)
+    lb = random_vector(d.tr_off[-1], cfg, 2) * ohdg.boundary_trace_mask(d)
+    u_ref, lam_ref, cond = ohdg.solve_stage(d, a, f, lb)
+    s = _solver(p, precision="mixed_fp32", krylov_tol=1e-9, refine_tol=1e-12)
+    u, lam, it, rr = _gpu_stage(s, a, f, lb)
+    nref = s.query("last_refine")
+    errs = _rel_field_errors(ohdg, d, u, u_ref)
+    assert 1 <= nref <= 6
+    assert max(errs) <= 1e-10, (errs, nref)
+    assert np.linalg.norm(lam - lam_ref) <= 1e-10 * np.linalg.norm(lam_ref)
+    # the FP32 Schur complements themselves are only single-precision accurate
+    t = cond.Ke[0].shape[0]
+    Ke = s.element_data("K", 0, 1, t * t).reshape(t, t)
+    rel = np.abs(Ke - cond.Ke[0]).max() / np.abs(cond.Ke[0]).max()
+    assert 1e-9 < rel < 1e-5
+    # a second recover without a new condensation is a call-order error
+    from paper_1807_00086_amd import HDGError
+    with pytest.raises(HDGError) as ei:
+        s.recover(_dev(lam), _dev(u))
+    assert ei.value.code == 7
+    s.close()
+
+
+def test_full_size_acoustic3d_mixed_equals_fp64():
+    """Full 82,944-element workload: the refined mixed solution equals the FP64 path
+    (itself oracle-checked above) to 1e-10 per field."""
+    _need_gpu()
+    p = make_problem(2)
+    a = 1.0 / (0.43586652150845899 * p.dt)
+    s64 = _solver(p)
+    nl, nt = s64.query("n_local_dofs"), s64.query("n_trace_dofs")
+    f = random_vector(nl, 2, 11)
+    lb = random_vector(nt, 2, 12)
+    # only the boundary-face entries of lam_bnd are read by the library
+    u64, l64, _, _ = _gpu_stage(s64, a, f, lb)
+    s64.close()
+    s32 = _solver(p, precision="mixed_fp32", krylov_tol=1e-8, refine_tol=1e-12)
+    u32, l32, _, _ = _gpu_stage(s32, a, f, lb)
+    assert s32.query("last_refine") >= 1
+    N = 20
+    ue, ue32 = u64.reshape(p.n_elem, 4, N), u32.reshape(p.n_elem, 4, N)
+    for comps in ([0, 1, 2], [3]):
+        num = np.sqrt(np.sum(np.abs(_detJ(p))[:, None, None] * (ue32[:, comps] - ue[:, comps]) ** 2))
+        den = np.sqrt(np.sum(np.abs(_detJ(p))[:, None, None] * ue[:, comps] ** 2))
+        assert num / den <= 1e-10, (comps, num / den)
+    assert np.linalg.norm(l32 - l64) <= 1e-10 * np.linalg.norm(l64)
+    s32.close()
+
+
+def _detJ(p):
+    X = p.xyz[p.elem_vert]
+    return np.linalg.det(np.transpose(X[:, 1:, :] - X[:, :1, :], (0, 2, 1)))
 
 
 def test_stage_parity_repeatable_bitwise():
