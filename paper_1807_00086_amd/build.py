@@ -16,7 +16,8 @@ OUT = os.path.join(HERE, "libhdg.so")
 OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["reftab.cpp", "mesh.cpp", "capi.cpp", "condense_acoustic.hip", "trace.hip", "stage.hip"]
+SOURCES = ["reftab.cpp", "mesh.cpp", "capi.cpp", "condense_acoustic.hip", "condense_general.hip", "trace.hip",
+           "stage.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -87,7 +87,11 @@ int check_status(hdg_ctx* c) {
 
 bool supported(hdg_ctx* c) {
     if (c->physics == HDG_ACOUSTIC) return c->nrhs == 1 && c->k >= 1 && c->k <= 4;
-    return false;
+    return general_supported(c->physics, c->k, c->nrhs);
+}
+
+int launch_recover_any(hdg_ctx* c, const double* lam, double* u) {
+    return c->physics == HDG_ACOUSTIC ? launch_recover(c, lam, u, false) : launch_recover_general(c, lam, u);
 }
 
 }  // namespace
@@ -196,6 +200,16 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(upload_f32(c, &c->tab.Mf32, c->ref.Mf));
     TRY(upload_f32(c, &c->tab.Tsym32, c->ref.Tsym));
     TRY(upload_f32(c, &c->tab.Ef32, c->reff.E));
+    TRY(upload(c, &c->tab.Tfull, c->ref.Tfull));
+    TRY(upload_f32(c, &c->tab.Tfull32, c->ref.Tfull));
+    if (c->physics == HDG_MAXWELL) {
+        std::vector<double> ef(c->n_elem * (d + 1) * 6);
+        for (int64_t e = 0; e < c->n_elem; ++e)
+            for (int f = 0; f <= d; ++f)
+                for (int q = 0; q < 6; ++q)
+                    ef[(e * (d + 1) + f) * 6 + q] = c->frame[(int64_t)c->elem_face[e * (d + 1) + f] * 6 + q];
+        TRY(upload(c, &c->d_eframe, ef));
+    }
 
 
     const size_t tsz = (c->precision == HDG_FP64) ? sizeof(double) : sizeof(float);
@@ -280,7 +294,8 @@ hdg_status hdg_condense(hdg_ctx* c, double a, const double* f_loc, const double*
     int e;
     {
         EventTimer t(c, &c->tim.condense);
-        e = (c->physics == HDG_ACOUSTIC) ? launch_condense_acoustic(c, a, f_loc) : -1;
+        e = (c->physics == HDG_ACOUSTIC) ? launch_condense_acoustic(c, a, f_loc)
+                                         : launch_condense_general(c, a, f_loc);
     }
     if (e) return fail(c, HDG_E_HIP, "condensation kernel launch failed");
     {
@@ -323,7 +338,7 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
     int e;
     {
         EventTimer t(c, &c->tim.recover);
-        e = launch_recover(c, lambda, u, false);
+        e = launch_recover_any(c, lambda, u);
     }
     if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
     c->last_refine = 0;
@@ -340,7 +355,8 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
         float t_res = 0.f, t_sol = 0.f, t_rec = 0.f;
         {
             EventTimer t(c, &t_res);
-            e = launch_refine_residual(c, u, lambda, c->d_sq);
+            e = (c->physics == HDG_ACOUSTIC) ? launch_refine_residual(c, u, lambda, c->d_sq)
+                                             : launch_refine_general(c, u, lambda);
             if (!e) e = launch_assemble_rhs64(c, c->d_re64);
         }
         if (e) return fail(c, HDG_E_HIP, "refinement kernel launch failed");
@@ -355,7 +371,7 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
         if (r && r != HDG_E_NOCONV) return fail(c, r, "refinement trace solve failed");
         {
             EventTimer t(c, &t_rec);
-            e = launch_recover(c, c->d_dlam, c->d_du, false);
+            e = launch_recover_any(c, c->d_dlam, c->d_du);
         }
         if (e) return fail(c, HDG_E_HIP, "refinement recovery launch failed");
         c->tim.refine_elem += t_res + t_rec;
@@ -613,7 +629,7 @@ void hdg_destroy(hdg_ctx* c) {
     if (!c) return;
     void* ptrs[] = {c->d_geom, c->d_eface, c->d_eperm, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
                     c->d_bsr_cols, c->tab.Sr, c->tab.Mf, c->tab.Tsym, c->tab.Ef, c->tab.Sr32, c->tab.Mf32,
-                    c->tab.Tsym32, c->tab.Ef32, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
+                    c->tab.Tsym32, c->tab.Ef32, c->tab.Tfull, c->tab.Tfull32, c->d_eframe, c->d_xscratch, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
                     c->d_bsr, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
                     c->d_scal, c->d_f_saved, c->d_lbnd_saved, c->d_su, c->d_slam, c->d_du, c->d_dlam,
                     c->d_re64, c->d_sq,

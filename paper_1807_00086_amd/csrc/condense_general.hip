@@ -1,0 +1,882 @@
+// Elastodynamic and Maxwell HDG condensation / recovery kernels for gfx950.
+//
+// Both physics share one block structure of the element stage matrix (unknowns
+// u = [u1 (M1 flux-like components), u2 (M2 components)], trace lam with MT components):
+//   A = [[D1, X], [-X^T, A22]],   D1 = |J| dmat (x) I_N,   X = |J| sum_r c_r (x) Sr_r^T,
+//   B = [B1; B2] with B1_a[(f,c)] = b1[a][f,c] s_f E_f,  B2_b[(f,c)] = b2[b][f,c] s_f E_f,
+//   C = [j1 B1^T, j2 B2^T] (j2 = -j1),   D = dface s_f I per face block,
+//   A22 = |J| amass (x) I + sum_f s_f af_f (x) Mf_f.
+//   elastic (u1 = stress s11..s12 with the symmetric test tensors, u2 = velocity, trace v_hat):
+//     dmat = a Acomp (compliance in the weighted symmetric basis), c_r[a][x] = sum_b E_a[x][b] G_rb,
+//     b1[a][f,y] = -(E_a n_f)_y, b2[x][f,y] = -S delta_xy, amass = a rho I, af_f = S I,
+//     dface = S, j1 = -1.
+//   maxwell (u1 = H, u2 = E, trace E_hat^t in the face frame (t1, t2)):
+//     dmat = a mu I, c_r[y][x] = sum_s eps_{x s y} G_rs, b1[y][f,c] = (n_f x t_fc)_y,
+//     b2[x][f,c] = -tau t_fc,x, amass = (a eps + sigma) I, af_f = tau (I - n_f n_f^T),
+//     dface = tau, j1 = -1.
+// LU without pivoting of A with the D1 block first (closed form) leaves the SPD Schur block
+//   S   = A22 + X^T D1^{-1} X = A22 + |J| sum_{r,r'} (c_r^T dmat^{-1} c_r') (x) Sr_r Sr_r'^T
+//   B~2 = B2 + X^T D1^{-1} B1,  f~2 = f2 + X^T D1^{-1} f1,
+// and with S = L L^T, W = L^{-1} B~2, w = L^{-1} f~2:
+//   K_e = D - j1 B1^T D1^{-1} B1 - j2 W^T W,   r_e = -j1 B1^T D1^{-1} f1 - j2 W^T w,
+//   Z2 = L^{-T} W, z2 = L^{-T} w, z1 = D1^{-1} f1 (the coupling -D1^{-1}(B1 lam + X u2) is applied
+//   at recovery).  One element per workgroup of 256 threads.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "physics.h"
+
+namespace hdg {
+
+namespace {
+
+constexpr int NTG = 256;
+constexpr int PH_ELASTIC = 1, PH_MAXWELL = 2;
+
+template <int PHYS>
+struct PhysDims;
+template <>
+struct PhysDims<PH_ELASTIC> {
+    static constexpr int M1 = 6, M2 = 3, MT = 3;
+};
+template <>
+struct PhysDims<PH_MAXWELL> {
+    static constexpr int M1 = 3, M2 = 3, MT = 2;
+};
+
+template <int PHYS, int K, int R>
+struct GDims {
+    static constexpr int D = 3, NFACE = 4, NPERM = 6;
+    static constexpr int M1 = PhysDims<PHYS>::M1, M2 = PhysDims<PHYS>::M2, MT = PhysDims<PHYS>::MT;
+    static constexpr int N = dimp(K, 3), NF = dimp(K, 2);
+    static constexpr int N1 = M1 * N, N2 = M2 * N, NLOC = N1 + N2;
+    static constexpr int NFC = NFACE * MT;             // (face, component) pairs
+    static constexpr int TT = NFC * NF;
+    static constexpr int C = TT + R;
+    static constexpr int YE = NFACE * D * N * NF;      // Sr_r E_f products
+    static constexpr int HV = D * M2 * N * R;
+    static constexpr int SBUF = (N2 * N2 > YE + HV) ? N2 * N2 : YE + HV;
+};
+
+template <int PHYS>
+struct Coef {
+    static constexpr int M1 = PhysDims<PHYS>::M1, M2 = PhysDims<PHYS>::M2, MT = PhysDims<PHYS>::MT;
+    static constexpr int NFC = 4 * MT;
+    double d1inv[M1][M1];
+    double dmat[M1][M1];       // D1 = |J| dmat (x) I
+    double c[3][M1][M2];
+    double cd[3][M1][M2];      // dmat^{-1} c_r
+    double b1[M1][NFC];
+    double bd[M1][NFC];        // dmat^{-1} b1
+    double b2[M2][NFC];
+    double amass[M2][M2];
+    double af[4][M2][M2];
+    double Gam[M2][M2][9];     // c_r^T dmat^{-1} c_r'
+    double kap[M2][NFC][3];    // c_r^T dmat^{-1} b1
+    double g1[NFC][NFC];       // b1^T dmat^{-1} b1
+    double dface;
+    double j1;
+};
+
+// primary coefficients from the geometry record, material and (Maxwell) face frames
+template <int PHYS>
+__device__ void coef_primary(const double* g, const double* frm, double a, Coef<PHYS>& cf) {
+    constexpr int M1 = Coef<PHYS>::M1, M2 = Coef<PHYS>::M2, MT = Coef<PHYS>::MT, NFC = Coef<PHYS>::NFC;
+    double G[3][3], n[4][3];
+    for (int r = 0; r < 3; ++r)
+        for (int x = 0; x < 3; ++x) G[r][x] = g[1 + r * 3 + x];
+    for (int f = 0; f < 4; ++f)
+        for (int x = 0; x < 3; ++x) n[f][x] = g[14 + f * 3 + x];
+    for (int a1 = 0; a1 < M1; ++a1)
+        for (int a2 = 0; a2 < M1; ++a2) cf.d1inv[a1][a2] = cf.dmat[a1][a2] = 0.0;
+    for (int b = 0; b < M2; ++b)
+        for (int b2 = 0; b2 < M2; ++b2) {
+            cf.amass[b][b2] = 0.0;
+            for (int f = 0; f < 4; ++f) cf.af[f][b][b2] = 0.0;
+        }
+    cf.j1 = -1.0;
+    if constexpr (PHYS == PH_ELASTIC) {
+        const double rho = g[GEO_PAR], lam = g[GEO_PAR + 1], mu = g[GEO_PAR + 2], S = g[GEO_STAB];
+        // stress pairs (0,0),(1,1),(2,2),(1,2),(0,2),(0,1); E_a = e_i e_j^T + e_j e_i^T (i != j)
+        const int pi[6] = {0, 1, 2, 1, 0, 0}, pj[6] = {0, 1, 2, 2, 2, 1};
+        auto Ea = [&](int al, int x, int b) {
+            return ((x == pi[al] && b == pj[al]) || (x == pj[al] && b == pi[al])) ? 1.0 : 0.0;
+        };
+        // dmat^{-1} = (2 mu W^{-1} + lambda t t^T) / a,  W = diag(1,1,1,2,2,2), t = (1,1,1,0,0,0)
+        for (int a1 = 0; a1 < 6; ++a1)
+            for (int a2 = 0; a2 < 6; ++a2) {
+                double v = 0.0;
+                if (a1 < 3 && a2 < 3) v = lam + (a1 == a2 ? 2.0 * mu : 0.0);
+                else if (a1 == a2) v = mu;
+                cf.d1inv[a1][a2] = v / a;
+                // dmat = a Acomp: (E_a : E_b - lambda/(3 lambda + 2 mu) tr E_a tr E_b) / (2 mu)
+                const double ee = (a1 == a2) ? (a1 < 3 ? 1.0 : 2.0) : 0.0;
+                const double tt = (a1 < 3 && a2 < 3) ? 1.0 : 0.0;
+                cf.dmat[a1][a2] = a * (ee - lam / (3.0 * lam + 2.0 * mu) * tt) / (2.0 * mu);
+            }
+        for (int r = 0; r < 3; ++r)
+            for (int al = 0; al < 6; ++al)
+                for (int x = 0; x < 3; ++x) {
+                    double s = 0.0;
+                    for (int b = 0; b < 3; ++b) s += Ea(al, x, b) * G[r][b];
+                    cf.c[r][al][x] = s;
+                }
+        for (int al = 0; al < 6; ++al)
+            for (int f = 0; f < 4; ++f)
+                for (int y = 0; y < 3; ++y) {
+                    double s = 0.0;
+                    for (int b = 0; b < 3; ++b) s += Ea(al, y, b) * n[f][b];
+                    cf.b1[al][f * 3 + y] = -s;
+                }
+        for (int x = 0; x < 3; ++x)
+            for (int fc = 0; fc < NFC; ++fc) cf.b2[x][fc] = (fc % 3 == x) ? -S : 0.0;
+        for (int x = 0; x < 3; ++x) {
+            cf.amass[x][x] = a * rho;
+            for (int f = 0; f < 4; ++f) cf.af[f][x][x] = S;
+        }
+        cf.dface = S;
+    } else {
+        const double eps = g[GEO_PAR], mu = g[GEO_PAR + 1], sig = g[GEO_PAR + 2], tau = g[GEO_STAB];
+        for (int y = 0; y < 3; ++y) {
+            cf.d1inv[y][y] = 1.0 / (a * mu);
+            cf.dmat[y][y] = a * mu;
+        }
+        auto lc = [](int i, int j, int k) { return (double)((i - j) * (j - k) * (k - i)) / 2.0; };
+        for (int r = 0; r < 3; ++r)
+            for (int y = 0; y < 3; ++y)
+                for (int x = 0; x < 3; ++x) {
+                    double s = 0.0;
+                    for (int sx = 0; sx < 3; ++sx) s += lc(x, sx, y) * G[r][sx];
+                    cf.c[r][y][x] = s;
+                }
+        for (int f = 0; f < 4; ++f)
+            for (int cc = 0; cc < 2; ++cc) {
+                const double* t = frm + f * 6 + cc * 3;
+                const double w[3] = {n[f][1] * t[2] - n[f][2] * t[1], n[f][2] * t[0] - n[f][0] * t[2],
+                                     n[f][0] * t[1] - n[f][1] * t[0]};
+                for (int y = 0; y < 3; ++y) {
+                    cf.b1[y][f * 2 + cc] = w[y];
+                    cf.b2[y][f * 2 + cc] = -tau * t[y];
+                }
+            }
+        for (int x = 0; x < 3; ++x) {
+            cf.amass[x][x] = a * eps + sig;
+            for (int f = 0; f < 4; ++f)
+                for (int z = 0; z < 3; ++z) cf.af[f][x][z] = tau * ((x == z ? 1.0 : 0.0) - n[f][x] * n[f][z]);
+        }
+        cf.dface = tau;
+    }
+    (void)MT;
+}
+
+// derived coefficient products, spread over the threads of a group (stride nthr)
+template <int PHYS>
+__device__ void coef_derived_a(Coef<PHYS>& cf, int t, int nthr) {
+    constexpr int M1 = Coef<PHYS>::M1, M2 = Coef<PHYS>::M2, NFC = Coef<PHYS>::NFC;
+    for (int idx = t; idx < 3 * M1 * M2; idx += nthr) {
+        const int r = idx / (M1 * M2), al = (idx / M2) % M1, b = idx % M2;
+        double s = 0.0;
+        for (int a2 = 0; a2 < M1; ++a2) s += cf.d1inv[al][a2] * cf.c[r][a2][b];
+        cf.cd[r][al][b] = s;
+    }
+    for (int idx = t; idx < M1 * NFC; idx += nthr) {
+        const int al = idx / NFC, fc = idx % NFC;
+        double s = 0.0;
+        for (int a2 = 0; a2 < M1; ++a2) s += cf.d1inv[al][a2] * cf.b1[a2][fc];
+        cf.bd[al][fc] = s;
+    }
+}
+
+template <int PHYS>
+__device__ void coef_derived_b(Coef<PHYS>& cf, int t, int nthr) {
+    constexpr int M1 = Coef<PHYS>::M1, M2 = Coef<PHYS>::M2, NFC = Coef<PHYS>::NFC;
+    for (int idx = t; idx < M2 * M2 * 9; idx += nthr) {
+        const int b = idx / (M2 * 9), gm = (idx / 9) % M2, rr = idx % 9;
+        const int r = rr / 3, r2 = rr % 3;
+        double s = 0.0;
+        for (int al = 0; al < M1; ++al) s += cf.c[r][al][b] * cf.cd[r2][al][gm];
+        cf.Gam[b][gm][rr] = s;
+    }
+    for (int idx = t; idx < M2 * NFC * 3; idx += nthr) {
+        const int b = idx / (NFC * 3), fc = (idx / 3) % NFC, r = idx % 3;
+        double s = 0.0;
+        for (int al = 0; al < M1; ++al) s += cf.c[r][al][b] * cf.bd[al][fc];
+        cf.kap[b][fc][r] = s;
+    }
+    for (int idx = t; idx < NFC * NFC; idx += nthr) {
+        const int fc = idx / NFC, gd = idx % NFC;
+        double s = 0.0;
+        for (int al = 0; al < M1; ++al) s += cf.b1[al][fc] * cf.bd[al][gd];
+        cf.g1[fc][gd] = s;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T geps() {
+    return sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7);
+}
+
+template <int PHYS, int K, int R, typename T, bool XG>
+__global__ __launch_bounds__(NTG) void condense_general_kernel(
+    int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
+    const int32_t* __restrict__ eperm, const T* __restrict__ Sr, const T* __restrict__ Mf,
+    const T* __restrict__ Tfull, const T* __restrict__ Ef, const double* __restrict__ f_loc,
+    T* __restrict__ Ke, T* __restrict__ re, T* __restrict__ Zs, T* __restrict__ zs, T* __restrict__ Lout,
+    T* __restrict__ Xglob, int* __restrict__ status) {
+    using Dm = GDims<PHYS, K, R>;
+    constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, NPERM = Dm::NPERM, D = Dm::D;
+    constexpr int M1 = Dm::M1, M2 = Dm::M2, MT = Dm::MT, N1 = Dm::N1, N2 = Dm::N2, NLOC = Dm::NLOC;
+    constexpr int NFC = Dm::NFC, TT = Dm::TT, C = Dm::C;
+
+    __shared__ T Srs[D * N * N];
+    __shared__ T Sb[Dm::SBUF];
+    __shared__ T El[NFACE * N * NF];
+    __shared__ T F1[N1 * R];
+    __shared__ T Xl[XG ? 1 : N2 * C];
+    __shared__ Coef<PHYS> cf;
+    __shared__ double geo[GEOM_STRIDE];
+    __shared__ double frm[24];
+    T* X = XG ? Xglob + (size_t)blockIdx.x * N2 * C : Xl;
+    const int tid = threadIdx.x;
+
+    for (int idx = tid; idx < D * N * N; idx += NTG) Srs[idx] = Sr[idx];
+
+    for (int64_t e = blockIdx.x; e < ne; e += gridDim.x) {
+        __syncthreads();
+        // ------------------------------------------------------------ load
+        if (tid < GEOM_STRIDE) geo[tid] = geom[e * GEOM_STRIDE + tid];
+        if (PHYS == PH_MAXWELL && tid >= 64 && tid < 64 + 24) frm[tid - 64] = eframe[e * 24 + tid - 64];
+        for (int idx = tid; idx < NFACE * N * NF; idx += NTG) {
+            const int f = idx / (N * NF);
+            const int p = eperm[e * NFACE + f];
+            El[idx] = Ef[(size_t)(f * NPERM + p) * N * NF + (idx - f * N * NF)];
+        }
+        const double* fe = f_loc + (size_t)e * NLOC * R;
+        for (int idx = tid; idx < N1 * R; idx += NTG) F1[idx] = (T)fe[idx];
+        for (int idx = tid; idx < N2 * R; idx += NTG) X[(idx / R) * C + TT + idx % R] = (T)fe[N1 * R + idx];
+        __syncthreads();
+        if (tid == 0) coef_primary<PHYS>(geo, frm, a, cf);
+        __syncthreads();
+        coef_derived_a<PHYS>(cf, tid, NTG);
+        __syncthreads();
+        coef_derived_b<PHYS>(cf, tid, NTG);
+        __syncthreads();
+        const T J = (T)geo[0];
+        const T invJ = T(1) / J;
+
+        // ------------------------------------------------------------ Sr_r E_f and the f1 coupling
+        T* YE = Sb;                       // [f][r][i][l]
+        T* HV = Sb + Dm::YE;              // [r][b][j][q] = sum_a cd[r][a][b] f1_a[j][q]
+        for (int idx = tid; idx < Dm::YE; idx += NTG) {
+            const int f = idx / (D * N * NF), r = (idx / (N * NF)) % D, i = (idx / NF) % N, l = idx % NF;
+            const T* Srow = &Srs[(r * N + i) * N];
+            const T* Ec = &El[f * N * NF + l];
+            T acc = 0;
+            for (int j = 0; j < N; ++j) acc += Srow[j] * Ec[j * NF];
+            YE[idx] = acc;
+        }
+        for (int idx = tid; idx < Dm::HV; idx += NTG) {
+            const int r = idx / (M2 * N * R), b = (idx / (N * R)) % M2, jq = idx % (N * R);
+            T acc = 0;
+#pragma unroll
+            for (int al = 0; al < M1; ++al) acc += (T)cf.cd[r][al][b] * F1[al * N * R + jq];
+            HV[idx] = acc;
+        }
+        __syncthreads();
+        // ------------------------------------------------------------ B~2 and f~2
+        for (int idx = tid; idx < N2 * C; idx += NTG) {
+            const int row = idx / C, c = idx % C;
+            const int b = row / N, i = row % N;
+            if (c < TT) {
+                const int fc = c / NF, l = c % NF, f = fc / MT;
+                T acc = (T)cf.b2[b][fc] * El[(f * N + i) * NF + l];
+#pragma unroll
+                for (int r = 0; r < D; ++r) acc += (T)cf.kap[b][fc][r] * YE[((f * D + r) * N + i) * NF + l];
+                X[idx] = (T)geo[1 + D * D + f] * acc;
+            } else {
+                const int q = c - TT;
+                T acc = 0;
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    const T* Srow = &Srs[(r * N + i) * N];
+                    for (int j = 0; j < N; ++j) acc += Srow[j] * HV[((r * M2 + b) * N + j) * R + q];
+                }
+                X[idx] += acc;
+            }
+        }
+        __syncthreads();
+        // ------------------------------------------------------------ S
+        for (int idx = tid; idx < N2 * N2; idx += NTG) {
+            const int row = idx / N2, col = idx % N2;
+            const int b = row / N, i = row % N, gm = col / N, j = col % N;
+            T s = (i == j) ? J * (T)cf.amass[b][gm] : T(0);
+#pragma unroll
+            for (int f = 0; f < NFACE; ++f) {
+                const T cfc = (T)cf.af[f][b][gm];
+                if (cfc != T(0)) s += (T)geo[1 + D * D + f] * cfc * Mf[(f * N + i) * N + j];
+            }
+            T q = 0;
+#pragma unroll
+            for (int rr = 0; rr < 9; ++rr) q += (T)cf.Gam[b][gm][rr] * Tfull[(rr * N + i) * N + j];
+            Sb[idx] = s + J * q;
+        }
+        __syncthreads();
+        // ------------------------------------------------------------ Cholesky S = L L^T
+        {
+            T dmax = 0;
+            for (int i = 0; i < N2; ++i) dmax = fmax(dmax, fabs(Sb[i * N2 + i]));
+            const T ptol = T(64 * N2) * geps<T>() * dmax;
+            for (int j = 0; j < N2; ++j) {
+                const T djj = Sb[j * N2 + j];
+                if (tid == 0 && !(djj > ptol && djj - djj == T(0))) atomicOr(status, 1);
+                const T ljj = sqrt(djj);
+                const T inv = T(1) / ljj;
+                __syncthreads();
+                for (int i = j + 1 + tid; i < N2; i += NTG) Sb[i * N2 + j] *= inv;
+                if (tid == 0) Sb[j * N2 + j] = ljj;
+                __syncthreads();
+                const int m = N2 - j - 1;
+                for (int idx = tid; idx < m * (m + 1) / 2; idx += NTG) {
+                    // lower triangle of the trailing block, row-major packed
+                    int ii = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+                    while ((ii + 1) * (ii + 2) / 2 <= idx) ++ii;
+                    while (ii * (ii + 1) / 2 > idx) --ii;
+                    const int mm = idx - ii * (ii + 1) / 2;
+                    const int gi = j + 1 + ii, gmm = j + 1 + mm;
+                    Sb[gi * N2 + gmm] -= Sb[gi * N2 + j] * Sb[gmm * N2 + j];
+                }
+                __syncthreads();
+            }
+        }
+        if (Lout)
+            for (int idx = tid; idx < N2 * N2; idx += NTG) Lout[(size_t)e * N2 * N2 + idx] = Sb[idx];
+        // ------------------------------------------------------------ [W | w] = L^{-1} [B~2 | f~2] (blocked)
+        constexpr int BS = 8;
+        for (int b0 = 0; b0 < N2; b0 += BS) {
+            const int be = min(b0 + BS, N2);
+            for (int c = tid; c < C; c += NTG)
+                for (int i = b0; i < be; ++i) {
+                    T s = X[i * C + c];
+                    for (int m = b0; m < i; ++m) s -= Sb[i * N2 + m] * X[m * C + c];
+                    X[i * C + c] = s / Sb[i * N2 + i];
+                }
+            __syncthreads();
+            for (int idx = tid; idx < (N2 - be) * C; idx += NTG) {
+                const int i = be + idx / C, c = idx % C;
+                T s = 0;
+                for (int m = b0; m < be; ++m) s += Sb[i * N2 + m] * X[m * C + c];
+                X[i * C + c] -= s;
+            }
+            __syncthreads();
+        }
+        // ------------------------------------------------------------ K_e, r_e
+        {
+            const T j1 = (T)cf.j1;
+            const T j2 = -j1;
+            constexpr int NBA = (TT + 3) / 4;
+            T* Kee = Ke + (size_t)e * TT * TT;
+            for (int blk = tid; blk < NBA * NBA; blk += NTG) {
+                const int a0 = 4 * (blk / NBA), b0 = 4 * (blk % NBA);
+                T ww[4][4] = {}, ee[4][4] = {};
+                for (int row = 0; row < N2; ++row) {
+                    T xa[4], xb[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        xa[u] = X[row * C + min(a0 + u, TT - 1)];
+                        xb[u] = X[row * C + min(b0 + u, TT - 1)];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) ww[u][v] += xa[u] * xb[v];
+                }
+                int fa[4], la[4], fb[4], lb[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int aa = min(a0 + u, TT - 1), bb = min(b0 + u, TT - 1);
+                    fa[u] = aa / NF / MT;
+                    la[u] = aa % NF;
+                    fb[u] = bb / NF / MT;
+                    lb[u] = bb % NF;
+                }
+                for (int i = 0; i < N; ++i) {
+                    T ea[4], eb[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        ea[u] = El[(fa[u] * N + i) * NF + la[u]];
+                        eb[u] = El[(fb[u] * N + i) * NF + lb[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) ee[u][v] += ea[u] * eb[v];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int aa = a0 + u;
+                    if (aa >= TT) continue;
+                    const int fca = aa / NF;
+                    const T sa = (T)geo[1 + D * D + fa[u]];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int bb = b0 + v;
+                        if (bb >= TT) continue;
+                        const int fcb = bb / NF;
+                        const T sb = (T)geo[1 + D * D + fb[v]];
+                        T val = -j1 * invJ * sa * sb * (T)cf.g1[fca][fcb] * ee[u][v] - j2 * ww[u][v];
+                        if (aa == bb) val += (T)cf.dface * sa;
+                        Kee[aa * TT + bb] = val;
+                    }
+                }
+            }
+            T* ree = re + (size_t)e * TT * R;
+            for (int idx = tid; idx < TT * R; idx += NTG) {
+                const int aa = idx / R, q = idx % R;
+                const int fc = aa / NF, l = aa % NF, f = fc / MT;
+                T acc = 0, accb = 0;
+                for (int row = 0; row < N2; ++row) acc += X[row * C + aa] * X[row * C + TT + q];
+                for (int i = 0; i < N; ++i) {
+                    T fb = 0;
+#pragma unroll
+                    for (int al = 0; al < M1; ++al) fb += (T)cf.bd[al][fc] * F1[(al * N + i) * R + q];
+                    accb += El[(f * N + i) * NF + l] * fb;
+                }
+                ree[idx] = -j1 * invJ * (T)geo[1 + D * D + f] * accb - j2 * acc;
+            }
+        }
+        __syncthreads();
+        // ------------------------------------------------------------ Z2 = L^{-T} W, z2 = L^{-T} w (blocked)
+        for (int b1 = N2; b1 > 0; b1 -= BS) {
+            const int bs0 = max(b1 - BS, 0);
+            for (int c = tid; c < C; c += NTG)
+                for (int i = b1 - 1; i >= bs0; --i) {
+                    T s = X[i * C + c];
+                    for (int m = i + 1; m < b1; ++m) s -= Sb[m * N2 + i] * X[m * C + c];
+                    X[i * C + c] = s / Sb[i * N2 + i];
+                }
+            __syncthreads();
+            for (int idx = tid; idx < bs0 * C; idx += NTG) {
+                const int i = idx / C, c = idx % C;
+                T s = 0;
+                for (int m = bs0; m < b1; ++m) s += Sb[m * N2 + i] * X[m * C + c];
+                X[i * C + c] -= s;
+            }
+            __syncthreads();
+        }
+        T* Zse = Zs + (size_t)e * N2 * TT;
+        for (int idx = tid; idx < N2 * TT; idx += NTG) Zse[idx] = X[(idx / TT) * C + idx % TT];
+        T* zse = zs + (size_t)e * NLOC * R;
+        for (int idx = tid; idx < N2 * R; idx += NTG) zse[N1 * R + idx] = X[(idx / R) * C + TT + idx % R];
+        for (int idx = tid; idx < N1 * R; idx += NTG) {
+            const int al = idx / (N * R), iq = idx % (N * R);
+            T s = 0;
+#pragma unroll
+            for (int a2 = 0; a2 < M1; ++a2) s += (T)cf.d1inv[al][a2] * F1[a2 * N * R + iq];
+            zse[idx] = s * invJ;
+        }
+    }
+}
+
+// Recovery: u2 = z2 - Z2 lam_e ;
+// u1_a = z1_a - (1/|J|) sum_fc bd[a][fc] s_f E_f lam_fc - sum_{r,b} cd[r][a][b] Sr_r^T u2_b
+template <int PHYS, int K, int R, typename T, int WPB>
+__global__ __launch_bounds__(64 * WPB) void recover_general_kernel(
+    int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
+    const int32_t* __restrict__ eperm, const int32_t* __restrict__ eface, const T* __restrict__ Sr,
+    const T* __restrict__ Ef, const T* __restrict__ Zs, const T* __restrict__ zs,
+    const double* __restrict__ lam, double* __restrict__ u) {
+    using Dm = GDims<PHYS, K, R>;
+    constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, NPERM = Dm::NPERM, D = Dm::D;
+    constexpr int M1 = Dm::M1, M2 = Dm::M2, MT = Dm::MT, N1 = Dm::N1, N2 = Dm::N2, NLOC = Dm::NLOC;
+    constexpr int NFC = Dm::NFC, TT = Dm::TT;
+    struct Scr {
+        double geo[GEOM_STRIDE];
+        double frm[24];
+        double lm[TT * R];
+        double u2[N2 * R];
+        double ef[NFC * N * R];
+        double yu[D * M2 * N * R];
+        Coef<PHYS> cf;
+    };
+    __shared__ double Srs[D * N * N];
+    __shared__ Scr scr_all[WPB];
+    for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = (double)Sr[idx];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Scr& sc = scr_all[wave];
+    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
+        if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
+        if (PHYS == PH_MAXWELL && lane < 24) sc.frm[lane] = eframe[e * 24 + lane];
+        for (int idx = lane; idx < TT * R; idx += 64) {
+            const int c = idx / R, q = idx % R;
+            const int f = c / (MT * NF);
+            const int32_t F = eface[e * NFACE + f];
+            sc.lm[idx] = lam[((int64_t)F * MT * NF + c % (MT * NF)) * R + q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane == 0) coef_primary<PHYS>(sc.geo, sc.frm, a, sc.cf);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        coef_derived_a<PHYS>(sc.cf, lane, 64);
+        const T* Zse = Zs + (size_t)e * N2 * TT;
+        const T* zse = zs + (size_t)e * NLOC * R;
+        double* ue = u + (size_t)e * NLOC * R;
+        for (int idx = lane; idx < N2 * R; idx += 64) {
+            const int row = idx / R, q = idx % R;
+            double acc = (double)zse[N1 * R + idx];
+            const T* Zr = Zse + row * TT;
+            for (int c = 0; c < TT; ++c) acc -= (double)Zr[c] * sc.lm[c * R + q];
+            sc.u2[idx] = acc;
+            ue[N1 * R + idx] = acc;
+        }
+        for (int idx = lane; idx < NFC * N * R; idx += 64) {
+            const int fc = idx / (N * R), i = (idx / R) % N, q = idx % R;
+            const int f = fc / MT, p = eperm[e * NFACE + f];
+            const T* Er = Ef + (size_t)(f * NPERM + p) * N * NF + i * NF;
+            double s = 0.0;
+            for (int l = 0; l < NF; ++l) s += (double)Er[l] * sc.lm[(fc * NF + l) * R + q];
+            sc.ef[idx] = s * sc.geo[1 + D * D + f];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int idx = lane; idx < D * M2 * N * R; idx += 64) {
+            const int r = idx / (M2 * N * R), b = (idx / (N * R)) % M2, i = (idx / R) % N, q = idx % R;
+            double s = 0.0;
+            for (int j = 0; j < N; ++j) s += Srs[(r * N + j) * N + i] * sc.u2[(b * N + j) * R + q];
+            sc.yu[idx] = s;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double invJ = 1.0 / sc.geo[0];
+        for (int idx = lane; idx < N1 * R; idx += 64) {
+            const int al = idx / (N * R), iq = idx % (N * R);
+            double s1 = 0.0, s2 = 0.0;
+            for (int fc = 0; fc < NFC; ++fc) s1 += sc.cf.bd[al][fc] * sc.ef[fc * N * R + iq];
+            for (int r = 0; r < D; ++r)
+                for (int b = 0; b < M2; ++b) s2 += sc.cf.cd[r][al][b] * sc.yu[(r * M2 + b) * N * R + iq];
+            ue[idx] = (double)zse[idx] - invJ * s1 - s2;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Mixed-precision refinement step (FP64 residual of the full stage system, correction through
+// the stored FP32 factors):
+//   s1 = f1 - |J| (dmat (x) I) u1 - X u2 - B1 lam,   s2 = f2 + X^T u1 - A22 u2 - B2 lam
+//   t_e = j1 B1^T u1 + j2 B2^T u2 + D lam
+//   s~2 = s2 + X^T D1^{-1} s1,  z' = [D1^{-1} s1 ; L^{-T} L^{-1} s~2]
+//   re64 = -j1 B1^T D1^{-1} s1 - j2 Z2^T s~2 - t_e
+// One element per wavefront; operator applications staged as short products with lanes over
+// their outputs; the triangular solves are column-oriented with lanes over rows.
+template <int PHYS, int K, int R, typename T, int WPB>
+__global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
+    int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
+    const int32_t* __restrict__ eperm, const int32_t* __restrict__ eface, const double* __restrict__ Sr,
+    const double* __restrict__ Mf, const double* __restrict__ Ef, const T* __restrict__ Zs,
+    const T* __restrict__ Lst, const double* __restrict__ u, const double* __restrict__ lam,
+    const double* __restrict__ f, T* __restrict__ zout, double* __restrict__ re64) {
+    using Dm = GDims<PHYS, K, R>;
+    constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, NPERM = Dm::NPERM, D = Dm::D;
+    constexpr int M1 = Dm::M1, M2 = Dm::M2, MT = Dm::MT, N1 = Dm::N1, N2 = Dm::N2, NLOC = Dm::NLOC;
+    constexpr int NFC = Dm::NFC, TT = Dm::TT;
+    struct Scr {
+        double geo[GEOM_STRIDE];
+        double frm[24];
+        double uu[NLOC * R];
+        double su[NLOC * R];
+        double lm[TT * R];
+        double ef[NFC * N * R];        // s_f E_f lam_fc
+        double yu[D * M2 * N * R];     // Sr_r^T u2_b
+        double gu[D * M2 * N * R];     // sum_a c[r][a][b] u1_a, later sum_a cd[r][a][b] s1_a
+        double mu[NFACE * M2 * N * R]; // Mf_f u2_b
+        double st[N2 * R];             // s~2, then S^{-1} s~2
+        double te[TT * R];
+        double El[NFACE * N * NF];
+        Coef<PHYS> cf;
+    };
+    __shared__ double Srs[D * N * N];
+    __shared__ double Mfs[NFACE * N * N];
+    __shared__ Scr scr_all[WPB];
+    for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
+    for (int idx = threadIdx.x; idx < NFACE * N * N; idx += 64 * WPB) Mfs[idx] = Mf[idx];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Scr& sc = scr_all[wave];
+    auto ws = []() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
+        if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
+        if (PHYS == PH_MAXWELL && lane < 24) sc.frm[lane] = eframe[e * 24 + lane];
+        for (int idx = lane; idx < NLOC * R; idx += 64) {
+            sc.uu[idx] = u[(size_t)e * NLOC * R + idx];
+            sc.su[idx] = f[(size_t)e * NLOC * R + idx];
+        }
+        for (int idx = lane; idx < TT * R; idx += 64) {
+            const int c = idx / R, q = idx % R;
+            const int32_t F = eface[e * NFACE + c / (MT * NF)];
+            sc.lm[idx] = lam[((int64_t)F * MT * NF + c % (MT * NF)) * R + q];
+        }
+        for (int idx = lane; idx < NFACE * N * NF; idx += 64) {
+            const int fc = idx / (N * NF);
+            const int p = eperm[e * NFACE + fc];
+            sc.El[idx] = Ef[(size_t)(fc * NPERM + p) * N * NF + (idx - fc * N * NF)];
+        }
+        ws();
+        if (lane == 0) coef_primary<PHYS>(sc.geo, sc.frm, a, sc.cf);
+        ws();
+        coef_derived_a<PHYS>(sc.cf, lane, 64);
+        const double J = sc.geo[0];
+        const double* u1 = sc.uu;
+        const double* u2 = sc.uu + N1 * R;
+        // ---- stage 1: E_f lam, Sr^T u2, c-weighted u1, Mf u2
+        for (int idx = lane; idx < NFC * N * R; idx += 64) {
+            const int fc = idx / (N * R), i = (idx / R) % N, q = idx % R;
+            const int f = fc / MT;
+            double s = 0.0;
+            for (int l = 0; l < NF; ++l) s += sc.El[(f * N + i) * NF + l] * sc.lm[(fc * NF + l) * R + q];
+            sc.ef[idx] = sc.geo[1 + D * D + f] * s;
+        }
+        for (int idx = lane; idx < D * M2 * N * R; idx += 64) {
+            const int r = idx / (M2 * N * R), b = (idx / (N * R)) % M2, i = (idx / R) % N, q = idx % R;
+            double y = 0.0, g = 0.0;
+            for (int j = 0; j < N; ++j) y += Srs[(r * N + j) * N + i] * u2[(b * N + j) * R + q];
+            for (int al = 0; al < M1; ++al) g += sc.cf.c[r][al][b] * u1[(al * N + i) * R + q];
+            sc.yu[idx] = y;
+            sc.gu[idx] = g;
+        }
+        for (int idx = lane; idx < NFACE * M2 * N * R; idx += 64) {
+            const int fa = idx / (M2 * N * R), b = (idx / (N * R)) % M2, i = (idx / R) % N, q = idx % R;
+            double s = 0.0;
+            for (int j = 0; j < N; ++j) s += Mfs[(fa * N + i) * N + j] * u2[(b * N + j) * R + q];
+            sc.mu[idx] = s;
+        }
+        ws();
+        // ---- stage 2: s = f - A u - B lam
+        for (int idx = lane; idx < NLOC * R; idx += 64) {
+            const int row = idx / R, q = idx % R;
+            double Au;
+            if (row < N1) {
+                const int al = row / N, i = row % N;
+                double s = 0.0;
+                for (int a2 = 0; a2 < M1; ++a2) s += sc.cf.dmat[al][a2] * u1[(a2 * N + i) * R + q];
+                Au = J * s;
+                double x = 0.0;
+                for (int r = 0; r < D; ++r)
+                    for (int b = 0; b < M2; ++b) x += sc.cf.c[r][al][b] * sc.yu[((r * M2 + b) * N + i) * R + q];
+                Au += J * x;
+                for (int fc = 0; fc < NFC; ++fc) Au += sc.cf.b1[al][fc] * sc.ef[(fc * N + i) * R + q];
+            } else {
+                const int b = (row - N1) / N, i = (row - N1) % N;
+                double xt = 0.0;
+                for (int r = 0; r < D; ++r) {
+                    const double* Srow = &Srs[(r * N + i) * N];
+                    for (int j = 0; j < N; ++j) xt += Srow[j] * sc.gu[((r * M2 + b) * N + j) * R + q];
+                }
+                double s = 0.0;
+                for (int gm = 0; gm < M2; ++gm) {
+                    s += J * sc.cf.amass[b][gm] * u2[(gm * N + i) * R + q];
+                    for (int fa = 0; fa < NFACE; ++fa)
+                        s += sc.geo[1 + D * D + fa] * sc.cf.af[fa][b][gm] * sc.mu[((fa * M2 + gm) * N + i) * R + q];
+                }
+                for (int fc = 0; fc < NFC; ++fc) s += sc.cf.b2[b][fc] * sc.ef[(fc * N + i) * R + q];
+                Au = -J * xt + s;
+            }
+            sc.su[idx] -= Au;
+        }
+        // ---- t_e = j1 B1^T u1 + j2 B2^T u2 + D lam
+        const double j1 = sc.cf.j1, j2 = -j1;
+        for (int idx = lane; idx < TT * R; idx += 64) {
+            const int aa = idx / R, q = idx % R;
+            const int fc = aa / NF, l = aa % NF, f = fc / MT;
+            double s = 0.0;
+            for (int i = 0; i < N; ++i) {
+                double w = 0.0;
+                for (int al = 0; al < M1; ++al) w += j1 * sc.cf.b1[al][fc] * u1[(al * N + i) * R + q];
+                for (int b = 0; b < M2; ++b) w += j2 * sc.cf.b2[b][fc] * u2[(b * N + i) * R + q];
+                s += sc.El[(f * N + i) * NF + l] * w;
+            }
+            const double sf = sc.geo[1 + D * D + f];
+            sc.te[idx] = sf * s + sc.cf.dface * sf * sc.lm[idx];
+        }
+        ws();
+        const double* s1 = sc.su;
+        const double* s2 = sc.su + N1 * R;
+        // ---- stage 3: cd-weighted s1, then s~2
+        for (int idx = lane; idx < D * M2 * N * R; idx += 64) {
+            const int r = idx / (M2 * N * R), b = (idx / (N * R)) % M2, iq = idx % (N * R);
+            double g = 0.0;
+            for (int al = 0; al < M1; ++al) g += sc.cf.cd[r][al][b] * s1[al * N * R + iq];
+            sc.gu[idx] = g;
+        }
+        ws();
+        for (int idx = lane; idx < N2 * R; idx += 64) {
+            const int b = idx / (N * R), i = (idx / R) % N, q = idx % R;
+            double acc = 0.0;
+            for (int r = 0; r < D; ++r) {
+                const double* Srow = &Srs[(r * N + i) * N];
+                for (int j = 0; j < N; ++j) acc += Srow[j] * sc.gu[((r * M2 + b) * N + j) * R + q];
+            }
+            sc.st[idx] = s2[idx] + acc;
+        }
+        ws();
+        // ---- re64 = -j1 B1^T D1^{-1} s1 - j2 Z2^T s~2 - t_e
+        const T* Zse = Zs + (size_t)e * N2 * TT;
+        for (int idx = lane; idx < TT * R; idx += 64) {
+            const int aa = idx / R, q = idx % R;
+            const int fc = aa / NF, l = aa % NF, f = fc / MT;
+            double rb = 0.0, zt = 0.0;
+            for (int i = 0; i < N; ++i) {
+                double w = 0.0;
+                for (int al = 0; al < M1; ++al) w += sc.cf.bd[al][fc] * s1[(al * N + i) * R + q];
+                rb += sc.El[(f * N + i) * NF + l] * w;
+            }
+            for (int row = 0; row < N2; ++row) zt += (double)Zse[row * TT + aa] * sc.st[row * R + q];
+            re64[(size_t)e * TT * R + idx] = -j1 * sc.geo[1 + D * D + f] / J * rb - j2 * zt - sc.te[idx];
+        }
+        // ---- z' = [D1^{-1} s1 ; S^{-1} s~2]
+        T* ze = zout + (size_t)e * NLOC * R;
+        for (int idx = lane; idx < N1 * R; idx += 64) {
+            const int al = idx / (N * R), iq = idx % (N * R);
+            double s = 0.0;
+            for (int a2 = 0; a2 < M1; ++a2) s += sc.cf.d1inv[al][a2] * s1[a2 * N * R + iq];
+            ze[idx] = (T)(s / J);
+        }
+        ws();
+        const T* L = Lst + (size_t)e * N2 * N2;
+        for (int q = 0; q < R; ++q) {
+            for (int j = 0; j < N2; ++j) {            // forward: L y = s~2
+                const double yj = sc.st[j * R + q] / (double)L[j * N2 + j];
+                ws();
+                if (lane == 0) sc.st[j * R + q] = yj;
+                for (int i = j + 1 + lane; i < N2; i += 64) sc.st[i * R + q] -= (double)L[i * N2 + j] * yj;
+                ws();
+            }
+            for (int j = N2 - 1; j >= 0; --j) {       // backward: L^T x = y
+                const double xj = sc.st[j * R + q] / (double)L[j * N2 + j];
+                ws();
+                if (lane == 0) sc.st[j * R + q] = xj;
+                for (int i = lane; i < j; i += 64) sc.st[i * R + q] -= (double)L[j * N2 + i] * xj;
+                ws();
+            }
+        }
+        for (int idx = lane; idx < N2 * R; idx += 64) ze[N1 * R + idx] = (T)sc.st[idx];
+        ws();
+    }
+}
+
+template <int PHYS, int K, int R, typename T>
+int launch_gen_ref(hdg_ctx* c, const double* u, const double* lam) {
+    constexpr int WPB = 1;
+    const int grid = (int)std::min<int64_t>(c->n_elem, 256 * 16);
+    hipLaunchKernelGGL((refine_general_kernel<PHYS, K, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream,
+                       c->n_elem, c->last_a, c->d_geom, c->d_eframe, c->d_eperm, c->d_eface, c->tab.Sr, c->tab.Mf,
+                       c->tab.Ef, (const T*)c->d_Zt, (const T*)c->d_LU, u, lam, c->d_f_saved, (T*)c->d_z,
+                       c->d_re64);
+    return (int)hipGetLastError();
+}
+
+template <int PHYS, int K, int R, typename T>
+constexpr bool x_global() {
+    using Dm = GDims<PHYS, K, R>;
+    constexpr size_t lds = sizeof(T) * (Dm::D * Dm::N * Dm::N + Dm::SBUF + Dm::NFACE * Dm::N * Dm::NF +
+                                        Dm::N1 * R + Dm::N2 * Dm::C) +
+                           sizeof(Coef<PHYS>) + 8 * 64;
+    return lds > 150 * 1024;
+}
+
+template <int PHYS, int K, int R, typename T>
+int launch_gen(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* Mf, const T* Tf, const T* Ef) {
+    using Dm = GDims<PHYS, K, R>;
+    constexpr bool XG = x_global<PHYS, K, R, T>();
+    const int grid = (int)std::min<int64_t>(c->n_elem, 256 * 8);
+    if (XG && !c->d_xscratch) {
+        hipError_t er = hipMalloc(&c->d_xscratch, (size_t)grid * Dm::N2 * Dm::C * sizeof(T));
+        if (er != hipSuccess) return (int)er;
+    }
+    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, R, T, XG>), dim3(grid), dim3(NTG), 0, c->stream,
+                       c->n_elem, a, c->d_geom, c->d_eframe, c->d_eperm, Sr, Mf, Tf, Ef, f_loc, (T*)c->d_Ke,
+                       (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
+                       c->precision == HDG_MIXED_FP32 ? (T*)c->d_LU : (T*)nullptr, (T*)c->d_xscratch,
+                       c->d_status);
+    return (int)hipGetLastError();
+}
+
+template <int PHYS, int K, int R, typename T>
+int launch_gen_rec(hdg_ctx* c, const T* Sr, const T* Ef, const double* lam, double* u) {
+    constexpr int WPB = 2;
+    int64_t groups = (c->n_elem + WPB - 1) / WPB;
+    int grid = (int)std::min<int64_t>(groups, 256 * 16);
+    hipLaunchKernelGGL((recover_general_kernel<PHYS, K, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream,
+                       c->n_elem, c->last_a, c->d_geom, c->d_eframe, c->d_eperm, c->d_eface, Sr, Ef,
+                       (const T*)c->d_Zt, (const T*)c->d_z, lam, u);
+    return (int)hipGetLastError();
+}
+
+#define HDG_GEN_CASES(X) X(1, 1, 1) X(1, 2, 1) X(1, 3, 1) X(1, 4, 1) X(2, 1, 1) X(2, 2, 1) X(2, 3, 1)
+
+template <typename T>
+int dispatch_gen(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* Mf, const T* Tf, const T* Ef) {
+    const int P = c->physics, K = c->k, R = c->nrhs;
+#define HDG_CASE(PP, KK, RR) \
+    if (P == PP && K == KK && R == RR) return launch_gen<PP, KK, RR, T>(c, a, f_loc, Sr, Mf, Tf, Ef);
+    HDG_GEN_CASES(HDG_CASE)
+#undef HDG_CASE
+    return -1;
+}
+
+template <typename T>
+int dispatch_gen_rec(hdg_ctx* c, const T* Sr, const T* Ef, const double* lam, double* u) {
+    const int P = c->physics, K = c->k, R = c->nrhs;
+#define HDG_CASE(PP, KK, RR) \
+    if (P == PP && K == KK && R == RR) return launch_gen_rec<PP, KK, RR, T>(c, Sr, Ef, lam, u);
+    HDG_GEN_CASES(HDG_CASE)
+#undef HDG_CASE
+    return -1;
+}
+
+int dispatch_gen_ref(hdg_ctx* c, const double* u, const double* lam) {
+    const int P = c->physics, K = c->k, R = c->nrhs;
+#define HDG_CASE(PP, KK, RR) \
+    if (P == PP && K == KK && R == RR) return launch_gen_ref<PP, KK, RR, float>(c, u, lam);
+    HDG_GEN_CASES(HDG_CASE)
+#undef HDG_CASE
+    return -1;
+}
+
+}  // namespace
+
+int launch_refine_general(hdg_ctx* c, const double* u, const double* lam) {
+    if (c->precision != HDG_MIXED_FP32) return -1;
+    return dispatch_gen_ref(c, u, lam);
+}
+
+bool general_supported(int physics, int k, int nrhs) {
+#define HDG_CASE(PP, KK, RR) \
+    if (physics == PP && k == KK && nrhs == RR) return true;
+    HDG_GEN_CASES(HDG_CASE)
+#undef HDG_CASE
+    return false;
+}
+
+int launch_condense_general(hdg_ctx* c, double a, const double* f_loc) {
+    if (c->precision == HDG_FP64)
+        return dispatch_gen<double>(c, a, f_loc, c->tab.Sr, c->tab.Mf, c->tab.Tfull, c->tab.Ef);
+    return dispatch_gen<float>(c, a, f_loc, c->tab.Sr32, c->tab.Mf32, c->tab.Tfull32, c->tab.Ef32);
+}
+
+int launch_recover_general(hdg_ctx* c, const double* lam, double* u) {
+    if (c->precision == HDG_FP64) return dispatch_gen_rec<double>(c, c->tab.Sr, c->tab.Ef, lam, u);
+    return dispatch_gen_rec<float>(c, c->tab.Sr32, c->tab.Ef32, lam, u);
+}
+
+}  // namespace hdg

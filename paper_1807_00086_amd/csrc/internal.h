@@ -26,7 +26,9 @@ constexpr int GEO_STAB = 29;
 struct DeviceTables {         // one polynomial degree (uniform meshes: face degree = k)
     int k = 0, N = 0, NF = 0;
     double *Sr = nullptr, *Mf = nullptr, *Tsym = nullptr, *Ef = nullptr;     // FP64
+    double* Tfull = nullptr;
     float *Sr32 = nullptr, *Mf32 = nullptr, *Tsym32 = nullptr, *Ef32 = nullptr;
+    float* Tfull32 = nullptr;
 };
 
 struct Timings {
@@ -80,6 +82,8 @@ struct hdg_ctx {
     int32_t* d_face_lf = nullptr;
     uint8_t* d_face_bnd = nullptr;
     int32_t* d_bsr_cols = nullptr;
+    double* d_eframe = nullptr;    // [ne][d+1][6] face frames of each element's faces (Maxwell)
+    void* d_xscratch = nullptr;    // per-workgroup condensation scratch when it exceeds LDS
     hdg::DeviceTables tab;
 
     // condensation outputs (precision-typed: double or float)
@@ -139,4 +143,9 @@ int launch_axpy(hdg_ctx* c, int64_t n, double alpha, const double* x, double* y)
 int launch_lincomb(hdg_ctx* c, int64_t n, double a, const double* x, double b, const double* y,
                    double* out);
 int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out);
+// condense_general.hip (elastodynamics, Maxwell)
+bool general_supported(int physics, int k, int nrhs);
+int launch_condense_general(hdg_ctx* c, double a, const double* f_loc);
+int launch_recover_general(hdg_ctx* c, const double* lam, double* u);
+int launch_refine_general(hdg_ctx* c, const double* u, const double* lam);
 }  // namespace hdg

@@ -299,6 +299,16 @@ void build_ref_tables(int d, int k, RefTables& T) {
             for (int i = 0; i < N; ++i)
                 for (int j = 0; j < N; ++j) T.Mf[(f * N + i) * N + j] += fw[q] * val[i] * val[j];
         }
+    // all products Sr Ss^T
+    T.Tfull.assign(d * d * N * N, 0.0);
+    for (int r = 0; r < d; ++r)
+        for (int s = 0; s < d; ++s)
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < N; ++j) {
+                    double acc = 0.0;
+                    for (int m = 0; m < N; ++m) acc += T.Sr[(r * N + i) * N + m] * T.Sr[(s * N + j) * N + m];
+                    T.Tfull[((r * d + s) * N + i) * N + j] = acc;
+                }
     // symmetric products Sr Ss^T
     int npair = d * (d + 1) / 2;
     T.Tsym.assign(npair * N * N, 0.0);

@@ -33,6 +33,8 @@ struct RefTables {
     std::vector<double> Mf;
     // Tsym[c][i][j]: c over the symmetric pairs (r,s), r<=s:  Sr[r] Sr[s]^T (+ transpose if r<s)
     std::vector<double> Tsym;
+    // Tfull[r][s][i][j] = (Sr[r] Sr[s]^T)[i][j]   (d x d x N x N)
+    std::vector<double> Tfull;
 };
 
 // Ef[kF][f][p][i][l] = int_{ref face} phi_i(xi_{f,p}(s)) psi_l(s) ds for face degree kF:

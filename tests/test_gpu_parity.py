@@ -74,6 +74,13 @@ CASES = [
     (2, dict(n=2, k=2)),
     (2, dict(n=3, k=3)),             # 162 tets: several workgroup waves, ragged
     (2, dict(n=2, k=4)),
+    (3, dict(n=1, k=1)),             # elastic (velocity + symmetric stress)
+    (3, dict(n=2, k=2)),
+    (3, dict(n=1, k=3)),
+    (3, dict(n=1, k=4)),             # workload degree; Schur right-hand sides in global scratch
+    (5, dict(n=2, k=1)),             # Maxwell (E, H)
+    (5, dict(n=2, k=2)),
+    (5, dict(n=2, k=3)),             # workload degree
 ]
 
 
@@ -117,6 +124,10 @@ MIXED_CASES = [
     (1, dict(n=4, k=4)),
     (2, dict(n=2, k=2)),
     (2, dict(n=3, k=3)),
+    (3, dict(n=1, k=2)),
+    (3, dict(n=1, k=4)),
+    (5, dict(n=2, k=2)),
+    (5, dict(n=2, k=3)),
 ]
 
 
