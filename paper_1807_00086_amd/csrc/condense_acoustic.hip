@@ -39,6 +39,33 @@ __device__ __forceinline__ T eps_of() {
     return sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7);
 }
 
+// ---- 16x16x4 MFMA tiles (one wavefront).  Operand layout: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator element v of lane l is C[row][l%16] with
+// row = l/16 + 4 v (FP64 instruction) or 4 (l/16) + v (FP32 instruction).
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    using acc = mf64x4;
+    __device__ static __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+    __device__ static __forceinline__ acc mac(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+    using acc = mf32x4;
+    __device__ static __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static __forceinline__ acc mac(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
 template <int D, int K, int R>
 struct AcDims {
     static constexpr int N = dimp(K, D);
@@ -63,7 +90,7 @@ struct AcScratch {
 };
 
 template <int D, int K, int R, typename T, int WPB>
-__global__ __launch_bounds__(64 * WPB) void condense_acoustic_kernel(
+__global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
     int64_t ne, double a_in, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
     const T* __restrict__ Sr, const T* __restrict__ Mf, const T* __restrict__ Tsym,
     const T* __restrict__ Ef, const double* __restrict__ f_loc, T* __restrict__ Ke,
@@ -155,29 +182,31 @@ __global__ __launch_bounds__(64 * WPB) void condense_acoustic_kernel(
                 Sb[idx] = w;
             }
             wsync();
-            // X[:, f NF + l] = -s_f W_f E_f   (2 x 2 register blocks)
-            constexpr int NBR = (N + 1) / 2, NBC = (NF + 1) / 2;
-            const T* Ef_ = &El[f * N * NF];
-            for (int blk = lane; blk < NBR * NBC; blk += 64) {
-                const int i0 = 2 * (blk / NBC), l0 = 2 * (blk % NBC);
-                const bool i1ok = i0 + 1 < N, l1ok = l0 + 1 < NF;
-                T a00 = 0, a01 = 0, a10 = 0, a11 = 0;
-                for (int j = 0; j < N; ++j) {
-                    const T w0 = Sb[i0 * N + j];
-                    const T w1 = i1ok ? Sb[(i0 + 1) * N + j] : T(0);
-                    const T e0 = Ef_[j * NF + l0];
-                    const T e1 = l1ok ? Ef_[j * NF + l0 + 1] : T(0);
-                    a00 += w0 * e0;
-                    a01 += w0 * e1;
-                    a10 += w1 * e0;
-                    a11 += w1 * e1;
-                }
+            // X[:, f NF + l] = -s_f W_f E_f   (16x16x4 MFMA tiles over rows i, columns l)
+            {
+                using MF = Mfma<T>;
+                constexpr int TM = (N + 15) / 16, TK = (N + 3) / 4;
+                const T* Ef_ = &El[f * N * NF];
+                const int lc = lane & 15, lk = lane >> 4;
                 const T s = -sf[f];
-                X[i0 * C + f * NF + l0] = s * a00;
-                if (l1ok) X[i0 * C + f * NF + l0 + 1] = s * a01;
-                if (i1ok) {
-                    X[(i0 + 1) * C + f * NF + l0] = s * a10;
-                    if (l1ok) X[(i0 + 1) * C + f * NF + l0 + 1] = s * a11;
+#pragma unroll
+                for (int tm = 0; tm < TM; ++tm) {
+                    typename MF::acc acc = MF::zero();
+                    const int am = tm * 16 + lc;
+#pragma unroll
+                    for (int tk = 0; tk < TK; ++tk) {
+                        const int k = tk * 4 + lk;
+                        const T av = (am < N && k < N) ? Sb[am * N + k] : T(0);
+                        const T bv = (lc < NF && k < N) ? Ef_[k * NF + lc] : T(0);
+                        acc = MF::mac(av, bv, acc);
+                    }
+                    if (lc < NF) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = tm * 16 + MF::row(lane, v);
+                            if (i < N) X[i * C + f * NF + lc] = s * acc[v];
+                        }
+                    }
                 }
             }
             wsync();
@@ -251,51 +280,50 @@ __global__ __launch_bounds__(64 * WPB) void condense_acoustic_kernel(
 
         // ------------------------------------------------------------ K_e, r_e
         {
-            // K = D - (1/(a rho |J|)) [s_f s_g (n_f.n_g) E_f^T E_g] + W^T W, 4 x 4 register blocks
-            constexpr int NBA = (TT + 3) / 4;
+            // K = D - (1/(a rho |J|)) [s_f s_g (n_f.n_g) E_f^T E_g] + W^T W: two MFMA chains per
+            // 16x16 output tile (inner dimension N)
+            using MF = Mfma<T>;
+            constexpr int TA = (TT + 15) / 16, TK = (N + 3) / 4;
             T* Kee = Ke + (size_t)e * TT * TT;
-            for (int blk = lane; blk < NBA * NBA; blk += 64) {
-                const int a0 = 4 * (blk / NBA), b0 = 4 * (blk % NBA);
-                T ww[4][4] = {}, ee[4][4] = {};
-                int fa[4], la[4], fb[4], lb[4];
+            const int lc = lane & 15, lk = lane >> 4;
+#pragma unroll 1
+            for (int ta = 0; ta < TA; ++ta) {
+                const int am = ta * 16 + lc;                       // this lane's A row
+                const bool aok = am < TT;
+                const int fam = aok ? am / NF : 0, lam_ = aok ? am % NF : 0;
+#pragma unroll 1
+                for (int tb = 0; tb < TA; ++tb) {
+                    const int bn = tb * 16 + lc;                   // this lane's B column
+                    const bool bok = bn < TT;
+                    const int fbn = bok ? bn / NF : 0, lbn = bok ? bn % NF : 0;
+                    typename MF::acc ww = MF::zero(), ee = MF::zero();
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int aa = min(a0 + u, TT - 1), bb = min(b0 + u, TT - 1);
-                    fa[u] = aa / NF;
-                    la[u] = aa % NF;
-                    fb[u] = bb / NF;
-                    lb[u] = bb % NF;
-                }
-                for (int i = 0; i < N; ++i) {
-                    T xa[4], xb[4], ea[4], eb[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int aa = min(a0 + u, TT - 1), bb = min(b0 + u, TT - 1);
-                        xa[u] = X[i * C + aa];
-                        xb[u] = X[i * C + bb];
-                        ea[u] = El[(fa[u] * N + i) * NF + la[u]];
-                        eb[u] = El[(fb[u] * N + i) * NF + lb[u]];
+                    for (int tk = 0; tk < TK; ++tk) {
+                        const int k = tk * 4 + lk;
+                        const bool kok = k < N;
+                        const T xa = (aok && kok) ? X[k * C + am] : T(0);
+                        const T xb = (bok && kok) ? X[k * C + bn] : T(0);
+                        const T ea = (aok && kok) ? El[(fam * N + k) * NF + lam_] : T(0);
+                        const T eb = (bok && kok) ? El[(fbn * N + k) * NF + lbn] : T(0);
+                        ww = MF::mac(xa, xb, ww);
+                        ee = MF::mac(ea, eb, ee);
                     }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    if (bok) {
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            ww[u][v] += xa[u] * xb[v];
-                            ee[u][v] += ea[u] * eb[v];
+                            const int ar = ta * 16 + MF::row(lane, v);
+                            if (ar >= TT) continue;
+                            const int fa = ar / NF;
+                            const double* ga = &sc.geo[1 + D * D];
+                            T nn = 0;
+#pragma unroll
+                            for (int x = 0; x < D; ++x)
+                                nn += (T)ga[NFACE + fa * D + x] * (T)ga[NFACE + fbn * D + x];
+                            const T sfa = (T)ga[fa], sfb = (T)ga[fbn];
+                            T val = ww[v] - inv_av * sfa * sfb * nn * ee[v];
+                            if (ar == bn) val -= tau * sfa;
+                            Kee[ar * TT + bn] = val;
                         }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (a0 + u >= TT) continue;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        if (b0 + v >= TT) continue;
-                        T nn = 0;
-#pragma unroll
-                        for (int x = 0; x < D; ++x) nn += nf[fa[u]][x] * nf[fb[v]][x];
-                        T val = ww[u][v] - inv_av * sf[fa[u]] * sf[fb[v]] * nn * ee[u][v];
-                        if (a0 + u == b0 + v) val -= tau * sf[fa[u]];
-                        Kee[(a0 + u) * TT + b0 + v] = val;
                     }
                 }
             }
