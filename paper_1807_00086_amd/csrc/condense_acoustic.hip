@@ -82,12 +82,26 @@ struct AcDims {
 template <int D, int K, int R, typename T>
 struct AcScratch {
     using Dm = AcDims<D, K, R>;
-    T Sb[Dm::N * Dm::N];                 // S, then its Cholesky factor L
+    static constexpr int NST = (Dm::N * Dm::N > Dm::NFACE * Dm::N * R) ? Dm::N * Dm::N : Dm::NFACE * Dm::N * R;
+    T Sb[NST];                           // S; staging of G f_v and n.f_v
     T X[Dm::N * Dm::C];                  // [B~ | f~] -> [W | w]
     T El[Dm::NFACE * Dm::N * Dm::NF];    // oriented face tables of the element
     T FV[D * Dm::N * R];                 // velocity right-hand side
+    T cf[Dm::NFACE * Dm::NFACE];         // s_f s_g (n_f . n_g) / (a rho |J|)
+    T dv[Dm::N];                         // inverse pivots
     double geo[GEOM_STRIDE];
 };
+
+// Broadcast of lane `src`'s value (src a compile-time constant after unrolling).
+__device__ __forceinline__ double bcast(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float bcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
 
 template <int D, int K, int R, typename T, int WPB>
 __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
@@ -97,8 +111,12 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
     T* __restrict__ re, T* __restrict__ Zs, T* __restrict__ zs, T* __restrict__ Lout,
     int* __restrict__ status) {
     using Dm = AcDims<D, K, R>;
+    using MF = Mfma<T>;
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT, C = Dm::C;
     constexpr int NLOC = Dm::NLOC, NPERM = Dm::NPERM, NPAIR = Dm::NPAIR;
+    constexpr int NC = N + C;                 // columns of the augmented matrix [S | B~ | f~]
+    constexpr int P = (NC + 63) / 64;         // columns held per lane
+    static_assert(N <= 64, "pivot columns must sit in the first register slot");
 
     __shared__ T Srs[D * N * N];
     __shared__ AcScratch<D, K, R, T> scr_all[WPB];
@@ -113,6 +131,7 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
     T* El = sc.El;
     T* FV = sc.FV;
     const T a = (T)a_in;
+    const int lc = lane & 15, lk = lane >> 4;
 
     for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
         // ------------------------------------------------------------ load
@@ -145,72 +164,86 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
         const T inv_av = inv_arho / J;          // 1 / (a rho |J|)
         const T alpha_p = a * J / (rho * cc * cc);
 
-        // ------------------------------------------------------------ f~ (pressure rhs)
+        // face-pair coefficients of the velocity part of K; G f_v for f~
+        if (lane < NFACE * NFACE) {
+            const int f = lane / NFACE, g = lane % NFACE;
+            T nn = 0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) nn += (T)sc.geo[1 + D * D + NFACE + f * D + x] * (T)sc.geo[1 + D * D + NFACE + g * D + x];
+            sc.cf[lane] = inv_av * (T)sc.geo[1 + D * D + f] * (T)sc.geo[1 + D * D + g] * nn;
+        }
+        for (int idx = lane; idx < D * N * R; idx += 64) {
+            const int r = idx / (N * R), jq = idx - r * N * R;
+            T g = 0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) g += G[r][x] * FV[x * N * R + jq];
+            Sb[idx] = g * inv_arho;
+        }
+
+        // ------------------------------------------------------------ B~ = [-s_f W_f E_f]_f
+        // W_f = tau I + (1/(a rho)) sum_r beta_fr Sr_r, formed in the MFMA operand itself;
+        // all faces share the Sr reads of one (row tile, k) step.
+        {
+            constexpr int TM = (N + 15) / 16, TK = (N + 3) / 4;
+            T beta[NFACE][D];
+#pragma unroll
+            for (int f = 0; f < NFACE; ++f)
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    T b = 0;
+#pragma unroll
+                    for (int x = 0; x < D; ++x) b += G[r][x] * nf[f][x];
+                    beta[f][r] = b * inv_arho;
+                }
+#pragma unroll
+            for (int tm = 0; tm < TM; ++tm) {
+                typename MF::acc acc[NFACE];
+#pragma unroll
+                for (int f = 0; f < NFACE; ++f) acc[f] = MF::zero();
+                const int am = tm * 16 + lc;
+#pragma unroll
+                for (int tk = 0; tk < TK; ++tk) {
+                    const int k = tk * 4 + lk;
+                    const bool aok = am < N && k < N, bok = lc < NF && k < N;
+                    T sv[D];
+#pragma unroll
+                    for (int r = 0; r < D; ++r) sv[r] = aok ? Srs[(r * N + am) * N + k] : T(0);
+                    const T dg = (aok && am == k) ? tau : T(0);
+#pragma unroll
+                    for (int f = 0; f < NFACE; ++f) {
+                        T av = dg;
+#pragma unroll
+                        for (int r = 0; r < D; ++r) av += beta[f][r] * sv[r];
+                        const T bv = bok ? El[(f * N + k) * NF + lc] : T(0);
+                        acc[f] = MF::mac(av, bv, acc[f]);
+                    }
+                }
+                if (lc < NF) {
+#pragma unroll
+                    for (int f = 0; f < NFACE; ++f)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = tm * 16 + MF::row(lane, v);
+                            if (i < N) X[i * C + f * NF + lc] = -sf[f] * acc[f][v];
+                        }
+                }
+            }
+        }
+        wsync();
+
+        // ------------------------------------------------------------ f~ = f_p - sum_r Sr_r (G f_v)_r / (a rho)
         for (int idx = lane; idx < N * R; idx += 64) {
             const int i = idx / R, q = idx % R;
             T acc = 0;
 #pragma unroll
             for (int r = 0; r < D; ++r) {
                 const T* Srow = &Srs[(r * N + i) * N];
-                for (int j = 0; j < N; ++j) {
-                    T g = 0;
 #pragma unroll
-                    for (int x = 0; x < D; ++x) g += G[r][x] * FV[(x * N + j) * R + q];
-                    acc += Srow[j] * g;
-                }
+                for (int j = 0; j < N; ++j) acc += Srow[j] * Sb[(r * N + j) * R + q];
             }
-            X[i * C + TT + q] -= inv_arho * acc;
+            X[i * C + TT + q] -= acc;
         }
-
-        // ------------------------------------------------------------ B~ face by face
-#pragma unroll 1
-        for (int f = 0; f < NFACE; ++f) {
-            T beta[D];
-#pragma unroll
-            for (int r = 0; r < D; ++r) {
-                T b = 0;
-#pragma unroll
-                for (int x = 0; x < D; ++x) b += G[r][x] * nf[f][x];
-                beta[r] = b * inv_arho;
-            }
-            // W_f = tau I + (1/(a rho)) sum_r beta_fr Sr_r  (in the S buffer, not yet in use)
-            for (int idx = lane; idx < N * N; idx += 64) {
-                T w = 0;
-#pragma unroll
-                for (int r = 0; r < D; ++r) w += beta[r] * Srs[r * N * N + idx];
-                if (idx / N == idx % N) w += tau;
-                Sb[idx] = w;
-            }
-            wsync();
-            // X[:, f NF + l] = -s_f W_f E_f   (16x16x4 MFMA tiles over rows i, columns l)
-            {
-                using MF = Mfma<T>;
-                constexpr int TM = (N + 15) / 16, TK = (N + 3) / 4;
-                const T* Ef_ = &El[f * N * NF];
-                const int lc = lane & 15, lk = lane >> 4;
-                const T s = -sf[f];
-#pragma unroll
-                for (int tm = 0; tm < TM; ++tm) {
-                    typename MF::acc acc = MF::zero();
-                    const int am = tm * 16 + lc;
-#pragma unroll
-                    for (int tk = 0; tk < TK; ++tk) {
-                        const int k = tk * 4 + lk;
-                        const T av = (am < N && k < N) ? Sb[am * N + k] : T(0);
-                        const T bv = (lc < NF && k < N) ? Ef_[k * NF + lc] : T(0);
-                        acc = MF::mac(av, bv, acc);
-                    }
-                    if (lc < NF) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int i = tm * 16 + MF::row(lane, v);
-                            if (i < N) X[i * C + f * NF + lc] = s * acc[v];
-                        }
-                    }
-                }
-            }
-            wsync();
-        }
+        wsync();
 
         // ------------------------------------------------------------ S
         {
@@ -238,54 +271,96 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
         }
         wsync();
 
-        // ------------------------------------------------------------ Cholesky S = L L^T
+        // ------------------------------------------------------------ elimination in registers
+        // Lane l holds columns l, l+64, ... of [S | B~ | f~].  Gaussian elimination without
+        // pivoting (S is SPD): S = L_u U with L_u unit lower, U = diag(d) L_u^T.  Pivot column j
+        // sits in lane j; its entries reach the other lanes through readlane broadcasts.
+        //   forward:  Y = L_u^{-1} [B~ | f~]; row j of W = diag(d)^{-1/2} Y is final at step j
+        //             (and so is column j of the Cholesky factor L = L_u diag(d)^{1/2});
+        //   backward: [Z_p | z_p] = U^{-1} Y.
+        T x[P][N];
         {
-            T dmax = 0;
-            for (int i = 0; i < N; ++i) dmax = fmax(dmax, fabs(Sb[i * N + i]));
+            T dmax = lane < N ? fabs(Sb[min(lane, N - 1) * (N + 1)]) : T(0);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
             const T ptol = T(64 * N) * eps_of<T>() * dmax;
-#pragma unroll 1
-            for (int j = 0; j < N; ++j) {
-                const T djj = Sb[j * N + j];
-                if (lane == 0 && !(djj > ptol && djj - djj == T(0))) atomicOr(status, 1);
-                const T ljj = sqrt(djj);
-                const T inv = T(1) / ljj;
-                wsync();
-                for (int i = j + 1 + lane; i < N; i += 64) Sb[i * N + j] *= inv;
-                if (lane == 0) Sb[j * N + j] = ljj;
-                wsync();
-                const int m = N - j - 1;
-                for (int idx = lane; idx < m * m; idx += 64) {
-                    const int ii = j + 1 + idx / m, mm = j + 1 + idx % m;
-                    if (mm <= ii) Sb[ii * N + mm] -= Sb[ii * N + j] * Sb[mm * N + j];
-                }
-                wsync();
+#pragma unroll
+            for (int s = 0; s < P; ++s) {
+                const int col = s * 64 + lane;
+#pragma unroll
+                for (int i = 0; i < N; ++i)
+                    x[s][i] = col < N ? Sb[i * N + min(col, N - 1)]
+                                      : (col < NC ? X[i * C + min(max(col - N, 0), C - 1)] : T(0));
             }
-        }
-        if (Lout)
-            for (int idx = lane; idx < N * N; idx += 64) Lout[(size_t)e * N * N + idx] = Sb[idx];
-
-        // ------------------------------------------------------------ [W | w] = L^{-1} [B~ | f~]
-        for (int c = lane; c < C; c += 64) {
-            T x[N];
+            T* Le = Lout ? Lout + (size_t)e * N * N : nullptr;
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                T s = X[i * C + c];
+            for (int j = 0; j < N; ++j) {
+                const T p = bcast(x[0][j], j);
+                if (lane == 0) {
+                    if (!(p > ptol && p - p == T(0))) atomicOr(status, 1);
+                    sc.dv[j] = T(1) / p;
+                }
+                const T ip = T(1) / p;
+                const T sq = sqrt(ip);
+                T t[P];
 #pragma unroll
-                for (int m = 0; m < i; ++m) s -= Sb[i * N + m] * x[m];
-                x[i] = s / Sb[i * N + i];
-                X[i * C + c] = x[i];
+                for (int s = 0; s < P; ++s) {
+                    const int col = s * 64 + lane;
+                    if (col >= N && col < NC) X[j * C + col - N] = x[s][j] * sq;
+                    t[s] = x[s][j] * ip;
+                }
+                if (Le && lane < N) Le[j * N + lane] = lane >= j ? x[0][j] * sq : T(0);
+#pragma unroll
+                for (int i = j + 1; i < N; ++i) {
+                    const T aij = bcast(x[0][i], j);
+#pragma unroll
+                    for (int s = 0; s < P; ++s) x[s][i] -= aij * t[s];
+                }
             }
         }
         wsync();
-
-        // ------------------------------------------------------------ K_e, r_e
         {
-            // K = D - (1/(a rho |J|)) [s_f s_g (n_f.n_g) E_f^T E_g] + W^T W: two MFMA chains per
-            // 16x16 output tile (inner dimension N)
-            using MF = Mfma<T>;
+#pragma unroll
+            for (int j = N - 1; j >= 0; --j) {
+                const T ip = sc.dv[j];
+                T t[P];
+#pragma unroll
+                for (int s = 0; s < P; ++s) {
+                    const bool rhs = s * 64 + lane >= N;
+                    const T z = x[s][j] * ip;
+                    t[s] = rhs ? z : T(0);
+                    if (rhs) x[s][j] = z;
+                }
+#pragma unroll
+                for (int i = 0; i < j; ++i) {
+                    const T uij = bcast(x[0][i], j);
+#pragma unroll
+                    for (int s = 0; s < P; ++s) x[s][i] -= uij * t[s];
+                }
+            }
+            T* Zse = Zs + (size_t)e * N * TT;
+            T* zse = zs + (size_t)e * NLOC * R;
+#pragma unroll
+            for (int s = 0; s < P; ++s) {
+                const int c = s * 64 + lane - N;
+                if (c >= 0 && c < TT) {
+#pragma unroll
+                    for (int i = 0; i < N; ++i) Zse[i * TT + c] = x[s][i];
+                } else if (c >= TT && c < C) {
+#pragma unroll
+                    for (int i = 0; i < N; ++i) zse[(D * N + i) * R + (c - TT)] = x[s][i];
+                }
+            }
+            // velocity rows of z: D1^{-1} f_v (the coupling to p is applied at recovery)
+            for (int idx = lane; idx < D * N * R; idx += 64) zse[idx] = FV[idx] * inv_av;
+        }
+
+        // ------------------------------------------------------------ K_e
+        // K = D - (1/(a rho |J|)) [s_f s_g (n_f.n_g) E_f^T E_g] + W^T W: two MFMA chains per
+        // 16x16 output tile (inner dimension N)
+        {
             constexpr int TA = (TT + 15) / 16, TK = (N + 3) / 4;
             T* Kee = Ke + (size_t)e * TT * TT;
-            const int lc = lane & 15, lk = lane >> 4;
 #pragma unroll 1
             for (int ta = 0; ta < TA; ++ta) {
                 const int am = ta * 16 + lc;                       // this lane's A row
@@ -314,60 +389,39 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
                             const int ar = ta * 16 + MF::row(lane, v);
                             if (ar >= TT) continue;
                             const int fa = ar / NF;
-                            const double* ga = &sc.geo[1 + D * D];
-                            T nn = 0;
-#pragma unroll
-                            for (int x = 0; x < D; ++x)
-                                nn += (T)ga[NFACE + fa * D + x] * (T)ga[NFACE + fbn * D + x];
-                            const T sfa = (T)ga[fa], sfb = (T)ga[fbn];
-                            T val = ww[v] - inv_av * sfa * sfb * nn * ee[v];
-                            if (ar == bn) val -= tau * sfa;
+                            T val = ww[v] - sc.cf[fa * NFACE + fbn] * ee[v];
+                            if (ar == bn) val -= tau * (T)sc.geo[1 + D * D + fa];
                             Kee[ar * TT + bn] = val;
                         }
                     }
                 }
             }
+        }
+
+        // ------------------------------------------------------------ r_e
+        // r_e = -(1/(a rho |J|)) B_v^T f_v + W^T w
+        for (int idx = lane; idx < NFACE * N * R; idx += 64) {
+            const int f = idx / (N * R), iq = idx - f * N * R;
+            T s = 0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) s += (T)sc.geo[1 + D * D + NFACE + f * D + x] * FV[x * N * R + iq];
+            Sb[idx] = s;
+        }
+        wsync();
+        {
             T* ree = re + (size_t)e * TT * R;
             for (int idx = lane; idx < TT * R; idx += 64) {
                 const int aa = idx / R, q = idx % R;
                 const int f = aa / NF, l = aa % NF;
                 T acc = 0, accv = 0;
+#pragma unroll
                 for (int i = 0; i < N; ++i) {
                     acc += X[i * C + aa] * X[i * C + TT + q];
-                    T fvn = 0;
-#pragma unroll
-                    for (int x = 0; x < D; ++x) fvn += nf[f][x] * FV[(x * N + i) * R + q];
-                    accv += El[(f * N + i) * NF + l] * fvn;
+                    accv += El[(f * N + i) * NF + l] * Sb[(f * N + i) * R + q];
                 }
-                ree[idx] = acc - inv_av * sf[f] * accv;
+                ree[idx] = acc - inv_av * (T)sc.geo[1 + D * D + f] * accv;
             }
         }
-        wsync();
-
-        // ------------------------------------------------------------ Z_p = L^{-T} W, z_p = L^{-T} w
-        T* Zse = Zs + (size_t)e * N * TT;
-        T* zse = zs + (size_t)e * NLOC * R;
-        for (int c = lane; c < C; c += 64) {
-            T x[N];
-#pragma unroll
-            for (int i = 0; i < N; ++i) x[i] = X[i * C + c];
-#pragma unroll
-            for (int i = N - 1; i >= 0; --i) {
-                T s = x[i];
-#pragma unroll
-                for (int m = i + 1; m < N; ++m) s -= Sb[m * N + i] * x[m];
-                x[i] = s / Sb[i * N + i];
-            }
-            if (c < TT) {
-#pragma unroll
-                for (int i = 0; i < N; ++i) Zse[i * TT + c] = x[i];
-            } else {
-#pragma unroll
-                for (int i = 0; i < N; ++i) zse[(D * N + i) * R + (c - TT)] = x[i];
-            }
-        }
-        // velocity rows of z: D1^{-1} f_v (the coupling to p is applied at recovery)
-        for (int idx = lane; idx < D * N * R; idx += 64) zse[idx] = FV[idx] * inv_av;
         wsync();
     }
 }
@@ -634,14 +688,14 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
             for (int i = 0; i < N; ++i) {
                 T s = (T)sc.st[i * R + q];
 #pragma unroll
-                for (int m = 0; m < i; ++m) s -= sc.L[i * N + m] * x[m];
+                for (int m = 0; m < i; ++m) s -= sc.L[m * N + i] * x[m];
                 x[i] = s / sc.L[i * N + i];
             }
 #pragma unroll
             for (int i = N - 1; i >= 0; --i) {
                 T s = x[i];
 #pragma unroll
-                for (int m = i + 1; m < N; ++m) s -= sc.L[m * N + i] * x[m];
+                for (int m = i + 1; m < N; ++m) s -= sc.L[i * N + m] * x[m];
                 x[i] = s / sc.L[i * N + i];
             }
 #pragma unroll
