@@ -88,8 +88,12 @@ typedef struct {
     int nrhs;                   /* right-hand sides solved together (1..32)                   */
     double krylov_tol;          /* relative residual of the FP64 trace solve                  */
     int krylov_maxit;
-    double refine_tol;          /* mixed precision: relative FP64 residual of the full system */
+    double refine_tol;          /* mixed precision: stop when the FP64 correction (or the error
+                                   left after it, estimated from the observed contraction) is
+                                   below refine_tol relative to the solution (0: 1e-13)       */
     int refine_maxit;
+    double refine_inner_tol;    /* mixed precision: relative residual of the trace solves of
+                                   the corrections (0: 1e-6)                                  */
 } hdg_options;
 
 /* Query keys for hdg_query. */
@@ -152,13 +156,13 @@ hdg_status hdg_trace_solve(hdg_ctx* ctx, double* lambda, int* iters, double* rel
  * hdg_recover -- local fields from the trace: u_e = z_e - Z_e lam_e (first block row of
  * the stage system).  In HDG_MIXED_FP32 mode the result is then refined: the residual of
  * the full uncondensed system is evaluated in FP64 from the element operators, corrected
- * through the FP32 factors and a new FP64 trace solve, until it is below refine_tol
- * relative to the right-hand side (lambda is refined in place as well).
+ * through the FP32 factors and a new FP64 trace solve, until the correction is below
+ * refine_tol relative to the solution (lambda is refined in place as well).
  *   lambda   device [n_trace_dofs][nrhs] FP64 (in; in/out in mixed mode)
  *   u_loc    device [n_local_dofs][nrhs] FP64 out
  * HDG_E_NOCONV when refinement stalls.  In mixed mode the refinement reuses the
  * condensation buffers: a second hdg_recover needs a new hdg_condense (HDG_E_STATE).
- * The inner trace solves of the refinement use krylov_tol.
+ * The inner trace solves of the refinement use refine_inner_tol.
  */
 hdg_status hdg_recover(hdg_ctx* ctx, double* lambda, double* u_loc);
 

@@ -139,6 +139,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     c->krylov_maxit = o->krylov_maxit > 0 ? o->krylov_maxit : 5000;
     c->refine_tol = o->refine_tol > 0 ? o->refine_tol : 1e-13;
     c->refine_maxit = o->refine_maxit > 0 ? o->refine_maxit : 10;
+    c->refine_inner_tol = o->refine_inner_tol > 0 ? o->refine_inner_tol : 1e-6;
     c->stream = (hipStream_t)stream;
     int st = build_mesh(c, m, p);
     if (st) {
@@ -238,7 +239,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
         TRY(dalloc(c, &c->d_du, nl));
         TRY(dalloc(c, &c->d_dlam, ntr * R));
         TRY(dalloc(c, &c->d_re64, ne * c->n_tr * R));
-        TRY(dalloc(c, &c->d_sq, ne));
+        TRY(dalloc(c, &c->d_sq, 2 * ne));
     }
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         g_init_err = "hipEventCreate failed";
@@ -319,11 +320,86 @@ hdg_status hdg_trace_solve(hdg_ctx* c, double* lambda, int* iters, double* relre
     int r;
     {
         EventTimer t(c, &c->tim.solve);
-        r = trace_cg(c, lambda, iters, relres);
+        r = trace_cg(c, lambda, c->krylov_tol, iters, relres);
     }
     if (r == HDG_E_NOCONV) return fail(c, r, "trace solve did not reach krylov_tol");
     if (r) return fail(c, r, "trace solve failed");
     return HDG_OK;
+}
+
+// Stopping test of the refinement: the correction is below refine_tol relative to the
+// solution, or (from the second correction on) the error left after it, estimated by the
+// observed contraction rel_k / rel_{k-1} times rel_k, is.  Returns -1 to continue.
+static bool refine_converged(const hdg_ctx* c, int it, double rel, double prev) {
+    if (rel <= c->refine_tol) return true;
+    return it > 1 && prev > 0.0 && rel * (rel / prev) <= c->refine_tol;
+}
+
+static int refine_verdict(hdg_ctx* c, int it, double rel, double prev) {
+    if (!(rel == rel)) return fail(c, HDG_E_NOCONV, "refinement produced a non-finite correction");
+    if (refine_converged(c, it, rel, prev)) return HDG_OK;
+    if (it > 1 && rel > 0.5 * prev) return fail(c, HDG_E_NOCONV, "refinement stagnated");
+    return -1;
+}
+
+// Acoustic mixed precision: recovery and refinement fused per element (the velocity is
+// recovered in closed form in FP64, so the iteration runs on (p, lam)).  When the trace
+// correction alone already meets the stopping test, the last element pass recovers without
+// forming a new residual; should the full correction then miss the test after all, a pass
+// without correction forms the residual and the iteration goes on.
+static hdg_status recover_refine_acoustic(hdg_ctx* c, double* lambda, double* u) {
+    const int64_t nt = c->n_trace_dofs * c->nrhs;
+    int e;
+    {
+        EventTimer t(c, &c->tim.recover);
+        e = launch_refine_acoustic(c, lambda, lambda, 1, true, u, nullptr);
+    }
+    if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
+    c->z_consumed = true;
+    double prev = 0.0, prev_l = 0.0;
+    for (int it = 1; it <= c->refine_maxit; ++it) {
+        float t_sol = 0.f, t_el = 0.f;
+        int r;
+        {
+            EventTimer t(c, &t_sol);
+            e = launch_assemble_rhs64(c, c->d_re64);
+            if (e) return fail(c, HDG_E_HIP, "refinement assembly launch failed");
+            HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
+            int its;
+            double rr;
+            r = trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr);
+        }
+        if (r && r != HDG_E_NOCONV) return fail(c, r, "refinement trace solve failed");
+        launch_axpy(c, nt, 1.0, c->d_dlam, lambda);
+        double ndl, nlam;
+        launch_norm2(c, nt, c->d_dlam, &ndl);
+        launch_norm2(c, nt, lambda, &nlam);
+        const double rel_l = ndl / (nlam > 0 ? nlam : 1.0);
+        const bool last = (rel_l == rel_l) && refine_converged(c, it, rel_l, prev_l);
+        {
+            EventTimer t(c, &t_el);
+            e = launch_refine_acoustic(c, lambda, c->d_dlam, 0, !last, u, c->d_sq);
+        }
+        if (e) return fail(c, HDG_E_HIP, "refinement kernel launch failed");
+        c->tim.refine_elem += t_el;
+        c->tim.refine_solve += t_sol;
+        double ndu, nu;
+        launch_norm2(c, c->n_elem, c->d_sq, &ndu);
+        launch_norm2(c, c->n_elem, c->d_sq + c->n_elem, &nu);
+        const double rel = std::max(ndu / (nu > 0 ? nu : 1.0), rel_l);
+        c->last_refine = it;
+        const int v = refine_verdict(c, it, rel, prev);
+        if (v >= 0) return v;
+        if (last) {   // residual of the current iterate, no correction
+            EventTimer t(c, &t_el);
+            e = launch_refine_acoustic(c, lambda, c->d_dlam, 2, true, u, c->d_sq);
+            if (e) return fail(c, HDG_E_HIP, "refinement kernel launch failed");
+        }
+        if (last) c->tim.refine_elem += t_el;
+        prev = rel;
+        prev_l = rel_l;
+    }
+    return fail(c, HDG_E_NOCONV, "refinement did not reach refine_tol within refine_maxit");
 }
 
 hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
@@ -335,15 +411,17 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
                                     "condensation buffers; call hdg_condense again");
     int s = check_status(c);
     if (s) return s;
-    int e;
-    {
-        EventTimer t(c, &c->tim.recover);
-        e = launch_recover_any(c, lambda, u);
-    }
-    if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
     c->last_refine = 0;
     c->tim.refine_elem = 0.f;
     c->tim.refine_solve = 0.f;
+    if (c->precision == HDG_MIXED_FP32 && c->physics == HDG_ACOUSTIC) return recover_refine_acoustic(c, lambda, u);
+    int e;
+    {
+        EventTimer t(c, &c->tim.recover);
+        e = (c->physics == HDG_ACOUSTIC) ? launch_refine_acoustic(c, lambda, lambda, 1, false, u, nullptr)
+                                         : launch_recover_any(c, lambda, u);
+    }
+    if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
     if (c->precision != HDG_MIXED_FP32) return HDG_OK;
 
     // Iterative refinement of the full stage system: FP64 residual, correction through the
@@ -355,18 +433,18 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
         float t_res = 0.f, t_sol = 0.f, t_rec = 0.f;
         {
             EventTimer t(c, &t_res);
-            e = (c->physics == HDG_ACOUSTIC) ? launch_refine_residual(c, u, lambda, c->d_sq)
-                                             : launch_refine_general(c, u, lambda);
-            if (!e) e = launch_assemble_rhs64(c, c->d_re64);
+            e = launch_refine_general(c, u, lambda);
         }
         if (e) return fail(c, HDG_E_HIP, "refinement kernel launch failed");
-        HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
         int r;
         {
             EventTimer t(c, &t_sol);
+            e = launch_assemble_rhs64(c, c->d_re64);
+            if (e) return fail(c, HDG_E_HIP, "refinement assembly launch failed");
+            HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
             int its;
             double rr;
-            r = trace_cg(c, c->d_dlam, &its, &rr);
+            r = trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr);
         }
         if (r && r != HDG_E_NOCONV) return fail(c, r, "refinement trace solve failed");
         {
@@ -385,9 +463,8 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
         launch_norm2(c, nt, lambda, &nlam);
         const double rel = std::max(ndu / (nu > 0 ? nu : 1.0), ndl / (nlam > 0 ? nlam : 1.0));
         c->last_refine = it;
-        if (!(rel == rel)) return fail(c, HDG_E_NOCONV, "refinement produced a non-finite correction");
-        if (rel <= c->refine_tol) return HDG_OK;
-        if (it > 1 && rel > 0.5 * prev) return fail(c, HDG_E_NOCONV, "refinement stagnated");
+        const int v = refine_verdict(c, it, rel, prev);
+        if (v >= 0) return v;
         prev = rel;
     }
     return fail(c, HDG_E_NOCONV, "refinement did not reach refine_tol within refine_maxit");

@@ -115,7 +115,13 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT, C = Dm::C;
     constexpr int NLOC = Dm::NLOC, NPERM = Dm::NPERM, NPAIR = Dm::NPAIR;
     constexpr int NC = N + C;                 // columns of the augmented matrix [S | B~ | f~]
-    constexpr int P = (NC + 63) / 64;         // columns held per lane
+    // The low-precision kernel (mixed precision) also carries the identity through the forward
+    // elimination: it becomes L_u^{-1}, and diag(d)^{-1/2} L_u^{-1} = L^{-1} is kept for the
+    // refinement.
+    constexpr int NI = sizeof(T) == 4 ? N : 0;
+    constexpr int NCT = NC + NI;
+    constexpr int P = (NCT + 63) / 64;        // columns held per lane
+    constexpr int SB0 = N / 64, SB1 = (NC - 1) / 64;   // slots holding [B~ | f~]
     static_assert(N <= 64, "pivot columns must sit in the first register slot");
 
     __shared__ T Srs[D * N * N];
@@ -272,11 +278,11 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
         wsync();
 
         // ------------------------------------------------------------ elimination in registers
-        // Lane l holds columns l, l+64, ... of [S | B~ | f~].  Gaussian elimination without
-        // pivoting (S is SPD): S = L_u U with L_u unit lower, U = diag(d) L_u^T.  Pivot column j
-        // sits in lane j; its entries reach the other lanes through readlane broadcasts.
-        //   forward:  Y = L_u^{-1} [B~ | f~]; row j of W = diag(d)^{-1/2} Y is final at step j
-        //             (and so is column j of the Cholesky factor L = L_u diag(d)^{1/2});
+        // Lane l holds columns l, l+64, ... of [S | B~ | f~ (| I)].  Gaussian elimination
+        // without pivoting (S is SPD): S = L_u U with L_u unit lower, U = diag(d) L_u^T.  Pivot
+        // column j sits in lane j; its entries reach the other lanes through readlane broadcasts.
+        //   forward:  Y = L_u^{-1} [B~ | f~ (| I)]; row j of diag(d)^{-1/2} Y is final at step j:
+        //             W for K and, from the identity columns, row j of L^{-1};
         //   backward: [Z_p | z_p] = U^{-1} Y.
         T x[P][N];
         {
@@ -289,8 +295,9 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
                 const int col = s * 64 + lane;
 #pragma unroll
                 for (int i = 0; i < N; ++i)
-                    x[s][i] = col < N ? Sb[i * N + min(col, N - 1)]
-                                      : (col < NC ? X[i * C + min(max(col - N, 0), C - 1)] : T(0));
+                    x[s][i] = col < N    ? Sb[i * N + min(col, N - 1)]
+                              : col < NC ? X[i * C + min(max(col - N, 0), C - 1)]
+                                         : (col - NC == i ? T(1) : T(0));
             }
             T* Le = Lout ? Lout + (size_t)e * N * N : nullptr;
 #pragma unroll
@@ -307,9 +314,9 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
                 for (int s = 0; s < P; ++s) {
                     const int col = s * 64 + lane;
                     if (col >= N && col < NC) X[j * C + col - N] = x[s][j] * sq;
+                    if (NI && Le && col >= NC && col < NCT) Le[j * N + col - NC] = x[s][j] * sq;
                     t[s] = x[s][j] * ip;
                 }
-                if (Le && lane < N) Le[j * N + lane] = lane >= j ? x[0][j] * sq : T(0);
 #pragma unroll
                 for (int i = j + 1; i < N; ++i) {
                     const T aij = bcast(x[0][i], j);
@@ -325,8 +332,9 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
                 const T ip = sc.dv[j];
                 T t[P];
 #pragma unroll
-                for (int s = 0; s < P; ++s) {
-                    const bool rhs = s * 64 + lane >= N;
+                for (int s = SB0; s <= SB1; ++s) {
+                    const int col = s * 64 + lane;
+                    const bool rhs = col >= N && col < NC;
                     const T z = x[s][j] * ip;
                     t[s] = rhs ? z : T(0);
                     if (rhs) x[s][j] = z;
@@ -335,13 +343,13 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
                 for (int i = 0; i < j; ++i) {
                     const T uij = bcast(x[0][i], j);
 #pragma unroll
-                    for (int s = 0; s < P; ++s) x[s][i] -= uij * t[s];
+                    for (int s = SB0; s <= SB1; ++s) x[s][i] -= uij * t[s];
                 }
             }
             T* Zse = Zs + (size_t)e * N * TT;
             T* zse = zs + (size_t)e * NLOC * R;
 #pragma unroll
-            for (int s = 0; s < P; ++s) {
+            for (int s = SB0; s <= SB1; ++s) {
                 const int c = s * 64 + lane - N;
                 if (c >= 0 && c < TT) {
 #pragma unroll
@@ -490,226 +498,397 @@ __global__ __launch_bounds__(64 * WPB) void recover_acoustic_kernel(
     }
 }
 
-// wavefronts per workgroup: as many as fit in 80 KB of LDS (two workgroups per CU), at most 4
-// Mixed-precision refinement step (FP64 residual, FP32 correction factors).
-// For the current iterate (u, lam) of the full uncondensed stage system:
-//   s_u = f - A u - B lam   (FP64, element operators applied from the FP64 tables)
-//   t_e = C u + D lam       (the element's contribution to the trace residual)
-// and the correction right-hand sides through the stored low-precision factors:
-//   s~_p = s_p - (1/(a rho)) sum_r Sr_r (sum_x G_rx s_vx)
-//   z'   = [ s_v / (a rho |J|) ;  L^{-T} L^{-1} s~_p ]     (stored in the z buffer)
-//   r'_e = -(1/(a rho |J|)) B_v^T s_v + Z_p^T s~_p          (= -C A~^{-1} s_u)
-//   re64 = r'_e - t_e                                         (FP64, assembled into the rhs)
-// Every operator application is staged as a short matrix-vector product with the lanes over
-// its outputs (one element per wavefront).
-template <int D, int K, int R, typename T, int WPB>
+// Mixed-precision refinement step on the full stage system (FP64 residual, low-precision
+// correction factors).  The velocity block of A is a rho |J| I, so for given (p, lam) the
+// velocity that satisfies the first block row exactly is
+//   v_x = (f_vx + |J| sum_r G_rx Sr_r^T p - sum_f n_fx s_f E_f lam_f) / (a rho |J|),
+// and the refinement iterates on (p, lam) only; the velocity residual is zero up to FP64
+// rounding.  With the face trace of P_k inside the face space, Mf_f = E_f E_f^T, so the face
+// terms of the pressure row share ep_f = E_f^T p with the trace row.  One call, per element:
+//   p   <- p_prev + z'_p - Z_p dlam_e       (correction through the stored factors; mode 1, the
+//                                            first call, starts from p_prev = 0, z'_p = z_p,
+//                                            dlam = lam; mode 2 applies no correction)
+//   v   <- closed form above (FP64), u = (v, p) written back
+//   s_p  = f_p - |J| sum_r Sr_r (G v)_r - alpha p + tau sum_f s_f E_f (lam_f - ep_f)
+//   t_e  = s_f (E_f^T (n_f . v) - tau (lam_f - ep_f))                (= C u + D lam, element part)
+//   re64 = Z_p^T s_p - t_e                   (element part of the trace residual of the correction)
+//   z'_p = S^{-1} s_p = L^{-T} L^{-1} s_p    (stored inverse Cholesky factor of S)
+// and the per-element norms |du| and |u| for the stopping test.  RESID = false stops after
+// the recovery (p, v): that is the plain recovery of the condensed solve.
+//
+// Every global read of an element is issued one element ahead into registers (software
+// pipeline, one element per wavefront), so the compute phases read LDS only.  The oriented
+// face tables of all orientations are shared by the workgroup when they are small.
+
+template <int D, int K>
+constexpr bool rf_shared_faces() {
+    return (D + 1) * ((D == 3) ? 6 : 2) * dimp(K, D) * dimp(K, D - 1) * 8 <= 48 * 1024;
+}
+
+// per-wavefront LDS scratch of the refinement/recovery kernel
+template <int D, int K, int R, typename T, bool RESID>
+struct RfScratch {
+    using Dm = AcDims<D, K, R>;
+    static constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT, NLOC = Dm::NLOC;
+    static constexpr bool SHE = rf_shared_faces<D, K>();
+    double geo[GEOM_STRIDE];
+    double lm[TT * R];            // lam_e
+    double dl[TT * R];            // dlam_e
+    double uo[NLOC * R];          // u_e on entry
+    double ff[NLOC * R];          // f_e
+    double pp[N * R];             // p
+    double ef[NFACE * N * R];     // E_f lam_f
+    double yp[D * N * R];         // Sr_r^T p ; later sum_x G_rx v_x
+    double vv[D * N * R];         // v
+    double ep[TT * R];            // lam - E_f^T p
+    double nv[NFACE * N * R];     // n_f . v
+    double sp[N * R];             // s_p
+    double te[TT * R];            // t_e
+    double El[SHE ? 1 : NFACE * N * NF];
+    T Zl[N * TT];
+    T zb[N * R];                  // z'_p on entry
+    T Ll[RESID ? N * N : 1];      // inverse Cholesky factor L^{-1} of S, row-major
+    int fq[32][8];                // face ids [0..NFACE) and orientations [4..4+NFACE) of the
+                                  // next 32 elements of this wavefront
+    int fc[8];                    // the same for the element being computed
+};
+
+template <int M>
+struct PerLane {
+    static constexpr int n = (M + 63) / 64;
+};
+
+template <int D, int K, int R, typename T, int WPB, bool RESID>
 __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
-    const int32_t* __restrict__ eface, const double* __restrict__ Sr, const double* __restrict__ Mf,
-    const double* __restrict__ Ef, const T* __restrict__ Zs, const T* __restrict__ Lst,
-    const double* __restrict__ u, const double* __restrict__ lam, const double* __restrict__ f,
-    T* __restrict__ zout, double* __restrict__ re64, double* __restrict__ sq) {
+    const int32_t* __restrict__ eface, const double* __restrict__ Sr, const double* __restrict__ Ef,
+    const T* __restrict__ Zs, const T* __restrict__ Lst, const double* __restrict__ f,
+    const double* __restrict__ lam, const double* __restrict__ dlam, int mode, T* __restrict__ zb,
+    double* __restrict__ u, double* __restrict__ re64, double* __restrict__ nrm) {
     using Dm = AcDims<D, K, R>;
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT;
     constexpr int NLOC = Dm::NLOC, NPERM = Dm::NPERM;
-    struct Scr {
-        double geo[GEOM_STRIDE];
-        double uu[NLOC * R];          // iterate u_e
-        double su[NLOC * R];          // f_e, then s_u
-        double lm[TT * R];            // lam_e
-        double ef[NFACE * N * R];     // E_f lam_f
-        double gv[D * N * R];         // sum_x G_rx v_x ; later sum_x G_rx s_vx
-        double yp[D * N * R];         // Sr_r^T p
-        double vn[NFACE * N * R];     // sum_x n_fx v_x + tau p ; later sum_x n_fx s_vx
-        double st[N * R];             // s~_p
-        double te[TT * R];            // t_e = C u + D lam
-        double El[NFACE * N * NF];
-        T L[N * N];
-    };
+    constexpr int NEL = NFACE * N * NF, NZ = N * TT, NLL = RESID ? N * N : 0;
+    constexpr bool SHE = rf_shared_faces<D, K>();
+    constexpr int PT = PerLane<TT * R>::n, PE = SHE ? 0 : PerLane<NEL>::n, PZ = PerLane<NZ>::n;
+    constexpr int PB = PerLane<N * R>::n, PU = PerLane<NLOC * R>::n, PL = PerLane<NLL>::n;
+    using Scr = RfScratch<D, K, R, T, RESID>;
     __shared__ double Srs[D * N * N];
-    __shared__ double Mfs[NFACE * N * N];
+    __shared__ double Efs[SHE ? NFACE * NPERM * N * NF : 1];
     __shared__ Scr scr_all[WPB];
     for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
-    for (int idx = threadIdx.x; idx < NFACE * N * N; idx += 64 * WPB) Mfs[idx] = Mf[idx];
+    if (SHE)
+        for (int idx = threadIdx.x; idx < NFACE * NPERM * N * NF; idx += 64 * WPB) Efs[idx] = Ef[idx];
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     Scr& sc = scr_all[wave];
-    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
-        if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
-        for (int idx = lane; idx < NLOC * R; idx += 64) {
-            sc.uu[idx] = u[(size_t)e * NLOC * R + idx];
-            sc.su[idx] = f[(size_t)e * NLOC * R + idx];
-        }
-        for (int idx = lane; idx < TT * R; idx += 64) {
+    const double* g = sc.geo;
+    const int64_t stride = (int64_t)gridDim.x * WPB;
+
+    // ---- registers of the element in flight
+    double rgeo = 0.0, rlm[PT], rdl[PT], rel[PE > 0 ? PE : 1], ru[PU], rf[PU];
+    T rz[PZ], rzb[PB], rl[PL > 0 ? PL : 1];
+    // Face ids and orientations are staged through LDS 32 elements at a time (one vector load
+    // per lane), so the gathers of an element never wait on a load of the same pass.
+    auto load_faces = [&](int64_t e0) {
+        const int k = lane >> 1, part = lane & 1;
+        const int64_t ek = e0 + (int64_t)k * stride;
+        int v[NFACE];
+#pragma unroll
+        for (int fc = 0; fc < NFACE; ++fc)
+            v[fc] = ek < ne ? (part ? eperm : eface)[ek * NFACE + fc] : 0;
+#pragma unroll
+        for (int fc = 0; fc < NFACE; ++fc) sc.fq[k][part * 4 + fc] = v[fc];
+    };
+    auto issue = [&](int64_t en, int k) {
+        if (lane < GEOM_STRIDE) rgeo = geom[en * GEOM_STRIDE + lane];
+#pragma unroll
+        for (int t = 0; t < PT; ++t) {
+            const int idx = min(lane + 64 * t, TT * R - 1);
             const int c = idx / R, q = idx % R;
-            const int32_t F = eface[e * NFACE + c / NF];
-            sc.lm[idx] = lam[((int64_t)F * NF + c % NF) * R + q];
+            const int64_t off = ((int64_t)sc.fq[k][c / NF] * NF + c % NF) * R + q;
+            rlm[t] = lam[off];
+            rdl[t] = dlam[off];
         }
-        for (int idx = lane; idx < NFACE * N * NF; idx += 64) {
-            const int fc = idx / (N * NF);
-            const int p = eperm[e * NFACE + fc];
-            sc.El[idx] = Ef[(size_t)(fc * NPERM + p) * N * NF + (idx - fc * N * NF)];
+        if (!SHE)
+#pragma unroll
+            for (int t = 0; t < PE; ++t) {
+                const int idx = min(lane + 64 * t, NEL - 1);
+                const int fc = idx / (N * NF);
+                rel[t] = Ef[(size_t)(fc * NPERM + sc.fq[k][4 + fc]) * N * NF + (idx - fc * N * NF)];
+            }
+        const T* Zse = Zs + (size_t)en * NZ;
+#pragma unroll
+        for (int t = 0; t < PZ; ++t) rz[t] = Zse[min(lane + 64 * t, NZ - 1)];
+        const T* zbe = zb + (size_t)en * NLOC * R + D * N * R;
+#pragma unroll
+        for (int t = 0; t < PB; ++t) rzb[t] = zbe[min(lane + 64 * t, N * R - 1)];
+        const double* ue = u + (size_t)en * NLOC * R;
+        // without f (FP64 recovery) the velocity rows of z, D1^{-1} f_v, take its place
+        const T* zve = zb + (size_t)en * NLOC * R;
+#pragma unroll
+        for (int t = 0; t < PU; ++t) {
+            const int idx = min(lane + 64 * t, NLOC * R - 1);
+            ru[t] = mode == 1 ? 0.0 : ue[idx];
+            if (f) rf[t] = f[(size_t)en * NLOC * R + idx];
+            else rf[t] = idx < D * N * R ? (double)zve[idx] : 0.0;
         }
-        for (int idx = lane; idx < N * N; idx += 64) sc.L[idx] = Lst[(size_t)e * N * N + idx];
+        if (RESID) {
+            const T* Le = Lst + (size_t)en * NLL;
+#pragma unroll
+            for (int t = 0; t < PL; ++t) rl[t] = Le[min(lane + 64 * t, NLL - 1)];
+        }
+    };
+    auto commit = [&]() {
+        if (lane < GEOM_STRIDE) sc.geo[lane] = rgeo;
+#pragma unroll
+        for (int t = 0; t < PT; ++t)
+            if (lane + 64 * t < TT * R) {
+                sc.lm[lane + 64 * t] = rlm[t];
+                sc.dl[lane + 64 * t] = rdl[t];
+            }
+        if (!SHE)
+#pragma unroll
+            for (int t = 0; t < PE; ++t)
+                if (lane + 64 * t < NEL) sc.El[lane + 64 * t] = rel[t];
+#pragma unroll
+        for (int t = 0; t < PZ; ++t)
+            if (lane + 64 * t < NZ) sc.Zl[lane + 64 * t] = rz[t];
+#pragma unroll
+        for (int t = 0; t < PB; ++t)
+            if (lane + 64 * t < N * R) sc.zb[lane + 64 * t] = rzb[t];
+#pragma unroll
+        for (int t = 0; t < PU; ++t)
+            if (lane + 64 * t < NLOC * R) {
+                sc.uo[lane + 64 * t] = ru[t];
+                sc.ff[lane + 64 * t] = rf[t];
+            }
+        if (RESID)
+#pragma unroll
+            for (int t = 0; t < PL; ++t)
+                if (lane + 64 * t < NLL) sc.Ll[lane + 64 * t] = rl[t];
+    };
+
+    int64_t e = (int64_t)blockIdx.x * WPB + wave;
+    if (e < ne) {
+        load_faces(e);
         wsync();
-        const double* g = sc.geo;
+        issue(e, 0);
+    }
+    for (int it = 0; e < ne; e += stride, ++it) {
+        commit();
+        if (lane < 8) sc.fc[lane] = sc.fq[it & 31][lane];
+        const int kn = (it + 1) & 31;
+        if (kn == 0) load_faces(e + stride);
+        wsync();
+        if (e + stride < ne) issue(e + stride, kn);
+        // oriented face table of local face fc of this element
+        auto Eface = [&](int fc) -> const double* {
+            return SHE ? &Efs[(fc * NPERM + sc.fc[4 + fc]) * N * NF] : &sc.El[fc * N * NF];
+        };
+        double* ue = u + (size_t)e * NLOC * R;
         const double J = g[0];
         const double rho = g[GEO_PAR], cc = g[GEO_PAR + 1], tau = g[GEO_STAB];
-        const double arho = a * rho, inv_av = 1.0 / (arho * J), alpha_p = a * J / (rho * cc * cc);
-        double G[D][D], sf[NFACE], nf[NFACE][D];
+        const double inv_av = 1.0 / (a * rho * J), alpha_p = a * J / (rho * cc * cc);
+        double dn = 0.0, un = 0.0;
+        // ---- p = p_prev + z'_p - Z_p dlam ; E_f lam_f
 #pragma unroll
-        for (int r = 0; r < D; ++r)
-#pragma unroll
-            for (int x = 0; x < D; ++x) G[r][x] = g[1 + r * D + x];
-#pragma unroll
-        for (int fc = 0; fc < NFACE; ++fc) {
-            sf[fc] = g[1 + D * D + fc];
-#pragma unroll
-            for (int x = 0; x < D; ++x) nf[fc][x] = g[1 + D * D + NFACE + fc * D + x];
+        for (int t = 0; t < PerLane<N * R>::n; ++t) {
+            const int idx = lane + 64 * t;
+            if (idx < N * R) {
+                const int i = idx / R, q = idx % R;
+                double s = 0.0;
+                if (mode != 2) {
+                    s = (double)sc.zb[idx];
+#pragma unroll 8
+                    for (int c = 0; c < TT; ++c) s -= (double)sc.Zl[i * TT + c] * sc.dl[c * R + q];
+                }
+                const double p = sc.uo[D * N * R + idx] + s;
+                sc.pp[idx] = p;
+                ue[D * N * R + idx] = p;
+                dn += s * s;
+                un += p * p;
+            }
         }
-        const double* v = sc.uu;
-        const double* pp = sc.uu + D * N * R;
-        // ---- stage 1: E_f lam_f, G v, Sr^T p, n.v + tau p
-        for (int idx = lane; idx < NFACE * N * R; idx += 64) {
-            const int fc = idx / (N * R), i = (idx / R) % N, q = idx % R;
-            double s = 0.0;
 #pragma unroll
-            for (int l = 0; l < NF; ++l) s += sc.El[(fc * N + i) * NF + l] * sc.lm[(fc * NF + l) * R + q];
-            sc.ef[idx] = s;
-            double vn = tau * pp[i * R + q];
+        for (int t = 0; t < PerLane<NFACE * N * R>::n; ++t) {
+            const int idx = lane + 64 * t;
+            if (idx < NFACE * N * R) {
+                const int fc = idx / (N * R), i = (idx / R) % N, q = idx % R;
+                const double* Er = Eface(fc) + i * NF;
+                double s = 0.0;
 #pragma unroll
-            for (int x = 0; x < D; ++x) vn += nf[fc][x] * v[(x * N + i) * R + q];
-            sc.vn[idx] = vn;
-        }
-        for (int idx = lane; idx < D * N * R; idx += 64) {
-            const int r = idx / (N * R), i = (idx / R) % N, q = idx % R;
-            double s = 0.0, y = 0.0;
-#pragma unroll
-            for (int x = 0; x < D; ++x) s += G[r][x] * v[(x * N + i) * R + q];
-            sc.gv[idx] = s;
-#pragma unroll
-            for (int j = 0; j < N; ++j) y += Srs[(r * N + j) * N + i] * pp[j * R + q];
-            sc.yp[idx] = y;
+                for (int l = 0; l < NF; ++l) s += Er[l] * sc.lm[(fc * NF + l) * R + q];
+                sc.ef[idx] = s;
+            }
         }
         wsync();
-        // ---- stage 2: s_u = f - A u - B lam ; t_e part of re64
-        for (int idx = lane; idx < NLOC * R; idx += 64) {
-            const int row = idx / R, q = idx % R;
-            const int x = row / N, i = row % N;
-            double Au;
-            if (x < D) {
-                double qt = 0.0, bl = 0.0;
+        // ---- Sr_r^T p ; lam - E_f^T p
 #pragma unroll
-                for (int r = 0; r < D; ++r) qt += G[r][x] * sc.yp[(r * N + i) * R + q];
+        for (int t = 0; t < PerLane<D * N * R>::n; ++t) {
+            const int idx = lane + 64 * t;
+            if (idx < D * N * R) {
+                const int r = idx / (N * R), i = (idx / R) % N, q = idx % R;
+                double s = 0.0;
 #pragma unroll
-                for (int fc = 0; fc < NFACE; ++fc) bl += nf[fc][x] * sf[fc] * sc.ef[(fc * N + i) * R + q];
-                Au = arho * J * v[idx] - J * qt + bl;
-            } else {
-                double qv = 0.0, mp = 0.0, bp = 0.0;
+                for (int j = 0; j < N; ++j) s += Srs[(r * N + j) * N + i] * sc.pp[j * R + q];
+                sc.yp[idx] = s;
+            }
+        }
+        if (RESID)
 #pragma unroll
-                for (int r = 0; r < D; ++r) {
-                    const double* Srow = &Srs[(r * N + i) * N];
-#pragma unroll
-                    for (int j = 0; j < N; ++j) qv += Srow[j] * sc.gv[(r * N + j) * R + q];
-                }
-#pragma unroll
-                for (int fc = 0; fc < NFACE; ++fc) {
-                    const double* Mrow = &Mfs[(fc * N + i) * N];
+            for (int t = 0; t < PerLane<TT * R>::n; ++t) {
+                const int idx = lane + 64 * t;
+                if (idx < TT * R) {
+                    const int aa = idx / R, q = idx % R, fc = aa / NF, l = aa % NF;
+                    const double* Ec = Eface(fc) + l;
                     double s = 0.0;
 #pragma unroll
-                    for (int j = 0; j < N; ++j) s += Mrow[j] * pp[j * R + q];
-                    mp += sf[fc] * s;
-                    bp += sf[fc] * sc.ef[(fc * N + i) * R + q];
+                    for (int i = 0; i < N; ++i) s += Ec[i * NF] * sc.pp[i * R + q];
+                    sc.ep[idx] = sc.lm[idx] - s;
                 }
-                Au = J * qv + alpha_p * pp[i * R + q] + tau * mp - tau * bp;
             }
-            sc.su[idx] -= Au;
-        }
         wsync();
-        const double* sv = sc.su;
-        const double* sp = sc.su + D * N * R;
-        // ---- stage 3: G s_v and n.s_v (reuse gv, ef buffers); t_e into re64 accumulator
-        for (int idx = lane; idx < TT * R; idx += 64) {
-            const int aa = idx / R, q = idx % R;
-            const int fc = aa / NF, l = aa % NF;
-            double s = 0.0;
+        // ---- v in closed form
 #pragma unroll
-            for (int i = 0; i < N; ++i) s += sc.El[(fc * N + i) * NF + l] * sc.vn[(fc * N + i) * R + q];
-            sc.te[idx] = sf[fc] * s - tau * sf[fc] * sc.lm[idx];
-        }
-        wsync();
-        for (int idx = lane; idx < D * N * R; idx += 64) {
-            const int r = idx / (N * R), iq = idx % (N * R);
-            double s = 0.0;
+        for (int t = 0; t < PerLane<D * N * R>::n; ++t) {
+            const int idx = lane + 64 * t;
+            if (idx < D * N * R) {
+                const int x = idx / (N * R), iq = idx - x * N * R;
+                double s = f ? sc.ff[idx] : 0.0;
 #pragma unroll
-            for (int x = 0; x < D; ++x) s += G[r][x] * sv[x * N * R + iq];
-            sc.gv[idx] = s;
-        }
-        for (int idx = lane; idx < NFACE * N * R; idx += 64) {
-            const int fc = idx / (N * R), iq = idx % (N * R);
-            double s = 0.0;
+                for (int r = 0; r < D; ++r) s += J * g[1 + r * D + x] * sc.yp[r * N * R + iq];
 #pragma unroll
-            for (int x = 0; x < D; ++x) s += nf[fc][x] * sv[x * N * R + iq];
-            sc.vn[idx] = s;
-        }
-        wsync();
-        // ---- stage 4: s~_p
-        for (int idx = lane; idx < N * R; idx += 64) {
-            const int i = idx / R, q = idx % R;
-            double acc = 0.0;
-#pragma unroll
-            for (int r = 0; r < D; ++r) {
-                const double* Srow = &Srs[(r * N + i) * N];
-#pragma unroll
-                for (int j = 0; j < N; ++j) acc += Srow[j] * sc.gv[(r * N + j) * R + q];
+                for (int fc = 0; fc < NFACE; ++fc)
+                    s -= g[1 + D * D + NFACE + fc * D + x] * g[1 + D * D + fc] * sc.ef[fc * N * R + iq];
+                const double v = f ? s * inv_av : sc.ff[idx] + s * inv_av;
+                sc.vv[idx] = v;
+                const double d = v - sc.uo[idx];
+                dn += d * d;
+                un += v * v;
+                ue[idx] = v;
             }
-            sc.st[idx] = sp[idx] - acc / arho;
         }
-        wsync();
-        // ---- stage 5: re64 = -(1/(a rho |J|)) B_v^T s_v + Z_p^T s~_p - t_e
-        const T* Zse = Zs + (size_t)e * N * TT;
-        for (int idx = lane; idx < TT * R; idx += 64) {
-            const int aa = idx / R, q = idx % R;
-            const int fc = aa / NF, l = aa % NF;
-            double rv = 0.0, zt = 0.0;
+        if (RESID) {
+            wsync();
+            // ---- G v (over Sr^T p, no longer needed) ; n_f . v
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                rv += sc.El[(fc * N + i) * NF + l] * sc.vn[(fc * N + i) * R + q];
-                zt += (double)Zse[i * TT + aa] * sc.st[i * R + q];
-            }
-            re64[(size_t)e * TT * R + idx] = -inv_av * sf[fc] * rv + zt - sc.te[idx];
-        }
-        // ---- stage 6: z' = [s_v/(a rho |J|); S^{-1} s~_p]
-        T* ze = zout + (size_t)e * NLOC * R;
-        for (int idx = lane; idx < D * N * R; idx += 64) ze[idx] = (T)(sv[idx] * inv_av);
-        for (int q = lane; q < R; q += 64) {
-            T x[N];
+            for (int t = 0; t < PerLane<D * N * R>::n; ++t) {
+                const int idx = lane + 64 * t;
+                if (idx < D * N * R) {
+                    const int r = idx / (N * R), iq = idx - r * N * R;
+                    double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                T s = (T)sc.st[i * R + q];
-#pragma unroll
-                for (int m = 0; m < i; ++m) s -= sc.L[m * N + i] * x[m];
-                x[i] = s / sc.L[i * N + i];
+                    for (int x = 0; x < D; ++x) s += g[1 + r * D + x] * sc.vv[x * N * R + iq];
+                    sc.yp[idx] = s;
+                }
             }
 #pragma unroll
-            for (int i = N - 1; i >= 0; --i) {
-                T s = x[i];
+            for (int t = 0; t < PerLane<NFACE * N * R>::n; ++t) {
+                const int idx = lane + 64 * t;
+                if (idx < NFACE * N * R) {
+                    const int fc = idx / (N * R), iq = idx - fc * N * R;
+                    double s = 0.0;
 #pragma unroll
-                for (int m = i + 1; m < N; ++m) s -= sc.L[i * N + m] * x[m];
-                x[i] = s / sc.L[i * N + i];
+                    for (int x = 0; x < D; ++x) s += g[1 + D * D + NFACE + fc * D + x] * sc.vv[x * N * R + iq];
+                    sc.nv[idx] = s;
+                }
+            }
+            wsync();
+            // ---- s_p ; t_e
+#pragma unroll
+            for (int t = 0; t < PerLane<N * R>::n; ++t) {
+                const int idx = lane + 64 * t;
+                if (idx < N * R) {
+                    const int i = idx / R, q = idx % R;
+                    double qv = 0.0;
+#pragma unroll
+                    for (int r = 0; r < D; ++r) {
+                        const double* Srow = &Srs[(r * N + i) * N];
+#pragma unroll
+                        for (int j = 0; j < N; ++j) qv += Srow[j] * sc.yp[(r * N + j) * R + q];
+                    }
+                    double fe = 0.0;
+#pragma unroll
+                    for (int fc = 0; fc < NFACE; ++fc) {
+                        const double* Er = Eface(fc) + i * NF;
+                        double s = 0.0;
+#pragma unroll
+                        for (int l = 0; l < NF; ++l) s += Er[l] * sc.ep[(fc * NF + l) * R + q];
+                        fe += g[1 + D * D + fc] * s;
+                    }
+                    sc.sp[idx] = sc.ff[D * N * R + idx] - J * qv - alpha_p * sc.pp[idx] + tau * fe;
+                }
             }
 #pragma unroll
-            for (int i = 0; i < N; ++i) ze[(D * N + i) * R + q] = x[i];
+            for (int t = 0; t < PerLane<TT * R>::n; ++t) {
+                const int idx = lane + 64 * t;
+                if (idx < TT * R) {
+                    const int aa = idx / R, q = idx % R, fc = aa / NF, l = aa % NF;
+                    const double* Ec = Eface(fc) + l;
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) s += Ec[i * NF] * sc.nv[(fc * N + i) * R + q];
+                    sc.te[idx] = g[1 + D * D + fc] * (s - tau * sc.ep[idx]);
+                }
+            }
+            wsync();
+            // ---- re64 = Z_p^T s_p - t_e
+#pragma unroll
+            for (int t = 0; t < PerLane<TT * R>::n; ++t) {
+                const int idx = lane + 64 * t;
+                if (idx < TT * R) {
+                    const int aa = idx / R, q = idx % R;
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) s += (double)sc.Zl[i * TT + aa] * sc.sp[i * R + q];
+                    re64[(size_t)e * TT * R + idx] = s - sc.te[idx];
+                }
+            }
+            // ---- z'_p = L^{-T} (L^{-1} s_p) with the stored inverse factor (two triangular
+            // matrix-vector products; p is no longer needed, its buffer takes L^{-1} s_p)
+#pragma unroll
+            for (int t = 0; t < PerLane<N * R>::n; ++t) {
+                const int idx = lane + 64 * t;
+                if (idx < N * R) {
+                    const int i = idx / R, q = idx % R;
+                    double s = 0.0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) s += (double)sc.Ll[i * N + m] * sc.sp[m * R + q];
+                    sc.pp[idx] = s;
+                }
+            }
+            wsync();
+            T* zbe = zb + (size_t)e * NLOC * R + D * N * R;
+#pragma unroll
+            for (int t = 0; t < PerLane<N * R>::n; ++t) {
+                const int idx = lane + 64 * t;
+                if (idx < N * R) {
+                    const int i = idx / R, q = idx % R;
+                    double s = 0.0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) s += (double)sc.Ll[m * N + i] * sc.pp[m * R + q];
+                    zbe[idx] = (T)s;
+                }
+            }
         }
-        // ---- squared residual norm of this element's local equations
-        double acc = 0.0;
-        for (int idx = lane; idx < NLOC * R; idx += 64) acc += sc.su[idx] * sc.su[idx];
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-        if (lane == 0) sq[e] = acc;
+        // ---- per-element norms of the correction and of u
+        if (nrm) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                dn += __shfl_xor(dn, off, 64);
+                un += __shfl_xor(un, off, 64);
+            }
+            if (lane == 0) {
+                nrm[e] = sqrt(dn);
+                nrm[ne + e] = sqrt(un);
+            }
+        }
         wsync();
     }
 }
 
+// wavefronts per workgroup: as many as fit in 80 KB of LDS (two workgroups per CU), at most 4
 template <int D, int K, typename T>
 constexpr int ac_wpb() {
     constexpr int sb = (int)sizeof(AcScratch<D, K, 1, T>);
@@ -741,14 +920,32 @@ int launch_ac_rec(hdg_ctx* c, const T* Sr, const T* Ef, const double* lam, doubl
     return (int)hipGetLastError();
 }
 
-template <int D, int K, int R, typename T>
-int launch_ac_ref(hdg_ctx* c, const double* u, const double* lam, double* sq) {
-    constexpr int WPB = 2;
+// wavefronts per workgroup of the refinement kernel: as many as fit next to the shared tables
+// in the 160 KB of LDS of a CU (one workgroup per CU), at most 8
+template <int D, int K, typename T, bool RESID>
+constexpr int rf_wpb() {
+    constexpr int N = dimp(K, D), NF = dimp(K, D - 1);
+    constexpr int sb = (int)sizeof(RfScratch<D, K, 1, T, RESID>);
+    constexpr int tb = (D * N * N + (rf_shared_faces<D, K>() ? (D + 1) * ((D == 3) ? 6 : 2) * N * NF : 0)) * 8;
+    constexpr int w = (160 * 1024 - tb) / sb;
+    return w >= 8 ? 8 : (w < 1 ? 1 : w);
+}
+
+template <int D, int K, int R, typename T, bool RESID>
+int launch_ac_ref(hdg_ctx* c, const double* lam, const double* dlam, int mode, double* u, double* nrm) {
+    constexpr int WPB = rf_wpb<D, K, T, RESID>();
+    // the residual needs the FP64 right-hand side, the inverse factor and the residual buffer,
+    // which exist in mixed precision only; the plain recovery reads none of them
+    if (RESID && (!c->d_f_saved || !c->d_LU || !c->d_re64)) return -1;
+    if (mode != 1 && !c->d_f_saved) return -1;
     int64_t groups = (c->n_elem + WPB - 1) / WPB;
-    int grid = (int)std::min<int64_t>(groups, 256 * 32);
-    hipLaunchKernelGGL((refine_acoustic_kernel<D, K, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream,
-                       c->n_elem, c->last_a, c->d_geom, c->d_eperm, c->d_eface, c->tab.Sr, c->tab.Mf, c->tab.Ef,
-                       (const T*)c->d_Zt, (const T*)c->d_LU, u, lam, c->d_f_saved, (T*)c->d_z, c->d_re64, sq);
+    static const int resident =
+        resident_groups((const void*)refine_acoustic_kernel<D, K, R, T, WPB, RESID>, 64 * WPB);
+    int grid = (int)std::min<int64_t>(groups, resident);
+    hipLaunchKernelGGL((refine_acoustic_kernel<D, K, R, T, WPB, RESID>), dim3(grid), dim3(64 * WPB), 0,
+                       c->stream, c->n_elem, c->last_a, c->d_geom, c->d_eperm, c->d_eface, c->tab.Sr, c->tab.Ef,
+                       (const T*)c->d_Zt, (const T*)(RESID ? c->d_LU : nullptr), c->d_f_saved, lam, dlam, mode,
+                       (T*)c->d_z, u, RESID ? c->d_re64 : nullptr, nrm);
     return (int)hipGetLastError();
 }
 
@@ -775,10 +972,15 @@ int dispatch_ac_rec(hdg_ctx* c, const T* Sr, const T* Ef, const double* lam, dou
     return -1;
 }
 
-int dispatch_ac_ref(hdg_ctx* c, const double* u, const double* lam, double* sq) {
+int dispatch_ac_ref(hdg_ctx* c, const double* lam, const double* dlam, int mode, bool resid, double* u,
+                    double* nrm) {
     const int D = c->dim, K = c->k, R = c->nrhs;
-#define HDG_CASE(DD, KK, RR) \
-    if (D == DD && K == KK && R == RR) return launch_ac_ref<DD, KK, RR, float>(c, u, lam, sq);
+#define HDG_CASE(DD, KK, RR)                                                                     \
+    if (D == DD && K == KK && R == RR) {                                                         \
+        if (c->precision == HDG_FP64) return launch_ac_ref<DD, KK, RR, double, false>(c, lam, dlam, mode, u, nrm); \
+        return resid ? launch_ac_ref<DD, KK, RR, float, true>(c, lam, dlam, mode, u, nrm)        \
+                     : launch_ac_ref<DD, KK, RR, float, false>(c, lam, dlam, mode, u, nrm);      \
+    }
     HDG_AC_CASES(HDG_CASE)
 #undef HDG_CASE
     return -1;
@@ -786,9 +988,11 @@ int dispatch_ac_ref(hdg_ctx* c, const double* u, const double* lam, double* sq) 
 
 }  // namespace
 
-int launch_refine_residual(hdg_ctx* c, const double* u, const double* lam, double* sq) {
-    if (c->physics != HDG_ACOUSTIC || c->precision != HDG_MIXED_FP32) return -1;
-    return dispatch_ac_ref(c, u, lam, sq);
+int launch_refine_acoustic(hdg_ctx* c, const double* lam, const double* dlam, int mode, bool resid,
+                           double* u, double* nrm) {
+    if (c->physics != HDG_ACOUSTIC) return -1;
+    if (c->precision == HDG_FP64 && resid) return -1;
+    return dispatch_ac_ref(c, lam, dlam, mode, resid, u, nrm);
 }
 
 int launch_condense_acoustic(hdg_ctx* c, double a, const double* f_loc) {

@@ -42,7 +42,7 @@ struct hdg_ctx {
     int dim = 0, physics = 0, precision = 0, nrhs = 1, k = 0;
     bool uniform = true;
     double stab_scale = 1.0;
-    double krylov_tol = 1e-13, refine_tol = 1e-13;
+    double krylov_tol = 1e-13, refine_tol = 1e-13, refine_inner_tol = 1e-6;
     int krylov_maxit = 2000, refine_maxit = 8;
     hipStream_t stream = nullptr;
     std::string err;
@@ -113,7 +113,7 @@ struct hdg_ctx {
     double* d_du = nullptr;          // [n_local_dofs][r] correction
     double* d_dlam = nullptr;        // [n_trace_dofs][r] correction
     double* d_re64 = nullptr;        // [ne][t][r] FP64 correction trace right-hand side
-    double* d_sq = nullptr;          // [ne] squared local residual norms
+    double* d_sq = nullptr;          // [2 ne] per-element norms of the refinement correction and of u
     double* d_stage = nullptr;       // [3][n_local_dofs][r] DIRK stages
     double* d_ustar = nullptr;
     double* d_fstage = nullptr;
@@ -134,11 +134,20 @@ int launch_assemble(hdg_ctx* c, const double* lam_bnd);
 int launch_recover(hdg_ctx* c, const double* lambda, double* u, bool rhs_only_z);
 int launch_residual(hdg_ctx* c, double a, const double* u, const double* lam, const double* f,
                     const double* lam_bnd, double* su, double* slam);
-int launch_refine_residual(hdg_ctx* c, const double* u, const double* lam, double* sq);
+// Acoustic recovery of (v, p) from the stored factors (FP64: the plain recovery; mixed
+// precision: then, with `resid`, the FP64 residual, the correction right-hand side and the
+// element part of the trace residual).  mode 1 starts from p = 0 with dlam = lam (the first
+// recovery), mode 0 applies the correction dlam, mode 2 none.  nrm: [2 ne] per-element |du|, |u|.
+int launch_refine_acoustic(hdg_ctx* c, const double* lam, const double* dlam, int mode, bool resid,
+                           double* u, double* nrm);
 int launch_assemble_rhs64(hdg_ctx* c, const double* re64);
 int launch_apply_mass(hdg_ctx* c, double a, const double* u, double* f);
 int launch_block_inverse(hdg_ctx* c);
-int trace_cg(hdg_ctx* c, double* lambda, int* iters, double* relres);
+int trace_cg(hdg_ctx* c, double* lambda, double tol, int* iters, double* relres);
+
+// Workgroups that stay resident on the whole device at once for `kernel` with `block` threads
+// (at least 1): a grid of this size visits every element with one wave per element slot.
+int resident_groups(const void* kernel, int block);
 int launch_axpy(hdg_ctx* c, int64_t n, double alpha, const double* x, double* y);
 int launch_lincomb(hdg_ctx* c, int64_t n, double a, const double* x, double b, const double* y,
                    double* out);

@@ -274,6 +274,15 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
 }  // namespace
 
+int resident_groups(const void* kernel, int block) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return ncu * per_cu;
+}
+
 int launch_assemble(hdg_ctx* c, const double* lam_bnd) {
     int grid = (int)std::min<int64_t>(c->n_faces, 65536);
     if (c->precision == HDG_FP64)
@@ -346,7 +355,7 @@ int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out) {
 
 // Preconditioned CG on the assembled (sign-adjusted) system; all rhs columns iterate
 // together with their own scalars.  Convergence is checked on the host every iteration.
-int trace_cg(hdg_ctx* c, double* x, int* iters, double* relres) {
+int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
     const int R = c->nrhs;
     const int64_t n = c->n_faces * c->bs;
     double* rr = c->d_cg_r;
@@ -389,7 +398,7 @@ int trace_cg(hdg_ctx* c, double* x, int* iters, double* relres) {
             worst = std::numeric_limits<double>::quiet_NaN();
             break;
         }
-        if (worst <= c->krylov_tol || it == c->krylov_maxit) break;
+        if (worst <= tol || it == c->krylov_maxit) break;
         spmv(c, pp, qq);
         dot(c, pp, qq, s_pq);
         hipLaunchKernelGGL(axpy_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, 1.0,
@@ -405,7 +414,7 @@ int trace_cg(hdg_ctx* c, double* x, int* iters, double* relres) {
     if (iters) *iters = it;
     if (relres) *relres = worst;
     c->last_iters = it;
-    if (!(worst <= c->krylov_tol)) return HDG_E_NOCONV;
+    if (!(worst <= tol)) return HDG_E_NOCONV;
     return HDG_OK;
 }
 

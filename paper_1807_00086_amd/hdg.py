@@ -51,7 +51,8 @@ class PhysDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("k", C.c_int), ("nrhs", C.c_int),
                 ("krylov_tol", C.c_double), ("krylov_maxit", C.c_int),
-                ("refine_tol", C.c_double), ("refine_maxit", C.c_int)]
+                ("refine_tol", C.c_double), ("refine_maxit", C.c_int),
+                ("refine_inner_tol", C.c_double)]
 
 
 _lib = None
@@ -119,7 +120,7 @@ class Solver:
 
     def __init__(self, xyz, elem_vert, physics, elem_par, k=None, degree=None, precision="fp64",
                  nrhs=1, stab_scale=1.0, krylov_tol=1e-13, krylov_maxit=5000, refine_tol=1e-13,
-                 refine_maxit=10, stream=None):
+                 refine_maxit=10, refine_inner_tol=1e-6, stream=None):
         self.lib = load_library()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._ev = np.ascontiguousarray(elem_vert, dtype=np.int64)
@@ -137,7 +138,7 @@ class Solver:
         prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
         od = Options(prec, int(k if k is not None else (int(degree[0]) if degree is not None else 1)),
                      self.nrhs, float(krylov_tol), int(krylov_maxit), float(refine_tol),
-                     int(refine_maxit))
+                     int(refine_maxit), float(refine_inner_tol))
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
