@@ -88,9 +88,11 @@ typedef struct {
     int nrhs;                   /* right-hand sides solved together (1..32)                   */
     double krylov_tol;          /* relative residual of the FP64 trace solve                  */
     int krylov_maxit;
-    double refine_tol;          /* mixed precision: stop when the FP64 correction (or the error
-                                   left after it, estimated from the observed contraction) is
-                                   below refine_tol relative to the solution (0: 1e-13)       */
+    double refine_tol;          /* mixed precision: stop when the FP64 correction, or the error
+                                   left after it estimated from the observed contraction of
+                                   successive corrections (the low-precision solve counts as
+                                   a first correction of relative size 1), is below
+                                   refine_tol relative to the solution (0: 1e-13)             */
     int refine_maxit;
     double refine_inner_tol;    /* mixed precision: relative residual of the trace solves of
                                    the corrections (0: 1e-6)                                  */

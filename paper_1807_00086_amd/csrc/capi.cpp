@@ -328,11 +328,13 @@ hdg_status hdg_trace_solve(hdg_ctx* c, double* lambda, int* iters, double* relre
 }
 
 // Stopping test of the refinement: the correction is below refine_tol relative to the
-// solution, or (from the second correction on) the error left after it, estimated by the
-// observed contraction rel_k / rel_{k-1} times rel_k, is.  Returns -1 to continue.
-static bool refine_converged(const hdg_ctx* c, int it, double rel, double prev) {
+// solution, or the error left after it, estimated by the observed contraction
+// rel_k / rel_{k-1} times rel_k, is.  The low-precision solve itself counts as correction 0
+// of relative size 1 (it is one application of the same approximate inverse to the whole
+// right-hand side), so after the first correction the estimate is rel_1^2.
+static bool refine_converged(const hdg_ctx* c, int, double rel, double prev) {
     if (rel <= c->refine_tol) return true;
-    return it > 1 && prev > 0.0 && rel * (rel / prev) <= c->refine_tol;
+    return prev > 0.0 && rel * (rel / prev) <= c->refine_tol;
 }
 
 static int refine_verdict(hdg_ctx* c, int it, double rel, double prev) {
@@ -356,7 +358,7 @@ static hdg_status recover_refine_acoustic(hdg_ctx* c, double* lambda, double* u)
     }
     if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
     c->z_consumed = true;
-    double prev = 0.0, prev_l = 0.0;
+    double prev = 1.0, prev_l = 1.0;
     for (int it = 1; it <= c->refine_maxit; ++it) {
         float t_sol = 0.f, t_el = 0.f;
         int r;
@@ -428,7 +430,7 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
     // FP32 factors and an FP64 trace solve, until the correction is below refine_tol.
     c->z_consumed = true;
     const int64_t nl = c->n_local_dofs * c->nrhs, nt = c->n_trace_dofs * c->nrhs;
-    double prev = 0.0;
+    double prev = 1.0;
     for (int it = 1; it <= c->refine_maxit; ++it) {
         float t_res = 0.f, t_sol = 0.f, t_rec = 0.f;
         {
@@ -687,6 +689,10 @@ hdg_status hdg_element_data(hdg_ctx* c, int which, int64_t e0, int64_t count, do
             // which == 3: only the Schur-block rows of z are A^{-1} f (the eliminated rows hold
             // the closed-form part applied at recovery)
             int64_t src_i = (which == 3) ? c->s_row0 * R + i : i;
+            if (which == 0 && c->ke_tile > 0) {   // K_e stored by its upper tiles
+                const int64_t r = i / t, cc = i % t;
+                if (r / c->ke_tile > cc / c->ke_tile) src_i = cc * t + r;
+            }
             int64_t k = e * blk + src_i;
             out[e * oblk + i] = (tsz == 8) ? ((double*)buf.data())[k] : (double)((float*)buf.data())[k];
         }

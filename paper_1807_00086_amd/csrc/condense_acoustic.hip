@@ -34,6 +34,17 @@ __device__ __forceinline__ void wsync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Reciprocal of a pivot: hardware estimate refined by Newton steps (FP64: two steps from the
+// half-precision estimate; FP32: the estimate is within one ulp already).
+__device__ __forceinline__ double pivot_rcp(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    double e = fma(-p, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-p, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float pivot_rcp(float p) { return __builtin_amdgcn_rcpf(p); }
+
 template <typename T>
 __device__ __forceinline__ T eps_of() {
     return sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7);
@@ -104,7 +115,7 @@ __device__ __forceinline__ float bcast(float v, int src) {
 }
 
 template <int D, int K, int R, typename T, int WPB>
-__global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
+__global__ __launch_bounds__(64 * WPB, sizeof(T) == 4 ? 3 : 2) void condense_acoustic_kernel(
     int64_t ne, double a_in, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
     const T* __restrict__ Sr, const T* __restrict__ Mf, const T* __restrict__ Tsym,
     const T* __restrict__ Ef, const double* __restrict__ f_loc, T* __restrict__ Ke,
@@ -303,11 +314,11 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
 #pragma unroll
             for (int j = 0; j < N; ++j) {
                 const T p = bcast(x[0][j], j);
+                const T ip = pivot_rcp(p);
                 if (lane == 0) {
                     if (!(p > ptol && p - p == T(0))) atomicOr(status, 1);
-                    sc.dv[j] = T(1) / p;
+                    sc.dv[j] = ip;
                 }
-                const T ip = T(1) / p;
                 const T sq = sqrt(ip);
                 T t[P];
 #pragma unroll
@@ -365,7 +376,8 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
 
         // ------------------------------------------------------------ K_e
         // K = D - (1/(a rho |J|)) [s_f s_g (n_f.n_g) E_f^T E_g] + W^T W: two MFMA chains per
-        // 16x16 output tile (inner dimension N)
+        // 16x16 output tile (inner dimension N).  K_e is symmetric: only the tiles on and above
+        // the diagonal are formed and stored.
         {
             constexpr int TA = (TT + 15) / 16, TK = (N + 3) / 4;
             T* Kee = Ke + (size_t)e * TT * TT;
@@ -375,7 +387,7 @@ __global__ __launch_bounds__(64 * WPB, 2) void condense_acoustic_kernel(
                 const bool aok = am < TT;
                 const int fam = aok ? am / NF : 0, lam_ = aok ? am % NF : 0;
 #pragma unroll 1
-                for (int tb = 0; tb < TA; ++tb) {
+                for (int tb = ta; tb < TA; ++tb) {
                     const int bn = tb * 16 + lc;                   // this lane's B column
                     const bool bok = bn < TT;
                     const int fbn = bok ? bn / NF : 0, lbn = bok ? bn % NF : 0;
@@ -996,6 +1008,7 @@ int launch_refine_acoustic(hdg_ctx* c, const double* lam, const double* dlam, in
 }
 
 int launch_condense_acoustic(hdg_ctx* c, double a, const double* f_loc) {
+    c->ke_tile = 16;
     if (c->precision == HDG_FP64)
         return dispatch_ac<double>(c, a, f_loc, c->tab.Sr, c->tab.Mf, c->tab.Tsym, c->tab.Ef);
     return dispatch_ac<float>(c, a, f_loc, c->tab.Sr32, c->tab.Mf32, c->tab.Tsym32, c->tab.Ef32);

@@ -93,6 +93,8 @@ struct hdg_ctx {
     void* d_z = nullptr;       // [ne][n][r]
     void* d_LU = nullptr;      // [ne][Ns][Ns] factored Schur block (mixed precision)
     int Ns = 0;                // size of the densely factored (Schur) block
+    int ke_tile = 0;           // > 0: K_e holds only the entries whose row tile (of this many
+                               // rows) is <= their column tile; the rest is read mirrored
     int s_row0 = 0;            // first local row of that block
     int* d_status = nullptr;   // device status word (0 ok, 1 singular pivot)
 

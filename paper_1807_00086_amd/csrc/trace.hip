@@ -19,9 +19,16 @@ namespace hdg {
 namespace {
 constexpr int NT = 256;
 
+// K_e[r][c] of an element matrix stored in full (ktile = 0) or as its tiles on and above the
+// diagonal (symmetric K_e, tiles of ktile x ktile)
+template <typename T>
+__device__ __forceinline__ double kget(const T* K, int tt, int r, int c, int ktile) {
+    return (ktile > 0 && r / ktile > c / ktile) ? (double)K[c * tt + r] : (double)K[r * tt + c];
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void assemble_kernel(
-    int64_t nf, int d, int bs, int tt, int R, double sign, const int32_t* __restrict__ face_elem,
+    int64_t nf, int d, int bs, int tt, int R, double sign, int ktile, const int32_t* __restrict__ face_elem,
     const int32_t* __restrict__ face_lf, const uint8_t* __restrict__ face_bnd,
     const int32_t* __restrict__ eface, const T* __restrict__ Ke, const T* __restrict__ re,
     const double* __restrict__ lam_bnd, double* __restrict__ bsr, double* __restrict__ rhs) {
@@ -41,7 +48,7 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
                 } else {
                     for (int s = 0; s < 2; ++s) {
                         const T* K = Ke + (size_t)es[s] * tt * tt;
-                        v += (double)K[(ls[s] * bs + a) * tt + ls[s] * bs + b];
+                        v += kget(K, tt, ls[s] * bs + a, ls[s] * bs + b, ktile);
                     }
                     v *= sign;
                 }
@@ -52,7 +59,7 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
                     int lf = ls[s];
                     int q = (m < lf) ? m : m + 1;
                     int32_t F2 = eface[(size_t)e * nv + q];
-                    if (!face_bnd[F2]) v = sign * (double)Ke[(size_t)e * tt * tt + (lf * bs + a) * tt + q * bs + b];
+                    if (!face_bnd[F2]) v = sign * kget(Ke + (size_t)e * tt * tt, tt, lf * bs + a, q * bs + b, ktile);
                 }
             }
             B[idx] = v;
@@ -74,7 +81,7 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
                         int32_t F2 = eface[(size_t)e * nv + q];
                         if (!face_bnd[F2]) continue;
                         for (int b = 0; b < bs; ++b)
-                            acc -= (double)K[(lf * bs + a) * tt + q * bs + b] *
+                            acc -= kget(K, tt, lf * bs + a, q * bs + b, ktile) *
                                    lam_bnd[((size_t)F2 * bs + b) * R + r];
                     }
                     v += acc;
@@ -287,12 +294,12 @@ int launch_assemble(hdg_ctx* c, const double* lam_bnd) {
     int grid = (int)std::min<int64_t>(c->n_faces, 65536);
     if (c->precision == HDG_FP64)
         hipLaunchKernelGGL((assemble_kernel<double>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
-                           c->bs, c->n_tr, c->nrhs, c->K_sign, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
+                           c->bs, c->n_tr, c->nrhs, c->K_sign, c->ke_tile, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
                            c->d_eface, (const double*)c->d_Ke, (const double*)c->d_re, lam_bnd, c->d_bsr,
                            c->d_rhs);
     else
         hipLaunchKernelGGL((assemble_kernel<float>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
-                           c->bs, c->n_tr, c->nrhs, c->K_sign, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
+                           c->bs, c->n_tr, c->nrhs, c->K_sign, c->ke_tile, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
                            c->d_eface, (const float*)c->d_Ke, (const float*)c->d_re, lam_bnd, c->d_bsr,
                            c->d_rhs);
     return (int)hipGetLastError();
