@@ -36,29 +36,53 @@ def dimp(k, d):
 
 
 def acoustic_counts(D, K, R, elt_bytes, mixed=False):
-    """Algorithmic HBM bytes and executed flops per element of the acoustic condensation
-    kernel (condense_acoustic.hip: closed-form velocity elimination, Cholesky of the pressure
-    Schur block, K = D - B_v^T B_v/(a rho |J|) + W^T W) and of the recovery kernel.  Reads of
-    the degree-dependent reference tables hit the caches and are not counted as HBM traffic."""
+    """Algorithmic HBM bytes and executed flops per element of the acoustic kernels
+    (condense_acoustic.hip).  Condensation: closed-form velocity elimination, B~ and W_f by
+    MFMA tiles, the pressure Schur block S from reference tables, elimination of [S | B~ | f~]
+    (plus the identity in mixed precision, for L^{-1}) without pivoting, K_e = D - B_v^T B_v /
+    (a rho |J|) + W^T W formed and stored by its tiles on and above the diagonal.  Recovery:
+    p = z_p - Z_p lam, v in closed form.  Reads of the degree-dependent reference tables hit
+    the caches and are not counted as HBM traffic; padding of MFMA tiles is not counted."""
     N, NF, NFACE = dimp(K, D), dimp(K, D - 1), D + 1
     TT, NLOC = NFACE * NF, (D + 1) * N
     C = TT + R
+    NI = N if mixed else 0
     npair = D * (D + 1) // 2
-    fma = (N * R * D * N * (D + 1)          # condensed pressure rhs
-           + NFACE * N * N * D              # W_f = tau I + sum_r beta_fr Sr_r
-           + NFACE * N * NF * N             # B~_f = -s_f W_f E_f
-           + N * N * (NFACE + npair)        # S from reference tables
-           + N ** 3 / 6.0                   # Cholesky
-           + C * N * N / 2.0                # L^{-1} [B~ | f~]
-           + 2 * TT * TT * N                # W^T W and E^T E
-           + TT * R * N * (D + 2)           # r_e
-           + C * N * N / 2.0)               # L^{-T} [W | w]
+    k_stored = sum(1 for r in range(TT) for c in range(TT) if r // 16 <= c // 16)
+    fma = (D * D * N * R + D * N * N * R     # condensed pressure rhs
+           + NFACE * N * N * D               # W_f = tau I + sum_r beta_fr Sr_r (MFMA operand)
+           + NFACE * N * NF * N              # B~_f = -s_f W_f E_f
+           + N * N * (NFACE + npair)         # S from reference tables
+           + N ** 3 / 3.0 + N * N * (C + NI) / 2.0   # forward elimination
+           + N * N * C / 2.0                 # back substitution
+           + 2 * k_stored * N                # W^T W and E^T E on the stored tiles
+           + TT * R * 2 * N + NFACE * N * R * D)     # r_e
     reads = NLOC * R * 8 + 32 * 8 + NFACE * 4
-    writes = (TT * TT + TT * R + N * TT + NLOC * R + (N * N if mixed else 0)) * elt_bytes
+    writes = (k_stored + TT * R + N * TT + NLOC * R + (N * N if mixed else 0)) * elt_bytes
     rec_bytes = (N * TT + NLOC * R) * elt_bytes + TT * R * 8 + 32 * 8 + 2 * NFACE * 4 + NLOC * R * 8
-    rec_fma = N * TT * R + D * N * R * (NFACE * NF + D * N)
+    rec_fma = N * TT * R + NFACE * N * NF * R + D * N * N * R + D * N * R * (D + NFACE)
     return dict(cond_bytes=reads + writes, cond_flops=2.0 * fma, rec_bytes=rec_bytes,
                 rec_flops=2.0 * rec_fma)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the plain-copy calibration), or None when the
+    summary is missing or was taken on a different version of the kernel source."""
+    import hashlib
+    import re as _re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_acoustic_k3.md")
+    src = os.path.join(ROOT, "paper_1807_00086_amd", "csrc", "condense_acoustic.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    for m in _re.finditer(r"^traffic: (\{.*\})$", text, _re.M):
+        rec = json.loads(m.group(1))
+        if rec.get("kernel") == kernel and rec.get("source_sha256_16") == digest:
+            return rec["bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(problem, a, budget_s=15.0):
@@ -213,6 +237,7 @@ def main():
     value = elem_rate(r)
     eb = 8 if head == "fp64" else 4
     cnt = acoustic_counts(3, k, 1, eb, mixed=head != "fp64")
+    kname = f"condense_acoustic_kernel<3,{k},1,{'double' if head == 'fp64' else 'float'}>"
     cond_s = r["condense"] * 1e-3
     achieved_gbs = cnt["cond_bytes"] * p.n_elem / cond_s / 1e9
     achieved_tf = cnt["cond_flops"] * p.n_elem / cond_s / 1e12
@@ -239,8 +264,8 @@ def main():
             "elements_per_s": elem_rate(rr)} for pr, rr in res.items()},
         "mixed_vs_fp64_rel_l2": equal_error,
         "roofline": {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"condense_acoustic_kernel<3,3,1,{'double' if head == 'fp64' else 'float'}>",
+                     "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
+                     "kernel": kname,
                      "bytes_per_element": cnt["cond_bytes"], "flops_per_element": cnt["cond_flops"],
                      "flop_frac_fp64_peak": achieved_tf / FP64_PEAK_TFLOPS},
         "recover_roofline": {"bound": "hbm", "achieved": rec_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
