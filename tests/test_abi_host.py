@@ -74,6 +74,19 @@ def test_reference_face_tables(d, k, kF):
                 np.testing.assert_allclose(Mf[f], np.einsum("q,qi,qj->ij", w, phi, phi), atol=1e-11)
 
 
+@pytest.mark.parametrize("d,k,kF", [(2, 1, 1), (2, 3, 3), (2, 2, 4), (3, 1, 1), (3, 3, 3), (3, 2, 4), (3, 4, 4)])
+def test_face_mass_is_gram_of_face_moments(d, k, kF):
+    # The trace of P_k on a face lies in P_kF (kF >= k) and the face basis is orthonormal, so the
+    # face mass of the volume basis equals E_f E_f^T for every orientation; the acoustic
+    # recovery/refinement kernel applies Mf_f p as E_f (E_f^T p).
+    N, NF = P.dim_p(k, d), P.dim_p(kF, d - 1)
+    E = hdgmod.reference_table(d, k, kF, 3).reshape(d + 1, len(PERMS[d]), N, NF)
+    Mf = hdgmod.reference_table(d, k, k, 1).reshape(d + 1, N, N)
+    for f in range(d + 1):
+        for p in range(len(PERMS[d])):
+            np.testing.assert_allclose(E[f, p] @ E[f, p].T, Mf[f], atol=1e-12 * max(1.0, np.abs(Mf[f]).max()) * 50)
+
+
 def _init(mesh_xyz, ev, physics="acoustic", k=2, nrhs=1, par=None, degree=None):
     lib = hdgmod.load_library()
     xyz = np.ascontiguousarray(mesh_xyz, dtype=np.float64)
