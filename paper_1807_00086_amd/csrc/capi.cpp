@@ -63,6 +63,17 @@ int upload_f32(hdg_ctx* c, float** p, const std::vector<double>& h) {
     return upload(c, p, f);
 }
 
+// FP64 and FP32 copies of the reference tables of one degree
+int upload_tables(hdg_ctx* c, DeviceTables& t, const RefTables& ref, const RefFaceTables& ef) {
+    int s = HDG_OK;
+    if ((s = upload(c, &t.Sr, ref.Sr)) || (s = upload(c, &t.Mf, ref.Mf)) || (s = upload(c, &t.Tsym, ref.Tsym)) ||
+        (s = upload(c, &t.Ef, ef.E)) || (s = upload(c, &t.Tfull, ref.Tfull)) || (s = upload_f32(c, &t.Sr32, ref.Sr)) ||
+        (s = upload_f32(c, &t.Mf32, ref.Mf)) || (s = upload_f32(c, &t.Tsym32, ref.Tsym)) ||
+        (s = upload_f32(c, &t.Ef32, ef.E)) || (s = upload_f32(c, &t.Tfull32, ref.Tfull)))
+        return s;
+    return HDG_OK;
+}
+
 void dfree(void* p) {
     if (p) (void)hipFree(p);
 }
@@ -86,13 +97,19 @@ int check_status(hdg_ctx* c) {
 }
 
 bool supported(hdg_ctx* c) {
-    if (c->physics == HDG_ACOUSTIC) return c->nrhs == 1 && c->k >= 1 && c->k <= 4;
-    return general_supported(c->physics, c->k, c->nrhs);
+    if (c->vardeg) {
+        for (int k = 1; k <= 5; ++k)
+            if (c->cls_n[k] && !general_supported(HDG_ACOUSTIC, k, var_face_degree(), c->nrhs)) return false;
+        return true;
+    }
+    if (c->fast_ac) return c->k >= 1 && c->k <= 4;
+    return c->dim == 3 && general_supported(c->physics, c->k, c->k, c->nrhs);
 }
 
 int launch_recover_any(hdg_ctx* c, const double* lam, double* u) {
-    return c->physics == HDG_ACOUSTIC ? launch_recover(c, lam, u, false) : launch_recover_general(c, lam, u);
+    return c->fast_ac ? launch_recover(c, lam, u, false) : launch_recover_general(c, lam, u);
 }
+
 
 }  // namespace
 
@@ -147,21 +164,51 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
         delete c;
         return st;
     }
-    if (!uniform) {
-        g_init_err = "variable polynomial degree is not supported by this build";
-        delete c;
-        return HDG_E_UNSUPPORTED;
-    }
     const int d = c->dim;
+    if (!uniform) {
+        if (c->physics != HDG_ACOUSTIC || d != 3) {
+            g_init_err = "variable polynomial degree is built for 3D acoustics only";
+            delete c;
+            return HDG_E_UNSUPPORTED;
+        }
+        c->vardeg = true;
+        c->degree.assign(m->degree, m->degree + m->n_elem);
+        for (int64_t e = 0; e < c->n_elem; ++e) kk = std::max<int>(kk, c->degree[e]);
+        c->k = kk;
+    }
+    c->fast_ac = c->physics == HDG_ACOUSTIC && !c->vardeg && c->nrhs == 1;
     c->m_local = (c->physics == HDG_ACOUSTIC) ? d + 1 : (c->physics == HDG_ELASTIC ? 9 : 6);
     c->m_trace = (c->physics == HDG_ACOUSTIC) ? 1 : (c->physics == HDG_ELASTIC ? 3 : 2);
+    const int kface = c->vardeg ? var_face_degree() : kk;
     c->N = dim_p(kk, d);
-    c->NF = dim_p(kk, d - 1);
+    c->NF = dim_p(kface, d - 1);
     c->n_loc = c->m_local * c->N;
     c->bs = c->m_trace * c->NF;
     c->n_tr = (d + 1) * c->bs;
     c->n_local_dofs = c->n_elem * c->n_loc;
     c->n_trace_dofs = c->n_faces * c->bs;
+    std::vector<int8_t> efnf, face_nf;
+    std::vector<int32_t> cls[6];
+    if (c->vardeg) {
+        // face degree: the larger degree of the face's elements; compact local offsets
+        std::vector<int> fk(c->n_faces, 0);
+        for (int64_t F = 0; F < c->n_faces; ++F)
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const int32_t e = c->face_elem[2 * F + s2];
+                if (e >= 0) fk[F] = std::max<int>(fk[F], c->degree[e]);
+            }
+        face_nf.resize(c->n_faces);
+        for (int64_t F = 0; F < c->n_faces; ++F) face_nf[F] = (int8_t)dim_p(fk[F], d - 1);
+        efnf.resize(c->n_elem * (d + 1));
+        for (int64_t i = 0; i < c->n_elem * (d + 1); ++i) efnf[i] = face_nf[c->elem_face[i]];
+        c->loc_off_h.assign(c->n_elem + 1, 0);
+        for (int64_t e = 0; e < c->n_elem; ++e) {
+            c->loc_off_h[e + 1] = c->loc_off_h[e] + c->m_local * dim_p(c->degree[e], d);
+            cls[c->degree[e]].push_back((int32_t)e);
+        }
+        c->n_local_dofs = c->loc_off_h[c->n_elem];
+        for (int k = 1; k <= 5; ++k) c->cls_n[k] = (int64_t)cls[k].size();
+    }
     c->K_sign = (c->physics == HDG_ACOUSTIC) ? -1.0 : 1.0;
     // densely factored (Schur) block: acoustic p, elastic v, maxwell E
     c->Ns = (c->physics == HDG_ACOUSTIC) ? c->N : 3 * c->N;
@@ -175,7 +222,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     }
     // reference tables
     build_ref_tables(d, kk, c->ref);
-    build_face_tables(d, kk, kk, c->reff);
+    build_face_tables(d, kk, kface, c->reff);
 
     int s = 0;
 #define TRY(x)                       \
@@ -203,6 +250,22 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(upload_f32(c, &c->tab.Ef32, c->reff.E));
     TRY(upload(c, &c->tab.Tfull, c->ref.Tfull));
     TRY(upload_f32(c, &c->tab.Tfull32, c->ref.Tfull));
+    if (c->vardeg) {
+        std::vector<int8_t> edeg(c->degree.begin(), c->degree.end());
+        TRY(upload(c, &c->d_loc_off, c->loc_off_h));
+        TRY(upload(c, &c->d_efnf, efnf));
+        TRY(upload(c, &c->d_face_nf, face_nf));
+        TRY(upload(c, &c->d_edeg, edeg));
+        for (int k = 1; k <= 5; ++k) {
+            if (!c->cls_n[k]) continue;
+            TRY(upload(c, &c->d_cls[k], cls[k]));
+            RefTables rk;
+            RefFaceTables ek;
+            build_ref_tables(d, k, rk);
+            build_face_tables(d, k, kface, ek);
+            TRY(upload_tables(c, c->tabk[k], rk, ek));
+        }
+    }
     if (c->physics == HDG_MAXWELL) {
         std::vector<double> ef(c->n_elem * (d + 1) * 6);
         for (int64_t e = 0; e < c->n_elem; ++e)
@@ -295,8 +358,7 @@ hdg_status hdg_condense(hdg_ctx* c, double a, const double* f_loc, const double*
     int e;
     {
         EventTimer t(c, &c->tim.condense);
-        e = (c->physics == HDG_ACOUSTIC) ? launch_condense_acoustic(c, a, f_loc)
-                                         : launch_condense_general(c, a, f_loc);
+        e = c->fast_ac ? launch_condense_acoustic(c, a, f_loc) : launch_condense_general(c, a, f_loc);
     }
     if (e) return fail(c, HDG_E_HIP, "condensation kernel launch failed");
     {
@@ -416,12 +478,12 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
     c->last_refine = 0;
     c->tim.refine_elem = 0.f;
     c->tim.refine_solve = 0.f;
-    if (c->precision == HDG_MIXED_FP32 && c->physics == HDG_ACOUSTIC) return recover_refine_acoustic(c, lambda, u);
+    if (c->precision == HDG_MIXED_FP32 && c->fast_ac) return recover_refine_acoustic(c, lambda, u);
     int e;
     {
         EventTimer t(c, &c->tim.recover);
-        e = (c->physics == HDG_ACOUSTIC) ? launch_refine_acoustic(c, lambda, lambda, 1, false, u, nullptr)
-                                         : launch_recover_any(c, lambda, u);
+        e = c->fast_ac ? launch_refine_acoustic(c, lambda, lambda, 1, false, u, nullptr)
+                       : launch_recover_any(c, lambda, u);
     }
     if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
     if (c->precision != HDG_MIXED_FP32) return HDG_OK;
@@ -552,6 +614,7 @@ hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, doub
 
 hdg_status hdg_volume_points(const hdg_ctx* c, double* pts) {
     if (!c || !pts) return HDG_E_ARG;
+    if (c->vardeg) return HDG_E_UNSUPPORTED;
     std::vector<double> p, w;
     simplex_quadrature(c->dim, c->k + 2, p, w);
     const int d = c->dim, nq = (int)w.size();
@@ -569,6 +632,7 @@ hdg_status hdg_volume_points(const hdg_ctx* c, double* pts) {
 
 hdg_status hdg_project_volume(const hdg_ctx* c, const double* vals, double* u) {
     if (!c || !vals || !u) return HDG_E_ARG;
+    if (c->vardeg) return HDG_E_UNSUPPORTED;
     std::vector<double> p, w;
     simplex_quadrature(c->dim, c->k + 2, p, w);
     const int d = c->dim, nq = (int)w.size(), N = c->N, m = c->m_local;
@@ -586,6 +650,7 @@ hdg_status hdg_project_volume(const hdg_ctx* c, const double* vals, double* u) {
 
 hdg_status hdg_boundary_points(const hdg_ctx* c, double* pts) {
     if (!c || !pts) return HDG_E_ARG;
+    if (c->vardeg) return HDG_E_UNSUPPORTED;
     std::vector<double> p, w;
     const int d = c->dim;
     simplex_quadrature(d - 1, c->k + 3, p, w);
@@ -605,6 +670,7 @@ hdg_status hdg_boundary_points(const hdg_ctx* c, double* pts) {
 
 hdg_status hdg_project_boundary(const hdg_ctx* c, const double* vals, double* lam) {
     if (!c || !vals || !lam) return HDG_E_ARG;
+    if (c->vardeg) return HDG_E_UNSUPPORTED;
     std::vector<double> p, w;
     const int d = c->dim;
     simplex_quadrature(d - 1, c->k + 3, p, w);
@@ -638,9 +704,9 @@ hdg_status hdg_project_boundary(const hdg_ctx* c, const double* vals, double* la
 hdg_status hdg_point_sources(const hdg_ctx* c, int n_src, const double* pts, double* f) {
     if (!c || !pts || !f || n_src < 1) return HDG_E_ARG;
     if (c->physics != HDG_ACOUSTIC) return HDG_E_UNSUPPORTED;
-    const int d = c->dim, N = c->N;
+    const int d = c->dim;
     std::fill(f, f + c->n_local_dofs * n_src, 0.0);
-    std::vector<double> phi(N);
+    std::vector<double> phi(c->N);
     for (int s = 0; s < n_src; ++s) {
         const double* x = pts + s * d;
         bool found = false;
@@ -657,8 +723,10 @@ hdg_status hdg_point_sources(const hdg_ctx* c, int n_src, const double* pts, dou
                 if (acc < -1e-12) inside = false;
             }
             if (!inside || sum > 1.0 + 1e-12) continue;
-            pkd_eval(d, c->k, xi, phi.data(), nullptr);
-            for (int i = 0; i < N; ++i) f[(e * c->n_loc + d * N + i) * n_src + s] = phi[i];
+            const int ke = c->vardeg ? c->degree[e] : c->k, Ne = dim_p(ke, d);
+            const int64_t base = c->vardeg ? c->loc_off_h[e] : e * c->n_loc;
+            pkd_eval(d, ke, xi, phi.data(), nullptr);
+            for (int i = 0; i < Ne; ++i) f[(base + d * Ne + i) * n_src + s] = phi[i];
             found = true;
         }
         if (!found) return HDG_E_ARG;
@@ -669,6 +737,7 @@ hdg_status hdg_point_sources(const hdg_ctx* c, int n_src, const double* pts, dou
 hdg_status hdg_element_data(hdg_ctx* c, int which, int64_t e0, int64_t count, double* out) {
     if (!c || !out || which < 0 || which > 3 || e0 < 0 || count < 0 || e0 + count > c->n_elem) return HDG_E_ARG;
     if (!c->condensed) return fail(c, HDG_E_STATE, "no condensed data");
+    if (c->vardeg && which == 3) return fail(c, HDG_E_UNSUPPORTED, "z rows are per-class on variable degree");
     const int64_t R = c->nrhs, n = c->n_loc, t = c->n_tr;
     int64_t blk;
     void* src;
@@ -716,9 +785,14 @@ void hdg_destroy(hdg_ctx* c) {
                     c->d_bsr, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
                     c->d_scal, c->d_f_saved, c->d_lbnd_saved, c->d_su, c->d_slam, c->d_du, c->d_dlam,
                     c->d_re64, c->d_sq,
-                    c->d_stage, c->d_ustar, c->d_fstage};
+                    c->d_stage, c->d_ustar, c->d_fstage, c->d_loc_off, c->d_efnf, c->d_face_nf, c->d_edeg,
+                    c->d_cls[1], c->d_cls[2], c->d_cls[3], c->d_cls[4], c->d_cls[5]};
     if (c->stream || c->d_geom) (void)hipStreamSynchronize(c->stream);
     for (void* p : ptrs) dfree(p);
+    for (auto& t : c->tabk) {
+        void* tp[] = {t.Sr, t.Mf, t.Tsym, t.Ef, t.Tfull, t.Sr32, t.Mf32, t.Tsym32, t.Ef32, t.Tfull32};
+        for (void* p : tp) dfree(p);
+    }
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;

@@ -1,6 +1,8 @@
-// Elastodynamic and Maxwell HDG condensation / recovery kernels for gfx950.
+// Block-structured HDG condensation / recovery / refinement kernels for gfx950: elastodynamics,
+// Maxwell, and acoustics on meshes of variable polynomial degree or with several right-hand
+// sides.
 //
-// Both physics share one block structure of the element stage matrix (unknowns
+// All three physics share one block structure of the element stage matrix (unknowns
 // u = [u1 (M1 flux-like components), u2 (M2 components)], trace lam with MT components):
 //   A = [[D1, X], [-X^T, A22]],   D1 = |J| dmat (x) I_N,   X = |J| sum_r c_r (x) Sr_r^T,
 //   B = [B1; B2] with B1_a[(f,c)] = b1[a][f,c] s_f E_f,  B2_b[(f,c)] = b2[b][f,c] s_f E_f,
@@ -14,6 +16,14 @@
 //     dmat = a mu I, c_r[y][x] = sum_s eps_{x s y} G_rs, b1[y][f,c] = (n_f x t_fc)_y,
 //     b2[x][f,c] = -tau t_fc,x, amass = (a eps + sigma) I, af_f = tau (I - n_f n_f^T),
 //     dface = tau, j1 = -1.
+//   acoustic (u1 = velocity, u2 = pressure, trace p_hat):
+//     dmat = a rho I, c_r[x][0] = -G_rx, b1[x][f] = n_fx, b2[0][f] = -tau, amass = a/(rho c^2),
+//     af_f = tau, dface = -tau, j1 = +1.
+// Variable degree (acoustic): the face tables are built at the largest element degree of the
+// mesh and the modes of a face above its own degree (the larger degree of its two elements)
+// are masked out; elements are launched by degree class through an element list, local
+// vectors are addressed through compact offsets, and per-element outputs use the strides of
+// the largest class.
 // LU without pivoting of A with the D1 block first (closed form) leaves the SPD Schur block
 //   S   = A22 + X^T D1^{-1} X = A22 + |J| sum_{r,r'} (c_r^T dmat^{-1} c_r') (x) Sr_r Sr_r'^T
 //   B~2 = B2 + X^T D1^{-1} B1,  f~2 = f2 + X^T D1^{-1} f1,
@@ -31,10 +41,14 @@ namespace hdg {
 namespace {
 
 constexpr int NTG = 256;
-constexpr int PH_ELASTIC = 1, PH_MAXWELL = 2;
+constexpr int PH_ACOUSTIC = 0, PH_ELASTIC = 1, PH_MAXWELL = 2;
 
 template <int PHYS>
 struct PhysDims;
+template <>
+struct PhysDims<PH_ACOUSTIC> {
+    static constexpr int M1 = 3, M2 = 1, MT = 1;
+};
 template <>
 struct PhysDims<PH_ELASTIC> {
     static constexpr int M1 = 6, M2 = 3, MT = 3;
@@ -44,11 +58,11 @@ struct PhysDims<PH_MAXWELL> {
     static constexpr int M1 = 3, M2 = 3, MT = 2;
 };
 
-template <int PHYS, int K, int R>
+template <int PHYS, int K, int KF, int R>
 struct GDims {
     static constexpr int D = 3, NFACE = 4, NPERM = 6;
     static constexpr int M1 = PhysDims<PHYS>::M1, M2 = PhysDims<PHYS>::M2, MT = PhysDims<PHYS>::MT;
-    static constexpr int N = dimp(K, 3), NF = dimp(K, 2);
+    static constexpr int N = dimp(K, 3), NF = dimp(KF, 2);
     static constexpr int N1 = M1 * N, N2 = M2 * N, NLOC = N1 + N2;
     static constexpr int NFC = NFACE * MT;             // (face, component) pairs
     static constexpr int TT = NFC * NF;
@@ -95,7 +109,24 @@ __device__ void coef_primary(const double* g, const double* frm, double a, Coef<
             for (int f = 0; f < 4; ++f) cf.af[f][b][b2] = 0.0;
         }
     cf.j1 = -1.0;
-    if constexpr (PHYS == PH_ELASTIC) {
+    if constexpr (PHYS == PH_ACOUSTIC) {
+        const double rho = g[GEO_PAR], cc = g[GEO_PAR + 1], tau = g[GEO_STAB];
+        for (int x = 0; x < 3; ++x) {
+            cf.dmat[x][x] = a * rho;
+            cf.d1inv[x][x] = 1.0 / (a * rho);
+        }
+        for (int r = 0; r < 3; ++r)
+            for (int x = 0; x < 3; ++x) cf.c[r][x][0] = -G[r][x];
+        for (int x = 0; x < 3; ++x)
+            for (int f = 0; f < 4; ++f) cf.b1[x][f] = n[f][x];
+        for (int f = 0; f < 4; ++f) {
+            cf.b2[0][f] = -tau;
+            cf.af[f][0][0] = tau;
+        }
+        cf.amass[0][0] = a / (rho * cc * cc);
+        cf.dface = -tau;
+        cf.j1 = 1.0;
+    } else if constexpr (PHYS == PH_ELASTIC) {
         const double rho = g[GEO_PAR], lam = g[GEO_PAR + 1], mu = g[GEO_PAR + 2], S = g[GEO_STAB];
         // stress pairs (0,0),(1,1),(2,2),(1,2),(0,2),(0,1); E_a = e_i e_j^T + e_j e_i^T (i != j)
         const int pi[6] = {0, 1, 2, 1, 0, 0}, pj[6] = {0, 1, 2, 2, 2, 1};
@@ -211,37 +242,59 @@ __device__ void coef_derived_b(Coef<PHYS>& cf, int t, int nthr) {
     }
 }
 
+// Addressing of meshes of variable degree (all null / zero on a mesh of uniform degree).
+struct VarArgs {
+    const int32_t* elist;    // elements of the launched degree class (null: 0 .. count-1)
+    const int64_t* loc_off;  // compact local dof offsets (null: e * NLOC)
+    const int8_t* efnf;      // [e][4] size of the face space of each local face (null: NF)
+    int64_t strZ, strz, strL;   // per-element strides of Z, z, L (0: the class's own sizes)
+};
+
 template <typename T>
 __device__ __forceinline__ T geps() {
     return sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7);
 }
 
-template <int PHYS, int K, int R, typename T, bool XG>
+// SG: 0 all scratch in LDS; 1 the [B~2 | f~2] block in global scratch; 2 also the Schur block
+// buffer and f1 (per workgroup, when the LDS cannot hold them).
+template <int PHYS, int K, int KF, int R>
+constexpr int64_t gen_gstride(int SG) {
+    using Dm = GDims<PHYS, K, KF, R>;
+    return (SG >= 1 ? (int64_t)Dm::N2 * Dm::C : 0) + (SG >= 2 ? (int64_t)Dm::SBUF + Dm::N1 * R : 0);
+}
+
+template <int PHYS, int K, int KF, int R, typename T, int SG>
 __global__ __launch_bounds__(NTG) void condense_general_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
     const int32_t* __restrict__ eperm, const T* __restrict__ Sr, const T* __restrict__ Mf,
     const T* __restrict__ Tfull, const T* __restrict__ Ef, const double* __restrict__ f_loc,
     T* __restrict__ Ke, T* __restrict__ re, T* __restrict__ Zs, T* __restrict__ zs, T* __restrict__ Lout,
-    T* __restrict__ Xglob, int* __restrict__ status) {
-    using Dm = GDims<PHYS, K, R>;
+    T* __restrict__ Xglob, int* __restrict__ status, VarArgs va) {
+    using Dm = GDims<PHYS, K, KF, R>;
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, NPERM = Dm::NPERM, D = Dm::D;
     constexpr int M1 = Dm::M1, M2 = Dm::M2, MT = Dm::MT, N1 = Dm::N1, N2 = Dm::N2, NLOC = Dm::NLOC;
     constexpr int NFC = Dm::NFC, TT = Dm::TT, C = Dm::C;
 
     __shared__ T Srs[D * N * N];
-    __shared__ T Sb[Dm::SBUF];
+    __shared__ T Sbl[SG >= 2 ? 1 : Dm::SBUF];
     __shared__ T El[NFACE * N * NF];
-    __shared__ T F1[N1 * R];
-    __shared__ T Xl[XG ? 1 : N2 * C];
+    __shared__ T F1l[SG >= 2 ? 1 : N1 * R];
+    __shared__ T Xl[SG >= 1 ? 1 : N2 * C];
     __shared__ Coef<PHYS> cf;
     __shared__ double geo[GEOM_STRIDE];
     __shared__ double frm[24];
-    T* X = XG ? Xglob + (size_t)blockIdx.x * N2 * C : Xl;
+    T* gsc = Xglob + (size_t)blockIdx.x * gen_gstride<PHYS, K, KF, R>(SG);
+    T* X = SG >= 1 ? gsc : Xl;
+    T* Sb = SG >= 2 ? gsc + (int64_t)N2 * C : Sbl;
+    T* F1 = SG >= 2 ? gsc + (int64_t)N2 * C + Dm::SBUF : F1l;
+    const int64_t strZ = va.strZ ? va.strZ : (int64_t)N2 * TT, strz = va.strz ? va.strz : (int64_t)NLOC * R;
+    const int64_t strL = va.strL ? va.strL : (int64_t)N2 * N2;
     const int tid = threadIdx.x;
 
     for (int idx = tid; idx < D * N * N; idx += NTG) Srs[idx] = Sr[idx];
 
-    for (int64_t e = blockIdx.x; e < ne; e += gridDim.x) {
+    for (int64_t ie = blockIdx.x; ie < ne; ie += gridDim.x) {
+        const int64_t e = va.elist ? (int64_t)va.elist[ie] : ie;
         __syncthreads();
         // ------------------------------------------------------------ load
         if (tid < GEOM_STRIDE) geo[tid] = geom[e * GEOM_STRIDE + tid];
@@ -249,9 +302,10 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
         for (int idx = tid; idx < NFACE * N * NF; idx += NTG) {
             const int f = idx / (N * NF);
             const int p = eperm[e * NFACE + f];
-            El[idx] = Ef[(size_t)(f * NPERM + p) * N * NF + (idx - f * N * NF)];
+            const int nfv = va.efnf ? (int)va.efnf[e * NFACE + f] : NF;
+            El[idx] = (idx % NF) < nfv ? Ef[(size_t)(f * NPERM + p) * N * NF + (idx - f * N * NF)] : T(0);
         }
-        const double* fe = f_loc + (size_t)e * NLOC * R;
+        const double* fe = f_loc + (va.loc_off ? va.loc_off[e] : e * NLOC) * R;
         for (int idx = tid; idx < N1 * R; idx += NTG) F1[idx] = (T)fe[idx];
         for (int idx = tid; idx < N2 * R; idx += NTG) X[(idx / R) * C + TT + idx % R] = (T)fe[N1 * R + idx];
         __syncthreads();
@@ -349,7 +403,7 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
             }
         }
         if (Lout)
-            for (int idx = tid; idx < N2 * N2; idx += NTG) Lout[(size_t)e * N2 * N2 + idx] = Sb[idx];
+            for (int idx = tid; idx < N2 * N2; idx += NTG) Lout[e * strL + idx] = Sb[idx];
         // ------------------------------------------------------------ [W | w] = L^{-1} [B~2 | f~2] (blocked)
         constexpr int BS = 8;
         for (int b0 = 0; b0 < N2; b0 += BS) {
@@ -463,9 +517,9 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
             }
             __syncthreads();
         }
-        T* Zse = Zs + (size_t)e * N2 * TT;
+        T* Zse = Zs + e * strZ;
         for (int idx = tid; idx < N2 * TT; idx += NTG) Zse[idx] = X[(idx / TT) * C + idx % TT];
-        T* zse = zs + (size_t)e * NLOC * R;
+        T* zse = zs + e * strz;
         for (int idx = tid; idx < N2 * R; idx += NTG) zse[N1 * R + idx] = X[(idx / R) * C + TT + idx % R];
         for (int idx = tid; idx < N1 * R; idx += NTG) {
             const int al = idx / (N * R), iq = idx % (N * R);
@@ -477,25 +531,26 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
     }
 }
 
-// Recovery: u2 = z2 - Z2 lam_e ;
+// Recovery, one right-hand-side column at a time: u2 = z2 - Z2 lam_e ;
 // u1_a = z1_a - (1/|J|) sum_fc bd[a][fc] s_f E_f lam_fc - sum_{r,b} cd[r][a][b] Sr_r^T u2_b
-template <int PHYS, int K, int R, typename T, int WPB>
+template <int PHYS, int K, int KF, int R, typename T, int WPB>
 __global__ __launch_bounds__(64 * WPB) void recover_general_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
     const int32_t* __restrict__ eperm, const int32_t* __restrict__ eface, const T* __restrict__ Sr,
     const T* __restrict__ Ef, const T* __restrict__ Zs, const T* __restrict__ zs,
-    const double* __restrict__ lam, double* __restrict__ u) {
-    using Dm = GDims<PHYS, K, R>;
+    const double* __restrict__ lam, double* __restrict__ u, VarArgs va) {
+    using Dm = GDims<PHYS, K, KF, R>;
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, NPERM = Dm::NPERM, D = Dm::D;
     constexpr int M1 = Dm::M1, M2 = Dm::M2, MT = Dm::MT, N1 = Dm::N1, N2 = Dm::N2, NLOC = Dm::NLOC;
     constexpr int NFC = Dm::NFC, TT = Dm::TT;
     struct Scr {
         double geo[GEOM_STRIDE];
         double frm[24];
-        double lm[TT * R];
-        double u2[N2 * R];
-        double ef[NFC * N * R];
-        double yu[D * M2 * N * R];
+        double lm[TT];
+        double u2[N2];
+        double ef[NFC * N];
+        double yu[D * M2 * N];
+        int nfv[NFACE];
         Coef<PHYS> cf;
     };
     __shared__ double Srs[D * N * N];
@@ -504,353 +559,436 @@ __global__ __launch_bounds__(64 * WPB) void recover_general_kernel(
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     Scr& sc = scr_all[wave];
-    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
+    const int64_t strZ = va.strZ ? va.strZ : (int64_t)N2 * TT, strz = va.strz ? va.strz : (int64_t)NLOC * R;
+    auto ws = []() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    for (int64_t ie = (int64_t)blockIdx.x * WPB + wave; ie < ne; ie += (int64_t)gridDim.x * WPB) {
+        const int64_t e = va.elist ? (int64_t)va.elist[ie] : ie;
         if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
         if (PHYS == PH_MAXWELL && lane < 24) sc.frm[lane] = eframe[e * 24 + lane];
-        for (int idx = lane; idx < TT * R; idx += 64) {
-            const int c = idx / R, q = idx % R;
-            const int f = c / (MT * NF);
-            const int32_t F = eface[e * NFACE + f];
-            sc.lm[idx] = lam[((int64_t)F * MT * NF + c % (MT * NF)) * R + q];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane < NFACE) sc.nfv[lane] = va.efnf ? (int)va.efnf[e * NFACE + lane] : NF;
+        ws();
         if (lane == 0) coef_primary<PHYS>(sc.geo, sc.frm, a, sc.cf);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        ws();
         coef_derived_a<PHYS>(sc.cf, lane, 64);
-        const T* Zse = Zs + (size_t)e * N2 * TT;
-        const T* zse = zs + (size_t)e * NLOC * R;
-        double* ue = u + (size_t)e * NLOC * R;
-        for (int idx = lane; idx < N2 * R; idx += 64) {
-            const int row = idx / R, q = idx % R;
-            double acc = (double)zse[N1 * R + idx];
-            const T* Zr = Zse + row * TT;
-            for (int c = 0; c < TT; ++c) acc -= (double)Zr[c] * sc.lm[c * R + q];
-            sc.u2[idx] = acc;
-            ue[N1 * R + idx] = acc;
-        }
-        for (int idx = lane; idx < NFC * N * R; idx += 64) {
-            const int fc = idx / (N * R), i = (idx / R) % N, q = idx % R;
-            const int f = fc / MT, p = eperm[e * NFACE + f];
-            const T* Er = Ef + (size_t)(f * NPERM + p) * N * NF + i * NF;
-            double s = 0.0;
-            for (int l = 0; l < NF; ++l) s += (double)Er[l] * sc.lm[(fc * NF + l) * R + q];
-            sc.ef[idx] = s * sc.geo[1 + D * D + f];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int idx = lane; idx < D * M2 * N * R; idx += 64) {
-            const int r = idx / (M2 * N * R), b = (idx / (N * R)) % M2, i = (idx / R) % N, q = idx % R;
-            double s = 0.0;
-            for (int j = 0; j < N; ++j) s += Srs[(r * N + j) * N + i] * sc.u2[(b * N + j) * R + q];
-            sc.yu[idx] = s;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const T* Zse = Zs + e * strZ;
+        const T* zse = zs + e * strz;
+        double* ue = u + (va.loc_off ? va.loc_off[e] : e * NLOC) * R;
         const double invJ = 1.0 / sc.geo[0];
-        for (int idx = lane; idx < N1 * R; idx += 64) {
-            const int al = idx / (N * R), iq = idx % (N * R);
-            double s1 = 0.0, s2 = 0.0;
-            for (int fc = 0; fc < NFC; ++fc) s1 += sc.cf.bd[al][fc] * sc.ef[fc * N * R + iq];
-            for (int r = 0; r < D; ++r)
-                for (int b = 0; b < M2; ++b) s2 += sc.cf.cd[r][al][b] * sc.yu[(r * M2 + b) * N * R + iq];
-            ue[idx] = (double)zse[idx] - invJ * s1 - s2;
+#pragma unroll 1
+        for (int q = 0; q < R; ++q) {
+            for (int c = lane; c < TT; c += 64) {
+                const int f = c / (MT * NF), l = c % NF;
+                const int32_t F = eface[e * NFACE + f];
+                sc.lm[c] = l < sc.nfv[f] ? lam[((int64_t)F * MT * NF + c % (MT * NF)) * R + q] : 0.0;
+            }
+            ws();
+            for (int row = lane; row < N2; row += 64) {
+                double acc = (double)zse[(N1 + row) * R + q];
+                const T* Zr = Zse + row * TT;
+                for (int c = 0; c < TT; ++c) acc -= (double)Zr[c] * sc.lm[c];
+                sc.u2[row] = acc;
+                ue[(N1 + row) * R + q] = acc;
+            }
+            for (int idx = lane; idx < NFC * N; idx += 64) {
+                const int fc = idx / N, i = idx % N;
+                const int f = fc / MT, p = eperm[e * NFACE + f];
+                const T* Er = Ef + (size_t)(f * NPERM + p) * N * NF + i * NF;
+                double s = 0.0;
+                for (int l = 0; l < NF; ++l) s += (double)Er[l] * sc.lm[fc * NF + l];
+                sc.ef[idx] = s * sc.geo[1 + D * D + f];
+            }
+            ws();
+            for (int idx = lane; idx < D * M2 * N; idx += 64) {
+                const int r = idx / (M2 * N), b = (idx / N) % M2, i = idx % N;
+                double s = 0.0;
+                for (int j = 0; j < N; ++j) s += Srs[(r * N + j) * N + i] * sc.u2[b * N + j];
+                sc.yu[idx] = s;
+            }
+            ws();
+            for (int idx = lane; idx < N1; idx += 64) {
+                const int al = idx / N, i = idx % N;
+                double s1 = 0.0, s2 = 0.0;
+                for (int fc = 0; fc < NFC; ++fc) s1 += sc.cf.bd[al][fc] * sc.ef[fc * N + i];
+                for (int r = 0; r < D; ++r)
+                    for (int b = 0; b < M2; ++b) s2 += sc.cf.cd[r][al][b] * sc.yu[(r * M2 + b) * N + i];
+                ue[idx * R + q] = (double)zse[idx * R + q] - invJ * s1 - s2;
+            }
+            ws();
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
 // Mixed-precision refinement step (FP64 residual of the full stage system, correction through
-// the stored FP32 factors):
+// the stored FP32 factors), one right-hand-side column at a time:
 //   s1 = f1 - |J| (dmat (x) I) u1 - X u2 - B1 lam,   s2 = f2 + X^T u1 - A22 u2 - B2 lam
 //   t_e = j1 B1^T u1 + j2 B2^T u2 + D lam
 //   s~2 = s2 + X^T D1^{-1} s1,  z' = [D1^{-1} s1 ; L^{-T} L^{-1} s~2]
 //   re64 = -j1 B1^T D1^{-1} s1 - j2 Z2^T s~2 - t_e
 // One element per wavefront; operator applications staged as short products with lanes over
-// their outputs; the triangular solves are column-oriented with lanes over rows.
-template <int PHYS, int K, int R, typename T, int WPB>
+// their outputs; the triangular solves are column-oriented with lanes over rows.  TL: the
+// reference tables Sr, Mf are staged in LDS (otherwise read through the caches).
+template <int PHYS, int K, int KF, int R, typename T, int WPB, bool TL>
 __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
     const int32_t* __restrict__ eperm, const int32_t* __restrict__ eface, const double* __restrict__ Sr,
     const double* __restrict__ Mf, const double* __restrict__ Ef, const T* __restrict__ Zs,
     const T* __restrict__ Lst, const double* __restrict__ u, const double* __restrict__ lam,
-    const double* __restrict__ f, T* __restrict__ zout, double* __restrict__ re64) {
-    using Dm = GDims<PHYS, K, R>;
+    const double* __restrict__ f, T* __restrict__ zout, double* __restrict__ re64, VarArgs va) {
+    using Dm = GDims<PHYS, K, KF, R>;
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, NPERM = Dm::NPERM, D = Dm::D;
     constexpr int M1 = Dm::M1, M2 = Dm::M2, MT = Dm::MT, N1 = Dm::N1, N2 = Dm::N2, NLOC = Dm::NLOC;
     constexpr int NFC = Dm::NFC, TT = Dm::TT;
     struct Scr {
         double geo[GEOM_STRIDE];
         double frm[24];
-        double uu[NLOC * R];
-        double su[NLOC * R];
-        double lm[TT * R];
-        double ef[NFC * N * R];        // s_f E_f lam_fc
-        double yu[D * M2 * N * R];     // Sr_r^T u2_b
-        double gu[D * M2 * N * R];     // sum_a c[r][a][b] u1_a, later sum_a cd[r][a][b] s1_a
-        double mu[NFACE * M2 * N * R]; // Mf_f u2_b
-        double st[N2 * R];             // s~2, then S^{-1} s~2
-        double te[TT * R];
+        double uu[NLOC];
+        double su[NLOC];
+        double lm[TT];
+        double ef[NFC * N];        // s_f E_f lam_fc
+        double yu[D * M2 * N];     // Sr_r^T u2_b
+        double gu[D * M2 * N];     // sum_a c[r][a][b] u1_a, later sum_a cd[r][a][b] s1_a
+        double mu[NFACE * M2 * N]; // Mf_f u2_b
+        double st[N2];             // s~2, then S^{-1} s~2
+        double te[TT];
         double El[NFACE * N * NF];
+        int nfv[NFACE];
         Coef<PHYS> cf;
     };
-    __shared__ double Srs[D * N * N];
-    __shared__ double Mfs[NFACE * N * N];
+    __shared__ double Srl[TL ? D * N * N : 1];
+    __shared__ double Mfl[TL ? NFACE * N * N : 1];
     __shared__ Scr scr_all[WPB];
-    for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
-    for (int idx = threadIdx.x; idx < NFACE * N * N; idx += 64 * WPB) Mfs[idx] = Mf[idx];
+    if (TL) {
+        for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srl[idx] = Sr[idx];
+        for (int idx = threadIdx.x; idx < NFACE * N * N; idx += 64 * WPB) Mfl[idx] = Mf[idx];
+    }
     __syncthreads();
+    const double* Srs = TL ? Srl : Sr;
+    const double* Mfs = TL ? Mfl : Mf;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     Scr& sc = scr_all[wave];
+    const int64_t strZ = va.strZ ? va.strZ : (int64_t)N2 * TT, strz = va.strz ? va.strz : (int64_t)NLOC * R;
+    const int64_t strL = va.strL ? va.strL : (int64_t)N2 * N2;
     auto ws = []() {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
-    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
+    for (int64_t ie = (int64_t)blockIdx.x * WPB + wave; ie < ne; ie += (int64_t)gridDim.x * WPB) {
+        const int64_t e = va.elist ? (int64_t)va.elist[ie] : ie;
+        const int64_t loc = (va.loc_off ? va.loc_off[e] : e * NLOC) * R;
         if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
         if (PHYS == PH_MAXWELL && lane < 24) sc.frm[lane] = eframe[e * 24 + lane];
-        for (int idx = lane; idx < NLOC * R; idx += 64) {
-            sc.uu[idx] = u[(size_t)e * NLOC * R + idx];
-            sc.su[idx] = f[(size_t)e * NLOC * R + idx];
-        }
-        for (int idx = lane; idx < TT * R; idx += 64) {
-            const int c = idx / R, q = idx % R;
-            const int32_t F = eface[e * NFACE + c / (MT * NF)];
-            sc.lm[idx] = lam[((int64_t)F * MT * NF + c % (MT * NF)) * R + q];
-        }
+        if (lane < NFACE) sc.nfv[lane] = va.efnf ? (int)va.efnf[e * NFACE + lane] : NF;
         for (int idx = lane; idx < NFACE * N * NF; idx += 64) {
             const int fc = idx / (N * NF);
             const int p = eperm[e * NFACE + fc];
-            sc.El[idx] = Ef[(size_t)(fc * NPERM + p) * N * NF + (idx - fc * N * NF)];
+            const int nfv = va.efnf ? (int)va.efnf[e * NFACE + fc] : NF;
+            sc.El[idx] = (idx % NF) < nfv ? Ef[(size_t)(fc * NPERM + p) * N * NF + (idx - fc * N * NF)] : 0.0;
         }
         ws();
         if (lane == 0) coef_primary<PHYS>(sc.geo, sc.frm, a, sc.cf);
         ws();
         coef_derived_a<PHYS>(sc.cf, lane, 64);
         const double J = sc.geo[0];
+        const double j1 = sc.cf.j1, j2 = -j1;
+        const T* Zse = Zs + e * strZ;
+        const T* L = Lst + e * strL;
+        T* ze = zout + e * strz;
         const double* u1 = sc.uu;
-        const double* u2 = sc.uu + N1 * R;
-        // ---- stage 1: E_f lam, Sr^T u2, c-weighted u1, Mf u2
-        for (int idx = lane; idx < NFC * N * R; idx += 64) {
-            const int fc = idx / (N * R), i = (idx / R) % N, q = idx % R;
-            const int f = fc / MT;
-            double s = 0.0;
-            for (int l = 0; l < NF; ++l) s += sc.El[(f * N + i) * NF + l] * sc.lm[(fc * NF + l) * R + q];
-            sc.ef[idx] = sc.geo[1 + D * D + f] * s;
-        }
-        for (int idx = lane; idx < D * M2 * N * R; idx += 64) {
-            const int r = idx / (M2 * N * R), b = (idx / (N * R)) % M2, i = (idx / R) % N, q = idx % R;
-            double y = 0.0, g = 0.0;
-            for (int j = 0; j < N; ++j) y += Srs[(r * N + j) * N + i] * u2[(b * N + j) * R + q];
-            for (int al = 0; al < M1; ++al) g += sc.cf.c[r][al][b] * u1[(al * N + i) * R + q];
-            sc.yu[idx] = y;
-            sc.gu[idx] = g;
-        }
-        for (int idx = lane; idx < NFACE * M2 * N * R; idx += 64) {
-            const int fa = idx / (M2 * N * R), b = (idx / (N * R)) % M2, i = (idx / R) % N, q = idx % R;
-            double s = 0.0;
-            for (int j = 0; j < N; ++j) s += Mfs[(fa * N + i) * N + j] * u2[(b * N + j) * R + q];
-            sc.mu[idx] = s;
-        }
-        ws();
-        // ---- stage 2: s = f - A u - B lam
-        for (int idx = lane; idx < NLOC * R; idx += 64) {
-            const int row = idx / R, q = idx % R;
-            double Au;
-            if (row < N1) {
-                const int al = row / N, i = row % N;
+        const double* u2 = sc.uu + N1;
+        const double* s1 = sc.su;
+        const double* s2 = sc.su + N1;
+#pragma unroll 1
+        for (int q = 0; q < R; ++q) {
+            for (int idx = lane; idx < NLOC; idx += 64) {
+                sc.uu[idx] = u[loc + (int64_t)idx * R + q];
+                sc.su[idx] = f[loc + (int64_t)idx * R + q];
+            }
+            for (int c = lane; c < TT; c += 64) {
+                const int fo = c / (MT * NF), l = c % NF;
+                const int32_t F = eface[e * NFACE + fo];
+                sc.lm[c] = l < sc.nfv[fo] ? lam[((int64_t)F * MT * NF + c % (MT * NF)) * R + q] : 0.0;
+            }
+            ws();
+            // ---- stage 1: E_f lam, Sr^T u2, c-weighted u1, Mf u2
+            for (int idx = lane; idx < NFC * N; idx += 64) {
+                const int fc = idx / N, i = idx % N;
+                const int fo = fc / MT;
                 double s = 0.0;
-                for (int a2 = 0; a2 < M1; ++a2) s += sc.cf.dmat[al][a2] * u1[(a2 * N + i) * R + q];
-                Au = J * s;
-                double x = 0.0;
-                for (int r = 0; r < D; ++r)
-                    for (int b = 0; b < M2; ++b) x += sc.cf.c[r][al][b] * sc.yu[((r * M2 + b) * N + i) * R + q];
-                Au += J * x;
-                for (int fc = 0; fc < NFC; ++fc) Au += sc.cf.b1[al][fc] * sc.ef[(fc * N + i) * R + q];
-            } else {
-                const int b = (row - N1) / N, i = (row - N1) % N;
-                double xt = 0.0;
+                for (int l = 0; l < NF; ++l) s += sc.El[(fo * N + i) * NF + l] * sc.lm[fc * NF + l];
+                sc.ef[idx] = sc.geo[1 + D * D + fo] * s;
+            }
+            for (int idx = lane; idx < D * M2 * N; idx += 64) {
+                const int r = idx / (M2 * N), b = (idx / N) % M2, i = idx % N;
+                double y = 0.0, gg = 0.0;
+                for (int j = 0; j < N; ++j) y += Srs[(r * N + j) * N + i] * u2[b * N + j];
+                for (int al = 0; al < M1; ++al) gg += sc.cf.c[r][al][b] * u1[al * N + i];
+                sc.yu[idx] = y;
+                sc.gu[idx] = gg;
+            }
+            for (int idx = lane; idx < NFACE * M2 * N; idx += 64) {
+                const int fa = idx / (M2 * N), b = (idx / N) % M2, i = idx % N;
+                double s = 0.0;
+                for (int j = 0; j < N; ++j) s += Mfs[(fa * N + i) * N + j] * u2[b * N + j];
+                sc.mu[idx] = s;
+            }
+            ws();
+            // ---- stage 2: s = f - A u - B lam ; t_e = j1 B1^T u1 + j2 B2^T u2 + D lam
+            for (int row = lane; row < NLOC; row += 64) {
+                double Au;
+                if (row < N1) {
+                    const int al = row / N, i = row % N;
+                    double s = 0.0;
+                    for (int a2 = 0; a2 < M1; ++a2) s += sc.cf.dmat[al][a2] * u1[a2 * N + i];
+                    Au = J * s;
+                    double x = 0.0;
+                    for (int r = 0; r < D; ++r)
+                        for (int b = 0; b < M2; ++b) x += sc.cf.c[r][al][b] * sc.yu[(r * M2 + b) * N + i];
+                    Au += J * x;
+                    for (int fc = 0; fc < NFC; ++fc) Au += sc.cf.b1[al][fc] * sc.ef[fc * N + i];
+                } else {
+                    const int b = (row - N1) / N, i = (row - N1) % N;
+                    double xt = 0.0;
+                    for (int r = 0; r < D; ++r) {
+                        const double* Srow = &Srs[(r * N + i) * N];
+                        for (int j = 0; j < N; ++j) xt += Srow[j] * sc.gu[(r * M2 + b) * N + j];
+                    }
+                    double s = 0.0;
+                    for (int gm = 0; gm < M2; ++gm) {
+                        s += J * sc.cf.amass[b][gm] * u2[gm * N + i];
+                        for (int fa = 0; fa < NFACE; ++fa)
+                            s += sc.geo[1 + D * D + fa] * sc.cf.af[fa][b][gm] * sc.mu[(fa * M2 + gm) * N + i];
+                    }
+                    for (int fc = 0; fc < NFC; ++fc) s += sc.cf.b2[b][fc] * sc.ef[fc * N + i];
+                    Au = -J * xt + s;
+                }
+                sc.su[row] -= Au;
+            }
+            for (int aa = lane; aa < TT; aa += 64) {
+                const int fc = aa / NF, l = aa % NF, fo = fc / MT;
+                double s = 0.0;
+                for (int i = 0; i < N; ++i) {
+                    double w = 0.0;
+                    for (int al = 0; al < M1; ++al) w += j1 * sc.cf.b1[al][fc] * u1[al * N + i];
+                    for (int b = 0; b < M2; ++b) w += j2 * sc.cf.b2[b][fc] * u2[b * N + i];
+                    s += sc.El[(fo * N + i) * NF + l] * w;
+                }
+                const double sf = sc.geo[1 + D * D + fo];
+                sc.te[aa] = sf * s + sc.cf.dface * sf * sc.lm[aa];
+            }
+            ws();
+            // ---- stage 3: cd-weighted s1, then s~2
+            for (int idx = lane; idx < D * M2 * N; idx += 64) {
+                const int r = idx / (M2 * N), b = (idx / N) % M2, i = idx % N;
+                double gg = 0.0;
+                for (int al = 0; al < M1; ++al) gg += sc.cf.cd[r][al][b] * s1[al * N + i];
+                sc.gu[idx] = gg;
+            }
+            ws();
+            for (int idx = lane; idx < N2; idx += 64) {
+                const int b = idx / N, i = idx % N;
+                double acc = 0.0;
                 for (int r = 0; r < D; ++r) {
                     const double* Srow = &Srs[(r * N + i) * N];
-                    for (int j = 0; j < N; ++j) xt += Srow[j] * sc.gu[((r * M2 + b) * N + j) * R + q];
+                    for (int j = 0; j < N; ++j) acc += Srow[j] * sc.gu[(r * M2 + b) * N + j];
                 }
+                sc.st[idx] = s2[idx] + acc;
+            }
+            ws();
+            // ---- re64 = -j1 B1^T D1^{-1} s1 - j2 Z2^T s~2 - t_e (zero on masked face modes)
+            for (int aa = lane; aa < TT; aa += 64) {
+                const int fc = aa / NF, l = aa % NF, fo = fc / MT;
+                double rb = 0.0, zt = 0.0;
+                for (int i = 0; i < N; ++i) {
+                    double w = 0.0;
+                    for (int al = 0; al < M1; ++al) w += sc.cf.bd[al][fc] * s1[al * N + i];
+                    rb += sc.El[(fo * N + i) * NF + l] * w;
+                }
+                for (int row = 0; row < N2; ++row) zt += (double)Zse[row * TT + aa] * sc.st[row];
+                const double v = -j1 * sc.geo[1 + D * D + fo] / J * rb - j2 * zt - sc.te[aa];
+                re64[(e * TT + aa) * R + q] = l < sc.nfv[fo] ? v : 0.0;
+            }
+            // ---- z' = [D1^{-1} s1 ; S^{-1} s~2]
+            for (int idx = lane; idx < N1; idx += 64) {
+                const int al = idx / N, i = idx % N;
                 double s = 0.0;
-                for (int gm = 0; gm < M2; ++gm) {
-                    s += J * sc.cf.amass[b][gm] * u2[(gm * N + i) * R + q];
-                    for (int fa = 0; fa < NFACE; ++fa)
-                        s += sc.geo[1 + D * D + fa] * sc.cf.af[fa][b][gm] * sc.mu[((fa * M2 + gm) * N + i) * R + q];
-                }
-                for (int fc = 0; fc < NFC; ++fc) s += sc.cf.b2[b][fc] * sc.ef[(fc * N + i) * R + q];
-                Au = -J * xt + s;
+                for (int a2 = 0; a2 < M1; ++a2) s += sc.cf.d1inv[al][a2] * s1[a2 * N + i];
+                ze[idx * R + q] = (T)(s / J);
             }
-            sc.su[idx] -= Au;
-        }
-        // ---- t_e = j1 B1^T u1 + j2 B2^T u2 + D lam
-        const double j1 = sc.cf.j1, j2 = -j1;
-        for (int idx = lane; idx < TT * R; idx += 64) {
-            const int aa = idx / R, q = idx % R;
-            const int fc = aa / NF, l = aa % NF, f = fc / MT;
-            double s = 0.0;
-            for (int i = 0; i < N; ++i) {
-                double w = 0.0;
-                for (int al = 0; al < M1; ++al) w += j1 * sc.cf.b1[al][fc] * u1[(al * N + i) * R + q];
-                for (int b = 0; b < M2; ++b) w += j2 * sc.cf.b2[b][fc] * u2[(b * N + i) * R + q];
-                s += sc.El[(f * N + i) * NF + l] * w;
-            }
-            const double sf = sc.geo[1 + D * D + f];
-            sc.te[idx] = sf * s + sc.cf.dface * sf * sc.lm[idx];
-        }
-        ws();
-        const double* s1 = sc.su;
-        const double* s2 = sc.su + N1 * R;
-        // ---- stage 3: cd-weighted s1, then s~2
-        for (int idx = lane; idx < D * M2 * N * R; idx += 64) {
-            const int r = idx / (M2 * N * R), b = (idx / (N * R)) % M2, iq = idx % (N * R);
-            double g = 0.0;
-            for (int al = 0; al < M1; ++al) g += sc.cf.cd[r][al][b] * s1[al * N * R + iq];
-            sc.gu[idx] = g;
-        }
-        ws();
-        for (int idx = lane; idx < N2 * R; idx += 64) {
-            const int b = idx / (N * R), i = (idx / R) % N, q = idx % R;
-            double acc = 0.0;
-            for (int r = 0; r < D; ++r) {
-                const double* Srow = &Srs[(r * N + i) * N];
-                for (int j = 0; j < N; ++j) acc += Srow[j] * sc.gu[((r * M2 + b) * N + j) * R + q];
-            }
-            sc.st[idx] = s2[idx] + acc;
-        }
-        ws();
-        // ---- re64 = -j1 B1^T D1^{-1} s1 - j2 Z2^T s~2 - t_e
-        const T* Zse = Zs + (size_t)e * N2 * TT;
-        for (int idx = lane; idx < TT * R; idx += 64) {
-            const int aa = idx / R, q = idx % R;
-            const int fc = aa / NF, l = aa % NF, f = fc / MT;
-            double rb = 0.0, zt = 0.0;
-            for (int i = 0; i < N; ++i) {
-                double w = 0.0;
-                for (int al = 0; al < M1; ++al) w += sc.cf.bd[al][fc] * s1[(al * N + i) * R + q];
-                rb += sc.El[(f * N + i) * NF + l] * w;
-            }
-            for (int row = 0; row < N2; ++row) zt += (double)Zse[row * TT + aa] * sc.st[row * R + q];
-            re64[(size_t)e * TT * R + idx] = -j1 * sc.geo[1 + D * D + f] / J * rb - j2 * zt - sc.te[idx];
-        }
-        // ---- z' = [D1^{-1} s1 ; S^{-1} s~2]
-        T* ze = zout + (size_t)e * NLOC * R;
-        for (int idx = lane; idx < N1 * R; idx += 64) {
-            const int al = idx / (N * R), iq = idx % (N * R);
-            double s = 0.0;
-            for (int a2 = 0; a2 < M1; ++a2) s += sc.cf.d1inv[al][a2] * s1[a2 * N * R + iq];
-            ze[idx] = (T)(s / J);
-        }
-        ws();
-        const T* L = Lst + (size_t)e * N2 * N2;
-        for (int q = 0; q < R; ++q) {
+            ws();
             for (int j = 0; j < N2; ++j) {            // forward: L y = s~2
-                const double yj = sc.st[j * R + q] / (double)L[j * N2 + j];
+                const double yj = sc.st[j] / (double)L[j * N2 + j];
                 ws();
-                if (lane == 0) sc.st[j * R + q] = yj;
-                for (int i = j + 1 + lane; i < N2; i += 64) sc.st[i * R + q] -= (double)L[i * N2 + j] * yj;
+                if (lane == 0) sc.st[j] = yj;
+                for (int i = j + 1 + lane; i < N2; i += 64) sc.st[i] -= (double)L[i * N2 + j] * yj;
                 ws();
             }
             for (int j = N2 - 1; j >= 0; --j) {       // backward: L^T x = y
-                const double xj = sc.st[j * R + q] / (double)L[j * N2 + j];
+                const double xj = sc.st[j] / (double)L[j * N2 + j];
                 ws();
-                if (lane == 0) sc.st[j * R + q] = xj;
-                for (int i = lane; i < j; i += 64) sc.st[i * R + q] -= (double)L[j * N2 + i] * xj;
+                if (lane == 0) sc.st[j] = xj;
+                for (int i = lane; i < j; i += 64) sc.st[i] -= (double)L[j * N2 + i] * xj;
                 ws();
             }
+            for (int idx = lane; idx < N2; idx += 64) ze[(N1 + idx) * R + q] = (T)sc.st[idx];
+            ws();
         }
-        for (int idx = lane; idx < N2 * R; idx += 64) ze[N1 * R + idx] = (T)sc.st[idx];
-        ws();
     }
 }
 
-template <int PHYS, int K, int R, typename T>
-int launch_gen_ref(hdg_ctx* c, const double* u, const double* lam) {
-    constexpr int WPB = 1;
-    const int grid = (int)std::min<int64_t>(c->n_elem, 256 * 16);
-    hipLaunchKernelGGL((refine_general_kernel<PHYS, K, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream,
-                       c->n_elem, c->last_a, c->d_geom, c->d_eframe, c->d_eperm, c->d_eface, c->tab.Sr, c->tab.Mf,
-                       c->tab.Ef, (const T*)c->d_Zt, (const T*)c->d_LU, u, lam, c->d_f_saved, (T*)c->d_z,
-                       c->d_re64);
-    return (int)hipGetLastError();
+// ---------------------------------------------------------------------------------- launches
+template <typename T>
+struct TabOf;
+template <>
+struct TabOf<double> {
+    static const double* Sr(const DeviceTables& t) { return t.Sr; }
+    static const double* Mf(const DeviceTables& t) { return t.Mf; }
+    static const double* Tf(const DeviceTables& t) { return t.Tfull; }
+    static const double* Ef(const DeviceTables& t) { return t.Ef; }
+};
+template <>
+struct TabOf<float> {
+    static const float* Sr(const DeviceTables& t) { return t.Sr32; }
+    static const float* Mf(const DeviceTables& t) { return t.Mf32; }
+    static const float* Tf(const DeviceTables& t) { return t.Tfull32; }
+    static const float* Ef(const DeviceTables& t) { return t.Ef32; }
+};
+
+VarArgs var_args(const hdg_ctx* c, const int32_t* elist) {
+    VarArgs va{};
+    va.elist = elist;
+    if (c->vardeg) {
+        va.loc_off = c->d_loc_off;
+        va.efnf = c->d_efnf;
+        va.strZ = (int64_t)c->Ns * c->n_tr;
+        va.strz = (int64_t)c->n_loc * c->nrhs;
+        va.strL = (int64_t)c->Ns * c->Ns;
+    }
+    return va;
 }
 
-template <int PHYS, int K, int R, typename T>
-constexpr bool x_global() {
-    using Dm = GDims<PHYS, K, R>;
-    constexpr size_t lds = sizeof(T) * (Dm::D * Dm::N * Dm::N + Dm::SBUF + Dm::NFACE * Dm::N * Dm::NF +
-                                        Dm::N1 * R + Dm::N2 * Dm::C) +
-                           sizeof(Coef<PHYS>) + 8 * 64;
-    return lds > 150 * 1024;
+// scratch placement of the condensation kernel (see SG)
+template <int PHYS, int K, int KF, int R, typename T>
+constexpr int gen_sg() {
+    using Dm = GDims<PHYS, K, KF, R>;
+    constexpr size_t base = sizeof(T) * (Dm::D * Dm::N * Dm::N + Dm::NFACE * Dm::N * Dm::NF) +
+                            sizeof(Coef<PHYS>) + 8 * 64;
+    constexpr size_t mid = base + sizeof(T) * (Dm::SBUF + Dm::N1 * R);
+    constexpr size_t all = mid + sizeof(T) * Dm::N2 * Dm::C;
+    return all <= 150 * 1024 ? 0 : (mid <= 150 * 1024 ? 1 : 2);
 }
 
-template <int PHYS, int K, int R, typename T>
-int launch_gen(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* Mf, const T* Tf, const T* Ef) {
-    using Dm = GDims<PHYS, K, R>;
-    constexpr bool XG = x_global<PHYS, K, R, T>();
-    const int grid = (int)std::min<int64_t>(c->n_elem, 256 * 8);
-    if (XG && !c->d_xscratch) {
-        hipError_t er = hipMalloc(&c->d_xscratch, (size_t)grid * Dm::N2 * Dm::C * sizeof(T));
+template <int PHYS, int K, int KF, int R, typename T>
+int launch_gen(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist,
+               int64_t n) {
+    constexpr int SG = gen_sg<PHYS, K, KF, R, T>();
+    const int grid = (int)std::min<int64_t>(n, 256 * 8);
+    const size_t need = (size_t)grid * gen_gstride<PHYS, K, KF, R>(SG) * sizeof(T);
+    if (need > c->xscratch_bytes) {
+        if (c->d_xscratch) (void)hipFree(c->d_xscratch);
+        c->d_xscratch = nullptr;
+        c->xscratch_bytes = 0;
+        hipError_t er = hipMalloc(&c->d_xscratch, need);
         if (er != hipSuccess) return (int)er;
+        c->xscratch_bytes = need;
     }
-    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, R, T, XG>), dim3(grid), dim3(NTG), 0, c->stream,
-                       c->n_elem, a, c->d_geom, c->d_eframe, c->d_eperm, Sr, Mf, Tf, Ef, f_loc, (T*)c->d_Ke,
-                       (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
-                       c->precision == HDG_MIXED_FP32 ? (T*)c->d_LU : (T*)nullptr, (T*)c->d_xscratch,
-                       c->d_status);
+    using TB = TabOf<T>;
+    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, KF, R, T, SG>), dim3(grid), dim3(NTG), 0, c->stream, n, a,
+                       c->d_geom, c->d_eframe, c->d_eperm, TB::Sr(tb), TB::Mf(tb), TB::Tf(tb), TB::Ef(tb), f_loc,
+                       (T*)c->d_Ke, (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
+                       c->precision == HDG_MIXED_FP32 ? (T*)c->d_LU : (T*)nullptr, (T*)c->d_xscratch, c->d_status,
+                       var_args(c, elist));
     return (int)hipGetLastError();
 }
 
-template <int PHYS, int K, int R, typename T>
-int launch_gen_rec(hdg_ctx* c, const T* Sr, const T* Ef, const double* lam, double* u) {
+template <int PHYS, int K, int KF, int R, typename T>
+int launch_gen_rec(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int64_t n, const double* lam,
+                   double* u) {
     constexpr int WPB = 2;
-    int64_t groups = (c->n_elem + WPB - 1) / WPB;
+    int64_t groups = (n + WPB - 1) / WPB;
     int grid = (int)std::min<int64_t>(groups, 256 * 16);
-    hipLaunchKernelGGL((recover_general_kernel<PHYS, K, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream,
-                       c->n_elem, c->last_a, c->d_geom, c->d_eframe, c->d_eperm, c->d_eface, Sr, Ef,
-                       (const T*)c->d_Zt, (const T*)c->d_z, lam, u);
+    using TB = TabOf<T>;
+    hipLaunchKernelGGL((recover_general_kernel<PHYS, K, KF, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream, n,
+                       c->last_a, c->d_geom, c->d_eframe, c->d_eperm, c->d_eface, TB::Sr(tb), TB::Ef(tb),
+                       (const T*)c->d_Zt, (const T*)c->d_z, lam, u, var_args(c, elist));
     return (int)hipGetLastError();
 }
 
-#define HDG_GEN_CASES(X) X(1, 1, 1) X(1, 2, 1) X(1, 3, 1) X(1, 4, 1) X(2, 1, 1) X(2, 2, 1) X(2, 3, 1)
+template <int PHYS, int K, int KF, int R, typename T>
+int launch_gen_ref(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int64_t n, const double* u,
+                   const double* lam) {
+    constexpr int WPB = 1;
+    constexpr int N = dimp(K, 3);
+    constexpr bool TL = (3 + 4) * N * N * 8 <= 64 * 1024;
+    const int grid = (int)std::min<int64_t>(n, 256 * 16);
+    hipLaunchKernelGGL((refine_general_kernel<PHYS, K, KF, R, T, WPB, TL>), dim3(grid), dim3(64 * WPB), 0, c->stream,
+                       n, c->last_a, c->d_geom, c->d_eframe, c->d_eperm, c->d_eface, tb.Sr, tb.Mf, tb.Ef,
+                       (const T*)c->d_Zt, (const T*)c->d_LU, u, lam, c->d_f_saved, (T*)c->d_z, c->d_re64,
+                       var_args(c, elist));
+    return (int)hipGetLastError();
+}
 
-template <typename T>
-int dispatch_gen(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* Mf, const T* Tf, const T* Ef) {
-    const int P = c->physics, K = c->k, R = c->nrhs;
-#define HDG_CASE(PP, KK, RR) \
-    if (P == PP && K == KK && R == RR) return launch_gen<PP, KK, RR, T>(c, a, f_loc, Sr, Mf, Tf, Ef);
-    HDG_GEN_CASES(HDG_CASE)
-#undef HDG_CASE
-    return -1;
+// built configurations: (physics, volume degree, face-table degree, right-hand sides).
+// Uniform meshes use face degree = volume degree; meshes of variable degree (acoustic) use
+// face tables of degree 5 for every class.
+#define HDG_GEN_CASES(X)                                                                            \
+    X(1, 1, 1, 1) X(1, 2, 2, 1) X(1, 3, 3, 1) X(1, 4, 4, 1) X(2, 1, 1, 1) X(2, 2, 2, 1) X(2, 3, 3, 1) \
+    X(0, 1, 1, 32) X(0, 2, 2, 32) X(0, 3, 3, 32) X(0, 4, 4, 32)                                       \
+    X(0, 1, 5, 1) X(0, 2, 5, 1) X(0, 3, 5, 1) X(0, 4, 5, 1) X(0, 5, 5, 1)                             \
+    X(0, 1, 5, 32) X(0, 2, 5, 32) X(0, 3, 5, 32) X(0, 4, 5, 32) X(0, 5, 5, 32)
+
+constexpr int VAR_KF = 5;
+
+// Calls `fn(K, KF, tables, list, count)` for every launch of the current mesh: one per degree
+// class on a mesh of variable degree, one for all elements otherwise.
+template <typename Fn>
+int for_each_class(hdg_ctx* c, Fn fn) {
+    if (!c->vardeg) return fn(c->k, c->k, c->tab, (const int32_t*)nullptr, c->n_elem);
+    for (int k = 1; k <= 5; ++k) {
+        if (c->cls_n[k] == 0) continue;
+        const int e = fn(k, VAR_KF, c->tabk[k], c->d_cls[k], c->cls_n[k]);
+        if (e) return e;
+    }
+    return 0;
 }
 
 template <typename T>
-int dispatch_gen_rec(hdg_ctx* c, const T* Sr, const T* Ef, const double* lam, double* u) {
-    const int P = c->physics, K = c->k, R = c->nrhs;
-#define HDG_CASE(PP, KK, RR) \
-    if (P == PP && K == KK && R == RR) return launch_gen_rec<PP, KK, RR, T>(c, Sr, Ef, lam, u);
-    HDG_GEN_CASES(HDG_CASE)
+int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
+    const int P = c->physics, R = c->nrhs;
+    return for_each_class(c, [&](int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n) {
+#define HDG_CASE(PP, KK, FF, RR) \
+    if (P == PP && K == KK && KF == FF && R == RR) return launch_gen<PP, KK, FF, RR, T>(c, a, f_loc, tb, el, n);
+        HDG_GEN_CASES(HDG_CASE)
 #undef HDG_CASE
-    return -1;
+        return -1;
+    });
+}
+
+template <typename T>
+int dispatch_gen_rec(hdg_ctx* c, const double* lam, double* u) {
+    const int P = c->physics, R = c->nrhs;
+    return for_each_class(c, [&](int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n) {
+#define HDG_CASE(PP, KK, FF, RR) \
+    if (P == PP && K == KK && KF == FF && R == RR) return launch_gen_rec<PP, KK, FF, RR, T>(c, tb, el, n, lam, u);
+        HDG_GEN_CASES(HDG_CASE)
+#undef HDG_CASE
+        return -1;
+    });
 }
 
 int dispatch_gen_ref(hdg_ctx* c, const double* u, const double* lam) {
-    const int P = c->physics, K = c->k, R = c->nrhs;
-#define HDG_CASE(PP, KK, RR) \
-    if (P == PP && K == KK && R == RR) return launch_gen_ref<PP, KK, RR, float>(c, u, lam);
-    HDG_GEN_CASES(HDG_CASE)
+    const int P = c->physics, R = c->nrhs;
+    return for_each_class(c, [&](int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n) {
+#define HDG_CASE(PP, KK, FF, RR) \
+    if (P == PP && K == KK && KF == FF && R == RR) return launch_gen_ref<PP, KK, FF, RR, float>(c, tb, el, n, u, lam);
+        HDG_GEN_CASES(HDG_CASE)
 #undef HDG_CASE
-    return -1;
+        return -1;
+    });
 }
 
 }  // namespace
@@ -860,23 +998,24 @@ int launch_refine_general(hdg_ctx* c, const double* u, const double* lam) {
     return dispatch_gen_ref(c, u, lam);
 }
 
-bool general_supported(int physics, int k, int nrhs) {
-#define HDG_CASE(PP, KK, RR) \
-    if (physics == PP && k == KK && nrhs == RR) return true;
+bool general_supported(int physics, int k, int kf, int nrhs) {
+#define HDG_CASE(PP, KK, FF, RR) \
+    if (physics == PP && k == KK && kf == FF && nrhs == RR) return true;
     HDG_GEN_CASES(HDG_CASE)
 #undef HDG_CASE
     return false;
 }
 
+int var_face_degree() { return VAR_KF; }
+
 int launch_condense_general(hdg_ctx* c, double a, const double* f_loc) {
-    if (c->precision == HDG_FP64)
-        return dispatch_gen<double>(c, a, f_loc, c->tab.Sr, c->tab.Mf, c->tab.Tfull, c->tab.Ef);
-    return dispatch_gen<float>(c, a, f_loc, c->tab.Sr32, c->tab.Mf32, c->tab.Tfull32, c->tab.Ef32);
+    if (c->precision == HDG_FP64) return dispatch_gen<double>(c, a, f_loc);
+    return dispatch_gen<float>(c, a, f_loc);
 }
 
 int launch_recover_general(hdg_ctx* c, const double* lam, double* u) {
-    if (c->precision == HDG_FP64) return dispatch_gen_rec<double>(c, c->tab.Sr, c->tab.Ef, lam, u);
-    return dispatch_gen_rec<float>(c, c->tab.Sr32, c->tab.Ef32, lam, u);
+    if (c->precision == HDG_FP64) return dispatch_gen_rec<double>(c, lam, u);
+    return dispatch_gen_rec<float>(c, lam, u);
 }
 
 }  // namespace hdg

@@ -98,6 +98,23 @@ struct hdg_ctx {
     int s_row0 = 0;            // first local row of that block
     int* d_status = nullptr;   // device status word (0 ok, 1 singular pivot)
 
+    // routing: the acoustic kernels of condense_acoustic.hip serve uniform degree with one
+    // right-hand side; every other configuration goes through the block-structured kernels
+    bool fast_ac = false;
+    // variable polynomial degree (acoustic, 3D): degree classes, compact local offsets, per-face
+    // sizes.  n_loc, N, Ns are then the strides of the largest class and NF, bs, n_tr those of
+    // the face tables (degree 5); faces of lower degree are padded.
+    bool vardeg = false;
+    size_t xscratch_bytes = 0;
+    std::vector<int64_t> loc_off_h;  // [ne + 1]
+    int64_t* d_loc_off = nullptr;
+    int8_t* d_efnf = nullptr;        // [ne][d+1] face space size of each local face
+    int8_t* d_face_nf = nullptr;     // [nf] face space size of each face
+    int8_t* d_edeg = nullptr;        // [ne] element degree
+    int64_t cls_n[6] = {0, 0, 0, 0, 0, 0};
+    int32_t* d_cls[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hdg::DeviceTables tabk[6];       // tables of each element degree (face tables of degree 5)
+
     // global trace system (FP64)
     double* d_bsr = nullptr;   // [nf][nslot][bs][bs]
     double* d_rhs = nullptr;   // [ntr][r]
@@ -155,7 +172,8 @@ int launch_lincomb(hdg_ctx* c, int64_t n, double a, const double* x, double b, c
                    double* out);
 int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out);
 // condense_general.hip (elastodynamics, Maxwell)
-bool general_supported(int physics, int k, int nrhs);
+bool general_supported(int physics, int k, int kf, int nrhs);
+int var_face_degree();   // face-table degree used on meshes of variable degree
 int launch_condense_general(hdg_ctx* c, double a, const double* f_loc);
 int launch_recover_general(hdg_ctx* c, const double* lam, double* u);
 int launch_refine_general(hdg_ctx* c, const double* u, const double* lam);

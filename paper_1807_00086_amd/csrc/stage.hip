@@ -6,6 +6,8 @@
 //   maxwell   diag(mu, mu, mu, eps, eps, eps)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace hdg {
@@ -54,9 +56,33 @@ __global__ __launch_bounds__(NT) void apply_mass_kernel(int64_t ne, int physics,
     }
     f[gid] = a * J * acc;
 }
+// acoustics on a mesh of variable degree: one workgroup per element, compact local layout
+__global__ __launch_bounds__(NT) void apply_mass_var_kernel(int64_t ne, int m, int R, double a,
+                                                            const double* __restrict__ geom,
+                                                            const int64_t* __restrict__ loc_off,
+                                                            const double* __restrict__ u, double* __restrict__ f) {
+    for (int64_t e = blockIdx.x; e < ne; e += gridDim.x) {
+        const double* g = geom + e * GEOM_STRIDE;
+        const double J = g[0];
+        const double* par = g + GEO_PAR;
+        const int64_t b0 = loc_off[e] * R, n = (loc_off[e + 1] - loc_off[e]) * R;
+        const int64_t Nr = n / m;   // basis functions x rhs per component
+        for (int64_t i = threadIdx.x; i < n; i += NT) {
+            const int comp = (int)(i / Nr);
+            const double w = (comp < m - 1) ? par[0] : 1.0 / (par[0] * par[1] * par[1]);
+            f[b0 + i] = a * J * w * u[b0 + i];
+        }
+    }
+}
 }  // namespace
 
 int launch_apply_mass(hdg_ctx* c, double a, const double* u, double* f) {
+    if (c->vardeg) {
+        const int grid = (int)std::min<int64_t>(c->n_elem, 65536);
+        hipLaunchKernelGGL(apply_mass_var_kernel, dim3(grid), dim3(NT), 0, c->stream, c->n_elem, c->m_local, c->nrhs,
+                           a, c->d_geom, c->d_loc_off, u, f);
+        return (int)hipGetLastError();
+    }
     int64_t n = c->n_elem * (int64_t)c->n_loc * c->nrhs;
     hipLaunchKernelGGL(apply_mass_kernel, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, c->stream, c->n_elem,
                        c->physics, c->m_local, c->N, c->nrhs, a, c->d_geom, u, f);

@@ -31,10 +31,14 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
     int64_t nf, int d, int bs, int tt, int R, double sign, int ktile, const int32_t* __restrict__ face_elem,
     const int32_t* __restrict__ face_lf, const uint8_t* __restrict__ face_bnd,
     const int32_t* __restrict__ eface, const T* __restrict__ Ke, const T* __restrict__ re,
-    const double* __restrict__ lam_bnd, double* __restrict__ bsr, double* __restrict__ rhs) {
+    const double* __restrict__ lam_bnd, const int8_t* __restrict__ face_nf, double* __restrict__ bsr,
+    double* __restrict__ rhs) {
+    // face_nf (variable degree): modes of a face at or above its own size are padding and get
+    // identity rows with a zero right-hand side
     const int nslot = 1 + 2 * d, nv = d + 1;
     for (int64_t F = blockIdx.x; F < nf; F += gridDim.x) {
         const bool bnd = face_bnd[F] != 0;
+        const int nfF = face_nf ? (int)face_nf[F] : bs;
         int32_t es[2] = {face_elem[2 * F], face_elem[2 * F + 1]};
         int32_t ls[2] = {face_lf[2 * F], face_lf[2 * F + 1]};
         double* B = bsr + (size_t)F * nslot * bs * bs;
@@ -43,7 +47,7 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
             int b = rem / bs, a = rem % bs;   // column-major block
             double v = 0.0;
             if (slot == 0) {
-                if (bnd) {
+                if (bnd || a >= nfF || b >= nfF) {
                     v = (a == b) ? 1.0 : 0.0;
                 } else {
                     for (int s = 0; s < 2; ++s) {
@@ -59,7 +63,9 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
                     int lf = ls[s];
                     int q = (m < lf) ? m : m + 1;
                     int32_t F2 = eface[(size_t)e * nv + q];
-                    if (!face_bnd[F2]) v = sign * kget(Ke + (size_t)e * tt * tt, tt, lf * bs + a, q * bs + b, ktile);
+                    const int nf2 = face_nf ? (int)face_nf[F2] : bs;
+                    if (!face_bnd[F2] && a < nfF && b < nf2)
+                        v = sign * kget(Ke + (size_t)e * tt * tt, tt, lf * bs + a, q * bs + b, ktile);
                 }
             }
             B[idx] = v;
@@ -68,7 +74,9 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
             int a = idx / R, r = idx % R;
             double v;
             if (bnd) {
-                v = lam_bnd[((size_t)F * bs + a) * R + r];
+                v = a < nfF ? lam_bnd[((size_t)F * bs + a) * R + r] : 0.0;
+            } else if (a >= nfF) {
+                v = 0.0;
             } else {
                 v = 0.0;
                 for (int s = 0; s < 2; ++s) {
@@ -80,7 +88,8 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
                         if (q == lf) continue;
                         int32_t F2 = eface[(size_t)e * nv + q];
                         if (!face_bnd[F2]) continue;
-                        for (int b = 0; b < bs; ++b)
+                        const int nf2 = face_nf ? (int)face_nf[F2] : bs;
+                        for (int b = 0; b < nf2; ++b)
                             acc -= kget(K, tt, lf * bs + a, q * bs + b, ktile) *
                                    lam_bnd[((size_t)F2 * bs + b) * R + r];
                     }
@@ -295,13 +304,13 @@ int launch_assemble(hdg_ctx* c, const double* lam_bnd) {
     if (c->precision == HDG_FP64)
         hipLaunchKernelGGL((assemble_kernel<double>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
                            c->bs, c->n_tr, c->nrhs, c->K_sign, c->ke_tile, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
-                           c->d_eface, (const double*)c->d_Ke, (const double*)c->d_re, lam_bnd, c->d_bsr,
-                           c->d_rhs);
+                           c->d_eface, (const double*)c->d_Ke, (const double*)c->d_re, lam_bnd, c->d_face_nf,
+                           c->d_bsr, c->d_rhs);
     else
         hipLaunchKernelGGL((assemble_kernel<float>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
                            c->bs, c->n_tr, c->nrhs, c->K_sign, c->ke_tile, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
-                           c->d_eface, (const float*)c->d_Ke, (const float*)c->d_re, lam_bnd, c->d_bsr,
-                           c->d_rhs);
+                           c->d_eface, (const float*)c->d_Ke, (const float*)c->d_re, lam_bnd, c->d_face_nf,
+                           c->d_bsr, c->d_rhs);
     return (int)hipGetLastError();
 }
 

@@ -139,3 +139,20 @@ def test_rejects_bad_arguments():
     assert lib.hdg_condense(None, 1.0, None, None) == 1
     lib.hdg_destroy(None)
     assert lib.hdg_reference_table(4, 1, 1, 0, None, 0) < 0
+
+
+def test_variable_degree_scope():
+    # variable polynomial degree is built for 3D acoustics; other physics or 2D meshes are
+    # refused before any device work
+    p2 = make_problem(1, n=2)
+    deg2 = (np.arange(p2.n_elem) % 3 + 1).astype(np.int8)
+    st, msg = _init(p2.xyz, p2.elem_vert, degree=deg2)
+    assert st == 8 and "3D acoustics" in msg
+    p3 = make_problem(3, n=1, k=1)
+    deg3 = (np.arange(p3.n_elem) % 2 + 1).astype(np.int8)
+    st, msg = _init(p3.xyz, p3.elem_vert, physics="elastic", degree=deg3)
+    assert st == 8 and "3D acoustics" in msg
+    deg_bad = deg3.copy()
+    deg_bad[0] = 6
+    st, msg = _init(p3.xyz, p3.elem_vert, degree=deg_bad)
+    assert st == 2 and "degree" in msg
