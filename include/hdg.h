@@ -28,6 +28,11 @@
  *      acoustic [v_1..v_d, p];  elastic [s11,s22,s33,s23,s13,s12, v_1,v_2,v_3];
  *      maxwell [H_1,H_2,H_3, E_1,E_2,E_3].
  *  - Trace dofs: face-major, then component, then face basis index, then rhs.
+ *    On a mesh of variable degree the face degree is the larger degree of the face's
+ *    elements (the element's own degree on the boundary), and every face is padded to the
+ *    face space of degree 5 (21 entries per rhs; entries past the face's own space are
+ *    zero on output and ignored on input).  Local dofs stay compact: element e starts at
+ *    the prefix sum of (d+1) dim P_{k_e} over the elements before it.
  *    Maxwell trace components are coefficients along the face frame (t1, t2):
  *    t1 = unit(X_g1 - X_g0), t2 = n_F x t1, n_F = unit((X_g1-X_g0) x (X_g2-X_g0)).
  *  - Device pointers are borrowed for the duration of the call (stream-ordered on the
@@ -72,7 +77,8 @@ typedef struct {
     const double* xyz;          /* host [n_vert][dim]                                         */
     int64_t n_elem;
     const int64_t* elem_vert;   /* host [n_elem][dim+1], positively oriented                  */
-    const int8_t* degree;       /* host [n_elem] polynomial degree (1..5); NULL: options.k     */
+    const int8_t* degree;       /* host [n_elem] polynomial degree (1..5); NULL: options.k.
+                                   Degrees that differ between elements: 3D acoustics only  */
 } hdg_mesh_desc;
 
 typedef struct {
@@ -119,6 +125,12 @@ enum hdg_query_key {
  * fails with HDG_E_MESH / HDG_E_ARG before any device work.  `stream` is a hipStream_t
  * (NULL: the default stream); every later call is ordered on it.  Faces with one
  * neighbour are Dirichlet faces.
+ * Built configurations (others return HDG_E_UNSUPPORTED before any device work):
+ *   acoustics 2D/3D, uniform k = 1..4, nrhs = 1; acoustics 3D, uniform k = 1..4, nrhs = 32;
+ *   acoustics 3D of variable degree (k_e in 1..5, face degree = the larger neighbour's),
+ *   nrhs = 1 or 32; elastodynamics 3D, k = 1..4; Maxwell 3D, k = 1..3 (nrhs = 1).
+ * On a mesh of variable degree the projection helpers (hdg_volume_points and siblings)
+ * return HDG_E_UNSUPPORTED; hdg_point_sources and hdg_apply_mass work on it.
  */
 hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* mesh, const hdg_phys_desc* phys,
                          const hdg_options* opts, void* stream);
