@@ -120,7 +120,7 @@ def cpu_baseline(problem, a, budget_s=15.0):
                        f"{el:.1f} s, 1 BLAS thread, per-element form+factor+Schur+recover")
 
 
-def run_precision(p, prec, steps, warmup, keep_solution=False):
+def run_precision(p, prec, steps, warmup, keep_solution=False, refine_tol=1e-11):
     """Time `steps` whole stages in one precision; returns timings and (optionally) the
     final stage solution on the host."""
     import torch
@@ -128,7 +128,7 @@ def run_precision(p, prec, steps, warmup, keep_solution=False):
     from paper_1807_00086_amd import Solver
     k = int(p.degree[0])
     a = 1.0 / (GAMMA * p.dt)
-    kw = dict(krylov_tol=1e-13) if prec == "fp64" else dict(krylov_tol=1e-8, refine_tol=1e-12)
+    kw = dict(krylov_tol=1e-13) if prec == "fp64" else dict(krylov_tol=1e-8, refine_tol=refine_tol)
     s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=k, precision=prec, **kw)
     nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
     # inputs: projected plane wave p0 = sin(2 pi x), v0 = (p0, 0, 0); Dirichlet p = sin 2pi(x - t)
@@ -183,6 +183,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed_fp32"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--refine-tol", type=float, default=1e-11,
+                    help="mixed precision: refinement stopping tolerance (the result is checked "
+                         "against FP64 to 1e-10 before mixed can be the headline)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -212,7 +215,8 @@ def main():
     k = int(p.degree[0])
     a = 1.0 / (GAMMA * p.dt)
     precs = ["fp64", "mixed_fp32"] if args.precision == "both" else [args.precision]
-    res = {pr: run_precision(p, pr, args.steps, args.warmup, keep_solution=(len(precs) == 2))
+    res = {pr: run_precision(p, pr, args.steps, args.warmup, keep_solution=(len(precs) == 2),
+                             refine_tol=args.refine_tol)
            for pr in precs}
 
     def elem_rate(r):
