@@ -545,17 +545,12 @@ struct RfScratch {
     static constexpr bool SHE = rf_shared_faces<D, K>();
     double geo[GEOM_STRIDE];
     double lm[TT * R];            // lam_e
-    double dl[TT * R];            // dlam_e
     double uo[NLOC * R];          // u_e on entry
     double ff[NLOC * R];          // f_e
-    double pp[N * R];             // p
     double ef[NFACE * N * R];     // E_f lam_f
-    double yp[D * N * R];         // Sr_r^T p ; later sum_x G_rx v_x
+    double yp[D * N * R];         // Sr_r^T p
     double vv[D * N * R];         // v
-    double ep[TT * R];            // lam - E_f^T p
     double nv[NFACE * N * R];     // n_f . v
-    double sp[N * R];             // s_p
-    double te[TT * R];            // t_e
     double El[SHE ? 1 : NFACE * N * NF];
     T Zl[N * TT];
     T zb[N * R];                  // z'_p on entry
@@ -569,6 +564,23 @@ template <int M>
 struct PerLane {
     static constexpr int n = (M + 63) / 64;
 };
+
+// sum_{j < L} term(j) with four independent accumulators (FP64 FMA chains of a quarter of the
+// length; the summation order is fixed)
+template <int L, typename F>
+__device__ __forceinline__ double dot4(F term) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+    for (int j = 0; j + 3 < L; j += 4) {
+        a0 += term(j);
+        a1 += term(j + 1);
+        a2 += term(j + 2);
+        a3 += term(j + 3);
+    }
+#pragma unroll
+    for (int j = L & ~3; j < L; ++j) a0 += term(j);
+    return (a0 + a1) + (a2 + a3);
+}
 
 template <int D, int K, int R, typename T, int WPB, bool RESID>
 __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
@@ -585,6 +597,8 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
     constexpr int PT = PerLane<TT * R>::n, PE = SHE ? 0 : PerLane<NEL>::n, PZ = PerLane<NZ>::n;
     constexpr int PB = PerLane<N * R>::n, PU = PerLane<NLOC * R>::n, PL = PerLane<NLL>::n;
     using Scr = RfScratch<D, K, R, T, RESID>;
+    constexpr int SDN = PerLane<D * N>::n;
+    static_assert(R == 1 && TT <= 64 && N <= 64, "one right-hand side; trace and Schur vectors fit a wavefront");
     __shared__ double Srs[D * N * N];
     __shared__ double Efs[SHE ? NFACE * NPERM * N * NF : 1];
     __shared__ Scr scr_all[WPB];
@@ -655,10 +669,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
         if (lane < GEOM_STRIDE) sc.geo[lane] = rgeo;
 #pragma unroll
         for (int t = 0; t < PT; ++t)
-            if (lane + 64 * t < TT * R) {
-                sc.lm[lane + 64 * t] = rlm[t];
-                sc.dl[lane + 64 * t] = rdl[t];
-            }
+            if (lane + 64 * t < TT * R) sc.lm[lane + 64 * t] = rlm[t];
         if (!SHE)
 #pragma unroll
             for (int t = 0; t < PE; ++t)
@@ -689,6 +700,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
     }
     for (int it = 0; e < ne; e += stride, ++it) {
         commit();
+        const double lmv = rlm[0], dlv = rdl[0];   // lam_e, dlam_e: entry c in lane c
         if (lane < 8) sc.fc[lane] = sc.fq[it & 31][lane];
         const int kn = (it + 1) & 31;
         if (kn == 0) load_faces(e + stride);
@@ -698,191 +710,129 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
         auto Eface = [&](int fc) -> const double* {
             return SHE ? &Efs[(fc * NPERM + sc.fc[4 + fc]) * N * NF] : &sc.El[fc * N * NF];
         };
-        double* ue = u + (size_t)e * NLOC * R;
+        double* ue = u + (size_t)e * NLOC;
         const double J = g[0];
         const double rho = g[GEO_PAR], cc = g[GEO_PAR + 1], tau = g[GEO_STAB];
         const double inv_av = 1.0 / (a * rho * J), alpha_p = a * J / (rho * cc * cc);
         double dn = 0.0, un = 0.0;
-        // ---- p = p_prev + z'_p - Z_p dlam ; E_f lam_f
-#pragma unroll
-        for (int t = 0; t < PerLane<N * R>::n; ++t) {
-            const int idx = lane + 64 * t;
-            if (idx < N * R) {
-                const int i = idx / R, q = idx % R;
-                double s = 0.0;
-                if (mode != 2) {
-                    s = (double)sc.zb[idx];
-#pragma unroll 8
-                    for (int c = 0; c < TT; ++c) s -= (double)sc.Zl[i * TT + c] * sc.dl[c * R + q];
-                }
-                const double p = sc.uo[D * N * R + idx] + s;
-                sc.pp[idx] = p;
-                ue[D * N * R + idx] = p;
+        // Vectors that a phase needs whole (p, G v, lam - E^T p, s_p, L^{-1} s_p) stay in
+        // registers, entry m in lane m % 64 of slot m / 64, and reach the other lanes by readlane;
+        // only the lane-varying operands (reference tables, Z_p, L^{-1}) are read from LDS.
+        // Phases that broadcast by readlane run in uniform control flow (every lane computes,
+        // with clamped indices; only the stores are masked), so the source lanes are active.
+        const int il = min(lane, N - 1), al = min(lane, TT - 1);
+        // ---- p = p_prev + z'_p - Z_p dlam (lane i) ; E_f lam_f
+        double pv;
+        {
+            double s = 0.0;
+            if (mode != 2)
+                s = (double)sc.zb[il] - dot4<TT>([&](int c) { return (double)sc.Zl[il * TT + c] * bcast(dlv, c); });
+            pv = sc.uo[D * N + il] + s;
+            if (lane < N) {
+                ue[D * N + lane] = pv;
                 dn += s * s;
-                un += p * p;
+                un += pv * pv;
             }
         }
 #pragma unroll
-        for (int t = 0; t < PerLane<NFACE * N * R>::n; ++t) {
+        for (int t = 0; t < PerLane<NFACE * N>::n; ++t) {
             const int idx = lane + 64 * t;
-            if (idx < NFACE * N * R) {
-                const int fc = idx / (N * R), i = (idx / R) % N, q = idx % R;
+            if (idx < NFACE * N) {
+                const int fc = idx / N, i = idx - fc * N;
                 const double* Er = Eface(fc) + i * NF;
-                double s = 0.0;
-#pragma unroll
-                for (int l = 0; l < NF; ++l) s += Er[l] * sc.lm[(fc * NF + l) * R + q];
-                sc.ef[idx] = s;
+                sc.ef[idx] = dot4<NF>([&](int l) { return Er[l] * sc.lm[fc * NF + l]; });
             }
         }
-        wsync();
         // ---- Sr_r^T p ; lam - E_f^T p
 #pragma unroll
-        for (int t = 0; t < PerLane<D * N * R>::n; ++t) {
-            const int idx = lane + 64 * t;
-            if (idx < D * N * R) {
-                const int r = idx / (N * R), i = (idx / R) % N, q = idx % R;
-                double s = 0.0;
-#pragma unroll
-                for (int j = 0; j < N; ++j) s += Srs[(r * N + j) * N + i] * sc.pp[j * R + q];
-                sc.yp[idx] = s;
-            }
+        for (int t = 0; t < SDN; ++t) {
+            const int idx = min(lane + 64 * t, D * N - 1);
+            const int r = idx / N, i = idx - r * N;
+            const double y = dot4<N>([&](int j) { return Srs[(r * N + j) * N + i] * bcast(pv, j); });
+            if (lane + 64 * t < D * N) sc.yp[idx] = y;
         }
-        if (RESID)
-#pragma unroll
-            for (int t = 0; t < PerLane<TT * R>::n; ++t) {
-                const int idx = lane + 64 * t;
-                if (idx < TT * R) {
-                    const int aa = idx / R, q = idx % R, fc = aa / NF, l = aa % NF;
-                    const double* Ec = Eface(fc) + l;
-                    double s = 0.0;
-#pragma unroll
-                    for (int i = 0; i < N; ++i) s += Ec[i * NF] * sc.pp[i * R + q];
-                    sc.ep[idx] = sc.lm[idx] - s;
-                }
-            }
+        double epv = 0.0;
+        if (RESID) {
+            const int fc = al / NF, l = al - fc * NF;
+            const double* Ec = Eface(fc) + l;
+            epv = lmv - dot4<N>([&](int i) { return Ec[i * NF] * bcast(pv, i); });
+        }
         wsync();
         // ---- v in closed form
 #pragma unroll
-        for (int t = 0; t < PerLane<D * N * R>::n; ++t) {
+        for (int t = 0; t < SDN; ++t) {
             const int idx = lane + 64 * t;
-            if (idx < D * N * R) {
-                const int x = idx / (N * R), iq = idx - x * N * R;
+            if (idx < D * N) {
+                const int x = idx / N, i = idx - x * N;
                 double s = f ? sc.ff[idx] : 0.0;
 #pragma unroll
-                for (int r = 0; r < D; ++r) s += J * g[1 + r * D + x] * sc.yp[r * N * R + iq];
+                for (int r = 0; r < D; ++r) s += J * g[1 + r * D + x] * sc.yp[r * N + i];
 #pragma unroll
                 for (int fc = 0; fc < NFACE; ++fc)
-                    s -= g[1 + D * D + NFACE + fc * D + x] * g[1 + D * D + fc] * sc.ef[fc * N * R + iq];
+                    s -= g[1 + D * D + NFACE + fc * D + x] * g[1 + D * D + fc] * sc.ef[fc * N + i];
                 const double v = f ? s * inv_av : sc.ff[idx] + s * inv_av;
                 sc.vv[idx] = v;
-                const double d = v - sc.uo[idx];
-                dn += d * d;
+                const double dd = v - sc.uo[idx];
+                dn += dd * dd;
                 un += v * v;
                 ue[idx] = v;
             }
         }
         if (RESID) {
             wsync();
-            // ---- G v (over Sr^T p, no longer needed) ; n_f . v
+            // ---- G v (registers) ; n_f . v
+            double gvv[SDN];
 #pragma unroll
-            for (int t = 0; t < PerLane<D * N * R>::n; ++t) {
-                const int idx = lane + 64 * t;
-                if (idx < D * N * R) {
-                    const int r = idx / (N * R), iq = idx - r * N * R;
-                    double s = 0.0;
+            for (int t = 0; t < SDN; ++t) {
+                const int idx = min(lane + 64 * t, D * N - 1);
+                const int r = idx / N, i = idx - r * N;
+                double s = 0.0;
 #pragma unroll
-                    for (int x = 0; x < D; ++x) s += g[1 + r * D + x] * sc.vv[x * N * R + iq];
-                    sc.yp[idx] = s;
-                }
+                for (int x = 0; x < D; ++x) s += g[1 + r * D + x] * sc.vv[x * N + i];
+                gvv[t] = s;
             }
 #pragma unroll
-            for (int t = 0; t < PerLane<NFACE * N * R>::n; ++t) {
+            for (int t = 0; t < PerLane<NFACE * N>::n; ++t) {
                 const int idx = lane + 64 * t;
-                if (idx < NFACE * N * R) {
-                    const int fc = idx / (N * R), iq = idx - fc * N * R;
+                if (idx < NFACE * N) {
+                    const int fc = idx / N, i = idx - fc * N;
                     double s = 0.0;
 #pragma unroll
-                    for (int x = 0; x < D; ++x) s += g[1 + D * D + NFACE + fc * D + x] * sc.vv[x * N * R + iq];
+                    for (int x = 0; x < D; ++x) s += g[1 + D * D + NFACE + fc * D + x] * sc.vv[x * N + i];
                     sc.nv[idx] = s;
                 }
             }
             wsync();
-            // ---- s_p ; t_e
-#pragma unroll
-            for (int t = 0; t < PerLane<N * R>::n; ++t) {
-                const int idx = lane + 64 * t;
-                if (idx < N * R) {
-                    const int i = idx / R, q = idx % R;
-                    double qv = 0.0;
-#pragma unroll
-                    for (int r = 0; r < D; ++r) {
-                        const double* Srow = &Srs[(r * N + i) * N];
-#pragma unroll
-                        for (int j = 0; j < N; ++j) qv += Srow[j] * sc.yp[(r * N + j) * R + q];
-                    }
-                    double fe = 0.0;
-#pragma unroll
-                    for (int fc = 0; fc < NFACE; ++fc) {
-                        const double* Er = Eface(fc) + i * NF;
-                        double s = 0.0;
-#pragma unroll
-                        for (int l = 0; l < NF; ++l) s += Er[l] * sc.ep[(fc * NF + l) * R + q];
-                        fe += g[1 + D * D + fc] * s;
-                    }
-                    sc.sp[idx] = sc.ff[D * N * R + idx] - J * qv - alpha_p * sc.pp[idx] + tau * fe;
-                }
+            // ---- s_p (lane i) ; t_e (lane a)
+            double spv;
+            {
+                const int i = il;
+                const double qv = dot4<D * N>([&](int rj) {
+                    const int r = rj / N, j = rj - r * N;
+                    return Srs[(r * N + i) * N + j] * bcast(gvv[rj / 64], rj % 64);
+                });
+                const double fe = dot4<NFACE * NF>([&](int fl) {
+                    const int fc = fl / NF, l = fl - fc * NF;
+                    return g[1 + D * D + fc] * Eface(fc)[i * NF + l] * bcast(epv, fl);
+                });
+                spv = sc.ff[D * N + i] - J * qv - alpha_p * pv + tau * fe;
             }
-#pragma unroll
-            for (int t = 0; t < PerLane<TT * R>::n; ++t) {
-                const int idx = lane + 64 * t;
-                if (idx < TT * R) {
-                    const int aa = idx / R, q = idx % R, fc = aa / NF, l = aa % NF;
-                    const double* Ec = Eface(fc) + l;
-                    double s = 0.0;
-#pragma unroll
-                    for (int i = 0; i < N; ++i) s += Ec[i * NF] * sc.nv[(fc * N + i) * R + q];
-                    sc.te[idx] = g[1 + D * D + fc] * (s - tau * sc.ep[idx]);
-                }
+            double tev;
+            {
+                const int fc = al / NF, l = al - fc * NF;
+                const double* Ec = Eface(fc) + l;
+                const double s = dot4<N>([&](int i) { return Ec[i * NF] * sc.nv[fc * N + i]; });
+                tev = g[1 + D * D + fc] * (s - tau * epv);
             }
-            wsync();
-            // ---- re64 = Z_p^T s_p - t_e
-#pragma unroll
-            for (int t = 0; t < PerLane<TT * R>::n; ++t) {
-                const int idx = lane + 64 * t;
-                if (idx < TT * R) {
-                    const int aa = idx / R, q = idx % R;
-                    double s = 0.0;
-#pragma unroll
-                    for (int i = 0; i < N; ++i) s += (double)sc.Zl[i * TT + aa] * sc.sp[i * R + q];
-                    re64[(size_t)e * TT * R + idx] = s - sc.te[idx];
-                }
+            // ---- re64 = Z_p^T s_p - t_e ; z'_p = L^{-T} (L^{-1} s_p)
+            {
+                const double s = dot4<N>([&](int i) { return (double)sc.Zl[i * TT + al] * bcast(spv, i); });
+                if (lane < TT) re64[(size_t)e * TT + lane] = s - tev;
             }
-            // ---- z'_p = L^{-T} (L^{-1} s_p) with the stored inverse factor (two triangular
-            // matrix-vector products; p is no longer needed, its buffer takes L^{-1} s_p)
-#pragma unroll
-            for (int t = 0; t < PerLane<N * R>::n; ++t) {
-                const int idx = lane + 64 * t;
-                if (idx < N * R) {
-                    const int i = idx / R, q = idx % R;
-                    double s = 0.0;
-#pragma unroll
-                    for (int m = 0; m < N; ++m) s += (double)sc.Ll[i * N + m] * sc.sp[m * R + q];
-                    sc.pp[idx] = s;
-                }
-            }
-            wsync();
-            T* zbe = zb + (size_t)e * NLOC * R + D * N * R;
-#pragma unroll
-            for (int t = 0; t < PerLane<N * R>::n; ++t) {
-                const int idx = lane + 64 * t;
-                if (idx < N * R) {
-                    const int i = idx / R, q = idx % R;
-                    double s = 0.0;
-#pragma unroll
-                    for (int m = 0; m < N; ++m) s += (double)sc.Ll[m * N + i] * sc.pp[m * R + q];
-                    zbe[idx] = (T)s;
-                }
-            }
+            const double yv = dot4<N>([&](int m) { return (double)sc.Ll[il * N + m] * bcast(spv, m); });
+            const double zv = dot4<N>([&](int m) { return (double)sc.Ll[m * N + il] * bcast(yv, m); });
+            T* zbe = zb + (size_t)e * NLOC + D * N;
+            if (lane < N) zbe[lane] = (T)zv;
         }
         // ---- per-element norms of the correction and of u
         if (nrm) {
