@@ -107,7 +107,7 @@ bool supported(hdg_ctx* c) {
 }
 
 int launch_recover_any(hdg_ctx* c, const double* lam, double* u) {
-    return c->fast_ac ? launch_recover(c, lam, u, false) : launch_recover_general(c, lam, u);
+    return c->fast_ac ? launch_refine_acoustic(c, lam, lam, 1, false, u, nullptr) : launch_recover_general(c, lam, u);
 }
 
 

@@ -89,18 +89,45 @@ struct AcDims {
     static constexpr int NPAIR = D * (D + 1) / 2;
 };
 
-// per-wavefront LDS scratch
-template <int D, int K, int R, typename T>
+// per-wavefront LDS scratch (SHE: the oriented face tables are read from the workgroup's copy
+// of all orientations instead of being gathered per element)
+template <int D, int K, int R, typename T, bool SHE>
 struct AcScratch {
     using Dm = AcDims<D, K, R>;
     static constexpr int NST = (Dm::N * Dm::N > Dm::NFACE * Dm::N * R) ? Dm::N * Dm::N : Dm::NFACE * Dm::N * R;
-    T Sb[NST];                           // S; staging of G f_v and n.f_v
-    T X[Dm::N * Dm::C];                  // [B~ | f~] -> [W | w]
-    T El[Dm::NFACE * Dm::N * Dm::NF];    // oriented face tables of the element
-    T FV[D * Dm::N * R];                 // velocity right-hand side
-    T cf[Dm::NFACE * Dm::NFACE];         // s_f s_g (n_f . n_g) / (a rho |J|)
-    T dv[Dm::N];                         // inverse pivots
+    T Sb[NST];                                   // S; staging of G f_v and n.f_v
+    T X[Dm::N * Dm::C];                          // [B~ | f~] -> [W | w]
+    T El[SHE ? 1 : Dm::NFACE * Dm::N * Dm::NF];  // oriented face tables of the element
+    T FV[D * Dm::N * R];                         // velocity right-hand side
+    T cf[Dm::NFACE * Dm::NFACE];                 // s_f s_g (n_f . n_g) / (a rho |J|)
+    T dv[Dm::N];                                 // inverse pivots
     double geo[GEOM_STRIDE];
+    int pf[Dm::NFACE];                           // orientation of each face
+};
+
+// LDS plan of the condensation kernel.  Target occupancy: three wavefronts per SIMD in FP32,
+// two in FP64 (the register budgets of the two instantiations).  The reference face tables of
+// all orientations are shared by the workgroup when they fit at that occupancy, with four
+// wavefronts per workgroup or, failing that, eight; otherwise every wavefront gathers the
+// oriented tables of its element and the workgroup holds as many wavefronts (at most four) as
+// fit two workgroups per CU.
+template <int D, int K, int R, typename T, bool SHE>
+constexpr int ac_block_lds(int wpb) {
+    using Dm = AcDims<D, K, R>;
+    return (int)((D * Dm::N * Dm::N + (SHE ? Dm::NFACE * Dm::NPERM * Dm::N * Dm::NF : 0)) * sizeof(T) +
+                 wpb * sizeof(AcScratch<D, K, R, T, SHE>));
+}
+template <int D, int K, int R, typename T>
+struct AcPlan {
+    static constexpr int LDS = 160 * 1024;
+    static constexpr int WAVES = sizeof(T) == 4 ? 12 : 8;   // per CU
+    static constexpr bool S4 = (WAVES / 4) * ac_block_lds<D, K, R, T, true>(4) <= LDS;
+    static constexpr bool S8 = WAVES % 8 == 0 && ac_block_lds<D, K, R, T, true>(8) <= LDS;
+    static constexpr bool SHE = S4 || S8;
+    static constexpr int WPB_G = (4 * (int)sizeof(AcScratch<D, K, R, T, false>) + D * dimp(K, D) * dimp(K, D) * (int)sizeof(T) <= 80 * 1024) ? 4
+                                 : (2 * (int)sizeof(AcScratch<D, K, R, T, false>) + D * dimp(K, D) * dimp(K, D) * (int)sizeof(T) <= 80 * 1024) ? 2 : 1;
+    static constexpr int WPB = S4 ? 4 : (S8 ? 8 : WPB_G);
+    static constexpr int MINB = SHE ? WAVES / WPB : (sizeof(T) == 4 ? 3 : 2);
 };
 
 // Broadcast of lane `src`'s value (src a compile-time constant after unrolling).
@@ -114,8 +141,8 @@ __device__ __forceinline__ float bcast(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
-template <int D, int K, int R, typename T, int WPB>
-__global__ __launch_bounds__(64 * WPB, sizeof(T) == 4 ? 3 : 2) void condense_acoustic_kernel(
+template <int D, int K, int R, typename T, int WPB, bool SHE, int MINB>
+__global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
     int64_t ne, double a_in, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
     const T* __restrict__ Sr, const T* __restrict__ Mf, const T* __restrict__ Tsym,
     const T* __restrict__ Ef, const double* __restrict__ f_loc, T* __restrict__ Ke,
@@ -136,13 +163,16 @@ __global__ __launch_bounds__(64 * WPB, sizeof(T) == 4 ? 3 : 2) void condense_aco
     static_assert(N <= 64, "pivot columns must sit in the first register slot");
 
     __shared__ T Srs[D * N * N];
-    __shared__ AcScratch<D, K, R, T> scr_all[WPB];
+    __shared__ T Efs[SHE ? NFACE * NPERM * N * NF : 1];
+    __shared__ AcScratch<D, K, R, T, SHE> scr_all[WPB];
 
     for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
+    if (SHE)
+        for (int idx = threadIdx.x; idx < NFACE * NPERM * N * NF; idx += 64 * WPB) Efs[idx] = Ef[idx];
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    AcScratch<D, K, R, T>& sc = scr_all[wave];
+    AcScratch<D, K, R, T, SHE>& sc = scr_all[wave];
     T* Sb = sc.Sb;
     T* X = sc.X;
     T* El = sc.El;
@@ -150,18 +180,45 @@ __global__ __launch_bounds__(64 * WPB, sizeof(T) == 4 ? 3 : 2) void condense_aco
     const T a = (T)a_in;
     const int lc = lane & 15, lk = lane >> 4;
 
-    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
+    // Inputs of the next element (geometry record, face orientations, right-hand side) are
+    // loaded into registers while the current one is condensed.
+    constexpr int PF = (NLOC * R + 63) / 64;
+    const int64_t stride = (int64_t)gridDim.x * WPB;
+    double rgeo = 0.0, rf[PF];
+    int rperm = 0;
+    auto issue = [&](int64_t en) {
+        if (lane < GEOM_STRIDE) rgeo = geom[en * GEOM_STRIDE + lane];
+        if (lane < NFACE) rperm = eperm[en * NFACE + lane];
+        const double* fe = f_loc + (size_t)en * NLOC * R;
+#pragma unroll
+        for (int t = 0; t < PF; ++t) rf[t] = fe[min(lane + 64 * t, NLOC * R - 1)];
+    };
+    int64_t e = (int64_t)blockIdx.x * WPB + wave;
+    if (e < ne) issue(e);
+    for (; e < ne; e += stride) {
         // ------------------------------------------------------------ load
-        if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
-        for (int idx = lane; idx < NFACE * N * NF; idx += 64) {
-            const int f = idx / (N * NF);
-            const int p = eperm[e * NFACE + f];
-            El[idx] = Ef[(size_t)(f * NPERM + p) * N * NF + (idx - f * N * NF)];
+        if (lane < GEOM_STRIDE) sc.geo[lane] = rgeo;
+        if (lane < NFACE) sc.pf[lane] = rperm;
+#pragma unroll
+        for (int t = 0; t < PF; ++t) {
+            const int idx = lane + 64 * t;
+            if (idx < D * N * R) FV[idx] = (T)rf[t];
+            else if (idx < NLOC * R) {
+                const int j = idx - D * N * R;
+                X[(j / R) * C + TT + j % R] = (T)rf[t];
+            }
         }
-        const double* fe = f_loc + (size_t)e * NLOC * R;
-        for (int idx = lane; idx < D * N * R; idx += 64) FV[idx] = (T)fe[idx];
-        for (int idx = lane; idx < N * R; idx += 64) X[(idx / R) * C + TT + idx % R] = (T)fe[D * N * R + idx];
         wsync();
+        if (!SHE) {
+            for (int idx = lane; idx < NFACE * N * NF; idx += 64) {
+                const int f = idx / (N * NF);
+                El[idx] = Ef[(size_t)(f * NPERM + sc.pf[f]) * N * NF + (idx - f * N * NF)];
+            }
+            wsync();
+        }
+        if (e + stride < ne) issue(e + stride);
+        // oriented face table of local face f (row-major N x NF)
+        auto EF = [&](int f) -> const T* { return SHE ? &Efs[(f * NPERM + sc.pf[f]) * N * NF] : &El[f * N * NF]; };
 
         const T J = (T)sc.geo[0];
         T G[D][D], sf[NFACE], nf[NFACE][D];
@@ -231,7 +288,7 @@ __global__ __launch_bounds__(64 * WPB, sizeof(T) == 4 ? 3 : 2) void condense_aco
                         T av = dg;
 #pragma unroll
                         for (int r = 0; r < D; ++r) av += beta[f][r] * sv[r];
-                        const T bv = bok ? El[(f * N + k) * NF + lc] : T(0);
+                        const T bv = bok ? EF(f)[k * NF + lc] : T(0);
                         acc[f] = MF::mac(av, bv, acc[f]);
                     }
                 }
@@ -386,11 +443,13 @@ __global__ __launch_bounds__(64 * WPB, sizeof(T) == 4 ? 3 : 2) void condense_aco
                 const int am = ta * 16 + lc;                       // this lane's A row
                 const bool aok = am < TT;
                 const int fam = aok ? am / NF : 0, lam_ = aok ? am % NF : 0;
+                const T* Ea = EF(fam) + lam_;
 #pragma unroll 1
                 for (int tb = ta; tb < TA; ++tb) {
                     const int bn = tb * 16 + lc;                   // this lane's B column
                     const bool bok = bn < TT;
                     const int fbn = bok ? bn / NF : 0, lbn = bok ? bn % NF : 0;
+                    const T* Eb = EF(fbn) + lbn;
                     typename MF::acc ww = MF::zero(), ee = MF::zero();
 #pragma unroll
                     for (int tk = 0; tk < TK; ++tk) {
@@ -398,8 +457,8 @@ __global__ __launch_bounds__(64 * WPB, sizeof(T) == 4 ? 3 : 2) void condense_aco
                         const bool kok = k < N;
                         const T xa = (aok && kok) ? X[k * C + am] : T(0);
                         const T xb = (bok && kok) ? X[k * C + bn] : T(0);
-                        const T ea = (aok && kok) ? El[(fam * N + k) * NF + lam_] : T(0);
-                        const T eb = (bok && kok) ? El[(fbn * N + k) * NF + lbn] : T(0);
+                        const T ea = (aok && kok) ? Ea[k * NF] : T(0);
+                        const T eb = (bok && kok) ? Eb[k * NF] : T(0);
                         ww = MF::mac(xa, xb, ww);
                         ee = MF::mac(ea, eb, ee);
                     }
@@ -434,77 +493,14 @@ __global__ __launch_bounds__(64 * WPB, sizeof(T) == 4 ? 3 : 2) void condense_aco
                 const int aa = idx / R, q = idx % R;
                 const int f = aa / NF, l = aa % NF;
                 T acc = 0, accv = 0;
+                const T* Er = EF(f) + l;
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
                     acc += X[i * C + aa] * X[i * C + TT + q];
-                    accv += El[(f * N + i) * NF + l] * Sb[(f * N + i) * R + q];
+                    accv += Er[i * NF] * Sb[(f * N + i) * R + q];
                 }
                 ree[idx] = acc - inv_av * (T)sc.geo[1 + D * D + f] * accv;
             }
-        }
-        wsync();
-    }
-}
-
-// Recovery: p = z_p - Z_p lam_e, v_x = z1_x - (sum_f n_fx s_f E_f lam_f - Q_x^T p)/(a rho |J|)
-template <int D, int K, int R, typename T, int WPB>
-__global__ __launch_bounds__(64 * WPB) void recover_acoustic_kernel(
-    int64_t ne, double a_in, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
-    const int32_t* __restrict__ eface, const T* __restrict__ Sr, const T* __restrict__ Ef,
-    const T* __restrict__ Zs, const T* __restrict__ zs, const double* __restrict__ lam,
-    double* __restrict__ u) {
-    using Dm = AcDims<D, K, R>;
-    constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT;
-    constexpr int NLOC = Dm::NLOC, NPERM = Dm::NPERM;
-    __shared__ T Srs[D * N * N];
-    __shared__ double lamsh[WPB][TT * R];
-    __shared__ double psh[WPB][N * R];
-    __shared__ double geo[WPB][GEOM_STRIDE];
-    for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const double a = a_in;
-    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
-        if (lane < GEOM_STRIDE) geo[wave][lane] = geom[e * GEOM_STRIDE + lane];
-        for (int idx = lane; idx < TT * R; idx += 64) {
-            const int c = idx / R, q = idx % R;
-            const int32_t F = eface[e * NFACE + c / NF];
-            lamsh[wave][idx] = lam[((int64_t)F * NF + c % NF) * R + q];
-        }
-        wsync();
-        const T* Zse = Zs + (size_t)e * N * TT;
-        const T* zse = zs + (size_t)e * NLOC * R;
-        double* ue = u + (size_t)e * NLOC * R;
-        for (int idx = lane; idx < N * R; idx += 64) {
-            const int i = idx / R, q = idx % R;
-            double acc = (double)zse[(D * N + i) * R + q];
-            const T* Zrow = Zse + i * TT;
-            for (int c = 0; c < TT; ++c) acc -= (double)Zrow[c] * lamsh[wave][c * R + q];
-            psh[wave][idx] = acc;
-            ue[(D * N + i) * R + q] = acc;
-        }
-        wsync();
-        const double J = geo[wave][0];
-        const double inv_av = 1.0 / (a * geo[wave][GEO_PAR] * J);
-        for (int idx = lane; idx < D * N * R; idx += 64) {
-            const int x = idx / (N * R), i = (idx / R) % N, q = idx % R;
-            double bl = 0.0;
-#pragma unroll
-            for (int f = 0; f < NFACE; ++f) {
-                const int p = eperm[e * NFACE + f];
-                const T* Er = Ef + (size_t)(f * NPERM + p) * N * NF + i * NF;
-                double s = 0.0;
-                for (int l = 0; l < NF; ++l) s += (double)Er[l] * lamsh[wave][(f * NF + l) * R + q];
-                bl += geo[wave][1 + D * D + NFACE + f * D + x] * geo[wave][1 + D * D + f] * s;
-            }
-            double qp = 0.0;
-#pragma unroll
-            for (int r = 0; r < D; ++r) {
-                double s = 0.0;
-                for (int j = 0; j < N; ++j) s += (double)Srs[(r * N + j) * N + i] * psh[wave][j * R + q];
-                qp += geo[wave][1 + r * D + x] * s;
-            }
-            ue[idx] = (double)zse[idx] - inv_av * (bl - J * qp);
         }
         wsync();
     }
@@ -850,35 +846,18 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
     }
 }
 
-// wavefronts per workgroup: as many as fit in 80 KB of LDS (two workgroups per CU), at most 4
-template <int D, int K, typename T>
-constexpr int ac_wpb() {
-    constexpr int sb = (int)sizeof(AcScratch<D, K, 1, T>);
-    constexpr int tb = D * dimp(K, D) * dimp(K, D) * (int)sizeof(T);
-    return (4 * sb + tb <= 80 * 1024) ? 4 : ((2 * sb + tb <= 80 * 1024) ? 2 : 1);
-}
-
 template <int D, int K, int R, typename T>
 int launch_ac(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* Mf, const T* Tsym,
               const T* Ef) {
-    constexpr int WPB = ac_wpb<D, K, T>();
-    int64_t groups = (c->n_elem + WPB - 1) / WPB;
-    int grid = (int)std::min<int64_t>(groups, 256 * 16);
-    hipLaunchKernelGGL((condense_acoustic_kernel<D, K, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream,
+    using Pl = AcPlan<D, K, R, T>;
+    constexpr int WPB = Pl::WPB;
+    auto kern = condense_acoustic_kernel<D, K, R, T, WPB, Pl::SHE, Pl::MINB>;
+    const int64_t groups = (c->n_elem + WPB - 1) / WPB;
+    const int grid = (int)std::min<int64_t>(groups, resident_groups((const void*)kern, 64 * WPB));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WPB), 0, c->stream,
                        c->n_elem, a, c->d_geom, c->d_eperm, Sr, Mf, Tsym, Ef, f_loc, (T*)c->d_Ke,
                        (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
                        c->precision == HDG_MIXED_FP32 ? (T*)c->d_LU : (T*)nullptr, c->d_status);
-    return (int)hipGetLastError();
-}
-
-template <int D, int K, int R, typename T>
-int launch_ac_rec(hdg_ctx* c, const T* Sr, const T* Ef, const double* lam, double* u) {
-    constexpr int WPB = 4;
-    int64_t groups = (c->n_elem + WPB - 1) / WPB;
-    int grid = (int)std::min<int64_t>(groups, 256 * 32);
-    hipLaunchKernelGGL((recover_acoustic_kernel<D, K, R, T, WPB>), dim3(grid), dim3(64 * WPB), 0, c->stream,
-                       c->n_elem, c->last_a, c->d_geom, c->d_eperm, c->d_eface, Sr, Ef, (const T*)c->d_Zt,
-                       (const T*)c->d_z, lam, u);
     return (int)hipGetLastError();
 }
 
@@ -924,16 +903,6 @@ int dispatch_ac(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T*
     return -1;
 }
 
-template <typename T>
-int dispatch_ac_rec(hdg_ctx* c, const T* Sr, const T* Ef, const double* lam, double* u) {
-    const int D = c->dim, K = c->k, R = c->nrhs;
-#define HDG_CASE(DD, KK, RR) \
-    if (D == DD && K == KK && R == RR) return launch_ac_rec<DD, KK, RR, T>(c, Sr, Ef, lam, u);
-    HDG_AC_CASES(HDG_CASE)
-#undef HDG_CASE
-    return -1;
-}
-
 int dispatch_ac_ref(hdg_ctx* c, const double* lam, const double* dlam, int mode, bool resid, double* u,
                     double* nrm) {
     const int D = c->dim, K = c->k, R = c->nrhs;
@@ -962,12 +931,6 @@ int launch_condense_acoustic(hdg_ctx* c, double a, const double* f_loc) {
     if (c->precision == HDG_FP64)
         return dispatch_ac<double>(c, a, f_loc, c->tab.Sr, c->tab.Mf, c->tab.Tsym, c->tab.Ef);
     return dispatch_ac<float>(c, a, f_loc, c->tab.Sr32, c->tab.Mf32, c->tab.Tsym32, c->tab.Ef32);
-}
-
-int launch_recover(hdg_ctx* c, const double* lambda, double* u, bool) {
-    if (c->physics != HDG_ACOUSTIC) return -1;
-    if (c->precision == HDG_FP64) return dispatch_ac_rec<double>(c, c->tab.Sr, c->tab.Ef, lambda, u);
-    return dispatch_ac_rec<float>(c, c->tab.Sr32, c->tab.Ef32, lambda, u);
 }
 
 }  // namespace hdg

@@ -150,7 +150,6 @@ int build_mesh(hdg_ctx* c, const hdg_mesh_desc* m, const hdg_phys_desc* p);
 // kernels (launchers, in .hip files); all return hipError_t as int
 int launch_condense(hdg_ctx* c, double a, const double* f_loc, const double* lam_bnd);
 int launch_assemble(hdg_ctx* c, const double* lam_bnd);
-int launch_recover(hdg_ctx* c, const double* lambda, double* u, bool rhs_only_z);
 int launch_residual(hdg_ctx* c, double a, const double* u, const double* lam, const double* f,
                     const double* lam_bnd, double* su, double* slam);
 // Acoustic recovery of (v, p) from the stored factors (FP64: the plain recovery; mixed
