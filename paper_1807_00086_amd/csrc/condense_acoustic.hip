@@ -44,6 +44,10 @@ __device__ __forceinline__ double pivot_rcp(double p) {
     return fma(r, e, r);
 }
 __device__ __forceinline__ float pivot_rcp(float p) { return __builtin_amdgcn_rcpf(p); }
+// Square root of an inverse pivot: correctly rounded in FP64; in FP32 the hardware square root
+// (within one ulp), as the FP32 factors are refined in FP64 anyway.
+__device__ __forceinline__ double pivot_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float pivot_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 template <typename T>
 __device__ __forceinline__ T eps_of() {
@@ -376,7 +380,7 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
                     if (!(p > ptol && p - p == T(0))) atomicOr(status, 1);
                     sc.dv[j] = ip;
                 }
-                const T sq = sqrt(ip);
+                const T sq = pivot_sqrt(ip);
                 T t[P];
 #pragma unroll
                 for (int s = 0; s < P; ++s) {
@@ -434,43 +438,96 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
         // ------------------------------------------------------------ K_e
         // K = D - (1/(a rho |J|)) [s_f s_g (n_f.n_g) E_f^T E_g] + W^T W: two MFMA chains per
         // 16x16 output tile (inner dimension N).  K_e is symmetric: only the tiles on and above
-        // the diagonal are formed and stored.
-        {
-            constexpr int TA = (TT + 15) / 16, TK = (N + 3) / 4;
-            T* Kee = Ke + (size_t)e * TT * TT;
-#pragma unroll 1
-            for (int ta = 0; ta < TA; ++ta) {
-                const int am = ta * 16 + lc;                       // this lane's A row
-                const bool aok = am < TT;
-                const int fam = aok ? am / NF : 0, lam_ = aok ? am % NF : 0;
-                const T* Ea = EF(fam) + lam_;
-#pragma unroll 1
-                for (int tb = ta; tb < TA; ++tb) {
-                    const int bn = tb * 16 + lc;                   // this lane's B column
-                    const bool bok = bn < TT;
-                    const int fbn = bok ? bn / NF : 0, lbn = bok ? bn % NF : 0;
-                    const T* Eb = EF(fbn) + lbn;
-                    typename MF::acc ww = MF::zero(), ee = MF::zero();
+        // the diagonal are formed and stored.  In FP64 the tiles are unrolled (their MFMA chains
+        // overlap) and the A operands of a row tile are read once for all its column tiles; the
+        // FP32 instantiation, at three wavefronts per SIMD, has no registers for that and forms
+        // one tile at a time.
+        if constexpr (sizeof(T) == 8) {
+            {
+                constexpr int TA = (TT + 15) / 16, TK = (N + 3) / 4;
+                T* Kee = Ke + (size_t)e * TT * TT;
+#pragma unroll
+                for (int ta = 0; ta < TA; ++ta) {
+                    const int am = ta * 16 + lc;                       // this lane's A row
+                    const bool aok = am < TT;
+                    const int fam = aok ? am / NF : 0, lam_ = aok ? am % NF : 0;
+                    const T* Ea = EF(fam) + lam_;
+                    T xa[TK], ea[TK];
 #pragma unroll
                     for (int tk = 0; tk < TK; ++tk) {
                         const int k = tk * 4 + lk;
-                        const bool kok = k < N;
-                        const T xa = (aok && kok) ? X[k * C + am] : T(0);
-                        const T xb = (bok && kok) ? X[k * C + bn] : T(0);
-                        const T ea = (aok && kok) ? Ea[k * NF] : T(0);
-                        const T eb = (bok && kok) ? Eb[k * NF] : T(0);
-                        ww = MF::mac(xa, xb, ww);
-                        ee = MF::mac(ea, eb, ee);
+                        const bool ok = aok && k < N;
+                        xa[tk] = ok ? X[k * C + am] : T(0);
+                        ea[tk] = ok ? Ea[k * NF] : T(0);
                     }
-                    if (bok) {
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int ar = ta * 16 + MF::row(lane, v);
-                            if (ar >= TT) continue;
-                            const int fa = ar / NF;
-                            T val = ww[v] - sc.cf[fa * NFACE + fbn] * ee[v];
-                            if (ar == bn) val -= tau * (T)sc.geo[1 + D * D + fa];
-                            Kee[ar * TT + bn] = val;
+                    for (int tb = ta; tb < TA; ++tb) {
+                        const int bn = tb * 16 + lc;                   // this lane's B column
+                        const bool bok = bn < TT;
+                        const int fbn = bok ? bn / NF : 0, lbn = bok ? bn % NF : 0;
+                        const T* Eb = EF(fbn) + lbn;
+                        typename MF::acc ww = MF::zero(), ee = MF::zero();
+#pragma unroll
+                        for (int tk = 0; tk < TK; ++tk) {
+                            const int k = tk * 4 + lk;
+                            const bool ok = bok && k < N;
+                            const T xb = ok ? X[k * C + bn] : T(0);
+                            const T eb = ok ? Eb[k * NF] : T(0);
+                            ww = MF::mac(xa[tk], xb, ww);
+                            ee = MF::mac(ea[tk], eb, ee);
+                        }
+                        if (bok && tb >= ta) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int ar = ta * 16 + MF::row(lane, v);
+                                if (ar >= TT) continue;
+                                const int fa = ar / NF;
+                                T val = ww[v] - sc.cf[fa * NFACE + fbn] * ee[v];
+                                if (ar == bn) val -= tau * (T)sc.geo[1 + D * D + fa];
+                                Kee[ar * TT + bn] = val;
+                            }
+                        }
+                    }
+                }
+            }
+        } else {
+            {
+                constexpr int TA = (TT + 15) / 16, TK = (N + 3) / 4;
+                T* Kee = Ke + (size_t)e * TT * TT;
+#pragma unroll 1
+                for (int ta = 0; ta < TA; ++ta) {
+                    const int am = ta * 16 + lc;                       // this lane's A row
+                    const bool aok = am < TT;
+                    const int fam = aok ? am / NF : 0, lam_ = aok ? am % NF : 0;
+                    const T* Ea = EF(fam) + lam_;
+#pragma unroll 1
+                    for (int tb = ta; tb < TA; ++tb) {
+                        const int bn = tb * 16 + lc;                   // this lane's B column
+                        const bool bok = bn < TT;
+                        const int fbn = bok ? bn / NF : 0, lbn = bok ? bn % NF : 0;
+                        const T* Eb = EF(fbn) + lbn;
+                        typename MF::acc ww = MF::zero(), ee = MF::zero();
+#pragma unroll
+                        for (int tk = 0; tk < TK; ++tk) {
+                            const int k = tk * 4 + lk;
+                            const bool kok = k < N;
+                            const T xa = (aok && kok) ? X[k * C + am] : T(0);
+                            const T xb = (bok && kok) ? X[k * C + bn] : T(0);
+                            const T ea = (aok && kok) ? Ea[k * NF] : T(0);
+                            const T eb = (bok && kok) ? Eb[k * NF] : T(0);
+                            ww = MF::mac(xa, xb, ww);
+                            ee = MF::mac(ea, eb, ee);
+                        }
+                        if (bok) {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int ar = ta * 16 + MF::row(lane, v);
+                                if (ar >= TT) continue;
+                                const int fa = ar / NF;
+                                T val = ww[v] - sc.cf[fa * NFACE + fbn] * ee[v];
+                                if (ar == bn) val -= tau * (T)sc.geo[1 + D * D + fa];
+                                Kee[ar * TT + bn] = val;
+                            }
                         }
                     }
                 }
