@@ -157,12 +157,7 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT, C = Dm::C;
     constexpr int NLOC = Dm::NLOC, NPERM = Dm::NPERM, NPAIR = Dm::NPAIR;
     constexpr int NC = N + C;                 // columns of the augmented matrix [S | B~ | f~]
-    // The low-precision kernel (mixed precision) also carries the identity through the forward
-    // elimination: it becomes L_u^{-1}, and diag(d)^{-1/2} L_u^{-1} = L^{-1} is kept for the
-    // refinement.
-    constexpr int NI = sizeof(T) == 4 ? N : 0;
-    constexpr int NCT = NC + NI;
-    constexpr int P = (NCT + 63) / 64;        // columns held per lane
+    constexpr int P = (NC + 63) / 64;         // columns held per lane
     constexpr int SB0 = N / 64, SB1 = (NC - 1) / 64;   // slots holding [B~ | f~]
     static_assert(N <= 64, "pivot columns must sit in the first register slot");
 
@@ -353,9 +348,10 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
         // Lane l holds columns l, l+64, ... of [S | B~ | f~ (| I)].  Gaussian elimination
         // without pivoting (S is SPD): S = L_u U with L_u unit lower, U = diag(d) L_u^T.  Pivot
         // column j sits in lane j; its entries reach the other lanes through readlane broadcasts.
-        //   forward:  Y = L_u^{-1} [B~ | f~ (| I)]; row j of diag(d)^{-1/2} Y is final at step j:
-        //             W for K and, from the identity columns, row j of L^{-1};
+        //   forward:  Y = L_u^{-1} [B~ | f~]; row j of diag(d)^{-1/2} Y is final at step j: W;
         //   backward: [Z_p | z_p] = U^{-1} Y.
+        // In mixed precision U, with 1/d_j in place of its diagonal, is kept for the refinement
+        // (Lout, row-major N x N, zero below the diagonal).
         T x[P][N];
         {
             T dmax = lane < N ? fabs(Sb[min(lane, N - 1) * (N + 1)]) : T(0);
@@ -369,9 +365,8 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
                 for (int i = 0; i < N; ++i)
                     x[s][i] = col < N    ? Sb[i * N + min(col, N - 1)]
                               : col < NC ? X[i * C + min(max(col - N, 0), C - 1)]
-                                         : (col - NC == i ? T(1) : T(0));
+                                         : (col - NC == i ? T(1) : T(0));   // padding lanes
             }
-            T* Le = Lout ? Lout + (size_t)e * N * N : nullptr;
 #pragma unroll
             for (int j = 0; j < N; ++j) {
                 const T p = bcast(x[0][j], j);
@@ -386,7 +381,6 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
                 for (int s = 0; s < P; ++s) {
                     const int col = s * 64 + lane;
                     if (col >= N && col < NC) X[j * C + col - N] = x[s][j] * sq;
-                    if (NI && Le && col >= NC && col < NCT) Le[j * N + col - NC] = x[s][j] * sq;
                     t[s] = x[s][j] * ip;
                 }
 #pragma unroll
@@ -398,6 +392,13 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
             }
         }
         wsync();
+        if constexpr (sizeof(T) == 4) {
+            if (Lout && lane < N) {
+                T* Le = Lout + (size_t)e * N * N;
+#pragma unroll
+                for (int i = 0; i < N; ++i) Le[i * N + lane] = i < lane ? x[0][i] : (i == lane ? sc.dv[lane] : T(0));
+            }
+        }
         {
 #pragma unroll
             for (int j = N - 1; j >= 0; --j) {
@@ -577,7 +578,7 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
 //   s_p  = f_p - |J| sum_r Sr_r (G v)_r - alpha p + tau sum_f s_f E_f (lam_f - ep_f)
 //   t_e  = s_f (E_f^T (n_f . v) - tau (lam_f - ep_f))                (= C u + D lam, element part)
 //   re64 = Z_p^T s_p - t_e                   (element part of the trace residual of the correction)
-//   z'_p = S^{-1} s_p = L^{-T} L^{-1} s_p    (stored inverse Cholesky factor of S)
+//   z'_p = S^{-1} s_p                        (two triangular solves with the stored factor U)
 // and the per-element norms |du| and |u| for the stopping test.  RESID = false stops after
 // the recovery (p, v): that is the plain recovery of the condensed solve.
 //
@@ -607,7 +608,7 @@ struct RfScratch {
     double El[SHE ? 1 : NFACE * N * NF];
     T Zl[N * TT];
     T zb[N * R];                  // z'_p on entry
-    T Ll[RESID ? N * N : 1];      // inverse Cholesky factor L^{-1} of S, row-major
+    T Ll[RESID ? N * N : 1];      // U = diag(d) L_u^T of S = L_u diag(d) L_u^T, 1/d_j on the diagonal
     int fq[32][8];                // face ids [0..NFACE) and orientations [4..4+NFACE) of the
                                   // next 32 elements of this wavefront
     int fc[8];                    // the same for the element being computed
@@ -768,9 +769,9 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
         const double rho = g[GEO_PAR], cc = g[GEO_PAR + 1], tau = g[GEO_STAB];
         const double inv_av = 1.0 / (a * rho * J), alpha_p = a * J / (rho * cc * cc);
         double dn = 0.0, un = 0.0;
-        // Vectors that a phase needs whole (p, G v, lam - E^T p, s_p, L^{-1} s_p) stay in
+        // Vectors that a phase needs whole (p, G v, lam - E^T p, s_p, S^{-1} s_p) stay in
         // registers, entry m in lane m % 64 of slot m / 64, and reach the other lanes by readlane;
-        // only the lane-varying operands (reference tables, Z_p, L^{-1}) are read from LDS.
+        // only the lane-varying operands (reference tables, Z_p, U) are read from LDS.
         // Phases that broadcast by readlane run in uniform control flow (every lane computes,
         // with clamped indices; only the stores are masked), so the source lanes are active.
         const int il = min(lane, N - 1), al = min(lane, TT - 1);
@@ -877,13 +878,33 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
                 const double s = dot4<N>([&](int i) { return Ec[i * NF] * sc.nv[fc * N + i]; });
                 tev = g[1 + D * D + fc] * (s - tau * epv);
             }
-            // ---- re64 = Z_p^T s_p - t_e ; z'_p = L^{-T} (L^{-1} s_p)
+            // ---- re64 = Z_p^T s_p - t_e ; z'_p = S^{-1} s_p
             {
                 const double s = dot4<N>([&](int i) { return (double)sc.Zl[i * TT + al] * bcast(spv, i); });
                 if (lane < TT) re64[(size_t)e * TT + lane] = s - tev;
             }
-            const double yv = dot4<N>([&](int m) { return (double)sc.Ll[il * N + m] * bcast(spv, m); });
-            const double zv = dot4<N>([&](int m) { return (double)sc.Ll[m * N + il] * bcast(yv, m); });
+            // z'_p = S^{-1} s_p with S = L_u diag(d) L_u^T, U = diag(d) L_u^T stored with 1/d_j on
+            // its diagonal: w = L_u^{-1} s_p column by column (L_u[i][j] = U[j][i] / d_j), then
+            // U z = w from the last column back.
+            // Lane i first takes column i of U above the diagonal, row i right of it and 1/d_i
+            // into registers, so that a step of either solve is one multiply, one broadcast
+            // and one FMA.  The solves run in the precision of the factor (and of the stored
+            // correction), T.
+            T cu[N], ru_[N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                cu[j] = j < lane ? sc.Ll[j * N + il] : T(0);
+                ru_[j] = j > lane ? sc.Ll[il * N + j] : T(0);
+            }
+            const T dl = sc.Ll[il * N + il];
+            T zv = (T)spv;
+#pragma unroll
+            for (int j = 0; j < N; ++j) zv -= cu[j] * bcast(zv * dl, j);
+#pragma unroll
+            for (int j = N - 1; j >= 0; --j) {
+                const T zj = bcast(zv * dl, j);
+                zv = lane == j ? zj : zv - ru_[j] * zj;
+            }
             T* zbe = zb + (size_t)e * NLOC + D * N;
             if (lane < N) zbe[lane] = (T)zv;
         }
