@@ -134,6 +134,18 @@ struct AcPlan {
     static constexpr int MINB = SHE ? WAVES / WPB : (sizeof(T) == 4 ? 3 : 2);
 };
 
+// Row and column (i <= j) of entry q of the row-major upper triangle of an n x n matrix: the
+// float root estimate of the row is corrected against the exact row offsets.
+__device__ __forceinline__ void upper_pair(int q, int n, int& i, int& j) {
+    const float b = 2.f * n + 1.f;
+    int r = (int)((b - __builtin_amdgcn_sqrtf(b * b - 8.f * q)) * 0.5f);
+    r = max(0, min(r, n - 1));
+    if (r + 1 < n && (r + 1) * n - (r + 1) * r / 2 <= q) ++r;
+    if (r * n - r * (r - 1) / 2 > q) --r;
+    i = r;
+    j = q - (r * n - r * (r - 1) / 2) + r;
+}
+
 // Broadcast of lane `src`'s value (src a compile-time constant after unrolling).
 __device__ __forceinline__ double bcast(double v, int src) {
     const long long b = __double_as_longlong(v);
@@ -331,8 +343,12 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
                     for (int x = 0; x < D; ++x) g += G[r][x] * G[s][x];
                     gam[c] = g * J * inv_arho;
                 }
-            for (int idx = lane; idx < N * N; idx += 64) {
-                T s = (idx / N == idx % N) ? alpha_p : T(0);
+            // S and the tables are symmetric: the upper triangle is formed and mirrored
+            for (int q = lane; q < N * (N + 1) / 2; q += 64) {
+                int i, j;
+                upper_pair(q, N, i, j);
+                const int idx = i * N + j;
+                T s = (i == j) ? alpha_p : T(0);
                 T fm = 0;
 #pragma unroll
                 for (int f = 0; f < NFACE; ++f) fm += sf[f] * Mf[f * N * N + idx];
@@ -340,12 +356,13 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
 #pragma unroll
                 for (int c2 = 0; c2 < NPAIR; ++c2) s += gam[c2] * Tsym[c2 * N * N + idx];
                 Sb[idx] = s;
+                Sb[j * N + i] = s;
             }
         }
         wsync();
 
         // ------------------------------------------------------------ elimination in registers
-        // Lane l holds columns l, l+64, ... of [S | B~ | f~ (| I)].  Gaussian elimination
+        // Lane l holds columns l, l+64, ... of [S | B~ | f~].  Gaussian elimination
         // without pivoting (S is SPD): S = L_u U with L_u unit lower, U = diag(d) L_u^T.  Pivot
         // column j sits in lane j; its entries reach the other lanes through readlane broadcasts.
         //   forward:  Y = L_u^{-1} [B~ | f~]; row j of diag(d)^{-1/2} Y is final at step j: W;
