@@ -110,27 +110,42 @@ struct AcScratch {
 };
 
 // LDS plan of the condensation kernel.  Target occupancy: three wavefronts per SIMD in FP32,
-// two in FP64 (the register budgets of the two instantiations).  The reference face tables of
-// all orientations are shared by the workgroup when they fit at that occupancy, with four
-// wavefronts per workgroup or, failing that, eight; otherwise every wavefront gathers the
-// oriented tables of its element and the workgroup holds as many wavefronts (at most four) as
-// fit two workgroups per CU.
-template <int D, int K, int R, typename T, bool SHE>
+// two in FP64 (the register budgets of the two instantiations).  In order of preference the
+// workgroup shares in LDS, beside Sr: the face tables of all orientations (SHE) and the upper
+// triangles of the reference tables of S (TBL).  With TBL no global load other than the
+// one-element-ahead prefetch happens inside an element; this matters because vector loads and
+// stores share one in-order counter, so a load issued after an element's stores cannot be used
+// before those stores complete.  The first configuration that fits at the target wavefronts per
+// CU (LDS allocated in 512-byte granules), with 4, 8 or 12 wavefronts per workgroup (whole
+// wavefronts per SIMD), wins;
+// failing all, every wavefront gathers the oriented tables of its element.
+template <int D, int K, int R, typename T, bool SHE, bool TBL>
 constexpr int ac_block_lds(int wpb) {
     using Dm = AcDims<D, K, R>;
-    return (int)((D * Dm::N * Dm::N + (SHE ? Dm::NFACE * Dm::NPERM * Dm::N * Dm::NF : 0)) * sizeof(T) +
-                 wpb * sizeof(AcScratch<D, K, R, T, SHE>));
+    const int np = Dm::N * (Dm::N + 1) / 2;
+    const int b = (int)((D * Dm::N * Dm::N + (SHE ? Dm::NFACE * Dm::NPERM * Dm::N * Dm::NF : 0) +
+                         (TBL ? (Dm::NFACE + Dm::NPAIR) * np : 0)) * sizeof(T) +
+                        wpb * sizeof(AcScratch<D, K, R, T, SHE>));
+    return (b + 511) / 512 * 512;
+}
+template <int D, int K, int R, typename T, bool SHE, bool TBL>
+constexpr int ac_fit_wpb(int waves) {   // wavefronts per workgroup, 0 if none fits
+    const int cand[3] = {4, 8, 12};
+    for (int i = 0; i < 3; ++i)
+        if (waves % cand[i] == 0 && (waves / cand[i]) * ac_block_lds<D, K, R, T, SHE, TBL>(cand[i]) <= 160 * 1024)
+            return cand[i];
+    return 0;
 }
 template <int D, int K, int R, typename T>
 struct AcPlan {
-    static constexpr int LDS = 160 * 1024;
     static constexpr int WAVES = sizeof(T) == 4 ? 12 : 8;   // per CU
-    static constexpr bool S4 = (WAVES / 4) * ac_block_lds<D, K, R, T, true>(4) <= LDS;
-    static constexpr bool S8 = WAVES % 8 == 0 && ac_block_lds<D, K, R, T, true>(8) <= LDS;
-    static constexpr bool SHE = S4 || S8;
+    static constexpr int W_ST = ac_fit_wpb<D, K, R, T, true, true>(WAVES);
+    static constexpr int W_S = ac_fit_wpb<D, K, R, T, true, false>(WAVES);
+    static constexpr bool SHE = W_ST > 0 || W_S > 0;
+    static constexpr bool TBL = W_ST > 0;
     static constexpr int WPB_G = (4 * (int)sizeof(AcScratch<D, K, R, T, false>) + D * dimp(K, D) * dimp(K, D) * (int)sizeof(T) <= 80 * 1024) ? 4
                                  : (2 * (int)sizeof(AcScratch<D, K, R, T, false>) + D * dimp(K, D) * dimp(K, D) * (int)sizeof(T) <= 80 * 1024) ? 2 : 1;
-    static constexpr int WPB = S4 ? 4 : (S8 ? 8 : WPB_G);
+    static constexpr int WPB = W_ST ? W_ST : (W_S ? W_S : WPB_G);
     static constexpr int MINB = SHE ? WAVES / WPB : (sizeof(T) == 4 ? 3 : 2);
 };
 
@@ -157,7 +172,7 @@ __device__ __forceinline__ float bcast(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
-template <int D, int K, int R, typename T, int WPB, bool SHE, int MINB>
+template <int D, int K, int R, typename T, int WPB, bool SHE, bool TBL, int MINB>
 __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
     int64_t ne, double a_in, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
     const T* __restrict__ Sr, const T* __restrict__ Mf, const T* __restrict__ Tsym,
@@ -174,12 +189,21 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
     static_assert(N <= 64, "pivot columns must sit in the first register slot");
 
     __shared__ T Srs[D * N * N];
+    constexpr int NP = N * (N + 1) / 2;       // entries of an upper triangle
     __shared__ T Efs[SHE ? NFACE * NPERM * N * NF : 1];
+    __shared__ T Tbs[TBL ? (NFACE + NPAIR) * NP : 1];   // upper triangles of Mf_f, then Tsym_c
     __shared__ AcScratch<D, K, R, T, SHE> scr_all[WPB];
 
     for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
     if (SHE)
         for (int idx = threadIdx.x; idx < NFACE * NPERM * N * NF; idx += 64 * WPB) Efs[idx] = Ef[idx];
+    if (TBL)
+        for (int q = threadIdx.x; q < NP; q += 64 * WPB) {
+            int i, j;
+            upper_pair(q, N, i, j);
+            for (int f = 0; f < NFACE; ++f) Tbs[f * NP + q] = Mf[f * N * N + i * N + j];
+            for (int c = 0; c < NPAIR; ++c) Tbs[(NFACE + c) * NP + q] = Tsym[c * N * N + i * N + j];
+        }
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -344,17 +368,18 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
                     gam[c] = g * J * inv_arho;
                 }
             // S and the tables are symmetric: the upper triangle is formed and mirrored
-            for (int q = lane; q < N * (N + 1) / 2; q += 64) {
+            for (int q = lane; q < NP; q += 64) {
                 int i, j;
                 upper_pair(q, N, i, j);
                 const int idx = i * N + j;
                 T s = (i == j) ? alpha_p : T(0);
                 T fm = 0;
 #pragma unroll
-                for (int f = 0; f < NFACE; ++f) fm += sf[f] * Mf[f * N * N + idx];
+                for (int f = 0; f < NFACE; ++f) fm += sf[f] * (TBL ? Tbs[f * NP + q] : Mf[f * N * N + idx]);
                 s += tau * fm;
 #pragma unroll
-                for (int c2 = 0; c2 < NPAIR; ++c2) s += gam[c2] * Tsym[c2 * N * N + idx];
+                for (int c2 = 0; c2 < NPAIR; ++c2)
+                    s += gam[c2] * (TBL ? Tbs[(NFACE + c2) * NP + q] : Tsym[c2 * N * N + idx]);
                 Sb[idx] = s;
                 Sb[j * N + i] = s;
             }
@@ -946,7 +971,7 @@ int launch_ac(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* M
               const T* Ef) {
     using Pl = AcPlan<D, K, R, T>;
     constexpr int WPB = Pl::WPB;
-    auto kern = condense_acoustic_kernel<D, K, R, T, WPB, Pl::SHE, Pl::MINB>;
+    auto kern = condense_acoustic_kernel<D, K, R, T, WPB, Pl::SHE, Pl::TBL, Pl::MINB>;
     const int64_t groups = (c->n_elem + WPB - 1) / WPB;
     const int grid = (int)std::min<int64_t>(groups, resident_groups((const void*)kern, 64 * WPB));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WPB), 0, c->stream,
