@@ -648,7 +648,9 @@ struct RfScratch {
     double vv[D * N * R];         // v
     double nv[NFACE * N * R];     // n_f . v
     double El[SHE ? 1 : NFACE * N * NF];
-    T Zl[N * TT];
+    // Z_p, rows padded to an odd stride: a lane per row reads distinct LDS banks
+    static constexpr int ZS = (Dm::TT % 2 == 0) ? Dm::TT + 1 : Dm::TT;
+    T Zl[N * ZS];
     T zb[N * R];                  // z'_p on entry
     T Ll[RESID ? N * N : 1];      // U = diag(d) L_u^T of S = L_u diag(d) L_u^T, 1/d_j on the diagonal
     int fq[32][8];                // face ids [0..NFACE) and orientations [4..4+NFACE) of the
@@ -772,7 +774,10 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
                 if (lane + 64 * t < NEL) sc.El[lane + 64 * t] = rel[t];
 #pragma unroll
         for (int t = 0; t < PZ; ++t)
-            if (lane + 64 * t < NZ) sc.Zl[lane + 64 * t] = rz[t];
+            if (lane + 64 * t < NZ) {
+                const int idx = lane + 64 * t;
+                sc.Zl[(idx / TT) * Scr::ZS + idx % TT] = rz[t];
+            }
 #pragma unroll
         for (int t = 0; t < PB; ++t)
             if (lane + 64 * t < N * R) sc.zb[lane + 64 * t] = rzb[t];
@@ -822,7 +827,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
         {
             double s = 0.0;
             if (mode != 2)
-                s = (double)sc.zb[il] - dot4<TT>([&](int c) { return (double)sc.Zl[il * TT + c] * bcast(dlv, c); });
+                s = (double)sc.zb[il] - dot4<TT>([&](int c) { return (double)sc.Zl[il * Scr::ZS + c] * bcast(dlv, c); });
             pv = sc.uo[D * N + il] + s;
             if (lane < N) {
                 ue[D * N + lane] = pv;
@@ -922,7 +927,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
             }
             // ---- re64 = Z_p^T s_p - t_e ; z'_p = S^{-1} s_p
             {
-                const double s = dot4<N>([&](int i) { return (double)sc.Zl[i * TT + al] * bcast(spv, i); });
+                const double s = dot4<N>([&](int i) { return (double)sc.Zl[i * Scr::ZS + al] * bcast(spv, i); });
                 if (lane < TT) re64[(size_t)e * TT + lane] = s - tev;
             }
             // z'_p = S^{-1} s_p with S = L_u diag(d) L_u^T, U = diag(d) L_u^T stored with 1/d_j on
