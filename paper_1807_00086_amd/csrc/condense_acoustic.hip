@@ -663,11 +663,11 @@ struct PerLane {
     static constexpr int n = (M + 63) / 64;
 };
 
-// sum_{j < L} term(j) with four independent accumulators (FP64 FMA chains of a quarter of the
-// length; the summation order is fixed)
-template <int L, typename F>
-__device__ __forceinline__ double dot4(F term) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+// sum_{j < L} term(j) with four independent accumulators of type A (FMA chains of a quarter of
+// the length; the summation order is fixed)
+template <int L, typename A = double, typename F>
+__device__ __forceinline__ A dot4(F term) {
+    A a0 = A(0), a1 = A(0), a2 = A(0), a3 = A(0);
 #pragma unroll
     for (int j = 0; j + 3 < L; j += 4) {
         a0 += term(j);
@@ -822,12 +822,16 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
         // Phases that broadcast by readlane run in uniform control flow (every lane computes,
         // with clamped indices; only the stores are masked), so the source lanes are active.
         const int il = min(lane, N - 1), al = min(lane, TT - 1);
+        // The products with the stored factors (Z_p dlam here, Z_p^T s_p below) are taken in
+        // their precision T: in mixed precision they carry the FP32 factors' error anyway, which
+        // the refinement removes, while the sums with p and the residuals stay FP64.
         // ---- p = p_prev + z'_p - Z_p dlam (lane i) ; E_f lam_f
         double pv;
         {
             double s = 0.0;
+            const T dlt = (T)dlv;
             if (mode != 2)
-                s = (double)sc.zb[il] - dot4<TT>([&](int c) { return (double)sc.Zl[il * Scr::ZS + c] * bcast(dlv, c); });
+                s = (double)(sc.zb[il] - dot4<TT, T>([&](int c) { return sc.Zl[il * Scr::ZS + c] * bcast(dlt, c); }));
             pv = sc.uo[D * N + il] + s;
             if (lane < N) {
                 ue[D * N + lane] = pv;
@@ -927,7 +931,8 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
             }
             // ---- re64 = Z_p^T s_p - t_e ; z'_p = S^{-1} s_p
             {
-                const double s = dot4<N>([&](int i) { return (double)sc.Zl[i * Scr::ZS + al] * bcast(spv, i); });
+                const T spt = (T)spv;
+                const double s = (double)dot4<N, T>([&](int i) { return sc.Zl[i * Scr::ZS + al] * bcast(spt, i); });
                 if (lane < TT) re64[(size_t)e * TT + lane] = s - tev;
             }
             // z'_p = S^{-1} s_p with S = L_u diag(d) L_u^T, U = diag(d) L_u^T stored with 1/d_j on
