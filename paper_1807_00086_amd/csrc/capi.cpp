@@ -758,6 +758,7 @@ hdg_status hdg_element_data(hdg_ctx* c, int which, int64_t e0, int64_t count, do
             // which == 3: only the Schur-block rows of z are A^{-1} f (the eliminated rows hold
             // the closed-form part applied at recovery)
             int64_t src_i = (which == 3) ? c->s_row0 * R + i : i;
+            if (which == 2 && c->fast_ac) src_i = (i % t) * ns + i / t;   // Z_p stored column-major
             if (which == 0 && c->ke_tile > 0) {   // K_e stored by its upper tiles
                 const int64_t r = i / t, cc = i % t;
                 if (r / c->ke_tile > cc / c->ke_tile) src_i = cc * t + r;

@@ -393,7 +393,7 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
         //   forward:  Y = L_u^{-1} [B~ | f~]; row j of diag(d)^{-1/2} Y is final at step j: W;
         //   backward: [Z_p | z_p] = U^{-1} Y.
         // In mixed precision U, with 1/d_j in place of its diagonal, is kept for the refinement
-        // (Lout, row-major N x N, zero below the diagonal).
+        // (Lout, column-major N x N: each column contiguous, zero below the diagonal).
         T x[P][N];
         {
             T dmax = lane < N ? fabs(Sb[min(lane, N - 1) * (N + 1)]) : T(0);
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
             if (Lout && lane < N) {
                 T* Le = Lout + (size_t)e * N * N;
 #pragma unroll
-                for (int i = 0; i < N; ++i) Le[i * N + lane] = i < lane ? x[0][i] : (i == lane ? sc.dv[lane] : T(0));
+                for (int i = 0; i < N; ++i) Le[lane * N + i] = i < lane ? x[0][i] : (i == lane ? sc.dv[lane] : T(0));
             }
         }
         {
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
                 const int c = s * 64 + lane - N;
                 if (c >= 0 && c < TT) {
 #pragma unroll
-                    for (int i = 0; i < N; ++i) Zse[i * TT + c] = x[s][i];
+                    for (int i = 0; i < N; ++i) Zse[c * N + i] = x[s][i];
                 } else if (c >= TT && c < C) {
 #pragma unroll
                     for (int i = 0; i < N; ++i) zse[(D * N + i) * R + (c - TT)] = x[s][i];
@@ -652,7 +652,8 @@ struct RfScratch {
     static constexpr int ZS = (Dm::TT % 2 == 0) ? Dm::TT + 1 : Dm::TT;
     T Zl[N * ZS];
     T zb[N * R];                  // z'_p on entry
-    T Ll[RESID ? N * N : 1];      // U = diag(d) L_u^T of S = L_u diag(d) L_u^T, 1/d_j on the diagonal
+    T Ll[RESID ? N * N : 1];      // U = diag(d) L_u^T of S = L_u diag(d) L_u^T, 1/d_j on the
+                                  // diagonal, column-major
     int fq[32][8];                // face ids [0..NFACE) and orientations [4..4+NFACE) of the
                                   // next 32 elements of this wavefront
     int fc[8];                    // the same for the element being computed
@@ -776,7 +777,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
         for (int t = 0; t < PZ; ++t)
             if (lane + 64 * t < NZ) {
                 const int idx = lane + 64 * t;
-                sc.Zl[(idx / TT) * Scr::ZS + idx % TT] = rz[t];
+                sc.Zl[(idx % N) * Scr::ZS + idx / N] = rz[t];   // Z_p is stored column-major
             }
 #pragma unroll
         for (int t = 0; t < PB; ++t)
@@ -945,8 +946,8 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
             T cu[N], ru_[N];
 #pragma unroll
             for (int j = 0; j < N; ++j) {
-                cu[j] = j < lane ? sc.Ll[j * N + il] : T(0);
-                ru_[j] = j > lane ? sc.Ll[il * N + j] : T(0);
+                cu[j] = j < lane ? sc.Ll[il * N + j] : T(0);   // U is stored column-major
+                ru_[j] = j > lane ? sc.Ll[j * N + il] : T(0);
             }
             const T dl = sc.Ll[il * N + il];
             T zv = (T)spv;

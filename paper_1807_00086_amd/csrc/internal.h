@@ -89,9 +89,11 @@ struct hdg_ctx {
     // condensation outputs (precision-typed: double or float)
     void* d_Ke = nullptr;      // [ne][t][t]
     void* d_re = nullptr;      // [ne][t][r]
-    void* d_Zt = nullptr;      // [ne][Ns][t]  rows of Z = A^{-1} B for the Schur block
+    void* d_Zt = nullptr;      // [ne][Ns][t]  rows of Z = A^{-1} B for the Schur block (the
+                               // acoustic kernels of the fast path store it column-major, [ne][t][Ns])
     void* d_z = nullptr;       // [ne][n][r]
-    void* d_LU = nullptr;      // [ne][Ns][Ns] factored Schur block (mixed precision)
+    void* d_LU = nullptr;      // [ne][Ns][Ns] factored Schur block (mixed precision; acoustic fast
+                               // path: U = diag(d) L_u^T column-major, inverse pivots on the diagonal)
     int Ns = 0;                // size of the densely factored (Schur) block
     int ke_tile = 0;           // > 0: K_e holds only the entries whose row tile (of this many
                                // rows) is <= their column tile; the rest is read mirrored
