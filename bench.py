@@ -38,22 +38,22 @@ def dimp(k, d):
 def acoustic_counts(D, K, R, elt_bytes, mixed=False):
     """Algorithmic HBM bytes and executed flops per element of the acoustic kernels
     (condense_acoustic.hip).  Condensation: closed-form velocity elimination, B~ and W_f by
-    MFMA tiles, the pressure Schur block S from reference tables, elimination of [S | B~ | f~]
-    (plus the identity in mixed precision, for L^{-1}) without pivoting, K_e = D - B_v^T B_v /
-    (a rho |J|) + W^T W formed and stored by its tiles on and above the diagonal.  Recovery:
+    MFMA tiles, the pressure Schur block S (upper triangle) from reference tables, elimination
+    of [S | B~ | f~] without pivoting (mixed precision also stores the factor U of S),
+    K_e = D - B_v^T B_v / (a rho |J|) + W^T W formed and stored by its tiles on and above the
+    diagonal.  Recovery:
     p = z_p - Z_p lam, v in closed form.  Reads of the degree-dependent reference tables hit
     the caches and are not counted as HBM traffic; padding of MFMA tiles is not counted."""
     N, NF, NFACE = dimp(K, D), dimp(K, D - 1), D + 1
     TT, NLOC = NFACE * NF, (D + 1) * N
     C = TT + R
-    NI = N if mixed else 0
     npair = D * (D + 1) // 2
     k_stored = sum(1 for r in range(TT) for c in range(TT) if r // 16 <= c // 16)
     fma = (D * D * N * R + D * N * N * R     # condensed pressure rhs
            + NFACE * N * N * D               # W_f = tau I + sum_r beta_fr Sr_r (MFMA operand)
            + NFACE * N * NF * N              # B~_f = -s_f W_f E_f
-           + N * N * (NFACE + npair)         # S from reference tables
-           + N ** 3 / 3.0 + N * N * (C + NI) / 2.0   # forward elimination
+           + N * (N + 1) / 2.0 * (NFACE + npair)   # upper triangle of S from reference tables
+           + N ** 3 / 3.0 + N * N * C / 2.0  # forward elimination
            + N * N * C / 2.0                 # back substitution
            + 2 * k_stored * N                # W^T W and E^T E on the stored tiles
            + TT * R * 2 * N + NFACE * N * R * D)     # r_e
