@@ -102,6 +102,12 @@ typedef struct {
     int refine_maxit;
     double refine_inner_tol;    /* mixed precision: relative residual of the trace solves of
                                    the corrections (0: 1e-6)                                  */
+    int cache_factors;          /* nonzero: keep the factors of every condensation so that
+                                   hdg_condense_rhs (and hdg_step, whose stages share one
+                                   stage coefficient) can condense a new right-hand side
+                                   without refactoring.  Acoustic fast path (uniform degree,
+                                   one rhs); costs n_s^2 values per element in FP64 (the
+                                   mixed-precision path keeps them anyway)                   */
 } hdg_options;
 
 /* Query keys for hdg_query. */
@@ -155,6 +161,22 @@ hdg_status hdg_query(const hdg_ctx* ctx, int key, int64_t* value);
 hdg_status hdg_condense(hdg_ctx* ctx, double a, const double* f_loc, const double* lam_bnd);
 
 /*
+ * hdg_condense_rhs -- condensation of a new right-hand side with the factors of the last
+ * hdg_condense.  The element matrices A, B, C, D depend on the stage coefficient only
+ * (section 2.4.1), so for the same `a` the factors Z and the assembled trace matrix stay
+ * valid and only z = A^{-1} f and r_e = -C z change (static condensation of the right-hand
+ * side, section 2.4.1): r_e and z are recomputed from the stored factors and the trace
+ * right-hand side is assembled; the trace matrix and its preconditioner are kept.
+ *   a        must equal the stage coefficient of the last hdg_condense
+ *   f_loc    device [n_local_dofs][nrhs] FP64, lam_bnd device [n_trace_dofs][nrhs] FP64,
+ *            as for hdg_condense
+ * HDG_E_STATE without an earlier hdg_condense at this `a` whose factors were kept
+ * (options.cache_factors in FP64; always in mixed precision); HDG_E_UNSUPPORTED outside the
+ * acoustic fast path (uniform degree, one right-hand side).  Asynchronous.
+ */
+hdg_status hdg_condense_rhs(hdg_ctx* ctx, double a, const double* f_loc, const double* lam_bnd);
+
+/*
  * hdg_trace_solve -- solve the assembled trace system K lam = r in FP64 (section 2.4.2;
  * K is symmetric and definite for every physics here, so preconditioned conjugate
  * gradients replace GMRES; block-Jacobi preconditioner).
@@ -184,7 +206,9 @@ hdg_status hdg_recover(hdg_ctx* ctx, double* lambda, double* u_loc);
  * hdg_step -- advance u^n -> u^{n+1} by backward Euler or DIRK(3,3) (section 2.3.2,
  * stiffly accurate, so u^{n+1} is the last stage).  Per stage i:
  * u*_i = u^n - (1/d_ii) sum_{j<i} d_ij (U_j - u^n), f = a Mw u*_i with a = d_ii / dt, then
- * condense, trace solve, recover.
+ * condense, trace solve, recover.  The DIRK(3,3) stages share d_ii, so with
+ * options.cache_factors set every stage after the first condensation at a given dt only
+ * condenses its right-hand side (hdg_condense_rhs).
  *   u          device [n_local_dofs][nrhs] in: u^n, out: u^{n+1}
  *   lambda     device [n_trace_dofs][nrhs] in: initial guess, out: trace of the last stage
  *   lam_bnd    device [n_stages][n_trace_dofs][nrhs] Dirichlet data at t + c_i dt

@@ -157,6 +157,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     c->refine_tol = o->refine_tol > 0 ? o->refine_tol : 1e-13;
     c->refine_maxit = o->refine_maxit > 0 ? o->refine_maxit : 10;
     c->refine_inner_tol = o->refine_inner_tol > 0 ? o->refine_inner_tol : 1e-6;
+    c->cache_factors = o->cache_factors != 0;
     c->stream = (hipStream_t)stream;
     int st = build_mesh(c, m, p);
     if (st) {
@@ -282,7 +283,8 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(dalloc(c, (char**)&c->d_re, ne * c->n_tr * R * tsz));
     TRY(dalloc(c, (char**)&c->d_Zt, ne * c->n_tr * c->Ns * tsz));
     TRY(dalloc(c, (char**)&c->d_z, ne * c->n_loc * R * tsz));
-    if (c->precision == HDG_MIXED_FP32) TRY(dalloc(c, (char**)&c->d_LU, ne * c->Ns * c->Ns * tsz));
+    if (c->precision == HDG_MIXED_FP32 || (c->cache_factors && c->fast_ac))
+        TRY(dalloc(c, (char**)&c->d_LU, ne * c->Ns * c->Ns * tsz));
     TRY(dalloc(c, &c->d_status, 1));
     const int64_t ntr = c->n_trace_dofs;
     TRY(dalloc(c, &c->d_bsr, c->n_faces * c->nslot * c->bs * c->bs));
@@ -369,6 +371,36 @@ hdg_status hdg_condense(hdg_ctx* c, double a, const double* f_loc, const double*
     if (e) return fail(c, HDG_E_HIP, "assembly kernel launch failed");
     c->last_a = a;
     c->condensed = true;
+    c->z_consumed = false;
+    c->factors_cached = c->fast_ac && c->d_LU != nullptr;
+    return HDG_OK;
+}
+
+hdg_status hdg_condense_rhs(hdg_ctx* c, double a, const double* f_loc, const double* lam_bnd) {
+    if (!c) return HDG_E_ARG;
+    if (!f_loc || !lam_bnd) return fail(c, HDG_E_ARG, "null f_loc or lam_bnd");
+    if (!c->fast_ac) return fail(c, HDG_E_UNSUPPORTED, "right-hand-side condensation: acoustic, uniform degree, one rhs");
+    if (!c->condensed || !c->factors_cached)
+        return fail(c, HDG_E_STATE, "hdg_condense_rhs needs the factors of an earlier hdg_condense (FP64: cache_factors)");
+    if (a != c->last_a) return fail(c, HDG_E_STATE, "hdg_condense_rhs: stage coefficient differs from the factored one");
+    const int64_t R = c->nrhs;
+    if (c->precision == HDG_MIXED_FP32) {   // kept for the FP64 refinement residuals
+        HIPCHK(hipMemcpyAsync(c->d_f_saved, f_loc, c->n_local_dofs * R * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(hipMemcpyAsync(c->d_lbnd_saved, lam_bnd, c->n_trace_dofs * R * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
+    }
+    int e;
+    {
+        EventTimer t(c, &c->tim.condense);
+        e = launch_condense_rhs_acoustic(c, a, f_loc);
+    }
+    if (e) return fail(c, HDG_E_HIP, "right-hand-side condensation launch failed");
+    {
+        EventTimer t(c, &c->tim.assemble);
+        e = launch_assemble_rhs(c, lam_bnd);
+    }
+    if (e) return fail(c, HDG_E_HIP, "right-hand-side assembly launch failed");
     c->z_consumed = false;
     return HDG_OK;
 }
@@ -599,7 +631,11 @@ hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, doub
         if (wsum != 0.0) launch_axpy(c, nl, -wsum, u, c->d_ustar);
         launch_apply_mass(c, a, c->d_ustar, c->d_fstage);
         if (src) launch_axpy(c, nl, 1.0, src, c->d_fstage);
-        int s = hdg_condense(c, a, c->d_fstage, lam_bnd + i * nt);
+        // the stage matrices depend on a only: with cached factors a repeated a needs only the
+        // right-hand side condensed
+        const bool reuse = c->cache_factors && c->factors_cached && c->condensed && a == c->last_a;
+        int s = reuse ? hdg_condense_rhs(c, a, c->d_fstage, lam_bnd + i * nt)
+                      : hdg_condense(c, a, c->d_fstage, lam_bnd + i * nt);
         if (s) return s;
         int it;
         double rr;

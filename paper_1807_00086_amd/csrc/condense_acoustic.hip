@@ -172,7 +172,7 @@ __device__ __forceinline__ float bcast(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
-template <int D, int K, int R, typename T, int WPB, bool SHE, bool TBL, int MINB>
+template <int D, int K, int R, typename T, int WPB, bool SHE, bool TBL, int MINB, bool SU>
 __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
     int64_t ne, double a_in, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
     const T* __restrict__ Sr, const T* __restrict__ Mf, const T* __restrict__ Tsym,
@@ -392,8 +392,9 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
         // column j sits in lane j; its entries reach the other lanes through readlane broadcasts.
         //   forward:  Y = L_u^{-1} [B~ | f~]; row j of diag(d)^{-1/2} Y is final at step j: W;
         //   backward: [Z_p | z_p] = U^{-1} Y.
-        // In mixed precision U, with 1/d_j in place of its diagonal, is kept for the refinement
-        // (Lout, column-major N x N: each column contiguous, zero below the diagonal).
+        // With SU (mixed precision, or cached factors) U, with 1/d_j in place of its diagonal,
+        // is kept for the refinement and for right-hand-side condensations (Lout, column-major
+        // N x N: each column contiguous, zero below the diagonal).
         T x[P][N];
         {
             T dmax = lane < N ? fabs(Sb[min(lane, N - 1) * (N + 1)]) : T(0);
@@ -434,7 +435,7 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
             }
         }
         wsync();
-        if constexpr (sizeof(T) == 4) {
+        if constexpr (SU) {
             if (Lout && lane < N) {
                 T* Le = Lout + (size_t)e * N * N;
 #pragma unroll
@@ -602,6 +603,103 @@ __global__ __launch_bounds__(64 * WPB, MINB) void condense_acoustic_kernel(
                 ree[idx] = acc - inv_av * (T)sc.geo[1 + D * D + f] * accv;
             }
         }
+        wsync();
+    }
+}
+
+// Right-hand-side condensation with the factors of the last condensation at the same stage
+// coefficient (the stage matrices depend on a only, so Z_p, U and K_e stay valid).  For a new f:
+//   f~  = f_p - (1/(a rho)) sum_r Sr_r (G f_v)_r,
+//   z_p = S^{-1} f~  (forward substitution with L_u, backward with U, from the stored U),
+//   z_v = f_v / (a rho |J|),
+//   r_e = Z_p^T f~ - (1/(a rho |J|)) B_v^T f_v     (W^T w = B~^T S^{-1} f~ = Z_p^T f~, S symmetric),
+// all in the factors' precision T.  One element per wavefront; Sr in LDS, U staged per
+// wavefront, Z_p (column-major) read by its columns, the oriented face tables through L2.
+template <int D, int K, int R, typename T>
+struct RhScratch {
+    using Dm = AcDims<D, K, R>;
+    double geo[GEOM_STRIDE];
+    T fv[D * Dm::N];              // f_v
+    T gf[D * Dm::N];              // (G f_v)_r / (a rho)
+    T nf[Dm::NFACE * Dm::N];      // n_f . f_v
+    T ul[Dm::N * Dm::N];          // U, column-major
+    int pf[Dm::NFACE];
+};
+
+template <int D, int K, int R, typename T, int WPB>
+__global__ __launch_bounds__(64 * WPB, 2) void rhs_acoustic_kernel(
+    int64_t ne, double a_in, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
+    const T* __restrict__ Sr, const T* __restrict__ Ef, const T* __restrict__ Zs, const T* __restrict__ Us,
+    const double* __restrict__ f_loc, T* __restrict__ re, T* __restrict__ zs) {
+    using Dm = AcDims<D, K, R>;
+    constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT, NLOC = Dm::NLOC;
+    constexpr int NPERM = Dm::NPERM;
+    static_assert(R == 1 && TT <= 64 && N <= 64, "one right-hand side; trace and Schur vectors fit a wavefront");
+    __shared__ T Srs[D * N * N];
+    __shared__ RhScratch<D, K, R, T> scr_all[WPB];
+    for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    RhScratch<D, K, R, T>& sc = scr_all[wave];
+    const int il = min(lane, N - 1), al = min(lane, TT - 1);
+    const T a = (T)a_in;
+    for (int64_t e = (int64_t)blockIdx.x * WPB + wave; e < ne; e += (int64_t)gridDim.x * WPB) {
+        const double* fe = f_loc + (size_t)e * NLOC;
+        if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
+        if (lane < NFACE) sc.pf[lane] = eperm[e * NFACE + lane];
+        for (int idx = lane; idx < D * N; idx += 64) sc.fv[idx] = (T)fe[idx];
+        for (int idx = lane; idx < N * N; idx += 64) sc.ul[idx] = Us[(size_t)e * N * N + idx];
+        const T fpv = (T)fe[D * N + il];
+        wsync();
+        const double* g = sc.geo;
+        const T J = (T)g[0], rho = (T)g[GEO_PAR];
+        const T inv_arho = T(1) / (a * rho), inv_av = inv_arho / J;
+        for (int idx = lane; idx < D * N; idx += 64) {
+            const int r = idx / N, j = idx - r * N;
+            T s = 0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) s += (T)g[1 + r * D + x] * sc.fv[x * N + j];
+            sc.gf[idx] = s * inv_arho;
+        }
+        for (int idx = lane; idx < NFACE * N; idx += 64) {
+            const int f = idx / N, i = idx - f * N;
+            T s = 0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) s += (T)g[1 + D * D + NFACE + f * D + x] * sc.fv[x * N + i];
+            sc.nf[idx] = s;
+        }
+        wsync();
+        // f~ (lane i)
+        T ft = fpv;
+#pragma unroll 6
+        for (int rj = 0; rj < D * N; ++rj) {
+            const int r = rj / N, j = rj - r * N;
+            ft -= Srs[(r * N + il) * N + j] * sc.gf[rj];
+        }
+        // z_p = S^{-1} f~ by forward substitution with L_u (L_u[i][j] = U[j][i] / d_j) and
+        // backward substitution with U; lane i holds entry i, U is read from LDS (column-major:
+        // U[j][i] = ul[i N + j]) and 1/d_i sits on its diagonal
+        const T dl = sc.ul[il * N + il];
+        T zv = ft;
+#pragma unroll 4
+        for (int j = 0; j < N; ++j) zv -= (j < lane ? sc.ul[il * N + j] : T(0)) * bcast(zv * dl, j);
+#pragma unroll 4
+        for (int j = N - 1; j >= 0; --j) {
+            const T zj = bcast(zv * dl, j);
+            zv = lane == j ? zj : zv - (j > lane ? sc.ul[j * N + il] : T(0)) * zj;
+        }
+        // r_e (lane a): Z_p column a dot f~, minus the velocity-block term
+        {
+            const int fc = al / NF, l = al - fc * NF;
+            const T* Zc = Zs + ((size_t)e * TT + al) * N;
+            const T* Ec = Ef + (size_t)(fc * NPERM + sc.pf[fc]) * N * NF + l;
+            const T zf = dot4<N, T>([&](int i) { return Zc[i] * bcast(ft, i); });
+            const T bf = dot4<N, T>([&](int i) { return Ec[i * NF] * sc.nf[fc * N + i]; });
+            if (lane < TT) re[(size_t)e * TT + lane] = zf - inv_av * (T)g[1 + D * D + fc] * bf;
+        }
+        T* ze = zs + (size_t)e * NLOC;
+        for (int idx = lane; idx < D * N; idx += 64) ze[idx] = sc.fv[idx] * inv_av;
+        if (lane < N) ze[D * N + lane] = zv;
         wsync();
     }
 }
@@ -982,14 +1080,23 @@ int launch_ac(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* M
               const T* Ef) {
     using Pl = AcPlan<D, K, R, T>;
     constexpr int WPB = Pl::WPB;
-    auto kern = condense_acoustic_kernel<D, K, R, T, WPB, Pl::SHE, Pl::TBL, Pl::MINB>;
-    const int64_t groups = (c->n_elem + WPB - 1) / WPB;
-    const int grid = (int)std::min<int64_t>(groups, resident_groups((const void*)kern, 64 * WPB));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WPB), 0, c->stream,
-                       c->n_elem, a, c->d_geom, c->d_eperm, Sr, Mf, Tsym, Ef, f_loc, (T*)c->d_Ke,
-                       (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
-                       c->precision == HDG_MIXED_FP32 ? (T*)c->d_LU : (T*)nullptr, c->d_status);
-    return (int)hipGetLastError();
+    // U is stored in mixed precision (refinement) and with cached factors; the FP64 kernel
+    // without it is a separate instantiation
+    auto launch = [&](auto kern) {
+        const int64_t groups = (c->n_elem + WPB - 1) / WPB;
+        const int grid = (int)std::min<int64_t>(groups, resident_groups((const void*)kern, 64 * WPB));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WPB), 0, c->stream, c->n_elem, a, c->d_geom,
+                           c->d_eperm, Sr, Mf, Tsym, Ef, f_loc, (T*)c->d_Ke, (T*)c->d_re, (T*)c->d_Zt,
+                           (T*)c->d_z, (T*)c->d_LU, c->d_status);
+        return (int)hipGetLastError();
+    };
+    if constexpr (sizeof(T) == 4) {
+        return launch(condense_acoustic_kernel<D, K, R, T, WPB, Pl::SHE, Pl::TBL, Pl::MINB, true>);
+    } else {
+        if (c->cache_factors && c->d_LU)
+            return launch(condense_acoustic_kernel<D, K, R, T, WPB, Pl::SHE, Pl::TBL, Pl::MINB, true>);
+        return launch(condense_acoustic_kernel<D, K, R, T, WPB, Pl::SHE, Pl::TBL, Pl::MINB, false>);
+    }
 }
 
 // wavefronts per workgroup of the refinement kernel: as many as fit next to the shared tables
@@ -1057,11 +1164,38 @@ int launch_refine_acoustic(hdg_ctx* c, const double* lam, const double* dlam, in
     return dispatch_ac_ref(c, lam, dlam, mode, resid, u, nrm);
 }
 
+template <int D, int K, int R, typename T>
+int launch_rh(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* Ef) {
+    constexpr int WPB = 8;
+    auto kern = rhs_acoustic_kernel<D, K, R, T, WPB>;
+    const int64_t groups = (c->n_elem + WPB - 1) / WPB;
+    const int grid = (int)std::min<int64_t>(groups, resident_groups((const void*)kern, 64 * WPB));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WPB), 0, c->stream, c->n_elem, a, c->d_geom, c->d_eperm, Sr, Ef,
+                       (const T*)c->d_Zt, (const T*)c->d_LU, f_loc, (T*)c->d_re, (T*)c->d_z);
+    return (int)hipGetLastError();
+}
+
+template <typename T>
+int dispatch_rh(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* Ef) {
+    const int D = c->dim, K = c->k, R = c->nrhs;
+#define HDG_CASE(DD, KK, RR) \
+    if (D == DD && K == KK && R == RR) return launch_rh<DD, KK, RR, T>(c, a, f_loc, Sr, Ef);
+    HDG_AC_CASES(HDG_CASE)
+#undef HDG_CASE
+    return -1;
+}
+
 int launch_condense_acoustic(hdg_ctx* c, double a, const double* f_loc) {
     c->ke_tile = 16;
     if (c->precision == HDG_FP64)
         return dispatch_ac<double>(c, a, f_loc, c->tab.Sr, c->tab.Mf, c->tab.Tsym, c->tab.Ef);
     return dispatch_ac<float>(c, a, f_loc, c->tab.Sr32, c->tab.Mf32, c->tab.Tsym32, c->tab.Ef32);
+}
+
+int launch_condense_rhs_acoustic(hdg_ctx* c, double a, const double* f_loc) {
+    if (!c->d_LU) return -1;
+    if (c->precision == HDG_FP64) return dispatch_rh<double>(c, a, f_loc, c->tab.Sr, c->tab.Ef);
+    return dispatch_rh<float>(c, a, f_loc, c->tab.Sr32, c->tab.Ef32);
 }
 
 }  // namespace hdg

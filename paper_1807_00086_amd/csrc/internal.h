@@ -103,6 +103,10 @@ struct hdg_ctx {
     // routing: the acoustic kernels of condense_acoustic.hip serve uniform degree with one
     // right-hand side; every other configuration goes through the block-structured kernels
     bool fast_ac = false;
+    // cached factors (acoustic fast path): the condensation also keeps U of every element so
+    // that hdg_condense_rhs can condense a new right-hand side with the same stage coefficient
+    bool cache_factors = false;
+    bool factors_cached = false;   // the last hdg_condense left Z_p, U and K assembled
     // variable polynomial degree (acoustic, 3D): degree classes, compact local offsets, per-face
     // sizes.  n_loc, N, Ns are then the strides of the largest class and NF, bs, n_tr those of
     // the face tables (degree 5); faces of lower degree are padded.
@@ -160,6 +164,10 @@ int launch_residual(hdg_ctx* c, double a, const double* u, const double* lam, co
 // recovery), mode 0 applies the correction dlam, mode 2 none.  nrm: [2 ne] per-element |du|, |u|.
 int launch_refine_acoustic(hdg_ctx* c, const double* lam, const double* dlam, int mode, bool resid,
                            double* u, double* nrm);
+// Right-hand-side condensation with the factors of the last condensation (acoustic fast path):
+// r_e and z for a new f_loc; launch_assemble_rhs then assembles the trace right-hand side only.
+int launch_condense_rhs_acoustic(hdg_ctx* c, double a, const double* f_loc);
+int launch_assemble_rhs(hdg_ctx* c, const double* lam_bnd);
 int launch_assemble_rhs64(hdg_ctx* c, const double* re64);
 int launch_apply_mass(hdg_ctx* c, double a, const double* u, double* f);
 int launch_block_inverse(hdg_ctx* c);

@@ -26,7 +26,8 @@ __device__ __forceinline__ double kget(const T* K, int tt, int r, int c, int kti
     return (ktile > 0 && r / ktile > c / ktile) ? (double)K[c * tt + r] : (double)K[r * tt + c];
 }
 
-template <typename T>
+// MAT = false: the right-hand side only (the matrix of an earlier assembly is kept)
+template <typename T, bool MAT>
 __global__ __launch_bounds__(NT) void assemble_kernel(
     int64_t nf, int d, int bs, int tt, int R, double sign, int ktile, const int32_t* __restrict__ face_elem,
     const int32_t* __restrict__ face_lf, const uint8_t* __restrict__ face_bnd,
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
         int32_t es[2] = {face_elem[2 * F], face_elem[2 * F + 1]};
         int32_t ls[2] = {face_lf[2 * F], face_lf[2 * F + 1]};
         double* B = bsr + (size_t)F * nslot * bs * bs;
-        for (int idx = threadIdx.x; idx < nslot * bs * bs; idx += NT) {
+        for (int idx = threadIdx.x; MAT && idx < nslot * bs * bs; idx += NT) {
             int slot = idx / (bs * bs), rem = idx % (bs * bs);
             int b = rem / bs, a = rem % bs;   // column-major block
             double v = 0.0;
@@ -299,20 +300,24 @@ int resident_groups(const void* kernel, int block) {
     return ncu * per_cu;
 }
 
-int launch_assemble(hdg_ctx* c, const double* lam_bnd) {
+template <bool MAT>
+static int launch_asm(hdg_ctx* c, const double* lam_bnd) {
     int grid = (int)std::min<int64_t>(c->n_faces, 65536);
     if (c->precision == HDG_FP64)
-        hipLaunchKernelGGL((assemble_kernel<double>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
+        hipLaunchKernelGGL((assemble_kernel<double, MAT>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
                            c->bs, c->n_tr, c->nrhs, c->K_sign, c->ke_tile, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
                            c->d_eface, (const double*)c->d_Ke, (const double*)c->d_re, lam_bnd, c->d_face_nf,
                            c->d_bsr, c->d_rhs);
     else
-        hipLaunchKernelGGL((assemble_kernel<float>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
+        hipLaunchKernelGGL((assemble_kernel<float, MAT>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
                            c->bs, c->n_tr, c->nrhs, c->K_sign, c->ke_tile, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
                            c->d_eface, (const float*)c->d_Ke, (const float*)c->d_re, lam_bnd, c->d_face_nf,
                            c->d_bsr, c->d_rhs);
     return (int)hipGetLastError();
 }
+
+int launch_assemble(hdg_ctx* c, const double* lam_bnd) { return launch_asm<true>(c, lam_bnd); }
+int launch_assemble_rhs(hdg_ctx* c, const double* lam_bnd) { return launch_asm<false>(c, lam_bnd); }
 
 int launch_assemble_rhs64(hdg_ctx* c, const double* re64) {
     const int64_t n = c->n_faces * c->bs * c->nrhs;

@@ -26,7 +26,7 @@ Q = dict(n_elem=0, n_faces=1, n_bfaces=2, n_local_dofs=3, n_trace_dofs=4, n_vol_
          n_bnd_points=6, last_iters=7, last_refine=8, m_local=9, m_trace=10)
 
 # every function declared in include/hdg.h
-EXPORTS = ["hdg_init_mesh", "hdg_query", "hdg_condense", "hdg_trace_solve", "hdg_recover",
+EXPORTS = ["hdg_init_mesh", "hdg_query", "hdg_condense", "hdg_condense_rhs", "hdg_trace_solve", "hdg_recover",
            "hdg_step", "hdg_apply_mass", "hdg_volume_points", "hdg_project_volume",
            "hdg_boundary_points", "hdg_project_boundary", "hdg_point_sources",
            "hdg_element_data", "hdg_last_timing", "hdg_reference_table", "hdg_destroy",
@@ -52,7 +52,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("k", C.c_int), ("nrhs", C.c_int),
                 ("krylov_tol", C.c_double), ("krylov_maxit", C.c_int),
                 ("refine_tol", C.c_double), ("refine_maxit", C.c_int),
-                ("refine_inner_tol", C.c_double)]
+                ("refine_inner_tol", C.c_double), ("cache_factors", C.c_int)]
 
 
 _lib = None
@@ -73,6 +73,7 @@ def load_library(path: str = LIB_PATH):
                                  C.POINTER(Options), vp]),
         "hdg_query": (cint, [vp, cint, C.POINTER(i64)]),
         "hdg_condense": (cint, [vp, dbl, vp, vp]),
+        "hdg_condense_rhs": (cint, [vp, dbl, vp, vp]),
         "hdg_trace_solve": (cint, [vp, vp, C.POINTER(cint), C.POINTER(dbl)]),
         "hdg_recover": (cint, [vp, vp, vp]),
         "hdg_step": (cint, [vp, dbl, dbl, cint, vp, vp, vp, vp]),
@@ -120,7 +121,7 @@ class Solver:
 
     def __init__(self, xyz, elem_vert, physics, elem_par, k=None, degree=None, precision="fp64",
                  nrhs=1, stab_scale=1.0, krylov_tol=1e-13, krylov_maxit=5000, refine_tol=1e-13,
-                 refine_maxit=10, refine_inner_tol=1e-6, stream=None):
+                 refine_maxit=10, refine_inner_tol=1e-6, cache_factors=False, stream=None):
         self.lib = load_library()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._ev = np.ascontiguousarray(elem_vert, dtype=np.int64)
@@ -138,7 +139,7 @@ class Solver:
         prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
         od = Options(prec, int(k if k is not None else (int(degree[0]) if degree is not None else 1)),
                      self.nrhs, float(krylov_tol), int(krylov_maxit), float(refine_tol),
-                     int(refine_maxit), float(refine_inner_tol))
+                     int(refine_maxit), float(refine_inner_tol), int(bool(cache_factors)))
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -172,6 +173,10 @@ class Solver:
     # ------------------------------------------------------------------ path
     def condense(self, a, f_loc, lam_bnd):
         self._check(self.lib.hdg_condense(self.ctx, float(a), _ptr(f_loc), _ptr(lam_bnd)))
+
+    def condense_rhs(self, a, f_loc, lam_bnd):
+        """Condense a new right-hand side with the factors of the last condense (same a)."""
+        self._check(self.lib.hdg_condense_rhs(self.ctx, float(a), _ptr(f_loc), _ptr(lam_bnd)))
 
     def trace_solve(self, lam):
         it = C.c_int()
