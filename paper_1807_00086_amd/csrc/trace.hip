@@ -192,6 +192,51 @@ __global__ __launch_bounds__(NT) void bsr_spmv_kernel(int64_t nf, int nslot, int
     y[gid] = acc;
 }
 
+// The same with the block size and the blocks per row fixed at compile time: the row's
+// NS * BS matrix loads are independent and unrolled (slots without a neighbour read a valid
+// x entry whose product is discarded).
+template <int BS, int NS>
+__global__ __launch_bounds__(NT) void bsr_spmv_fixed_kernel(int64_t nf, int R, const int32_t* __restrict__ cols,
+                                                            const double* __restrict__ bsr,
+                                                            const double* __restrict__ x, double* __restrict__ y) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nf * BS * R) return;
+    const int r = (int)(gid % R);
+    const int64_t Fa = gid / R;
+    const int64_t F = Fa / BS;
+    const int a = (int)(Fa % BS);
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int32_t cF = cols[F * NS + s];
+        const double* B = bsr + ((size_t)F * NS + s) * BS * BS + a;
+        const double* xv = x + (size_t)max(cF, 0) * BS * R + r;
+        double t = 0.0;
+#pragma unroll
+        for (int b = 0; b < BS; ++b) t += B[b * BS] * xv[b * R];
+        acc += cF >= 0 ? t : 0.0;
+    }
+    y[gid] = acc;
+}
+
+template <int BS>
+__global__ __launch_bounds__(NT) void block_apply_fixed_kernel(int64_t nf, int R, const double* __restrict__ pinv,
+                                                               const double* __restrict__ x,
+                                                               double* __restrict__ y) {
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nf * BS * R) return;
+    const int r = (int)(gid % R);
+    const int64_t Fa = gid / R;
+    const int64_t F = Fa / BS;
+    const int a = (int)(Fa % BS);
+    const double* B = pinv + (size_t)F * BS * BS + a;
+    const double* xv = x + (size_t)F * BS * R + r;
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < BS; ++b) acc += B[b * BS] * xv[b * R];
+    y[gid] = acc;
+}
+
 __global__ __launch_bounds__(NT) void block_apply_kernel(int64_t nf, int bs, int R,
                                                          const double* __restrict__ pinv,
                                                          const double* __restrict__ x,
@@ -334,14 +379,36 @@ int launch_block_inverse(hdg_ctx* c) {
     return (int)hipGetLastError();
 }
 
+// block sizes of the built 3D configurations (m_trace * N_F: acoustic k = 1..5, Maxwell
+// k = 3, elastic k = 4) get the fixed-size kernels
+#define HDG_BS_CASES(X) X(3) X(6) X(10) X(15) X(20) X(21) X(45)
+
 static void spmv(hdg_ctx* c, const double* x, double* y) {
     int64_t n = c->n_faces * c->bs * c->nrhs;
+    if (c->nslot == 7) {
+#define HDG_BS(B)                                                                                          \
+    if (c->bs == B) {                                                                                      \
+        hipLaunchKernelGGL((bsr_spmv_fixed_kernel<B, 7>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, \
+                           c->nrhs, c->d_bsr_cols, c->d_bsr, x, y);                                       \
+        return;                                                                                            \
+    }
+        HDG_BS_CASES(HDG_BS)
+#undef HDG_BS
+    }
     hipLaunchKernelGGL(bsr_spmv_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->nslot, c->bs,
                        c->nrhs, c->d_bsr_cols, c->d_bsr, x, y);
 }
 
 static void precond(hdg_ctx* c, const double* x, double* y) {
     int64_t n = c->n_faces * c->bs * c->nrhs;
+#define HDG_BS(B)                                                                                            \
+    if (c->bs == B) {                                                                                        \
+        hipLaunchKernelGGL((block_apply_fixed_kernel<B>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces,   \
+                           c->nrhs, c->d_pinv, x, y);                                                        \
+        return;                                                                                              \
+    }
+    HDG_BS_CASES(HDG_BS)
+#undef HDG_BS
     hipLaunchKernelGGL(block_apply_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->bs, c->nrhs,
                        c->d_pinv, x, y);
 }
