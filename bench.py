@@ -228,6 +228,60 @@ def run_cached(p, prec, steps, warmup, refine_tol=1e-11):
     return out
 
 
+def run_workload(cfg, prec, steps, warmup):
+    """Element-kernel throughput of one of the other workloads at full size (secondary figures,
+    not the headline): elastic k = 4 (3), p-heterogeneous acoustics with 32 point-source
+    right-hand sides (4), Maxwell k = 3 (5).  Seeded random stage right-hand side (point
+    sources for workload 4) and homogeneous Dirichlet data; the trace solves run to 1e-10 (the
+    element kernels do not depend on it)."""
+    import torch
+
+    from paper_1807_00086_amd import Solver
+    from synth import make_problem, random_vector
+    p = make_problem(cfg)
+    a = 1.0 / (GAMMA * p.dt) if p.scheme == "dirk33" else 1.0 / p.dt
+    kw = dict(krylov_tol=1e-10, krylov_maxit=20000)
+    if prec != "fp64":
+        kw.update(refine_tol=1e-11)
+    uk = p.uniform_k
+    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=uk, degree=None if uk else p.degree,
+               precision=prec, nrhs=p.nrhs, **kw)
+    nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+    if p.nrhs > 1:
+        f = torch.as_tensor(s.point_sources(p.sources), device="cuda")
+    else:
+        f = torch.as_tensor(random_vector(nl, cfg, 1), device="cuda")
+    lb = torch.zeros(nt * p.nrhs, dtype=torch.float64, device="cuda")
+    lam = torch.zeros_like(lb)
+    u = torch.zeros(nl * p.nrhs, dtype=torch.float64, device="cuda")
+
+    def stage():
+        s.condense(a, f, lb)
+        lam.zero_()
+        it, _ = s.trace_solve(lam)
+        s.recover(lam, u)
+        return it
+
+    for _ in range(warmup):
+        stage()
+    torch.cuda.synchronize()
+    tm = dict(condense=0.0, recover=0.0, assemble=0.0, solve=0.0, refine_elem=0.0, refine_solve=0.0)
+    its = []
+    for _ in range(steps):
+        its.append(stage())
+        for key in tm:
+            tm[key] += s.timing(key)
+    torch.cuda.synchronize()
+    refine = s.query("last_refine")
+    s.close()
+    del f, lb, lam, u
+    torch.cuda.empty_cache()
+    out = {k2: v / steps for k2, v in tm.items()}
+    out.update(workload=p.name, elements=p.n_elem, nrhs=p.nrhs, iters=float(np.mean(its)), refine=refine,
+               elements_per_s=p.n_elem / ((out["condense"] + out["recover"] + out["refine_elem"]) * 1e-3))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +293,9 @@ def main():
                     help="mixed precision: refinement stopping tolerance (the result is checked "
                          "against FP64 to 1e-10 before mixed can be the headline)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--all-workloads", action="store_true",
+                    help="also time the element kernels of the other workloads (elastic k=4, "
+                         "p-heterogeneous 32-rhs acoustics, Maxwell k=3) at full size")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -332,6 +389,12 @@ def main():
                  "(right-hand-side condensation + recover [+ refinement element passes]); "
                  "one factorisation per dt, not per stage",
         **{pr: run_cached(p, pr, args.steps, args.warmup, args.refine_tol) for pr in precs}}
+    if args.all_workloads:
+        out["other_workloads"] = {}
+        for cfg in (3, 4, 5):
+            for pr in ("fp64", "mixed_fp32"):
+                out["other_workloads"][f"{cfg}_{pr}"] = w = run_workload(cfg, pr, 2, 1)
+                print(f"workload {cfg} {pr}: {w['elements_per_s']:.4g} elements/s", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, a, args.cpu_budget)
     print(json.dumps(out))
