@@ -746,9 +746,12 @@ struct RfScratch {
     double vv[D * N * R];         // v
     double nv[NFACE * N * R];     // n_f . v
     double El[SHE ? 1 : NFACE * N * NF];
-    // Z_p, rows padded to an odd stride: a lane per row reads distinct LDS banks
-    static constexpr int ZS = (Dm::TT % 2 == 0) ? Dm::TT + 1 : Dm::TT;
-    T Zl[N * ZS];
+    // Z_p, rows padded so that a lane per row reads distinct LDS banks: FP64 an odd stride;
+    // FP32 a multiple of four floats with an odd quotient, so rows stay 16-byte aligned for
+    // 128-bit reads and eight consecutive lanes cover the 32 banks once
+    static constexpr int ZS = sizeof(T) == 8 ? ((Dm::TT % 2 == 0) ? Dm::TT + 1 : Dm::TT)
+                                             : ((Dm::TT + 3) / 4 % 2 == 1 ? (Dm::TT + 3) / 4 * 4 : (Dm::TT + 3) / 4 * 4 + 4);
+    alignas(16) T Zl[N * ZS];
     T zb[N * R];                  // z'_p on entry
     T Ll[RESID ? N * N : 1];      // U = diag(d) L_u^T of S = L_u diag(d) L_u^T, 1/d_j on the
                                   // diagonal, column-major
