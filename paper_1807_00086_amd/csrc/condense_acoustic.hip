@@ -726,6 +726,10 @@ __global__ __launch_bounds__(64 * WPB, 2) void rhs_acoustic_kernel(
 // pipeline, one element per wavefront), so the compute phases read LDS only.  The oriented
 // face tables of all orientations are shared by the workgroup when they are small.
 
+// row stride of the refinement kernel's LDS copy of Sr: 2 x odd doubles (16-byte aligned rows
+// whose 128-bit reads by a lane per row hit distinct LDS banks for eight consecutive lanes)
+constexpr int rf_sr_stride(int n) { return ((n + 1) / 2 % 2 == 1) ? (n + 1) / 2 * 2 : (n + 1) / 2 * 2 + 2; }
+
 template <int D, int K>
 constexpr bool rf_shared_faces() {
     return (D + 1) * ((D == 3) ? 6 : 2) * dimp(K, D) * dimp(K, D - 1) * 8 <= 48 * 1024;
@@ -799,10 +803,11 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
     using Scr = RfScratch<D, K, R, T, RESID>;
     constexpr int SDN = PerLane<D * N>::n;
     static_assert(R == 1 && TT <= 64 && N <= 64, "one right-hand side; trace and Schur vectors fit a wavefront");
-    __shared__ double Srs[D * N * N];
+    constexpr int SS = rf_sr_stride(N);
+    __shared__ double Srs[D * N * SS];
     __shared__ double Efs[SHE ? NFACE * NPERM * N * NF : 1];
     __shared__ Scr scr_all[WPB];
-    for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[idx] = Sr[idx];
+    for (int idx = threadIdx.x; idx < D * N * N; idx += 64 * WPB) Srs[(idx / N) * SS + idx % N] = Sr[idx];
     if (SHE)
         for (int idx = threadIdx.x; idx < NFACE * NPERM * N * NF; idx += 64 * WPB) Efs[idx] = Ef[idx];
     __syncthreads();
@@ -955,7 +960,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
         for (int t = 0; t < SDN; ++t) {
             const int idx = min(lane + 64 * t, D * N - 1);
             const int r = idx / N, i = idx - r * N;
-            const double y = dot4<N>([&](int j) { return Srs[(r * N + j) * N + i] * bcast(pv, j); });
+            const double y = dot4<N>([&](int j) { return Srs[(r * N + j) * SS + i] * bcast(pv, j); });
             if (lane + 64 * t < D * N) sc.yp[idx] = y;
         }
         double epv = 0.0;
@@ -1016,7 +1021,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
                 const int i = il;
                 const double qv = dot4<D * N>([&](int rj) {
                     const int r = rj / N, j = rj - r * N;
-                    return Srs[(r * N + i) * N + j] * bcast(gvv[rj / 64], rj % 64);
+                    return Srs[(r * N + i) * SS + j] * bcast(gvv[rj / 64], rj % 64);
                 });
                 const double fe = dot4<NFACE * NF>([&](int fl) {
                     const int fc = fl / NF, l = fl - fc * NF;
@@ -1108,7 +1113,7 @@ template <int D, int K, typename T, bool RESID>
 constexpr int rf_wpb() {
     constexpr int N = dimp(K, D), NF = dimp(K, D - 1);
     constexpr int sb = (int)sizeof(RfScratch<D, K, 1, T, RESID>);
-    constexpr int tb = (D * N * N + (rf_shared_faces<D, K>() ? (D + 1) * ((D == 3) ? 6 : 2) * N * NF : 0)) * 8;
+    constexpr int tb = (D * N * rf_sr_stride(N) + (rf_shared_faces<D, K>() ? (D + 1) * ((D == 3) ? 6 : 2) * N * NF : 0)) * 8;
     constexpr int w = (160 * 1024 - tb) / sb;
     return w >= 8 ? 8 : (w < 1 ? 1 : w);
 }
