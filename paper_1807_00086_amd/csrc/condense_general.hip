@@ -879,7 +879,9 @@ constexpr int gen_sg() {
                             sizeof(Coef<PHYS>) + 8 * 64;
     constexpr size_t mid = base + sizeof(T) * (Dm::SBUF + Dm::N1 * R);
     constexpr size_t all = mid + sizeof(T) * Dm::N2 * Dm::C;
-    return all <= 150 * 1024 ? 0 : (mid <= 150 * 1024 ? 1 : 2);
+    // at most 75 KB of LDS per workgroup, so that two workgroups share a CU: the element
+    // buffers that do not fit go to per-workgroup global scratch (L2-resident)
+    return all <= 75 * 1024 ? 0 : (mid <= 75 * 1024 ? 1 : 2);
 }
 
 template <int PHYS, int K, int KF, int R, typename T>
