@@ -283,6 +283,7 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
     __shared__ Coef<PHYS> cf;
     __shared__ double geo[GEOM_STRIDE];
     __shared__ double frm[24];
+    __shared__ T dinv[N2];
     T* gsc = Xglob + (size_t)blockIdx.x * gen_gstride<PHYS, K, KF, R>(SG);
     T* X = SG >= 1 ? gsc : Xl;
     T* Sb = SG >= 2 ? gsc + (int64_t)N2 * C : Sbl;
@@ -404,25 +405,47 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
         }
         if (Lout)
             for (int idx = tid; idx < N2 * N2; idx += NTG) Lout[e * strL + idx] = Sb[idx];
-        // ------------------------------------------------------------ [W | w] = L^{-1} [B~2 | f~2] (blocked)
-        constexpr int BS = 8;
-        for (int b0 = 0; b0 < N2; b0 += BS) {
-            const int be = min(b0 + BS, N2);
-            for (int c = tid; c < C; c += NTG)
-                for (int i = b0; i < be; ++i) {
-                    T s = X[i * C + c];
-                    for (int m = b0; m < i; ++m) s -= Sb[i * N2 + m] * X[m * C + c];
-                    X[i * C + c] = s / Sb[i * N2 + i];
-                }
-            __syncthreads();
-            for (int idx = tid; idx < (N2 - be) * C; idx += NTG) {
-                const int i = be + idx / C, c = idx % C;
-                T s = 0;
-                for (int m = b0; m < be; ++m) s += Sb[i * N2 + m] * X[m * C + c];
-                X[i * C + c] -= s;
-            }
-            __syncthreads();
+        // ------------------------------------------------------------ [W | w] = L^{-1} [B~2 | f~2]
+        // One column per thread, 16 rows at a time: the diagonal block is solved in registers
+        // and its rows update the rest of the thread's own column (no barrier inside the
+        // solve); the factor is read by broadcast from LDS.  The upper triangle of Sb receives
+        // L^T for the backward solve.
+        constexpr int BR = 16, NBR = (N2 + BR - 1) / BR;
+        __syncthreads();
+        for (int idx = tid; idx < N2 * N2; idx += NTG) {
+            const int i = idx / N2, m = idx - i * N2;
+            if (m > i) Sb[idx] = Sb[m * N2 + i];
         }
+        for (int i = tid; i < N2; i += NTG) dinv[i] = T(1) / Sb[i * N2 + i];
+        __syncthreads();
+        for (int c = tid; c < C; c += NTG) {
+#pragma unroll 1
+            for (int kb = 0; kb < NBR; ++kb) {
+                const int r0 = kb * BR;
+                T xb[BR];
+#pragma unroll
+                for (int u = 0; u < BR; ++u) xb[u] = r0 + u < N2 ? X[(r0 + u) * C + c] : T(0);
+#pragma unroll
+                for (int u = 0; u < BR; ++u) {
+                    if (r0 + u >= N2) break;
+                    const T* Lr = &Sb[(r0 + u) * N2 + r0];
+                    T s = xb[u];
+#pragma unroll
+                    for (int m = 0; m < u; ++m) s -= Lr[m] * xb[m];
+                    xb[u] = s * dinv[r0 + u];
+                    X[(r0 + u) * C + c] = xb[u];
+                }
+#pragma unroll 2
+                for (int i = r0 + BR; i < N2; ++i) {
+                    const T* Lr = &Sb[i * N2 + r0];
+                    T s = X[i * C + c];
+#pragma unroll
+                    for (int m = 0; m < BR; ++m) s -= Lr[m] * xb[m];
+                    X[i * C + c] = s;
+                }
+            }
+        }
+        __syncthreads();
         // ------------------------------------------------------------ K_e, r_e
         {
             const T j1 = (T)cf.j1;
@@ -499,24 +522,36 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
             }
         }
         __syncthreads();
-        // ------------------------------------------------------------ Z2 = L^{-T} W, z2 = L^{-T} w (blocked)
-        for (int b1 = N2; b1 > 0; b1 -= BS) {
-            const int bs0 = max(b1 - BS, 0);
-            for (int c = tid; c < C; c += NTG)
-                for (int i = b1 - 1; i >= bs0; --i) {
-                    T s = X[i * C + c];
-                    for (int m = i + 1; m < b1; ++m) s -= Sb[m * N2 + i] * X[m * C + c];
-                    X[i * C + c] = s / Sb[i * N2 + i];
+        // ------------------------------------------------------------ Z2 = L^{-T} W, z2 = L^{-T} w
+        // the same by blocks of rows from the bottom, with L^T from the upper triangle of Sb
+        for (int c = tid; c < C; c += NTG) {
+#pragma unroll 1
+            for (int kb = NBR - 1; kb >= 0; --kb) {
+                const int r0 = kb * BR;
+                T xb[BR];
+#pragma unroll
+                for (int u = 0; u < BR; ++u) xb[u] = r0 + u < N2 ? X[(r0 + u) * C + c] : T(0);
+#pragma unroll
+                for (int u = BR - 1; u >= 0; --u) {
+                    if (r0 + u >= N2) continue;
+                    const T* Lr = &Sb[(r0 + u) * N2 + r0];   // row r0+u of L^T
+                    T s = xb[u];
+#pragma unroll
+                    for (int m = u + 1; m < BR; ++m) s -= (r0 + m < N2 ? Lr[m] : T(0)) * xb[m];
+                    xb[u] = s * dinv[r0 + u];
+                    X[(r0 + u) * C + c] = xb[u];
                 }
-            __syncthreads();
-            for (int idx = tid; idx < bs0 * C; idx += NTG) {
-                const int i = idx / C, c = idx % C;
-                T s = 0;
-                for (int m = bs0; m < b1; ++m) s += Sb[m * N2 + i] * X[m * C + c];
-                X[i * C + c] -= s;
+#pragma unroll 2
+                for (int i = 0; i < r0; ++i) {
+                    const T* Lr = &Sb[i * N2 + r0];          // row i of L^T, columns of the block
+                    T s = X[i * C + c];
+#pragma unroll
+                    for (int m = 0; m < BR; ++m) s -= (r0 + m < N2 ? Lr[m] : T(0)) * xb[m];
+                    X[i * C + c] = s;
+                }
             }
-            __syncthreads();
         }
+        __syncthreads();
         T* Zse = Zs + e * strZ;
         for (int idx = tid; idx < N2 * TT; idx += NTG) Zse[idx] = X[(idx / TT) * C + idx % TT];
         T* zse = zs + e * strz;
