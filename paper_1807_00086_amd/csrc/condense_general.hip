@@ -43,6 +43,17 @@ namespace {
 constexpr int NTG = 256;
 constexpr int PH_ACOUSTIC = 0, PH_ELASTIC = 1, PH_MAXWELL = 2;
 
+// Broadcast of lane `src`'s value within the wavefront (src uniform)
+__device__ __forceinline__ double wbcast(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float wbcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 template <int PHYS>
 struct PhysDims;
 template <>
@@ -377,6 +388,42 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
         }
         __syncthreads();
         // ------------------------------------------------------------ Cholesky S = L L^T
+        // N2 <= 64: one wavefront, lane c holding column c of S in registers, Gaussian
+        // elimination without pivoting (S = L_u diag(d) L_u^T) with readlane broadcasts; lane c
+        // then writes row c of L = L_u diag(d)^{1/2} (L[c][j] = U[j][c] / sqrt(d_j), U =
+        // diag(d) L_u^T the eliminated rows).  Larger blocks: right-looking with barriers.
+        if constexpr (N2 <= 64) {
+            __syncthreads();
+            if (tid < 64) {
+                const int lane = tid, cl = min(lane, N2 - 1);
+                T x[N2];
+#pragma unroll
+                for (int i = 0; i < N2; ++i) x[i] = Sb[cl * N2 + i];   // row cl = column cl
+                T dmax = lane < N2 ? fabs(Sb[cl * N2 + cl]) : T(0);
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+                const T ptol = T(64 * N2) * geps<T>() * dmax;
+                T dl = T(1);
+                bool bad = false;
+#pragma unroll
+                for (int j = 0; j < N2; ++j) {
+                    const T p = wbcast(x[j], j);
+                    bad |= !(p > ptol && p - p == T(0));
+                    dl = lane == j ? p : dl;
+                    const T t = x[j] / p;
+#pragma unroll
+                    for (int i = j + 1; i < N2; ++i) x[i] -= wbcast(x[i], j) * t;
+                }
+                if (bad && lane == 0) atomicOr(status, 1);
+                const T isq = T(1) / sqrt(dl);
+#pragma unroll
+                for (int j = 0; j < N2; ++j) {
+                    const T sj = wbcast(isq, j);
+                    if (lane < N2 && j <= lane) Sb[lane * N2 + j] = x[j] * sj;
+                }
+            }
+            __syncthreads();
+        } else
         {
             T dmax = 0;
             for (int i = 0; i < N2; ++i) dmax = fmax(dmax, fabs(Sb[i * N2 + i]));
