@@ -16,7 +16,7 @@ OUT = os.path.join(HERE, "libhdg.so")
 OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["reftab.cpp", "mesh.cpp", "capi.cpp", "condense_acoustic.hip", "condense_general.hip", "trace.hip",
+SOURCES = ["reftab.cpp", "mesh.cpp", "capi.cpp", "condense_acoustic.hip", "condense_general.hip", "recover_mrhs.hip", "trace.hip",
            "stage.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",

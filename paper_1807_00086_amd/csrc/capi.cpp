@@ -63,9 +63,26 @@ int upload_f32(hdg_ctx* c, float** p, const std::vector<double>& h) {
     return upload(c, p, f);
 }
 
+// transposed FP64 copies of Sr and of the oriented face tables (3D)
+int upload_transposed(hdg_ctx* c, DeviceTables& t, const RefTables& ref, const RefFaceTables& ef) {
+    if (ref.d != 3) return HDG_OK;
+    const int N = ref.N, NF = ef.NF, P = ef.nperm;
+    std::vector<double> st(ref.Sr.size()), et(ef.E.size());
+    for (int r = 0; r < 3; ++r)
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) st[((size_t)r * N + j) * N + i] = ref.Sr[((size_t)r * N + i) * N + j];
+    for (int fp = 0; fp < 4 * P; ++fp)
+        for (int i = 0; i < N; ++i)
+            for (int l = 0; l < NF; ++l) et[((size_t)fp * NF + l) * N + i] = ef.E[((size_t)fp * N + i) * NF + l];
+    int s = HDG_OK;
+    if ((s = upload(c, &t.SrT, st)) || (s = upload(c, &t.EfT, et))) return s;
+    return HDG_OK;
+}
+
 // FP64 and FP32 copies of the reference tables of one degree
 int upload_tables(hdg_ctx* c, DeviceTables& t, const RefTables& ref, const RefFaceTables& ef) {
-    int s = HDG_OK;
+    int s = upload_transposed(c, t, ref, ef);
+    if (s) return s;
     if ((s = upload(c, &t.Sr, ref.Sr)) || (s = upload(c, &t.Mf, ref.Mf)) || (s = upload(c, &t.Tsym, ref.Tsym)) ||
         (s = upload(c, &t.Ef, ef.E)) || (s = upload(c, &t.Tfull, ref.Tfull)) || (s = upload_f32(c, &t.Sr32, ref.Sr)) ||
         (s = upload_f32(c, &t.Mf32, ref.Mf)) || (s = upload_f32(c, &t.Tsym32, ref.Tsym)) ||
@@ -251,6 +268,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(upload_f32(c, &c->tab.Ef32, c->reff.E));
     TRY(upload(c, &c->tab.Tfull, c->ref.Tfull));
     TRY(upload_f32(c, &c->tab.Tfull32, c->ref.Tfull));
+    TRY(upload_transposed(c, c->tab, c->ref, c->reff));
     if (c->vardeg) {
         std::vector<int8_t> edeg(c->degree.begin(), c->degree.end());
         TRY(upload(c, &c->d_loc_off, c->loc_off_h));
@@ -818,7 +836,7 @@ void hdg_destroy(hdg_ctx* c) {
     if (!c) return;
     void* ptrs[] = {c->d_geom, c->d_eface, c->d_eperm, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
                     c->d_bsr_cols, c->tab.Sr, c->tab.Mf, c->tab.Tsym, c->tab.Ef, c->tab.Sr32, c->tab.Mf32,
-                    c->tab.Tsym32, c->tab.Ef32, c->tab.Tfull, c->tab.Tfull32, c->d_eframe, c->d_xscratch, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
+                    c->tab.Tsym32, c->tab.Ef32, c->tab.Tfull, c->tab.Tfull32, c->tab.SrT, c->tab.EfT, c->d_eframe, c->d_xscratch, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
                     c->d_bsr, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
                     c->d_scal, c->d_f_saved, c->d_lbnd_saved, c->d_su, c->d_slam, c->d_du, c->d_dlam,
                     c->d_re64, c->d_sq,
@@ -827,7 +845,7 @@ void hdg_destroy(hdg_ctx* c) {
     if (c->stream || c->d_geom) (void)hipStreamSynchronize(c->stream);
     for (void* p : ptrs) dfree(p);
     for (auto& t : c->tabk) {
-        void* tp[] = {t.Sr, t.Mf, t.Tsym, t.Ef, t.Tfull, t.Sr32, t.Mf32, t.Tsym32, t.Ef32, t.Tfull32};
+        void* tp[] = {t.Sr, t.Mf, t.Tsym, t.Ef, t.Tfull, t.Sr32, t.Mf32, t.Tsym32, t.Ef32, t.Tfull32, t.SrT, t.EfT};
         for (void* p : tp) dfree(p);
     }
     if (c->ev0) (void)hipEventDestroy(c->ev0);

@@ -1019,10 +1019,13 @@ int launch_gen_ref(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int
 // built configurations: (physics, volume degree, face-table degree, right-hand sides).
 // Uniform meshes use face degree = volume degree; meshes of variable degree (acoustic) use
 // face tables of degree 5 for every class.
-#define HDG_GEN_CASES(X)                                                                            \
+// The acoustic cases with 32 right-hand sides recover and refine in recover_mrhs.hip.
+#define HDG_GEN_CASES_R1(X)                                                                         \
     X(1, 1, 1, 1) X(1, 2, 2, 1) X(1, 3, 3, 1) X(1, 4, 4, 1) X(2, 1, 1, 1) X(2, 2, 2, 1) X(2, 3, 3, 1) \
+    X(0, 1, 5, 1) X(0, 2, 5, 1) X(0, 3, 5, 1) X(0, 4, 5, 1) X(0, 5, 5, 1)
+#define HDG_GEN_CASES(X)                                                                            \
+    HDG_GEN_CASES_R1(X)                                                                             \
     X(0, 1, 1, 32) X(0, 2, 2, 32) X(0, 3, 3, 32) X(0, 4, 4, 32)                                       \
-    X(0, 1, 5, 1) X(0, 2, 5, 1) X(0, 3, 5, 1) X(0, 4, 5, 1) X(0, 5, 5, 1)                             \
     X(0, 1, 5, 32) X(0, 2, 5, 32) X(0, 3, 5, 32) X(0, 4, 5, 32) X(0, 5, 5, 32)
 
 constexpr int VAR_KF = 5;
@@ -1058,7 +1061,7 @@ int dispatch_gen_rec(hdg_ctx* c, const double* lam, double* u) {
     return for_each_class(c, [&](int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n) {
 #define HDG_CASE(PP, KK, FF, RR) \
     if (P == PP && K == KK && KF == FF && R == RR) return launch_gen_rec<PP, KK, FF, RR, T>(c, tb, el, n, lam, u);
-        HDG_GEN_CASES(HDG_CASE)
+        HDG_GEN_CASES_R1(HDG_CASE)
 #undef HDG_CASE
         return -1;
     });
@@ -1069,7 +1072,7 @@ int dispatch_gen_ref(hdg_ctx* c, const double* u, const double* lam) {
     return for_each_class(c, [&](int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n) {
 #define HDG_CASE(PP, KK, FF, RR) \
     if (P == PP && K == KK && KF == FF && R == RR) return launch_gen_ref<PP, KK, FF, RR, float>(c, tb, el, n, u, lam);
-        HDG_GEN_CASES(HDG_CASE)
+        HDG_GEN_CASES_R1(HDG_CASE)
 #undef HDG_CASE
         return -1;
     });
@@ -1079,6 +1082,7 @@ int dispatch_gen_ref(hdg_ctx* c, const double* u, const double* lam) {
 
 int launch_refine_general(hdg_ctx* c, const double* u, const double* lam) {
     if (c->precision != HDG_MIXED_FP32) return -1;
+    if (mr_supported(c)) return launch_refine_mr(c, u, lam);
     return dispatch_gen_ref(c, u, lam);
 }
 
@@ -1098,6 +1102,7 @@ int launch_condense_general(hdg_ctx* c, double a, const double* f_loc) {
 }
 
 int launch_recover_general(hdg_ctx* c, const double* lam, double* u) {
+    if (mr_supported(c)) return launch_recover_mr(c, lam, u);
     if (c->precision == HDG_FP64) return dispatch_gen_rec<double>(c, lam, u);
     return dispatch_gen_rec<float>(c, lam, u);
 }

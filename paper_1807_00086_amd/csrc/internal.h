@@ -29,6 +29,8 @@ struct DeviceTables {         // one polynomial degree (uniform meshes: face deg
     double* Tfull = nullptr;
     float *Sr32 = nullptr, *Mf32 = nullptr, *Tsym32 = nullptr, *Ef32 = nullptr;
     float* Tfull32 = nullptr;
+    // transposed FP64 copies (3D): SrT[r][j][i] = Sr[r][i][j], EfT[f][p][l][i] = Ef[f][p][i][l]
+    double *SrT = nullptr, *EfT = nullptr;
 };
 
 struct Timings {
@@ -186,4 +188,8 @@ int var_face_degree();   // face-table degree used on meshes of variable degree
 int launch_condense_general(hdg_ctx* c, double a, const double* f_loc);
 int launch_recover_general(hdg_ctx* c, const double* lam, double* u);
 int launch_refine_general(hdg_ctx* c, const double* u, const double* lam);
+// recover_mrhs.hip (acoustic, 3D, 32 right-hand sides: matrix-core recovery and refinement)
+bool mr_supported(const hdg_ctx* c);
+int launch_recover_mr(hdg_ctx* c, const double* lam, double* u);
+int launch_refine_mr(hdg_ctx* c, const double* u, const double* lam);
 }  // namespace hdg

@@ -103,9 +103,11 @@ def test_pvar_stage_parity(nxyz, R, prec):
     s.close()
 
 
-@pytest.mark.parametrize("k,prec", [(2, "fp64"), (3, "mixed_fp32")])
+@pytest.mark.parametrize("k,prec", [(1, "fp64"), (2, "fp64"), (4, "fp64"), (1, "mixed_fp32"), (3, "mixed_fp32"),
+                                    (4, "mixed_fp32")])
 def test_uniform_acoustic3d_32_rhs(k, prec):
-    """Uniform degree with 32 right-hand sides runs through the block-structured kernels."""
+    """Uniform degree with 32 right-hand sides: block-structured condensation, matrix-core
+    recovery and refinement (every degree is its own kernel instantiation)."""
     _need_gpu()
     from oracle import hdg as ohdg
     from paper_1807_00086_amd import Solver
