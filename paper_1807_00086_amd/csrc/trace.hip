@@ -219,6 +219,61 @@ __global__ __launch_bounds__(NT) void bsr_spmv_fixed_kernel(int64_t nf, int R, c
     y[gid] = acc;
 }
 
+// The same products for 32 right-hand sides: one wavefront per block row (face) F, its
+// BS x 32 output as 16x16x4 FP64 MFMA tiles over (block rows, right-hand sides); the stored
+// blocks are column-major (entry (a, b) at b BS + a), so the 16 lanes of an A-operand column
+// read consecutive entries, and the B operands are 16 consecutive right-hand sides of a row of
+// x.  NS = 1 with cols null applies the block diagonal (the preconditioner).  Rows and
+// columns past BS are clamped on load (padded k rows of x are zero, padded output rows dropped).
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+
+template <int BS, int NS>
+__global__ __launch_bounds__(256) void bsr_spmm32_kernel(int64_t nf, const int32_t* __restrict__ cols,
+                                                         const double* __restrict__ bsr,
+                                                         const double* __restrict__ x, double* __restrict__ y) {
+    constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4, R = 32;
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int64_t F = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (F >= nf) return;   // whole wavefronts
+    mf64x4 acc[MT][2];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = mf64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int s = 0; s < NS; ++s) {
+        const int cF = cols ? __builtin_amdgcn_readfirstlane(cols[F * NS + s]) : (int)F;
+        if (cF < 0) continue;
+        const double* B = bsr + ((size_t)F * NS + s) * BS * BS;
+        const double* xv = x + (size_t)cF * BS * R;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            const int b = min(4 * kk + lg, BS - 1);
+            const bool bok = 4 * kk + lg < BS;
+            double xb[2];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const double t = xv[b * R + 16 * nt + lr];
+                xb[nt] = bok ? t : 0.0;
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const double av = B[b * BS + min(16 * mt + lr, BS - 1)];
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xb[nt], acc[mt][nt], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = 16 * mt + lg + 4 * v;
+                if (a < BS) y[((size_t)F * BS + a) * R + 16 * nt + lr] = acc[mt][nt][v];
+            }
+}
+
 template <int BS>
 __global__ __launch_bounds__(NT) void block_apply_fixed_kernel(int64_t nf, int R, const double* __restrict__ pinv,
                                                                const double* __restrict__ x,
@@ -259,19 +314,28 @@ __global__ __launch_bounds__(NT) void block_apply_kernel(int64_t nf, int bs, int
 __global__ __launch_bounds__(NT) void dot_partial_kernel(int64_t n, int R, const double* __restrict__ x,
                                                          const double* __restrict__ y,
                                                          double* __restrict__ part) {
+    // thread t of a block owns column t % R of rows t / R, t / R + T, ... (T = NT / R rows per
+    // pass): consecutive threads read consecutive entries of the row-major [n][R] vectors
     __shared__ double sh[NT];
-    for (int r = 0; r < R; ++r) {
-        double acc = 0.0;
-        for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    const int T = NT / R, t = threadIdx.x;
+    double acc = 0.0;
+    if (t < T * R) {
+        const int r = t % R;
+        for (int64_t i = (int64_t)blockIdx.x * T + t / R; i < n; i += (int64_t)gridDim.x * T)
             acc += x[i * R + r] * y[i * R + r];
-        sh[threadIdx.x] = acc;
-        __syncthreads();
+    }
+    sh[t] = acc;
+    __syncthreads();
+    if (R == 1) {
         for (int s = NT / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+            if (t < s) sh[t] += sh[t + s];
             __syncthreads();
         }
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * R + r] = sh[0];
-        __syncthreads();
+        if (t == 0) part[blockIdx.x] = sh[0];
+    } else if (t < R) {
+        double s = 0.0;
+        for (int k = 0; k < T; ++k) s += sh[k * R + t];
+        part[(size_t)blockIdx.x * R + t] = s;
     }
 }
 
@@ -383,8 +447,20 @@ int launch_block_inverse(hdg_ctx* c) {
 // k = 3, elastic k = 4) get the fixed-size kernels
 #define HDG_BS_CASES(X) X(3) X(6) X(10) X(15) X(20) X(21) X(45)
 
+static int64_t nblk_faces(const hdg_ctx* c) { return (c->n_faces + 3) / 4; }
+
 static void spmv(hdg_ctx* c, const double* x, double* y) {
     int64_t n = c->n_faces * c->bs * c->nrhs;
+    if (c->nslot == 7 && c->nrhs == 32) {
+#define HDG_BS(B)                                                                                          \
+    if (c->bs == B) {                                                                                      \
+        hipLaunchKernelGGL((bsr_spmm32_kernel<B, 7>), dim3(nblk_faces(c)), dim3(256), 0, c->stream,           \
+                           c->n_faces, c->d_bsr_cols, c->d_bsr, x, y);                                     \
+        return;                                                                                            \
+    }
+        HDG_BS_CASES(HDG_BS)
+#undef HDG_BS
+    }
     if (c->nslot == 7) {
 #define HDG_BS(B)                                                                                          \
     if (c->bs == B) {                                                                                      \
@@ -401,6 +477,16 @@ static void spmv(hdg_ctx* c, const double* x, double* y) {
 
 static void precond(hdg_ctx* c, const double* x, double* y) {
     int64_t n = c->n_faces * c->bs * c->nrhs;
+    if (c->nrhs == 32) {
+#define HDG_BS(B)                                                                                          \
+    if (c->bs == B) {                                                                                      \
+        hipLaunchKernelGGL((bsr_spmm32_kernel<B, 1>), dim3(nblk_faces(c)), dim3(256), 0, c->stream,           \
+                           c->n_faces, (const int32_t*)nullptr, c->d_pinv, x, y);                          \
+        return;                                                                                            \
+    }
+        HDG_BS_CASES(HDG_BS)
+#undef HDG_BS
+    }
 #define HDG_BS(B)                                                                                            \
     if (c->bs == B) {                                                                                        \
         hipLaunchKernelGGL((block_apply_fixed_kernel<B>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces,   \
