@@ -65,6 +65,20 @@ def acoustic_counts(D, K, R, elt_bytes, mixed=False):
                 rec_flops=2.0 * rec_fma)
 
 
+def acoustic_pass_bytes(D, K):
+    """Algorithmic HBM bytes per element of the two element passes of the mixed-precision
+    refinement (refine_acoustic_kernel<float>, one right-hand side).  F0: recovery from the
+    FP32 factors fused with the FP64 residual and the correction right-hand side (reads the
+    geometry record, face ids and orientations, lam, Z_p, z_p, f, U; writes u, re64, z'_p and two
+    norms).  R: the correction (reads lam, dlam, Z_p, z'_p, u, f; writes u and two norms)."""
+    N, NF, NFACE = dimp(K, D), dimp(K, D - 1), D + 1
+    TT, NLOC = NFACE * NF, (D + 1) * N
+    common = 32 * 8 + 2 * NFACE * 4 + N * TT * 4 + N * 4 + NLOC * 8 + NLOC * 8 + 2 * 8
+    f0 = common + TT * 8 + N * N * 4 + TT * 8 + N * 4
+    r = common + 2 * TT * 8 + NLOC * 8
+    return {"F0": f0, "R": r}
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
     (FETCH_SIZE and WRITE_SIZE scaled by the plain-copy calibration), or None when the
@@ -296,6 +310,9 @@ def main():
     ap.add_argument("--all-workloads", action="store_true",
                     help="also time the element kernels of the other workloads (elastic k=4, "
                          "p-heterogeneous 32-rhs acoustics, Maxwell k=3) at full size")
+    ap.add_argument("--workload", type=int, choices=[3, 4, 5], default=None,
+                    help="time only the element kernels of one of the other workloads (elastic k = 4, "
+                         "p-heterogeneous acoustics with 32 right-hand sides, Maxwell k = 3) and print them")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -314,6 +331,16 @@ def main():
                                    "element partition; nothing here uses a second GPU)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload is not None:
+        precs = ["fp64", "mixed_fp32"] if args.precision == "both" else [args.precision]
+        res = {}
+        for pr in precs:
+            res[pr] = run_workload(args.workload, pr, args.steps, args.warmup)
+            print(f"workload {args.workload} {pr}: {res[pr]['elements_per_s']:.4g} elements/s", file=sys.stderr,
+                  flush=True)
+        print(json.dumps({"workload": args.workload, "steps": args.steps, "warmup": args.warmup, "results": res}))
+        return
 
     import torch
 
@@ -354,7 +381,20 @@ def main():
     cond_s = r["condense"] * 1e-3
     achieved_gbs = cnt["cond_bytes"] * p.n_elem / cond_s / 1e9
     achieved_tf = cnt["cond_flops"] * p.n_elem / cond_s / 1e12
-    rec_gbs = cnt["rec_bytes"] * p.n_elem / (r["recover"] * 1e-3) / 1e9
+    # recovery roofline on the plain FP64 recovery (refine_acoustic_kernel<..., double, ..., false>);
+    # in mixed precision the recovery is fused with the residual (pass F0) and the correction is
+    # applied by a second pass (R): both are reported with their own byte counts
+    rec_src = "fp64" if "fp64" in res else head
+    rec_cnt = acoustic_counts(3, k, 1, 8 if rec_src == "fp64" else 4, mixed=rec_src != "fp64")
+    rec_gbs = rec_cnt["rec_bytes"] * p.n_elem / (res[rec_src]["recover"] * 1e-3) / 1e9
+    mixed_passes = None
+    if "mixed_fp32" in res:
+        rm, pb = res["mixed_fp32"], acoustic_pass_bytes(3, k)
+        mixed_passes = {
+            name: {"ms": ms, "bytes_per_element": b, "GB/s": b * p.n_elem / (ms * 1e-3) / 1e9,
+                   "frac": b * p.n_elem / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            for name, ms, b in (("F0_recovery_residual", rm["recover"], pb["F0"]),
+                                ("R_correction_recovery", rm["refine_elem"], pb["R"]))}
     out = {
         "metric": "elements/s for batched HDG condensation+recovery, mixed vs FP64 at equal error",
         "value": value,
@@ -382,7 +422,11 @@ def main():
                      "bytes_per_element": cnt["cond_bytes"], "flops_per_element": cnt["cond_flops"],
                      "flop_frac_fp64_peak": achieved_tf / FP64_PEAK_TFLOPS},
         "recover_roofline": {"bound": "hbm", "achieved": rec_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": rec_gbs / HBM_PEAK_GBS, "bytes_per_element": cnt["rec_bytes"]},
+                             "frac": rec_gbs / HBM_PEAK_GBS, "bytes_per_element": rec_cnt["rec_bytes"],
+                             "kernel": f"refine_acoustic_kernel<3,{k},1,{'double' if rec_src == 'fp64' else 'float'},"
+                                       f"{'false' if rec_src == 'fp64' else 'true'}>",
+                             "precision": rec_src},
+        "mixed_refinement_passes": mixed_passes,
     }
     out["cached_factor_stage"] = {
         "basis": "secondary: per-stage element kernels with the factors kept across stages "
