@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "mfma.h"
 #include "physics.h"
 
 namespace hdg {
@@ -53,33 +54,6 @@ template <typename T>
 __device__ __forceinline__ T eps_of() {
     return sizeof(T) == 8 ? T(2.220446049250313e-16) : T(1.1920929e-7);
 }
-
-// ---- 16x16x4 MFMA tiles (one wavefront).  Operand layout: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; accumulator element v of lane l is C[row][l%16] with
-// row = l/16 + 4 v (FP64 instruction) or 4 (l/16) + v (FP32 instruction).
-typedef double mf64x4 __attribute__((ext_vector_type(4)));
-typedef float mf32x4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<double> {
-    using acc = mf64x4;
-    __device__ static __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
-    __device__ static __forceinline__ acc mac(double a, double b, acc c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    __device__ static __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
-};
-template <>
-struct Mfma<float> {
-    using acc = mf32x4;
-    __device__ static __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
-    __device__ static __forceinline__ acc mac(float a, float b, acc c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ static __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
 
 template <int D, int K, int R>
 struct AcDims {

@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "mfma.h"
 #include "physics.h"
 
 namespace hdg {
@@ -41,6 +42,7 @@ namespace hdg {
 namespace {
 
 constexpr int NTG = 256;
+constexpr int NWG = NTG / 64;   // wavefronts per workgroup
 constexpr int PH_ACOUSTIC = 0, PH_ELASTIC = 1, PH_MAXWELL = 2;
 
 // Broadcast of lane `src`'s value within the wavefront (src uniform)
@@ -275,7 +277,7 @@ constexpr int64_t gen_gstride(int SG) {
 }
 
 template <int PHYS, int K, int KF, int R, typename T, int SG>
-__global__ __launch_bounds__(NTG) void condense_general_kernel(
+__global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void condense_general_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
     const int32_t* __restrict__ eperm, const T* __restrict__ Sr, const T* __restrict__ Mf,
     const T* __restrict__ Tfull, const T* __restrict__ Ef, const double* __restrict__ f_loc,
@@ -333,13 +335,41 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
         // ------------------------------------------------------------ Sr_r E_f and the f1 coupling
         T* YE = Sb;                       // [f][r][i][l]
         T* HV = Sb + Dm::YE;              // [r][b][j][q] = sum_a cd[r][a][b] f1_a[j][q]
-        for (int idx = tid; idx < Dm::YE; idx += NTG) {
-            const int f = idx / (D * N * NF), r = (idx / (N * NF)) % D, i = (idx / NF) % N, l = idx % NF;
-            const T* Srow = &Srs[(r * N + i) * N];
-            const T* Ec = &El[f * N * NF + l];
-            T acc = 0;
-            for (int j = 0; j < N; ++j) acc += Srow[j] * Ec[j * NF];
-            YE[idx] = acc;
+        const int wv = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+        using MF = Mfma<T>;
+        if constexpr (N >= 16) {
+            // YE[f][r] = Sr_r E_f as 16x16 MFMA tiles, one wavefront per tile
+            constexpr int NIT = (N + 15) / 16, NLT = (NF + 15) / 16;
+            for (int t = wv; t < NFACE * D * NIT * NLT; t += NWG) {
+                const int fr = t / (NIT * NLT), it = (t / NLT) % NIT, lt = t % NLT;
+                const int f = fr / D, r = fr % D;
+                const int ia = min(it * 16 + li, N - 1), lb = min(lt * 16 + li, NF - 1);
+                const T* Arow = &Srs[(r * N + ia) * N];
+                const T* Bcol = &El[f * N * NF + lb];
+                typename MF::acc acc = MF::zero();
+#pragma unroll 4
+                for (int j0 = 0; j0 < N; j0 += 4) {
+                    const int j = j0 + lk;
+                    const int jc = min(j, N - 1);
+                    const T av = j < N ? Arow[jc] : T(0);
+                    acc = MF::mac(av, Bcol[jc * NF], acc);
+                }
+                const int l = lt * 16 + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = it * 16 + MF::row(lane, v);
+                    if (i < N && l < NF) YE[((f * D + r) * N + i) * NF + l] = acc[v];
+                }
+            }
+        } else {
+            for (int idx = tid; idx < Dm::YE; idx += NTG) {
+                const int f = idx / (D * N * NF), r = (idx / (N * NF)) % D, i = (idx / NF) % N, l = idx % NF;
+                const T* Srow = &Srs[(r * N + i) * N];
+                const T* Ec = &El[f * N * NF + l];
+                T acc = 0;
+                for (int j = 0; j < N; ++j) acc += Srow[j] * Ec[j * NF];
+                YE[idx] = acc;
+            }
         }
         for (int idx = tid; idx < Dm::HV; idx += NTG) {
             const int r = idx / (M2 * N * R), b = (idx / (N * R)) % M2, jq = idx % (N * R);
@@ -350,6 +380,9 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
         }
         __syncthreads();
         // ------------------------------------------------------------ B~2 and f~2
+        // With many right-hand sides and one Schur component the f~2 columns are the product
+        // [Sr_0 Sr_1 Sr_2] HV, formed as MFMA tiles over the flattened (r, j) index.
+        constexpr bool FMF = (R >= 16 && M2 == 1);
         for (int idx = tid; idx < N2 * C; idx += NTG) {
             const int row = idx / C, c = idx % C;
             const int b = row / N, i = row % N;
@@ -359,7 +392,7 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
 #pragma unroll
                 for (int r = 0; r < D; ++r) acc += (T)cf.kap[b][fc][r] * YE[((f * D + r) * N + i) * NF + l];
                 X[idx] = (T)geo[1 + D * D + f] * acc;
-            } else {
+            } else if (!FMF) {
                 const int q = c - TT;
                 T acc = 0;
 #pragma unroll
@@ -368,6 +401,31 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
                     for (int j = 0; j < N; ++j) acc += Srow[j] * HV[((r * M2 + b) * N + j) * R + q];
                 }
                 X[idx] += acc;
+            }
+        }
+        if constexpr (FMF) {
+            constexpr int NIT = (N + 15) / 16, NQT = R / 16, KK = D * N;
+            for (int t = wv; t < NIT * NQT; t += NWG) {
+                const int it = t / NQT, q0 = (t % NQT) * 16;
+                const int ia = min(it * 16 + li, N - 1);
+                typename MF::acc acc;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = min(it * 16 + MF::row(lane, v), N - 1);
+                    acc[v] = X[i * C + TT + q0 + li];
+                }
+#pragma unroll 4
+                for (int k0 = 0; k0 < KK; k0 += 4) {
+                    const int kk = min(k0 + lk, KK - 1);
+                    const int r = kk / N, j = kk - r * N;
+                    const T av = k0 + lk < KK ? Srs[(r * N + ia) * N + j] : T(0);
+                    acc = MF::mac(av, HV[kk * R + q0 + li], acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = it * 16 + MF::row(lane, v);
+                    if (i < N) X[i * C + TT + q0 + li] = acc[v];
+                }
             }
         }
         __syncthreads();
@@ -425,39 +483,44 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
             __syncthreads();
         } else
         {
+            // Right-looking elimination S = L_u diag(d) L_u^T with one barrier per pivot: at step
+            // j column j below the diagonal is final, and the threads, as a 16 x 16 grid, update
+            // the trailing lower triangle (rows i = ty mod 16, columns m = tx mod 16, m <= i)
+            // with S[i][m] -= S[i][j] S[m][j] / d_j.  Column j is never written at step j.
+            // Then L = L_u diag(d)^{1/2}: L[i][j] = S[i][j] / sqrt(d_j).
+            const int ty = tid >> 4, tx = tid & 15;
             T dmax = 0;
             for (int i = 0; i < N2; ++i) dmax = fmax(dmax, fabs(Sb[i * N2 + i]));
             const T ptol = T(64 * N2) * geps<T>() * dmax;
             for (int j = 0; j < N2; ++j) {
                 const T djj = Sb[j * N2 + j];
                 if (tid == 0 && !(djj > ptol && djj - djj == T(0))) atomicOr(status, 1);
-                const T ljj = sqrt(djj);
-                const T inv = T(1) / ljj;
-                __syncthreads();
-                for (int i = j + 1 + tid; i < N2; i += NTG) Sb[i * N2 + j] *= inv;
-                if (tid == 0) Sb[j * N2 + j] = ljj;
-                __syncthreads();
-                const int m = N2 - j - 1;
-                for (int idx = tid; idx < m * (m + 1) / 2; idx += NTG) {
-                    // lower triangle of the trailing block, row-major packed
-                    int ii = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-                    while ((ii + 1) * (ii + 2) / 2 <= idx) ++ii;
-                    while (ii * (ii + 1) / 2 > idx) --ii;
-                    const int mm = idx - ii * (ii + 1) / 2;
-                    const int gi = j + 1 + ii, gmm = j + 1 + mm;
-                    Sb[gi * N2 + gmm] -= Sb[gi * N2 + j] * Sb[gmm * N2 + j];
+                const T rinv = T(1) / djj;
+                for (int i = j + 1 + ((ty - j - 1) & 15); i < N2; i += 16) {
+                    const T lij = Sb[i * N2 + j] * rinv;
+                    T* Si = &Sb[i * N2];
+                    for (int m = j + 1 + ((tx - j - 1) & 15); m <= i; m += 16) Si[m] -= lij * Sb[m * N2 + j];
                 }
                 __syncthreads();
             }
+            for (int j = tid; j < N2; j += NTG) dinv[j] = T(1) / sqrt(Sb[j * N2 + j]);
+            __syncthreads();
+            for (int idx = tid; idx < N2 * N2; idx += NTG) {
+                const int i = idx / N2, j = idx - i * N2;
+                if (j < i) Sb[idx] *= dinv[j];
+            }
+            __syncthreads();
+            for (int j = tid; j < N2; j += NTG) Sb[j * N2 + j] = sqrt(Sb[j * N2 + j]);
+            __syncthreads();
         }
         if (Lout)
             for (int idx = tid; idx < N2 * N2; idx += NTG) Lout[e * strL + idx] = Sb[idx];
         // ------------------------------------------------------------ [W | w] = L^{-1} [B~2 | f~2]
-        // One column per thread, 16 rows at a time: the diagonal block is solved in registers
-        // and its rows update the rest of the thread's own column (no barrier inside the
-        // solve); the factor is read by broadcast from LDS.  The upper triangle of Sb receives
-        // L^T for the backward solve.
-        constexpr int BR = 16, NBR = (N2 + BR - 1) / BR;
+        // Blocks of 16 rows: the diagonal block is solved one column per thread in registers
+        // (factor entries by LDS broadcast), then the rows below are updated as MFMA tiles,
+        // X[below] -= L[below][block] X[block], one wavefront per 16 x 16 tile.  The upper
+        // triangle of Sb receives L^T for the backward solve.
+        constexpr int BR = 16, NBR = (N2 + BR - 1) / BR, NCT = (C + 15) / 16;
         __syncthreads();
         for (int idx = tid; idx < N2 * N2; idx += NTG) {
             const int i = idx / N2, m = idx - i * N2;
@@ -465,10 +528,29 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
         }
         for (int i = tid; i < N2; i += NTG) dinv[i] = T(1) / Sb[i * N2 + i];
         __syncthreads();
-        for (int c = tid; c < C; c += NTG) {
+        // X[i0.., c0..] -= sum_k F[i][r0 + k] X[r0 + k][c0..] for one 16 x 16 tile (F = L or L^T
+        // as stored in Sb; rows at or past N2 are read clamped and not written; k < BR).
+        auto tile_update = [&](int i0, int c0, int r0) {
+            const int ia = min(i0 + li, N2 - 1), cb = min(c0 + li, C - 1);
+            typename MF::acc acc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] = X[min(i0 + MF::row(lane, v), N2 - 1) * C + cb];
+#pragma unroll
+            for (int k0 = 0; k0 < BR; k0 += 4) {
+                const int kr = min(r0 + k0 + lk, N2 - 1);
+                const T av = r0 + k0 + lk < N2 ? -Sb[ia * N2 + kr] : T(0);
+                acc = MF::mac(av, X[kr * C + cb], acc);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + MF::row(lane, v);
+                if (i < N2 && c0 + li < C) X[i * C + c0 + li] = acc[v];
+            }
+        };
 #pragma unroll 1
-            for (int kb = 0; kb < NBR; ++kb) {
-                const int r0 = kb * BR;
+        for (int kb = 0; kb < NBR; ++kb) {
+            const int r0 = kb * BR;
+            for (int c = tid; c < C; c += NTG) {
                 T xb[BR];
 #pragma unroll
                 for (int u = 0; u < BR; ++u) xb[u] = r0 + u < N2 ? X[(r0 + u) * C + c] : T(0);
@@ -482,99 +564,123 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
                     xb[u] = s * dinv[r0 + u];
                     X[(r0 + u) * C + c] = xb[u];
                 }
-#pragma unroll 2
-                for (int i = r0 + BR; i < N2; ++i) {
-                    const T* Lr = &Sb[i * N2 + r0];
-                    T s = X[i * C + c];
-#pragma unroll
-                    for (int m = 0; m < BR; ++m) s -= Lr[m] * xb[m];
-                    X[i * C + c] = s;
-                }
             }
+            __syncthreads();
+            const int nrt = (N2 - r0 - BR + 15) / 16;   // row tiles below the block (<= 0: none)
+            for (int t = wv; t < nrt * NCT; t += NWG) tile_update(r0 + BR + (t / NCT) * 16, (t % NCT) * 16, r0);
+            __syncthreads();
         }
-        __syncthreads();
         // ------------------------------------------------------------ K_e, r_e
+        // K_e = D - j1 B1^T D1^{-1} B1 - j2 W^T W on the upper 16 x 16 tiles (mirrored on
+        // store): one wavefront per tile, two MFMA chains (W^T W over the N2 rows of W, and
+        // E_fa^T E_fb over the N volume modes, scaled per face pair in the epilogue).
         {
             const T j1 = (T)cf.j1;
             const T j2 = -j1;
-            constexpr int NBA = (TT + 3) / 4;
+            constexpr int NTT = (TT + 15) / 16, NPAIR = NTT * (NTT + 1) / 2;
             T* Kee = Ke + (size_t)e * TT * TT;
-            for (int blk = tid; blk < NBA * NBA; blk += NTG) {
-                const int a0 = 4 * (blk / NBA), b0 = 4 * (blk % NBA);
-                T ww[4][4] = {}, ee[4][4] = {};
-                for (int row = 0; row < N2; ++row) {
-                    T xa[4], xb[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        xa[u] = X[row * C + min(a0 + u, TT - 1)];
-                        xb[u] = X[row * C + min(b0 + u, TT - 1)];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) ww[u][v] += xa[u] * xb[v];
+            for (int pr = wv; pr < NPAIR; pr += NWG) {
+                int ta = 0, rem = pr;
+                while (rem >= NTT - ta) {
+                    rem -= NTT - ta;
+                    ++ta;
                 }
-                int fa[4], la[4], fb[4], lb[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int aa = min(a0 + u, TT - 1), bb = min(b0 + u, TT - 1);
-                    fa[u] = aa / NF / MT;
-                    la[u] = aa % NF;
-                    fb[u] = bb / NF / MT;
-                    lb[u] = bb % NF;
+                const int tb = ta + rem;
+                const int a0 = ta * 16, b0 = tb * 16;
+                const int ca = min(a0 + li, TT - 1), cb = min(b0 + li, TT - 1);
+                typename MF::acc w0 = MF::zero(), w1 = MF::zero(), ee = MF::zero();
+#pragma unroll 2
+                for (int k0 = 0; k0 < N2; k0 += 8) {
+                    const int r = k0 + lk, r2 = k0 + 4 + lk;
+                    const int rc = min(r, N2 - 1), rc2 = min(r2, N2 - 1);
+                    const T av = r < N2 ? X[rc * C + ca] : T(0);
+                    const T av2 = r2 < N2 ? X[rc2 * C + ca] : T(0);
+                    w0 = MF::mac(av, X[rc * C + cb], w0);
+                    w1 = MF::mac(av2, X[rc2 * C + cb], w1);
                 }
-                for (int i = 0; i < N; ++i) {
-                    T ea[4], eb[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        ea[u] = El[(fa[u] * N + i) * NF + la[u]];
-                        eb[u] = El[(fb[u] * N + i) * NF + lb[u]];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) ee[u][v] += ea[u] * eb[v];
+                const int fa = ca / NF / MT, la = ca % NF, fb = cb / NF / MT, lb = cb % NF;
+#pragma unroll 2
+                for (int k0 = 0; k0 < N; k0 += 4) {
+                    const int i = k0 + lk, ic = min(i, N - 1);
+                    const T av = i < N ? El[(fa * N + ic) * NF + la] : T(0);
+                    ee = MF::mac(av, El[(fb * N + ic) * NF + lb], ee);
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int aa = a0 + u;
-                    if (aa >= TT) continue;
-                    const int fca = aa / NF;
-                    const T sa = (T)geo[1 + D * D + fa[u]];
+                const int bb = b0 + li;
+                if (bb < TT) {
+                    const int fcb = bb / NF;
+                    const T sb = (T)geo[1 + D * D + fcb / MT];
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int bb = b0 + v;
-                        if (bb >= TT) continue;
-                        const int fcb = bb / NF;
-                        const T sb = (T)geo[1 + D * D + fb[v]];
-                        T val = -j1 * invJ * sa * sb * (T)cf.g1[fca][fcb] * ee[u][v] - j2 * ww[u][v];
+                        const int aa = a0 + MF::row(lane, v);
+                        if (aa >= TT) continue;
+                        const int fca = aa / NF;
+                        const T sa = (T)geo[1 + D * D + fca / MT];
+                        T val = -j1 * invJ * sa * sb * (T)cf.g1[fca][fcb] * ee[v] - j2 * (w0[v] + w1[v]);
                         if (aa == bb) val += (T)cf.dface * sa;
                         Kee[aa * TT + bb] = val;
+                        if (ta != tb) Kee[bb * TT + aa] = val;
                     }
                 }
             }
             T* ree = re + (size_t)e * TT * R;
-            for (int idx = tid; idx < TT * R; idx += NTG) {
-                const int aa = idx / R, q = idx % R;
-                const int fc = aa / NF, l = aa % NF, f = fc / MT;
-                T acc = 0, accb = 0;
-                for (int row = 0; row < N2; ++row) acc += X[row * C + aa] * X[row * C + TT + q];
-                for (int i = 0; i < N; ++i) {
-                    T fb = 0;
+            if constexpr (R >= 16) {
+                // r_e = -j1 (1/|J|) s_f E_f^T (sum_a bd[a][fc] f1_a) - j2 W^T w as 16 x 16 MFMA
+                // tiles (rows: trace unknowns, columns: right-hand sides); the bd factor of a row
+                // is folded into that row's A operand.
+                constexpr int NQT = R / 16;
+                for (int t = wv; t < NTT * NQT; t += NWG) {
+                    const int a0 = (t / NQT) * 16, q0 = (t % NQT) * 16;
+                    const int ca = min(a0 + li, TT - 1);
+                    typename MF::acc acc = MF::zero(), accb = MF::zero();
+#pragma unroll 2
+                    for (int k0 = 0; k0 < N2; k0 += 4) {
+                        const int r = k0 + lk, rc = min(r, N2 - 1);
+                        const T av = r < N2 ? X[rc * C + ca] : T(0);
+                        acc = MF::mac(av, X[rc * C + TT + q0 + li], acc);
+                    }
+                    const int fc = ca / NF, f = fc / MT, l = ca % NF;
 #pragma unroll
-                    for (int al = 0; al < M1; ++al) fb += (T)cf.bd[al][fc] * F1[(al * N + i) * R + q];
-                    accb += El[(f * N + i) * NF + l] * fb;
+                    for (int al = 0; al < M1; ++al) {
+                        const T bdv = (T)cf.bd[al][fc];
+#pragma unroll 2
+                        for (int k0 = 0; k0 < N; k0 += 4) {
+                            const int i = k0 + lk, ic = min(i, N - 1);
+                            const T av = i < N ? bdv * El[(f * N + ic) * NF + l] : T(0);
+                            accb = MF::mac(av, F1[(al * N + ic) * R + q0 + li], accb);
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int aa = a0 + MF::row(lane, v);
+                        if (aa >= TT) continue;
+                        const int fr = (aa / NF) / MT;
+                        ree[aa * R + q0 + li] = -j1 * invJ * (T)geo[1 + D * D + fr] * accb[v] - j2 * acc[v];
+                    }
                 }
-                ree[idx] = -j1 * invJ * (T)geo[1 + D * D + f] * accb - j2 * acc;
+            } else {
+                for (int idx = tid; idx < TT * R; idx += NTG) {
+                    const int aa = idx / R, q = idx % R;
+                    const int fc = aa / NF, l = aa % NF, f = fc / MT;
+                    T acc = 0, accb = 0;
+                    for (int row = 0; row < N2; ++row) acc += X[row * C + aa] * X[row * C + TT + q];
+                    for (int i = 0; i < N; ++i) {
+                        T fb = 0;
+#pragma unroll
+                        for (int al = 0; al < M1; ++al) fb += (T)cf.bd[al][fc] * F1[(al * N + i) * R + q];
+                        accb += El[(f * N + i) * NF + l] * fb;
+                    }
+                    ree[idx] = -j1 * invJ * (T)geo[1 + D * D + f] * accb - j2 * acc;
+                }
             }
         }
         __syncthreads();
         // ------------------------------------------------------------ Z2 = L^{-T} W, z2 = L^{-T} w
-        // the same by blocks of rows from the bottom, with L^T from the upper triangle of Sb
-        for (int c = tid; c < C; c += NTG) {
+        // The same by blocks of rows from the bottom, with L^T from the upper triangle of Sb:
+        // the diagonal block in registers, then the rows above as MFMA tiles.
 #pragma unroll 1
-            for (int kb = NBR - 1; kb >= 0; --kb) {
-                const int r0 = kb * BR;
+        for (int kb = NBR - 1; kb >= 0; --kb) {
+            const int r0 = kb * BR;
+            for (int c = tid; c < C; c += NTG) {
                 T xb[BR];
 #pragma unroll
                 for (int u = 0; u < BR; ++u) xb[u] = r0 + u < N2 ? X[(r0 + u) * C + c] : T(0);
@@ -588,17 +694,11 @@ __global__ __launch_bounds__(NTG) void condense_general_kernel(
                     xb[u] = s * dinv[r0 + u];
                     X[(r0 + u) * C + c] = xb[u];
                 }
-#pragma unroll 2
-                for (int i = 0; i < r0; ++i) {
-                    const T* Lr = &Sb[i * N2 + r0];          // row i of L^T, columns of the block
-                    T s = X[i * C + c];
-#pragma unroll
-                    for (int m = 0; m < BR; ++m) s -= (r0 + m < N2 ? Lr[m] : T(0)) * xb[m];
-                    X[i * C + c] = s;
-                }
             }
+            __syncthreads();
+            for (int t = wv; t < (r0 / 16) * NCT; t += NWG) tile_update((t / NCT) * 16, (t % NCT) * 16, r0);
+            __syncthreads();
         }
-        __syncthreads();
         T* Zse = Zs + e * strZ;
         for (int idx = tid; idx < N2 * TT; idx += NTG) Zse[idx] = X[(idx / TT) * C + idx % TT];
         T* zse = zs + e * strz;
