@@ -258,8 +258,10 @@ def run_workload(cfg, prec, steps, warmup):
     if prec != "fp64":
         kw.update(refine_tol=1e-11)
     uk = p.uniform_k
+    # launch schedules picked by the library's autotuner on the first (warm-up) stage; on the
+    # mesh of variable degree the degree classes run as one hipGraph
     s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=uk, degree=None if uk else p.degree,
-               precision=prec, nrhs=p.nrhs, **kw)
+               precision=prec, nrhs=p.nrhs, autotune=True, use_graph=not uk, **kw)
     nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
     if p.nrhs > 1:
         f = torch.as_tensor(s.point_sources(p.sources), device="cuda")
@@ -287,11 +289,13 @@ def run_workload(cfg, prec, steps, warmup):
             tm[key] += s.timing(key)
     torch.cuda.synchronize()
     refine = s.query("last_refine")
+    schedules = s.schedules()
     s.close()
     del f, lb, lam, u
     torch.cuda.empty_cache()
     out = {k2: v / steps for k2, v in tm.items()}
     out.update(workload=p.name, elements=p.n_elem, nrhs=p.nrhs, iters=float(np.mean(its)), refine=refine,
+               schedules=schedules,
                elements_per_s=p.n_elem / ((out["condense"] + out["recover"] + out["refine_elem"]) * 1e-3))
     return out
 

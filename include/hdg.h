@@ -108,6 +108,24 @@ typedef struct {
                                    without refactoring.  Acoustic fast path (uniform degree,
                                    one rhs); costs n_s^2 values per element in FP64 (the
                                    mixed-precision path keeps them anyway)                   */
+    int autotune;               /* nonzero: the first hdg_condense of each degree class of the
+                                   block-structured kernels (elastic, Maxwell, acoustics of
+                                   variable degree or with 32 rhs) times every launch schedule
+                                   built for it (where the element buffers live: LDS only, or
+                                   part of them in per-workgroup global scratch, which trades
+                                   LDS for workgroups per CU) on the mesh's own elements, keeps
+                                   the fastest for the life of the context and synchronises
+                                   once to read the timers.  Zero: the built-in default.     */
+    const char* autotune_table; /* NULL, or a text file of tuned schedules: read at
+                                   hdg_init_mesh (entries for this physics, nrhs, precision
+                                   and device replace the defaults), rewritten after tuning.
+                                   One line per class: device physics k kF nrhs precision
+                                   schedule ms_0 ms_1 (lines starting with '#' are comments) */
+    int use_graph;              /* nonzero, mesh of variable degree: hdg_condense runs its
+                                   per-degree-class launches as one hipGraph whose class
+                                   kernels are independent branches (they may overlap on the
+                                   device); the graph is captured on the first call and again
+                                   whenever a, f_loc or a tuned schedule changes             */
 } hdg_options;
 
 /* Query keys for hdg_query. */
@@ -120,7 +138,10 @@ enum hdg_query_key {
     HDG_Q_LAST_ITERS = 7,       /* Krylov iterations of the last trace solve                 */
     HDG_Q_LAST_REFINE = 8,      /* refinement iterations of the last mixed recover          */
     HDG_Q_M_LOCAL = 9,          /* field components per element                             */
-    HDG_Q_M_TRACE = 10          /* trace components per face                                */
+    HDG_Q_M_TRACE = 10,         /* trace components per face                                */
+    HDG_Q_SCHEDULE = 11         /* launch schedule of the block-structured condensation per
+                                   degree class: 4 bits per degree k = 1..5 at bit 4 (k - 1),
+                                   each 0 (no class or not chosen yet) or schedule + 1       */
 };
 
 /*

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <sstream>
@@ -16,6 +17,66 @@
 namespace hdg {
 int launch_condense_acoustic(hdg_ctx* c, double a, const double* f_loc);
 int launch_condense_general(hdg_ctx* c, double a, const double* f_loc);
+
+// Autotune table: one line per tuned class, "device physics k kF nrhs precision schedule ms_0
+// ms_1"; '#' starts a comment line.
+namespace {
+bool tune_key_matches(const hdg_ctx* c, const std::string& dev, int phys, int k, int kf, int nrhs, int prec) {
+    const int kf_c = c->vardeg ? var_face_degree() : k;
+    const bool has = c->vardeg ? (k >= 1 && k <= 5 && c->cls_n[k] > 0) : k == c->k;
+    return has && dev == c->device_name && phys == c->physics && kf == kf_c && nrhs == c->nrhs && prec == c->precision;
+}
+}  // namespace
+
+void read_tune_table(hdg_ctx* c) {
+    FILE* fp = std::fopen(c->tune_path.c_str(), "r");
+    if (!fp) return;
+    char line[512];
+    const int pi = c->precision == HDG_FP64 ? 1 : 0;
+    while (std::fgets(line, sizeof line, fp)) {
+        if (line[0] == '#') continue;
+        char dev[128];
+        int phys, k, kf, nrhs, prec, sch;
+        if (std::sscanf(line, "%127s %d %d %d %d %d %d", dev, &phys, &k, &kf, &nrhs, &prec, &sch) != 7) continue;
+        if (sch < 0 || sch > 1 || !tune_key_matches(c, dev, phys, k, kf, nrhs, prec)) continue;
+        c->sched[pi][k] = (int8_t)sch;
+    }
+    std::fclose(fp);
+}
+
+void write_tune_table(const hdg_ctx* c) {
+    // only classes timed by this context are (re)written; other lines are kept as they are
+    const int pi = c->precision == HDG_FP64 ? 1 : 0;
+    auto timed = [&](int k) { return k >= 1 && k <= 5 && c->sched[pi][k] >= 0 && c->sched_ms[pi][k][0] > 0; };
+    std::vector<std::string> keep;
+    if (FILE* fp = std::fopen(c->tune_path.c_str(), "r")) {
+        char line[512];
+        while (std::fgets(line, sizeof line, fp)) {
+            char dev[128];
+            int phys, k, kf, nrhs, prec, sch;
+            if (line[0] != '#' && std::sscanf(line, "%127s %d %d %d %d %d %d", dev, &phys, &k, &kf, &nrhs, &prec, &sch) == 7 &&
+                tune_key_matches(c, dev, phys, k, kf, nrhs, prec) && timed(k))
+                continue;   // replaced below
+            keep.emplace_back(line);
+        }
+        std::fclose(fp);
+    }
+    const std::string tmp = c->tune_path + ".tmp";
+    FILE* fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return;
+    if (keep.empty()) std::fprintf(fp, "# device physics k kF nrhs precision schedule ms_0 ms_1\n");
+    for (const auto& l : keep) std::fputs(l.c_str(), fp);
+    for (int k = 1; k <= 5; ++k) {
+        if (!timed(k) || !tune_key_matches(c, c->device_name, c->physics, k, c->vardeg ? var_face_degree() : k,
+                                                     c->nrhs, c->precision))
+            continue;
+        std::fprintf(fp, "%s %d %d %d %d %d %d %.4f %.4f\n", c->device_name.c_str(), c->physics, k,
+                     c->vardeg ? var_face_degree() : k, c->nrhs, c->precision, c->sched[pi][k], c->sched_ms[pi][k][0],
+                     c->sched_ms[pi][k][1]);
+    }
+    std::fclose(fp);
+    std::rename(tmp.c_str(), c->tune_path.c_str());
+}
 }  // namespace hdg
 
 using namespace hdg;
@@ -175,6 +236,9 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     c->refine_maxit = o->refine_maxit > 0 ? o->refine_maxit : 10;
     c->refine_inner_tol = o->refine_inner_tol > 0 ? o->refine_inner_tol : 1e-6;
     c->cache_factors = o->cache_factors != 0;
+    c->autotune = o->autotune != 0;
+    if (o->autotune_table) c->tune_path = o->autotune_table;
+    c->use_graph = o->use_graph != 0;
     c->stream = (hipStream_t)stream;
     int st = build_mesh(c, m, p);
     if (st) {
@@ -329,6 +393,30 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
         hdg_destroy(c);
         return HDG_E_HIP;
     }
+    if (c->use_graph && c->vardeg) {
+        bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; i < 6 && ok; ++i)
+            ok = hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&c->ev_join[i], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            g_init_err = "stream or event creation for the condensation graph failed";
+            hdg_destroy(c);
+            return HDG_E_HIP;
+        }
+    }
+    {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            c->device_name = prop.gcnArchName;
+            const size_t colon = c->device_name.find(':');
+            if (colon != std::string::npos) c->device_name.resize(colon);
+        }
+        if (c->device_name.empty()) c->device_name = "unknown";
+    }
+    if (!c->tune_path.empty()) read_tune_table(c);
 #undef TRY
     *out = c;
     return HDG_OK;
@@ -358,6 +446,15 @@ hdg_status hdg_query(const hdg_ctx* c, int key, int64_t* v) {
         case HDG_Q_LAST_REFINE: *v = c->last_refine; break;
         case HDG_Q_M_LOCAL: *v = c->m_local; break;
         case HDG_Q_M_TRACE: *v = c->m_trace; break;
+        case HDG_Q_SCHEDULE: {
+            const int pi = c->precision == HDG_FP64 ? 1 : 0;
+            int64_t x = 0;
+            for (int k = 1; k <= 5; ++k)
+                if (c->sched[pi][k] >= 0 && (c->vardeg ? c->cls_n[k] > 0 : k == c->k))
+                    x |= (int64_t)(c->sched[pi][k] + 1) << (4 * (k - 1));
+            *v = x;
+            break;
+        }
         default: return HDG_E_ARG;
     }
     return HDG_OK;
@@ -850,6 +947,17 @@ void hdg_destroy(hdg_ctx* c) {
     }
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (int i = 0; i < 6; ++i) {
+        if (c->side[i]) {
+            (void)hipStreamSynchronize(c->side[i]);
+            (void)hipStreamDestroy(c->side[i]);
+        }
+        if (c->ev_join[i]) (void)hipEventDestroy(c->ev_join[i]);
+    }
+    hipEvent_t evs[] = {c->ev_fork, c->ev_in, c->ev_out};
+    for (hipEvent_t e : evs)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 

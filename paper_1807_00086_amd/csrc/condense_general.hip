@@ -33,6 +33,10 @@
 //   at recovery).  One element per workgroup of 256 threads.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <utility>
+#include <vector>
+
 #include "internal.h"
 #include "mfma.h"
 #include "physics.h"
@@ -430,19 +434,27 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
         }
         __syncthreads();
         // ------------------------------------------------------------ S
-        for (int idx = tid; idx < N2 * N2; idx += NTG) {
-            const int row = idx / N2, col = idx % N2;
-            const int b = row / N, i = row % N, gm = col / N, j = col % N;
-            T s = (i == j) ? J * (T)cf.amass[b][gm] : T(0);
+        // the reference tables depend on the mode pair (i, j) only: each is read once per pair
+        // and serves every component pair (b, gm)
+        for (int idx = tid; idx < N * N; idx += NTG) {
+            const int i = idx / N, j = idx % N;
+            T mf[NFACE], tf[9];
 #pragma unroll
-            for (int f = 0; f < NFACE; ++f) {
-                const T cfc = (T)cf.af[f][b][gm];
-                if (cfc != T(0)) s += (T)geo[1 + D * D + f] * cfc * Mf[(f * N + i) * N + j];
-            }
-            T q = 0;
+            for (int f = 0; f < NFACE; ++f) mf[f] = (T)geo[1 + D * D + f] * Mf[(f * N + i) * N + j];
 #pragma unroll
-            for (int rr = 0; rr < 9; ++rr) q += (T)cf.Gam[b][gm][rr] * Tfull[(rr * N + i) * N + j];
-            Sb[idx] = s + J * q;
+            for (int rr = 0; rr < 9; ++rr) tf[rr] = Tfull[(rr * N + i) * N + j];
+#pragma unroll
+            for (int b = 0; b < M2; ++b)
+#pragma unroll
+                for (int gm = 0; gm < M2; ++gm) {
+                    T s = (i == j) ? J * (T)cf.amass[b][gm] : T(0);
+#pragma unroll
+                    for (int f = 0; f < NFACE; ++f) s += (T)cf.af[f][b][gm] * mf[f];
+                    T q = 0;
+#pragma unroll
+                    for (int rr = 0; rr < 9; ++rr) q += (T)cf.Gam[b][gm][rr] * tf[rr];
+                    Sb[(b * N + i) * N2 + gm * N + j] = s + J * q;
+                }
         }
         __syncthreads();
         // ------------------------------------------------------------ Cholesky S = L L^T
@@ -1053,40 +1065,60 @@ VarArgs var_args(const hdg_ctx* c, const int32_t* elist) {
     return va;
 }
 
-// scratch placement of the condensation kernel (see SG)
+// Launch schedules of the condensation kernel: SG places the element buffers (see
+// gen_gstride).  LDS bytes of a workgroup for each placement:
 template <int PHYS, int K, int KF, int R, typename T>
-constexpr int gen_sg() {
+constexpr size_t gen_lds(int SG) {
     using Dm = GDims<PHYS, K, KF, R>;
-    constexpr size_t base = sizeof(T) * (Dm::D * Dm::N * Dm::N + Dm::NFACE * Dm::N * Dm::NF) +
-                            sizeof(Coef<PHYS>) + 8 * 64;
-    constexpr size_t mid = base + sizeof(T) * (Dm::SBUF + Dm::N1 * R);
-    constexpr size_t all = mid + sizeof(T) * Dm::N2 * Dm::C;
-    // at most 75 KB of LDS per workgroup, so that two workgroups share a CU: the element
-    // buffers that do not fit go to per-workgroup global scratch (L2-resident)
-    return all <= 75 * 1024 ? 0 : (mid <= 75 * 1024 ? 1 : 2);
+    const size_t base = sizeof(T) * (Dm::D * Dm::N * Dm::N + Dm::NFACE * Dm::N * Dm::NF + Dm::N2) +
+                        sizeof(Coef<PHYS>) + 8 * 64;
+    const size_t mid = base + sizeof(T) * (Dm::SBUF + Dm::N1 * R);
+    const size_t all = mid + sizeof(T) * Dm::N2 * Dm::C;
+    return SG == 0 ? all : (SG == 1 ? mid : base);
+}
+constexpr size_t LDS_SHARE = 75 * 1024;    // two workgroups per CU
+constexpr size_t LDS_CU = 159 * 1024;      // one workgroup per CU (160 KB less slack)
+// schedule 0 (default): at most 75 KB of LDS per workgroup, so that two workgroups share a CU,
+// the element buffers that do not fit in global scratch (L2-resident); schedule 1 (when it
+// differs): the fewest buffers in global scratch that fit a whole CU's LDS, one workgroup per CU
+template <int PHYS, int K, int KF, int R, typename T>
+constexpr int gen_sg(int sched) {
+    constexpr int s0 = gen_lds<PHYS, K, KF, R, T>(0) <= LDS_SHARE ? 0 : (gen_lds<PHYS, K, KF, R, T>(1) <= LDS_SHARE ? 1 : 2);
+    constexpr int s1 = gen_lds<PHYS, K, KF, R, T>(0) <= LDS_CU ? 0 : (gen_lds<PHYS, K, KF, R, T>(1) <= LDS_CU ? 1 : 2);
+    return sched == 1 ? s1 : s0;
+}
+template <int PHYS, int K, int KF, int R, typename T>
+constexpr int gen_nsched() {
+    return gen_sg<PHYS, K, KF, R, T>(0) == gen_sg<PHYS, K, KF, R, T>(1) ? 1 : 2;
+}
+template <int PHYS, int K, int KF, int R>
+int gen_grid(int64_t n) {
+    return (int)std::min<int64_t>(n, 256 * 8);
+}
+// global scratch bytes a launch of `n` elements needs under schedule `sched`
+template <int PHYS, int K, int KF, int R, typename T>
+size_t gen_scratch(int64_t n, int sched) {
+    return (size_t)gen_grid<PHYS, K, KF, R>(n) * gen_gstride<PHYS, K, KF, R>(gen_sg<PHYS, K, KF, R, T>(sched)) * sizeof(T);
+}
+
+template <int PHYS, int K, int KF, int R, typename T, int SG>
+int launch_gen_sg(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist,
+                  int64_t n, T* scratch, hipStream_t st) {
+    using TB = TabOf<T>;
+    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, KF, R, T, SG>), dim3(gen_grid<PHYS, K, KF, R>(n)), dim3(NTG),
+                       0, st, n, a, c->d_geom, c->d_eframe, c->d_eperm, TB::Sr(tb), TB::Mf(tb), TB::Tf(tb), TB::Ef(tb),
+                       f_loc, (T*)c->d_Ke, (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
+                       c->precision == HDG_MIXED_FP32 ? (T*)c->d_LU : (T*)nullptr, scratch, c->d_status,
+                       var_args(c, elist));
+    return (int)hipGetLastError();
 }
 
 template <int PHYS, int K, int KF, int R, typename T>
-int launch_gen(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist,
-               int64_t n) {
-    constexpr int SG = gen_sg<PHYS, K, KF, R, T>();
-    const int grid = (int)std::min<int64_t>(n, 256 * 8);
-    const size_t need = (size_t)grid * gen_gstride<PHYS, K, KF, R>(SG) * sizeof(T);
-    if (need > c->xscratch_bytes) {
-        if (c->d_xscratch) (void)hipFree(c->d_xscratch);
-        c->d_xscratch = nullptr;
-        c->xscratch_bytes = 0;
-        hipError_t er = hipMalloc(&c->d_xscratch, need);
-        if (er != hipSuccess) return (int)er;
-        c->xscratch_bytes = need;
-    }
-    using TB = TabOf<T>;
-    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, KF, R, T, SG>), dim3(grid), dim3(NTG), 0, c->stream, n, a,
-                       c->d_geom, c->d_eframe, c->d_eperm, TB::Sr(tb), TB::Mf(tb), TB::Tf(tb), TB::Ef(tb), f_loc,
-                       (T*)c->d_Ke, (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
-                       c->precision == HDG_MIXED_FP32 ? (T*)c->d_LU : (T*)nullptr, (T*)c->d_xscratch, c->d_status,
-                       var_args(c, elist));
-    return (int)hipGetLastError();
+int launch_gen(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist, int64_t n,
+               int sched, T* scratch, hipStream_t st) {
+    constexpr int S0 = gen_sg<PHYS, K, KF, R, T>(0), S1 = gen_sg<PHYS, K, KF, R, T>(1);
+    if (sched == 1 && S1 != S0) return launch_gen_sg<PHYS, K, KF, R, T, S1>(c, a, f_loc, tb, elist, n, scratch, st);
+    return launch_gen_sg<PHYS, K, KF, R, T, S0>(c, a, f_loc, tb, elist, n, scratch, st);
 }
 
 template <int PHYS, int K, int KF, int R, typename T>
@@ -1143,16 +1175,185 @@ int for_each_class(hdg_ctx* c, Fn fn) {
     return 0;
 }
 
+// One class launch (op 0), its schedule count (op 1) or its scratch need in bytes (op 2).
+struct GenOp {
+    int op = 0, sched = 0;
+    double a = 0;
+    const double* f_loc = nullptr;
+    void* scratch = nullptr;
+    hipStream_t st = nullptr;
+    size_t out = 0;
+};
+
+template <typename T>
+int gen_class(hdg_ctx* c, int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n, GenOp& g) {
+    const int P = c->physics, R = c->nrhs;
+#define HDG_CASE(PP, KK, FF, RR)                                                                        \
+    if (P == PP && K == KK && KF == FF && R == RR) {                                                     \
+        if (g.op == 1) {                                                                                 \
+            g.out = (size_t)gen_nsched<PP, KK, FF, RR, T>();                                             \
+            return 0;                                                                                    \
+        }                                                                                                \
+        if (g.op == 2) {                                                                                 \
+            g.out = std::max(gen_scratch<PP, KK, FF, RR, T>(n, 0), gen_scratch<PP, KK, FF, RR, T>(n, 1)); \
+            return 0;                                                                                    \
+        }                                                                                                \
+        return launch_gen<PP, KK, FF, RR, T>(c, g.a, g.f_loc, tb, el, n, g.sched, (T*)g.scratch, g.st);   \
+    }
+    HDG_GEN_CASES(HDG_CASE)
+#undef HDG_CASE
+    return -1;
+}
+
+// Degree classes of the mesh: (K, KF, tables, element list, count) for class slot k.
+struct ClassRef {
+    int K, KF;
+    const DeviceTables* tb;
+    const int32_t* el;
+    int64_t n;
+};
+std::vector<std::pair<int, ClassRef>> gen_classes(hdg_ctx* c) {
+    std::vector<std::pair<int, ClassRef>> v;
+    if (!c->vardeg) {
+        v.push_back({c->k, ClassRef{c->k, c->k, &c->tab, nullptr, c->n_elem}});
+        return v;
+    }
+    for (int k = 1; k <= 5; ++k)
+        if (c->cls_n[k] > 0) v.push_back({k, ClassRef{k, VAR_KF, &c->tabk[k], c->d_cls[k], c->cls_n[k]}});
+    return v;
+}
+
+template <typename T>
+int gen_run(hdg_ctx* c, const ClassRef& cr, int k, GenOp g) {
+    g.op = 0;
+    g.scratch = (char*)c->d_xscratch + c->xs_off[k];
+    return gen_class<T>(c, cr.K, cr.KF, *cr.tb, cr.el, cr.n, g);
+}
+
 template <typename T>
 int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
-    const int P = c->physics, R = c->nrhs;
-    return for_each_class(c, [&](int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n) {
-#define HDG_CASE(PP, KK, FF, RR) \
-    if (P == PP && K == KK && KF == FF && R == RR) return launch_gen<PP, KK, FF, RR, T>(c, a, f_loc, tb, el, n);
-        HDG_GEN_CASES(HDG_CASE)
-#undef HDG_CASE
+    const int pi = c->precision == HDG_FP64 ? 1 : 0;
+    auto classes = gen_classes(c);
+    // per-class scratch regions (classes may run concurrently inside the graph)
+    size_t total = 0;
+    for (auto& [k, cr] : classes) {
+        GenOp q;
+        q.op = 2;
+        if (gen_class<T>(c, cr.K, cr.KF, *cr.tb, cr.el, cr.n, q)) return -1;
+        c->xs_off[k] = total;
+        total += (q.out + 255) / 256 * 256;
+    }
+    if (total > c->xscratch_bytes) {
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+        if (c->d_xscratch) (void)hipFree(c->d_xscratch);
+        c->d_xscratch = nullptr;
+        c->xscratch_bytes = 0;
+        hipError_t er = hipMalloc(&c->d_xscratch, total);
+        if (er != hipSuccess) return (int)er;
+        c->xscratch_bytes = total;
+    }
+    GenOp g;
+    g.a = a;
+    g.f_loc = f_loc;
+    g.st = c->stream;
+    // schedules: tuned on the first condensation of a class (or read from the table), else 0
+    bool tuned = false;
+    for (auto& [k, cr] : classes) {
+        if (c->sched[pi][k] >= 0) continue;
+        GenOp q;
+        q.op = 1;
+        (void)gen_class<T>(c, cr.K, cr.KF, *cr.tb, cr.el, cr.n, q);
+        const int ns = (int)q.out;
+        if (!c->autotune || ns < 2) {
+            c->sched[pi][k] = 0;
+            continue;
+        }
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+            if (t0) (void)hipEventDestroy(t0);
+            return -1;
+        }
+        float best = 0;
+        int bs = 0, err = 0;
+        for (int s = 0; s < ns && !err; ++s) {
+            float ms = 0, t = 0;
+            for (int rep = 0; rep < 2 && !err; ++rep) {   // the first run warms caches and code
+                g.sched = s;
+                err = hipEventRecord(t0, c->stream);
+                if (!err) err = gen_run<T>(c, cr, k, g);
+                if (!err) err = hipEventRecord(t1, c->stream);
+                if (!err) err = hipEventSynchronize(t1);
+                if (!err) err = hipEventElapsedTime(&t, t0, t1);
+                ms = rep ? std::min(ms, t) : t;
+            }
+            c->sched_ms[pi][k][s] = ms;
+            if (s == 0 || ms < best) {
+                best = ms;
+                bs = s;
+            }
+        }
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+        if (err) return err;
+        c->sched[pi][k] = (int8_t)bs;
+        tuned = true;
+    }
+    if (tuned && !c->tune_path.empty()) write_tune_table(c);
+    int key = 0;
+    for (auto& [k, cr] : classes) key = key * 4 + c->sched[pi][k];
+
+    if (!c->use_graph || !c->vardeg || !c->side[0]) {
+        for (auto& [k, cr] : classes) {
+            g.sched = c->sched[pi][k];
+            const int e = gen_run<T>(c, cr, k, g);
+            if (e) return e;
+        }
+        return 0;
+    }
+    // one graph: fork from side[0] to a side stream per class, join back into side[0]
+    if (!c->gexec || c->g_a != a || c->g_f != f_loc || c->g_sched != key) {
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+        hipStream_t s0 = c->side[0];
+        if (hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal) != hipSuccess) return -1;
+        int err = hipEventRecord(c->ev_fork, s0);
+        int i = 0;
+        for (auto& [k, cr] : classes) {
+            hipStream_t si = c->side[1 + i % 5];
+            if (!err) err = hipStreamWaitEvent(si, c->ev_fork, 0);
+            g.st = si;
+            g.sched = c->sched[pi][k];
+            if (!err) err = gen_run<T>(c, cr, k, g);
+            if (!err) err = hipEventRecord(c->ev_join[i], si);
+            if (!err) err = hipStreamWaitEvent(s0, c->ev_join[i], 0);
+            ++i;
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(s0, &graph);
+        if (err || ee != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return err ? err : (int)ee;
+        }
+        const hipError_t ie = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            c->gexec = nullptr;
+            return (int)ie;
+        }
+        c->g_a = a;
+        c->g_f = f_loc;
+        c->g_sched = key;
+    }
+    if (hipEventRecord(c->ev_in, c->stream) != hipSuccess || hipStreamWaitEvent(c->side[0], c->ev_in, 0) != hipSuccess ||
+        hipGraphLaunch(c->gexec, c->side[0]) != hipSuccess || hipEventRecord(c->ev_out, c->side[0]) != hipSuccess ||
+        hipStreamWaitEvent(c->stream, c->ev_out, 0) != hipSuccess)
         return -1;
-    });
+    return 0;
 }
 
 template <typename T>
@@ -1195,6 +1396,7 @@ bool general_supported(int physics, int k, int kf, int nrhs) {
 }
 
 int var_face_degree() { return VAR_KF; }
+
 
 int launch_condense_general(hdg_ctx* c, double a, const double* f_loc) {
     if (c->precision == HDG_FP64) return dispatch_gen<double>(c, a, f_loc);

@@ -150,6 +150,25 @@ struct hdg_ctx {
     int last_iters = 0, last_refine = 0;
     hdg::Timings tim;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    // launch schedules of the block-structured condensation (index: [FP32 | FP64][degree]);
+    // -1: not chosen yet.  Autotuning times every built schedule of a class on its first
+    // condensation; the table file keeps the choices across contexts.
+    bool autotune = false;
+    std::string tune_path, device_name;
+    int8_t sched[2][6] = {{-1, -1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1, -1}};
+    float sched_ms[2][6][2] = {};
+    size_t xs_off[6] = {0, 0, 0, 0, 0, 0};   // per-class offsets into d_xscratch (bytes)
+    // one hipGraph per condensation of a mesh of variable degree: class launches on side
+    // streams forked from and joined into side[0]
+    bool use_graph = false;
+    hipStream_t side[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_in = nullptr, ev_out = nullptr;
+    hipEvent_t ev_join[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipGraphExec_t gexec = nullptr;
+    double g_a = 0.0;
+    const double* g_f = nullptr;
+    int g_sched = -1;
 };
 
 namespace hdg {
@@ -186,6 +205,9 @@ int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out);
 bool general_supported(int physics, int k, int kf, int nrhs);
 int var_face_degree();   // face-table degree used on meshes of variable degree
 int launch_condense_general(hdg_ctx* c, double a, const double* f_loc);
+// autotune table (capi.cpp): read the entries of this context, write the tuned ones back
+void read_tune_table(hdg_ctx* c);
+void write_tune_table(const hdg_ctx* c);
 int launch_recover_general(hdg_ctx* c, const double* lam, double* u);
 int launch_refine_general(hdg_ctx* c, const double* u, const double* lam);
 // recover_mrhs.hip (acoustic, 3D, 32 right-hand sides: matrix-core recovery and refinement)
