@@ -1014,21 +1014,49 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
                 ze[idx * R + q] = (T)(s / J);
             }
             ws();
-            for (int j = 0; j < N2; ++j) {            // forward: L y = s~2
-                const double yj = sc.st[j] / (double)L[j * N2 + j];
-                ws();
-                if (lane == 0) sc.st[j] = yj;
-                for (int i = j + 1 + lane; i < N2; i += 64) sc.st[i] -= (double)L[i * N2 + j] * yj;
-                ws();
+            // ---- z2' = S^{-1} s~2 = L^{-T} L^{-1} s~2, one row per lane (rows lane + 64 s): the
+            // entry each step solves for is broadcast by readlane, and the factor entries come
+            // from the factor's global copy (L2-resident), independent of the substitution
+            // chain, so their loads run ahead of it
+            {
+                constexpr int PS = (N2 + 63) / 64;
+                double sv[PS], rd[PS];
+#pragma unroll
+                for (int t = 0; t < PS; ++t) {
+                    const int i = min(lane + 64 * t, N2 - 1);
+                    sv[t] = sc.st[i];
+                    rd[t] = 1.0 / (double)L[i * N2 + i];
+                }
+#pragma unroll 4
+                for (int j = 0; j < N2; ++j) {       // forward: L y = s~2
+                    double yj = 0.0;
+#pragma unroll
+                    for (int t = 0; t < PS; ++t)
+                        if (t == (j >> 6)) yj = wbcast(sv[t] * rd[t], j & 63);
+#pragma unroll
+                    for (int t = 0; t < PS; ++t) {
+                        const int i = lane + 64 * t;
+                        const double lij = (double)L[min(i, N2 - 1) * N2 + j];
+                        sv[t] = i == j ? yj : (i > j ? sv[t] - lij * yj : sv[t]);
+                    }
+                }
+#pragma unroll 4
+                for (int j = N2 - 1; j >= 0; --j) {  // backward: L^T x = y
+                    double xj = 0.0;
+#pragma unroll
+                    for (int t = 0; t < PS; ++t)
+                        if (t == (j >> 6)) xj = wbcast(sv[t] * rd[t], j & 63);
+#pragma unroll
+                    for (int t = 0; t < PS; ++t) {
+                        const int i = lane + 64 * t;
+                        const double lji = (double)L[j * N2 + min(i, N2 - 1)];
+                        sv[t] = i == j ? xj : (i < j ? sv[t] - lji * xj : sv[t]);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < PS; ++t)
+                    if (lane + 64 * t < N2) ze[(N1 + lane + 64 * t) * R + q] = (T)sv[t];
             }
-            for (int j = N2 - 1; j >= 0; --j) {       // backward: L^T x = y
-                const double xj = sc.st[j] / (double)L[j * N2 + j];
-                ws();
-                if (lane == 0) sc.st[j] = xj;
-                for (int i = lane; i < j; i += 64) sc.st[i] -= (double)L[j * N2 + i] * xj;
-                ws();
-            }
-            for (int idx = lane; idx < N2; idx += 64) ze[(N1 + idx) * R + q] = (T)sc.st[idx];
             ws();
         }
     }
