@@ -79,6 +79,27 @@ def acoustic_pass_bytes(D, K):
     return {"F0": f0, "R": r}
 
 
+def copy_bandwidth(reps=10):
+    """Achieved HBM bandwidth of a plain 1 GiB device-to-device copy (torch copy_, timed with
+    HIP events): the practical ceiling a streaming kernel meets on this GPU, for context."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * 8 * n / (ms * 1e-3) / 1e9
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
     (FETCH_SIZE and WRITE_SIZE scaled by the plain-copy calibration), or None when the
@@ -431,6 +452,7 @@ def main():
                                        f"{'false' if rec_src == 'fp64' else 'true'}>",
                              "precision": rec_src},
         "mixed_refinement_passes": mixed_passes,
+        "hbm_copy_achieved_GBs": copy_bandwidth(),
     }
     out["cached_factor_stage"] = {
         "basis": "secondary: per-stage element kernels with the factors kept across stages "
