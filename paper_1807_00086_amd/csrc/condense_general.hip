@@ -443,18 +443,27 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
             for (int f = 0; f < NFACE; ++f) mf[f] = (T)geo[1 + D * D + f] * Mf[(f * N + i) * N + j];
 #pragma unroll
             for (int rr = 0; rr < 9; ++rr) tf[rr] = Tfull[(rr * N + i) * N + j];
+            auto put = [&](int b, int gm) {
+                T s = (i == j) ? J * (T)cf.amass[b][gm] : T(0);
 #pragma unroll
-            for (int b = 0; b < M2; ++b)
+                for (int f = 0; f < NFACE; ++f) s += (T)cf.af[f][b][gm] * mf[f];
+                T q = 0;
 #pragma unroll
-                for (int gm = 0; gm < M2; ++gm) {
-                    T s = (i == j) ? J * (T)cf.amass[b][gm] : T(0);
+                for (int rr = 0; rr < 9; ++rr) q += (T)cf.Gam[b][gm][rr] * tf[rr];
+                Sb[(b * N + i) * N2 + gm * N + j] = s + J * q;
+            };
+            // FP64 keeps the component-pair loop rolled (unrolled, its registers spill)
+            if constexpr (sizeof(T) == 4) {
 #pragma unroll
-                    for (int f = 0; f < NFACE; ++f) s += (T)cf.af[f][b][gm] * mf[f];
-                    T q = 0;
+                for (int b = 0; b < M2; ++b)
 #pragma unroll
-                    for (int rr = 0; rr < 9; ++rr) q += (T)cf.Gam[b][gm][rr] * tf[rr];
-                    Sb[(b * N + i) * N2 + gm * N + j] = s + J * q;
-                }
+                    for (int gm = 0; gm < M2; ++gm) put(b, gm);
+            } else {
+#pragma unroll 1
+                for (int b = 0; b < M2; ++b)
+#pragma unroll 1
+                    for (int gm = 0; gm < M2; ++gm) put(b, gm);
+            }
         }
         __syncthreads();
         // ------------------------------------------------------------ Cholesky S = L L^T
@@ -1167,7 +1176,7 @@ int launch_gen_ref(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int
                    const double* lam) {
     constexpr int WPB = 1;
     constexpr int N = dimp(K, 3);
-    constexpr bool TL = (3 + 4) * N * N * 8 <= 64 * 1024;
+    constexpr bool TL = false;   // tables read through L1/L2: more wavefronts per CU than with LDS copies
     const int grid = (int)std::min<int64_t>(n, 256 * 16);
     hipLaunchKernelGGL((refine_general_kernel<PHYS, K, KF, R, T, WPB, TL>), dim3(grid), dim3(64 * WPB), 0, c->stream,
                        n, c->last_a, c->d_geom, c->d_eframe, c->d_eperm, c->d_eface, tb.Sr, tb.Mf, tb.Ef,
