@@ -337,44 +337,9 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
         const T invJ = T(1) / J;
 
         // ------------------------------------------------------------ Sr_r E_f and the f1 coupling
-        T* YE = Sb;                       // [f][r][i][l]
         T* HV = Sb + Dm::YE;              // [r][b][j][q] = sum_a cd[r][a][b] f1_a[j][q]
         const int wv = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
         using MF = Mfma<T>;
-        if constexpr (N >= 16) {
-            // YE[f][r] = Sr_r E_f as 16x16 MFMA tiles, one wavefront per tile
-            constexpr int NIT = (N + 15) / 16, NLT = (NF + 15) / 16;
-            for (int t = wv; t < NFACE * D * NIT * NLT; t += NWG) {
-                const int fr = t / (NIT * NLT), it = (t / NLT) % NIT, lt = t % NLT;
-                const int f = fr / D, r = fr % D;
-                const int ia = min(it * 16 + li, N - 1), lb = min(lt * 16 + li, NF - 1);
-                const T* Arow = &Srs[(r * N + ia) * N];
-                const T* Bcol = &El[f * N * NF + lb];
-                typename MF::acc acc = MF::zero();
-#pragma unroll 4
-                for (int j0 = 0; j0 < N; j0 += 4) {
-                    const int j = j0 + lk;
-                    const int jc = min(j, N - 1);
-                    const T av = j < N ? Arow[jc] : T(0);
-                    acc = MF::mac(av, Bcol[jc * NF], acc);
-                }
-                const int l = lt * 16 + li;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = it * 16 + MF::row(lane, v);
-                    if (i < N && l < NF) YE[((f * D + r) * N + i) * NF + l] = acc[v];
-                }
-            }
-        } else {
-            for (int idx = tid; idx < Dm::YE; idx += NTG) {
-                const int f = idx / (D * N * NF), r = (idx / (N * NF)) % D, i = (idx / NF) % N, l = idx % NF;
-                const T* Srow = &Srs[(r * N + i) * N];
-                const T* Ec = &El[f * N * NF + l];
-                T acc = 0;
-                for (int j = 0; j < N; ++j) acc += Srow[j] * Ec[j * NF];
-                YE[idx] = acc;
-            }
-        }
         for (int idx = tid; idx < Dm::HV; idx += NTG) {
             const int r = idx / (M2 * N * R), b = (idx / (N * R)) % M2, jq = idx % (N * R);
             T acc = 0;
@@ -384,27 +349,52 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
         }
         __syncthreads();
         // ------------------------------------------------------------ B~2 and f~2
-        // With many right-hand sides and one Schur component the f~2 columns are the product
-        // [Sr_0 Sr_1 Sr_2] HV, formed as MFMA tiles over the flattened (r, j) index.
+        // B~2 block (component b, face component fc) = s_f W_{b,fc} E_f with
+        // W_{b,fc} = b2[b][fc] I + sum_r kap[b][fc][r] Sr_r formed inside the A operand: one
+        // MFMA chain over the N modes per 16 x 16 tile.  With many right-hand sides and one
+        // Schur component the f~2 columns are the product [Sr_0 Sr_1 Sr_2] HV, formed as MFMA
+        // tiles over the flattened (r, j) index; otherwise one entry per thread.
         constexpr bool FMF = (R >= 16 && M2 == 1);
-        for (int idx = tid; idx < N2 * C; idx += NTG) {
-            const int row = idx / C, c = idx % C;
-            const int b = row / N, i = row % N;
-            if (c < TT) {
-                const int fc = c / NF, l = c % NF, f = fc / MT;
-                T acc = (T)cf.b2[b][fc] * El[(f * N + i) * NF + l];
+        {
+            constexpr int NIT = (N + 15) / 16, NLT = (NF + 15) / 16;
+            for (int t = wv; t < M2 * NFC * NIT * NLT; t += NWG) {
+                const int bfc = t / (NIT * NLT), it = (t / NLT) % NIT, lt = t % NLT;
+                const int b = bfc / NFC, fc = bfc % NFC, f = fc / MT;
+                const T b2 = (T)cf.b2[b][fc], c0 = (T)cf.kap[b][fc][0], c1 = (T)cf.kap[b][fc][1],
+                        c2 = (T)cf.kap[b][fc][2];
+                const int ia = min(it * 16 + li, N - 1), lb = min(lt * 16 + li, NF - 1);
+                const T* A0 = &Srs[ia * N];
+                const T* A1 = &Srs[(N + ia) * N];
+                const T* A2 = &Srs[(2 * N + ia) * N];
+                const T* Bc = &El[f * N * NF + lb];
+                typename MF::acc acc = MF::zero();
+#pragma unroll 4
+                for (int j0 = 0; j0 < N; j0 += 4) {
+                    const int j = j0 + lk, jc = min(j, N - 1);
+                    T av = c0 * A0[jc] + c1 * A1[jc] + c2 * A2[jc] + (ia == j ? b2 : T(0));
+                    av = j < N ? av : T(0);
+                    acc = MF::mac(av, Bc[jc * NF], acc);
+                }
+                const T sf = (T)geo[1 + D * D + f];
+                const int l = lt * 16 + li;
 #pragma unroll
-                for (int r = 0; r < D; ++r) acc += (T)cf.kap[b][fc][r] * YE[((f * D + r) * N + i) * NF + l];
-                X[idx] = (T)geo[1 + D * D + f] * acc;
-            } else if (!FMF) {
-                const int q = c - TT;
+                for (int v = 0; v < 4; ++v) {
+                    const int i = it * 16 + MF::row(lane, v);
+                    if (i < N && l < NF) X[(b * N + i) * C + fc * NF + l] = sf * acc[v];
+                }
+            }
+        }
+        if constexpr (!FMF) {
+            for (int idx = tid; idx < N2 * R; idx += NTG) {
+                const int row = idx / R, q = idx % R;
+                const int b = row / N, i = row % N;
                 T acc = 0;
 #pragma unroll
                 for (int r = 0; r < D; ++r) {
                     const T* Srow = &Srs[(r * N + i) * N];
                     for (int j = 0; j < N; ++j) acc += Srow[j] * HV[((r * M2 + b) * N + j) * R + q];
                 }
-                X[idx] += acc;
+                X[row * C + TT + q] += acc;
             }
         }
         if constexpr (FMF) {
