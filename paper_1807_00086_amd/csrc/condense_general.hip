@@ -84,9 +84,8 @@ struct GDims {
     static constexpr int NFC = NFACE * MT;             // (face, component) pairs
     static constexpr int TT = NFC * NF;
     static constexpr int C = TT + R;
-    static constexpr int YE = NFACE * D * N * NF;      // Sr_r E_f products
     static constexpr int HV = D * M2 * N * R;
-    static constexpr int SBUF = (N2 * N2 > YE + HV) ? N2 * N2 : YE + HV;
+    static constexpr int SBUF = (N2 * N2 > HV) ? N2 * N2 : HV;   // HV, then the Schur block
 };
 
 template <int PHYS>
@@ -337,7 +336,7 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
         const T invJ = T(1) / J;
 
         // ------------------------------------------------------------ Sr_r E_f and the f1 coupling
-        T* HV = Sb + Dm::YE;              // [r][b][j][q] = sum_a cd[r][a][b] f1_a[j][q]
+        T* HV = Sb;                       // [r][b][j][q] = sum_a cd[r][a][b] f1_a[j][q]
         const int wv = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
         using MF = Mfma<T>;
         for (int idx = tid; idx < Dm::HV; idx += NTG) {
