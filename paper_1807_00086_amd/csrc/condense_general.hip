@@ -528,7 +528,7 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
         // ------------------------------------------------------------ [W | w] = L^{-1} [B~2 | f~2]
         // Blocks of 16 rows: the diagonal block is solved one column per thread in registers
         // (factor entries by LDS broadcast), then the rows below are updated as MFMA tiles,
-        // X[below] -= L[below][block] X[block], one wavefront per 16 x 16 tile.  The upper
+        // X[below] -= L[below][block] X[block], one wavefront per strip of tiles.  The upper
         // triangle of Sb receives L^T for the backward solve.
         constexpr int BR = 16, NBR = (N2 + BR - 1) / BR, NCT = (C + 15) / 16;
         __syncthreads();
@@ -538,23 +538,43 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
         }
         for (int i = tid; i < N2; i += NTG) dinv[i] = T(1) / Sb[i * N2 + i];
         __syncthreads();
-        // X[i0.., c0..] -= sum_k F[i][r0 + k] X[r0 + k][c0..] for one 16 x 16 tile (F = L or L^T
-        // as stored in Sb; rows at or past N2 are read clamped and not written; k < BR).
-        auto tile_update = [&](int i0, int c0, int r0) {
-            const int ia = min(i0 + li, N2 - 1), cb = min(c0 + li, C - 1);
-            typename MF::acc acc;
+        // X[i0.., c0..] -= sum_k F[i][r0 + k] X[r0 + k][c0..] for a strip of up to SW 16 x 16
+        // tiles at column tiles ct0.. (F = L or L^T as stored in Sb; rows at or past N2 are read
+        // clamped and not written; k < BR).  Every load of the strip (its A operands, the tiles
+        // and their B operands) is issued before the first MFMA and every store after the last,
+        // so the strip waits on one round of (L2) latency instead of one per tile.
+        constexpr int SW = 4, NCS = (NCT + SW - 1) / SW;
+        auto strip_update = [&](int i0, int ct0, int r0) {
+            const int ia = min(i0 + li, N2 - 1);
+            T av[BR / 4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] = X[min(i0 + MF::row(lane, v), N2 - 1) * C + cb];
+            for (int k = 0; k < BR / 4; ++k) {
+                const int kr = min(r0 + 4 * k + lk, N2 - 1);
+                av[k] = r0 + 4 * k + lk < N2 ? -Sb[ia * N2 + kr] : T(0);
+            }
+            typename MF::acc acc[SW];
+            T bv[SW][BR / 4];
 #pragma unroll
-            for (int k0 = 0; k0 < BR; k0 += 4) {
-                const int kr = min(r0 + k0 + lk, N2 - 1);
-                const T av = r0 + k0 + lk < N2 ? -Sb[ia * N2 + kr] : T(0);
-                acc = MF::mac(av, X[kr * C + cb], acc);
+            for (int u = 0; u < SW; ++u) {
+                const int cb = min((ct0 + u) * 16 + li, C - 1);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] = X[min(i0 + MF::row(lane, v), N2 - 1) * C + cb];
+#pragma unroll
+                for (int k = 0; k < BR / 4; ++k) bv[u][k] = X[min(r0 + 4 * k + lk, N2 - 1) * C + cb];
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = i0 + MF::row(lane, v);
-                if (i < N2 && c0 + li < C) X[i * C + c0 + li] = acc[v];
+            for (int u = 0; u < SW; ++u)
+#pragma unroll
+                for (int k = 0; k < BR / 4; ++k) acc[u] = MF::mac(av[k], bv[u][k], acc[u]);
+#pragma unroll
+            for (int u = 0; u < SW; ++u) {
+                const int c = (ct0 + u) * 16 + li;
+                if (ct0 + u < NCT && c < C)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = i0 + MF::row(lane, v);
+                        if (i < N2) X[i * C + c] = acc[u][v];
+                    }
             }
         };
 #pragma unroll 1
@@ -577,7 +597,7 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
             }
             __syncthreads();
             const int nrt = (N2 - r0 - BR + 15) / 16;   // row tiles below the block (<= 0: none)
-            for (int t = wv; t < nrt * NCT; t += NWG) tile_update(r0 + BR + (t / NCT) * 16, (t % NCT) * 16, r0);
+            for (int t = wv; t < nrt * NCS; t += NWG) strip_update(r0 + BR + (t / NCS) * 16, (t % NCS) * SW, r0);
             __syncthreads();
         }
         // ------------------------------------------------------------ K_e, r_e
@@ -706,7 +726,7 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                 }
             }
             __syncthreads();
-            for (int t = wv; t < (r0 / 16) * NCT; t += NWG) tile_update((t / NCT) * 16, (t % NCT) * 16, r0);
+            for (int t = wv; t < (r0 / 16) * NCS; t += NWG) strip_update((t / NCS) * 16, (t % NCS) * SW, r0);
             __syncthreads();
         }
         T* Zse = Zs + e * strZ;
