@@ -60,6 +60,18 @@ __device__ __forceinline__ float wbcast(float v, int src) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
+// Reciprocal of a pivot: the hardware reciprocal, refined by two Newton steps in FP64 (to the
+// rounding of a division); in FP32 the hardware value (within one ulp), as the FP32 factors are
+// refined in FP64 anyway.
+__device__ __forceinline__ double piv_rcp(double p) {
+    double r = __builtin_amdgcn_rcp(p);
+    double e = fma(-p, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-p, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float piv_rcp(float p) { return __builtin_amdgcn_rcpf(p); }
+
 template <int PHYS>
 struct PhysDims;
 template <>
@@ -478,7 +490,7 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                     const T p = wbcast(x[j], j);
                     bad |= !(p > ptol && p - p == T(0));
                     dl = lane == j ? p : dl;
-                    const T t = x[j] / p;
+                    const T t = x[j] * piv_rcp(p);
 #pragma unroll
                     for (int i = j + 1; i < N2; ++i) x[i] -= wbcast(x[i], j) * t;
                 }
@@ -505,7 +517,7 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
             for (int j = 0; j < N2; ++j) {
                 const T djj = Sb[j * N2 + j];
                 if (tid == 0 && !(djj > ptol && djj - djj == T(0))) atomicOr(status, 1);
-                const T rinv = T(1) / djj;
+                const T rinv = piv_rcp(djj);
                 for (int i = j + 1 + ((ty - j - 1) & 15); i < N2; i += 16) {
                     const T lij = Sb[i * N2 + j] * rinv;
                     T* Si = &Sb[i * N2];
