@@ -291,7 +291,9 @@ constexpr int64_t gen_gstride(int SG) {
     return (SG >= 1 ? (int64_t)Dm::N2 * Dm::C : 0) + (SG >= 2 ? (int64_t)Dm::SBUF + Dm::N1 * R : 0);
 }
 
-template <int PHYS, int K, int KF, int R, typename T, int SG>
+// TBL: the Sr tables staged in LDS once per workgroup (true) or read through L1/L2 (false, which
+// leaves more LDS for workgroups per CU).
+template <int PHYS, int K, int KF, int R, typename T, int SG, bool TBL>
 __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void condense_general_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
     const int32_t* __restrict__ eperm, const T* __restrict__ Sr, const T* __restrict__ Mf,
@@ -303,7 +305,8 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
     constexpr int M1 = Dm::M1, M2 = Dm::M2, MT = Dm::MT, N1 = Dm::N1, N2 = Dm::N2, NLOC = Dm::NLOC;
     constexpr int NFC = Dm::NFC, TT = Dm::TT, C = Dm::C;
 
-    __shared__ T Srs[D * N * N];
+    __shared__ T Srl[TBL ? D * N * N : 1];
+    const T* Srs = TBL ? Srl : Sr;
     __shared__ T Sbl[SG >= 2 ? 1 : Dm::SBUF];
     __shared__ T El[NFACE * N * NF];
     __shared__ T F1l[SG >= 2 ? 1 : N1 * R];
@@ -320,7 +323,8 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
     const int64_t strL = va.strL ? va.strL : (int64_t)N2 * N2;
     const int tid = threadIdx.x;
 
-    for (int idx = tid; idx < D * N * N; idx += NTG) Srs[idx] = Sr[idx];
+    if (TBL)
+        for (int idx = tid; idx < D * N * N; idx += NTG) Srl[idx] = Sr[idx];
 
     for (int64_t ie = blockIdx.x; ie < ne; ie += gridDim.x) {
         const int64_t e = va.elist ? (int64_t)va.elist[ie] : ie;
@@ -1124,11 +1128,11 @@ VarArgs var_args(const hdg_ctx* c, const int32_t* elist) {
 }
 
 // Launch schedules of the condensation kernel: SG places the element buffers (see
-// gen_gstride).  LDS bytes of a workgroup for each placement:
+// gen_gstride) and TBL the Sr tables.  LDS bytes of a workgroup for each placement:
 template <int PHYS, int K, int KF, int R, typename T>
-constexpr size_t gen_lds(int SG) {
+constexpr size_t gen_lds(int SG, bool TBL) {
     using Dm = GDims<PHYS, K, KF, R>;
-    const size_t base = sizeof(T) * (Dm::D * Dm::N * Dm::N + Dm::NFACE * Dm::N * Dm::NF + Dm::N2) +
+    const size_t base = sizeof(T) * ((TBL ? Dm::D * Dm::N * Dm::N : 0) + Dm::NFACE * Dm::N * Dm::NF + Dm::N2) +
                         sizeof(Coef<PHYS>) + 8 * 64;
     const size_t mid = base + sizeof(T) * (Dm::SBUF + Dm::N1 * R);
     const size_t all = mid + sizeof(T) * Dm::N2 * Dm::C;
@@ -1136,18 +1140,23 @@ constexpr size_t gen_lds(int SG) {
 }
 constexpr size_t LDS_SHARE = 75 * 1024;    // two workgroups per CU
 constexpr size_t LDS_CU = 159 * 1024;      // one workgroup per CU (160 KB less slack)
-// schedule 0 (default): at most 75 KB of LDS per workgroup, so that two workgroups share a CU,
-// the element buffers that do not fit in global scratch (L2-resident); schedule 1 (when it
-// differs): the fewest buffers in global scratch that fit a whole CU's LDS, one workgroup per CU
+template <int PHYS, int K, int KF, int R, typename T>
+constexpr int gen_fit(size_t cap, bool tbl) {
+    return gen_lds<PHYS, K, KF, R, T>(0, tbl) <= cap ? 0 : (gen_lds<PHYS, K, KF, R, T>(1, tbl) <= cap ? 1 : 2);
+}
+// schedule 0 (default): tables in LDS and at most 75 KB of LDS per workgroup, so that two
+// workgroups share a CU, the element buffers that do not fit in global scratch (L2-resident);
+// schedule 1: tables in LDS and the fewest buffers in global scratch that fit a whole CU's LDS
+// (one workgroup per CU); schedule 2: tables through L1/L2 and the 75 KB rule.  A schedule that
+// repeats an earlier placement is not built.
 template <int PHYS, int K, int KF, int R, typename T>
 constexpr int gen_sg(int sched) {
-    constexpr int s0 = gen_lds<PHYS, K, KF, R, T>(0) <= LDS_SHARE ? 0 : (gen_lds<PHYS, K, KF, R, T>(1) <= LDS_SHARE ? 1 : 2);
-    constexpr int s1 = gen_lds<PHYS, K, KF, R, T>(0) <= LDS_CU ? 0 : (gen_lds<PHYS, K, KF, R, T>(1) <= LDS_CU ? 1 : 2);
-    return sched == 1 ? s1 : s0;
+    return sched == 0 ? gen_fit<PHYS, K, KF, R, T>(LDS_SHARE, true)
+                      : (sched == 1 ? gen_fit<PHYS, K, KF, R, T>(LDS_CU, true) : gen_fit<PHYS, K, KF, R, T>(LDS_SHARE, false));
 }
 template <int PHYS, int K, int KF, int R, typename T>
-constexpr int gen_nsched() {
-    return gen_sg<PHYS, K, KF, R, T>(0) == gen_sg<PHYS, K, KF, R, T>(1) ? 1 : 2;
+constexpr bool gen_built(int sched) {
+    return sched == 0 || (sched == 1 && gen_sg<PHYS, K, KF, R, T>(1) != gen_sg<PHYS, K, KF, R, T>(0)) || sched == 2;
 }
 template <int PHYS, int K, int KF, int R>
 int gen_grid(int64_t n) {
@@ -1159,24 +1168,27 @@ size_t gen_scratch(int64_t n, int sched) {
     return (size_t)gen_grid<PHYS, K, KF, R>(n) * gen_gstride<PHYS, K, KF, R>(gen_sg<PHYS, K, KF, R, T>(sched)) * sizeof(T);
 }
 
-template <int PHYS, int K, int KF, int R, typename T, int SG>
+template <int PHYS, int K, int KF, int R, typename T, int SG, bool TBL>
 int launch_gen_sg(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist,
                   int64_t n, T* scratch, hipStream_t st) {
     using TB = TabOf<T>;
-    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, KF, R, T, SG>), dim3(gen_grid<PHYS, K, KF, R>(n)), dim3(NTG),
-                       0, st, n, a, c->d_geom, c->d_eframe, c->d_eperm, TB::Sr(tb), TB::Mf(tb), TB::Tf(tb), TB::Ef(tb),
-                       f_loc, (T*)c->d_Ke, (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
+    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, KF, R, T, SG, TBL>), dim3(gen_grid<PHYS, K, KF, R>(n)),
+                       dim3(NTG), 0, st, n, a, c->d_geom, c->d_eframe, c->d_eperm, TB::Sr(tb), TB::Mf(tb), TB::Tf(tb),
+                       TB::Ef(tb), f_loc, (T*)c->d_Ke, (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
                        c->precision == HDG_MIXED_FP32 ? (T*)c->d_LU : (T*)nullptr, scratch, c->d_status,
                        var_args(c, elist));
     return (int)hipGetLastError();
 }
 
+// schedule `sched` (0..2) of a class; a schedule that is not built falls back to 0
 template <int PHYS, int K, int KF, int R, typename T>
 int launch_gen(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist, int64_t n,
                int sched, T* scratch, hipStream_t st) {
-    constexpr int S0 = gen_sg<PHYS, K, KF, R, T>(0), S1 = gen_sg<PHYS, K, KF, R, T>(1);
-    if (sched == 1 && S1 != S0) return launch_gen_sg<PHYS, K, KF, R, T, S1>(c, a, f_loc, tb, elist, n, scratch, st);
-    return launch_gen_sg<PHYS, K, KF, R, T, S0>(c, a, f_loc, tb, elist, n, scratch, st);
+    constexpr int S0 = gen_sg<PHYS, K, KF, R, T>(0), S1 = gen_sg<PHYS, K, KF, R, T>(1), S2 = gen_sg<PHYS, K, KF, R, T>(2);
+    if constexpr (gen_built<PHYS, K, KF, R, T>(1))
+        if (sched == 1) return launch_gen_sg<PHYS, K, KF, R, T, S1, true>(c, a, f_loc, tb, elist, n, scratch, st);
+    if (sched == 2) return launch_gen_sg<PHYS, K, KF, R, T, S2, false>(c, a, f_loc, tb, elist, n, scratch, st);
+    return launch_gen_sg<PHYS, K, KF, R, T, S0, true>(c, a, f_loc, tb, elist, n, scratch, st);
 }
 
 template <int PHYS, int K, int KF, int R, typename T>
@@ -1219,6 +1231,7 @@ int launch_gen_ref(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int
     X(0, 1, 5, 32) X(0, 2, 5, 32) X(0, 3, 5, 32) X(0, 4, 5, 32) X(0, 5, 5, 32)
 
 constexpr int VAR_KF = 5;
+constexpr int NSCHED = 3;   // launch schedules of the condensation (see gen_sg)
 
 // Calls `fn(K, KF, tables, list, count)` for every launch of the current mesh: one per degree
 // class on a mesh of variable degree, one for all elements otherwise.
@@ -1233,7 +1246,8 @@ int for_each_class(hdg_ctx* c, Fn fn) {
     return 0;
 }
 
-// One class launch (op 0), its schedule count (op 1) or its scratch need in bytes (op 2).
+// One class launch (op 0), whether schedule g.sched is built for it (op 1) or its scratch need in
+// bytes (op 2).
 struct GenOp {
     int op = 0, sched = 0;
     double a = 0;
@@ -1249,11 +1263,12 @@ int gen_class(hdg_ctx* c, int K, int KF, const DeviceTables& tb, const int32_t* 
 #define HDG_CASE(PP, KK, FF, RR)                                                                        \
     if (P == PP && K == KK && KF == FF && R == RR) {                                                     \
         if (g.op == 1) {                                                                                 \
-            g.out = (size_t)gen_nsched<PP, KK, FF, RR, T>();                                             \
+            g.out = (size_t)(gen_built<PP, KK, FF, RR, T>(g.sched) ? 1 : 0);                             \
             return 0;                                                                                    \
         }                                                                                                \
         if (g.op == 2) {                                                                                 \
-            g.out = std::max(gen_scratch<PP, KK, FF, RR, T>(n, 0), gen_scratch<PP, KK, FF, RR, T>(n, 1)); \
+            g.out = std::max({gen_scratch<PP, KK, FF, RR, T>(n, 0), gen_scratch<PP, KK, FF, RR, T>(n, 1),  \
+                              gen_scratch<PP, KK, FF, RR, T>(n, 2)});                                    \
             return 0;                                                                                    \
         }                                                                                                \
         return launch_gen<PP, KK, FF, RR, T>(c, g.a, g.f_loc, tb, el, n, g.sched, (T*)g.scratch, g.st);   \
@@ -1321,10 +1336,16 @@ int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
     bool tuned = false;
     for (auto& [k, cr] : classes) {
         if (c->sched[pi][k] >= 0) continue;
-        GenOp q;
-        q.op = 1;
-        (void)gen_class<T>(c, cr.K, cr.KF, *cr.tb, cr.el, cr.n, q);
-        const int ns = (int)q.out;
+        bool built[NSCHED];
+        int ns = 0;
+        for (int sc = 0; sc < NSCHED; ++sc) {
+            GenOp q;
+            q.op = 1;
+            q.sched = sc;
+            (void)gen_class<T>(c, cr.K, cr.KF, *cr.tb, cr.el, cr.n, q);
+            built[sc] = q.out != 0;
+            ns += built[sc];
+        }
         if (!c->autotune || ns < 2) {
             c->sched[pi][k] = 0;
             continue;
@@ -1336,7 +1357,8 @@ int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
         }
         float best = 0;
         int bs = 0, err = 0;
-        for (int s = 0; s < ns && !err; ++s) {
+        for (int s = 0; s < NSCHED && !err; ++s) {
+            if (!built[s]) continue;
             float ms = 0, t = 0;
             for (int rep = 0; rep < 2 && !err; ++rep) {   // the first run warms caches and code
                 g.sched = s;
@@ -1361,7 +1383,7 @@ int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
     }
     if (tuned && !c->tune_path.empty()) write_tune_table(c);
     int key = 0;
-    for (auto& [k, cr] : classes) key = key * 4 + c->sched[pi][k];
+    for (auto& [k, cr] : classes) key = key * NSCHED + c->sched[pi][k];
 
     if (!c->use_graph || !c->vardeg || !c->side[0]) {
         for (auto& [k, cr] : classes) {

@@ -1,7 +1,8 @@
 """Launch schedules of the block-structured condensation: the autotuner, its table file, and
 the hipGraph that runs the degree classes of a variable-degree mesh as one launch.
 
-A schedule only moves element buffers between LDS and per-workgroup global scratch, and the
+A schedule only moves element buffers between LDS and per-workgroup global scratch (and the
+reference tables between LDS and the caches), and the
 graph only changes how the class kernels are launched, so every variant must give the
 default's result (relative 1e-13 here; in practice bitwise) and stay within the oracle
 tolerances (FP64 1e-12, mixed FP32 + FP64 refinement 1e-10, relative L2 per field).
@@ -93,7 +94,7 @@ def test_autotuned_schedules_match_default(cfg, kw, prec, tmp_path):
     u1b, _ = _stage(s1, a, f, lb)          # second stage: the tuned schedules, no timing
     s1.close()
     assert set(sch1) == set(sch0)
-    assert all(v in (0, 1) for v in sch1.values())
+    assert all(v in (0, 1, 2) for v in sch1.values())
     assert _rel(u1, u0) <= 1e-13 and _rel(lam1, lam0) <= 1e-13
     assert _rel(u1b, u0) <= 1e-13
     if p.uniform_k:
