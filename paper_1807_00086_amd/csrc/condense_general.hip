@@ -315,6 +315,10 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
     __shared__ double geo[GEOM_STRIDE];
     __shared__ double frm[24];
     __shared__ T dinv[N2];
+    // Schur blocks of at most 64 unknowns with one right-hand side: the one-wavefront register
+    // Cholesky runs while the other wavefronts form B~2 and f~2 (HV then has its own buffer)
+    constexpr bool OVL = (N2 <= 64 && R == 1);
+    __shared__ T HVl[OVL ? Dm::HV : 1];
     T* gsc = Xglob + (size_t)blockIdx.x * gen_gstride<PHYS, K, KF, R>(SG);
     T* X = SG >= 1 ? gsc : Xl;
     T* Sb = SG >= 2 ? gsc + (int64_t)N2 * C : Sbl;
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
         const T invJ = T(1) / J;
 
         // ------------------------------------------------------------ Sr_r E_f and the f1 coupling
-        T* HV = Sb;                       // [r][b][j][q] = sum_a cd[r][a][b] f1_a[j][q]
+        T* HV = OVL ? HVl : Sb;           // [r][b][j][q] = sum_a cd[r][a][b] f1_a[j][q]
         const int wv = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
         using MF = Mfma<T>;
         for (int idx = tid; idx < Dm::HV; idx += NTG) {
@@ -363,123 +367,125 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
             HV[idx] = acc;
         }
         __syncthreads();
-        // ------------------------------------------------------------ B~2 and f~2
-        // B~2 block (component b, face component fc) = s_f W_{b,fc} E_f with
-        // W_{b,fc} = b2[b][fc] I + sum_r kap[b][fc][r] Sr_r formed inside the A operand: one
-        // MFMA chain over the N modes per 16 x 16 tile.  With many right-hand sides and one
-        // Schur component the f~2 columns are the product [Sr_0 Sr_1 Sr_2] HV, formed as MFMA
-        // tiles over the flattened (r, j) index; otherwise one entry per thread.
-        constexpr bool FMF = (R >= 16 && M2 == 1);
-        {
-            constexpr int NIT = (N + 15) / 16, NLT = (NF + 15) / 16;
-            for (int t = wv; t < M2 * NFC * NIT * NLT; t += NWG) {
-                const int bfc = t / (NIT * NLT), it = (t / NLT) % NIT, lt = t % NLT;
-                const int b = bfc / NFC, fc = bfc % NFC, f = fc / MT;
-                const T b2 = (T)cf.b2[b][fc], c0 = (T)cf.kap[b][fc][0], c1 = (T)cf.kap[b][fc][1],
-                        c2 = (T)cf.kap[b][fc][2];
-                const int ia = min(it * 16 + li, N - 1), lb = min(lt * 16 + li, NF - 1);
-                const T* A0 = &Srs[ia * N];
-                const T* A1 = &Srs[(N + ia) * N];
-                const T* A2 = &Srs[(2 * N + ia) * N];
-                const T* Bc = &El[f * N * NF + lb];
-                typename MF::acc acc = MF::zero();
-#pragma unroll 4
-                for (int j0 = 0; j0 < N; j0 += 4) {
-                    const int j = j0 + lk, jc = min(j, N - 1);
-                    T av = c0 * A0[jc] + c1 * A1[jc] + c2 * A2[jc] + (ia == j ? b2 : T(0));
-                    av = j < N ? av : T(0);
-                    acc = MF::mac(av, Bc[jc * NF], acc);
-                }
-                const T sf = (T)geo[1 + D * D + f];
-                const int l = lt * 16 + li;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = it * 16 + MF::row(lane, v);
-                    if (i < N && l < NF) X[(b * N + i) * C + fc * NF + l] = sf * acc[v];
-                }
-            }
-        }
-        if constexpr (!FMF) {
-            for (int idx = tid; idx < N2 * R; idx += NTG) {
-                const int row = idx / R, q = idx % R;
-                const int b = row / N, i = row % N;
-                T acc = 0;
-#pragma unroll
-                for (int r = 0; r < D; ++r) {
-                    const T* Srow = &Srs[(r * N + i) * N];
-                    for (int j = 0; j < N; ++j) acc += Srow[j] * HV[((r * M2 + b) * N + j) * R + q];
-                }
-                X[row * C + TT + q] += acc;
-            }
-        }
-        if constexpr (FMF) {
-            constexpr int NIT = (N + 15) / 16, NQT = R / 16, KK = D * N;
-            for (int t = wv; t < NIT * NQT; t += NWG) {
-                const int it = t / NQT, q0 = (t % NQT) * 16;
-                const int ia = min(it * 16 + li, N - 1);
-                typename MF::acc acc;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = min(it * 16 + MF::row(lane, v), N - 1);
-                    acc[v] = X[i * C + TT + q0 + li];
-                }
-#pragma unroll 4
-                for (int k0 = 0; k0 < KK; k0 += 4) {
-                    const int kk = min(k0 + lk, KK - 1);
-                    const int r = kk / N, j = kk - r * N;
-                    const T av = k0 + lk < KK ? Srs[(r * N + ia) * N + j] : T(0);
-                    acc = MF::mac(av, HV[kk * R + q0 + li], acc);
-                }
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = it * 16 + MF::row(lane, v);
-                    if (i < N) X[i * C + TT + q0 + li] = acc[v];
+        // B~2 and f~2 by the wavefronts [w0, w0 + nw) of the workgroup
+        auto form_b2 = [&](int w0, int nw) {
+            // ------------------------------------------------------------ B~2 and f~2
+            // B~2 block (component b, face component fc) = s_f W_{b,fc} E_f with
+            // W_{b,fc} = b2[b][fc] I + sum_r kap[b][fc][r] Sr_r formed inside the A operand: one
+            // MFMA chain over the N modes per 16 x 16 tile.  With many right-hand sides and one
+            // Schur component the f~2 columns are the product [Sr_0 Sr_1 Sr_2] HV, formed as MFMA
+            // tiles over the flattened (r, j) index; otherwise one entry per thread.
+            constexpr bool FMF = (R >= 16 && M2 == 1);
+            {
+                constexpr int NIT = (N + 15) / 16, NLT = (NF + 15) / 16;
+                for (int t = wv - w0; t >= 0 && t < M2 * NFC * NIT * NLT; t += nw) {
+                    const int bfc = t / (NIT * NLT), it = (t / NLT) % NIT, lt = t % NLT;
+                    const int b = bfc / NFC, fc = bfc % NFC, f = fc / MT;
+                    const T b2 = (T)cf.b2[b][fc], c0 = (T)cf.kap[b][fc][0], c1 = (T)cf.kap[b][fc][1],
+                            c2 = (T)cf.kap[b][fc][2];
+                    const int ia = min(it * 16 + li, N - 1), lb = min(lt * 16 + li, NF - 1);
+                    const T* A0 = &Srs[ia * N];
+                    const T* A1 = &Srs[(N + ia) * N];
+                    const T* A2 = &Srs[(2 * N + ia) * N];
+                    const T* Bc = &El[f * N * NF + lb];
+                    typename MF::acc acc = MF::zero();
+    #pragma unroll 4
+                    for (int j0 = 0; j0 < N; j0 += 4) {
+                        const int j = j0 + lk, jc = min(j, N - 1);
+                        T av = c0 * A0[jc] + c1 * A1[jc] + c2 * A2[jc] + (ia == j ? b2 : T(0));
+                        av = j < N ? av : T(0);
+                        acc = MF::mac(av, Bc[jc * NF], acc);
+                    }
+                    const T sf = (T)geo[1 + D * D + f];
+                    const int l = lt * 16 + li;
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = it * 16 + MF::row(lane, v);
+                        if (i < N && l < NF) X[(b * N + i) * C + fc * NF + l] = sf * acc[v];
+                    }
                 }
             }
-        }
-        __syncthreads();
-        // ------------------------------------------------------------ S
-        // the reference tables depend on the mode pair (i, j) only: each is read once per pair
-        // and serves every component pair (b, gm)
-        for (int idx = tid; idx < N * N; idx += NTG) {
-            const int i = idx / N, j = idx % N;
-            T mf[NFACE], tf[9];
-#pragma unroll
-            for (int f = 0; f < NFACE; ++f) mf[f] = (T)geo[1 + D * D + f] * Mf[(f * N + i) * N + j];
-#pragma unroll
-            for (int rr = 0; rr < 9; ++rr) tf[rr] = Tfull[(rr * N + i) * N + j];
-            auto put = [&](int b, int gm) {
-                T s = (i == j) ? J * (T)cf.amass[b][gm] : T(0);
-#pragma unroll
-                for (int f = 0; f < NFACE; ++f) s += (T)cf.af[f][b][gm] * mf[f];
-                T q = 0;
-#pragma unroll
-                for (int rr = 0; rr < 9; ++rr) q += (T)cf.Gam[b][gm][rr] * tf[rr];
-                Sb[(b * N + i) * N2 + gm * N + j] = s + J * q;
-            };
-            // FP64 keeps the component-pair loop rolled (unrolled, its registers spill)
-            if constexpr (sizeof(T) == 4) {
-#pragma unroll
-                for (int b = 0; b < M2; ++b)
-#pragma unroll
-                    for (int gm = 0; gm < M2; ++gm) put(b, gm);
-            } else {
-#pragma unroll 1
-                for (int b = 0; b < M2; ++b)
-#pragma unroll 1
-                    for (int gm = 0; gm < M2; ++gm) put(b, gm);
+            if constexpr (!FMF) {
+                for (int idx = tid - 64 * w0; idx >= 0 && idx < N2 * R; idx += 64 * nw) {
+                    const int row = idx / R, q = idx % R;
+                    const int b = row / N, i = row % N;
+                    T acc = 0;
+    #pragma unroll
+                    for (int r = 0; r < D; ++r) {
+                        const T* Srow = &Srs[(r * N + i) * N];
+                        for (int j = 0; j < N; ++j) acc += Srow[j] * HV[((r * M2 + b) * N + j) * R + q];
+                    }
+                    X[row * C + TT + q] += acc;
+                }
             }
-        }
-        __syncthreads();
+            if constexpr (FMF) {
+                constexpr int NIT = (N + 15) / 16, NQT = R / 16, KK = D * N;
+                for (int t = wv - w0; t >= 0 && t < NIT * NQT; t += nw) {
+                    const int it = t / NQT, q0 = (t % NQT) * 16;
+                    const int ia = min(it * 16 + li, N - 1);
+                    typename MF::acc acc;
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = min(it * 16 + MF::row(lane, v), N - 1);
+                        acc[v] = X[i * C + TT + q0 + li];
+                    }
+    #pragma unroll 4
+                    for (int k0 = 0; k0 < KK; k0 += 4) {
+                        const int kk = min(k0 + lk, KK - 1);
+                        const int r = kk / N, j = kk - r * N;
+                        const T av = k0 + lk < KK ? Srs[(r * N + ia) * N + j] : T(0);
+                        acc = MF::mac(av, HV[kk * R + q0 + li], acc);
+                    }
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = it * 16 + MF::row(lane, v);
+                        if (i < N) X[i * C + TT + q0 + li] = acc[v];
+                    }
+                }
+            }
+        };
+        auto form_s = [&]() {
+            // ------------------------------------------------------------ S
+            // the reference tables depend on the mode pair (i, j) only: each is read once per pair
+            // and serves every component pair (b, gm)
+            for (int idx = tid; idx < N * N; idx += NTG) {
+                const int i = idx / N, j = idx % N;
+                T mf[NFACE], tf[9];
+    #pragma unroll
+                for (int f = 0; f < NFACE; ++f) mf[f] = (T)geo[1 + D * D + f] * Mf[(f * N + i) * N + j];
+    #pragma unroll
+                for (int rr = 0; rr < 9; ++rr) tf[rr] = Tfull[(rr * N + i) * N + j];
+                auto put = [&](int b, int gm) {
+                    T s = (i == j) ? J * (T)cf.amass[b][gm] : T(0);
+    #pragma unroll
+                    for (int f = 0; f < NFACE; ++f) s += (T)cf.af[f][b][gm] * mf[f];
+                    T q = 0;
+    #pragma unroll
+                    for (int rr = 0; rr < 9; ++rr) q += (T)cf.Gam[b][gm][rr] * tf[rr];
+                    Sb[(b * N + i) * N2 + gm * N + j] = s + J * q;
+                };
+                // FP64 keeps the component-pair loop rolled (unrolled, its registers spill)
+                if constexpr (sizeof(T) == 4) {
+    #pragma unroll
+                    for (int b = 0; b < M2; ++b)
+    #pragma unroll
+                        for (int gm = 0; gm < M2; ++gm) put(b, gm);
+                } else {
+    #pragma unroll 1
+                    for (int b = 0; b < M2; ++b)
+    #pragma unroll 1
+                        for (int gm = 0; gm < M2; ++gm) put(b, gm);
+                }
+            }
+        };
         // ------------------------------------------------------------ Cholesky S = L L^T
         // N2 <= 64: one wavefront, lane c holding column c of S in registers, Gaussian
         // elimination without pivoting (S = L_u diag(d) L_u^T) with readlane broadcasts; lane c
         // then writes row c of L = L_u diag(d)^{1/2} (L[c][j] = U[j][c] / sqrt(d_j), U =
         // diag(d) L_u^T the eliminated rows).  Larger blocks: right-looking with barriers.
-        if constexpr (N2 <= 64) {
-            __syncthreads();
-            if (tid < 64) {
-                const int lane = tid, cl = min(lane, N2 - 1);
+        auto chol_small = [&]() {   // wavefront 0
+            if constexpr (N2 <= 64) {
+                const int cl = min(lane, N2 - 1);
                 T x[N2];
 #pragma unroll
                 for (int i = 0; i < N2; ++i) x[i] = Sb[cl * N2 + i];   // row cl = column cl
@@ -506,9 +512,26 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                     if (lane < N2 && j <= lane) Sb[lane * N2 + j] = x[j] * sj;
                 }
             }
+        };
+        if constexpr (OVL) {
+            form_s();
+            __syncthreads();
+            if (wv == 0) chol_small();
+            else form_b2(1, NWG - 1);
+            __syncthreads();
+        } else if constexpr (N2 <= 64) {
+            form_b2(0, NWG);
+            __syncthreads();
+            form_s();
+            __syncthreads();
+            if (wv == 0) chol_small();
             __syncthreads();
         } else
         {
+            form_b2(0, NWG);
+            __syncthreads();
+            form_s();
+            __syncthreads();
             // Right-looking elimination S = L_u diag(d) L_u^T with one barrier per pivot: at step
             // j column j below the diagonal is final, and the threads, as a 16 x 16 grid, update
             // the trailing lower triangle (rows i = ty mod 16, columns m = tx mod 16, m <= i)
