@@ -100,24 +100,38 @@ def copy_bandwidth(reps=10):
     return 2 * 8 * n / (ms * 1e-3) / 1e9
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
-    (FETCH_SIZE and WRITE_SIZE scaled by the plain-copy calibration), or None when the
-    summary is missing or was taken on a different version of the kernel source."""
+def _profile_record(fname, tag, kernel):
+    """Machine-readable record `<tag>: {json}` of `kernel` in a committed rocprofv3 summary
+    under profiles/, or None when it is missing or was taken on a different version of the
+    kernel source (the record carries the first 16 hex digits of the source's SHA-256)."""
     import hashlib
     import re as _re
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_acoustic_k3.md")
+    path = os.path.join(ROOT, "profiles", fname)
     src = os.path.join(ROOT, "paper_1807_00086_amd", "csrc", "condense_acoustic.hip")
     try:
         text = open(path).read()
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    for m in _re.finditer(r"^traffic: (\{.*\})$", text, _re.M):
+    for m in _re.finditer(r"^" + tag + r": (\{.*\})$", text, _re.M):
         rec = json.loads(m.group(1))
         if rec.get("kernel") == kernel and rec.get("source_sha256_16") == digest:
-            return rec["bytes_per_launch"]
+            return rec
     return None
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary (FETCH_SIZE and
+    WRITE_SIZE scaled by the plain-copy calibration), or None (see _profile_record)."""
+    rec = _profile_record("hbm_traffic_acoustic_k3.md", "traffic", kernel)
+    return None if rec is None else rec["bytes_per_launch"]
+
+
+def measured_mfma_busy(kernel):
+    """Fraction of the matrix cores' cycles busy during `kernel` from the committed PMC summary
+    (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE per XCD x 256 CUs x 4 SIMDs), or None."""
+    rec = _profile_record("mfma_utilisation_condense.md", "mfma", kernel)
+    return None if rec is None else rec["busy"]
 
 
 def cpu_baseline(problem, a, budget_s=15.0):
@@ -445,7 +459,8 @@ def main():
                      "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(kname),
                      "kernel": kname,
                      "bytes_per_element": cnt["cond_bytes"], "flops_per_element": cnt["cond_flops"],
-                     "flop_frac_fp64_peak": achieved_tf / FP64_PEAK_TFLOPS},
+                     "flop_frac_fp64_peak": achieved_tf / FP64_PEAK_TFLOPS,
+                     "mfma_busy": measured_mfma_busy(kname)},
         "recover_roofline": {"bound": "hbm", "achieved": rec_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": rec_gbs / HBM_PEAK_GBS, "bytes_per_element": rec_cnt["rec_bytes"],
                              "kernel": f"refine_acoustic_kernel<3,{k},1,{'double' if rec_src == 'fp64' else 'float'},"
