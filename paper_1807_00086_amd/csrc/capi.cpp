@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <unistd.h>
 #include <new>
 #include <sstream>
 #include <string>
@@ -61,7 +62,9 @@ void write_tune_table(const hdg_ctx* c) {
         }
         std::fclose(fp);
     }
-    const std::string tmp = c->tune_path + ".tmp";
+    // written beside the table under a per-process name, then renamed over it (the rename is
+    // atomic, so a reader sees either the old or the new table; concurrent writers: last wins)
+    const std::string tmp = c->tune_path + ".tmp" + std::to_string((long)getpid());
     FILE* fp = std::fopen(tmp.c_str(), "w");
     if (!fp) return;
     if (keep.empty()) std::fprintf(fp, "# device physics k kF nrhs precision schedule ms_0 ms_1 ms_2 (0: not built)\n");
