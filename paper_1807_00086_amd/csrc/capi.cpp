@@ -373,6 +373,8 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(dalloc(c, &c->d_status, 1));
     const int64_t ntr = c->n_trace_dofs;
     TRY(dalloc(c, &c->d_bsr, c->n_faces * c->nslot * c->bs * c->bs));
+    if (c->precision == HDG_MIXED_FP32 && R == 1 && c->nslot == 7)
+        TRY(dalloc(c, &c->d_bsr32, c->n_faces * c->nslot * c->bs * c->bs));
     TRY(dalloc(c, &c->d_rhs, ntr * R));
     TRY(dalloc(c, &c->d_pinv, c->n_faces * c->bs * c->bs));
     TRY(dalloc(c, &c->d_cg_r, ntr * R));
@@ -485,6 +487,7 @@ hdg_status hdg_condense(hdg_ctx* c, double a, const double* f_loc, const double*
         EventTimer t(c, &c->tim.assemble);
         e = launch_assemble(c, lam_bnd);
         if (!e) e = launch_block_inverse(c);
+        if (!e) e = launch_bsr_f32(c);
     }
     if (e) return fail(c, HDG_E_HIP, "assembly kernel launch failed");
     c->last_a = a;
@@ -581,7 +584,7 @@ static hdg_status recover_refine_acoustic(hdg_ctx* c, double* lambda, double* u)
             HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
             int its;
             double rr;
-            r = trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr);
+            r = trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr, true);
         }
         if (r && r != HDG_E_NOCONV) return fail(c, r, "refinement trace solve failed");
         launch_axpy(c, nt, 1.0, c->d_dlam, lambda);
@@ -658,7 +661,7 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
             HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
             int its;
             double rr;
-            r = trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr);
+            r = trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr, true);
         }
         if (r && r != HDG_E_NOCONV) return fail(c, r, "refinement trace solve failed");
         {
@@ -937,7 +940,7 @@ void hdg_destroy(hdg_ctx* c) {
     void* ptrs[] = {c->d_geom, c->d_eface, c->d_eperm, c->d_face_elem, c->d_face_lf, c->d_face_bnd,
                     c->d_bsr_cols, c->tab.Sr, c->tab.Mf, c->tab.Tsym, c->tab.Ef, c->tab.Sr32, c->tab.Mf32,
                     c->tab.Tsym32, c->tab.Ef32, c->tab.Tfull, c->tab.Tfull32, c->tab.SrT, c->tab.EfT, c->d_eframe, c->d_xscratch, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
-                    c->d_bsr, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
+                    c->d_bsr, c->d_bsr32, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
                     c->d_scal, c->d_f_saved, c->d_lbnd_saved, c->d_su, c->d_slam, c->d_du, c->d_dlam,
                     c->d_re64, c->d_sq,
                     c->d_stage, c->d_ustar, c->d_fstage, c->d_loc_off, c->d_efnf, c->d_face_nf, c->d_edeg,

@@ -125,6 +125,8 @@ struct hdg_ctx {
 
     // global trace system (FP64)
     double* d_bsr = nullptr;   // [nf][nslot][bs][bs]
+    float* d_bsr32 = nullptr;  // FP32 copy for the correction solves of the refinement (mixed
+                               // precision, one right-hand side, 3D)
     double* d_rhs = nullptr;   // [ntr][r]
     double* d_pinv = nullptr;  // [nf][bs][bs] inverse diagonal blocks
     double *d_cg_r = nullptr, *d_cg_z = nullptr, *d_cg_p = nullptr, *d_cg_q = nullptr;
@@ -192,7 +194,10 @@ int launch_assemble_rhs(hdg_ctx* c, const double* lam_bnd);
 int launch_assemble_rhs64(hdg_ctx* c, const double* re64);
 int launch_apply_mass(hdg_ctx* c, double a, const double* u, double* f);
 int launch_block_inverse(hdg_ctx* c);
-int trace_cg(hdg_ctx* c, double* lambda, double tol, int* iters, double* relres);
+// lowp: products with the FP32 copy of the matrix (correction solves of the refinement, whose
+// tolerance is far above FP32 rounding; the refinement's FP64 residual removes the difference)
+int trace_cg(hdg_ctx* c, double* lambda, double tol, int* iters, double* relres, bool lowp = false);
+int launch_bsr_f32(hdg_ctx* c);
 
 // Workgroups that stay resident on the whole device at once for `kernel` with `block` threads
 // (at least 1): a grid of this size visits every element with one wave per element slot.

@@ -195,9 +195,11 @@ __global__ __launch_bounds__(NT) void bsr_spmv_kernel(int64_t nf, int nslot, int
 // The same with the block size and the blocks per row fixed at compile time: the row's
 // NS * BS matrix loads are independent and unrolled (slots without a neighbour read a valid
 // x entry whose product is discarded).
-template <int BS, int NS>
+// M: precision of the stored blocks (FP64, or the FP32 copy used by the refinement's correction
+// solves); products and sums in FP64.
+template <int BS, int NS, typename M>
 __global__ __launch_bounds__(NT) void bsr_spmv_fixed_kernel(int64_t nf, int R, const int32_t* __restrict__ cols,
-                                                            const double* __restrict__ bsr,
+                                                            const M* __restrict__ bsr,
                                                             const double* __restrict__ x, double* __restrict__ y) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= nf * BS * R) return;
@@ -209,11 +211,11 @@ __global__ __launch_bounds__(NT) void bsr_spmv_fixed_kernel(int64_t nf, int R, c
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int32_t cF = cols[F * NS + s];
-        const double* B = bsr + ((size_t)F * NS + s) * BS * BS + a;
+        const M* B = bsr + ((size_t)F * NS + s) * BS * BS + a;
         const double* xv = x + (size_t)max(cF, 0) * BS * R + r;
         double t = 0.0;
 #pragma unroll
-        for (int b = 0; b < BS; ++b) t += B[b * BS] * xv[b * R];
+        for (int b = 0; b < BS; ++b) t += (double)B[b * BS] * xv[b * R];
         acc += cF >= 0 ? t : 0.0;
     }
     y[gid] = acc;
@@ -449,7 +451,13 @@ int launch_block_inverse(hdg_ctx* c) {
 
 static int64_t nblk_faces(const hdg_ctx* c) { return (c->n_faces + 3) / 4; }
 
-static void spmv(hdg_ctx* c, const double* x, double* y) {
+// FP32 copy of the assembled trace matrix (mixed precision, one right-hand side)
+__global__ __launch_bounds__(NT) void to_f32_kernel(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+static void spmv(hdg_ctx* c, const double* x, double* y, bool lowp = false) {
     int64_t n = c->n_faces * c->bs * c->nrhs;
     if (c->nslot == 7 && c->nrhs == 32) {
 #define HDG_BS(B)                                                                                          \
@@ -464,8 +472,12 @@ static void spmv(hdg_ctx* c, const double* x, double* y) {
     if (c->nslot == 7) {
 #define HDG_BS(B)                                                                                          \
     if (c->bs == B) {                                                                                      \
-        hipLaunchKernelGGL((bsr_spmv_fixed_kernel<B, 7>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, \
-                           c->nrhs, c->d_bsr_cols, c->d_bsr, x, y);                                       \
+        if (lowp && c->d_bsr32)                                                                            \
+            hipLaunchKernelGGL((bsr_spmv_fixed_kernel<B, 7, float>), dim3(nblk(n)), dim3(NT), 0, c->stream,  \
+                               c->n_faces, c->nrhs, c->d_bsr_cols, c->d_bsr32, x, y);                      \
+        else                                                                                               \
+            hipLaunchKernelGGL((bsr_spmv_fixed_kernel<B, 7, double>), dim3(nblk(n)), dim3(NT), 0, c->stream, \
+                               c->n_faces, c->nrhs, c->d_bsr_cols, c->d_bsr, x, y);                        \
         return;                                                                                            \
     }
         HDG_BS_CASES(HDG_BS)
@@ -529,7 +541,14 @@ int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out) {
 
 // Preconditioned CG on the assembled (sign-adjusted) system; all rhs columns iterate
 // together with their own scalars.  Convergence is checked on the host every iteration.
-int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
+int launch_bsr_f32(hdg_ctx* c) {
+    if (!c->d_bsr32) return 0;
+    const int64_t n = c->n_faces * c->nslot * c->bs * c->bs;
+    hipLaunchKernelGGL(to_f32_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, n, c->d_bsr, c->d_bsr32);
+    return (int)hipGetLastError();
+}
+
+int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool lowp) {
     const int R = c->nrhs;
     const int64_t n = c->n_faces * c->bs;
     double* rr = c->d_cg_r;
@@ -544,7 +563,7 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
     // boundary entries of x are the Dirichlet values (identity rows)
     hipLaunchKernelGGL(copy_bnd_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, c->n_faces, c->bs, R,
                        c->d_face_bnd, c->d_rhs, x);
-    spmv(c, x, qq);
+    spmv(c, x, qq, lowp);
     launch_lincomb(c, n * R, 1.0, c->d_rhs, -1.0, qq, rr);
     precond(c, rr, zz);
     hipMemcpyAsync(pp, zz, n * R * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
@@ -573,7 +592,7 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
             break;
         }
         if (worst <= tol || it == c->krylov_maxit) break;
-        spmv(c, pp, qq);
+        spmv(c, pp, qq, lowp);
         dot(c, pp, qq, s_pq);
         hipLaunchKernelGGL(axpy_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, 1.0,
                            pp, x);
