@@ -1358,6 +1358,13 @@ int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
     // schedules: tuned on the first condensation of a class (or read from the table), else 0
     bool tuned = false;
     for (auto& [k, cr] : classes) {
+        if (c->sched[pi][k] > 0) {   // read from a tune table: keep it only if it is built here
+            GenOp q;
+            q.op = 1;
+            q.sched = c->sched[pi][k];
+            (void)gen_class<T>(c, cr.K, cr.KF, *cr.tb, cr.el, cr.n, q);
+            if (q.out == 0) c->sched[pi][k] = -1;
+        }
         if (c->sched[pi][k] >= 0) continue;
         bool built[NSCHED];
         int ns = 0;

@@ -143,3 +143,30 @@ def test_graph_replays_match_eager(prec, autotune):
         assert _rel(lg, le) <= 1e-13, (rnd, _rel(lg, le))
     se.close()
     sg.close()
+
+
+def test_tune_table_entries_validated(tmp_path):
+    """The table parser skips comments, malformed lines and other devices, and a schedule that is
+    not built for a class (Maxwell k = 3 FP32 fits the 75 KB rule whole, so schedule 1 does not
+    exist for it) falls back to the default; a built one (schedule 2) is taken as read."""
+    _need_gpu()
+    dev = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    p = make_problem(5, n=2, k=3)
+    print(f"case tune table device={dev} n_elem={p.n_elem}", flush=True)
+    a = 1.0 / p.dt
+    opts = dict(krylov_tol=1e-9, refine_tol=1e-12)
+    s0 = _solver(p, "mixed_fp32", **opts)
+    f, lb = _inputs(p, s0, 5)
+    u0, _ = _stage(s0, a, f, lb)
+    s0.close()
+    for sched, expect in ((1, 0), (2, 2)):
+        table = tmp_path / f"tune{sched}.txt"
+        table.write_text("# comment line\n"
+                         "not a table line\n"
+                         f"otherdevice 2 3 3 1 1 2 0 0 0\n"
+                         f"{dev} 2 3 3 1 1 {sched} 1.0 1.0 1.0\n")
+        s1 = _solver(p, "mixed_fp32", autotune_table=str(table), **opts)
+        u1, _ = _stage(s1, a, f, lb)
+        assert s1.schedules() == {3: expect}, (sched, s1.schedules())
+        s1.close()
+        assert _rel(u1, u0) <= 1e-13
