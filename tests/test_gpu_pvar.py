@@ -139,3 +139,40 @@ def test_pvar_point_sources_match_oracle():
     F = s.point_sources(p.sources)
     np.testing.assert_allclose(F, ohdg.point_source_rhs(d, p.sources), atol=1e-12)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_pvar_dirk_steps_graph(prec):
+    """Two DIRK(3,3) steps through hdg_step on a mesh of variable degree (one right-hand side),
+    with the degree classes condensed as one graph (captured at the first stage, replayed by
+    the later ones) and autotuned schedules, against the oracle's stage recursion."""
+    _need_gpu()
+    from oracle import hdg as ohdg
+    from paper_1807_00086_amd import Solver
+    p = make_problem(4, nxyz=(2, 2, 2))
+    print(f"case pvar dirk {prec} n_elem={p.n_elem} degrees={np.bincount(p.degree)}", flush=True)
+    d = ohdg.make_discretisation(p)
+    u0 = random_vector(d.loc_off[-1], 4, 31)
+    bm = ohdg.boundary_trace_mask(d)
+    _, _, c = ohdg.dirk33()
+    dt = 0.01
+    lbs = {}
+    for n in range(2):
+        for i in range(3):
+            lbs[round(n * dt + c[i] * dt, 12)] = random_vector(d.tr_off[-1], 4, 200 + 3 * n + i) * bm
+    u_ref = u0.copy()
+    for n in range(2):
+        u_ref = ohdg.dirk_step(d, u_ref, n * dt, dt, lambda t: lbs[round(t, 12)])
+    kw = dict(krylov_tol=1e-13) if prec == "fp64" else dict(krylov_tol=1e-9, refine_tol=1e-12)
+    s = Solver(p.xyz, p.elem_vert, "acoustic", p.elem_par, degree=p.degree, precision=prec, nrhs=1,
+               use_graph=True, autotune=True, **kw)
+    u = torch.as_tensor(u0.copy(), device="cuda")
+    lam = torch.zeros(d.skel.n_faces * BS, dtype=torch.float64, device="cuda")
+    for n in range(2):
+        stages = np.stack([_pad(d, lbs[round(n * dt + c[i] * dt, 12)][:, None])[:, 0] for i in range(3)])
+        s.step(n * dt, dt, "dirk33", u, lam, torch.as_tensor(stages, device="cuda"))
+    torch.cuda.synchronize()
+    s.close()
+    errs = _field_errors(ohdg, d, u.cpu().numpy()[:, None], u_ref[:, None])
+    tol = 1e-12 if prec == "fp64" else 1e-10
+    assert max(errs) <= tol, errs
