@@ -905,7 +905,9 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
         double mu[NFACE * M2 * N]; // Mf_f u2_b
         double st[N2];             // s~2, then S^{-1} s~2
         double te[TT];
-        double El[NFACE * N * NF];
+        int pf[NFACE];             // orientation of each local face (oriented face tables are
+                                   // read through L1/L2; modes past a face's space meet zero
+                                   // traces or are masked on store)
         int nfv[NFACE];
         Coef<PHYS> cf;
     };
@@ -934,12 +936,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
         if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
         if (PHYS == PH_MAXWELL && lane < 24) sc.frm[lane] = eframe[e * 24 + lane];
         if (lane < NFACE) sc.nfv[lane] = va.efnf ? (int)va.efnf[e * NFACE + lane] : NF;
-        for (int idx = lane; idx < NFACE * N * NF; idx += 64) {
-            const int fc = idx / (N * NF);
-            const int p = eperm[e * NFACE + fc];
-            const int nfv = va.efnf ? (int)va.efnf[e * NFACE + fc] : NF;
-            sc.El[idx] = (idx % NF) < nfv ? Ef[(size_t)(fc * NPERM + p) * N * NF + (idx - fc * N * NF)] : 0.0;
-        }
+        if (lane < NFACE) sc.pf[lane] = eperm[e * NFACE + lane];
         ws();
         if (lane == 0) coef_primary<PHYS>(sc.geo, sc.frm, a, sc.cf);
         ws();
@@ -970,7 +967,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
                 const int fc = idx / N, i = idx % N;
                 const int fo = fc / MT;
                 double s = 0.0;
-                for (int l = 0; l < NF; ++l) s += sc.El[(fo * N + i) * NF + l] * sc.lm[fc * NF + l];
+                for (int l = 0; l < NF; ++l) s += Ef[((size_t)(fo * NPERM + sc.pf[fo]) * N + i) * NF + l] * sc.lm[fc * NF + l];
                 sc.ef[idx] = sc.geo[1 + D * D + fo] * s;
             }
             for (int idx = lane; idx < D * M2 * N; idx += 64) {
@@ -1026,7 +1023,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
                     double w = 0.0;
                     for (int al = 0; al < M1; ++al) w += j1 * sc.cf.b1[al][fc] * u1[al * N + i];
                     for (int b = 0; b < M2; ++b) w += j2 * sc.cf.b2[b][fc] * u2[b * N + i];
-                    s += sc.El[(fo * N + i) * NF + l] * w;
+                    s += Ef[((size_t)(fo * NPERM + sc.pf[fo]) * N + i) * NF + l] * w;
                 }
                 const double sf = sc.geo[1 + D * D + fo];
                 sc.te[aa] = sf * s + sc.cf.dface * sf * sc.lm[aa];
@@ -1057,7 +1054,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
                 for (int i = 0; i < N; ++i) {
                     double w = 0.0;
                     for (int al = 0; al < M1; ++al) w += sc.cf.bd[al][fc] * s1[al * N + i];
-                    rb += sc.El[(fo * N + i) * NF + l] * w;
+                    rb += Ef[((size_t)(fo * NPERM + sc.pf[fo]) * N + i) * NF + l] * w;
                 }
                 for (int row = 0; row < N2; ++row) zt += (double)Zse[row * TT + aa] * sc.st[row];
                 const double v = -j1 * sc.geo[1 + D * D + fo] / J * rb - j2 * zt - sc.te[aa];
