@@ -170,3 +170,23 @@ def test_tune_table_entries_validated(tmp_path):
         assert s1.schedules() == {3: expect}, (sched, s1.schedules())
         s1.close()
         assert _rel(u1, u0) <= 1e-13
+
+
+def test_tune_table_unwritable_path_is_harmless(tmp_path):
+    """A table path that cannot be read or written (a missing directory) leaves tuning and the
+    results unaffected: the library times the schedules and simply keeps no file."""
+    _need_gpu()
+    p = make_problem(3, n=1, k=4)
+    print(f"case tune table unwritable n_elem={p.n_elem}", flush=True)
+    a = 1.0 / p.dt
+    path = tmp_path / "missing_dir" / "tune.txt"
+    s0 = _solver(p, "fp64", krylov_tol=1e-13)
+    f, lb = _inputs(p, s0, 3)
+    u0, _ = _stage(s0, a, f, lb)
+    s0.close()
+    s1 = _solver(p, "fp64", krylov_tol=1e-13, autotune=True, autotune_table=str(path))
+    u1, _ = _stage(s1, a, f, lb)
+    assert set(s1.schedules()) == {4}
+    s1.close()
+    assert not path.exists()
+    assert _rel(u1, u0) <= 1e-13
