@@ -373,7 +373,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(dalloc(c, &c->d_status, 1));
     const int64_t ntr = c->n_trace_dofs;
     TRY(dalloc(c, &c->d_bsr, c->n_faces * c->nslot * c->bs * c->bs));
-    if (c->precision == HDG_MIXED_FP32 && R == 1 && c->nslot == 7)
+    if (c->precision == HDG_MIXED_FP32 && (R == 1 || R == 32) && c->nslot == 7)
         TRY(dalloc(c, &c->d_bsr32, c->n_faces * c->nslot * c->bs * c->bs));
     TRY(dalloc(c, &c->d_rhs, ntr * R));
     TRY(dalloc(c, &c->d_pinv, c->n_faces * c->bs * c->bs));

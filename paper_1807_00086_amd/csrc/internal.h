@@ -126,7 +126,7 @@ struct hdg_ctx {
     // global trace system (FP64)
     double* d_bsr = nullptr;   // [nf][nslot][bs][bs]
     float* d_bsr32 = nullptr;  // FP32 copy for the correction solves of the refinement (mixed
-                               // precision, one right-hand side, 3D)
+                               // precision, 1 or 32 right-hand sides, 3D)
     double* d_rhs = nullptr;   // [ntr][r]
     double* d_pinv = nullptr;  // [nf][bs][bs] inverse diagonal blocks
     double *d_cg_r = nullptr, *d_cg_z = nullptr, *d_cg_p = nullptr, *d_cg_q = nullptr;

@@ -227,11 +227,12 @@ __global__ __launch_bounds__(NT) void bsr_spmv_fixed_kernel(int64_t nf, int R, c
 // read consecutive entries, and the B operands are 16 consecutive right-hand sides of a row of
 // x.  NS = 1 with cols null applies the block diagonal (the preconditioner).  Rows and
 // columns past BS are clamped on load (padded k rows of x are zero, padded output rows dropped).
+// M = float reads the FP32 copy of the blocks and widens each entry to FP64 before the MFMA.
 typedef double mf64x4 __attribute__((ext_vector_type(4)));
 
-template <int BS, int NS>
+template <int BS, int NS, typename M = double>
 __global__ __launch_bounds__(256) void bsr_spmm32_kernel(int64_t nf, const int32_t* __restrict__ cols,
-                                                         const double* __restrict__ bsr,
+                                                         const M* __restrict__ bsr,
                                                          const double* __restrict__ x, double* __restrict__ y) {
     constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4, R = 32;
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(256) void bsr_spmm32_kernel(int64_t nf, const int32
     for (int s = 0; s < NS; ++s) {
         const int cF = cols ? __builtin_amdgcn_readfirstlane(cols[F * NS + s]) : (int)F;
         if (cF < 0) continue;
-        const double* B = bsr + ((size_t)F * NS + s) * BS * BS;
+        const M* B = bsr + ((size_t)F * NS + s) * BS * BS;
         const double* xv = x + (size_t)cF * BS * R;
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) {
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(256) void bsr_spmm32_kernel(int64_t nf, const int32
             }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                const double av = B[b * BS + min(16 * mt + lr, BS - 1)];
+                const double av = (double)B[b * BS + min(16 * mt + lr, BS - 1)];
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xb[nt], acc[mt][nt], 0, 0, 0);
@@ -358,16 +359,43 @@ __global__ __launch_bounds__(NT) void dot_final_kernel(int nb, int R, const doub
     }
 }
 
-// y[i, r] += alpha[r] * x[i, r] (alpha from device array, optional sign)
-__global__ __launch_bounds__(NT) void axpy_cols_kernel(int64_t n, int R, const double* __restrict__ num,
-                                                       const double* __restrict__ den, double sgn,
-                                                       const double* __restrict__ x, double* __restrict__ y) {
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= n * R) return;
-    int r = (int)(gid % R);
-    double dd = den[r];
-    double al = (dd != 0.0) ? num[r] / dd : 0.0;
-    y[gid] += sgn * al * x[gid];
+// CG update of one iteration in a single pass: x += alpha p, r -= alpha q (alpha = num/den per
+// column), and the partial sums of the new r squared per column, in the thread layout of
+// dot_partial_kernel (part[blk][r], reduced by dot_final_kernel)
+__global__ __launch_bounds__(NT) void cg_update_kernel(int64_t n, int R, const double* __restrict__ num,
+                                                       const double* __restrict__ den,
+                                                       const double* __restrict__ p, const double* __restrict__ q,
+                                                       double* __restrict__ x, double* __restrict__ rv,
+                                                       double* __restrict__ part) {
+    __shared__ double sh[NT];
+    const int T = NT / R, t = threadIdx.x;
+    double acc = 0.0;
+    if (t < T * R) {
+        const int r = t % R;
+        const double dd = den[r];
+        const double al = (dd != 0.0) ? num[r] / dd : 0.0;
+#pragma unroll 4
+        for (int64_t i = (int64_t)blockIdx.x * T + t / R; i < n; i += (int64_t)gridDim.x * T) {
+            const int64_t k = i * R + r;
+            x[k] += al * p[k];
+            const double rn = rv[k] - al * q[k];
+            rv[k] = rn;
+            acc += rn * rn;
+        }
+    }
+    sh[t] = acc;
+    __syncthreads();
+    if (R == 1) {
+        for (int s = NT / 2; s > 0; s >>= 1) {
+            if (t < s) sh[t] += sh[t + s];
+            __syncthreads();
+        }
+        if (t == 0) part[blockIdx.x] = sh[0];
+    } else if (t < R) {
+        double s = 0.0;
+        for (int k = 0; k < T; ++k) s += sh[k * R + t];
+        part[(size_t)blockIdx.x * R + t] = s;
+    }
 }
 
 // p = z + beta p, beta = num/den per column
@@ -451,7 +479,7 @@ int launch_block_inverse(hdg_ctx* c) {
 
 static int64_t nblk_faces(const hdg_ctx* c) { return (c->n_faces + 3) / 4; }
 
-// FP32 copy of the assembled trace matrix (mixed precision, one right-hand side)
+// FP32 copy of the assembled trace matrix (mixed precision, 3D)
 __global__ __launch_bounds__(NT) void to_f32_kernel(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = (float)a[i];
@@ -462,8 +490,12 @@ static void spmv(hdg_ctx* c, const double* x, double* y, bool lowp = false) {
     if (c->nslot == 7 && c->nrhs == 32) {
 #define HDG_BS(B)                                                                                          \
     if (c->bs == B) {                                                                                      \
-        hipLaunchKernelGGL((bsr_spmm32_kernel<B, 7>), dim3(nblk_faces(c)), dim3(256), 0, c->stream,           \
-                           c->n_faces, c->d_bsr_cols, c->d_bsr, x, y);                                     \
+        if (lowp && c->d_bsr32)                                                                            \
+            hipLaunchKernelGGL((bsr_spmm32_kernel<B, 7, float>), dim3(nblk_faces(c)), dim3(256), 0, c->stream, \
+                               c->n_faces, c->d_bsr_cols, c->d_bsr32, x, y);                               \
+        else                                                                                               \
+            hipLaunchKernelGGL((bsr_spmm32_kernel<B, 7>), dim3(nblk_faces(c)), dim3(256), 0, c->stream,       \
+                               c->n_faces, c->d_bsr_cols, c->d_bsr, x, y);                                 \
         return;                                                                                            \
     }
         HDG_BS_CASES(HDG_BS)
@@ -575,8 +607,8 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
     for (int r = 0; r < R; ++r) hb[r] = std::sqrt(hb[r]) > 0 ? std::sqrt(hb[r]) : 1.0;
     int it = 0;
     double worst = 0.0;
+    dot(c, rr, rr, s_rr);   // later iterations get it from the fused update
     for (it = 0; it <= c->krylov_maxit; ++it) {
-        dot(c, rr, rr, s_rr);
         hipMemcpyAsync(hr.data(), s_rr, R * sizeof(double), hipMemcpyDeviceToHost, c->stream);
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return HDG_E_HIP;
@@ -594,10 +626,9 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
         if (worst <= tol || it == c->krylov_maxit) break;
         spmv(c, pp, qq, lowp);
         dot(c, pp, qq, s_pq);
-        hipLaunchKernelGGL(axpy_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, 1.0,
-                           pp, x);
-        hipLaunchKernelGGL(axpy_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, -1.0,
-                           qq, rr);
+        hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, pp,
+                           qq, x, rr, c->d_red);
+        hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, R, c->d_red, s_rr);
         precond(c, rr, zz);
         dot(c, rr, zz, s_rz_new);
         hipLaunchKernelGGL(xpby_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz_new, s_rz, zz,
