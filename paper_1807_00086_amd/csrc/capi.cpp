@@ -382,7 +382,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(dalloc(c, &c->d_cg_p, ntr * R));
     TRY(dalloc(c, &c->d_cg_q, std::max<int64_t>(ntr * R, c->n_faces * c->bs * c->bs)));
     c->red_blocks = 1024;
-    TRY(dalloc(c, &c->d_red, c->red_blocks * 32));
+    TRY(dalloc(c, &c->d_red, (int64_t)RED_MAX * 32));
     TRY(dalloc(c, &c->d_scal, 8 * 32));
     const int64_t nl = c->n_local_dofs * R;
     if (c->precision == HDG_MIXED_FP32) {

@@ -39,6 +39,9 @@ struct Timings {
 
 }  // namespace hdg
 
+// workgroups of the reductions over the trace vectors (partial sums per workgroup and column)
+constexpr int RED_MAX = 2048;
+
 struct hdg_ctx {
     // configuration
     int dim = 0, physics = 0, precision = 0, nrhs = 1, k = 0;
@@ -130,7 +133,7 @@ struct hdg_ctx {
     double* d_rhs = nullptr;   // [ntr][r]
     double* d_pinv = nullptr;  // [nf][bs][bs] inverse diagonal blocks
     double *d_cg_r = nullptr, *d_cg_z = nullptr, *d_cg_p = nullptr, *d_cg_q = nullptr;
-    double* d_red = nullptr;   // reduction scratch
+    double* d_red = nullptr;   // reduction scratch: RED_MAX x 32 partial sums
     double* d_scal = nullptr;  // device scalars
     int red_blocks = 0;
 
