@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <limits>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -700,7 +701,7 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
         precond(c, rr, zz, s_rz_new);
         hipLaunchKernelGGL(xpby_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz_new, s_rz, zz,
                            pp);
-        hipMemcpyAsync(s_rz, s_rz_new, R * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+        std::swap(s_rz, s_rz_new);   // the new r.z becomes the old one (no device copy)
     }
     if (iters) *iters = it;
     if (relres) *relres = worst;
