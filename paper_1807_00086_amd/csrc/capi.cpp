@@ -393,8 +393,15 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
         TRY(dalloc(c, &c->d_re64, ne * c->n_tr * R));
         TRY(dalloc(c, &c->d_sq, 2 * ne));
     }
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_rr, hipEventDisableTiming) != hipSuccess) {
         g_init_err = "hipEventCreate failed";
+        hdg_destroy(c);
+        return HDG_E_HIP;
+    }
+    if (hipHostMalloc((void**)&c->h_rr, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        c->h_rr = nullptr;
+        g_init_err = "hipHostMalloc failed";
         hdg_destroy(c);
         return HDG_E_HIP;
     }
@@ -953,6 +960,8 @@ void hdg_destroy(hdg_ctx* c) {
     }
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->ev_rr) (void)hipEventDestroy(c->ev_rr);
+    if (c->h_rr) (void)hipHostFree(c->h_rr);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (int i = 0; i < 6; ++i) {
         if (c->side[i]) {

@@ -169,6 +169,9 @@ struct hdg_ctx {
     bool use_graph = false;
     hipStream_t side[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_in = nullptr, ev_out = nullptr;
+    // trace CG: residual norms copied to pinned host memory while the next product runs
+    double* h_rr = nullptr;   // [32], hipHostMalloc
+    hipEvent_t ev_rr = nullptr;
     hipEvent_t ev_join[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     hipGraphExec_t gexec = nullptr;
     double g_a = 0.0;

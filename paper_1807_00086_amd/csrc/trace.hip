@@ -671,21 +671,27 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
     hipMemcpyAsync(pp, zz, n * R * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     dot(c, rr, zz, s_rz);
     dot(c, c->d_rhs, c->d_rhs, s_bb);
-    std::vector<double> hb(R), hr(R);
+    std::vector<double> hb(R);
     hipMemcpyAsync(hb.data(), s_bb, R * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     hipStreamSynchronize(c->stream);
     for (int r = 0; r < R; ++r) hb[r] = std::sqrt(hb[r]) > 0 ? std::sqrt(hb[r]) : 1.0;
     int it = 0;
     double worst = 0.0;
     dot(c, rr, rr, s_rr);   // later iterations get it from the fused update
+    double* hrr = c->h_rr;  // pinned: the copy is asynchronous
     for (it = 0; it <= c->krylov_maxit; ++it) {
-        hipMemcpyAsync(hr.data(), s_rr, R * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-        hipError_t e = hipStreamSynchronize(c->stream);
+        if (hipMemcpyAsync(hrr, s_rr, R * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipEventRecord(c->ev_rr, c->stream) != hipSuccess)
+            return HDG_E_HIP;
+        // the next product (reads p, writes q and p.q only) runs while the host waits for the
+        // norms; if they meet the test it is simply not used
+        if (it < c->krylov_maxit) spmv(c, pp, qq, lowp, s_pq);
+        hipError_t e = hipEventSynchronize(c->ev_rr);
         if (e != hipSuccess) return HDG_E_HIP;
         worst = 0.0;
         bool nonfinite = false;
         for (int r = 0; r < R; ++r) {
-            double v = std::sqrt(hr[r]) / hb[r];
+            double v = std::sqrt(hrr[r]) / hb[r];
             if (!(v - v == 0.0)) nonfinite = true;   // NaN or inf (std::max would drop a NaN)
             else worst = std::max(worst, v);
         }
@@ -694,7 +700,6 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
             break;
         }
         if (worst <= tol || it == c->krylov_maxit) break;
-        spmv(c, pp, qq, lowp, s_pq);
         hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, pp,
                            qq, x, rr, c->d_red);
         hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, R, c->d_red, s_rr);
