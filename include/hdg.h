@@ -207,6 +207,10 @@ hdg_status hdg_condense_rhs(hdg_ctx* ctx, double a, const double* f_loc, const d
  *            the Dirichlet values), out: solution
  *   iters    host, may be NULL: iterations used
  *   relres   host, may be NULL: final max over rhs of ||r - K lam|| / ||r||
+ * In HDG_MIXED_FP32 mode on 3D meshes with 1 or 32 right-hand sides the matrix products
+ * read an FP32 copy of K (K is assembled from the FP32 factors and hdg_recover's refinement
+ * evaluates the residual in FP64 from the element operators, so this changes the solve only
+ * at the level of error the refinement removes); relres then refers to that copy.
  * Synchronises the stream.  HDG_E_NOCONV if krylov_tol is not met within krylov_maxit.
  */
 hdg_status hdg_trace_solve(hdg_ctx* ctx, double* lambda, int* iters, double* relres);

@@ -542,7 +542,9 @@ hdg_status hdg_trace_solve(hdg_ctx* c, double* lambda, int* iters, double* relre
     int r;
     {
         EventTimer t(c, &c->tim.solve);
-        r = trace_cg(c, lambda, c->krylov_tol, iters, relres);
+        // mixed precision: K already carries the FP32 factors' error and the refinement's FP64
+        // residual removes it, so the products may read the FP32 copy as well
+        r = trace_cg(c, lambda, c->krylov_tol, iters, relres, c->d_bsr32 != nullptr);
     }
     if (r == HDG_E_NOCONV) return fail(c, r, "trace solve did not reach krylov_tol");
     if (r) return fail(c, r, "trace solve failed");
