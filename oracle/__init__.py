@@ -13,7 +13,10 @@ trace system is assembled with ``scipy.sparse`` and solved with a sparse direct 
 Modules
   polynomials  Jacobi polynomials, orthonormal simplex bases, collapsed Gauss rules
   mesh         faces, adjacency, canonical face parametrisations, outward normals
-  physics      local HDG matrices for acoustics, elastodynamics and Maxwell
+  physics      local HDG matrices for acoustics, elastodynamics and Maxwell (with and without
+               the GLM multiplier), and the paper's velocity / deformation-gradient elastic
+               form used to pin the velocity / stress form
+  postprocess  element-wise post-processing of the acoustic pressure (superconvergence pin)
   hdg          condensation, assembly, trace solve, recovery, full uncondensed solve,
                projections, norms, DIRK(3,3) stepping
 """

@@ -183,7 +183,7 @@ def project_boundary(disc: Discretisation, func, t=0.0):
         vals = np.atleast_2d(func(y, t))
         if vals.shape[0] != y.shape[0]:
             vals = vals.T
-        if disc.physics == "maxwell":
+        if disc.physics in ("maxwell", "maxwell_glm"):
             t1, t2 = face_frame(disc.xyz, disc.skel.faces[g])
             vals = np.stack([vals @ t1, vals @ t2], axis=1)
         Hm = np.einsum("q,ql,qm->lm", w, psi, psi)

@@ -38,6 +38,24 @@ Formulations
               ((a eps + sigma_c) E, v) - (H, curl v) - <H_hat^t, v x n> = (a eps E*, v)
               H_hat^t = H^t - tau (E - E_hat^t) x n
               sum_K <n x H_hat^t, mu>_F = 0
+  maxwell_glm  section 5.2 with the generalised Lagrange multiplier phi of section 5.1.2
+            (u = [H_1,H_2,H_3, E_1,E_2,E_3, phi]; equations (dmax1)-(dmax3) in stage form,
+            phi_hat = 0 on every face as in (dmax1), alpha_1 = alpha_2 = alpha_3 = 1, the only
+            values the paper runs in section 5.4; no charge density):
+              the two maxwell rows above, the E row also carrying - (phi, div v), and
+              ((a/alpha_1^2 + 1/alpha_2^2) phi, psi) + (1/alpha_3^2) <phi, psi>_dK
+                + (div E, psi) = (a/alpha_1^2 phi*, psi)
+            the trace equation is that of maxwell (phi does not enter it).
+  elastic_fv  the velocity / deformation-gradient form of section 4.1.2 exactly as the paper
+            writes it (u = [F_11,F_12,F_13,F_21,..,F_33, v_1,v_2,v_3], F row-major), used only
+            to pin the elastic form above (they must give the same v, v_hat and
+            sigma(F_h) = sigma_h):
+              (a F, G) + (v, div G) - <v_hat, G n> = (a F*, G)
+              (a rho v, w) + (sigma(F), grad w) - <sigma(F) n - S (v - v_hat), w> = (a rho v*, w)
+              sum_K <sigma(F) n - S (v - v_hat), mu>_F = 0
+            sigma(F) = mu (F + F^T) + lambda tr(F) I.  The law of section 4.1.1 adds the constant
+            (-lambda d - 2 mu) I; a constant tensor c I drops out of the last two lines
+            ((c I, grad w)_K = <c n, w>_dK), so F may be measured from the identity.
 """
 from __future__ import annotations
 
@@ -56,8 +74,11 @@ LEVI = np.zeros((3, 3, 3))
 LEVI[0, 1, 2] = LEVI[1, 2, 0] = LEVI[2, 0, 1] = 1.0
 LEVI[0, 2, 1] = LEVI[2, 1, 0] = LEVI[1, 0, 2] = -1.0
 
-N_COMP = {"acoustic": None, "elastic": 9, "maxwell": 6}
-N_TRACE_COMP = {"acoustic": 1, "elastic": 3, "maxwell": 2}
+N_COMP = {"acoustic": None, "elastic": 9, "maxwell": 6, "maxwell_glm": 7, "elastic_fv": 12}
+N_TRACE_COMP = {"acoustic": 1, "elastic": 3, "maxwell": 2, "maxwell_glm": 2, "elastic_fv": 3}
+
+# GLM coefficients alpha_1, alpha_2, alpha_3 of (dmax3) (section 5.4 runs all three at 1)
+GLM_ALPHA = (1.0, 1.0, 1.0)
 
 
 def n_local_comp(physics: str, dim: int) -> int:
@@ -69,7 +90,7 @@ def stabilisation(physics: str, par):
     if physics == "acoustic":
         rho, c = par[0], par[1]
         return 1.0 / (rho * c)
-    if physics == "elastic":
+    if physics in ("elastic", "elastic_fv"):
         rho, mu = par[0], par[2]
         return 2.0 * rho * np.sqrt(mu / rho)
     return 2.0
@@ -213,8 +234,8 @@ def local_system(physics, eq: ElementQuad, par, a):
                 D[tblk(f, y), tblk(f, y)] = S * Hf[f]
         return A, B, C, D, Mw
 
-    if physics == "maxwell":
-        eps, mu, sig = par
+    if physics in ("maxwell", "maxwell_glm"):
+        eps, mu, sig = par[0], par[1], par[2]
         for x in range(3):
             Mw[blk(x), blk(x)] = mu * M
             Mw[blk(3 + x), blk(3 + x)] = eps * M
@@ -240,6 +261,59 @@ def local_system(physics, eq: ElementQuad, par, a):
                     C[tblk(f, ci), blk(x)] = (tc @ np.cross(nrm, ex)) * Gf[f].T
                     C[tblk(f, ci), blk(3 + x)] = -tau * tc[x] * Gf[f].T
                 D[tblk(f, ci), tblk(f, ci)] = tau * Hf[f]
+        if physics == "maxwell_glm":
+            a1, a2, a3 = GLM_ALPHA
+            PH = 6
+            Mw[blk(PH), blk(PH)] = M / a1 ** 2
+            A[blk(PH), blk(PH)] = (a / a1 ** 2 + 1.0 / a2 ** 2) * M + sum(Ff) / a3 ** 2
+            for x in range(3):
+                # - (phi, div v): v = e_x phi_i, phi = phi_j
+                A[blk(3 + x), blk(PH)] = -Dx[x].T
+                # (div E, psi): E = e_x phi_j, psi = phi_i
+                A[blk(PH), blk(3 + x)] = Dx[x]
+        return A, B, C, D, Mw
+
+    if physics == "elastic_fv":
+        rho, lam, mu = par
+        S = tau
+        iF = lambda i, j: 3 * i + j
+        V = 9
+
+        def stress_coef(x, j, a_, b_):
+            """d sigma_xj / d F_ab for sigma(F) = mu (F + F^T) + lambda tr(F) I."""
+            return (mu * ((a_ == x) * (b_ == j) + (a_ == j) * (b_ == x))
+                    + lam * (x == j) * (a_ == b_))
+
+        for i in range(3):
+            for j in range(3):
+                Mw[blk(iF(i, j)), blk(iF(i, j))] = M
+                # (v, div G): G = e_i e_j^T phi_m, div G = e_i d_j phi_m
+                A[blk(iF(i, j)), blk(V + i)] = Dx[j].T
+        for x in range(3):
+            Mw[blk(V + x), blk(V + x)] = rho * M
+            for a_ in range(3):
+                for b_ in range(3):
+                    # (sigma(F), grad w) - <sigma(F) n, w>: w = e_x phi_m, F = e_a e_b^T phi_n
+                    A[blk(V + x), blk(iF(a_, b_))] = sum(
+                        stress_coef(x, j, a_, b_) * (Dx[j].T - sum(eq.faces[f]["n"][j] * Ff[f] for f in range(nf)))
+                        for j in range(3))
+        A += a * Mw
+        for x in range(3):
+            A[blk(V + x), blk(V + x)] += S * sum(Ff)
+        for f in range(nf):
+            nrm = eq.faces[f]["n"]
+            for i in range(3):
+                for j in range(3):
+                    # - <v_hat, G n>
+                    B[blk(iF(i, j)), tblk(f, i)] = -nrm[j] * Gf[f]
+            for y in range(3):
+                for a_ in range(3):
+                    for b_ in range(3):
+                        sn = sum(stress_coef(y, j, a_, b_) * nrm[j] for j in range(3))
+                        C[tblk(f, y), blk(iF(a_, b_))] = sn * Gf[f].T
+                B[blk(V + y), tblk(f, y)] = -S * Gf[f]
+                C[tblk(f, y), blk(V + y)] = -S * Gf[f].T
+                D[tblk(f, y), tblk(f, y)] = S * Hf[f]
         return A, B, C, D, Mw
 
     raise ValueError(physics)
