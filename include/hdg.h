@@ -94,11 +94,10 @@ typedef struct {
     int nrhs;                   /* right-hand sides solved together (1..32)                   */
     double krylov_tol;          /* relative residual of the FP64 trace solve                  */
     int krylov_maxit;
-    double refine_tol;          /* mixed precision: stop when the FP64 correction, or the error
-                                   left after it estimated from the observed contraction of
-                                   successive corrections (the low-precision solve counts as
-                                   a first correction of relative size 1), is below
-                                   refine_tol relative to the solution (0: 1e-13)             */
+    double refine_tol;          /* mixed precision: stop when the FP64 residual of the full
+                                   stage system at the refined iterate is at most refine_tol
+                                   times the norm of its right-hand side (f, Dirichlet data),
+                                   in every right-hand-side column (0: 1e-13)                */
     int refine_maxit;
     double refine_inner_tol;    /* mixed precision: relative residual of the trace solves of
                                    the corrections (0: 1e-6)                                  */
@@ -219,15 +218,28 @@ hdg_status hdg_trace_solve(hdg_ctx* ctx, double* lambda, int* iters, double* rel
  * hdg_recover -- local fields from the trace: u_e = z_e - Z_e lam_e (first block row of
  * the stage system).  In HDG_MIXED_FP32 mode the result is then refined: the residual of
  * the full uncondensed system is evaluated in FP64 from the element operators, corrected
- * through the FP32 factors and a new FP64 trace solve, until the correction is below
- * refine_tol relative to the solution (lambda is refined in place as well).
+ * through the FP32 factors and a new FP64 trace solve, and measured again in FP64 after each
+ * correction, until it is at most refine_tol times the norm of the system's right-hand side
+ * in every column (lambda is refined in place as well; hdg_last_residual reports the result).
  *   lambda   device [n_trace_dofs][nrhs] FP64 (in; in/out in mixed mode)
  *   u_loc    device [n_local_dofs][nrhs] FP64 out
- * HDG_E_NOCONV when refinement stalls.  In mixed mode the refinement reuses the
+ * HDG_E_NOCONV when the residual does not halve from one correction to the next or
+ * refine_maxit corrections do not reach refine_tol.  In mixed mode the refinement reuses the
  * condensation buffers: a second hdg_recover needs a new hdg_condense (HDG_E_STATE).
  * The inner trace solves of the refinement use refine_inner_tol.
  */
 hdg_status hdg_recover(hdg_ctx* ctx, double* lambda, double* u_loc);
+
+/*
+ * hdg_last_residual -- relative FP64 residual of the final iterate of the last mixed-precision
+ * hdg_recover, per right-hand-side column: |s_q| / |(f_q, lam_D,q)| with
+ * s = (f - A u - B lam, -(C u + D lam)) over the local rows and the trace rows of the
+ * non-Dirichlet faces of the full (uncondensed) stage system (section 2.4.1).  The refinement
+ * stops on this quantity (options.refine_tol).
+ *   rel      host [nrhs] out
+ * HDG_E_STATE if no mixed-precision hdg_recover has completed its check on this context.
+ */
+hdg_status hdg_last_residual(const hdg_ctx* ctx, double* rel);
 
 /*
  * hdg_step -- advance u^n -> u^{n+1} by backward Euler or DIRK(3,3) (section 2.3.2,

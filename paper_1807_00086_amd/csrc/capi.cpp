@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <unistd.h>
 #include <new>
 #include <sstream>
@@ -188,7 +189,7 @@ bool supported(hdg_ctx* c) {
 }
 
 int launch_recover_any(hdg_ctx* c, const double* lam, double* u) {
-    return c->fast_ac ? launch_refine_acoustic(c, lam, lam, 1, false, u, nullptr) : launch_recover_general(c, lam, u);
+    return c->fast_ac ? launch_refine_acoustic(c, lam, lam, 1, 0, u, nullptr) : launch_recover_general(c, lam, u);
 }
 
 
@@ -391,7 +392,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
         TRY(dalloc(c, &c->d_du, nl));
         TRY(dalloc(c, &c->d_dlam, ntr * R));
         TRY(dalloc(c, &c->d_re64, ne * c->n_tr * R));
-        TRY(dalloc(c, &c->d_sq, 2 * ne));
+        TRY(dalloc(c, &c->d_sq, std::max<int64_t>(3 * ne, ne * R)));
     }
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_rr, hipEventDisableTiming) != hipSuccess) {
@@ -551,79 +552,128 @@ hdg_status hdg_trace_solve(hdg_ctx* c, double* lambda, int* iters, double* relre
     return HDG_OK;
 }
 
-// Stopping test of the refinement: the correction is below refine_tol relative to the
-// solution, or the error left after it, estimated by the observed contraction
-// rel_k / rel_{k-1} times rel_k, is.  The low-precision solve itself counts as correction 0
-// of relative size 1 (it is one application of the same approximate inverse to the whole
-// right-hand side), so after the first correction the estimate is rel_1^2.
-static bool refine_converged(const hdg_ctx* c, int, double rel, double prev) {
-    if (rel <= c->refine_tol) return true;
-    return prev > 0.0 && rel * (rel / prev) <= c->refine_tol;
+// Mixed-precision refinement (iterative refinement of the full stage system): the residual of
+// the full uncondensed system [A B; C D] (u, lam) = (f, g) is evaluated in FP64 from the element
+// operators, corrected through the FP32 factors and an FP64 trace solve, until the measured FP64
+// residual of every right-hand-side column satisfies
+//     |s| <= refine_tol |(f, lam_D)|,
+// s = (f - A u - B lam, -(C u + D lam)) over the local rows and the trace rows of the
+// non-Dirichlet faces (the Dirichlet rows lam = lam_D hold exactly), (f, lam_D) the right-hand
+// side of the full system.  Each correction is followed by a check pass that forms this residual
+// at the corrected iterate; a full residual pass (which also forms the next correction's
+// right-hand side) runs only when the check fails.  The inner trace solves run to
+// refine_inner_tol; an inner solve that stops short of it still yields a correction, whose effect
+// the next check measures, so it is not an error by itself; a residual that does not halve from
+// one correction to the next is (HDG_E_NOCONV), as is refine_maxit corrections without meeting
+// the test.
+
+// |(f, lam_D)| per column, the scale of the relative residual
+static int refine_scale(hdg_ctx* c, std::vector<double>& scale) {
+    const int R = c->nrhs;
+    std::vector<double> fs(R), bs(R);
+    if (launch_col_sq(c, c->n_local_dofs, R, c->d_f_saved, fs.data()) ||
+        launch_col_sq(c, c->n_faces * c->bs, R, c->d_lbnd_saved, bs.data(), true))
+        return fail(c, HDG_E_HIP, "refinement norm reduction failed");
+    scale.assign(R, 1.0);
+    for (int r = 0; r < R; ++r) {
+        const double v = std::sqrt(fs[r] + bs[r]);
+        scale[r] = v > 0.0 ? v : 1.0;
+    }
+    return HDG_OK;
 }
 
-static int refine_verdict(hdg_ctx* c, int it, double rel, double prev) {
-    if (!(rel == rel)) return fail(c, HDG_E_NOCONV, "refinement produced a non-finite correction");
-    if (refine_converged(c, it, rel, prev)) return HDG_OK;
-    if (it > 1 && rel > 0.5 * prev) return fail(c, HDG_E_NOCONV, "refinement stagnated");
+// Relative residual per column after a check pass: elem_nrm holds |s| of the local rows per
+// element (and column), re64 the element parts -t_e of the trace rows.  Returns the largest.
+static int refine_residual(hdg_ctx* c, const double* elem_nrm, const std::vector<double>& scale, double* worst) {
+    const int R = c->nrhs;
+    std::vector<double> lo(R), tr(R);
+    if (launch_assemble_rhs64(c, c->d_re64) ||
+        launch_col_sq(c, c->n_elem, R, elem_nrm, lo.data()) ||
+        launch_col_sq(c, c->n_faces * c->bs, R, c->d_rhs, tr.data()))
+        return fail(c, HDG_E_HIP, "refinement residual reduction failed");
+    double w = 0.0;
+    bool finite = true;
+    for (int r = 0; r < R; ++r) {
+        const double v = std::sqrt(lo[r] + tr[r]) / scale[r];
+        c->last_resid[r] = v;
+        if (!(v - v == 0.0)) finite = false;
+        else w = std::max(w, v);
+    }
+    c->has_resid = true;
+    *worst = finite ? w : std::numeric_limits<double>::quiet_NaN();
+    return HDG_OK;
+}
+
+// Verdict after the check of correction `it` (residual res, previous res prev): HDG_OK when
+// converged, -1 to continue, or an error.
+static int refine_verdict(hdg_ctx* c, int it, double res, double prev) {
+    c->last_refine = it;
+    if (!(res == res)) return fail(c, HDG_E_NOCONV, "refinement produced a non-finite residual");
+    if (res <= c->refine_tol) return HDG_OK;
+    if (it > 1 && res > 0.5 * prev) return fail(c, HDG_E_NOCONV, "refinement stagnated");
+    if (it == c->refine_maxit) return fail(c, HDG_E_NOCONV, "refinement did not reach refine_tol within refine_maxit");
     return -1;
 }
 
-// Acoustic mixed precision: recovery and refinement fused per element (the velocity is
-// recovered in closed form in FP64, so the iteration runs on (p, lam)).  When the trace
-// correction alone already meets the stopping test, the last element pass recovers without
-// forming a new residual; should the full correction then miss the test after all, a pass
-// without correction forms the residual and the iteration goes on.
-static hdg_status recover_refine_acoustic(hdg_ctx* c, double* lambda, double* u) {
+// correction trace solve: lam += dlam with K dlam = (assembled re64)
+static int refine_trace_step(hdg_ctx* c, double* lambda, float* t_sol) {
     const int64_t nt = c->n_trace_dofs * c->nrhs;
+    int r;
+    {
+        EventTimer t(c, t_sol);
+        if (launch_assemble_rhs64(c, c->d_re64)) return fail(c, HDG_E_HIP, "refinement assembly launch failed");
+        HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
+        int its;
+        double rr;
+        r = trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr, true);
+    }
+    if (r && r != HDG_E_NOCONV) return fail(c, r, "refinement trace solve failed");
+    if (launch_axpy(c, nt, 1.0, c->d_dlam, lambda)) return fail(c, HDG_E_HIP, "refinement update launch failed");
+    return HDG_OK;
+}
+
+// Acoustic mixed precision: recovery and refinement fused per element (the velocity is
+// recovered in closed form in FP64, so the velocity rows of the residual vanish and the
+// iteration runs on (p, lam)).  First pass: recovery from the FP32 factors, FP64 residual and
+// the first correction's right-hand side.  Each correction pass applies the correction and
+// checks the residual of the corrected iterate.
+static hdg_status recover_refine_acoustic(hdg_ctx* c, double* lambda, double* u) {
+    const int64_t ne = c->n_elem;
     int e;
     {
         EventTimer t(c, &c->tim.recover);
-        e = launch_refine_acoustic(c, lambda, lambda, 1, true, u, nullptr);
+        e = launch_refine_acoustic(c, lambda, lambda, 1, 1, u, c->d_sq);
     }
     if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
     c->z_consumed = true;
-    double prev = 1.0, prev_l = 1.0;
+    std::vector<double> scale;
+    int s = refine_scale(c, scale);
+    if (s) return s;
+    double prev = 0.0;
     for (int it = 1; it <= c->refine_maxit; ++it) {
-        float t_sol = 0.f, t_el = 0.f;
-        int r;
-        {
-            EventTimer t(c, &t_sol);
-            e = launch_assemble_rhs64(c, c->d_re64);
-            if (e) return fail(c, HDG_E_HIP, "refinement assembly launch failed");
-            HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
-            int its;
-            double rr;
-            r = trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr, true);
-        }
-        if (r && r != HDG_E_NOCONV) return fail(c, r, "refinement trace solve failed");
-        launch_axpy(c, nt, 1.0, c->d_dlam, lambda);
-        double ndl, nlam;
-        launch_norm2(c, nt, c->d_dlam, &ndl);
-        launch_norm2(c, nt, lambda, &nlam);
-        const double rel_l = ndl / (nlam > 0 ? nlam : 1.0);
-        const bool last = (rel_l == rel_l) && refine_converged(c, it, rel_l, prev_l);
+        float t_sol = 0.f, t_el = 0.f, t_res = 0.f;
+        if ((s = refine_trace_step(c, lambda, &t_sol))) return s;
         {
             EventTimer t(c, &t_el);
-            e = launch_refine_acoustic(c, lambda, c->d_dlam, 0, !last, u, c->d_sq);
+            e = launch_refine_acoustic(c, lambda, c->d_dlam, 0, 2, u, c->d_sq);
+        }
+        if (e) return fail(c, HDG_E_HIP, "refinement kernel launch failed");
+        double res;
+        {
+            EventTimer t(c, &t_res);
+            if ((s = refine_residual(c, c->d_sq + 2 * ne, scale, &res))) return s;
+        }
+        c->tim.refine_elem += t_el;
+        c->tim.refine_solve += t_sol + t_res;
+        const int v = refine_verdict(c, it, res, prev);
+        if (v >= 0) return v;
+        prev = res;
+        {   // full residual of the current iterate (no correction): next right-hand side
+            EventTimer t(c, &t_el);
+            e = launch_refine_acoustic(c, lambda, c->d_dlam, 2, 1, u, c->d_sq);
         }
         if (e) return fail(c, HDG_E_HIP, "refinement kernel launch failed");
         c->tim.refine_elem += t_el;
-        c->tim.refine_solve += t_sol;
-        double ndu, nu;
-        launch_norm2(c, c->n_elem, c->d_sq, &ndu);
-        launch_norm2(c, c->n_elem, c->d_sq + c->n_elem, &nu);
-        const double rel = std::max(ndu / (nu > 0 ? nu : 1.0), rel_l);
-        c->last_refine = it;
-        const int v = refine_verdict(c, it, rel, prev);
-        if (v >= 0) return v;
-        if (last) {   // residual of the current iterate, no correction
-            EventTimer t(c, &t_el);
-            e = launch_refine_acoustic(c, lambda, c->d_dlam, 2, true, u, c->d_sq);
-            if (e) return fail(c, HDG_E_HIP, "refinement kernel launch failed");
-        }
-        if (last) c->tim.refine_elem += t_el;
-        prev = rel;
-        prev_l = rel_l;
     }
     return fail(c, HDG_E_NOCONV, "refinement did not reach refine_tol within refine_maxit");
 }
@@ -638,62 +688,77 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
     int s = check_status(c);
     if (s) return s;
     c->last_refine = 0;
+    c->has_resid = false;
     c->tim.refine_elem = 0.f;
     c->tim.refine_solve = 0.f;
     if (c->precision == HDG_MIXED_FP32 && c->fast_ac) return recover_refine_acoustic(c, lambda, u);
     int e;
     {
         EventTimer t(c, &c->tim.recover);
-        e = c->fast_ac ? launch_refine_acoustic(c, lambda, lambda, 1, false, u, nullptr)
+        e = c->fast_ac ? launch_refine_acoustic(c, lambda, lambda, 1, 0, u, nullptr)
                        : launch_recover_any(c, lambda, u);
     }
     if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
     if (c->precision != HDG_MIXED_FP32) return HDG_OK;
 
-    // Iterative refinement of the full stage system: FP64 residual, correction through the
-    // FP32 factors and an FP64 trace solve, until the correction is below refine_tol.
+    // Iterative refinement of the full stage system (see above), element work in separate passes:
+    // residual (and correction right-hand side), trace solve, recovery of the correction.
     c->z_consumed = true;
-    const int64_t nl = c->n_local_dofs * c->nrhs, nt = c->n_trace_dofs * c->nrhs;
-    double prev = 1.0;
-    for (int it = 1; it <= c->refine_maxit; ++it) {
-        float t_res = 0.f, t_sol = 0.f, t_rec = 0.f;
+    const int64_t nl = c->n_local_dofs * c->nrhs;
+    std::vector<double> scale;
+    if ((s = refine_scale(c, scale))) return s;
+    {
+        float t_res = 0.f;
         {
             EventTimer t(c, &t_res);
-            e = launch_refine_general(c, u, lambda);
+            e = launch_refine_general(c, u, lambda, false, nullptr);
         }
         if (e) return fail(c, HDG_E_HIP, "refinement kernel launch failed");
-        int r;
-        {
-            EventTimer t(c, &t_sol);
-            e = launch_assemble_rhs64(c, c->d_re64);
-            if (e) return fail(c, HDG_E_HIP, "refinement assembly launch failed");
-            HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
-            int its;
-            double rr;
-            r = trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr, true);
-        }
-        if (r && r != HDG_E_NOCONV) return fail(c, r, "refinement trace solve failed");
+        c->tim.refine_elem += t_res;
+    }
+    double prev = 0.0;
+    for (int it = 1; it <= c->refine_maxit; ++it) {
+        float t_sol = 0.f, t_rec = 0.f, t_chk = 0.f, t_res = 0.f;
+        if ((s = refine_trace_step(c, lambda, &t_sol))) return s;
         {
             EventTimer t(c, &t_rec);
             e = launch_recover_any(c, c->d_dlam, c->d_du);
+            if (!e) e = launch_axpy(c, nl, 1.0, c->d_du, u);
         }
         if (e) return fail(c, HDG_E_HIP, "refinement recovery launch failed");
-        c->tim.refine_elem += t_res + t_rec;
-        c->tim.refine_solve += t_sol;
-        launch_axpy(c, nl, 1.0, c->d_du, u);
-        launch_axpy(c, nt, 1.0, c->d_dlam, lambda);
-        double ndu, nu, ndl, nlam;
-        launch_norm2(c, nl, c->d_du, &ndu);
-        launch_norm2(c, nl, u, &nu);
-        launch_norm2(c, nt, c->d_dlam, &ndl);
-        launch_norm2(c, nt, lambda, &nlam);
-        const double rel = std::max(ndu / (nu > 0 ? nu : 1.0), ndl / (nlam > 0 ? nlam : 1.0));
-        c->last_refine = it;
-        const int v = refine_verdict(c, it, rel, prev);
+        {
+            EventTimer t(c, &t_chk);
+            e = launch_refine_general(c, u, lambda, true, c->d_sq);
+        }
+        if (e) return fail(c, HDG_E_HIP, "refinement check launch failed");
+        double res;
+        {
+            EventTimer t(c, &t_res);
+            if ((s = refine_residual(c, c->d_sq, scale, &res))) return s;
+        }
+        c->tim.refine_elem += t_rec + t_chk;
+        c->tim.refine_solve += t_sol + t_res;
+        const int v = refine_verdict(c, it, res, prev);
         if (v >= 0) return v;
-        prev = rel;
+        prev = res;
+        {
+            float t_full = 0.f;
+            {
+                EventTimer t(c, &t_full);
+                e = launch_refine_general(c, u, lambda, false, nullptr);
+            }
+            if (e) return fail(c, HDG_E_HIP, "refinement kernel launch failed");
+            c->tim.refine_elem += t_full;
+        }
     }
     return fail(c, HDG_E_NOCONV, "refinement did not reach refine_tol within refine_maxit");
+}
+
+hdg_status hdg_last_residual(const hdg_ctx* c, double* rel) {
+    if (!c || !rel) return HDG_E_ARG;
+    if (!c->has_resid) return HDG_E_STATE;
+    for (int r = 0; r < c->nrhs; ++r) rel[r] = c->last_resid[r];
+    return HDG_OK;
 }
 
 hdg_status hdg_apply_mass(hdg_ctx* c, double a, const double* u, double* f) {

@@ -693,8 +693,12 @@ __global__ __launch_bounds__(64 * WPB, 2) void rhs_acoustic_kernel(
 //   t_e  = s_f (E_f^T (n_f . v) - tau (lam_f - ep_f))                (= C u + D lam, element part)
 //   re64 = Z_p^T s_p - t_e                   (element part of the trace residual of the correction)
 //   z'_p = S^{-1} s_p                        (two triangular solves with the stored factor U)
-// and the per-element norms |du| and |u| for the stopping test.  RESID = false stops after
-// the recovery (p, v): that is the plain recovery of the condensed solve.
+// and the per-element norms |du| and |u|.  RM selects the residual work: 0 stops after the
+// recovery (p, v), the plain recovery of the condensed solve; 1 forms everything above, or, with
+// the run-time flag chk (the convergence check of the refinement), s_p and t_e only: re64 = -t_e
+// (the element part of the FP64 trace residual) and |s_p| per element in place of |du| (the
+// velocity rows of the residual vanish by construction).  The check is a run-time branch of the
+// RM = 1 kernel rather than an instantiation of its own: compiled separately it spilled registers.
 //
 // Every global read of an element is issued one element ahead into registers (software
 // pipeline, one element per wavefront), so the compute phases read LDS only.  The oriented
@@ -710,7 +714,7 @@ constexpr bool rf_shared_faces() {
 }
 
 // per-wavefront LDS scratch of the refinement/recovery kernel
-template <int D, int K, int R, typename T, bool RESID>
+template <int D, int K, int R, typename T, int RM>
 struct RfScratch {
     using Dm = AcDims<D, K, R>;
     static constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT, NLOC = Dm::NLOC;
@@ -731,7 +735,7 @@ struct RfScratch {
                                              : ((Dm::TT + 3) / 4 % 2 == 1 ? (Dm::TT + 3) / 4 * 4 : (Dm::TT + 3) / 4 * 4 + 4);
     alignas(16) T Zl[N * ZS];
     T zb[N * R];                  // z'_p on entry
-    T Ll[RESID ? N * N : 1];      // U = diag(d) L_u^T of S = L_u diag(d) L_u^T, 1/d_j on the
+    T Ll[RM == 1 ? N * N : 1];      // U = diag(d) L_u^T of S = L_u diag(d) L_u^T, 1/d_j on the
                                   // diagonal, column-major
     int fq[32][8];                // face ids [0..NFACE) and orientations [4..4+NFACE) of the
                                   // next 32 elements of this wavefront
@@ -760,21 +764,21 @@ __device__ __forceinline__ A dot4(F term) {
     return (a0 + a1) + (a2 + a3);
 }
 
-template <int D, int K, int R, typename T, int WPB, bool RESID>
+template <int D, int K, int R, typename T, int WPB, int RM>
 __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
     const int32_t* __restrict__ eface, const double* __restrict__ Sr, const double* __restrict__ Ef,
     const T* __restrict__ Zs, const T* __restrict__ Lst, const double* __restrict__ f,
-    const double* __restrict__ lam, const double* __restrict__ dlam, int mode, T* __restrict__ zb,
+    const double* __restrict__ lam, const double* __restrict__ dlam, int mode, int chk, T* __restrict__ zb,
     double* __restrict__ u, double* __restrict__ re64, double* __restrict__ nrm) {
     using Dm = AcDims<D, K, R>;
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, TT = Dm::TT;
     constexpr int NLOC = Dm::NLOC, NPERM = Dm::NPERM;
-    constexpr int NEL = NFACE * N * NF, NZ = N * TT, NLL = RESID ? N * N : 0;
+    constexpr int NEL = NFACE * N * NF, NZ = N * TT, NLL = RM == 1 ? N * N : 0;
     constexpr bool SHE = rf_shared_faces<D, K>();
     constexpr int PT = PerLane<TT * R>::n, PE = SHE ? 0 : PerLane<NEL>::n, PZ = PerLane<NZ>::n;
     constexpr int PB = PerLane<N * R>::n, PU = PerLane<NLOC * R>::n, PL = PerLane<NLL>::n;
-    using Scr = RfScratch<D, K, R, T, RESID>;
+    using Scr = RfScratch<D, K, R, T, RM>;
     constexpr int SDN = PerLane<D * N>::n;
     static_assert(R == 1 && TT <= 64 && N <= 64, "one right-hand side; trace and Schur vectors fit a wavefront");
     constexpr int SS = rf_sr_stride(N);
@@ -838,7 +842,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
             if (f) rf[t] = f[(size_t)en * NLOC * R + idx];
             else rf[t] = idx < D * N * R ? (double)zve[idx] : 0.0;
         }
-        if (RESID) {
+        if (RM == 1 && !chk) {
             const T* Le = Lst + (size_t)en * NLL;
 #pragma unroll
             for (int t = 0; t < PL; ++t) rl[t] = Le[min(lane + 64 * t, NLL - 1)];
@@ -868,7 +872,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
                 sc.uo[lane + 64 * t] = ru[t];
                 sc.ff[lane + 64 * t] = rf[t];
             }
-        if (RESID)
+        if (RM == 1 && !chk)
 #pragma unroll
             for (int t = 0; t < PL; ++t)
                 if (lane + 64 * t < NLL) sc.Ll[lane + 64 * t] = rl[t];
@@ -938,7 +942,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
             if (lane + 64 * t < D * N) sc.yp[idx] = y;
         }
         double epv = 0.0;
-        if (RESID) {
+        if (RM != 0) {
             const int fc = al / NF, l = al - fc * NF;
             const double* Ec = Eface(fc) + l;
             epv = lmv - dot4<N>([&](int i) { return Ec[i * NF] * bcast(pv, i); });
@@ -964,7 +968,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
                 ue[idx] = v;
             }
         }
-        if (RESID) {
+        if (RM != 0) {
             wsync();
             // ---- G v (registers) ; n_f . v
             double gvv[SDN];
@@ -1010,6 +1014,10 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
                 const double s = dot4<N>([&](int i) { return Ec[i * NF] * sc.nv[fc * N + i]; });
                 tev = g[1 + D * D + fc] * (s - tau * epv);
             }
+            if (chk) {   // convergence check: the residual only; |s_p|^2 replaces |du|^2
+                dn = lane < N ? spv * spv : 0.0;
+                if (lane < TT) re64[(size_t)e * TT + lane] = -tev;
+            } else {
             // ---- re64 = Z_p^T s_p - t_e ; z'_p = S^{-1} s_p
             {
                 const T spt = (T)spv;
@@ -1023,6 +1031,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
             // into registers, so that a step of either solve is one multiply, one broadcast
             // and one FMA.  The solves run in the precision of the factor (and of the stored
             // correction), T.
+            {
             T cu[N], ru_[N];
 #pragma unroll
             for (int j = 0; j < N; ++j) {
@@ -1040,8 +1049,10 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
             }
             T* zbe = zb + (size_t)e * NLOC + D * N;
             if (lane < N) zbe[lane] = (T)zv;
+            }
+            }
         }
-        // ---- per-element norms of the correction and of u
+        // ---- per-element norms of the correction and of u (check mode: and of s_p)
         if (nrm) {
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
@@ -1049,7 +1060,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_acoustic_kernel(
                 un += __shfl_xor(un, off, 64);
             }
             if (lane == 0) {
-                nrm[e] = sqrt(dn);
+                nrm[chk ? 2 * ne + e : e] = sqrt(dn);
                 nrm[ne + e] = sqrt(un);
             }
         }
@@ -1083,30 +1094,32 @@ int launch_ac(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T* M
 
 // wavefronts per workgroup of the refinement kernel: as many as fit next to the shared tables
 // in the 160 KB of LDS of a CU (one workgroup per CU), at most 8
-template <int D, int K, typename T, bool RESID>
+template <int D, int K, typename T, int RM>
 constexpr int rf_wpb() {
     constexpr int N = dimp(K, D), NF = dimp(K, D - 1);
-    constexpr int sb = (int)sizeof(RfScratch<D, K, 1, T, RESID>);
+    constexpr int sb = (int)sizeof(RfScratch<D, K, 1, T, RM>);
     constexpr int tb = (D * N * rf_sr_stride(N) + (rf_shared_faces<D, K>() ? (D + 1) * ((D == 3) ? 6 : 2) * N * NF : 0)) * 8;
     constexpr int w = (160 * 1024 - tb) / sb;
     return w >= 8 ? 8 : (w < 1 ? 1 : w);
 }
 
-template <int D, int K, int R, typename T, bool RESID>
-int launch_ac_ref(hdg_ctx* c, const double* lam, const double* dlam, int mode, double* u, double* nrm) {
-    constexpr int WPB = rf_wpb<D, K, T, RESID>();
+template <int D, int K, int R, typename T, int RM>
+int launch_ac_ref(hdg_ctx* c, const double* lam, const double* dlam, int mode, double* u, double* nrm,
+                  int chk = 0) {
+    constexpr int WPB = rf_wpb<D, K, T, RM>();
     // the residual needs the FP64 right-hand side, the inverse factor and the residual buffer,
     // which exist in mixed precision only; the plain recovery reads none of them
-    if (RESID && (!c->d_f_saved || !c->d_LU || !c->d_re64)) return -1;
+    if (RM != 0 && (!c->d_f_saved || !c->d_LU || !c->d_re64)) return -1;
+    if (chk && (RM != 1 || !nrm)) return -1;
     if (mode != 1 && !c->d_f_saved) return -1;
     int64_t groups = (c->n_elem + WPB - 1) / WPB;
     static const int resident =
-        resident_groups((const void*)refine_acoustic_kernel<D, K, R, T, WPB, RESID>, 64 * WPB);
+        resident_groups((const void*)refine_acoustic_kernel<D, K, R, T, WPB, RM>, 64 * WPB);
     int grid = (int)std::min<int64_t>(groups, resident);
-    hipLaunchKernelGGL((refine_acoustic_kernel<D, K, R, T, WPB, RESID>), dim3(grid), dim3(64 * WPB), 0,
+    hipLaunchKernelGGL((refine_acoustic_kernel<D, K, R, T, WPB, RM>), dim3(grid), dim3(64 * WPB), 0,
                        c->stream, c->n_elem, c->last_a, c->d_geom, c->d_eperm, c->d_eface, c->tab.Sr, c->tab.Ef,
-                       (const T*)c->d_Zt, (const T*)(RESID ? c->d_LU : nullptr), c->d_f_saved, lam, dlam, mode,
-                       (T*)c->d_z, u, RESID ? c->d_re64 : nullptr, nrm);
+                       (const T*)c->d_Zt, (const T*)(RM == 1 ? c->d_LU : nullptr), c->d_f_saved, lam, dlam, mode,
+                       chk, (T*)c->d_z, u, RM != 0 ? c->d_re64 : nullptr, nrm);
     return (int)hipGetLastError();
 }
 
@@ -1123,14 +1136,15 @@ int dispatch_ac(hdg_ctx* c, double a, const double* f_loc, const T* Sr, const T*
     return -1;
 }
 
-int dispatch_ac_ref(hdg_ctx* c, const double* lam, const double* dlam, int mode, bool resid, double* u,
+int dispatch_ac_ref(hdg_ctx* c, const double* lam, const double* dlam, int mode, int resid, double* u,
                     double* nrm) {
     const int D = c->dim, K = c->k, R = c->nrhs;
 #define HDG_CASE(DD, KK, RR)                                                                     \
     if (D == DD && K == KK && R == RR) {                                                         \
-        if (c->precision == HDG_FP64) return launch_ac_ref<DD, KK, RR, double, false>(c, lam, dlam, mode, u, nrm); \
-        return resid ? launch_ac_ref<DD, KK, RR, float, true>(c, lam, dlam, mode, u, nrm)        \
-                     : launch_ac_ref<DD, KK, RR, float, false>(c, lam, dlam, mode, u, nrm);      \
+        if (c->precision == HDG_FP64) return launch_ac_ref<DD, KK, RR, double, 0>(c, lam, dlam, mode, u, nrm); \
+        if (resid == 1) return launch_ac_ref<DD, KK, RR, float, 1>(c, lam, dlam, mode, u, nrm);  \
+        if (resid == 2) return launch_ac_ref<DD, KK, RR, float, 1>(c, lam, dlam, mode, u, nrm, 1); \
+        return launch_ac_ref<DD, KK, RR, float, 0>(c, lam, dlam, mode, u, nrm);                  \
     }
     HDG_AC_CASES(HDG_CASE)
 #undef HDG_CASE
@@ -1139,9 +1153,9 @@ int dispatch_ac_ref(hdg_ctx* c, const double* lam, const double* dlam, int mode,
 
 }  // namespace
 
-int launch_refine_acoustic(hdg_ctx* c, const double* lam, const double* dlam, int mode, bool resid,
+int launch_refine_acoustic(hdg_ctx* c, const double* lam, const double* dlam, int mode, int resid,
                            double* u, double* nrm) {
-    if (c->physics != HDG_ACOUSTIC) return -1;
+    if (c->physics != HDG_ACOUSTIC || resid < 0 || resid > 2) return -1;
     if (c->precision == HDG_FP64 && resid) return -1;
     return dispatch_ac_ref(c, lam, dlam, mode, resid, u, nrm);
 }

@@ -881,14 +881,17 @@ __global__ __launch_bounds__(64 * WPB) void recover_general_kernel(
 //   re64 = -j1 B1^T D1^{-1} s1 - j2 Z2^T s~2 - t_e
 // One element per wavefront; operator applications staged as short products with lanes over
 // their outputs; the triangular solves are column-oriented with lanes over rows.  TL: the
-// reference tables Sr, Mf are staged in LDS (otherwise read through the caches).
-template <int PHYS, int K, int KF, int R, typename T, int WPB, bool TL>
+// reference tables Sr, Mf are staged in LDS (otherwise read through the caches).  CHK (the
+// convergence check of the refinement): stop after s and t_e, write re64 = -t_e (the element
+// part of the FP64 trace residual) and nrm[e][q] = |s| of the element's rows.
+template <int PHYS, int K, int KF, int R, typename T, int WPB, bool TL, bool CHK>
 __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
     const int32_t* __restrict__ eperm, const int32_t* __restrict__ eface, const double* __restrict__ Sr,
     const double* __restrict__ Mf, const double* __restrict__ Ef, const T* __restrict__ Zs,
     const T* __restrict__ Lst, const double* __restrict__ u, const double* __restrict__ lam,
-    const double* __restrict__ f, T* __restrict__ zout, double* __restrict__ re64, VarArgs va) {
+    const double* __restrict__ f, T* __restrict__ zout, double* __restrict__ re64, double* __restrict__ nrm,
+    VarArgs va) {
     using Dm = GDims<PHYS, K, KF, R>;
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, NPERM = Dm::NPERM, D = Dm::D;
     constexpr int M1 = Dm::M1, M2 = Dm::M2, MT = Dm::MT, N1 = Dm::N1, N2 = Dm::N2, NLOC = Dm::NLOC;
@@ -1029,6 +1032,19 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
                 sc.te[aa] = sf * s + sc.cf.dface * sf * sc.lm[aa];
             }
             ws();
+            if constexpr (CHK) {
+                double sq = 0.0;
+                for (int idx = lane; idx < NLOC; idx += 64) sq += sc.su[idx] * sc.su[idx];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
+                if (lane == 0) nrm[e * R + q] = sqrt(sq);
+                for (int aa = lane; aa < TT; aa += 64) {
+                    const int l = aa % NF, fo = (aa / NF) / MT;
+                    re64[(e * TT + aa) * R + q] = l < sc.nfv[fo] ? -sc.te[aa] : 0.0;
+                }
+                ws();
+                continue;
+            }
             // ---- stage 3: cd-weighted s1, then s~2
             for (int idx = lane; idx < D * M2 * N; idx += 64) {
                 const int r = idx / (M2 * N), b = (idx / N) % M2, i = idx % N;
@@ -1226,16 +1242,18 @@ int launch_gen_rec(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int
 
 template <int PHYS, int K, int KF, int R, typename T>
 int launch_gen_ref(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int64_t n, const double* u,
-                   const double* lam) {
+                   const double* lam, bool chk, double* nrm) {
     constexpr int WPB = 1;
-    constexpr int N = dimp(K, 3);
     constexpr bool TL = false;   // tables read through L1/L2: more wavefronts per CU than with LDS copies
     const int grid = (int)std::min<int64_t>(n, 256 * 16);
-    hipLaunchKernelGGL((refine_general_kernel<PHYS, K, KF, R, T, WPB, TL>), dim3(grid), dim3(64 * WPB), 0, c->stream,
-                       n, c->last_a, c->d_geom, c->d_eframe, c->d_eperm, c->d_eface, tb.Sr, tb.Mf, tb.Ef,
-                       (const T*)c->d_Zt, (const T*)c->d_LU, u, lam, c->d_f_saved, (T*)c->d_z, c->d_re64,
-                       var_args(c, elist));
-    return (int)hipGetLastError();
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WPB), 0, c->stream, n, c->last_a, c->d_geom, c->d_eframe,
+                           c->d_eperm, c->d_eface, tb.Sr, tb.Mf, tb.Ef, (const T*)c->d_Zt, (const T*)c->d_LU, u,
+                           lam, c->d_f_saved, (T*)c->d_z, c->d_re64, nrm, var_args(c, elist));
+        return (int)hipGetLastError();
+    };
+    if (chk) return go(refine_general_kernel<PHYS, K, KF, R, T, WPB, TL, true>);
+    return go(refine_general_kernel<PHYS, K, KF, R, T, WPB, TL, false>);
 }
 
 // built configurations: (physics, volume degree, face-table degree, right-hand sides).
@@ -1475,11 +1493,12 @@ int dispatch_gen_rec(hdg_ctx* c, const double* lam, double* u) {
     });
 }
 
-int dispatch_gen_ref(hdg_ctx* c, const double* u, const double* lam) {
+int dispatch_gen_ref(hdg_ctx* c, const double* u, const double* lam, bool chk, double* nrm) {
     const int P = c->physics, R = c->nrhs;
     return for_each_class(c, [&](int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n) {
 #define HDG_CASE(PP, KK, FF, RR) \
-    if (P == PP && K == KK && KF == FF && R == RR) return launch_gen_ref<PP, KK, FF, RR, float>(c, tb, el, n, u, lam);
+    if (P == PP && K == KK && KF == FF && R == RR)            \
+        return launch_gen_ref<PP, KK, FF, RR, float>(c, tb, el, n, u, lam, chk, nrm);
         HDG_GEN_CASES_R1(HDG_CASE)
 #undef HDG_CASE
         return -1;
@@ -1488,10 +1507,10 @@ int dispatch_gen_ref(hdg_ctx* c, const double* u, const double* lam) {
 
 }  // namespace
 
-int launch_refine_general(hdg_ctx* c, const double* u, const double* lam) {
-    if (c->precision != HDG_MIXED_FP32) return -1;
-    if (mr_supported(c)) return launch_refine_mr(c, u, lam);
-    return dispatch_gen_ref(c, u, lam);
+int launch_refine_general(hdg_ctx* c, const double* u, const double* lam, bool check, double* nrm) {
+    if (c->precision != HDG_MIXED_FP32 || (check && !nrm)) return -1;
+    if (mr_supported(c)) return launch_refine_mr(c, u, lam, check, nrm);
+    return dispatch_gen_ref(c, u, lam, check, nrm);
 }
 
 bool general_supported(int physics, int k, int kf, int nrhs) {

@@ -145,7 +145,8 @@ struct hdg_ctx {
     double* d_du = nullptr;          // [n_local_dofs][r] correction
     double* d_dlam = nullptr;        // [n_trace_dofs][r] correction
     double* d_re64 = nullptr;        // [ne][t][r] FP64 correction trace right-hand side
-    double* d_sq = nullptr;          // [2 ne] per-element norms of the refinement correction and of u
+    double* d_sq = nullptr;          // refinement norms: acoustic fast path [3][ne] (|du|, |u|, |s_p| per
+                                     // element), otherwise [ne][r] (|s| per element and column)
     double* d_stage = nullptr;       // [3][n_local_dofs][r] DIRK stages
     double* d_ustar = nullptr;
     double* d_fstage = nullptr;
@@ -153,6 +154,9 @@ struct hdg_ctx {
     bool condensed = false;
     bool z_consumed = false;         // mixed: z buffer reused by the refinement corrections
     int last_iters = 0, last_refine = 0;
+    // relative FP64 residual per column of the final iterate of the last mixed-precision recover
+    double last_resid[32] = {};
+    bool has_resid = false;
     hdg::Timings tim;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
@@ -188,10 +192,12 @@ int launch_assemble(hdg_ctx* c, const double* lam_bnd);
 int launch_residual(hdg_ctx* c, double a, const double* u, const double* lam, const double* f,
                     const double* lam_bnd, double* su, double* slam);
 // Acoustic recovery of (v, p) from the stored factors (FP64: the plain recovery; mixed
-// precision: then, with `resid`, the FP64 residual, the correction right-hand side and the
-// element part of the trace residual).  mode 1 starts from p = 0 with dlam = lam (the first
-// recovery), mode 0 applies the correction dlam, mode 2 none.  nrm: [2 ne] per-element |du|, |u|.
-int launch_refine_acoustic(hdg_ctx* c, const double* lam, const double* dlam, int mode, bool resid,
+// precision: then, with resid = 1, the FP64 residual, the correction right-hand side and the
+// element part of the trace residual; with resid = 2 the FP64 residual only: re64 = -t_e and
+// nrm[2 ne + e] = |s_p|).  mode 1 starts from p = 0 with dlam = lam (the first recovery), mode 0
+// applies the correction dlam, mode 2 none.  nrm: [3 ne] per-element |du|, |u|, |s_p| (|du| is
+// not written by the check, resid = 2).
+int launch_refine_acoustic(hdg_ctx* c, const double* lam, const double* dlam, int mode, int resid,
                            double* u, double* nrm);
 // Right-hand-side condensation with the factors of the last condensation (acoustic fast path):
 // r_e and z for a new f_loc; launch_assemble_rhs then assembles the trace right-hand side only.
@@ -212,6 +218,9 @@ int launch_axpy(hdg_ctx* c, int64_t n, double alpha, const double* x, double* y)
 int launch_lincomb(hdg_ctx* c, int64_t n, double a, const double* x, double b, const double* y,
                    double* out);
 int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out);
+// sum of squares per column of a row-major [n][R] vector (R <= 32) to the host (synchronises);
+// bnd_only: rows of the Dirichlet faces of a trace vector only (n = faces x bs)
+int launch_col_sq(hdg_ctx* c, int64_t n, int R, const double* x, double* host_out, bool bnd_only = false);
 // condense_general.hip (elastodynamics, Maxwell)
 bool general_supported(int physics, int k, int kf, int nrhs);
 int var_face_degree();   // face-table degree used on meshes of variable degree
@@ -220,9 +229,12 @@ int launch_condense_general(hdg_ctx* c, double a, const double* f_loc);
 void read_tune_table(hdg_ctx* c);
 void write_tune_table(const hdg_ctx* c);
 int launch_recover_general(hdg_ctx* c, const double* lam, double* u);
-int launch_refine_general(hdg_ctx* c, const double* u, const double* lam);
+// FP64 residual of the full stage system at (u, lam) and, unless `check`, the correction right-hand
+// side (re64) and the element part of the correction (z buffer); with `check` only re64 = -t_e
+// and nrm[e][q] = |s| of element e, column q.
+int launch_refine_general(hdg_ctx* c, const double* u, const double* lam, bool check, double* nrm);
 // recover_mrhs.hip (acoustic, 3D, 32 right-hand sides: matrix-core recovery and refinement)
 bool mr_supported(const hdg_ctx* c);
 int launch_recover_mr(hdg_ctx* c, const double* lam, double* u);
-int launch_refine_mr(hdg_ctx* c, const double* u, const double* lam);
+int launch_refine_mr(hdg_ctx* c, const double* u, const double* lam, bool check, double* nrm);
 }  // namespace hdg

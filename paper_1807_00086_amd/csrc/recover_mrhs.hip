@@ -272,14 +272,16 @@ __global__ __launch_bounds__(256, 2) void recover_mr_kernel(
 // The two wavefronts of a workgroup are the two column blocks of one element; they share the
 // element's factor L, staged in LDS with its upper triangle and diagonal zeroed, for the
 // substitutions (one row per step, the pivot row's values broadcast across the four row groups).
-template <int K, int KF>
+// CHK (the convergence check of the refinement): stop after the residuals, leave re64 = -te_f
+// and write nrm[e][q] = |(s1, s2)| of element e, column q.
+template <int K, int KF, bool CHK>
 __global__ __launch_bounds__(128, 2) void refine_mr_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const int32_t* __restrict__ eperm,
     const int32_t* __restrict__ eface, const double* __restrict__ Sr, const double* __restrict__ SrT,
     const double* __restrict__ Mf, const double* __restrict__ Ef, const double* __restrict__ EfT,
     const float* __restrict__ Zs, const float* __restrict__ Lst, const double* __restrict__ u,
     const double* __restrict__ lam, const double* __restrict__ f, float* __restrict__ zout,
-    double* __restrict__ re64, MrArgs va) {
+    double* __restrict__ re64, double* __restrict__ nrm, MrArgs va) {
     using Dm = MrDims<K, KF>;
     constexpr int N = Dm::N, NF = Dm::NF, TT = Dm::TT, N1 = Dm::N1, NLOC = Dm::NLOC;
     constexpr int NT = Dm::NT, KS = Dm::KS, KSF = Dm::KSF, NTF = Dm::NTF, NP = Dm::NP, LS = Dm::LS;
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(128, 2) void refine_mr_kernel(
                         const unsigned l = 16 * mt + lg + 4 * v;
                         if (l < (unsigned)NF) {
                             const double te = m.sf[fc] * (acc[k][mt][v] - m.tau * lam_at(fc, l, z));
-                            rq[(fc * NF + l) * R + q] = -te;
+                            rq[(fc * NF + l) * R + q] = l < (unsigned)nfv[fc] ? -te : 0.0;
                         }
                     }
         }
@@ -430,6 +432,7 @@ __global__ __launch_bounds__(128, 2) void refine_mr_kernel(
                 }
         }
         // residuals, one row tile at a time: s1 (stored as z1') and s2
+        double sq = 0.0;   // CHK: this lane's share of |(s1, s2)|^2 of column q
         double wsm[4];
 #pragma unroll
         for (int fc = 0; fc < 4; ++fc) wsm[fc] = m.sf[fc] * m.tau;
@@ -498,15 +501,26 @@ __global__ __launch_bounds__(128, 2) void refine_mr_kernel(
                         double t = t1[x][v];
 #pragma unroll
                         for (int fc = 0; fc < 4; ++fc) t -= m.nf[fc][x] * m.sf[fc] * aE[fc][v];
-                        if (orow < (unsigned)N) zo[(x * N + orow) * R + q] = (float)(t * ijaro);
+                        if (orow < (unsigned)N) {
+                            if (CHK) sq += t * t;
+                            else zo[(x * N + orow) * R + q] = (float)(t * ijaro);
+                        }
                     }
                     double t = 0.0;
 #pragma unroll
                     for (int fc = 0; fc < 4; ++fc) t += wsm[fc] * aE[fc][v];
                     const double sv = S2[(4 * mt + v) * 64 + lane + z] + t;
                     S2[(4 * mt + v) * 64 + lane + z] = orow < (unsigned)N ? sv : 0.0;
+                    if (CHK && orow < (unsigned)N) sq += sv * sv;
                 }
             }
+        }
+        if constexpr (CHK) {
+            // the four row groups of column q hold lanes lr, lr + 16, lr + 32, lr + 48
+            sq += __shfl_xor(sq, 16, 64);
+            sq += __shfl_xor(sq, 32, 64);
+            if (lg == 0) nrm[e * R + q] = sqrt(sq);
+            continue;
         }
         // st = s2 - (1/(a rho)) sum_r Sr_r (sum_x G_rx s1_x)
         {
@@ -671,15 +685,15 @@ int launch_rec_mr(hdg_ctx* c, const DeviceTables& tb, const int32_t* el, int64_t
     return (int)hipGetLastError();
 }
 
-template <int K, int KF>
+template <int K, int KF, bool CHK>
 int launch_ref_mr(hdg_ctx* c, const DeviceTables& tb, const int32_t* el, int64_t n, const double* u,
-                  const double* lam) {
+                  const double* lam, double* nrm) {
     using Dm = MrDims<K, KF>;
-    const void* kern = (const void*)refine_mr_kernel<K, KF>;
+    const void* kern = (const void*)refine_mr_kernel<K, KF, CHK>;
     const int grid = (int)std::min<int64_t>(n, resident_groups(kern, 128));
-    hipLaunchKernelGGL((refine_mr_kernel<K, KF>), dim3(grid), dim3(128), 0, c->stream, n, c->last_a, c->d_geom,
+    hipLaunchKernelGGL((refine_mr_kernel<K, KF, CHK>), dim3(grid), dim3(128), 0, c->stream, n, c->last_a, c->d_geom,
                        c->d_eperm, c->d_eface, tb.Sr, tb.SrT, tb.Mf, tb.Ef, tb.EfT, (const float*)c->d_Zt,
-                       (const float*)c->d_LU, u, lam, c->d_f_saved, (float*)c->d_z, c->d_re64,
+                       (const float*)c->d_LU, u, lam, c->d_f_saved, (float*)c->d_z, c->d_re64, nrm,
                        mr_args(c, el, Dm::N, Dm::NLOC, Dm::TT));
     return (int)hipGetLastError();
 }
@@ -718,11 +732,13 @@ int launch_recover_mr(hdg_ctx* c, const double* lam, double* u) {
     });
 }
 
-int launch_refine_mr(hdg_ctx* c, const double* u, const double* lam) {
-    if (c->precision != HDG_MIXED_FP32) return -1;
+int launch_refine_mr(hdg_ctx* c, const double* u, const double* lam, bool check, double* nrm) {
+    if (c->precision != HDG_MIXED_FP32 || (check && !nrm)) return -1;
     return mr_for_each_class(c, [&](int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n) {
-#define HDG_CASE(KK, FF) \
-    if (K == KK && KF == FF) return launch_ref_mr<KK, FF>(c, tb, el, n, u, lam);
+#define HDG_CASE(KK, FF)                                                        \
+    if (K == KK && KF == FF)                                                    \
+        return check ? launch_ref_mr<KK, FF, true>(c, tb, el, n, u, lam, nrm)   \
+                     : launch_ref_mr<KK, FF, false>(c, tb, el, n, u, lam, nrm);
         HDG_MR_CASES(HDG_CASE)
 #undef HDG_CASE
         return -1;

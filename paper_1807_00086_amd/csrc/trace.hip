@@ -459,6 +459,33 @@ __global__ __launch_bounds__(NT) void copy_bnd_kernel(int64_t nf, int bs, int R,
     if (bnd[F]) dst[gid] = src[gid];
 }
 
+// partial sums of squares per rhs column over the rows of the boundary (Dirichlet) faces only,
+// in the thread layout of dot_partial_kernel (rows are face-major: row / bs is the face)
+__global__ __launch_bounds__(NT) void bnd_sq_partial_kernel(int64_t n, int R, int bs, const uint8_t* __restrict__ bnd,
+                                                            const double* __restrict__ x, double* __restrict__ part) {
+    __shared__ double sh[NT];
+    const int T = NT / R, t = threadIdx.x;
+    double acc = 0.0;
+    if (t < T * R) {
+        const int r = t % R;
+        for (int64_t i = (int64_t)blockIdx.x * T + t / R; i < n; i += (int64_t)gridDim.x * T)
+            if (bnd[i / bs]) acc += x[i * R + r] * x[i * R + r];
+    }
+    sh[t] = acc;
+    __syncthreads();
+    if (R == 1) {
+        for (int s = NT / 2; s > 0; s >>= 1) {
+            if (t < s) sh[t] += sh[t + s];
+            __syncthreads();
+        }
+        if (t == 0) part[blockIdx.x] = sh[0];
+    } else if (t < R) {
+        double s = 0.0;
+        for (int k = 0; k < T; ++k) s += sh[k * R + t];
+        part[(size_t)blockIdx.x * R + t] = s;
+    }
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + NT - 1) / NT); }
 
 }  // namespace
@@ -643,6 +670,20 @@ int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out) {
     return (int)e;
 }
 
+int launch_col_sq(hdg_ctx* c, int64_t n, int R, const double* x, double* host_out, bool bnd_only) {
+    if (R < 1 || R > 32) return (int)hipErrorInvalidValue;
+    if (bnd_only)
+        hipLaunchKernelGGL(bnd_sq_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, c->bs,
+                           c->d_face_bnd, x, c->d_red);
+    else
+        hipLaunchKernelGGL(dot_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, x, x, c->d_red);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, R, c->d_red,
+                       c->d_scal + 7 * 32);
+    hipError_t e = hipMemcpyAsync(host_out, c->d_scal + 7 * 32, R * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return (int)e;
+    return (int)hipStreamSynchronize(c->stream);
+}
+
 // Preconditioned CG on the assembled (sign-adjusted) system; all rhs columns iterate
 // together with their own scalars.  Convergence is checked on the host every iteration.
 int launch_bsr_f32(hdg_ctx* c) {
@@ -673,8 +714,8 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
     hipMemcpyAsync(pp, zz, n * R * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     dot(c, rr, zz, s_rz);
     dot(c, c->d_rhs, c->d_rhs, s_bb);
-    std::vector<double> hb(R);
-    hipMemcpyAsync(hb.data(), s_bb, R * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    double hb[32];
+    hipMemcpyAsync(hb, s_bb, R * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     hipStreamSynchronize(c->stream);
     for (int r = 0; r < R; ++r) hb[r] = std::sqrt(hb[r]) > 0 ? std::sqrt(hb[r]) : 1.0;
     int it = 0;

@@ -30,7 +30,7 @@ EXPORTS = ["hdg_init_mesh", "hdg_query", "hdg_condense", "hdg_condense_rhs", "hd
            "hdg_step", "hdg_apply_mass", "hdg_volume_points", "hdg_project_volume",
            "hdg_boundary_points", "hdg_project_boundary", "hdg_point_sources",
            "hdg_element_data", "hdg_last_timing", "hdg_reference_table", "hdg_destroy",
-           "hdg_last_error"]
+           "hdg_last_error", "hdg_last_residual"]
 
 
 class HDGError(RuntimeError):
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "hdg_reference_table": (i64, [cint, cint, cint, cint, vp, i64]),
         "hdg_destroy": (None, [vp]),
         "hdg_last_error": (C.c_char_p, [vp]),
+        "hdg_last_residual": (cint, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -99,12 +100,30 @@ def load_library(path: str = LIB_PATH):
 
 
 def _ptr(a):
-    """Device pointer of a torch tensor or host pointer of a contiguous numpy array."""
+    """Host pointer of a contiguous numpy array (host-side helpers only)."""
     if a is None:
         return None
     if hasattr(a, "data_ptr"):
         return C.c_void_p(a.data_ptr())
     return a.ctypes.data_as(C.c_void_p)
+
+
+def check_device_vector(t, n, name):
+    """Device pointer of `t` after checking that it is a contiguous FP64 torch tensor on the GPU
+    with at least `n` elements: the library's kernels read and write exactly that many, so a
+    host array, another dtype, a strided view or a short buffer is rejected here (HDG_E_ARG)
+    instead of being handed to them."""
+    if not (hasattr(t, "data_ptr") and hasattr(t, "is_cuda")):
+        raise HDGError(1, f"{name}: expected a torch tensor on the GPU, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise HDGError(1, f"{name}: tensor is on {t.device}, the library needs device memory")
+    if str(t.dtype) != "torch.float64":
+        raise HDGError(1, f"{name}: dtype {t.dtype}, the library reads and writes float64")
+    if not t.is_contiguous():
+        raise HDGError(1, f"{name}: tensor is not contiguous")
+    if t.numel() < n:
+        raise HDGError(1, f"{name}: {t.numel()} elements, {n} needed")
+    return C.c_void_p(t.data_ptr())
 
 
 def reference_table(dim, k, kF, which):
@@ -180,29 +199,49 @@ class Solver:
             pass
 
     # ------------------------------------------------------------------ path
+    def _nl(self):
+        return self.query("n_local_dofs") * self.nrhs
+
+    def _nt(self):
+        return self.query("n_trace_dofs") * self.nrhs
+
     def condense(self, a, f_loc, lam_bnd):
-        self._check(self.lib.hdg_condense(self.ctx, float(a), _ptr(f_loc), _ptr(lam_bnd)))
+        self._check(self.lib.hdg_condense(self.ctx, float(a), check_device_vector(f_loc, self._nl(), "f_loc"),
+                                          check_device_vector(lam_bnd, self._nt(), "lam_bnd")))
 
     def condense_rhs(self, a, f_loc, lam_bnd):
         """Condense a new right-hand side with the factors of the last condense (same a)."""
-        self._check(self.lib.hdg_condense_rhs(self.ctx, float(a), _ptr(f_loc), _ptr(lam_bnd)))
+        self._check(self.lib.hdg_condense_rhs(self.ctx, float(a), check_device_vector(f_loc, self._nl(), "f_loc"),
+                                              check_device_vector(lam_bnd, self._nt(), "lam_bnd")))
 
     def trace_solve(self, lam):
         it = C.c_int()
         rr = C.c_double()
-        self._check(self.lib.hdg_trace_solve(self.ctx, _ptr(lam), C.byref(it), C.byref(rr)))
+        self._check(self.lib.hdg_trace_solve(self.ctx, check_device_vector(lam, self._nt(), "lambda"),
+                                             C.byref(it), C.byref(rr)))
         return it.value, rr.value
 
     def recover(self, lam, u):
-        self._check(self.lib.hdg_recover(self.ctx, _ptr(lam), _ptr(u)))
+        self._check(self.lib.hdg_recover(self.ctx, check_device_vector(lam, self._nt(), "lambda"),
+                                         check_device_vector(u, self._nl(), "u_loc")))
+
+    def last_residual(self):
+        """Relative FP64 residual per column of the last mixed-precision recover."""
+        out = np.zeros(self.nrhs)
+        self._check(self.lib.hdg_last_residual(self.ctx, _ptr(out)))
+        return out
 
     def step(self, t, dt, scheme, u, lam, lam_bnd_stages, src=None):
         sc = {"be": BACKWARD_EULER, "dirk33": DIRK33}.get(scheme, scheme)
-        self._check(self.lib.hdg_step(self.ctx, float(t), float(dt), int(sc), _ptr(u), _ptr(lam),
-                                      _ptr(lam_bnd_stages), _ptr(src)))
+        ns = 3 if sc == DIRK33 else 1
+        self._check(self.lib.hdg_step(self.ctx, float(t), float(dt), int(sc), check_device_vector(u, self._nl(), "u"),
+                                      check_device_vector(lam, self._nt(), "lambda"),
+                                      check_device_vector(lam_bnd_stages, ns * self._nt(), "lam_bnd"),
+                                      None if src is None else check_device_vector(src, self._nl(), "src")))
 
     def apply_mass(self, a, u, f):
-        self._check(self.lib.hdg_apply_mass(self.ctx, float(a), _ptr(u), _ptr(f)))
+        self._check(self.lib.hdg_apply_mass(self.ctx, float(a), check_device_vector(u, self._nl(), "u"),
+                                            check_device_vector(f, self._nl(), "f")))
 
     # ------------------------------------------------------------------ host helpers
     def volume_points(self):

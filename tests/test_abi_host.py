@@ -156,3 +156,24 @@ def test_variable_degree_scope():
     deg_bad[0] = 6
     st, msg = _init(p3.xyz, p3.elem_vert, degree=deg_bad)
     assert st == 2 and "degree" in msg
+
+
+def test_binding_rejects_host_wrong_dtype_strided_and_short_buffers():
+    """The binding hands the library only contiguous FP64 device tensors of the needed length;
+    anything else is refused before a pointer reaches the kernels (HDG_E_ARG)."""
+    import torch
+    from paper_1807_00086_amd.hdg import HDGError, check_device_vector
+    cases = [np.zeros(10), torch.zeros(10, dtype=torch.float64), [0.0] * 10]
+    for bad in cases:
+        with pytest.raises(HDGError) as ei:
+            check_device_vector(bad, 10, "x")
+        assert ei.value.code == 1
+    if torch.cuda.is_available():
+        for bad, n in [(torch.zeros(10, dtype=torch.float32, device="cuda"), 10),
+                       (torch.zeros(20, dtype=torch.float64, device="cuda")[::2], 10),
+                       (torch.zeros(9, dtype=torch.float64, device="cuda"), 10)]:
+            with pytest.raises(HDGError) as ei:
+                check_device_vector(bad, n, "x")
+            assert ei.value.code == 1
+        good = torch.zeros(10, dtype=torch.float64, device="cuda")
+        assert check_device_vector(good, 10, "x").value == good.data_ptr()

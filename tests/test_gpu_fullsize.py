@@ -64,12 +64,14 @@ def _stage(s, a, f, lb):
 
 
 def _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, tmap, n_elem_sample, n_face_sample, seed,
-                           faces=None):
-    """Local equations on sampled elements and trace equations on sampled faces (or on the
-    given faces).  u, f are [n_local][r]; lam, lb are in the library's trace layout, tmap maps
-    the oracle's trace dof index to the library's."""
+                           faces=None, elems=None):
+    """Local equations on sampled elements (or on the given elements) and trace equations on
+    sampled faces (or on the given faces).  u, f are [n_local][r]; lam, lb are in the library's
+    trace layout, tmap maps the oracle's trace dof index to the library's."""
     rng = np.random.default_rng(seed)
-    elems = np.unique(np.concatenate([[0, p.n_elem - 1], rng.integers(0, p.n_elem, n_elem_sample)]))
+    if elems is None:
+        elems = np.unique(np.concatenate([[0, p.n_elem - 1], rng.integers(0, p.n_elem, n_elem_sample)]))
+    elems = np.asarray(elems, dtype=np.int64)
     _step(f"local equations on {elems.size} elements")
     for e in elems:
         A, B, Cm, Dm, _ = ohdg.element_system(d, int(e), a)
@@ -182,3 +184,65 @@ def test_full_size_pvar_sampled():
     # are many orders smaller than the global residual the trace solve controls)
     faces = np.unique(np.concatenate([list(d.skel.elem_faces[e]) for e in src_elems[:40]]))
     _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, tmap, 60, 0, 4, faces=faces)
+
+
+def test_full_size_acoustic_mixed_bench_settings_sampled():
+    """The benchmark workload (3D acoustics, k = 3, 82,944 tets) in mixed precision exactly as
+    the benchmark runs it: sampled local and trace equations against the oracle's element
+    systems, and the reported FP64 residual at or below refine_tol."""
+    _need_gpu()
+    import bench
+    from oracle import hdg as ohdg
+    _T0[0] = time.time()
+    p = make_problem(2)
+    print(f"case fullsize acoustic mixed bench settings n_elem={p.n_elem} {bench.MIXED_OPTS}", flush=True)
+    d = ohdg.make_discretisation(p)
+    a = 1.0 / (GAMMA * p.dt)
+    from paper_1807_00086_amd import Solver
+    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=3, precision="mixed_fp32", **bench.MIXED_OPTS)
+    nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+    f = random_vector(nl, 2, 31)[:, None]
+    lb = (random_vector(nt, 2, 32) * ohdg.boundary_trace_mask(d))[:, None]
+    u, lam, rr = _stage(s, a, f, lb)
+    res = s.last_residual()
+    _step(f"mixed stage done ({s.query('last_refine')} corrections, residual {res[0]:.2e})")
+    s.close()
+    assert np.all(res <= bench.MIXED_OPTS["refine_tol"]), res
+    _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, np.arange(nt), 60, 40, 2)
+
+
+def test_full_size_pvar_mixed_sampled():
+    """p-heterogeneous acoustics at full size (200,000 tets, 32 point-source columns) in mixed
+    precision with the degree classes as one graph: per-column residuals at or below refine_tol
+    and the local and trace equations of the source elements against the oracle."""
+    _need_gpu()
+    from oracle import hdg as ohdg
+    _T0[0] = time.time()
+    p = make_problem(4)
+    print(f"case fullsize pvar mixed n_elem={p.n_elem}", flush=True)
+    d = ohdg.make_discretisation(p)
+    a = 1.0 / p.dt
+    tol_res = 1e-12
+    s = _solver(p, "mixed_fp32", krylov_tol=1e-10, krylov_maxit=4000, refine_tol=tol_res)
+    nt = s.query("n_trace_dofs")
+    f = s.point_sources(p.sources)
+    lb = np.zeros((nt, p.nrhs))
+    u, lam, rr = _stage(s, a, f, lb)
+    res = s.last_residual()
+    _step(f"mixed stage done ({s.query('last_refine')} corrections, worst residual {res.max():.2e})")
+    s.close()
+    assert res.shape == (32,) and np.all(res <= tol_res), res
+    face_of = np.repeat(np.arange(d.skel.n_faces), np.diff(d.tr_off))
+    tmap = face_of * BS_VAR + (np.arange(d.tr_off[-1]) - d.tr_off[face_of])
+    hit = np.unique(np.nonzero(np.abs(f).sum(axis=1))[0])
+    src_elems = np.unique(np.searchsorted(d.loc_off, hit, side="right") - 1)
+    _step(f"local equations on {min(40, src_elems.size)} source elements")
+    for e in src_elems[:40]:
+        A, B, Cm, Dm, _ = ohdg.element_system(d, int(e), a)
+        li, ti = d.elem_local_dofs(e), tmap[d.elem_trace_dofs(e)]
+        r = A @ u[li] + B @ lam[ti] - f[li]
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(f[li]), int(e)
+    # trace equations on the faces of the source elements (elsewhere the fields are many orders
+    # below the scale the residual test controls)
+    faces = np.unique(np.concatenate([list(d.skel.elem_faces[e]) for e in src_elems[:40]]))
+    _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, tmap, 0, 0, 4, faces=faces, elems=[])

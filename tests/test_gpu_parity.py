@@ -149,6 +149,7 @@ def test_stage_parity_mixed(cfg, kw):
     errs = _rel_field_errors(ohdg, d, u, u_ref)
     assert 1 <= nref <= 6
     assert max(errs) <= 1e-10, (errs, nref)
+    assert np.all(s.last_residual() <= 1e-12), s.last_residual()
     assert np.linalg.norm(lam - lam_ref) <= 1e-10 * np.linalg.norm(lam_ref)
     # the FP32 Schur complements themselves are only single-precision accurate
     t = cond.Ke[0].shape[0]
@@ -160,6 +161,32 @@ def test_stage_parity_mixed(cfg, kw):
     with pytest.raises(HDGError) as ei:
         s.recover(_dev(lam), _dev(u))
     assert ei.value.code == 7
+    s.close()
+
+
+@pytest.mark.parametrize("cfg,kw", [(2, dict(n=3, k=3)), (2, dict(n=4, k=3)), (1, dict())])
+def test_stage_parity_mixed_bench_settings(cfg, kw):
+    """The mixed-precision path exactly as the benchmark runs it (first trace solve to its
+    krylov_tol, the refinement stopping on the FP64 residual at its refine_tol) matches the FP64
+    oracle to 1e-10 per field, and the reported residual meets refine_tol."""
+    _need_gpu()
+    import bench
+    ohdg = _oracle()
+    p = make_problem(cfg, **kw)
+    print(f"case mixed bench settings cfg={cfg} {kw} n_elem={p.n_elem} {bench.MIXED_OPTS}", flush=True)
+    d = ohdg.make_discretisation(p)
+    a = 1.0 / (0.43586652150845899 * p.dt)
+    f = random_vector(d.loc_off[-1], cfg, 5)
+    lb = random_vector(d.tr_off[-1], cfg, 6) * ohdg.boundary_trace_mask(d)
+    u_ref, lam_ref, _ = ohdg.solve_stage(d, a, f, lb)
+    s = _solver(p, precision="mixed_fp32", **bench.MIXED_OPTS)
+    u, lam, it, rr = _gpu_stage(s, a, f, lb)
+    errs = _rel_field_errors(ohdg, d, u, u_ref)
+    res = s.last_residual()
+    print(f"  corrections {s.query('last_refine')}, residual {res[0]:.2e}, errors {errs}", flush=True)
+    assert np.all(res <= bench.MIXED_OPTS["refine_tol"]), res
+    assert max(errs) <= 1e-10, errs
+    assert np.linalg.norm(lam - lam_ref) <= 1e-10 * np.linalg.norm(lam_ref)
     s.close()
 
 
