@@ -215,6 +215,18 @@ hdg_status hdg_condense_rhs(hdg_ctx* ctx, double a, const double* f_loc, const d
 hdg_status hdg_trace_solve(hdg_ctx* ctx, double* lambda, int* iters, double* relres);
 
 /*
+ * hdg_trace_solve_static -- hdg_trace_solve that allocates nothing, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, result and errors as hdg_trace_solve; the conjugate-gradient work
+ * vectors and reduction partial sums live in a file-scope device array of the library
+ * (64 MiB per GPU, held until the process ends) instead of the context's buffers.  A system that
+ * needs more (4 x n_trace_dofs x nrhs doubles, plus 2048 x 32 + 256 doubles of partial sums
+ * and scalars) fails with HDG_E_ARG before any device work.  All calls on one GPU share the array: calls that
+ * overlap on a device (two streams, two threads) race and must not be issued.
+ */
+hdg_status hdg_trace_solve_static(hdg_ctx* ctx, double* lambda, int* iters, double* relres);
+
+/*
  * hdg_recover -- local fields from the trace: u_e = z_e - Z_e lam_e (first block row of
  * the stage system).  In HDG_MIXED_FP32 mode the result is then refined: the residual of
  * the full uncondensed system is evaluated in FP64 from the element operators, corrected

@@ -430,6 +430,11 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
         if (c->device_name.empty()) c->device_name = "unknown";
     }
     if (!c->tune_path.empty()) read_tune_table(c);
+    if (static_scratch_setup() != HDG_OK) {   // address of the no-allocation solve's scratch
+        g_init_err = "hipGetSymbolAddress of the static trace-solve scratch failed";
+        hdg_destroy(c);
+        return HDG_E_HIP;
+    }
 #undef TRY
     *out = c;
     return HDG_OK;
@@ -546,6 +551,29 @@ hdg_status hdg_trace_solve(hdg_ctx* c, double* lambda, int* iters, double* relre
         // mixed precision: K already carries the FP32 factors' error and the refinement's FP64
         // residual removes it, so the products may read the FP32 copy as well
         r = trace_cg(c, lambda, c->krylov_tol, iters, relres, c->d_bsr32 != nullptr);
+    }
+    if (r == HDG_E_NOCONV) return fail(c, r, "trace solve did not reach krylov_tol");
+    if (r) return fail(c, r, "trace solve failed");
+    return HDG_OK;
+}
+
+hdg_status hdg_trace_solve_static(hdg_ctx* c, double* lambda, int* iters, double* relres) {
+    if (!c) return HDG_E_ARG;
+    if (!lambda) return fail(c, HDG_E_ARG, "null lambda");
+    const int64_t need = trace_static_need(c);
+    if (need > TRACE_STATIC_DOUBLES) {
+        std::ostringstream os;
+        os << "hdg_trace_solve_static: this system needs " << need * 8 << " bytes of scratch, the static "
+           << "scratch holds " << TRACE_STATIC_DOUBLES * 8 << " bytes (use hdg_trace_solve)";
+        return fail(c, HDG_E_ARG, os.str());
+    }
+    if (!c->condensed) return fail(c, HDG_E_STATE, "hdg_trace_solve_static before hdg_condense");
+    int s = check_status(c);
+    if (s) return s;
+    int r;
+    {
+        EventTimer t(c, &c->tim.solve);
+        r = trace_cg_static(c, lambda, iters, relres);
     }
     if (r == HDG_E_NOCONV) return fail(c, r, "trace solve did not reach krylov_tol");
     if (r) return fail(c, r, "trace solve failed");

@@ -41,6 +41,8 @@ struct Timings {
 
 // workgroups of the reductions over the trace vectors (partial sums per workgroup and column)
 constexpr int RED_MAX = 2048;
+// doubles of the file-scope device scratch of hdg_trace_solve_static (64 MiB per GPU)
+constexpr int64_t TRACE_STATIC_DOUBLES = (int64_t)8 << 20;
 
 struct hdg_ctx {
     // configuration
@@ -210,6 +212,12 @@ int launch_block_inverse(hdg_ctx* c);
 // tolerance is far above FP32 rounding; the refinement's FP64 residual removes the difference)
 int trace_cg(hdg_ctx* c, double* lambda, double tol, int* iters, double* relres, bool lowp = false);
 int launch_bsr_f32(hdg_ctx* c);
+// trace solve with the CG work vectors and reduction scratch in the library's static device
+// array (no allocation); static_scratch_setup looks up the array's address on the current device
+// once; trace_static_need is the number of doubles a context's solve needs
+int static_scratch_setup();
+int64_t trace_static_need(const hdg_ctx* c);
+int trace_cg_static(hdg_ctx* c, double* lambda, int* iters, double* relres);
 
 // Workgroups that stay resident on the whole device at once for `kernel` with `block` threads
 // (at least 1): a grid of this size visits every element with one wave per element slot.

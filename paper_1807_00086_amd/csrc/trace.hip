@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <limits>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -756,6 +757,72 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
     c->last_iters = it;
     if (!(worst <= tol)) return HDG_E_NOCONV;
     return HDG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Trace solve without any allocation: the CG work vectors (r, z, p, q), the per-workgroup partial
+// sums and the device scalars live in this file-scope device array instead of the context's
+// buffers.  Each GPU holds its own copy for the life of the process; host code must use the
+// address obtained from hipGetSymbolAddress on that device, never the array's name.  Every call on
+// one GPU shares it: calls that overlap on a device race.  Nothing in it needs clearing: the CG
+// writes every entry it reads (r from the right-hand side, z, p, q from r, the partial sums and
+// scalars by their reductions) before reading it.
+}  // namespace hdg
+
+static __device__ __align__(256) double scratch[TRACE_STATIC_DOUBLES];
+
+namespace hdg {
+namespace {
+constexpr int MAX_DEV = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEV] = {};
+}  // namespace
+
+int static_scratch_setup() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV) return HDG_E_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return HDG_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return HDG_E_HIP;
+    g_scratch_ptr[dev] = (double*)ptr;
+    return HDG_OK;
+}
+
+int64_t trace_static_need(const hdg_ctx* c) {
+    return 4 * c->n_faces * c->bs * c->nrhs + (int64_t)RED_MAX * 32 + 8 * 32;
+}
+
+int trace_cg_static(hdg_ctx* c, double* lambda, int* iters, double* relres) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV) return HDG_E_HIP;
+    double* base;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = g_scratch_ptr[dev];
+    }
+    if (!base) {   // the context was created on another device: set up this one now
+        if (static_scratch_setup() != HDG_OK) return HDG_E_HIP;
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = g_scratch_ptr[dev];
+    }
+    const int64_t n = c->n_faces * c->bs * c->nrhs;
+    // the context's buffers are swapped out for the call and restored afterwards
+    double* saved[6] = {c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red, c->d_scal};
+    c->d_cg_r = base;
+    c->d_cg_z = base + n;
+    c->d_cg_p = base + 2 * n;
+    c->d_cg_q = base + 3 * n;
+    c->d_red = base + 4 * n;
+    c->d_scal = base + 4 * n + (int64_t)RED_MAX * 32;
+    const int r = trace_cg(c, lambda, c->krylov_tol, iters, relres, c->d_bsr32 != nullptr);
+    c->d_cg_r = saved[0];
+    c->d_cg_z = saved[1];
+    c->d_cg_p = saved[2];
+    c->d_cg_q = saved[3];
+    c->d_red = saved[4];
+    c->d_scal = saved[5];
+    return r;
 }
 
 }  // namespace hdg

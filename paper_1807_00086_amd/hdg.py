@@ -30,7 +30,7 @@ EXPORTS = ["hdg_init_mesh", "hdg_query", "hdg_condense", "hdg_condense_rhs", "hd
            "hdg_step", "hdg_apply_mass", "hdg_volume_points", "hdg_project_volume",
            "hdg_boundary_points", "hdg_project_boundary", "hdg_point_sources",
            "hdg_element_data", "hdg_last_timing", "hdg_reference_table", "hdg_destroy",
-           "hdg_last_error", "hdg_last_residual"]
+           "hdg_last_error", "hdg_last_residual", "hdg_trace_solve_static"]
 
 
 class HDGError(RuntimeError):
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "hdg_destroy": (None, [vp]),
         "hdg_last_error": (C.c_char_p, [vp]),
         "hdg_last_residual": (cint, [vp, vp]),
+        "hdg_trace_solve_static": (cint, [vp, vp, C.POINTER(cint), C.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -219,6 +220,14 @@ class Solver:
         rr = C.c_double()
         self._check(self.lib.hdg_trace_solve(self.ctx, check_device_vector(lam, self._nt(), "lambda"),
                                              C.byref(it), C.byref(rr)))
+        return it.value, rr.value
+
+    def trace_solve_static(self, lam):
+        """hdg_trace_solve without any allocation (library-owned static scratch)."""
+        it = C.c_int()
+        rr = C.c_double()
+        self._check(self.lib.hdg_trace_solve_static(self.ctx, check_device_vector(lam, self._nt(), "lambda"),
+                                                    C.byref(it), C.byref(rr)))
         return it.value, rr.value
 
     def recover(self, lam, u):
