@@ -317,6 +317,16 @@ hdg_status hdg_last_timing(const hdg_ctx* ctx, int which, double* ms);
  */
 int64_t hdg_reference_table(int dim, int k, int kF, int which, double* out, int64_t cap);
 
+/*
+ * hdg_hbm_probe -- diagnostic: achievable HBM bandwidth of a streaming pass, for comparison with
+ * the element kernels' rooflines.  Times `reps` launches (after one untimed launch) of a read-only
+ * pass over src (dst NULL: each 16-byte load summed in registers, nothing written) or of a copy
+ * src -> dst, on `stream` with HIP events; grid = blocks_per_cu x compute units workgroups of 256
+ * threads.  src, dst: device [n] FP64, n even; ms: host out, milliseconds per launch.
+ */
+hdg_status hdg_hbm_probe(const double* src, double* dst, int64_t n, int reps, int blocks_per_cu, void* stream,
+                         double* ms);
+
 /* hdg_destroy -- free every buffer the context owns.  NULL-safe. */
 void hdg_destroy(hdg_ctx* ctx);
 

@@ -17,7 +17,7 @@ OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["reftab.cpp", "mesh.cpp", "capi.cpp", "condense_acoustic.hip", "condense_general.hip", "recover_mrhs.hip", "trace.hip",
-           "stage.hip"]
+           "stage.hip", "membench.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

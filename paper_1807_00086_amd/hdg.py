@@ -30,7 +30,8 @@ EXPORTS = ["hdg_init_mesh", "hdg_query", "hdg_condense", "hdg_condense_rhs", "hd
            "hdg_step", "hdg_apply_mass", "hdg_volume_points", "hdg_project_volume",
            "hdg_boundary_points", "hdg_project_boundary", "hdg_point_sources",
            "hdg_element_data", "hdg_last_timing", "hdg_reference_table", "hdg_destroy",
-           "hdg_last_error", "hdg_last_residual", "hdg_trace_solve_static"]
+           "hdg_last_error", "hdg_last_residual", "hdg_trace_solve_static",
+           "hdg_hbm_probe"]
 
 
 class HDGError(RuntimeError):
@@ -91,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "hdg_last_error": (C.c_char_p, [vp]),
         "hdg_last_residual": (cint, [vp, vp]),
         "hdg_trace_solve_static": (cint, [vp, vp, C.POINTER(cint), C.POINTER(dbl)]),
+        "hdg_hbm_probe": (cint, [vp, vp, i64, cint, cint, vp, C.POINTER(dbl)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -125,6 +127,25 @@ def check_device_vector(t, n, name):
     if t.numel() < n:
         raise HDGError(1, f"{name}: {t.numel()} elements, {n} needed")
     return C.c_void_p(t.data_ptr())
+
+
+def hbm_probe(src, dst=None, reps=10, blocks_per_cu=8, stream=None):
+    """Milliseconds per launch of the library's streaming read (dst None) or copy pass over the
+    FP64 device tensor src (diagnostic)."""
+    lib = load_library()
+    n = src.numel()
+    check_device_vector(src, n, "src")
+    if dst is not None:
+        check_device_vector(dst, n, "dst")
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    ms = C.c_double()
+    st = lib.hdg_hbm_probe(C.c_void_p(src.data_ptr()), None if dst is None else C.c_void_p(dst.data_ptr()),
+                           n, int(reps), int(blocks_per_cu), C.c_void_p(stream), C.byref(ms))
+    if st != 0:
+        raise HDGError(st, "hdg_hbm_probe failed")
+    return ms.value
 
 
 def reference_table(dim, k, kF, which):
