@@ -14,7 +14,9 @@
  *
  * Physics: acoustics (velocity v, pressure p; trace p_hat), linear elastodynamics
  * (velocity, symmetric stress; trace v_hat; section 4.1), Maxwell (E, H; tangential
- * trace E_hat^t; section 5.2).  The orderings are listed below; the local equations and
+ * trace E_hat^t; section 5.2), and Maxwell with the generalised Lagrange multiplier phi of
+ * section 5.1.2 (equations (dmax1)-(dmax3), alpha_1 = alpha_2 = alpha_3 = 1, phi eliminated
+ * locally, so the trace system is that of Maxwell).  The orderings are listed below; the local equations and
  * sign conventions of each physics are stated in csrc/physics.h.
  *
  * Conventions shared by every entry point
@@ -26,7 +28,7 @@
  *  - Local dofs: element-major, then field component, then basis index, then rhs (r
  *    innermost when nrhs > 1).  Component orders:
  *      acoustic [v_1..v_d, p];  elastic [s11,s22,s33,s23,s13,s12, v_1,v_2,v_3];
- *      maxwell [H_1,H_2,H_3, E_1,E_2,E_3].
+ *      maxwell [H_1,H_2,H_3, E_1,E_2,E_3];  maxwell_glm [H_1,H_2,H_3, E_1,E_2,E_3, phi].
  *  - Trace dofs: face-major, then component, then face basis index, then rhs.
  *    On a mesh of variable degree the face degree is the larger degree of the face's
  *    elements (the element's own degree on the boundary), and every face is padded to the
@@ -62,7 +64,7 @@ enum {
     HDG_E_UNSUPPORTED = 8  /* configuration not built into this library                     */
 };
 
-enum hdg_physics { HDG_ACOUSTIC = 0, HDG_ELASTIC = 1, HDG_MAXWELL = 2 };
+enum hdg_physics { HDG_ACOUSTIC = 0, HDG_ELASTIC = 1, HDG_MAXWELL = 2, HDG_MAXWELL_GLM = 3 };
 enum hdg_precision {
     HDG_FP64 = 0,          /* local factorisations, Z and K_e in FP64                       */
     HDG_MIXED_FP32 = 1     /* local factorisations, Z and K_e in FP32, FP64 refinement      */
@@ -84,7 +86,7 @@ typedef struct {
 typedef struct {
     int physics;                /* enum hdg_physics                                           */
     const double* elem_par;     /* host [n_elem][3]: acoustic (rho, c, -), elastic
-                                   (rho, lambda, mu), maxwell (eps, mu, sigma)               */
+                                   (rho, lambda, mu), maxwell and maxwell_glm (eps, mu, sigma) */
     double stab_scale;          /* multiplies tau = 1/(rho c) | S = 2 rho c_s | tau = 2       */
 } hdg_phys_desc;
 
@@ -156,7 +158,8 @@ enum hdg_query_key {
  * Built configurations (others return HDG_E_UNSUPPORTED before any device work):
  *   acoustics 2D/3D, uniform k = 1..4, nrhs = 1; acoustics 3D, uniform k = 1..4, nrhs = 32;
  *   acoustics 3D of variable degree (k_e in 1..5, face degree = the larger neighbour's),
- *   nrhs = 1 or 32; elastodynamics 3D, k = 1..4; Maxwell 3D, k = 1..3 (nrhs = 1).
+ *   nrhs = 1 or 32; elastodynamics 3D, k = 1..4; Maxwell and GLM-Maxwell 3D, k = 1..3
+ *   (nrhs = 1).
  * On a mesh of variable degree the projection helpers (hdg_volume_points and siblings)
  * return HDG_E_UNSUPPORTED; hdg_point_sources and hdg_apply_mass work on it.
  */

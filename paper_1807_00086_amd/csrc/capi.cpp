@@ -209,7 +209,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     if (!m->xyz || !m->elem_vert || m->n_elem <= 0 || m->n_vert <= 0)
         return fail(nullptr, HDG_E_ARG, "empty mesh or null mesh arrays");
     if (m->n_elem >= (int64_t)1 << 31) return fail(nullptr, HDG_E_ARG, "too many elements");
-    if (p->physics < 0 || p->physics > 2) return fail(nullptr, HDG_E_ARG, "unknown physics");
+    if (p->physics < 0 || p->physics > 3) return fail(nullptr, HDG_E_ARG, "unknown physics");
     if (p->physics != HDG_ACOUSTIC && m->dim != 3) return fail(nullptr, HDG_E_ARG, "elastic/maxwell need dim 3");
     if (!p->elem_par) return fail(nullptr, HDG_E_ARG, "null elem_par");
     if (o->precision != HDG_FP64 && o->precision != HDG_MIXED_FP32)
@@ -263,7 +263,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
         c->k = kk;
     }
     c->fast_ac = c->physics == HDG_ACOUSTIC && !c->vardeg && c->nrhs == 1;
-    c->m_local = (c->physics == HDG_ACOUSTIC) ? d + 1 : (c->physics == HDG_ELASTIC ? 9 : 6);
+    c->m_local = (c->physics == HDG_ACOUSTIC) ? d + 1 : (c->physics == HDG_ELASTIC ? 9 : (c->physics == HDG_MAXWELL ? 6 : 7));
     c->m_trace = (c->physics == HDG_ACOUSTIC) ? 1 : (c->physics == HDG_ELASTIC ? 3 : 2);
     const int kface = c->vardeg ? var_face_degree() : kk;
     c->N = dim_p(kk, d);
@@ -297,7 +297,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     }
     c->K_sign = (c->physics == HDG_ACOUSTIC) ? -1.0 : 1.0;
     // densely factored (Schur) block: acoustic p, elastic v, maxwell E
-    c->Ns = (c->physics == HDG_ACOUSTIC) ? c->N : 3 * c->N;
+    c->Ns = (c->physics == HDG_ACOUSTIC) ? c->N : (c->physics == HDG_MAXWELL_GLM ? 4 * c->N : 3 * c->N);
     c->s_row0 = (c->physics == HDG_ACOUSTIC) ? d * c->N : (c->physics == HDG_ELASTIC ? 6 * c->N : 3 * c->N);
     if (!supported(c)) {
         std::ostringstream os;
@@ -353,7 +353,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
             TRY(upload_tables(c, c->tabk[k], rk, ek));
         }
     }
-    if (c->physics == HDG_MAXWELL) {
+    if (c->physics == HDG_MAXWELL || c->physics == HDG_MAXWELL_GLM) {
         std::vector<double> ef(c->n_elem * (d + 1) * 6);
         for (int64_t e = 0; e < c->n_elem; ++e)
             for (int f = 0; f <= d; ++f)
@@ -946,7 +946,7 @@ hdg_status hdg_project_boundary(const hdg_ctx* c, const double* vals, double* la
                 for (int q = 0; q < nq; ++q) {
                     const double* v = &vals[(b * nq + q) * vw];
                     double g;
-                    if (c->physics == HDG_MAXWELL) {
+                    if (c->physics == HDG_MAXWELL || c->physics == HDG_MAXWELL_GLM) {
                         const double* t = &c->frame[F * 6 + comp * 3];
                         g = v[0] * t[0] + v[1] * t[1] + v[2] * t[2];
                     } else {

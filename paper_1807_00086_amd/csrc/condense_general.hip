@@ -19,6 +19,15 @@
 //   acoustic (u1 = velocity, u2 = pressure, trace p_hat):
 //     dmat = a rho I, c_r[x][0] = -G_rx, b1[x][f] = n_fx, b2[0][f] = -tau, amass = a/(rho c^2),
 //     af_f = tau, dface = -tau, j1 = +1.
+//   GLM-Maxwell (section 5.2 with the multiplier phi of section 5.1.2; u1 = H, u2 = [E, phi]):
+//     as Maxwell for H and E; the phi equation (dmax3) enters with its sign reversed, so that
+//     A22 stays symmetric: A22 gains the skew-free coupling Y of E and phi,
+//       Y[phi][E_x] = Y[E_x][phi]^T = -|J| sum_r G_rx Sr_r   (-(phi, div v) and -(div E, psi)),
+//     amass[phi][phi] = -(a/alpha_1^2 + 1/alpha_2^2), af_f[phi][phi] = -1/alpha_3^2, and the phi
+//     rows of f2 change sign.  The Schur block S is then quasi-definite (SPD in E, negative
+//     definite in phi after elimination), factored without pivoting as S = L Sigma L^T with
+//     Sigma = diag(sign of the pivots); phi is eliminated locally with the rest of the Schur
+//     block, so the trace system keeps its size (section 5.2).
 // Variable degree (acoustic): the face tables are built at the largest element degree of the
 // mesh and the modes of a face above its own degree (the larger degree of its two elements)
 // are masked out; elements are launched by degree class through an element list, local
@@ -47,7 +56,9 @@ namespace {
 
 constexpr int NTG = 256;
 constexpr int NWG = NTG / 64;   // wavefronts per workgroup
-constexpr int PH_ACOUSTIC = 0, PH_ELASTIC = 1, PH_MAXWELL = 2;
+constexpr int PH_ACOUSTIC = 0, PH_ELASTIC = 1, PH_MAXWELL = 2, PH_GLM = 3;
+// GLM coefficients alpha_1, alpha_2, alpha_3 of (dmax3): section 5.4 runs all three at 1
+constexpr double GLM_A1 = 1.0, GLM_A2 = 1.0, GLM_A3 = 1.0;
 
 // Broadcast of lane `src`'s value within the wavefront (src uniform)
 __device__ __forceinline__ double wbcast(double v, int src) {
@@ -86,6 +97,10 @@ template <>
 struct PhysDims<PH_MAXWELL> {
     static constexpr int M1 = 3, M2 = 3, MT = 2;
 };
+template <>
+struct PhysDims<PH_GLM> {
+    static constexpr int M1 = 3, M2 = 4, MT = 2;
+};
 
 template <int PHYS, int K, int KF, int R>
 struct GDims {
@@ -118,6 +133,8 @@ struct Coef {
     double g1[NFC][NFC];       // b1^T dmat^{-1} b1
     double dface;
     double j1;
+    double y[3][M2][M2];       // GLM: coefficient of |J| Sr_r[i][j] in block (b, gm) of A22
+    double f2s[M2];            // sign of the rows of f2 (GLM: -1 on phi)
 };
 
 // primary coefficients from the geometry record, material and (Maxwell) face frames
@@ -137,6 +154,10 @@ __device__ void coef_primary(const double* g, const double* frm, double a, Coef<
             for (int f = 0; f < 4; ++f) cf.af[f][b][b2] = 0.0;
         }
     cf.j1 = -1.0;
+    for (int r = 0; r < 3; ++r)
+        for (int b = 0; b < M2; ++b)
+            for (int b2 = 0; b2 < M2; ++b2) cf.y[r][b][b2] = 0.0;
+    for (int b = 0; b < M2; ++b) cf.f2s[b] = 1.0;
     if constexpr (PHYS == PH_ACOUSTIC) {
         const double rho = g[GEO_PAR], cc = g[GEO_PAR + 1], tau = g[GEO_STAB];
         for (int x = 0; x < 3; ++x) {
@@ -203,9 +224,10 @@ __device__ void coef_primary(const double* g, const double* frm, double a, Coef<
         auto lc = [](int i, int j, int k) { return (double)((i - j) * (j - k) * (k - i)) / 2.0; };
         for (int r = 0; r < 3; ++r)
             for (int y = 0; y < 3; ++y)
-                for (int x = 0; x < 3; ++x) {
+                for (int x = 0; x < M2; ++x) {
                     double s = 0.0;
-                    for (int sx = 0; sx < 3; ++sx) s += lc(x, sx, y) * G[r][sx];
+                    if (x < 3)
+                        for (int sx = 0; sx < 3; ++sx) s += lc(x, sx, y) * G[r][sx];
                     cf.c[r][y][x] = s;
                 }
         for (int f = 0; f < 4; ++f)
@@ -213,10 +235,8 @@ __device__ void coef_primary(const double* g, const double* frm, double a, Coef<
                 const double* t = frm + f * 6 + cc * 3;
                 const double w[3] = {n[f][1] * t[2] - n[f][2] * t[1], n[f][2] * t[0] - n[f][0] * t[2],
                                      n[f][0] * t[1] - n[f][1] * t[0]};
-                for (int y = 0; y < 3; ++y) {
-                    cf.b1[y][f * 2 + cc] = w[y];
-                    cf.b2[y][f * 2 + cc] = -tau * t[y];
-                }
+                for (int y = 0; y < 3; ++y) cf.b1[y][f * 2 + cc] = w[y];
+                for (int y = 0; y < M2; ++y) cf.b2[y][f * 2 + cc] = y < 3 ? -tau * t[y] : 0.0;
             }
         for (int x = 0; x < 3; ++x) {
             cf.amass[x][x] = a * eps + sig;
@@ -224,6 +244,17 @@ __device__ void coef_primary(const double* g, const double* frm, double a, Coef<
                 for (int z = 0; z < 3; ++z) cf.af[f][x][z] = tau * ((x == z ? 1.0 : 0.0) - n[f][x] * n[f][z]);
         }
         cf.dface = tau;
+        if constexpr (PHYS == PH_GLM) {
+            constexpr int P = 3;   // phi
+            cf.amass[P][P] = -(a / (GLM_A1 * GLM_A1) + 1.0 / (GLM_A2 * GLM_A2));
+            for (int f = 0; f < 4; ++f) cf.af[f][P][P] = -1.0 / (GLM_A3 * GLM_A3);
+            for (int r = 0; r < 3; ++r)
+                for (int x = 0; x < 3; ++x) {
+                    cf.y[r][P][x] = -G[r][x];   // -(div E, psi)  in the reversed phi row
+                    cf.y[r][x][P] = 0.0;        // -(phi, div v) is its transpose (Sr_r^T), see form_s
+                }
+            cf.f2s[P] = -1.0;
+        }
     }
     (void)MT;
 }
@@ -315,6 +346,7 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
     __shared__ double geo[GEOM_STRIDE];
     __shared__ double frm[24];
     __shared__ T dinv[N2];
+    __shared__ T sgn[N2];   // signs of the Schur block's pivots (all +1 unless GLM)
     // Schur blocks of at most 64 unknowns with one right-hand side: the one-wavefront register
     // Cholesky runs while the other wavefronts form B~2 and f~2 (HV then has its own buffer)
     constexpr bool OVL = (N2 <= 64 && R == 1);
@@ -335,7 +367,7 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
         __syncthreads();
         // ------------------------------------------------------------ load
         if (tid < GEOM_STRIDE) geo[tid] = geom[e * GEOM_STRIDE + tid];
-        if (PHYS == PH_MAXWELL && tid >= 64 && tid < 64 + 24) frm[tid - 64] = eframe[e * 24 + tid - 64];
+        if (PHYS >= PH_MAXWELL && tid >= 64 && tid < 64 + 24) frm[tid - 64] = eframe[e * 24 + tid - 64];
         for (int idx = tid; idx < NFACE * N * NF; idx += NTG) {
             const int f = idx / (N * NF);
             const int p = eperm[e * NFACE + f];
@@ -344,10 +376,11 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
         }
         const double* fe = f_loc + (va.loc_off ? va.loc_off[e] : e * NLOC) * R;
         for (int idx = tid; idx < N1 * R; idx += NTG) F1[idx] = (T)fe[idx];
-        for (int idx = tid; idx < N2 * R; idx += NTG) X[(idx / R) * C + TT + idx % R] = (T)fe[N1 * R + idx];
         __syncthreads();
         if (tid == 0) coef_primary<PHYS>(geo, frm, a, cf);
         __syncthreads();
+        for (int idx = tid; idx < N2 * R; idx += NTG)
+            X[(idx / R) * C + TT + idx % R] = (T)(cf.f2s[idx / (N * R)] * fe[N1 * R + idx]);
         coef_derived_a<PHYS>(cf, tid, NTG);
         __syncthreads();
         coef_derived_b<PHYS>(cf, tid, NTG);
@@ -455,6 +488,13 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                 for (int f = 0; f < NFACE; ++f) mf[f] = (T)geo[1 + D * D + f] * Mf[(f * N + i) * N + j];
     #pragma unroll
                 for (int rr = 0; rr < 9; ++rr) tf[rr] = Tfull[(rr * N + i) * N + j];
+                T sij[3], sji[3];
+                if constexpr (PHYS == PH_GLM)
+    #pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        sij[r] = Srs[(r * N + i) * N + j];
+                        sji[r] = Srs[(r * N + j) * N + i];
+                    }
                 auto put = [&](int b, int gm) {
                     T s = (i == j) ? J * (T)cf.amass[b][gm] : T(0);
     #pragma unroll
@@ -462,6 +502,9 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                     T q = 0;
     #pragma unroll
                     for (int rr = 0; rr < 9; ++rr) q += (T)cf.Gam[b][gm][rr] * tf[rr];
+                    if constexpr (PHYS == PH_GLM)   // the E-phi coupling Y and its transpose
+    #pragma unroll
+                        for (int r = 0; r < 3; ++r) q += (T)cf.y[r][b][gm] * sij[r] + (T)cf.y[r][gm][b] * sji[r];
                     Sb[(b * N + i) * N2 + gm * N + j] = s + J * q;
                 };
                 // FP64 keeps the component-pair loop rolled (unrolled, its registers spill)
@@ -498,14 +541,17 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
 #pragma unroll
                 for (int j = 0; j < N2; ++j) {
                     const T p = wbcast(x[j], j);
-                    bad |= !(p > ptol && p - p == T(0));
+                    bad |= !(fabs(p) > ptol && p - p == T(0)) || (PHYS != PH_GLM && !(p > T(0)));
                     dl = lane == j ? p : dl;
                     const T t = x[j] * piv_rcp(p);
 #pragma unroll
                     for (int i = j + 1; i < N2; ++i) x[i] -= wbcast(x[i], j) * t;
                 }
                 if (bad && lane == 0) atomicOr(status, 1);
-                const T isq = T(1) / sqrt(dl);
+                // L[c][j] = U[j][c] sign(d_j) / sqrt|d_j|  (S = L Sigma L^T, Sigma = sign(d))
+                const T sg = dl < T(0) ? T(-1) : T(1);
+                const T isq = sg / sqrt(fabs(dl));
+                if (lane < N2) sgn[lane] = sg;
 #pragma unroll
                 for (int j = 0; j < N2; ++j) {
                     const T sj = wbcast(isq, j);
@@ -543,7 +589,8 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
             const T ptol = T(64 * N2) * geps<T>() * dmax;
             for (int j = 0; j < N2; ++j) {
                 const T djj = Sb[j * N2 + j];
-                if (tid == 0 && !(djj > ptol && djj - djj == T(0))) atomicOr(status, 1);
+                if (tid == 0 && (!(fabs(djj) > ptol && djj - djj == T(0)) || (PHYS != PH_GLM && !(djj > T(0)))))
+                    atomicOr(status, 1);
                 const T rinv = piv_rcp(djj);
                 for (int i = j + 1 + ((ty - j - 1) & 15); i < N2; i += 16) {
                     const T lij = Sb[i * N2 + j] * rinv;
@@ -552,18 +599,26 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                 }
                 __syncthreads();
             }
-            for (int j = tid; j < N2; j += NTG) dinv[j] = T(1) / sqrt(Sb[j * N2 + j]);
+            for (int j = tid; j < N2; j += NTG) {
+                const T d = Sb[j * N2 + j];
+                sgn[j] = d < T(0) ? T(-1) : T(1);
+                dinv[j] = sgn[j] / sqrt(fabs(d));
+            }
             __syncthreads();
             for (int idx = tid; idx < N2 * N2; idx += NTG) {
                 const int i = idx / N2, j = idx - i * N2;
                 if (j < i) Sb[idx] *= dinv[j];
             }
             __syncthreads();
-            for (int j = tid; j < N2; j += NTG) Sb[j * N2 + j] = sqrt(Sb[j * N2 + j]);
+            for (int j = tid; j < N2; j += NTG) Sb[j * N2 + j] = sqrt(fabs(Sb[j * N2 + j]));
             __syncthreads();
         }
+        // the stored factor carries sign(d_j) on its diagonal (negative only for GLM's phi pivots)
         if (Lout)
-            for (int idx = tid; idx < N2 * N2; idx += NTG) Lout[e * strL + idx] = Sb[idx];
+            for (int idx = tid; idx < N2 * N2; idx += NTG) {
+                const int i = idx / N2;
+                Lout[e * strL + idx] = (idx == i * N2 + i) ? sgn[i] * Sb[idx] : Sb[idx];
+            }
         // ------------------------------------------------------------ [W | w] = L^{-1} [B~2 | f~2]
         // Blocks of 16 rows: the diagonal block is solved one column per thread in registers
         // (factor entries by LDS broadcast), then the rows below are updated as MFMA tiles,
@@ -662,8 +717,12 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                 for (int k0 = 0; k0 < N2; k0 += 8) {
                     const int r = k0 + lk, r2 = k0 + 4 + lk;
                     const int rc = min(r, N2 - 1), rc2 = min(r2, N2 - 1);
-                    const T av = r < N2 ? X[rc * C + ca] : T(0);
-                    const T av2 = r2 < N2 ? X[rc2 * C + ca] : T(0);
+                    T av = r < N2 ? X[rc * C + ca] : T(0);
+                    T av2 = r2 < N2 ? X[rc2 * C + ca] : T(0);
+                    if constexpr (PHYS == PH_GLM) {   // W^T Sigma W
+                        av *= sgn[rc];
+                        av2 *= sgn[rc2];
+                    }
                     w0 = MF::mac(av, X[rc * C + cb], w0);
                     w1 = MF::mac(av2, X[rc2 * C + cb], w1);
                 }
@@ -731,7 +790,11 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                     const int aa = idx / R, q = idx % R;
                     const int fc = aa / NF, l = aa % NF, f = fc / MT;
                     T acc = 0, accb = 0;
-                    for (int row = 0; row < N2; ++row) acc += X[row * C + aa] * X[row * C + TT + q];
+                    for (int row = 0; row < N2; ++row) {
+                        T w = X[row * C + aa] * X[row * C + TT + q];
+                        if constexpr (PHYS == PH_GLM) w *= sgn[row];
+                        acc += w;
+                    }
                     for (int i = 0; i < N; ++i) {
                         T fb = 0;
 #pragma unroll
@@ -743,6 +806,10 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
             }
         }
         __syncthreads();
+        if constexpr (PHYS == PH_GLM) {   // Z2 = L^{-T} Sigma W
+            for (int idx = tid; idx < N2 * C; idx += NTG) X[idx] *= sgn[idx / C];
+            __syncthreads();
+        }
         // ------------------------------------------------------------ Z2 = L^{-T} W, z2 = L^{-T} w
         // The same by blocks of rows from the bottom, with L^T from the upper triangle of Sb:
         // the diagonal block in registers, then the rows above as MFMA tiles.
@@ -819,7 +886,7 @@ __global__ __launch_bounds__(64 * WPB) void recover_general_kernel(
     for (int64_t ie = (int64_t)blockIdx.x * WPB + wave; ie < ne; ie += (int64_t)gridDim.x * WPB) {
         const int64_t e = va.elist ? (int64_t)va.elist[ie] : ie;
         if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
-        if (PHYS == PH_MAXWELL && lane < 24) sc.frm[lane] = eframe[e * 24 + lane];
+        if (PHYS >= PH_MAXWELL && lane < 24) sc.frm[lane] = eframe[e * 24 + lane];
         if (lane < NFACE) sc.nfv[lane] = va.efnf ? (int)va.efnf[e * NFACE + lane] : NF;
         ws();
         if (lane == 0) coef_primary<PHYS>(sc.geo, sc.frm, a, sc.cf);
@@ -937,7 +1004,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
         const int64_t e = va.elist ? (int64_t)va.elist[ie] : ie;
         const int64_t loc = (va.loc_off ? va.loc_off[e] : e * NLOC) * R;
         if (lane < GEOM_STRIDE) sc.geo[lane] = geom[e * GEOM_STRIDE + lane];
-        if (PHYS == PH_MAXWELL && lane < 24) sc.frm[lane] = eframe[e * 24 + lane];
+        if (PHYS >= PH_MAXWELL && lane < 24) sc.frm[lane] = eframe[e * 24 + lane];
         if (lane < NFACE) sc.nfv[lane] = va.efnf ? (int)va.efnf[e * NFACE + lane] : NF;
         if (lane < NFACE) sc.pf[lane] = eperm[e * NFACE + lane];
         ws();
@@ -957,7 +1024,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
         for (int q = 0; q < R; ++q) {
             for (int idx = lane; idx < NLOC; idx += 64) {
                 sc.uu[idx] = u[loc + (int64_t)idx * R + q];
-                sc.su[idx] = f[loc + (int64_t)idx * R + q];
+                sc.su[idx] = (idx >= N1 ? sc.cf.f2s[(idx - N1) / N] : 1.0) * f[loc + (int64_t)idx * R + q];
             }
             for (int c = lane; c < TT; c += 64) {
                 const int fo = c / (MT * NF), l = c % NF;
@@ -1015,6 +1082,21 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
                             s += sc.geo[1 + D * D + fa] * sc.cf.af[fa][b][gm] * sc.mu[(fa * M2 + gm) * N + i];
                     }
                     for (int fc = 0; fc < NFC; ++fc) s += sc.cf.b2[b][fc] * sc.ef[fc * N + i];
+                    if constexpr (PHYS == PH_GLM) {   // E-phi coupling: J sum_r (y Sr_r + y^T Sr_r^T) u2
+                        double yv = 0.0;
+                        for (int r = 0; r < D; ++r)
+                            for (int gm = 0; gm < M2; ++gm) {
+                                const double c1 = sc.cf.y[r][b][gm], c2 = sc.cf.y[r][gm][b];
+                                if (c1 != 0.0) {
+                                    const double* Srow = &Srs[(r * N + i) * N];
+                                    double t = 0.0;
+                                    for (int j = 0; j < N; ++j) t += Srow[j] * u2[gm * N + j];
+                                    yv += c1 * t;
+                                }
+                                yv += c2 * sc.yu[(r * M2 + gm) * N + i];
+                            }
+                        s += J * yv;
+                    }
                     Au = -J * xt + s;
                 }
                 sc.su[row] -= Au;
@@ -1091,11 +1173,14 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
             {
                 constexpr int PS = (N2 + 63) / 64;
                 double sv[PS], rd[PS];
+                double sg[PS];   // signs of the pivots, stored on the factor's diagonal
 #pragma unroll
                 for (int t = 0; t < PS; ++t) {
                     const int i = min(lane + 64 * t, N2 - 1);
                     sv[t] = sc.st[i];
-                    rd[t] = 1.0 / (double)L[i * N2 + i];
+                    const double dg = (double)L[i * N2 + i];
+                    sg[t] = dg < 0.0 ? -1.0 : 1.0;
+                    rd[t] = 1.0 / fabs(dg);
                 }
 #pragma unroll 4
                 for (int j = 0; j < N2; ++j) {       // forward: L y = s~2
@@ -1110,6 +1195,8 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
                         sv[t] = i == j ? yj : (i > j ? sv[t] - lij * yj : sv[t]);
                     }
                 }
+#pragma unroll
+                for (int t = 0; t < PS; ++t) sv[t] *= sg[t];   // y <- Sigma y (S^{-1} = L^{-T} Sigma L^{-1})
 #pragma unroll 4
                 for (int j = N2 - 1; j >= 0; --j) {  // backward: L^T x = y
                     double xj = 0.0;
@@ -1262,6 +1349,7 @@ int launch_gen_ref(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int
 // The acoustic cases with 32 right-hand sides recover and refine in recover_mrhs.hip.
 #define HDG_GEN_CASES_R1(X)                                                                         \
     X(1, 1, 1, 1) X(1, 2, 2, 1) X(1, 3, 3, 1) X(1, 4, 4, 1) X(2, 1, 1, 1) X(2, 2, 2, 1) X(2, 3, 3, 1) \
+    X(3, 1, 1, 1) X(3, 2, 2, 1) X(3, 3, 3, 1)                                                         \
     X(0, 1, 5, 1) X(0, 2, 5, 1) X(0, 3, 5, 1) X(0, 4, 5, 1) X(0, 5, 5, 1)
 #define HDG_GEN_CASES(X)                                                                            \
     HDG_GEN_CASES_R1(X)                                                                             \

@@ -4,6 +4,7 @@
 //   elastic   compliance Acomp on the six stress components (off-diagonal test tensors
 //             weigh twice), rho on the velocity
 //   maxwell   diag(mu, mu, mu, eps, eps, eps)
+//   maxwell with the GLM multiplier: the same and 1/alpha_1^2 = 1 on phi
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,8 +36,9 @@ __global__ __launch_bounds__(NT) void apply_mass_kernel(int64_t ne, int physics,
         f[gid] = a * J * w * ue[rem];
         return;
     }
-    if (physics == HDG_MAXWELL) {
-        w = (comp < 3) ? par[1] : par[0];
+    if (physics == HDG_MAXWELL || physics == HDG_MAXWELL_GLM) {
+        // GLM: the multiplier's weight is 1 / alpha_1^2 = 1 (section 5.4)
+        w = (comp < 3) ? par[1] : (comp < 6 ? par[0] : 1.0);
         f[gid] = a * J * w * ue[rem];
         return;
     }

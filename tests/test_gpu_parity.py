@@ -40,7 +40,7 @@ def _dev(x):
 def _rel_field_errors(ohdg, d, u_gpu, u_ref):
     out = []
     groups = {"acoustic": [list(range(d.dim)), [d.dim]], "elastic": [list(range(6)), [6, 7, 8]],
-              "maxwell": [[0, 1, 2], [3, 4, 5]]}[d.physics]
+              "maxwell": [[0, 1, 2], [3, 4, 5]], "maxwell_glm": [[0, 1, 2], [3, 4, 5], [6]]}[d.physics]
     for g in groups:
         num = ohdg.l2_norm_fields(d, u_gpu - u_ref, g)
         den = ohdg.l2_norm_fields(d, u_ref, g)
@@ -52,7 +52,8 @@ def _schur_rows(d):
     """(count, first row) of the densely factored block inside an element's local vector."""
     from oracle.polynomials import dim_p
     N = dim_p(int(d.degree[0]), d.dim)
-    return {"acoustic": (N, d.dim * N), "elastic": (3 * N, 6 * N), "maxwell": (3 * N, 3 * N)}[d.physics]
+    return {"acoustic": (N, d.dim * N), "elastic": (3 * N, 6 * N), "maxwell": (3 * N, 3 * N),
+            "maxwell_glm": (4 * N, 3 * N)}[d.physics]
 
 
 def _gpu_stage(s, a, f, lb):
@@ -366,4 +367,48 @@ def test_nonfinite_rhs_reports_noconv():
     with pytest.raises(HDGError) as ei:
         s.trace_solve(lam)
     assert ei.value.code == 6
+    s.close()
+
+
+GLM_CASES = [(dict(n=2, k=1), "fp64"), (dict(n=2, k=2), "fp64"), (dict(n=2, k=3), "fp64"),
+             (dict(n=2, k=1), "mixed_fp32"), (dict(n=2, k=2), "mixed_fp32"), (dict(n=2, k=3), "mixed_fp32")]
+
+
+@pytest.mark.parametrize("kw,prec", GLM_CASES)
+def test_stage_parity_glm_maxwell(kw, prec):
+    """GLM-Maxwell (section 5.2 with the multiplier phi of section 5.1.2, eliminated locally
+    through the signed factorisation of the Schur block): H, E, phi and the trace against the
+    oracle's (dmax1)-(dmax3) system; FP64 also the element Schur complements and local solves."""
+    _need_gpu()
+    ohdg = _oracle()
+    p = make_problem(5, **kw)
+    p.physics = "maxwell_glm"
+    print(f"case glm {kw} {prec} n_elem={p.n_elem}", flush=True)
+    d = ohdg.make_discretisation(p)
+    a = 1.0 / (0.43586652150845899 * p.dt)
+    f = random_vector(d.loc_off[-1], 5, 7)
+    lb = random_vector(d.tr_off[-1], 5, 8) * ohdg.boundary_trace_mask(d)
+    u_ref, lam_ref, cond = ohdg.solve_stage(d, a, f, lb)
+    kws = dict(krylov_tol=1e-13) if prec == "fp64" else dict(krylov_tol=1e-9, refine_tol=1e-12)
+    s = _solver(p, precision=prec, **kws)
+    assert s.query("m_local") == 7
+    u, lam, it, rr = _gpu_stage(s, a, f, lb)
+    tol = 1e-12 if prec == "fp64" else 1e-10
+    errs = _rel_field_errors(ohdg, d, u, u_ref)
+    assert max(errs) <= tol, errs
+    assert np.linalg.norm(lam - lam_ref) <= tol * np.linalg.norm(lam_ref)
+    if prec == "fp64":
+        t = cond.Ke[0].shape[0]
+        ne = p.n_elem
+        ns, r0 = _schur_rows(d)
+        Ke = s.element_data("K", 0, ne, t * t).reshape(ne, t, t)
+        Z = s.element_data("Z", 0, ne, ns * t).reshape(ne, ns, t)
+        z = s.element_data("z", 0, ne, ns).reshape(ne, ns)
+        for e in range(0, ne, max(1, ne // 11)):
+            assert np.abs(Ke[e] - cond.Ke[e]).max() <= 1e-11 * np.abs(cond.Ke[e]).max()
+            Zr, zr = cond.Z[e][r0:r0 + ns], cond.z[e][r0:r0 + ns, 0]
+            assert np.abs(Z[e] - Zr).max() <= 1e-11 * np.abs(Zr).max()
+            assert np.abs(z[e] - zr).max() <= 1e-11 * np.abs(zr).max()
+    else:
+        assert np.all(s.last_residual() <= 1e-12)
     s.close()
