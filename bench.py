@@ -94,11 +94,11 @@ def general_counts(phys, k, kf, R, elt_bytes, mixed):
     ids and orientations (Maxwell: face frames) and writes K_e (full), r_e, the Schur rows of Z,
     z and, in mixed precision, the Schur block's factor; the recovery reads Z, z, the element's
     traces and its geometry and writes u.  Reference tables hit the caches."""
-    m_local, m_trace = {0: 4, 1: 9, 2: 6}[phys], {0: 1, 1: 3, 2: 2}[phys]
+    m_local, m_trace = {0: 4, 1: 9, 2: 6, 3: 7}[phys], {0: 1, 1: 3, 2: 2, 3: 2}[phys]
     N, NF = dimp(k, 3), dimp(kf, 2)
     n, t = m_local * N, 4 * m_trace * NF
-    ns = N if phys == 0 else 3 * N
-    geo = 32 * 8 + 2 * 4 * 4 + (24 * 8 if phys == 2 else 0)
+    ns = {0: N, 1: 3 * N, 2: 3 * N, 3: 4 * N}[phys]
+    geo = 32 * 8 + 2 * 4 * 4 + (24 * 8 if phys >= 2 else 0)
     cond = n * R * 8 + geo + (t * t + t * R + ns * t + n * R + (ns * ns if mixed else 0)) * elt_bytes
     rec = (ns * t + n * R) * elt_bytes + t * R * 8 + geo + n * R * 8
     return cond, rec
@@ -385,7 +385,7 @@ def run_cached(p, prec, steps, warmup):
     return out
 
 
-def run_workload(cfg, prec, steps, warmup):
+def run_workload(cfg, prec, steps, warmup, physics=None):
     """Element-kernel throughput of one of the other workloads at full size (secondary figures,
     not the headline): elastic k = 4 (3), p-heterogeneous acoustics with 32 point-source
     right-hand sides (4), Maxwell k = 3 (5).  Seeded random stage right-hand side (point
@@ -396,6 +396,8 @@ def run_workload(cfg, prec, steps, warmup):
     from paper_1807_00086_amd import Solver
     from synth import make_problem, random_vector
     p = make_problem(cfg)
+    if physics is not None:
+        p.physics = physics
     a = 1.0 / (GAMMA * p.dt) if p.scheme == "dirk33" else 1.0 / p.dt
     kw = dict(krylov_tol=1e-10, krylov_maxit=20000)
     if prec != "fp64":
@@ -441,7 +443,7 @@ def run_workload(cfg, prec, steps, warmup):
                schedules=schedules,
                elements_per_s=p.n_elem / ((out["condense"] + out["recover"] + out["refine_elem"]) * 1e-3))
     # rooflines of the two element kernels (HBM, algorithmic bytes summed over the elements)
-    phys = {"acoustic": 0, "elastic": 1, "maxwell": 2}[p.physics]
+    phys = {"acoustic": 0, "elastic": 1, "maxwell": 2, "maxwell_glm": 3}[p.physics]
     eb = 8 if prec == "fp64" else 4
     cb = rb = 0.0
     for kk, cnt in zip(*np.unique(p.degree, return_counts=True)):
@@ -606,10 +608,12 @@ def main():
     if not args.no_workloads:
         # the other workloads at full size, element kernels of one stage (secondary figures)
         out["other_workloads"] = {}
-        for cfg in (3, 4, 5):
-            for pr in ("fp64", "mixed_fp32"):
-                out["other_workloads"][f"{cfg}_{pr}"] = w = run_workload(cfg, pr, 2, 1)
-                print(f"workload {cfg} {pr}: {w['elements_per_s']:.4g} elements/s", file=sys.stderr, flush=True)
+        both, three = ("fp64", "mixed_fp32"), ("fp64", "mixed_fp32", "mixed_bf16")
+        for cfg, phys, precs_w in ((3, None, three), (4, None, both), (5, None, three), (5, "maxwell_glm", three)):
+            for pr in precs_w:
+                key = f"{cfg}{'_glm' if phys else ''}_{pr}"
+                out["other_workloads"][key] = w = run_workload(cfg, pr, 2, 1, physics=phys)
+                print(f"workload {key}: {w['elements_per_s']:.4g} elements/s", file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, a, args.cpu_budget)
         out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(a, budget_s=min(args.cpu_budget, 10.0))

@@ -67,7 +67,12 @@ enum {
 enum hdg_physics { HDG_ACOUSTIC = 0, HDG_ELASTIC = 1, HDG_MAXWELL = 2, HDG_MAXWELL_GLM = 3 };
 enum hdg_precision {
     HDG_FP64 = 0,          /* local factorisations, Z and K_e in FP64                       */
-    HDG_MIXED_FP32 = 1     /* local factorisations, Z and K_e in FP32, FP64 refinement      */
+    HDG_MIXED_FP32 = 1,    /* local factorisations, Z and K_e in FP32, FP64 refinement      */
+    HDG_MIXED_BF16 = 2     /* as MIXED_FP32, with the matrix-core products of the local
+                              condensation (B~2, the triangular-solve updates, K_e) as
+                              split-BF16 products on the BF16 matrix cores (FP32 accumulation);
+                              the Schur factorisation stays FP32.  Elastic, Maxwell and
+                              GLM-Maxwell (uniform degree, one rhs)                         */
 };
 enum hdg_scheme { HDG_BACKWARD_EULER = 0, HDG_DIRK33 = 1 };
 

@@ -179,6 +179,8 @@ int check_status(hdg_ctx* c) {
 }
 
 bool supported(hdg_ctx* c) {
+    // split-BF16 products: the block-structured kernels of elastic and (GLM-)Maxwell only
+    if (c->precision == HDG_MIXED_BF16 && (c->physics == HDG_ACOUSTIC || c->vardeg || c->nrhs != 1)) return false;
     if (c->vardeg) {
         for (int k = 1; k <= 5; ++k)
             if (c->cls_n[k] && !general_supported(HDG_ACOUSTIC, k, var_face_degree(), c->nrhs)) return false;
@@ -212,7 +214,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     if (p->physics < 0 || p->physics > 3) return fail(nullptr, HDG_E_ARG, "unknown physics");
     if (p->physics != HDG_ACOUSTIC && m->dim != 3) return fail(nullptr, HDG_E_ARG, "elastic/maxwell need dim 3");
     if (!p->elem_par) return fail(nullptr, HDG_E_ARG, "null elem_par");
-    if (o->precision != HDG_FP64 && o->precision != HDG_MIXED_FP32)
+    if (o->precision != HDG_FP64 && o->precision != HDG_MIXED_FP32 && o->precision != HDG_MIXED_BF16)
         return fail(nullptr, HDG_E_ARG, "unknown precision");
     if (o->nrhs < 1 || o->nrhs > 32) return fail(nullptr, HDG_E_ARG, "nrhs must be in 1..32");
     if (!(p->stab_scale > 0)) return fail(nullptr, HDG_E_ARG, "stab_scale must be positive");
@@ -369,12 +371,12 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(dalloc(c, (char**)&c->d_re, ne * c->n_tr * R * tsz));
     TRY(dalloc(c, (char**)&c->d_Zt, ne * c->n_tr * c->Ns * tsz));
     TRY(dalloc(c, (char**)&c->d_z, ne * c->n_loc * R * tsz));
-    if (c->precision == HDG_MIXED_FP32 || (c->cache_factors && c->fast_ac))
+    if (c->precision != HDG_FP64 || (c->cache_factors && c->fast_ac))
         TRY(dalloc(c, (char**)&c->d_LU, ne * c->Ns * c->Ns * tsz));
     TRY(dalloc(c, &c->d_status, 1));
     const int64_t ntr = c->n_trace_dofs;
     TRY(dalloc(c, &c->d_bsr, c->n_faces * c->nslot * c->bs * c->bs));
-    if (c->precision == HDG_MIXED_FP32 && (R == 1 || R == 32) && c->nslot == 7)
+    if (c->precision != HDG_FP64 && (R == 1 || R == 32) && c->nslot == 7)
         TRY(dalloc(c, &c->d_bsr32, c->n_faces * c->nslot * c->bs * c->bs));
     TRY(dalloc(c, &c->d_rhs, ntr * R));
     TRY(dalloc(c, &c->d_pinv, c->n_faces * c->bs * c->bs));
@@ -386,7 +388,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(dalloc(c, &c->d_red, (int64_t)RED_MAX * 32));
     TRY(dalloc(c, &c->d_scal, 8 * 32));
     const int64_t nl = c->n_local_dofs * R;
-    if (c->precision == HDG_MIXED_FP32) {
+    if (c->precision != HDG_FP64) {
         TRY(dalloc(c, &c->d_f_saved, nl));
         TRY(dalloc(c, &c->d_lbnd_saved, ntr * R));
         TRY(dalloc(c, &c->d_du, nl));
@@ -484,7 +486,7 @@ hdg_status hdg_condense(hdg_ctx* c, double a, const double* f_loc, const double*
     if (!(a > 0) || !std::isfinite(a)) return fail(c, HDG_E_ARG, "stage coefficient must be positive");
     HIPCHK(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
     const int64_t R = c->nrhs;
-    if (c->precision == HDG_MIXED_FP32) {   // kept for the FP64 refinement residuals
+    if (c->precision != HDG_FP64) {   // kept for the FP64 refinement residuals
         HIPCHK(hipMemcpyAsync(c->d_f_saved, f_loc, c->n_local_dofs * R * sizeof(double),
                               hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(c->d_lbnd_saved, lam_bnd, c->n_trace_dofs * R * sizeof(double),
@@ -518,7 +520,7 @@ hdg_status hdg_condense_rhs(hdg_ctx* c, double a, const double* f_loc, const dou
         return fail(c, HDG_E_STATE, "hdg_condense_rhs needs the factors of an earlier hdg_condense (FP64: cache_factors)");
     if (a != c->last_a) return fail(c, HDG_E_STATE, "hdg_condense_rhs: stage coefficient differs from the factored one");
     const int64_t R = c->nrhs;
-    if (c->precision == HDG_MIXED_FP32) {   // kept for the FP64 refinement residuals
+    if (c->precision != HDG_FP64) {   // kept for the FP64 refinement residuals
         HIPCHK(hipMemcpyAsync(c->d_f_saved, f_loc, c->n_local_dofs * R * sizeof(double),
                               hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(hipMemcpyAsync(c->d_lbnd_saved, lam_bnd, c->n_trace_dofs * R * sizeof(double),
@@ -719,7 +721,7 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
     c->has_resid = false;
     c->tim.refine_elem = 0.f;
     c->tim.refine_solve = 0.f;
-    if (c->precision == HDG_MIXED_FP32 && c->fast_ac) return recover_refine_acoustic(c, lambda, u);
+    if (c->precision != HDG_FP64 && c->fast_ac) return recover_refine_acoustic(c, lambda, u);
     int e;
     {
         EventTimer t(c, &c->tim.recover);
@@ -727,7 +729,7 @@ hdg_status hdg_recover(hdg_ctx* c, double* lambda, double* u) {
                        : launch_recover_any(c, lambda, u);
     }
     if (e) return fail(c, HDG_E_HIP, "recovery kernel launch failed");
-    if (c->precision != HDG_MIXED_FP32) return HDG_OK;
+    if (c->precision == HDG_FP64) return HDG_OK;
 
     // Iterative refinement of the full stage system (see above), element work in separate passes:
     // residual (and correction right-hand side), trace solve, recovery of the correction.

@@ -323,8 +323,10 @@ constexpr int64_t gen_gstride(int SG) {
 }
 
 // TBL: the Sr tables staged in LDS once per workgroup (true) or read through L1/L2 (false, which
-// leaves more LDS for workgroups per CU).
-template <int PHYS, int K, int KF, int R, typename T, int SG, bool TBL>
+// leaves more LDS for workgroups per CU).  BF (T = float): the matrix-core products (B~2 tiles,
+// the strip updates of the triangular solves, the K_e tiles) run as split-BF16 products on the
+// BF16 matrix cores with FP32 accumulation (bf16x3_mac16); the factorisation stays FP32.
+template <int PHYS, int K, int KF, int R, typename T, int SG, bool TBL, bool BF = false>
 __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void condense_general_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
     const int32_t* __restrict__ eperm, const T* __restrict__ Sr, const T* __restrict__ Mf,
@@ -422,12 +424,26 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                     const T* A2 = &Srs[(2 * N + ia) * N];
                     const T* Bc = &El[f * N * NF + lb];
                     typename MF::acc acc = MF::zero();
+                    if constexpr (BF) {
+                        for (int j0 = 0; j0 < N; j0 += 16) {
+                            float av[4], bv[4];
+    #pragma unroll
+                            for (int t4 = 0; t4 < 4; ++t4) {
+                                const int j = j0 + 4 * lk + t4, jc = min(j, N - 1);
+                                const T v = c0 * A0[jc] + c1 * A1[jc] + c2 * A2[jc] + (ia == j ? b2 : T(0));
+                                av[t4] = j < N ? v : T(0);
+                                bv[t4] = j < N ? Bc[jc * NF] : T(0);
+                            }
+                            acc = bf16x3_mac16(av, bv, acc);
+                        }
+                    } else {
     #pragma unroll 4
-                    for (int j0 = 0; j0 < N; j0 += 4) {
-                        const int j = j0 + lk, jc = min(j, N - 1);
-                        T av = c0 * A0[jc] + c1 * A1[jc] + c2 * A2[jc] + (ia == j ? b2 : T(0));
-                        av = j < N ? av : T(0);
-                        acc = MF::mac(av, Bc[jc * NF], acc);
+                        for (int j0 = 0; j0 < N; j0 += 4) {
+                            const int j = j0 + lk, jc = min(j, N - 1);
+                            T av = c0 * A0[jc] + c1 * A1[jc] + c2 * A2[jc] + (ia == j ? b2 : T(0));
+                            av = j < N ? av : T(0);
+                            acc = MF::mac(av, Bc[jc * NF], acc);
+                        }
                     }
                     const T sf = (T)geo[1 + D * D + f];
                     const int l = lt * 16 + li;
@@ -640,6 +656,37 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
         constexpr int SW = 4, NCS = (NCT + SW - 1) / SW;
         auto strip_update = [&](int i0, int ct0, int r0) {
             const int ia = min(i0 + li, N2 - 1);
+            if constexpr (BF) {   // the k-range of 16 rows as one split-BF16 product per tile
+                float av[4];
+#pragma unroll
+                for (int t4 = 0; t4 < 4; ++t4) {
+                    const int kr = r0 + 4 * lk + t4;
+                    av[t4] = kr < N2 ? -Sb[ia * N2 + kr] : T(0);
+                }
+                typename MF::acc acc[SW];
+                float bv[SW][4];
+#pragma unroll
+                for (int u = 0; u < SW; ++u) {
+                    const int cb = min((ct0 + u) * 16 + li, C - 1);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[u][v] = X[min(i0 + MF::row(lane, v), N2 - 1) * C + cb];
+#pragma unroll
+                    for (int t4 = 0; t4 < 4; ++t4) bv[u][t4] = X[min(r0 + 4 * lk + t4, N2 - 1) * C + cb];
+                }
+#pragma unroll
+                for (int u = 0; u < SW; ++u) acc[u] = bf16x3_mac16(av, bv[u], acc[u]);
+#pragma unroll
+                for (int u = 0; u < SW; ++u) {
+                    const int c = (ct0 + u) * 16 + li;
+                    if (ct0 + u < NCT && c < C)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = i0 + MF::row(lane, v);
+                            if (i < N2) X[i * C + c] = acc[u][v];
+                        }
+                }
+                return;
+            }
             T av[BR / 4];
 #pragma unroll
             for (int k = 0; k < BR / 4; ++k) {
@@ -713,6 +760,31 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                 const int a0 = ta * 16, b0 = tb * 16;
                 const int ca = min(a0 + li, TT - 1), cb = min(b0 + li, TT - 1);
                 typename MF::acc w0 = MF::zero(), w1 = MF::zero(), ee = MF::zero();
+                if constexpr (BF) {
+                    for (int k0 = 0; k0 < N2; k0 += 16) {
+                        float av[4], bv[4];
+#pragma unroll
+                        for (int t4 = 0; t4 < 4; ++t4) {
+                            const int r = k0 + 4 * lk + t4, rc = min(r, N2 - 1);
+                            T x = r < N2 ? X[rc * C + ca] : T(0);
+                            if constexpr (PHYS == PH_GLM) x *= sgn[rc];
+                            av[t4] = x;
+                            bv[t4] = X[rc * C + cb];
+                        }
+                        w0 = bf16x3_mac16(av, bv, w0);
+                    }
+                    const int fa = ca / NF / MT, la = ca % NF, fb = cb / NF / MT, lb = cb % NF;
+                    for (int k0 = 0; k0 < N; k0 += 16) {
+                        float av[4], bv[4];
+#pragma unroll
+                        for (int t4 = 0; t4 < 4; ++t4) {
+                            const int i = k0 + 4 * lk + t4, ic = min(i, N - 1);
+                            av[t4] = i < N ? El[(fa * N + ic) * NF + la] : T(0);
+                            bv[t4] = El[(fb * N + ic) * NF + lb];
+                        }
+                        ee = bf16x3_mac16(av, bv, ee);
+                    }
+                } else {
 #pragma unroll 2
                 for (int k0 = 0; k0 < N2; k0 += 8) {
                     const int r = k0 + lk, r2 = k0 + 4 + lk;
@@ -732,6 +804,7 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
                     const int i = k0 + lk, ic = min(i, N - 1);
                     const T av = i < N ? El[(fa * N + ic) * NF + la] : T(0);
                     ee = MF::mac(av, El[(fb * N + ic) * NF + lb], ee);
+                }
                 }
                 const int bb = b0 + li;
                 if (bb < TT) {
@@ -1291,27 +1364,27 @@ size_t gen_scratch(int64_t n, int sched) {
     return (size_t)gen_grid<PHYS, K, KF, R>(n) * gen_gstride<PHYS, K, KF, R>(gen_sg<PHYS, K, KF, R, T>(sched)) * sizeof(T);
 }
 
-template <int PHYS, int K, int KF, int R, typename T, int SG, bool TBL>
+template <int PHYS, int K, int KF, int R, typename T, int SG, bool TBL, bool BF>
 int launch_gen_sg(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist,
                   int64_t n, T* scratch, hipStream_t st) {
     using TB = TabOf<T>;
-    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, KF, R, T, SG, TBL>), dim3(gen_grid<PHYS, K, KF, R>(n)),
+    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, KF, R, T, SG, TBL, BF>), dim3(gen_grid<PHYS, K, KF, R>(n)),
                        dim3(NTG), 0, st, n, a, c->d_geom, c->d_eframe, c->d_eperm, TB::Sr(tb), TB::Mf(tb), TB::Tf(tb),
                        TB::Ef(tb), f_loc, (T*)c->d_Ke, (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
-                       c->precision == HDG_MIXED_FP32 ? (T*)c->d_LU : (T*)nullptr, scratch, c->d_status,
+                       c->precision != HDG_FP64 ? (T*)c->d_LU : (T*)nullptr, scratch, c->d_status,
                        var_args(c, elist));
     return (int)hipGetLastError();
 }
 
 // schedule `sched` (0..2) of a class; a schedule that is not built falls back to 0
-template <int PHYS, int K, int KF, int R, typename T>
+template <int PHYS, int K, int KF, int R, typename T, bool BF>
 int launch_gen(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist, int64_t n,
                int sched, T* scratch, hipStream_t st) {
     constexpr int S0 = gen_sg<PHYS, K, KF, R, T>(0), S1 = gen_sg<PHYS, K, KF, R, T>(1), S2 = gen_sg<PHYS, K, KF, R, T>(2);
     if constexpr (gen_built<PHYS, K, KF, R, T>(1))
-        if (sched == 1) return launch_gen_sg<PHYS, K, KF, R, T, S1, true>(c, a, f_loc, tb, elist, n, scratch, st);
-    if (sched == 2) return launch_gen_sg<PHYS, K, KF, R, T, S2, false>(c, a, f_loc, tb, elist, n, scratch, st);
-    return launch_gen_sg<PHYS, K, KF, R, T, S0, true>(c, a, f_loc, tb, elist, n, scratch, st);
+        if (sched == 1) return launch_gen_sg<PHYS, K, KF, R, T, S1, true, BF>(c, a, f_loc, tb, elist, n, scratch, st);
+    if (sched == 2) return launch_gen_sg<PHYS, K, KF, R, T, S2, false, BF>(c, a, f_loc, tb, elist, n, scratch, st);
+    return launch_gen_sg<PHYS, K, KF, R, T, S0, true, BF>(c, a, f_loc, tb, elist, n, scratch, st);
 }
 
 template <int PHYS, int K, int KF, int R, typename T>
@@ -1383,7 +1456,8 @@ struct GenOp {
     size_t out = 0;
 };
 
-template <typename T>
+// BF: the split-BF16 matrix-core products (float only; elastic, Maxwell, GLM-Maxwell)
+template <typename T, bool BF = false>
 int gen_class(hdg_ctx* c, int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n, GenOp& g) {
     const int P = c->physics, R = c->nrhs;
 #define HDG_CASE(PP, KK, FF, RR)                                                                        \
@@ -1397,7 +1471,8 @@ int gen_class(hdg_ctx* c, int K, int KF, const DeviceTables& tb, const int32_t* 
                               gen_scratch<PP, KK, FF, RR, T>(n, 2)});                                    \
             return 0;                                                                                    \
         }                                                                                                \
-        return launch_gen<PP, KK, FF, RR, T>(c, g.a, g.f_loc, tb, el, n, g.sched, (T*)g.scratch, g.st);   \
+        if constexpr (BF && (PP == 0 || sizeof(T) != 4)) return -1;                                     \
+        else return launch_gen<PP, KK, FF, RR, T, BF>(c, g.a, g.f_loc, tb, el, n, g.sched, (T*)g.scratch, g.st); \
     }
     HDG_GEN_CASES(HDG_CASE)
 #undef HDG_CASE
@@ -1422,14 +1497,14 @@ std::vector<std::pair<int, ClassRef>> gen_classes(hdg_ctx* c) {
     return v;
 }
 
-template <typename T>
+template <typename T, bool BF>
 int gen_run(hdg_ctx* c, const ClassRef& cr, int k, GenOp g) {
     g.op = 0;
     g.scratch = (char*)c->d_xscratch + c->xs_off[k];
-    return gen_class<T>(c, cr.K, cr.KF, *cr.tb, cr.el, cr.n, g);
+    return gen_class<T, BF>(c, cr.K, cr.KF, *cr.tb, cr.el, cr.n, g);
 }
 
-template <typename T>
+template <typename T, bool BF = false>
 int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
     const int pi = c->precision == HDG_FP64 ? 1 : 0;
     auto classes = gen_classes(c);
@@ -1496,7 +1571,7 @@ int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
             for (int rep = 0; rep < 2 && !err; ++rep) {   // the first run warms caches and code
                 g.sched = s;
                 err = hipEventRecord(t0, c->stream);
-                if (!err) err = gen_run<T>(c, cr, k, g);
+                if (!err) err = gen_run<T, BF>(c, cr, k, g);
                 if (!err) err = hipEventRecord(t1, c->stream);
                 if (!err) err = hipEventSynchronize(t1);
                 if (!err) err = hipEventElapsedTime(&t, t0, t1);
@@ -1521,7 +1596,7 @@ int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
     if (!c->use_graph || !c->vardeg || !c->side[0]) {
         for (auto& [k, cr] : classes) {
             g.sched = c->sched[pi][k];
-            const int e = gen_run<T>(c, cr, k, g);
+            const int e = gen_run<T, BF>(c, cr, k, g);
             if (e) return e;
         }
         return 0;
@@ -1541,7 +1616,7 @@ int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
             if (!err) err = hipStreamWaitEvent(si, c->ev_fork, 0);
             g.st = si;
             g.sched = c->sched[pi][k];
-            if (!err) err = gen_run<T>(c, cr, k, g);
+            if (!err) err = gen_run<T, BF>(c, cr, k, g);
             if (!err) err = hipEventRecord(c->ev_join[i], si);
             if (!err) err = hipStreamWaitEvent(s0, c->ev_join[i], 0);
             ++i;
@@ -1596,7 +1671,7 @@ int dispatch_gen_ref(hdg_ctx* c, const double* u, const double* lam, bool chk, d
 }  // namespace
 
 int launch_refine_general(hdg_ctx* c, const double* u, const double* lam, bool check, double* nrm) {
-    if (c->precision != HDG_MIXED_FP32 || (check && !nrm)) return -1;
+    if (c->precision == HDG_FP64 || (check && !nrm)) return -1;
     if (mr_supported(c)) return launch_refine_mr(c, u, lam, check, nrm);
     return dispatch_gen_ref(c, u, lam, check, nrm);
 }
@@ -1614,6 +1689,7 @@ int var_face_degree() { return VAR_KF; }
 
 int launch_condense_general(hdg_ctx* c, double a, const double* f_loc) {
     if (c->precision == HDG_FP64) return dispatch_gen<double>(c, a, f_loc);
+    if (c->precision == HDG_MIXED_BF16) return dispatch_gen<float, true>(c, a, f_loc);
     return dispatch_gen<float>(c, a, f_loc);
 }
 

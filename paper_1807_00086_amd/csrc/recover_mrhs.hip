@@ -733,7 +733,7 @@ int launch_recover_mr(hdg_ctx* c, const double* lam, double* u) {
 }
 
 int launch_refine_mr(hdg_ctx* c, const double* u, const double* lam, bool check, double* nrm) {
-    if (c->precision != HDG_MIXED_FP32 || (check && !nrm)) return -1;
+    if (c->precision == HDG_FP64 || (check && !nrm)) return -1;
     return mr_for_each_class(c, [&](int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n) {
 #define HDG_CASE(KK, FF)                                                        \
     if (K == KK && KF == FF)                                                    \

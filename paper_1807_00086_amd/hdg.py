@@ -16,10 +16,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhdg.so")
 
 ACOUSTIC, ELASTIC, MAXWELL, MAXWELL_GLM = 0, 1, 2, 3
-FP64, MIXED_FP32 = 0, 1
+FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
 BACKWARD_EULER, DIRK33 = 0, 1
 PHYSICS = {"acoustic": ACOUSTIC, "elastic": ELASTIC, "maxwell": MAXWELL, "maxwell_glm": MAXWELL_GLM}
-PRECISION = {"fp64": FP64, "mixed_fp32": MIXED_FP32}
+PRECISION = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
 STATUS = {0: "HDG_OK", 1: "HDG_E_ARG", 2: "HDG_E_MESH", 3: "HDG_E_ALLOC", 4: "HDG_E_HIP",
           5: "HDG_E_SINGULAR", 6: "HDG_E_NOCONV", 7: "HDG_E_STATE", 8: "HDG_E_UNSUPPORTED"}
 Q = dict(n_elem=0, n_faces=1, n_bfaces=2, n_local_dofs=3, n_trace_dofs=4, n_vol_points=5,

@@ -246,3 +246,36 @@ def test_full_size_pvar_mixed_sampled():
     # below the scale the residual test controls)
     faces = np.unique(np.concatenate([list(d.skel.elem_faces[e]) for e in src_elems[:40]]))
     _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, tmap, 0, 0, 4, faces=faces, elems=[])
+
+
+def test_full_size_elastic_bf16_equals_fp64():
+    """Elastic k = 4 at full size (24,576 tets) with split-BF16 condensation products and FP64
+    refinement: within 1e-10 of the FP64 path per field (the FP64 path is checked against the
+    oracle above), residual at or below refine_tol."""
+    _need_gpu()
+    _T0[0] = time.time()
+    p = make_problem(3)
+    print(f"case fullsize elastic bf16 n_elem={p.n_elem}", flush=True)
+    a = 1.0 / (GAMMA * p.dt)
+    s = _solver(p, "fp64", krylov_tol=1e-12, krylov_maxit=4000)
+    nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+    f = random_vector(nl, 3, 11)[:, None]
+    from oracle import hdg as ohdg
+    d = ohdg.make_discretisation(p)
+    lb = (random_vector(nt, 3, 12) * ohdg.boundary_trace_mask(d))[:, None]
+    u, lam, _ = _stage(s, a, f, lb)
+    s.close()
+    sb = _solver(p, "mixed_bf16", krylov_tol=1e-12, krylov_maxit=4000, refine_tol=1e-11)
+    ub, lamb, _ = _stage(sb, a, f, lb)
+    res = sb.last_residual()
+    _step(f"bf16 stage done ({sb.query('last_refine')} corrections, residual {res[0]:.2e})")
+    sb.close()
+    assert np.all(res <= 1e-11)
+    X = p.xyz[p.elem_vert]
+    dj = np.abs(np.linalg.det(np.transpose(X[:, 1:, :] - X[:, :1, :], (0, 2, 1))))[:, None, None]
+    uf, ubf = u[:, 0].reshape(p.n_elem, 9, -1), ub[:, 0].reshape(p.n_elem, 9, -1)
+    for g in (list(range(6)), [6, 7, 8]):
+        num = np.sqrt(np.sum(dj * (ubf[:, g] - uf[:, g]) ** 2))
+        den = np.sqrt(np.sum(dj * uf[:, g] ** 2))
+        assert num <= 1e-10 * den, (g, num / den)
+    assert np.linalg.norm(lamb - lam) <= 1e-10 * np.linalg.norm(lam)

@@ -412,3 +412,36 @@ def test_stage_parity_glm_maxwell(kw, prec):
     else:
         assert np.all(s.last_residual() <= 1e-12)
     s.close()
+
+
+BF16_CASES = [(3, dict(n=1, k=2), "elastic"), (3, dict(n=1, k=3), "elastic"), (3, dict(n=1, k=4), "elastic"),
+              (5, dict(n=2, k=2), "maxwell"), (5, dict(n=2, k=3), "maxwell"), (5, dict(n=2, k=2), "maxwell_glm")]
+
+
+@pytest.mark.parametrize("cfg,kw,phys", BF16_CASES)
+def test_stage_parity_mixed_bf16(cfg, kw, phys):
+    """Split-BF16 matrix-core products in the condensation + FP64 refinement: the refined stage
+    reaches the FP64 oracle to 1e-10 per field, while the BF16 Schur complements themselves are
+    visibly less accurate than the FP32 ones (so the BF16 products are the ones that ran)."""
+    _need_gpu()
+    ohdg = _oracle()
+    p = make_problem(cfg, **kw)
+    p.physics = phys
+    print(f"case bf16 {phys} {kw} n_elem={p.n_elem}", flush=True)
+    d = ohdg.make_discretisation(p)
+    a = 1.0 / (0.43586652150845899 * p.dt)
+    f = random_vector(d.loc_off[-1], cfg, 9)
+    lb = random_vector(d.tr_off[-1], cfg, 10) * ohdg.boundary_trace_mask(d)
+    u_ref, lam_ref, cond = ohdg.solve_stage(d, a, f, lb)
+    s = _solver(p, precision="mixed_bf16", krylov_tol=1e-9, refine_tol=1e-12)
+    u, lam, it, rr = _gpu_stage(s, a, f, lb)
+    errs = _rel_field_errors(ohdg, d, u, u_ref)
+    print(f"  corrections {s.query('last_refine')}, residual {s.last_residual()[0]:.2e}, errors {errs}", flush=True)
+    assert max(errs) <= 1e-10, errs
+    assert np.linalg.norm(lam - lam_ref) <= 1e-10 * np.linalg.norm(lam_ref)
+    assert np.all(s.last_residual() <= 1e-12)
+    t = cond.Ke[0].shape[0]
+    Ke = s.element_data("K", 0, 1, t * t).reshape(t, t)
+    rel = np.abs(Ke - cond.Ke[0]).max() / np.abs(cond.Ke[0]).max()
+    assert 1e-7 < rel < 1e-2, rel
+    s.close()
