@@ -111,9 +111,9 @@ typedef struct {
     int cache_factors;          /* nonzero: keep the factors of every condensation so that
                                    hdg_condense_rhs (and hdg_step, whose stages share one
                                    stage coefficient) can condense a new right-hand side
-                                   without refactoring.  Acoustic fast path (uniform degree,
-                                   one rhs); costs n_s^2 values per element in FP64 (the
-                                   mixed-precision path keeps them anyway)                   */
+                                   without refactoring (one rhs, every physics); costs n_s^2
+                                   values per element in FP64 (the mixed-precision paths keep
+                                   them anyway)                                              */
     int autotune;               /* nonzero: the first hdg_condense of each degree class of the
                                    block-structured kernels (elastic, Maxwell, acoustics of
                                    variable degree or with 32 rhs) times every launch schedule
@@ -201,8 +201,8 @@ hdg_status hdg_condense(hdg_ctx* ctx, double a, const double* f_loc, const doubl
  *   f_loc    device [n_local_dofs][nrhs] FP64, lam_bnd device [n_trace_dofs][nrhs] FP64,
  *            as for hdg_condense
  * HDG_E_STATE without an earlier hdg_condense at this `a` whose factors were kept
- * (options.cache_factors in FP64; always in mixed precision); HDG_E_UNSUPPORTED outside the
- * acoustic fast path (uniform degree, one right-hand side).  Asynchronous.
+ * (options.cache_factors in FP64; always in mixed precision); HDG_E_UNSUPPORTED with more than
+ * one right-hand side.  Every physics and meshes of variable degree.  Asynchronous.
  */
 hdg_status hdg_condense_rhs(hdg_ctx* ctx, double a, const double* f_loc, const double* lam_bnd);
 

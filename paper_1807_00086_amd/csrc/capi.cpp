@@ -371,7 +371,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(dalloc(c, (char**)&c->d_re, ne * c->n_tr * R * tsz));
     TRY(dalloc(c, (char**)&c->d_Zt, ne * c->n_tr * c->Ns * tsz));
     TRY(dalloc(c, (char**)&c->d_z, ne * c->n_loc * R * tsz));
-    if (c->precision != HDG_FP64 || (c->cache_factors && c->fast_ac))
+    if (c->precision != HDG_FP64 || c->cache_factors)
         TRY(dalloc(c, (char**)&c->d_LU, ne * c->Ns * c->Ns * tsz));
     TRY(dalloc(c, &c->d_status, 1));
     const int64_t ntr = c->n_trace_dofs;
@@ -508,14 +508,14 @@ hdg_status hdg_condense(hdg_ctx* c, double a, const double* f_loc, const double*
     c->last_a = a;
     c->condensed = true;
     c->z_consumed = false;
-    c->factors_cached = c->fast_ac && c->d_LU != nullptr;
+    c->factors_cached = c->d_LU != nullptr && c->nrhs == 1;
     return HDG_OK;
 }
 
 hdg_status hdg_condense_rhs(hdg_ctx* c, double a, const double* f_loc, const double* lam_bnd) {
     if (!c) return HDG_E_ARG;
     if (!f_loc || !lam_bnd) return fail(c, HDG_E_ARG, "null f_loc or lam_bnd");
-    if (!c->fast_ac) return fail(c, HDG_E_UNSUPPORTED, "right-hand-side condensation: acoustic, uniform degree, one rhs");
+    if (c->nrhs != 1) return fail(c, HDG_E_UNSUPPORTED, "right-hand-side condensation: one right-hand side");
     if (!c->condensed || !c->factors_cached)
         return fail(c, HDG_E_STATE, "hdg_condense_rhs needs the factors of an earlier hdg_condense (FP64: cache_factors)");
     if (a != c->last_a) return fail(c, HDG_E_STATE, "hdg_condense_rhs: stage coefficient differs from the factored one");
@@ -529,7 +529,7 @@ hdg_status hdg_condense_rhs(hdg_ctx* c, double a, const double* f_loc, const dou
     int e;
     {
         EventTimer t(c, &c->tim.condense);
-        e = launch_condense_rhs_acoustic(c, a, f_loc);
+        e = c->fast_ac ? launch_condense_rhs_acoustic(c, a, f_loc) : launch_condense_rhs_general(c, f_loc);
     }
     if (e) return fail(c, HDG_E_HIP, "right-hand-side condensation launch failed");
     {

@@ -1031,7 +1031,7 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
     const double* __restrict__ Mf, const double* __restrict__ Ef, const T* __restrict__ Zs,
     const T* __restrict__ Lst, const double* __restrict__ u, const double* __restrict__ lam,
     const double* __restrict__ f, T* __restrict__ zout, double* __restrict__ re64, double* __restrict__ nrm,
-    VarArgs va) {
+    int zero_state, VarArgs va) {
     using Dm = GDims<PHYS, K, KF, R>;
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, NPERM = Dm::NPERM, D = Dm::D;
     constexpr int M1 = Dm::M1, M2 = Dm::M2, MT = Dm::MT, N1 = Dm::N1, N2 = Dm::N2, NLOC = Dm::NLOC;
@@ -1096,13 +1096,13 @@ __global__ __launch_bounds__(64 * WPB) void refine_general_kernel(
 #pragma unroll 1
         for (int q = 0; q < R; ++q) {
             for (int idx = lane; idx < NLOC; idx += 64) {
-                sc.uu[idx] = u[loc + (int64_t)idx * R + q];
+                sc.uu[idx] = zero_state ? 0.0 : u[loc + (int64_t)idx * R + q];
                 sc.su[idx] = (idx >= N1 ? sc.cf.f2s[(idx - N1) / N] : 1.0) * f[loc + (int64_t)idx * R + q];
             }
             for (int c = lane; c < TT; c += 64) {
                 const int fo = c / (MT * NF), l = c % NF;
                 const int32_t F = eface[e * NFACE + fo];
-                sc.lm[c] = l < sc.nfv[fo] ? lam[((int64_t)F * MT * NF + c % (MT * NF)) * R + q] : 0.0;
+                sc.lm[c] = (l < sc.nfv[fo] && !zero_state) ? lam[((int64_t)F * MT * NF + c % (MT * NF)) * R + q] : 0.0;
             }
             ws();
             // ---- stage 1: E_f lam, Sr^T u2, c-weighted u1, Mf u2
@@ -1371,7 +1371,7 @@ int launch_gen_sg(hdg_ctx* c, double a, const double* f_loc, const DeviceTables&
     hipLaunchKernelGGL((condense_general_kernel<PHYS, K, KF, R, T, SG, TBL, BF>), dim3(gen_grid<PHYS, K, KF, R>(n)),
                        dim3(NTG), 0, st, n, a, c->d_geom, c->d_eframe, c->d_eperm, TB::Sr(tb), TB::Mf(tb), TB::Tf(tb),
                        TB::Ef(tb), f_loc, (T*)c->d_Ke, (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
-                       c->precision != HDG_FP64 ? (T*)c->d_LU : (T*)nullptr, scratch, c->d_status,
+                       (T*)c->d_LU, scratch, c->d_status,
                        var_args(c, elist));
     return (int)hipGetLastError();
 }
@@ -1400,16 +1400,21 @@ int launch_gen_rec(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int
     return (int)hipGetLastError();
 }
 
+// f == nullptr: the saved right-hand side of the stage (refinement); zero_state: u = 0, lam = 0
+// (the residual is then f itself, and the pass condenses the right-hand side f with the kept
+// factors: z into the z buffer, r_e into re_out)
 template <int PHYS, int K, int KF, int R, typename T>
 int launch_gen_ref(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int64_t n, const double* u,
-                   const double* lam, bool chk, double* nrm) {
+                   const double* lam, bool chk, double* nrm, const double* f = nullptr, int zero_state = 0,
+                   double* re_out = nullptr) {
     constexpr int WPB = 1;
     constexpr bool TL = false;   // tables read through L1/L2: more wavefronts per CU than with LDS copies
     const int grid = (int)std::min<int64_t>(n, 256 * 16);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WPB), 0, c->stream, n, c->last_a, c->d_geom, c->d_eframe,
                            c->d_eperm, c->d_eface, tb.Sr, tb.Mf, tb.Ef, (const T*)c->d_Zt, (const T*)c->d_LU, u,
-                           lam, c->d_f_saved, (T*)c->d_z, c->d_re64, nrm, var_args(c, elist));
+                           lam, f ? f : c->d_f_saved, (T*)c->d_z, re_out ? re_out : c->d_re64, nrm, zero_state,
+                           var_args(c, elist));
         return (int)hipGetLastError();
     };
     if (chk) return go(refine_general_kernel<PHYS, K, KF, R, T, WPB, TL, true>);
@@ -1668,7 +1673,40 @@ int dispatch_gen_ref(hdg_ctx* c, const double* u, const double* lam, bool chk, d
     });
 }
 
+__global__ void narrow_kernel(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+// Right-hand-side condensation with the kept factors (one right-hand side): the refinement pass
+// at u = 0, lam = 0 (z = A^{-1} f in the z buffer, r_e = -C A^{-1} f into d_re)
+template <typename T>
+int dispatch_gen_rhs(hdg_ctx* c, const double* f_loc) {
+    const int P = c->physics, R = c->nrhs;
+    double* re_out = sizeof(T) == 8 ? (double*)c->d_re : c->d_re64;
+    int e = for_each_class(c, [&](int K, int KF, const DeviceTables& tb, const int32_t* el, int64_t n) {
+#define HDG_CASE(PP, KK, FF, RR)                                                                              \
+    if (P == PP && K == KK && KF == FF && R == RR)                                                            \
+        return launch_gen_ref<PP, KK, FF, RR, T>(c, tb, el, n, nullptr, nullptr, false, nullptr, f_loc, 1, re_out);
+        HDG_GEN_CASES_R1(HDG_CASE)
+#undef HDG_CASE
+        return -1;
+    });
+    if (e || sizeof(T) == 8) return e;
+    const int64_t nr = c->n_elem * c->n_tr * R;
+    hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, c->stream, nr, c->d_re64,
+                       (float*)c->d_re);
+    return (int)hipGetLastError();
+}
+
 }  // namespace
+
+int launch_condense_rhs_general(hdg_ctx* c, const double* f_loc) {
+    if (!c->d_LU || c->nrhs != 1 || mr_supported(c)) return -1;
+    if (c->precision == HDG_FP64) return dispatch_gen_rhs<double>(c, f_loc);
+    if (!c->d_re64) return -1;
+    return dispatch_gen_rhs<float>(c, f_loc);
+}
 
 int launch_refine_general(hdg_ctx* c, const double* u, const double* lam, bool check, double* nrm) {
     if (c->precision == HDG_FP64 || (check && !nrm)) return -1;

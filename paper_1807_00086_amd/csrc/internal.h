@@ -241,6 +241,10 @@ int launch_recover_general(hdg_ctx* c, const double* lam, double* u);
 // side (re64) and the element part of the correction (z buffer); with `check` only re64 = -t_e
 // and nrm[e][q] = |s| of element e, column q.
 int launch_refine_general(hdg_ctx* c, const double* u, const double* lam, bool check, double* nrm);
+// Right-hand-side condensation with the factors kept by the last condensation (block-structured
+// path, one right-hand side; the factor of the Schur block is kept with options.cache_factors in
+// FP64 and always in mixed precision): z and r_e of f_loc
+int launch_condense_rhs_general(hdg_ctx* c, const double* f_loc);
 // recover_mrhs.hip (acoustic, 3D, 32 right-hand sides: matrix-core recovery and refinement)
 bool mr_supported(const hdg_ctx* c);
 int launch_recover_mr(hdg_ctx* c, const double* lam, double* u);

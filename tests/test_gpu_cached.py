@@ -29,8 +29,9 @@ def _oracle():
 
 def _solver(p, precision="fp64", **kw):
     from paper_1807_00086_amd import Solver
-    return Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=int(p.degree[0]),
-                  precision=precision, nrhs=p.nrhs, **kw)
+    uk = p.uniform_k
+    return Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=uk, degree=None if uk else p.degree,
+                  precision=precision, nrhs=1, **kw)
 
 
 def _dev(x):
@@ -38,7 +39,8 @@ def _dev(x):
 
 
 def _rel_errors(ohdg, d, u_gpu, u_ref):
-    g = [list(range(d.dim)), [d.dim]]
+    g = {"acoustic": [list(range(d.dim)), [d.dim]], "elastic": [list(range(6)), [6, 7, 8]],
+         "maxwell": [[0, 1, 2], [3, 4, 5]], "maxwell_glm": [[0, 1, 2], [3, 4, 5], [6]]}[d.physics]
     return [ohdg.l2_norm_fields(d, u_gpu - u_ref, gi) / ohdg.l2_norm_fields(d, u_ref, gi) for gi in g]
 
 
@@ -48,7 +50,24 @@ CASES = [
     (2, dict(n=2, k=2)),
     (2, dict(n=3, k=3)),            # workload degree, 162 tets
     (2, dict(n=2, k=4)),
+    # block-structured kernels: the kept Schur factor, Z and K_e, the right-hand side condensed
+    # by the refinement's pass at u = 0, lam = 0
+    (3, dict(n=1, k=2)),            # elastic
+    (3, dict(n=1, k=4)),
+    (5, dict(n=2, k=2)),            # Maxwell
+    ("glm", dict(n=2, k=2)),        # GLM-Maxwell
+    (4, dict(nxyz=(2, 2, 1))),      # acoustics of variable degree, one right-hand side
 ]
+
+
+def _problem(cfg, kw):
+    if cfg == "glm":
+        p = make_problem(5, **kw)
+        p.physics = "maxwell_glm"
+        return p, 5
+    p = make_problem(cfg, **kw)
+    p.nrhs = 1
+    return p, cfg
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
@@ -58,8 +77,8 @@ def test_condense_rhs_parity(cfg, kw, precision):
     recover: the stage solution of the second right-hand side, as the oracle computes it."""
     _need_gpu()
     ohdg = _oracle()
-    p = make_problem(cfg, **kw)
-    print(f"case cached {precision} cfg={cfg} {kw} n_elem={p.n_elem}", flush=True)
+    p, cfg = _problem(cfg, kw)
+    print(f"case cached {precision} cfg={cfg} {p.physics} {kw} n_elem={p.n_elem}", flush=True)
     d = ohdg.make_discretisation(p)
     a = 1.0 / (GAMMA * p.dt)
     bm = ohdg.boundary_trace_mask(d)
@@ -69,6 +88,10 @@ def test_condense_rhs_parity(cfg, kw, precision):
     mixed = precision == "mixed_fp32"
     kw_s = dict(krylov_tol=1e-9, refine_tol=1e-12) if mixed else {}
     s = _solver(p, precision, cache_factors=True, **kw_s)
+    var = p.uniform_k is None     # variable degree: trace vectors padded to the degree-5 face space
+    if var:
+        from test_gpu_pvar import _pad, _unpad
+        lb1, lb2 = _pad(d, lb1[:, None])[:, 0], _pad(d, lb2[:, None])[:, 0]
     s.condense(a, _dev(f1), _dev(lb1))
     f2d, lb2d = _dev(f2), _dev(lb2)
     s.condense_rhs(a, f2d, lb2d)
@@ -78,11 +101,13 @@ def test_condense_rhs_parity(cfg, kw, precision):
     s.recover(lam, u)
     torch.cuda.synchronize()
     u, lam = u.cpu().numpy(), lam.cpu().numpy()
+    if var:
+        lam = _unpad(d, lam[:, None])[0][:, 0]
     errs = _rel_errors(ohdg, d, u, u_ref)
     tol = 1e-10 if mixed else 1e-12
     assert max(errs) <= tol, errs
     assert np.linalg.norm(lam - lam_ref) <= tol * np.linalg.norm(lam_ref)
-    if not mixed:
+    if not mixed and p.physics == "acoustic" and p.uniform_k:
         # element-wise right-hand side quantities of the condensation
         t = cond.Ke[0].shape[0]
         ne = p.n_elem
@@ -129,7 +154,7 @@ def test_dirk_step_cached_fp64():
 
 def test_condense_rhs_call_order_errors():
     """HDG_E_STATE (7) without kept factors at this stage coefficient, HDG_E_UNSUPPORTED (8)
-    outside the acoustic fast path; both before any device work."""
+    with 32 right-hand sides; both before any device work."""
     _need_gpu()
     from paper_1807_00086_amd import HDGError
     p = make_problem(2, n=1, k=2)
@@ -151,12 +176,48 @@ def test_condense_rhs_call_order_errors():
         s.condense_rhs(1.0, f, lb)
     assert ei.value.code == 7
     s.close()
-    q = make_problem(3, n=1, k=1)            # elastic: no right-hand-side path
-    s = _solver(q, cache_factors=True)
-    nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+    from paper_1807_00086_amd import Solver   # 32 right-hand sides: no right-hand-side path
+    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=2, nrhs=32, cache_factors=True)
+    nl, nt = s.query("n_local_dofs") * 32, s.query("n_trace_dofs") * 32
     f, lb = _dev(np.ones(nl)), _dev(np.zeros(nt))
     s.condense(1.0, f, lb)
     with pytest.raises(HDGError) as ei:
         s.condense_rhs(1.0, f, lb)
     assert ei.value.code == 8
+    s.close()
+
+
+@pytest.mark.parametrize("cfg,kw", [(3, dict(n=1, k=2)), ("glm", dict(n=2, k=1))])
+@pytest.mark.parametrize("precision", ["fp64", "mixed_fp32"])
+def test_dirk_step_cached_block_structured(cfg, kw, precision):
+    """Two DIRK(3,3) steps with cache_factors on the block-structured path (elastic and
+    GLM-Maxwell): one factorisation per step size, five right-hand-side condensations; same
+    result as the oracle's stage recursion."""
+    _need_gpu()
+    ohdg = _oracle()
+    p, cfgi = _problem(cfg, kw)
+    print(f"case cached dirk {precision} {p.physics} {kw} n_elem={p.n_elem}", flush=True)
+    d = ohdg.make_discretisation(p)
+    u0 = random_vector(d.loc_off[-1], cfgi, 51)
+    bm = ohdg.boundary_trace_mask(d)
+    _, _, c = ohdg.dirk33()
+    dt = 0.01
+    lbs = {}
+    for n in range(2):
+        for i in range(3):
+            lbs[round(n * dt + c[i] * dt, 12)] = random_vector(d.tr_off[-1], cfgi, 300 + 3 * n + i) * bm
+    u_ref = u0.copy()
+    for n in range(2):
+        u_ref = ohdg.dirk_step(d, u_ref, n * dt, dt, lambda t: lbs[round(t, 12)])
+    mixed = precision == "mixed_fp32"
+    kw_s = dict(krylov_tol=1e-9, refine_tol=1e-12) if mixed else {}
+    s = _solver(p, precision, cache_factors=True, **kw_s)
+    u = _dev(u0)
+    lam = torch.zeros(d.tr_off[-1], dtype=torch.float64, device="cuda")
+    for n in range(2):
+        stages = np.stack([lbs[round(n * dt + c[i] * dt, 12)] for i in range(3)])
+        s.step(n * dt, dt, "dirk33", u, lam, _dev(stages))
+    torch.cuda.synchronize()
+    errs = _rel_errors(ohdg, d, u.cpu().numpy(), u_ref)
+    assert max(errs) <= (1e-10 if mixed else 1e-12), errs
     s.close()
