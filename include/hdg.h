@@ -134,6 +134,21 @@ typedef struct {
                                    kernels are independent branches (they may overlap on the
                                    device); the graph is captured on the first call and again
                                    whenever a, f_loc or a tuned schedule changes             */
+    int graph_step;             /* nonzero (FP64 only, else HDG_E_UNSUPPORTED at init): hdg_step
+                                   runs a whole step as one hipGraph replay with no host
+                                   synchronisation inside it.  The trace CG then tests its
+                                   convergence on the device: the graph holds a fixed number of
+                                   iterations per stage (the most a stage took in the eager
+                                   step that preceded the capture, plus a quarter and 8) whose
+                                   kernels return at once after the test has passed.  The first
+                                   step with given (dt, scheme, u, lambda, lam_bnd, src) runs
+                                   eagerly and captures the graph; later steps with the same
+                                   arguments (and, with cache_factors, the factors of the same
+                                   stage coefficient still held) replay it.  A replay in which
+                                   a stage has not converged leaves u unchanged, the step runs
+                                   eagerly (reporting HDG_E_NOCONV as usual if it fails) and the
+                                   graph is captured again with twice the iterations (at most
+                                   krylov_maxit).  The iterate is that of the eager step. */
 } hdg_options;
 
 /* Query keys for hdg_query. */
@@ -147,9 +162,11 @@ enum hdg_query_key {
     HDG_Q_LAST_REFINE = 8,      /* refinement iterations of the last mixed recover          */
     HDG_Q_M_LOCAL = 9,          /* field components per element                             */
     HDG_Q_M_TRACE = 10,         /* trace components per face                                */
-    HDG_Q_SCHEDULE = 11         /* launch schedule of the block-structured condensation per
+    HDG_Q_SCHEDULE = 11,        /* launch schedule of the block-structured condensation per
                                    degree class: 4 bits per degree k = 1..5 at bit 4 (k - 1),
                                    each 0 (no class or not chosen yet) or schedule + 1       */
+    HDG_Q_STEP_GRAPH = 12,      /* 1 if the last hdg_step was a replay of the step graph     */
+    HDG_Q_STEP_GRAPH_ITERS = 13 /* CG iterations per stage held by the step graph (0: none)  */
 };
 
 /*
@@ -272,6 +289,9 @@ hdg_status hdg_last_residual(const hdg_ctx* ctx, double* rel);
  *   lambda     device [n_trace_dofs][nrhs] in: initial guess, out: trace of the last stage
  *   lam_bnd    device [n_stages][n_trace_dofs][nrhs] Dirichlet data at t + c_i dt
  *   src        device [n_local_dofs][nrhs] or NULL: time-independent tested source
+ * With options.graph_step the step is one graph replay after the first call with the same
+ * arguments (see there); HDG_Q_STEP_GRAPH tells whether the last step was a replay.
+ * Synchronises the stream.
  */
 hdg_status hdg_step(hdg_ctx* ctx, double t, double dt, int scheme, double* u, double* lambda,
                     const double* lam_bnd, const double* src);

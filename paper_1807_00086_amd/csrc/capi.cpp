@@ -245,6 +245,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     c->autotune = o->autotune != 0;
     if (o->autotune_table) c->tune_path = o->autotune_table;
     c->use_graph = o->use_graph != 0;
+    c->graph_step = o->graph_step != 0;
     c->stream = (hipStream_t)stream;
     int st = build_mesh(c, m, p);
     if (st) {
@@ -305,6 +306,11 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
         std::ostringstream os;
         os << "configuration not built: physics " << c->physics << ", k " << kk << ", nrhs " << c->nrhs;
         g_init_err = os.str();
+        delete c;
+        return HDG_E_UNSUPPORTED;
+    }
+    if (c->graph_step && c->precision != HDG_FP64) {
+        g_init_err = "graph_step: FP64 only (the refinement of the mixed precisions decides on the host)";
         delete c;
         return HDG_E_UNSUPPORTED;
     }
@@ -387,6 +393,7 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     c->red_blocks = 1024;
     TRY(dalloc(c, &c->d_red, (int64_t)RED_MAX * 32));
     TRY(dalloc(c, &c->d_scal, 8 * 32));
+    TRY(dalloc(c, &c->d_cgflags, 8));
     const int64_t nl = c->n_local_dofs * R;
     if (c->precision != HDG_FP64) {
         TRY(dalloc(c, &c->d_f_saved, nl));
@@ -405,6 +412,13 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     if (hipHostMalloc((void**)&c->h_rr, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         c->h_rr = nullptr;
         g_init_err = "hipHostMalloc failed";
+        hdg_destroy(c);
+        return HDG_E_HIP;
+    }
+    if (c->graph_step &&
+        hipStreamCreateWithFlags(&c->sg_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->sg_stream = nullptr;
+        g_init_err = "stream creation for the step graph failed";
         hdg_destroy(c);
         return HDG_E_HIP;
     }
@@ -466,6 +480,8 @@ hdg_status hdg_query(const hdg_ctx* c, int key, int64_t* v) {
         case HDG_Q_LAST_REFINE: *v = c->last_refine; break;
         case HDG_Q_M_LOCAL: *v = c->m_local; break;
         case HDG_Q_M_TRACE: *v = c->m_trace; break;
+        case HDG_Q_STEP_GRAPH: *v = c->sg_replayed ? 1 : 0; break;
+        case HDG_Q_STEP_GRAPH_ITERS: *v = c->sgexec ? c->sg_nit : 0; break;
         case HDG_Q_SCHEDULE: {
             const int pi = c->precision == HDG_FP64 ? 1 : 0;
             int64_t x = 0;
@@ -798,15 +814,12 @@ hdg_status hdg_apply_mass(hdg_ctx* c, double a, const double* u, double* f) {
     return HDG_OK;
 }
 
-hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, double* lambda,
-                    const double* lam_bnd, const double* src) {
-    if (!c) return HDG_E_ARG;
-    if (!u || !lambda || !lam_bnd) return fail(c, HDG_E_ARG, "null pointer");
-    if (!(dt > 0)) return fail(c, HDG_E_ARG, "dt must be positive");
-    if (scheme != HDG_BACKWARD_EULER && scheme != HDG_DIRK33) return fail(c, HDG_E_ARG, "unknown scheme");
-    (void)t;
-    // Butcher tableau and its inverse d = A^{-1}
-    double A[3][3] = {}, Dm[3][3] = {};
+}  // extern "C"
+
+namespace {
+// Butcher tableau of the scheme and the inverse d = A^{-1} of its (lower-triangular) matrix
+int step_tableau(int scheme, double Dm[3][3]) {
+    double A[3][3] = {};
     int ns = 1;
     if (scheme == HDG_BACKWARD_EULER) {
         A[0][0] = 1.0;
@@ -828,6 +841,7 @@ hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, doub
         A[2][2] = g;
     }
     for (int i = 0; i < ns; ++i) {   // forward substitution for the lower-triangular inverse
+        for (int j = 0; j < 3; ++j) Dm[i][j] = 0.0;
         Dm[i][i] = 1.0 / A[i][i];
         for (int j = 0; j < i; ++j) {
             double acc = 0.0;
@@ -835,6 +849,97 @@ hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, doub
             Dm[i][j] = -acc / A[i][i];
         }
     }
+    return ns;
+}
+
+// stage glue of stage i: d_fstage = a Mw u*_i (+ src), u*_i = u^n - (1/d_ii) sum_{j<i} d_ij (U_j - u^n)
+int stage_rhs(hdg_ctx* c, int i, const double Dm[3][3], double dt, const double* u, const double* src) {
+    const int64_t nl = c->n_local_dofs * c->nrhs;
+    const double a = Dm[i][i] / dt;
+    int e = launch_lincomb(c, nl, 1.0, u, 0.0, nullptr, c->d_ustar);
+    double wsum = 0.0;
+    for (int j = 0; j < i && !e; ++j) {
+        const double w = -Dm[i][j] / Dm[i][i];
+        wsum += w;
+        e = launch_axpy(c, nl, w, c->d_stage + j * nl, c->d_ustar);
+    }
+    if (!e && wsum != 0.0) e = launch_axpy(c, nl, -wsum, u, c->d_ustar);
+    if (!e) e = launch_apply_mass(c, a, c->d_ustar, c->d_fstage);
+    if (!e && src) e = launch_axpy(c, nl, 1.0, src, c->d_fstage);
+    return e;
+}
+
+// The launches of one whole step with no host synchronisation, for capture: stage glue,
+// condensation (of the right-hand side only when `reuse`), the device-side CG with `nit`
+// iterations, recovery into the stage buffer.  FP64 only.
+int step_launches(hdg_ctx* c, int ns, const double Dm[3][3], double dt, const double* u, double* lambda,
+                  const double* lam_bnd, const double* src, bool reuse, int nit) {
+    const int64_t nl = c->n_local_dofs * c->nrhs;
+    const int64_t nt = c->n_trace_dofs * c->nrhs;
+    int e = launch_zero_ints(c, c->d_status, 1);
+    for (int i = 0; i < ns && !e; ++i) {
+        const double a = Dm[i][i] / dt;
+        const double* lb = lam_bnd + i * nt;
+        e = stage_rhs(c, i, Dm, dt, u, src);
+        if (e) break;
+        if (reuse) {
+            e = c->fast_ac ? launch_condense_rhs_acoustic(c, a, c->d_fstage)
+                           : launch_condense_rhs_general(c, c->d_fstage);
+            if (!e) e = launch_assemble_rhs(c, lb);
+        } else {
+            e = c->fast_ac ? launch_condense_acoustic(c, a, c->d_fstage) : launch_condense_general(c, a, c->d_fstage);
+            if (!e) e = launch_assemble(c, lb);
+            if (!e) e = launch_block_inverse(c);
+        }
+        if (!e) e = trace_cg_device(c, lambda, c->krylov_tol, nit, c->d_cgflags + 2 * i, c->d_scal + 160 + i);
+        if (!e) e = launch_recover_any(c, lambda, c->d_stage + i * nl);
+    }
+    return e;
+}
+
+// capture the step into c->sgexec (nothing runs); the vardeg condensation graph is not nested
+int capture_step(hdg_ctx* c, int ns, const double Dm[3][3], double dt, const double* u, double* lambda,
+                 const double* lam_bnd, const double* src, bool reuse, int nit) {
+    if (c->sgexec) {
+        (void)hipGraphExecDestroy(c->sgexec);
+        c->sgexec = nullptr;
+    }
+    if (hipStreamBeginCapture(c->sg_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return -1;
+    hipStream_t user = c->stream;
+    const bool ug = c->use_graph;
+    c->stream = c->sg_stream;
+    c->use_graph = false;
+    const int e = step_launches(c, ns, Dm, dt, u, lambda, lam_bnd, src, reuse, nit);
+    c->stream = user;
+    c->use_graph = ug;
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->sg_stream, &graph);
+    if (e || ee != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return e ? e : (int)ee;
+    }
+    const hipError_t ie = hipGraphInstantiate(&c->sgexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        c->sgexec = nullptr;
+        return (int)ie;
+    }
+    c->sg_reuse = reuse;
+    c->sg_nit = nit;
+    return 0;
+}
+}  // namespace
+
+extern "C" {
+hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, double* lambda,
+                    const double* lam_bnd, const double* src) {
+    if (!c) return HDG_E_ARG;
+    if (!u || !lambda || !lam_bnd) return fail(c, HDG_E_ARG, "null pointer");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, HDG_E_ARG, "dt must be positive");
+    if (scheme != HDG_BACKWARD_EULER && scheme != HDG_DIRK33) return fail(c, HDG_E_ARG, "unknown scheme");
+    (void)t;
+    double Dm[3][3];
+    const int ns = step_tableau(scheme, Dm);
     const int64_t nl = c->n_local_dofs * c->nrhs;
     const int64_t nt = c->n_trace_dofs * c->nrhs;
     if (!c->d_stage) {
@@ -843,33 +948,71 @@ hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, doub
         if ((s = dalloc(c, &c->d_ustar, nl))) return s;
         if ((s = dalloc(c, &c->d_fstage, nl))) return s;
     }
-    for (int i = 0; i < ns; ++i) {
-        const double a = Dm[i][i] / dt;
-        // u* = u^n - (1/d_ii) sum_{j<i} d_ij (U_j - u^n)
-        HIPCHK(hipMemcpyAsync(c->d_ustar, u, nl * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-        double wsum = 0.0;
-        for (int j = 0; j < i; ++j) {
-            double w = -Dm[i][j] / Dm[i][i];
-            wsum += w;
-            launch_axpy(c, nl, w, c->d_stage + j * nl, c->d_ustar);
+    const double a = Dm[0][0] / dt;   // every stage of both schemes has this coefficient
+    c->sg_replayed = false;
+    hdg_ctx::StepKey key;
+    key.dt = dt;
+    key.scheme = scheme;
+    key.u = u;
+    key.lambda = lambda;
+    key.lam_bnd = lam_bnd;
+    key.src = src;
+    int retry_nit = 0;   // > 0: the replay ran out of CG iterations; recapture with at least this many
+    if (c->graph_step && c->sgexec && c->sg_key == key &&
+        (!c->sg_reuse || (c->factors_cached && c->condensed && c->last_a == a))) {
+        HIPCHK(hipGraphLaunch(c->sgexec, c->stream));
+        int h[8] = {}, st = 0;
+        HIPCHK(hipMemcpyAsync(h, c->d_cgflags, 2 * ns * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (st & 1) return fail(c, HDG_E_SINGULAR, "zero or non-finite pivot in a local factorisation");
+        bool ok = true;
+        for (int i = 0; i < ns; ++i) ok = ok && h[2 * i] == 1;
+        if (ok) {
+            HIPCHK(hipMemcpyAsync(u, c->d_stage + (ns - 1) * nl, nl * sizeof(double), hipMemcpyDeviceToDevice,
+                                  c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            c->last_iters = h[2 * (ns - 1) + 1];
+            c->last_a = a;
+            c->condensed = true;
+            c->z_consumed = false;
+            if (!c->sg_reuse) c->factors_cached = c->d_LU != nullptr && c->nrhs == 1;
+            c->sg_replayed = true;
+            return HDG_OK;
         }
-        if (wsum != 0.0) launch_axpy(c, nl, -wsum, u, c->d_ustar);
-        launch_apply_mass(c, a, c->d_ustar, c->d_fstage);
-        if (src) launch_axpy(c, nl, 1.0, src, c->d_fstage);
+        // a stage did not converge within the captured iterations (or went non-finite): u is
+        // untouched, so the step runs again below without the graph, which reports a failure
+        // properly, and the graph is captured again with a larger budget
+        retry_nit = std::min(c->krylov_maxit, 2 * c->sg_nit);
+    }
+    int max_it = 0;
+    for (int i = 0; i < ns; ++i) {
+        int s = stage_rhs(c, i, Dm, dt, u, src);
+        if (s) return fail(c, HDG_E_HIP, "stage right-hand-side launch failed");
         // the stage matrices depend on a only: with cached factors a repeated a needs only the
         // right-hand side condensed
         const bool reuse = c->cache_factors && c->factors_cached && c->condensed && a == c->last_a;
-        int s = reuse ? hdg_condense_rhs(c, a, c->d_fstage, lam_bnd + i * nt)
-                      : hdg_condense(c, a, c->d_fstage, lam_bnd + i * nt);
+        s = reuse ? hdg_condense_rhs(c, a, c->d_fstage, lam_bnd + i * nt)
+                  : hdg_condense(c, a, c->d_fstage, lam_bnd + i * nt);
         if (s) return s;
         int it;
         double rr;
         if ((s = hdg_trace_solve(c, lambda, &it, &rr))) return s;
+        max_it = std::max(max_it, it);
         if ((s = hdg_recover(c, lambda, c->d_stage + i * nl))) return s;
     }
     // stiffly accurate: u^{n+1} = U_s
     HIPCHK(hipMemcpyAsync(u, c->d_stage + (ns - 1) * nl, nl * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->graph_step) {
+        // capture for the next step with these arguments: the CG budget is the most iterations a
+        // stage took here plus a margin (iterations past convergence return at once)
+        const bool reuse = c->cache_factors && c->factors_cached && c->condensed && a == c->last_a;
+        const int nit = std::min(c->krylov_maxit, std::max(retry_nit, max_it + max_it / 4 + 8));
+        if (capture_step(c, ns, Dm, dt, u, lambda, lam_bnd, src, reuse, nit))
+            return fail(c, HDG_E_HIP, "capture of the step graph failed");
+        c->sg_key = key;
+    }
     return HDG_OK;
 }
 
@@ -1046,7 +1189,7 @@ void hdg_destroy(hdg_ctx* c) {
                     c->tab.Tsym32, c->tab.Ef32, c->tab.Tfull, c->tab.Tfull32, c->tab.SrT, c->tab.EfT, c->d_eframe, c->d_xscratch, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
                     c->d_bsr, c->d_bsr32, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
                     c->d_scal, c->d_f_saved, c->d_lbnd_saved, c->d_su, c->d_slam, c->d_du, c->d_dlam,
-                    c->d_re64, c->d_sq,
+                    c->d_re64, c->d_sq, c->d_cgflags,
                     c->d_stage, c->d_ustar, c->d_fstage, c->d_loc_off, c->d_efnf, c->d_face_nf, c->d_edeg,
                     c->d_cls[1], c->d_cls[2], c->d_cls[3], c->d_cls[4], c->d_cls[5]};
     if (c->stream || c->d_geom) (void)hipStreamSynchronize(c->stream);
@@ -1060,6 +1203,8 @@ void hdg_destroy(hdg_ctx* c) {
     if (c->ev_rr) (void)hipEventDestroy(c->ev_rr);
     if (c->h_rr) (void)hipHostFree(c->h_rr);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->sgexec) (void)hipGraphExecDestroy(c->sgexec);
+    if (c->sg_stream) (void)hipStreamDestroy(c->sg_stream);
     for (int i = 0; i < 6; ++i) {
         if (c->side[i]) {
             (void)hipStreamSynchronize(c->side[i]);

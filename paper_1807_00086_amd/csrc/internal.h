@@ -183,6 +183,28 @@ struct hdg_ctx {
     double g_a = 0.0;
     const double* g_f = nullptr;
     int g_sched = -1;
+
+    // device-side CG (graph capture): launches of the iteration kernels read *cg_done and return
+    // at once when it is set; null outside the captured solve
+    const int* cg_done = nullptr;
+    int* d_cgflags = nullptr;   // [3][2] per stage: done (1 converged, 2 non-finite), iterations
+    // hdg_step as one graph (options.graph_step, FP64): the executable, the stream it was
+    // captured on, and what it was captured for (a replay needs all of it unchanged)
+    bool graph_step = false;
+    hipGraphExec_t sgexec = nullptr;
+    hipStream_t sg_stream = nullptr;
+    struct StepKey {
+        double dt = 0.0;
+        int scheme = -1;
+        const double *u = nullptr, *lambda = nullptr, *lam_bnd = nullptr, *src = nullptr;
+        bool operator==(const StepKey& o) const {
+            return dt == o.dt && scheme == o.scheme && u == o.u && lambda == o.lambda && lam_bnd == o.lam_bnd &&
+                   src == o.src;
+        }
+    } sg_key;
+    bool sg_reuse = false;      // captured with the factors of last_a kept (right-hand sides only)
+    int sg_nit = 0;             // CG iterations per stage in the captured graph
+    bool sg_replayed = false;   // the last hdg_step ran as a graph replay
 };
 
 namespace hdg {
@@ -211,6 +233,10 @@ int launch_block_inverse(hdg_ctx* c);
 // lowp: products with the FP32 copy of the matrix (correction solves of the refinement, whose
 // tolerance is far above FP32 rounding; the refinement's FP64 residual removes the difference)
 int trace_cg(hdg_ctx* c, double* lambda, double tol, int* iters, double* relres, bool lowp = false);
+// The same CG with a fixed number of iterations and the convergence test on the device (for
+// graph capture): flags [2] = done, iterations; relres_dev = largest relative residual.
+int trace_cg_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, double* relres_dev);
+int launch_zero_ints(hdg_ctx* c, int* p, int n);
 int launch_bsr_f32(hdg_ctx* c);
 // trace solve with the CG work vectors and reduction scratch in the library's static device
 // array (no allocation); static_scratch_setup looks up the array's address on the current device

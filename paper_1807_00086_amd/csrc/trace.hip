@@ -175,7 +175,9 @@ __global__ __launch_bounds__(64) void block_inverse_kernel(int64_t nf, int nslot
 __global__ __launch_bounds__(NT) void bsr_spmv_kernel(int64_t nf, int nslot, int bs, int R,
                                                       const int32_t* __restrict__ cols,
                                                       const double* __restrict__ bsr,
-                                                      const double* __restrict__ x, double* __restrict__ y) {
+                                                      const double* __restrict__ x, double* __restrict__ y,
+                                                      const int* __restrict__ done) {
+    if (done && *done) return;
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t total = nf * bs * R;
     if (gid >= total) return;
@@ -202,7 +204,9 @@ __global__ __launch_bounds__(NT) void bsr_spmv_kernel(int64_t nf, int nslot, int
 template <int BS, int NS, typename M>
 __global__ __launch_bounds__(NT) void bsr_spmv_fixed_kernel(int64_t nf, int R, const int32_t* __restrict__ cols,
                                                             const M* __restrict__ bsr,
-                                                            const double* __restrict__ x, double* __restrict__ y) {
+                                                            const double* __restrict__ x, double* __restrict__ y,
+                                                            const int* __restrict__ done) {
+    if (done && *done) return;
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= nf * BS * R) return;
     const int r = (int)(gid % R);
@@ -239,7 +243,9 @@ template <int BS, int NS, typename M = double, bool DOT = false>
 __global__ __launch_bounds__(256) void bsr_spmm32_kernel(int64_t nf, const int32_t* __restrict__ cols,
                                                          const M* __restrict__ bsr,
                                                          const double* __restrict__ x, double* __restrict__ y,
-                                                         const double* __restrict__ dv, double* __restrict__ part) {
+                                                         const double* __restrict__ dv, double* __restrict__ part,
+                                                         const int* __restrict__ done) {
+    if (done && *done) return;
     constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4, R = 32, SU = sizeof(M) == 4 ? 2 : 1;
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -314,7 +320,8 @@ __global__ __launch_bounds__(256) void bsr_spmm32_kernel(int64_t nf, const int32
 template <int BS>
 __global__ __launch_bounds__(NT) void block_apply_fixed_kernel(int64_t nf, int R, const double* __restrict__ pinv,
                                                                const double* __restrict__ x,
-                                                               double* __restrict__ y) {
+                                                               double* __restrict__ y, const int* __restrict__ done) {
+    if (done && *done) return;
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= nf * BS * R) return;
     const int r = (int)(gid % R);
@@ -332,7 +339,8 @@ __global__ __launch_bounds__(NT) void block_apply_fixed_kernel(int64_t nf, int R
 __global__ __launch_bounds__(NT) void block_apply_kernel(int64_t nf, int bs, int R,
                                                          const double* __restrict__ pinv,
                                                          const double* __restrict__ x,
-                                                         double* __restrict__ y) {
+                                                         double* __restrict__ y, const int* __restrict__ done) {
+    if (done && *done) return;
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t total = nf * bs * R;
     if (gid >= total) return;
@@ -350,7 +358,8 @@ __global__ __launch_bounds__(NT) void block_apply_kernel(int64_t nf, int bs, int
 // partial dot products per rhs column: out[blk][r]
 __global__ __launch_bounds__(NT) void dot_partial_kernel(int64_t n, int R, const double* __restrict__ x,
                                                          const double* __restrict__ y,
-                                                         double* __restrict__ part) {
+                                                         double* __restrict__ part, const int* __restrict__ done) {
+    if (done && *done) return;
     // thread t of a block owns column t % R of rows t / R, t / R + T, ... (T = NT / R rows per
     // pass): consecutive threads read consecutive entries of the row-major [n][R] vectors
     __shared__ double sh[NT];
@@ -377,7 +386,8 @@ __global__ __launch_bounds__(NT) void dot_partial_kernel(int64_t n, int R, const
 }
 
 __global__ __launch_bounds__(NT) void dot_final_kernel(int nb, int R, const double* __restrict__ part,
-                                                       double* __restrict__ out) {
+                                                       double* __restrict__ out, const int* __restrict__ done) {
+    if (done && *done) return;
     __shared__ double sh[NT];
     for (int r = 0; r < R; ++r) {
         double acc = 0.0;
@@ -400,7 +410,10 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(int64_t n, int R, const d
                                                        const double* __restrict__ den,
                                                        const double* __restrict__ p, const double* __restrict__ q,
                                                        double* __restrict__ x, double* __restrict__ rv,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part, const int* __restrict__ done,
+                                                       int* __restrict__ iters) {
+    if (done && *done) return;
+    if (iters && blockIdx.x == 0 && threadIdx.x == 0) ++*iters;
     __shared__ double sh[NT];
     const int T = NT / R, t = threadIdx.x;
     double acc = 0.0;
@@ -435,7 +448,9 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(int64_t n, int R, const d
 // p = z + beta p, beta = num/den per column
 __global__ __launch_bounds__(NT) void xpby_cols_kernel(int64_t n, int R, const double* __restrict__ num,
                                                        const double* __restrict__ den,
-                                                       const double* __restrict__ z, double* __restrict__ p) {
+                                                       const double* __restrict__ z, double* __restrict__ p,
+                                                       const int* __restrict__ done) {
+    if (done && *done) return;
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= n * R) return;
     int r = (int)(gid % R);
@@ -558,13 +573,14 @@ static void launch_spmm32(hdg_ctx* c, const int32_t* cols, const M* blocks, cons
         if (dot_out) {
             const int g = dot_grid(c);
             hipLaunchKernelGGL((bsr_spmm32_kernel<BS, NS, M, true>), dim3(g), dim3(256), 0, c->stream,
-                               c->n_faces, cols, blocks, x, y, x, c->d_red);
-            hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, g, 32, c->d_red, dot_out);
+                               c->n_faces, cols, blocks, x, y, x, c->d_red, c->cg_done);
+            hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, g, 32, c->d_red, dot_out,
+                               c->cg_done);
             return;
         }
     }
     hipLaunchKernelGGL((bsr_spmm32_kernel<BS, NS, M>), dim3(nblk_faces(c)), dim3(256), 0, c->stream, c->n_faces,
-                       cols, blocks, x, y, (const double*)nullptr, (double*)nullptr);
+                       cols, blocks, x, y, (const double*)nullptr, (double*)nullptr, c->cg_done);
     if (dot_out) dot(c, x, y, dot_out);
 }
 
@@ -599,17 +615,17 @@ static void spmv_other(hdg_ctx* c, const double* x, double* y, bool lowp) {
     if (c->bs == B) {                                                                                      \
         if (lowp && c->d_bsr32)                                                                            \
             hipLaunchKernelGGL((bsr_spmv_fixed_kernel<B, 7, float>), dim3(nblk(n)), dim3(NT), 0, c->stream,  \
-                               c->n_faces, c->nrhs, c->d_bsr_cols, c->d_bsr32, x, y);                      \
+                               c->n_faces, c->nrhs, c->d_bsr_cols, c->d_bsr32, x, y, c->cg_done);          \
         else                                                                                               \
             hipLaunchKernelGGL((bsr_spmv_fixed_kernel<B, 7, double>), dim3(nblk(n)), dim3(NT), 0, c->stream, \
-                               c->n_faces, c->nrhs, c->d_bsr_cols, c->d_bsr, x, y);                        \
+                               c->n_faces, c->nrhs, c->d_bsr_cols, c->d_bsr, x, y, c->cg_done);            \
         return;                                                                                            \
     }
         HDG_BS_CASES(HDG_BS)
 #undef HDG_BS
     }
     hipLaunchKernelGGL(bsr_spmv_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->nslot, c->bs,
-                       c->nrhs, c->d_bsr_cols, c->d_bsr, x, y);
+                       c->nrhs, c->d_bsr_cols, c->d_bsr, x, y, c->cg_done);
 }
 
 static void precond_other(hdg_ctx* c, const double* x, double* y);
@@ -634,21 +650,21 @@ static void precond_other(hdg_ctx* c, const double* x, double* y) {
 #define HDG_BS(B)                                                                                            \
     if (c->bs == B) {                                                                                        \
         hipLaunchKernelGGL((block_apply_fixed_kernel<B>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces,   \
-                           c->nrhs, c->d_pinv, x, y);                                                        \
+                           c->nrhs, c->d_pinv, x, y, c->cg_done);                                            \
         return;                                                                                              \
     }
     HDG_BS_CASES(HDG_BS)
 #undef HDG_BS
     hipLaunchKernelGGL(block_apply_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->bs, c->nrhs,
-                       c->d_pinv, x, y);
+                       c->d_pinv, x, y, c->cg_done);
 }
 
 static void dot(hdg_ctx* c, const double* x, const double* y, double* out_dev) {
     int64_t n = c->n_faces * c->bs;
     hipLaunchKernelGGL(dot_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, c->nrhs, x, y,
-                       c->d_red);
+                       c->d_red, c->cg_done);
     hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, c->nrhs, c->d_red,
-                       out_dev);
+                       out_dev, c->cg_done);
 }
 
 int launch_lincomb(hdg_ctx* c, int64_t n, double a, const double* x, double b, const double* y, double* out) {
@@ -661,9 +677,10 @@ int launch_axpy(hdg_ctx* c, int64_t n, double alpha, const double* x, double* y)
 }
 
 int launch_norm2(hdg_ctx* c, int64_t n, const double* x, double* host_out) {
-    hipLaunchKernelGGL(dot_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, 1, x, x, c->d_red);
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, 1, x, x, c->d_red,
+                       (const int*)nullptr);
     hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, 1, c->d_red,
-                       c->d_scal + 7 * 32);
+                       c->d_scal + 7 * 32, (const int*)nullptr);
     hipError_t e = hipMemcpyAsync(host_out, c->d_scal + 7 * 32, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return (int)e;
     e = hipStreamSynchronize(c->stream);
@@ -677,9 +694,10 @@ int launch_col_sq(hdg_ctx* c, int64_t n, int R, const double* x, double* host_ou
         hipLaunchKernelGGL(bnd_sq_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, c->bs,
                            c->d_face_bnd, x, c->d_red);
     else
-        hipLaunchKernelGGL(dot_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, x, x, c->d_red);
+        hipLaunchKernelGGL(dot_partial_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, x, x, c->d_red,
+                           (const int*)nullptr);
     hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, R, c->d_red,
-                       c->d_scal + 7 * 32);
+                       c->d_scal + 7 * 32, (const int*)nullptr);
     hipError_t e = hipMemcpyAsync(host_out, c->d_scal + 7 * 32, R * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return (int)e;
     return (int)hipStreamSynchronize(c->stream);
@@ -745,11 +763,12 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
         }
         if (worst <= tol || it == c->krylov_maxit) break;
         hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, pp,
-                           qq, x, rr, c->d_red);
-        hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, R, c->d_red, s_rr);
+                           qq, x, rr, c->d_red, (const int*)nullptr, (int*)nullptr);
+        hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, R, c->d_red, s_rr,
+                           (const int*)nullptr);
         precond(c, rr, zz, s_rz_new);
         hipLaunchKernelGGL(xpby_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz_new, s_rz, zz,
-                           pp);
+                           pp, (const int*)nullptr);
         std::swap(s_rz, s_rz_new);   // the new r.z becomes the old one (no device copy)
     }
     if (iters) *iters = it;
@@ -757,6 +776,83 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
     c->last_iters = it;
     if (!(worst <= tol)) return HDG_E_NOCONV;
     return HDG_OK;
+}
+
+namespace {
+// Device-side convergence test of the captured CG: done = 1 once every column meets the
+// tolerance, 2 on a non-finite residual; relres = the largest relative residual.
+__global__ void cg_check_kernel(int R, const double* __restrict__ s_rr, const double* __restrict__ s_bb,
+                                double tol, int* __restrict__ flags, double* __restrict__ relres) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || flags[0]) return;
+    double worst = 0.0;
+    bool nonfinite = false;
+    for (int r = 0; r < R; ++r) {
+        const double b = sqrt(s_bb[r]);
+        const double v = sqrt(s_rr[r]) / (b > 0.0 ? b : 1.0);
+        if (!(v - v == 0.0)) nonfinite = true;
+        else worst = fmax(worst, v);
+    }
+    *relres = nonfinite ? __builtin_nan("") : worst;
+    if (nonfinite) flags[0] = 2;
+    else if (worst <= tol) flags[0] = 1;
+}
+
+__global__ void zero_ints_kernel(int* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+}  // namespace
+
+// a fill kernel rather than a memset: it may be captured into a graph
+int launch_zero_ints(hdg_ctx* c, int* p, int n) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 63) / 64), dim3(64), 0, c->stream, p, n);
+    return (int)hipGetLastError();
+}
+
+// The CG of trace_cg with a fixed number of iterations and the convergence test on the device,
+// for capture into a graph: every iteration's kernels return at once after the test has passed.
+// flags[0] (done: 1 converged, 2 non-finite), flags[1] (iterations) and relres_dev tell the host
+// afterwards whether it converged within `nit` iterations.  The arithmetic, and so the iterate,
+// is that of trace_cg (FP64 products).
+int trace_cg_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, double* relres_dev) {
+    const int R = c->nrhs;
+    const int64_t n = c->n_faces * c->bs;
+    double* rr = c->d_cg_r;
+    double* zz = c->d_cg_z;
+    double* pp = c->d_cg_p;
+    double* qq = c->d_cg_q;
+    double* s_rz = c->d_scal;
+    double* s_rz_new = c->d_scal + 32;
+    double* s_pq = c->d_scal + 64;
+    double* s_rr = c->d_scal + 96;
+    double* s_bb = c->d_scal + 128;
+    double* s_res = relres_dev;
+    launch_zero_ints(c, flags, 2);
+    hipLaunchKernelGGL(copy_bnd_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, c->n_faces, c->bs, R,
+                       c->d_face_bnd, c->d_rhs, x);
+    spmv(c, x, qq);
+    launch_lincomb(c, n * R, 1.0, c->d_rhs, -1.0, qq, rr);
+    precond(c, rr, zz);
+    launch_lincomb(c, n * R, 1.0, zz, 0.0, nullptr, pp);
+    dot(c, rr, zz, s_rz);
+    dot(c, c->d_rhs, c->d_rhs, s_bb);
+    dot(c, rr, rr, s_rr);
+    hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(64), 0, c->stream, R, s_rr, s_bb, tol, flags, s_res);
+    c->cg_done = flags;   // from here on every launch of the loop returns once converged
+    for (int it = 0; it < nit; ++it) {
+        spmv(c, pp, qq, false, s_pq);
+        hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, pp,
+                           qq, x, rr, c->d_red, (const int*)flags, flags + 1);
+        hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, R, c->d_red, s_rr,
+                           (const int*)flags);
+        hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(64), 0, c->stream, R, s_rr, s_bb, tol, flags, s_res);
+        precond(c, rr, zz, s_rz_new);
+        hipLaunchKernelGGL(xpby_cols_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, n, R, s_rz_new, s_rz, zz,
+                           pp, (const int*)flags);
+        std::swap(s_rz, s_rz_new);
+    }
+    c->cg_done = nullptr;
+    return (int)hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -23,7 +23,8 @@ PRECISION = {"fp64": FP64, "mixed_fp32": MIXED_FP32, "mixed_bf16": MIXED_BF16}
 STATUS = {0: "HDG_OK", 1: "HDG_E_ARG", 2: "HDG_E_MESH", 3: "HDG_E_ALLOC", 4: "HDG_E_HIP",
           5: "HDG_E_SINGULAR", 6: "HDG_E_NOCONV", 7: "HDG_E_STATE", 8: "HDG_E_UNSUPPORTED"}
 Q = dict(n_elem=0, n_faces=1, n_bfaces=2, n_local_dofs=3, n_trace_dofs=4, n_vol_points=5,
-         n_bnd_points=6, last_iters=7, last_refine=8, m_local=9, m_trace=10, schedule=11)
+         n_bnd_points=6, last_iters=7, last_refine=8, m_local=9, m_trace=10, schedule=11,
+         step_graph=12, step_graph_iters=13)
 
 # every function declared in include/hdg.h
 EXPORTS = ["hdg_init_mesh", "hdg_query", "hdg_condense", "hdg_condense_rhs", "hdg_trace_solve", "hdg_recover",
@@ -54,7 +55,8 @@ class Options(C.Structure):
                 ("krylov_tol", C.c_double), ("krylov_maxit", C.c_int),
                 ("refine_tol", C.c_double), ("refine_maxit", C.c_int),
                 ("refine_inner_tol", C.c_double), ("cache_factors", C.c_int),
-                ("autotune", C.c_int), ("autotune_table", C.c_char_p), ("use_graph", C.c_int)]
+                ("autotune", C.c_int), ("autotune_table", C.c_char_p), ("use_graph", C.c_int),
+                ("graph_step", C.c_int)]
 
 
 _lib = None
@@ -164,7 +166,7 @@ class Solver:
     def __init__(self, xyz, elem_vert, physics, elem_par, k=None, degree=None, precision="fp64",
                  nrhs=1, stab_scale=1.0, krylov_tol=1e-13, krylov_maxit=5000, refine_tol=1e-13,
                  refine_maxit=10, refine_inner_tol=1e-6, cache_factors=False, autotune=False,
-                 autotune_table=None, use_graph=False, stream=None):
+                 autotune_table=None, use_graph=False, graph_step=False, stream=None):
         self.lib = load_library()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._ev = np.ascontiguousarray(elem_vert, dtype=np.int64)
@@ -184,7 +186,7 @@ class Solver:
                      self.nrhs, float(krylov_tol), int(krylov_maxit), float(refine_tol),
                      int(refine_maxit), float(refine_inner_tol), int(bool(cache_factors)),
                      int(bool(autotune)), None if autotune_table is None else os.fsencode(autotune_table),
-                     int(bool(use_graph)))
+                     int(bool(use_graph)), int(bool(graph_step)))
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

@@ -1,0 +1,165 @@
+"""hdg_step as one graph replay (options.graph_step): the trace CG tests its convergence on the
+device, so a whole DIRK(3,3) step (stage glue, condensation, solve, recovery of all three
+stages) is captured once and replayed with no host synchronisation inside it.
+
+Every replay is checked against a second context that runs the same steps eagerly on the same
+inputs: the graph launches the same kernels on the same data with the same per-column scalars,
+so the results agree to the last bits (bound here: 1e-14 relative).  Between the replays the
+program does its own eager work (new boundary data copied into the captured buffers, a
+host synchronisation at the end of every step).  The eager path itself is pinned to the
+oracle's stage recursion by the hdg_step parity tests.
+"""
+import numpy as np
+import pytest
+
+from synth import make_problem, random_vector
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _solver(p, **kw):
+    from paper_1807_00086_amd import Solver
+    uk = p.uniform_k
+    return Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=uk, degree=None if uk else p.degree,
+                  precision="fp64", nrhs=1, **kw)
+
+
+def _setup(cfg, kw):
+    from oracle import hdg as ohdg
+    if cfg == "glm":
+        p = make_problem(5, **kw)
+        p.physics = "maxwell_glm"
+        cfg = 5
+    else:
+        p = make_problem(cfg, **kw)
+    p.nrhs = 1
+    d = ohdg.make_discretisation(p)
+    bm = ohdg.boundary_trace_mask(d)
+    return p, d, bm, cfg
+
+
+def _stage_data(d, bm, cfg, seed, var):
+    st = np.stack([random_vector(d.tr_off[-1], cfg, seed + i) * bm for i in range(3)])
+    if var:
+        from test_gpu_pvar import _pad
+        st = np.stack([_pad(d, x[:, None])[:, 0] for x in st])
+    return st
+
+
+def _rel(x, y):
+    return float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+
+
+CASES = [
+    (2, dict(n=2, k=2), dict()),                               # acoustic fast path
+    (2, dict(n=2, k=3), dict(cache_factors=True)),             # right-hand sides only
+    (3, dict(n=1, k=2), dict(cache_factors=True)),             # elastic, block-structured
+    ("glm", dict(n=1, k=2), dict()),                           # GLM-Maxwell, signed factors
+    (4, dict(nxyz=(2, 2, 1)), dict(use_graph=True)),           # variable degree (class graph)
+]
+
+
+@pytest.mark.parametrize("cfg,kw,opts", CASES)
+def test_step_graph_replays_match_eager(cfg, kw, opts):
+    """Four DIRK(3,3) steps: the first captures, the other three replay; every step equals the
+    eager context's.  With cache_factors the captured stages condense their right-hand sides
+    with the kept factors; a condensation at another stage coefficient in between invalidates
+    them, and the next step then runs eagerly (and captures again)."""
+    _need_gpu()
+    p, d, bm, cfgi = _setup(cfg, kw)
+    var = p.uniform_k is None
+    print(f"case step graph {p.physics} {kw} {opts} n_elem={p.n_elem}", flush=True)
+    ge = _solver(p, graph_step=True, **opts)
+    ee = _solver(p, **opts)
+    nl, nt = ge.query("n_local_dofs"), ge.query("n_trace_dofs")
+    u0 = random_vector(nl, cfgi, 61)
+    bufs = {}
+    for name, s in (("g", ge), ("e", ee)):
+        bufs[name] = dict(u=_dev(u0), lam=torch.zeros(nt, dtype=torch.float64, device="cuda"),
+                          st=torch.zeros((3, nt), dtype=torch.float64, device="cuda"))
+    dt = 0.01
+    cached = opts.get("cache_factors", False)
+    for n in range(5):
+        stages = _dev(_stage_data(d, bm, cfgi, 400 + 3 * n, var))
+        if cached and n == 3:
+            # another stage coefficient: the kept factors no longer belong to this dt
+            f = _dev(random_vector(nl, cfgi, 70))
+            for s in (ge, ee):
+                s.condense(7.0 / dt, f, stages[0])
+        outs = {}
+        for name, s in (("g", ge), ("e", ee)):
+            b = bufs[name]
+            b["st"].copy_(stages)     # same buffer every step: the graph keeps its pointers
+            s.step(n * dt, dt, "dirk33", b["u"], b["lam"], b["st"])
+            outs[name] = b["u"].cpu().numpy()
+        replayed = ge.query("step_graph")
+        expect = 0 if n == 0 or (cached and n == 3) else 1
+        assert replayed == expect, (n, replayed)
+        assert ee.query("step_graph") == 0
+        assert ge.query("step_graph_iters") > 0
+        r = _rel(outs["g"], outs["e"])
+        assert r <= 1e-14, (n, r)
+        assert ge.query("last_iters") == ee.query("last_iters"), n
+    ge.close()
+    ee.close()
+
+
+def test_step_graph_budget_exceeded_falls_back():
+    """A first step on zero data converges at once, so the captured CG holds few iterations; the
+    next step (non-zero data in the same buffers) runs out of them on the device: the replay is
+    discarded (u untouched), the step runs eagerly and the graph is captured again with more
+    iterations, which the step after that replays."""
+    _need_gpu()
+    p, d, bm, cfgi = _setup(2, dict(n=2, k=2))
+    ge = _solver(p, graph_step=True)
+    ee = _solver(p)
+    nl, nt = ge.query("n_local_dofs"), ge.query("n_trace_dofs")
+    bufs = {name: dict(u=torch.zeros(nl, dtype=torch.float64, device="cuda"),
+                       lam=torch.zeros(nt, dtype=torch.float64, device="cuda"),
+                       st=torch.zeros((3, nt), dtype=torch.float64, device="cuda")) for name in "ge"}
+    dt = 0.01
+    seen = []
+    for n in range(3):
+        if n == 1:
+            u1 = _dev(random_vector(nl, cfgi, 81))
+            for b in bufs.values():
+                b["u"].copy_(u1)
+        stages = _dev(_stage_data(d, bm, cfgi, 500 + 3 * n, False) * (n > 0))
+        outs = {}
+        for name, s in (("g", ge), ("e", ee)):
+            b = bufs[name]
+            b["st"].copy_(stages)
+            s.step(n * dt, dt, "dirk33", b["u"], b["lam"], b["st"])
+            outs[name] = b["u"].cpu().numpy()
+        seen.append((ge.query("step_graph"), ge.query("step_graph_iters")))
+        if n == 0:
+            assert np.all(outs["g"] == 0.0)
+        else:
+            # the fallback's CG starts from the discarded replay's trace, so it agrees with the
+            # eager context to the CG tolerance only
+            assert _rel(outs["g"], outs["e"]) <= 1e-10, n
+    assert seen[0][0] == 0 and seen[1][0] == 0 and seen[2][0] == 1, seen
+    assert seen[1][1] > seen[0][1], seen
+    ge.close()
+    ee.close()
+
+
+def test_step_graph_fp64_only():
+    """graph_step with a mixed precision is refused at init (HDG_E_UNSUPPORTED)."""
+    _need_gpu()
+    from paper_1807_00086_amd import HDGError, Solver
+    p = make_problem(2, n=1, k=2)
+    with pytest.raises(HDGError) as ei:
+        Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=2, precision="mixed_fp32", graph_step=True)
+    assert ei.value.code == 8
