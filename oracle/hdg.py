@@ -12,7 +12,11 @@ f directly; see the module docstring of ``physics``).
 
 Dirichlet faces carry the L2 projection of the boundary data onto the face space
 (the trace equations of sections 4.1.2 and 5.2 replace the jump condition there by
-<lam - g_D, mu>_F = 0); their values are moved to the right-hand side.
+<lam - g_D, mu>_F = 0); their values are moved to the right-hand side.  Neumann faces
+(section 4.1.2, the Gamma_N part of the trace equation: <flux_hat - g_N, mu>_F = 0) keep
+the one-sided flux row of their element and carry the tested datum <g_N, mu>_F on the
+right-hand side of that row.  The boundary vector lam_bnd of the solvers holds both: the
+projected Dirichlet values on Dirichlet faces and the tested fluxes on Neumann faces.
 
 Time stepping: DIRK stages written as in section 2.3.2,
     sum_j d_ij M (U_j - u^n) + dt f(U_i, V_i, t_n + c_i dt) = 0,
@@ -28,7 +32,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .mesh import build_skeleton, face_map, face_frame
+from .mesh import build_skeleton, face_map, face_frame, face_measure_and_normal
 from .physics import ElementQuad, local_system, n_local_comp, N_TRACE_COMP, stabilisation
 from .polynomials import dim_p, pkd_eval, rule_for_degree
 
@@ -66,6 +70,7 @@ class Discretisation:
     elem_face_k: np.ndarray = None     # [n_elem, dim+1]
     loc_off: np.ndarray = None         # [n_elem+1] local dof offsets
     tr_off: np.ndarray = None          # [n_faces+1] trace dof offsets
+    neumann: np.ndarray = None         # [n_faces] bool: boundary face with a Neumann condition
     quad: dict = field(default_factory=dict)
 
     @property
@@ -100,7 +105,9 @@ class Discretisation:
 
 
 def make_discretisation(problem) -> Discretisation:
-    """Skeleton, face degrees (k_F = max of the neighbours' degrees) and dof offsets."""
+    """Skeleton, face degrees (k_F = max of the neighbours' degrees) and dof offsets.
+    problem.bface_tag (optional, [n_elem, dim+1], the local face opposite vertex f): 1 marks a
+    Neumann boundary face, 0 a Dirichlet one; interior faces must carry 0."""
     skel = build_skeleton(problem.elem_vert)
     deg = np.asarray(problem.degree, dtype=np.int64)
     fk = np.zeros(skel.n_faces, dtype=np.int64)
@@ -117,6 +124,16 @@ def make_discretisation(problem) -> Discretisation:
     d.loc_off = np.concatenate([[0], np.cumsum(nloc)])
     ntr = np.array([d.m_trace * dim_p(int(k), dim - 1) for k in fk])
     d.tr_off = np.concatenate([[0], np.cumsum(ntr)])
+    d.neumann = np.zeros(skel.n_faces, dtype=bool)
+    tag = getattr(problem, "bface_tag", None)
+    if tag is not None:
+        tag = np.asarray(tag)
+        if tag.shape != skel.elem_faces.shape or not np.isin(tag, (0, 1)).all():
+            raise ValueError("bface_tag: [n_elem, dim+1] of 0 (Dirichlet) or 1 (Neumann)")
+        faces = skel.elem_faces[tag == 1]
+        if (~skel.is_boundary[faces]).any():
+            raise ValueError("bface_tag: Neumann tag on an interior face")
+        d.neumann[faces] = True
     return d
 
 
@@ -172,11 +189,11 @@ def face_quadrature(disc, g, deg):
 
 
 def project_boundary(disc: Discretisation, func, t=0.0):
-    """L2 projection of Dirichlet data onto the trace space of every boundary face.
+    """L2 projection of Dirichlet data onto the trace space of every Dirichlet boundary face.
     Maxwell: func returns the full field; its tangential part in the face frame is used.
-    Returns a full-length trace vector (zeros on interior faces)."""
+    Returns a full-length trace vector (zeros on interior and Neumann faces)."""
     lam = np.zeros(disc.tr_off[-1])
-    for g in np.nonzero(disc.skel.is_boundary)[0]:
+    for g in np.nonzero(disc.skel.is_boundary & ~disc.neumann)[0]:
         kf = int(disc.face_k[g])
         st, y, w = face_quadrature(disc, g, 2 * kf + 6)
         psi = pkd_eval(kf, st)
@@ -191,6 +208,29 @@ def project_boundary(disc: Discretisation, func, t=0.0):
         coef = np.linalg.solve(Hm, rhs.T).T
         lam[disc.tr_off[g]:disc.tr_off[g + 1]] = coef.ravel()
     return lam
+
+
+def neumann_load(disc: Discretisation, func, t=0.0):
+    """Tested Neumann data <g_N, mu_l>_F on every Neumann face (zeros elsewhere), the
+    right-hand side of the face's flux row (section 4.1.2, Gamma_N part of the trace
+    equation).  func(x, n, t) -> the prescribed flux at the points x with n the outward unit
+    normal: acoustic v.n (scalar), elastic the traction sigma n (3), Maxwell n x H (3; its
+    components along the face frame t1, t2 are tested)."""
+    out = np.zeros(disc.tr_off[-1])
+    for g in np.nonzero(disc.neumann)[0]:
+        kf = int(disc.face_k[g])
+        st, y, w = face_quadrature(disc, g, 2 * kf + 6)
+        psi = pkd_eval(kf, st)
+        e = int(disc.skel.face_elems[g, 0])
+        cen = disc.xyz[disc.elem_vert[e]].mean(axis=0)
+        _, nrm = face_measure_and_normal(disc.xyz, disc.skel.faces[g], cen)
+        vals = np.asarray(func(y, np.broadcast_to(nrm, y.shape), t), dtype=np.float64)
+        vals = vals.reshape(y.shape[0], -1)
+        if disc.physics in ("maxwell", "maxwell_glm"):
+            t1, t2 = face_frame(disc.xyz, disc.skel.faces[g])
+            vals = np.stack([vals @ t1, vals @ t2], axis=1)
+        out[disc.tr_off[g]:disc.tr_off[g + 1]] = np.einsum("q,ql,qc->cl", w, psi, vals).ravel()
+    return out
 
 
 def point_source_rhs(disc: Discretisation, points):
@@ -261,15 +301,25 @@ def condense(disc: Discretisation, a: float, f_loc, g_tr=None):
 
 
 def boundary_trace_mask(disc: Discretisation):
+    """Trace dofs of the Dirichlet faces (the rows that become lam = lam_D)."""
     mask = np.zeros(disc.tr_off[-1], dtype=bool)
-    for g in np.nonzero(disc.skel.is_boundary)[0]:
+    for g in np.nonzero(disc.skel.is_boundary & ~disc.neumann)[0]:
+        mask[disc.tr_off[g]:disc.tr_off[g + 1]] = True
+    return mask
+
+
+def neumann_trace_mask(disc: Discretisation):
+    """Trace dofs of the Neumann faces (flux rows with the tested datum on the right)."""
+    mask = np.zeros(disc.tr_off[-1], dtype=bool)
+    for g in np.nonzero(disc.neumann)[0]:
         mask[disc.tr_off[g]:disc.tr_off[g + 1]] = True
     return mask
 
 
 def trace_solve(disc: Discretisation, cond: Condensed, lam_bnd):
-    """Solve K lam = r on the interior trace dofs with the Dirichlet values lam_bnd
-    fixed on boundary faces (sparse LU)."""
+    """Solve K lam = r on the trace dofs of interior and Neumann faces with the Dirichlet
+    values lam_bnd fixed on Dirichlet faces (sparse LU); the Neumann rows add lam_bnd (the
+    tested flux data) to r."""
     bm = boundary_trace_mask(disc)
     im = ~bm
     r = cond.r
@@ -278,6 +328,9 @@ def trace_solve(disc: Discretisation, cond: Condensed, lam_bnd):
     LB = np.asarray(lam_bnd).reshape(R.shape[0], -1)
     if LB.shape[1] != R.shape[1]:
         LB = np.repeat(LB, R.shape[1], axis=1)
+    nm = neumann_trace_mask(disc)
+    R = R.copy()
+    R[nm] += LB[nm]
     K = cond.K.tocsr()
     Kii = K[im][:, im].tocsc()
     Kib = K[im][:, bm]
@@ -338,6 +391,8 @@ def solve_full(disc: Discretisation, a: float, f_loc, lam_bnd):
     rhs = np.zeros(nl + nt)
     rhs[:nl] = f_loc
     rhs[nl:][bm] = np.asarray(lam_bnd)[bm]
+    nm = neumann_trace_mask(disc)
+    rhs[nl:][nm] = np.asarray(lam_bnd)[nm]     # tested Neumann flux data
     sol = spla.spsolve(Mglob.tocsc(), rhs)
     return sol[:nl], sol[nl:]
 

@@ -1,8 +1,8 @@
 """Seeded synthetic inputs shared by the HIP path's tests/benchmark and the CPU oracle.
 
 This package holds input data only: simplicial meshes of the unit square / unit cube,
-vertex jitter, per-element material coefficients, polynomial degrees and point-source
-locations.  It contains none of the discretisation's arithmetic (no basis, quadrature,
+vertex jitter, per-element material coefficients, polynomial degrees, point-source
+locations and Neumann tags of box faces.  It contains none of the discretisation's arithmetic (no basis, quadrature,
 local matrices or solves), so that the oracle and the GPU library stay independent.
 """
 from .rhs import random_vector  # noqa: F401
@@ -13,5 +13,6 @@ from .meshes import (  # noqa: F401
     five_tet_box,
     jitter_vertices,
     make_problem,
+    tag_box_faces,
     CONFIGS,
 )

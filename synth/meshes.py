@@ -159,6 +159,7 @@ class Problem:
     nrhs: int = 1
     sources: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
     par_names: tuple = ()
+    bface_tag: np.ndarray | None = None   # [n_elem, dim+1] int8: 1 = Neumann boundary face
 
     @property
     def n_elem(self) -> int:
@@ -232,3 +233,20 @@ CONFIGS = {
     4: dict(name="acoustic3d_pvar", elems=200000),
     5: dict(name="maxwell3d", elems=196608),
 }
+
+
+def tag_box_faces(problem: Problem, planes) -> np.ndarray:
+    """Neumann tags [n_elem, dim+1] (local face f = the face opposite vertex f) for the boundary
+    faces of the unit box lying on the given planes, e.g. [(0, 0.0), (2, 1.0)] for x = 0 and
+    z = 1; every other face gets 0.  Sets problem.bface_tag and returns it."""
+    ev, xyz = problem.elem_vert, problem.xyz
+    nv = ev.shape[1]
+    tag = np.zeros(ev.shape, dtype=np.int8)
+    for f in range(nv):
+        fv = xyz[np.delete(ev, f, axis=1)]          # [ne, d, dim]
+        for axis, val in planes:
+            on = np.all(np.abs(fv[:, :, axis] - val) < 1e-12, axis=1)
+            tag[on, f] = 1
+    problem.bface_tag = tag
+    return tag
+
