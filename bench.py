@@ -385,6 +385,52 @@ def run_cached(p, prec, steps, warmup):
     return out
 
 
+def run_step_graph(p, steps, warmup):
+    """Secondary figure: whole DIRK(3,3) steps (hdg_step, FP64, factors kept across the stages)
+    run eagerly, with a host synchronisation per CG iteration, against the same steps replayed
+    as one hipGraph with the CG convergence test on the device (options.graph_step).  Both
+    contexts step the same initial data; the final states agree to the last bits."""
+    import torch
+
+    from paper_1807_00086_amd import Solver
+    k = int(p.degree[0])
+    out = {}
+    finals = {}
+    for mode in ("eager", "graph"):
+        s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=k, precision="fp64", krylov_tol=1e-13,
+                   cache_factors=True, graph_step=(mode == "graph"))
+        nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+        vp = s.volume_points()
+        p0 = np.sin(2 * np.pi * vp[:, 0])
+        u = torch.as_tensor(s.project_volume(np.stack([p0, 0 * p0, 0 * p0, p0], 1)), device="cuda")
+        bp = s.boundary_points()
+        lbs = torch.as_tensor(np.stack([s.project_boundary(np.sin(2 * np.pi * (bp[:, 0] - c * p.dt))[:, None])
+                                        for c in (GAMMA, 0.5 * (1 + GAMMA), 1.0)]), device="cuda")
+        lam = torch.zeros(nt, dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            s.step(0.0, p.dt, "dirk33", u, lam, lbs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        replays = 0
+        for _ in range(steps):
+            s.step(0.0, p.dt, "dirk33", u, lam, lbs)
+            replays += s.query("step_graph")
+        torch.cuda.synchronize()
+        out[f"{mode}_ms_step"] = 1e3 * (time.perf_counter() - t0) / steps
+        out[f"{mode}_iters_last_stage"] = s.query("last_iters")
+        if mode == "graph":
+            out["graph_replays"] = replays
+            out["graph_cg_iters_per_stage"] = s.query("step_graph_iters")
+        finals[mode] = u.cpu().numpy()
+        s.close()
+        del u, lbs, lam
+        torch.cuda.empty_cache()
+    out["graph_vs_eager_max_rel"] = float(np.abs(finals["graph"] - finals["eager"]).max() /
+                                          np.abs(finals["eager"]).max())
+    out["speedup"] = out["eager_ms_step"] / out["graph_ms_step"]
+    return out
+
+
 def run_workload(cfg, prec, steps, warmup, physics=None):
     """Element-kernel throughput of one of the other workloads at full size (secondary figures,
     not the headline): elastic k = 4 (3), p-heterogeneous acoustics with 32 point-source
@@ -605,6 +651,10 @@ def main():
                  "(right-hand-side condensation + recover [+ refinement element passes]); "
                  "one factorisation per dt, not per stage",
         **{pr: run_cached(p, pr, args.steps, args.warmup) for pr in precs}}
+    out["step_graph"] = {"basis": "secondary: whole DIRK(3,3) steps (hdg_step, FP64, cached factors) eager "
+                                  "against one hipGraph replay per step", **run_step_graph(p, 3, 1)}
+    print(f"step graph: {out['step_graph']['eager_ms_step']:.2f} ms eager, "
+          f"{out['step_graph']['graph_ms_step']:.2f} ms graph", file=sys.stderr, flush=True)
     if not args.no_workloads:
         # the other workloads at full size, element kernels of one stage (secondary figures)
         out["other_workloads"] = {}

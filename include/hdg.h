@@ -45,6 +45,7 @@
 #ifndef HDG_H
 #define HDG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -86,6 +87,12 @@ typedef struct {
     const int64_t* elem_vert;   /* host [n_elem][dim+1], positively oriented                  */
     const int8_t* degree;       /* host [n_elem] polynomial degree (1..5); NULL: options.k.
                                    Degrees that differ between elements: 3D acoustics only  */
+    const int8_t* bface_tag;    /* host [n_elem][dim+1] or NULL (every boundary face
+                                   Dirichlet): the condition on the local face opposite vertex
+                                   f, 0 Dirichlet, 1 Neumann (section 4.1.2, the Gamma_N part
+                                   of the trace equation: the face keeps its element's flux
+                                   row, whose right-hand side is the tested datum <g_N, mu>_F).
+                                   Interior faces must carry 0 (else HDG_E_MESH).            */
 } hdg_mesh_desc;
 
 typedef struct {
@@ -149,6 +156,18 @@ typedef struct {
                                    eagerly (reporting HDG_E_NOCONV as usual if it fails) and the
                                    graph is captured again with twice the iterations (at most
                                    krylov_maxit).  The iterate is that of the eager step. */
+    /* Device memory of the context's workspaces.  Both NULL: hipMalloc / hipFree.  Both set:
+       every device workspace (element factors and buffers, trace system, Krylov and stage
+       vectors, tables) comes from dev_alloc(alloc_user, bytes), which returns device memory
+       of the current device aligned to 256 bytes or NULL on failure (HDG_E_ALLOC), and goes
+       back through dev_free(alloc_user, ptr) at hdg_destroy (or when a workspace is
+       replaced), after the context's stream has been synchronised.  For callers whose
+       memory is pooled, e.g. a framework's caching allocator: the blocks are used on the
+       context's stream only.  Pinned host memory and the file-scope scratch of
+       hdg_trace_solve_static are not affected.  Exactly one of the two set: HDG_E_ARG.  */
+    void* (*dev_alloc)(void* alloc_user, size_t bytes);
+    void (*dev_free)(void* alloc_user, void* ptr);
+    void* alloc_user;
 } hdg_options;
 
 /* Query keys for hdg_query. */
@@ -200,8 +219,10 @@ hdg_status hdg_query(const hdg_ctx* ctx, int key, int64_t* value);
  * system in face-block sparse rows with the Dirichlet faces eliminated.
  *   a        stage coefficient d_ii / dt (> 0)
  *   f_loc    device [n_local_dofs][nrhs] FP64 local right-hand side (a Mw u* + sources)
- *   lam_bnd  device [n_trace_dofs][nrhs] FP64; only boundary-face entries are read
- *            (L2 projection of the Dirichlet data, see hdg_project_boundary)
+ *   lam_bnd  device [n_trace_dofs][nrhs] FP64; only boundary-face entries are read:
+ *            on Dirichlet faces the L2 projection of the Dirichlet data, on Neumann faces
+ *            (mesh.bface_tag) the tested flux datum <g_N, mu_l>_F, added to the right-hand
+ *            side of the face's flux rows (see hdg_project_boundary)
  * Asynchronous; a zero or non-finite pivot is reported by the next synchronising call
  * (hdg_trace_solve / hdg_recover) as HDG_E_SINGULAR.
  */
@@ -287,7 +308,8 @@ hdg_status hdg_last_residual(const hdg_ctx* ctx, double* rel);
  * condenses its right-hand side (hdg_condense_rhs).
  *   u          device [n_local_dofs][nrhs] in: u^n, out: u^{n+1}
  *   lambda     device [n_trace_dofs][nrhs] in: initial guess, out: trace of the last stage
- *   lam_bnd    device [n_stages][n_trace_dofs][nrhs] Dirichlet data at t + c_i dt
+ *   lam_bnd    device [n_stages][n_trace_dofs][nrhs] boundary data at t + c_i dt (as for
+ *              hdg_condense)
  *   src        device [n_local_dofs][nrhs] or NULL: time-independent tested source
  * With options.graph_step the step is one graph replay after the first call with the same
  * arguments (see there); HDG_Q_STEP_GRAPH tells whether the last step was a replay.
@@ -300,14 +322,17 @@ hdg_status hdg_step(hdg_ctx* ctx, double t, double dt, int scheme, double* u, do
 hdg_status hdg_apply_mass(hdg_ctx* ctx, double a, const double* u, double* f);
 
 /*
- * Projection helpers (L2 projections that fix initial data and Dirichlet traces).
+ * Projection helpers (L2 projections that fix initial data and boundary data).
  * hdg_volume_points: host out [n_vol_points][dim] physical quadrature points, element-major.
  * hdg_project_volume: vals host [n_vol_points][m_local] field values at those points ->
  *   u host [n_local_dofs] (nrhs = 1 layout) coefficients u_i = (val, phi_i)_K / |J_K|.
  * hdg_boundary_points: host out [n_bnd_points][dim], boundary faces in face order.
  * hdg_project_boundary: vals host [n_bnd_points][dim or 1] -> lam host [n_trace_dofs]
- *   (zero on interior faces); Maxwell takes the full E vector and keeps its tangential
- *   part along (t1, t2).
+ *   (zero on interior faces).  Dirichlet faces: vals is the trace (acoustic p, elastic v,
+ *   Maxwell the full E vector, of which the tangential part along (t1, t2) is kept) and lam
+ *   its L2 projection.  Neumann faces: vals is the prescribed flux with the outward normal
+ *   n (acoustic v.n, elastic the traction sigma n, Maxwell the vector n x H) and lam its
+ *   tested values <g, mu_l>_F.
  */
 hdg_status hdg_volume_points(const hdg_ctx* ctx, double* pts);
 hdg_status hdg_project_volume(const hdg_ctx* ctx, const double* vals, double* u);

@@ -20,6 +20,28 @@ namespace hdg {
 int launch_condense_acoustic(hdg_ctx* c, double a, const double* f_loc);
 int launch_condense_general(hdg_ctx* c, double a, const double* f_loc);
 
+int dev_malloc(hdg_ctx* c, void** p, size_t bytes) {
+    if (!c->dev_alloc) return (int)hipMalloc(p, bytes);
+    void* q = c->dev_alloc(c->alloc_user, bytes);
+    if (!q) {
+        *p = nullptr;
+        return (int)hipErrorOutOfMemory;
+    }
+    if (reinterpret_cast<uintptr_t>(q) % 256 != 0) {   // the kernels' vector loads assume it
+        c->dev_free(c->alloc_user, q);
+        *p = nullptr;
+        return (int)hipErrorInvalidValue;
+    }
+    *p = q;
+    return 0;
+}
+
+void dev_release(hdg_ctx* c, void* p) {
+    if (!p) return;
+    if (c->dev_free) c->dev_free(c->alloc_user, p);
+    else (void)hipFree(p);
+}
+
 // Autotune table: one line per tuned class, "device physics k kF nrhs precision schedule ms_0
 // ms_1 ms_2" (0: schedule not built for the class); '#' starts a comment line.
 namespace {
@@ -106,10 +128,10 @@ int fail(hdg_ctx* c, int code, const std::string& msg) {
 template <typename T>
 int dalloc(hdg_ctx* c, T** p, size_t count) {
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    hipError_t e = (hipError_t)dev_malloc(c, (void**)p, count * sizeof(T));
     if (e != hipSuccess) {
         std::ostringstream os;
-        os << "hipMalloc of " << count * sizeof(T) << " bytes failed: " << hipGetErrorString(e);
+        os << "device allocation of " << count * sizeof(T) << " bytes failed: " << hipGetErrorString(e);
         return fail(c, HDG_E_ALLOC, os.str());
     }
     return HDG_OK;
@@ -156,9 +178,7 @@ int upload_tables(hdg_ctx* c, DeviceTables& t, const RefTables& ref, const RefFa
     return HDG_OK;
 }
 
-void dfree(void* p) {
-    if (p) (void)hipFree(p);
-}
+void dfree(hdg_ctx* c, void* p) { dev_release(c, p); }
 
 struct EventTimer {
     hdg_ctx* c;
@@ -246,6 +266,14 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     if (o->autotune_table) c->tune_path = o->autotune_table;
     c->use_graph = o->use_graph != 0;
     c->graph_step = o->graph_step != 0;
+    if ((o->dev_alloc == nullptr) != (o->dev_free == nullptr)) {
+        g_init_err = "dev_alloc and dev_free: both or neither";
+        delete c;
+        return HDG_E_ARG;
+    }
+    c->dev_alloc = o->dev_alloc;
+    c->dev_free = o->dev_free;
+    c->alloc_user = o->alloc_user;
     c->stream = (hipStream_t)stream;
     int st = build_mesh(c, m, p);
     if (st) {
@@ -633,7 +661,7 @@ static int refine_scale(hdg_ctx* c, std::vector<double>& scale) {
 static int refine_residual(hdg_ctx* c, const double* elem_nrm, const std::vector<double>& scale, double* worst) {
     const int R = c->nrhs;
     std::vector<double> lo(R), tr(R);
-    if (launch_assemble_rhs64(c, c->d_re64) ||
+    if (launch_assemble_rhs64(c, c->d_re64, c->d_lbnd_saved) ||
         launch_col_sq(c, c->n_elem, R, elem_nrm, lo.data()) ||
         launch_col_sq(c, c->n_faces * c->bs, R, c->d_rhs, tr.data()))
         return fail(c, HDG_E_HIP, "refinement residual reduction failed");
@@ -667,7 +695,7 @@ static int refine_trace_step(hdg_ctx* c, double* lambda, float* t_sol) {
     int r;
     {
         EventTimer t(c, t_sol);
-        if (launch_assemble_rhs64(c, c->d_re64)) return fail(c, HDG_E_HIP, "refinement assembly launch failed");
+        if (launch_assemble_rhs64(c, c->d_re64, c->d_lbnd_saved)) return fail(c, HDG_E_HIP, "refinement assembly launch failed");
         HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
         int its;
         double rr;
@@ -1085,6 +1113,23 @@ hdg_status hdg_project_boundary(const hdg_ctx* c, const double* vals, double* la
     const int vw = (c->physics == HDG_ACOUSTIC) ? 1 : 3;
     for (size_t b = 0; b < c->bface_list.size(); ++b) {
         int64_t F = c->bface_list[b];
+        // Dirichlet: the projection (face mass = s_F I, the quadrature sum carries s_F);
+        // Neumann: the tested datum <g, psi_l>_F = s_F times that sum
+        double sF = 1.0;
+        if (c->face_bnd[F] == 2) {
+            const int64_t* fv = &c->face_vert[F * d];
+            double T[2][3] = {};
+            for (int s2 = 0; s2 + 1 < d; ++s2)
+                for (int r = 0; r < d; ++r) T[s2][r] = c->xyz[fv[s2 + 1] * d + r] - c->xyz[fv[0] * d + r];
+            if (d == 3) {
+                const double cx = T[0][1] * T[1][2] - T[0][2] * T[1][1];
+                const double cy = T[0][2] * T[1][0] - T[0][0] * T[1][2];
+                const double cz = T[0][0] * T[1][1] - T[0][1] * T[1][0];
+                sF = std::sqrt(cx * cx + cy * cy + cz * cz);
+            } else {
+                sF = std::sqrt(T[0][0] * T[0][0] + T[0][1] * T[0][1]);
+            }
+        }
         for (int comp = 0; comp < mt; ++comp)
             for (int l = 0; l < NF; ++l) {
                 double acc = 0.0;
@@ -1099,7 +1144,7 @@ hdg_status hdg_project_boundary(const hdg_ctx* c, const double* vals, double* la
                     }
                     acc += w[q] * psi[q * NF + l] * g;
                 }
-                lam[F * c->bs + comp * NF + l] = acc;   // face mass = s_F I, quadrature carries s_F
+                lam[F * c->bs + comp * NF + l] = sF * acc;
             }
     }
     return HDG_OK;
@@ -1193,10 +1238,10 @@ void hdg_destroy(hdg_ctx* c) {
                     c->d_stage, c->d_ustar, c->d_fstage, c->d_loc_off, c->d_efnf, c->d_face_nf, c->d_edeg,
                     c->d_cls[1], c->d_cls[2], c->d_cls[3], c->d_cls[4], c->d_cls[5]};
     if (c->stream || c->d_geom) (void)hipStreamSynchronize(c->stream);
-    for (void* p : ptrs) dfree(p);
+    for (void* p : ptrs) dfree(c, p);
     for (auto& t : c->tabk) {
         void* tp[] = {t.Sr, t.Mf, t.Tsym, t.Ef, t.Tfull, t.Sr32, t.Mf32, t.Tsym32, t.Ef32, t.Tfull32, t.SrT, t.EfT};
-        for (void* p : tp) dfree(p);
+        for (void* p : tp) dfree(c, p);
     }
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);

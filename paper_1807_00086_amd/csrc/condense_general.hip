@@ -1527,11 +1527,18 @@ int dispatch_gen(hdg_ctx* c, double a, const double* f_loc) {
             (void)hipGraphExecDestroy(c->gexec);
             c->gexec = nullptr;
         }
-        if (c->d_xscratch) (void)hipFree(c->d_xscratch);
+        if (c->sgexec) {   // a captured step reads the old scratch
+            (void)hipGraphExecDestroy(c->sgexec);
+            c->sgexec = nullptr;
+        }
+        if (c->d_xscratch) {
+            (void)hipStreamSynchronize(c->stream);
+            dev_release(c, c->d_xscratch);
+        }
         c->d_xscratch = nullptr;
         c->xscratch_bytes = 0;
-        hipError_t er = hipMalloc(&c->d_xscratch, total);
-        if (er != hipSuccess) return (int)er;
+        const int er = dev_malloc(c, &c->d_xscratch, total);
+        if (er) return er;
         c->xscratch_bytes = total;
     }
     GenOp g;

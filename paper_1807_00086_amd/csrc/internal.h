@@ -72,7 +72,8 @@ struct hdg_ctx {
     std::vector<int32_t> face_elem;            // [nf][2]
     std::vector<int32_t> face_lf;              // [nf][2]
     std::vector<int64_t> face_vert;            // [nf][d] sorted global ids
-    std::vector<uint8_t> face_bnd;             // [nf]
+    std::vector<uint8_t> face_bnd;             // [nf] 0 interior, 1 Dirichlet, 2 Neumann
+    int64_t n_neumann = 0;
     std::vector<double> geom;                  // [ne][GEOM_STRIDE]
     std::vector<double> frame;                 // [nf][6] Maxwell tangent frame (t1, t2)
     std::vector<int64_t> bface_list;           // boundary faces in face order
@@ -205,11 +206,19 @@ struct hdg_ctx {
     bool sg_reuse = false;      // captured with the factors of last_a kept (right-hand sides only)
     int sg_nit = 0;             // CG iterations per stage in the captured graph
     bool sg_replayed = false;   // the last hdg_step ran as a graph replay
+
+    // device memory of the workspaces (options.dev_alloc / dev_free; null: hipMalloc / hipFree)
+    void* (*dev_alloc)(void*, size_t) = nullptr;
+    void (*dev_free)(void*, void*) = nullptr;
+    void* alloc_user = nullptr;
 };
 
 namespace hdg {
 // mesh.cpp
 int build_mesh(hdg_ctx* c, const hdg_mesh_desc* m, const hdg_phys_desc* p);
+// device memory through the context's allocator (hipMalloc when none is set); hipError_t as int
+int dev_malloc(hdg_ctx* c, void** p, size_t bytes);
+void dev_release(hdg_ctx* c, void* p);
 // kernels (launchers, in .hip files); all return hipError_t as int
 int launch_condense(hdg_ctx* c, double a, const double* f_loc, const double* lam_bnd);
 int launch_assemble(hdg_ctx* c, const double* lam_bnd);
@@ -227,7 +236,7 @@ int launch_refine_acoustic(hdg_ctx* c, const double* lam, const double* dlam, in
 // r_e and z for a new f_loc; launch_assemble_rhs then assembles the trace right-hand side only.
 int launch_condense_rhs_acoustic(hdg_ctx* c, double a, const double* f_loc);
 int launch_assemble_rhs(hdg_ctx* c, const double* lam_bnd);
-int launch_assemble_rhs64(hdg_ctx* c, const double* re64);
+int launch_assemble_rhs64(hdg_ctx* c, const double* re64, const double* lam_bnd);
 int launch_apply_mass(hdg_ctx* c, double a, const double* u, double* f);
 int launch_block_inverse(hdg_ctx* c);
 // lowp: products with the FP32 copy of the matrix (correction solves of the refinement, whose

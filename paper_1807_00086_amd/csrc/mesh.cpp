@@ -88,6 +88,7 @@ int build_mesh(hdg_ctx* c, const hdg_mesh_desc* m, const hdg_phys_desc* p) {
         i = j;
     }
     c->n_faces = nf;
+    // 0 interior, 1 Dirichlet, 2 Neumann
     c->face_bnd.assign(nf, 0);
     c->bface_list.clear();
     for (int64_t f = 0; f < nf; ++f)
@@ -96,6 +97,25 @@ int build_mesh(hdg_ctx* c, const hdg_mesh_desc* m, const hdg_phys_desc* p) {
             c->bface_list.push_back(f);
         }
     c->n_bfaces = (int64_t)c->bface_list.size();
+    c->n_neumann = 0;
+    if (m->bface_tag) {
+        for (int64_t e = 0; e < ne; ++e)
+            for (int f = 0; f < nv; ++f) {
+                const int8_t t = m->bface_tag[e * nv + f];
+                if (t == 0) continue;
+                const int32_t F = c->elem_face[e * nv + f];
+                if (t != 1) {
+                    c->err = "bface_tag: 0 (Dirichlet) or 1 (Neumann) expected";
+                    return HDG_E_MESH;
+                }
+                if (c->face_elem[2 * F + 1] >= 0) {
+                    c->err = "bface_tag: Neumann tag on an interior face";
+                    return HDG_E_MESH;
+                }
+                c->face_bnd[F] = 2;
+                ++c->n_neumann;
+            }
+    }
 
     // ---- permutations of each element face
     c->elem_perm.assign(ne * nv, 0);

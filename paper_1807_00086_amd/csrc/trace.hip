@@ -37,10 +37,12 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
     const double* __restrict__ lam_bnd, const int8_t* __restrict__ face_nf, double* __restrict__ bsr,
     double* __restrict__ rhs) {
     // face_nf (variable degree): modes of a face at or above its own size are padding and get
-    // identity rows with a zero right-hand side
+    // identity rows with a zero right-hand side.  face_bnd: 1 Dirichlet (identity rows, the
+    // values moved to the neighbours' right-hand sides), 2 Neumann (the one element's flux rows
+    // with lam_bnd, the tested flux datum, added to the right-hand side)
     const int nslot = 1 + 2 * d, nv = d + 1;
     for (int64_t F = blockIdx.x; F < nf; F += gridDim.x) {
-        const bool bnd = face_bnd[F] != 0;
+        const bool bnd = face_bnd[F] == 1;
         const int nfF = face_nf ? (int)face_nf[F] : bs;
         int32_t es[2] = {face_elem[2 * F], face_elem[2 * F + 1]};
         int32_t ls[2] = {face_lf[2 * F], face_lf[2 * F + 1]};
@@ -54,6 +56,7 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
                     v = (a == b) ? 1.0 : 0.0;
                 } else {
                     for (int s = 0; s < 2; ++s) {
+                        if (es[s] < 0) continue;
                         const T* K = Ke + (size_t)es[s] * tt * tt;
                         v += kget(K, tt, ls[s] * bs + a, ls[s] * bs + b, ktile);
                     }
@@ -67,7 +70,7 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
                     int q = (m < lf) ? m : m + 1;
                     int32_t F2 = eface[(size_t)e * nv + q];
                     const int nf2 = face_nf ? (int)face_nf[F2] : bs;
-                    if (!face_bnd[F2] && a < nfF && b < nf2)
+                    if (face_bnd[F2] != 1 && a < nfF && b < nf2)
                         v = sign * kget(Ke + (size_t)e * tt * tt, tt, lf * bs + a, q * bs + b, ktile);
                 }
             }
@@ -81,16 +84,17 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
             } else if (a >= nfF) {
                 v = 0.0;
             } else {
-                v = 0.0;
+                v = face_bnd[F] == 2 ? lam_bnd[((size_t)F * bs + a) * R + r] : 0.0;
                 for (int s = 0; s < 2; ++s) {
                     int32_t e = es[s];
+                    if (e < 0) continue;
                     int lf = ls[s];
                     const T* K = Ke + (size_t)e * tt * tt;
                     double acc = (double)re[((size_t)e * tt + lf * bs + a) * R + r];
                     for (int q = 0; q < nv; ++q) {
                         if (q == lf) continue;
                         int32_t F2 = eface[(size_t)e * nv + q];
-                        if (!face_bnd[F2]) continue;
+                        if (face_bnd[F2] != 1) continue;
                         const int nf2 = face_nf ? (int)face_nf[F2] : bs;
                         for (int b = 0; b < nf2; ++b)
                             acc -= kget(K, tt, lf * bs + a, q * bs + b, ktile) *
@@ -105,22 +109,26 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
     }
 }
 
-// right-hand side of a correction equation: sum over the face's elements of the FP64
-// per-element contributions; Dirichlet faces carry a zero correction
+// right-hand side of a correction equation (the trace rows of the FP64 residual): sum over the
+// face's elements of the FP64 per-element contributions, plus the tested flux datum on Neumann
+// faces; Dirichlet faces carry a zero correction
 __global__ __launch_bounds__(NT) void assemble_rhs64_kernel(int64_t nf, int bs, int tt, int R, double sign,
                                                             const int32_t* __restrict__ face_elem,
                                                             const int32_t* __restrict__ face_lf,
                                                             const uint8_t* __restrict__ face_bnd,
                                                             const double* __restrict__ re64,
+                                                            const double* __restrict__ lam_bnd,
                                                             double* __restrict__ rhs) {
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= nf * bs * R) return;
     const int64_t F = gid / ((int64_t)bs * R);
     const int rem = (int)(gid % ((int64_t)bs * R));
     double v = 0.0;
-    if (!face_bnd[F]) {
+    if (face_bnd[F] != 1) {
+        if (face_bnd[F] == 2) v = lam_bnd[gid];
         for (int s = 0; s < 2; ++s) {
             const int32_t e = face_elem[2 * F + s];
+            if (e < 0) continue;
             const int lf = face_lf[2 * F + s];
             v += re64[((size_t)e * tt + lf * bs) * R + rem];
         }
@@ -472,10 +480,11 @@ __global__ __launch_bounds__(NT) void copy_bnd_kernel(int64_t nf, int bs, int R,
     int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= nf * bs * R) return;
     int64_t F = gid / ((int64_t)bs * R);
-    if (bnd[F]) dst[gid] = src[gid];
+    if (bnd[F] == 1) dst[gid] = src[gid];   // Dirichlet values
 }
 
-// partial sums of squares per rhs column over the rows of the boundary (Dirichlet) faces only,
+// partial sums of squares per rhs column over the rows of the boundary faces only (the
+// Dirichlet values and the tested Neumann data: the boundary part of the right-hand side),
 // in the thread layout of dot_partial_kernel (rows are face-major: row / bs is the face)
 __global__ __launch_bounds__(NT) void bnd_sq_partial_kernel(int64_t n, int R, int bs, const uint8_t* __restrict__ bnd,
                                                             const double* __restrict__ x, double* __restrict__ part) {
@@ -534,10 +543,10 @@ static int launch_asm(hdg_ctx* c, const double* lam_bnd) {
 int launch_assemble(hdg_ctx* c, const double* lam_bnd) { return launch_asm<true>(c, lam_bnd); }
 int launch_assemble_rhs(hdg_ctx* c, const double* lam_bnd) { return launch_asm<false>(c, lam_bnd); }
 
-int launch_assemble_rhs64(hdg_ctx* c, const double* re64) {
+int launch_assemble_rhs64(hdg_ctx* c, const double* re64, const double* lam_bnd) {
     const int64_t n = c->n_faces * c->bs * c->nrhs;
     hipLaunchKernelGGL(assemble_rhs64_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->bs, c->n_tr,
-                       c->nrhs, c->K_sign, c->d_face_elem, c->d_face_lf, c->d_face_bnd, re64, c->d_rhs);
+                       c->nrhs, c->K_sign, c->d_face_elem, c->d_face_lf, c->d_face_bnd, re64, lam_bnd, c->d_rhs);
     return (int)hipGetLastError();
 }
 

@@ -43,11 +43,16 @@ class HDGError(RuntimeError):
 
 class MeshDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_vert", C.c_int64), ("xyz", C.c_void_p),
-                ("n_elem", C.c_int64), ("elem_vert", C.c_void_p), ("degree", C.c_void_p)]
+                ("n_elem", C.c_int64), ("elem_vert", C.c_void_p), ("degree", C.c_void_p),
+                ("bface_tag", C.c_void_p)]
 
 
 class PhysDesc(C.Structure):
     _fields_ = [("physics", C.c_int), ("elem_par", C.c_void_p), ("stab_scale", C.c_double)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class Options(C.Structure):
@@ -56,7 +61,37 @@ class Options(C.Structure):
                 ("refine_tol", C.c_double), ("refine_maxit", C.c_int),
                 ("refine_inner_tol", C.c_double), ("cache_factors", C.c_int),
                 ("autotune", C.c_int), ("autotune_table", C.c_char_p), ("use_graph", C.c_int),
-                ("graph_step", C.c_int)]
+                ("graph_step", C.c_int), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("alloc_user", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Device workspaces of a context from torch's caching allocator (options.dev_alloc /
+    dev_free): each block is a uint8 tensor kept alive until the library returns it."""
+
+    def __init__(self, device=None):
+        import torch
+        self._torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        self.blocks = {}
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    def _alloc(self, user, nbytes):
+        try:
+            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=self.device)
+        except RuntimeError:
+            return None
+        p = t.data_ptr()
+        self.blocks[p] = t
+        return p
+
+    def _free(self, user, ptr):
+        self.blocks.pop(ptr, None)
+
+    @property
+    def nbytes(self):
+        return sum(t.numel() for t in self.blocks.values())
 
 
 _lib = None
@@ -166,7 +201,8 @@ class Solver:
     def __init__(self, xyz, elem_vert, physics, elem_par, k=None, degree=None, precision="fp64",
                  nrhs=1, stab_scale=1.0, krylov_tol=1e-13, krylov_maxit=5000, refine_tol=1e-13,
                  refine_maxit=10, refine_inner_tol=1e-6, cache_factors=False, autotune=False,
-                 autotune_table=None, use_graph=False, graph_step=False, stream=None):
+                 autotune_table=None, use_graph=False, graph_step=False, bface_tag=None, allocator=None,
+                 stream=None):
         self.lib = load_library()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._ev = np.ascontiguousarray(elem_vert, dtype=np.int64)
@@ -175,11 +211,17 @@ class Solver:
         par[:, :ep.shape[1]] = ep
         self._par = np.ascontiguousarray(par)
         self._deg = None if degree is None else np.ascontiguousarray(degree, dtype=np.int8)
+        self._tag = None
+        if bface_tag is not None:
+            self._tag = np.ascontiguousarray(bface_tag, dtype=np.int8)
+            if self._tag.shape != self._ev.shape:
+                raise ValueError(f"bface_tag: shape {self._tag.shape}, expected {self._ev.shape}")
         self.dim = self._xyz.shape[1]
         self.physics = PHYSICS[physics] if isinstance(physics, str) else int(physics)
         self.nrhs = int(nrhs)
         md = MeshDesc(self.dim, self._xyz.shape[0], _ptr(self._xyz).value, self._ev.shape[0],
-                      _ptr(self._ev).value, None if self._deg is None else _ptr(self._deg).value)
+                      _ptr(self._ev).value, None if self._deg is None else _ptr(self._deg).value,
+                      None if self._tag is None else _ptr(self._tag).value)
         pd = PhysDesc(self.physics, _ptr(self._par).value, float(stab_scale))
         prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
         od = Options(prec, int(k if k is not None else (int(degree[0]) if degree is not None else 1)),
@@ -187,6 +229,11 @@ class Solver:
                      int(refine_maxit), float(refine_inner_tol), int(bool(cache_factors)),
                      int(bool(autotune)), None if autotune_table is None else os.fsencode(autotune_table),
                      int(bool(use_graph)), int(bool(graph_step)))
+        # allocator: None (hipMalloc) or "torch" / a TorchAllocator (torch's caching allocator)
+        self.allocator = TorchAllocator() if allocator == "torch" else allocator
+        if self.allocator is not None:
+            od.dev_alloc = self.allocator.alloc_fn
+            od.dev_free = self.allocator.free_fn
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream

@@ -87,14 +87,15 @@ def test_face_mass_is_gram_of_face_moments(d, k, kF):
             np.testing.assert_allclose(E[f, p] @ E[f, p].T, Mf[f], atol=1e-12 * max(1.0, np.abs(Mf[f]).max()) * 50)
 
 
-def _init(mesh_xyz, ev, physics="acoustic", k=2, nrhs=1, par=None, degree=None):
+def _init(mesh_xyz, ev, physics="acoustic", k=2, nrhs=1, par=None, degree=None, tag=None):
     lib = hdgmod.load_library()
     xyz = np.ascontiguousarray(mesh_xyz, dtype=np.float64)
     ev = np.ascontiguousarray(ev, dtype=np.int64)
     par = np.ones((ev.shape[0], 3)) if par is None else np.ascontiguousarray(par, dtype=np.float64)
     deg = None if degree is None else np.ascontiguousarray(degree, dtype=np.int8)
+    tag = None if tag is None else np.ascontiguousarray(tag, dtype=np.int8)
     md = hdgmod.MeshDesc(xyz.shape[1], xyz.shape[0], xyz.ctypes.data, ev.shape[0], ev.ctypes.data,
-                         None if deg is None else deg.ctypes.data)
+                         None if deg is None else deg.ctypes.data, None if tag is None else tag.ctypes.data)
     pd = hdgmod.PhysDesc(hdgmod.PHYSICS[physics], par.ctypes.data, 1.0)
     od = hdgmod.Options(0, k, nrhs, 1e-12, 100, 1e-12, 5)
     ctx = C.c_void_p()
@@ -124,6 +125,46 @@ def test_rejects_non_manifold_face():
     ev = np.vstack([p.elem_vert, extra])
     st, msg = _init(xyz, ev)
     assert st == 2 and "non-manifold" in msg
+
+
+def test_rejects_bad_bface_tag():
+    """Neumann tags: 0 or 1 only, and only on boundary faces (HDG_E_MESH before device work)."""
+    from synth import tag_box_faces
+    p = make_problem(2, n=2, k=1)
+    tag = tag_box_faces(p, [(0, 0.0)])
+    assert tag.sum() == 8                       # 2 x 2 squares of 2 triangles on x = 0
+    bad = tag.copy()
+    bad[0, :] = 1                               # the first tet has interior faces
+    st, msg = _init(p.xyz, p.elem_vert, tag=bad)
+    assert st == 2 and "interior" in msg
+    bad = tag * 3
+    st, msg = _init(p.xyz, p.elem_vert, tag=bad)
+    assert st == 2 and "bface_tag" in msg
+
+
+def test_rejects_half_set_allocator_hooks():
+    """dev_alloc without dev_free (or the reverse) is an argument error before device work,
+    and neither hook is called."""
+    calls = []
+    alloc = hdgmod.ALLOC_FN(lambda user, n: calls.append(n) or None)
+    free = hdgmod.FREE_FN(lambda user, p: calls.append(p))
+    p = make_problem(2, n=1, k=1)
+    lib = hdgmod.load_library()
+    xyz = np.ascontiguousarray(p.xyz)
+    ev = np.ascontiguousarray(p.elem_vert)
+    par = np.ones((ev.shape[0], 3))
+    md = hdgmod.MeshDesc(3, xyz.shape[0], xyz.ctypes.data, ev.shape[0], ev.ctypes.data, None, None)
+    pd = hdgmod.PhysDesc(hdgmod.PHYSICS["acoustic"], par.ctypes.data, 1.0)
+    for a, f in ((alloc, None), (None, free)):
+        od = hdgmod.Options(0, 1, 1, 1e-12, 100, 1e-12, 5)
+        if a is not None:
+            od.dev_alloc = a
+        if f is not None:
+            od.dev_free = f
+        ctx = C.c_void_p()
+        st = lib.hdg_init_mesh(C.byref(ctx), C.byref(md), C.byref(pd), C.byref(od), None)
+        assert st == 1 and "dev_alloc" in lib.hdg_last_error(None).decode()
+    assert calls == []
 
 
 def test_rejects_bad_arguments():
