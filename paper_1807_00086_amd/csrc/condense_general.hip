@@ -594,40 +594,105 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
             __syncthreads();
             form_s();
             __syncthreads();
-            // Right-looking elimination S = L_u diag(d) L_u^T with one barrier per pivot: at step
-            // j column j below the diagonal is final, and the threads, as a 16 x 16 grid, update
-            // the trailing lower triangle (rows i = ty mod 16, columns m = tx mod 16, m <= i)
-            // with S[i][m] -= S[i][j] S[m][j] / d_j.  Column j is never written at step j.
-            // Then L = L_u diag(d)^{1/2}: L[i][j] = S[i][j] / sqrt(d_j).
-            const int ty = tid >> 4, tx = tid & 15;
+            // Blocked right-looking factorisation S = L Sigma L^T (Sigma = sign of the pivots, the
+            // identity unless GLM) in panels of 16 columns, three barriers per panel:
+            //   (1) wavefront 0 eliminates the diagonal block in registers (lane c holds column c)
+            //       and writes L11 = L_u |d|^{1/2} with the signs;
+            //   (2) one thread per row below: L21 = S21 L11^{-T} Sigma1 (forward substitution);
+            //   (3) the trailing lower triangle S22 -= L21 Sigma1 L21^T as 16 x 16 matrix-core
+            //       tiles (k = the 16 panel columns), the tiles spread over the wavefronts.
+            // The lower triangle of Sb then holds L (diagonal sqrt|d_j|); the upper triangle is
+            // not read.  Same factors as the unblocked elimination up to rounding order.
             T dmax = 0;
             for (int i = 0; i < N2; ++i) dmax = fmax(dmax, fabs(Sb[i * N2 + i]));
             const T ptol = T(64 * N2) * geps<T>() * dmax;
-            for (int j = 0; j < N2; ++j) {
-                const T djj = Sb[j * N2 + j];
-                if (tid == 0 && (!(fabs(djj) > ptol && djj - djj == T(0)) || (PHYS != PH_GLM && !(djj > T(0)))))
-                    atomicOr(status, 1);
-                const T rinv = piv_rcp(djj);
-                for (int i = j + 1 + ((ty - j - 1) & 15); i < N2; i += 16) {
-                    const T lij = Sb[i * N2 + j] * rinv;
-                    T* Si = &Sb[i * N2];
-                    for (int m = j + 1 + ((tx - j - 1) & 15); m <= i; m += 16) Si[m] -= lij * Sb[m * N2 + j];
+            constexpr int PW = 16, NPAN = (N2 + PW - 1) / PW;
+            for (int pn = 0; pn < NPAN; ++pn) {
+                const int j0 = pn * PW, b = min(PW, N2 - j0), j1 = j0 + b;
+                if (wv == 0) {   // (1)
+                    const int c = min(lane, b - 1);
+                    T x[PW];
+#pragma unroll
+                    for (int i = 0; i < PW; ++i) {
+                        const int ii = min(i, b - 1);
+                        x[i] = i >= b ? T(0) : (ii >= c ? Sb[(j0 + ii) * N2 + j0 + c] : Sb[(j0 + c) * N2 + j0 + ii]);
+                    }
+                    T dl = T(1);
+                    bool bad = false;
+#pragma unroll
+                    for (int j = 0; j < PW; ++j) {
+                        if (j < b) {
+                            const T pv = wbcast(x[j], j);
+                            bad |= !(fabs(pv) > ptol && pv - pv == T(0)) || (PHYS != PH_GLM && !(pv > T(0)));
+                            dl = lane == j ? pv : dl;
+                            const T t = x[j] * piv_rcp(pv);
+#pragma unroll
+                            for (int i = j + 1; i < PW; ++i) x[i] -= wbcast(x[i], j) * t;
+                        }
+                    }
+                    if (bad && lane == 0) atomicOr(status, 1);
+                    const T sg = dl < T(0) ? T(-1) : T(1);
+                    const T isq = sg / sqrt(fabs(dl));
+                    if (lane < b) {
+                        sgn[j0 + lane] = sg;
+                        dinv[j0 + lane] = fabs(isq);   // 1 / L[j][j]
+                    }
+#pragma unroll
+                    for (int j = 0; j < PW; ++j) {
+                        const T sj = wbcast(isq, j);
+                        if (lane < b && j <= lane) Sb[(j0 + lane) * N2 + j0 + j] = x[j] * sj;
+                    }
+                }
+                __syncthreads();
+                for (int i = j1 + tid; i < N2; i += NTG) {   // (2)
+                    T y[PW];
+#pragma unroll
+                    for (int c = 0; c < PW; ++c) {
+                        if (c < b) {
+                            T sv = Sb[i * N2 + j0 + c];
+#pragma unroll
+                            for (int j = 0; j < c; ++j) sv -= Sb[(j0 + c) * N2 + j0 + j] * y[j];
+                            y[c] = sv * dinv[j0 + c];
+                        } else {
+                            y[c] = T(0);
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < PW; ++c)
+                        if (c < b) Sb[i * N2 + j0 + c] = y[c] * sgn[j0 + c];
+                }
+                __syncthreads();
+                {   // (3)
+                    const int nt = (N2 - j1 + 15) / 16, ntile = nt * (nt + 1) / 2;
+                    for (int t = wv; t < ntile; t += NWG) {
+                        int ti = 0;
+                        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+                        const int tm = t - ti * (ti + 1) / 2;
+                        const int i0 = j1 + 16 * ti, m0 = j1 + 16 * tm;
+                        const int ia = min(i0 + li, N2 - 1), mb = min(m0 + li, N2 - 1);
+                        const bool aok = i0 + li < N2, bok = m0 + li < N2;
+                        typename MF::acc acc;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = i0 + MF::row(lane, v);
+                            acc[v] = (i < N2 && bok) ? Sb[i * N2 + mb] : T(0);
+                        }
+#pragma unroll
+                        for (int kk = 0; kk < PW / 4; ++kk) {
+                            const int c = 4 * kk + lk;
+                            const T av = (aok && c < b) ? -Sb[ia * N2 + j0 + c] * sgn[j0 + c] : T(0);
+                            const T bv = (bok && c < b) ? Sb[mb * N2 + j0 + c] : T(0);
+                            acc = MF::mac(av, bv, acc);
+                        }
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = i0 + MF::row(lane, v);
+                            if (i < N2 && bok && m0 + li <= i) Sb[i * N2 + mb] = acc[v];
+                        }
+                    }
                 }
                 __syncthreads();
             }
-            for (int j = tid; j < N2; j += NTG) {
-                const T d = Sb[j * N2 + j];
-                sgn[j] = d < T(0) ? T(-1) : T(1);
-                dinv[j] = sgn[j] / sqrt(fabs(d));
-            }
-            __syncthreads();
-            for (int idx = tid; idx < N2 * N2; idx += NTG) {
-                const int i = idx / N2, j = idx - i * N2;
-                if (j < i) Sb[idx] *= dinv[j];
-            }
-            __syncthreads();
-            for (int j = tid; j < N2; j += NTG) Sb[j * N2 + j] = sqrt(fabs(Sb[j * N2 + j]));
-            __syncthreads();
         }
         // the stored factor carries sign(d_j) on its diagonal (negative only for GLM's phi pivots)
         if (Lout)
