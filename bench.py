@@ -270,7 +270,7 @@ def cpu_baseline_all_cores(a, budget_s=10.0, max_workers=16):
                        f"form+factor+Schur+recover")
 
 
-def run_precision(p, prec, steps, warmup, keep_solution=False):
+def run_precision(p, prec, steps, warmup, keep_solution=False, precond="jacobi"):
     """Time `steps` whole stages in one precision; returns timings and (optionally) the
     final stage solution on the host."""
     import torch
@@ -279,7 +279,7 @@ def run_precision(p, prec, steps, warmup, keep_solution=False):
     k = int(p.degree[0])
     a = 1.0 / (GAMMA * p.dt)
     kw = dict(krylov_tol=1e-13) if prec == "fp64" else dict(MIXED_OPTS)
-    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=k, precision=prec, **kw)
+    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=k, precision=prec, precond=precond, **kw)
     nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
     # inputs: projected plane wave p0 = sin(2 pi x), v0 = (p0, 0, 0); Dirichlet p = sin 2pi(x - t)
     vp = s.volume_points()
@@ -651,6 +651,15 @@ def main():
                  "(right-hand-side condensation + recover [+ refinement element passes]); "
                  "one factorisation per dt, not per stage",
         **{pr: run_cached(p, pr, args.steps, args.warmup) for pr in precs}}
+    ss = run_precision(p, "fp64", args.steps, args.warmup, precond="ssor")
+    out["trace_solve_ssor"] = {
+        "basis": "secondary: the FP64 stage with the multicolour block SSOR preconditioner (Eisenstat form) "
+                 "in the trace CG instead of block Jacobi; same element kernels",
+        "solve_ms": ss["solve"], "iters": ss["iters"], "ms_step": ss["ms_step"],
+        "jacobi_solve_ms": res["fp64"]["solve"] if "fp64" in res else None,
+        "jacobi_iters": res["fp64"]["iters"] if "fp64" in res else None}
+    print(f"trace solve: ssor {ss['solve']:.2f} ms ({ss['iters']:.0f} it), jacobi "
+          f"{out['trace_solve_ssor']['jacobi_solve_ms']} ms", file=sys.stderr, flush=True)
     out["step_graph"] = {"basis": "secondary: whole DIRK(3,3) steps (hdg_step, FP64, cached factors) eager "
                                   "against one hipGraph replay per step", **run_step_graph(p, 3, 1)}
     print(f"step graph: {out['step_graph']['eager_ms_step']:.2f} ms eager, "

@@ -168,7 +168,25 @@ typedef struct {
     void* (*dev_alloc)(void* alloc_user, size_t bytes);
     void (*dev_free)(void* alloc_user, void* ptr);
     void* alloc_user;
+    int precond;                /* trace-solve preconditioner (enum hdg_precond).  HDG_PC_SSOR
+                                   applies to one right-hand side in 3D (the block sizes of the
+                                   built configurations); elsewhere, and inside the step graph,
+                                   block Jacobi is used.                                      */
 } hdg_options;
+
+/* Preconditioners of the trace CG (section 2.4.2 uses BILU(0) inside RAS; K is symmetric
+ * definite here, so the symmetric counterpart of a block incomplete factorisation is used). */
+enum hdg_precond {
+    HDG_PC_JACOBI = 0,          /* block Jacobi: the inverses of the face-diagonal blocks     */
+    HDG_PC_SSOR = 1             /* block symmetric Gauss-Seidel in a multicolour face order
+                                   (faces that share an element get different colours):
+                                   M = (D + L) D^-1 (D + U), applied through Eisenstat's form
+                                   (CG on (D + L)^-1 K (D + U)^-1 with the product D r as its
+                                   preconditioner), so an iteration costs one forward and one
+                                   backward colour sweep instead of a product and a Jacobi
+                                   step; convergence is confirmed on the same relative
+                                   residual |b - K x| / |b| as with block Jacobi            */
+};
 
 /* Query keys for hdg_query. */
 enum hdg_query_key {
@@ -185,7 +203,8 @@ enum hdg_query_key {
                                    degree class: 4 bits per degree k = 1..5 at bit 4 (k - 1),
                                    each 0 (no class or not chosen yet) or schedule + 1       */
     HDG_Q_STEP_GRAPH = 12,      /* 1 if the last hdg_step was a replay of the step graph     */
-    HDG_Q_STEP_GRAPH_ITERS = 13 /* CG iterations per stage held by the step graph (0: none)  */
+    HDG_Q_STEP_GRAPH_ITERS = 13,/* CG iterations per stage held by the step graph (0: none)  */
+    HDG_Q_N_COLORS = 14         /* face colours of the multicolour preconditioner (0: none)   */
 };
 
 /*

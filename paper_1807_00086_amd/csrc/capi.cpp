@@ -274,6 +274,12 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     c->dev_alloc = o->dev_alloc;
     c->dev_free = o->dev_free;
     c->alloc_user = o->alloc_user;
+    if (o->precond != HDG_PC_JACOBI && o->precond != HDG_PC_SSOR) {
+        g_init_err = "unknown precond";
+        delete c;
+        return HDG_E_ARG;
+    }
+    c->precond = o->precond;
     c->stream = (hipStream_t)stream;
     int st = build_mesh(c, m, p);
     if (st) {
@@ -361,6 +367,38 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
     TRY(upload(c, &c->d_face_elem, c->face_elem));
     TRY(upload(c, &c->d_face_lf, c->face_lf));
     TRY(upload(c, &c->d_face_bnd, c->face_bnd));
+    if (c->precond == HDG_PC_SSOR) {
+        // greedy colouring of the faces in face order: faces that share an element (a nonzero
+        // off-diagonal block of K) get different colours, so the faces of one colour are
+        // independent in a Gauss-Seidel sweep
+        const int nv = c->dim + 1;
+        std::vector<int8_t> color(c->n_faces, -1);
+        int nc = 0;
+        for (int64_t F = 0; F < c->n_faces; ++F) {
+            unsigned used = 0;
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const int32_t e = c->face_elem[2 * F + s2];
+                if (e < 0) continue;
+                for (int q = 0; q < nv; ++q) {
+                    const int32_t G = c->elem_face[(int64_t)e * nv + q];
+                    if (G != F && color[G] >= 0) used |= 1u << color[G];
+                }
+            }
+            int col = 0;
+            while (used & (1u << col)) ++col;
+            color[F] = (int8_t)col;
+            nc = std::max(nc, col + 1);
+        }
+        c->ncolors = nc;
+        c->color_off.assign(nc + 1, 0);
+        for (int64_t F = 0; F < c->n_faces; ++F) ++c->color_off[color[F] + 1];
+        for (int k2 = 0; k2 < nc; ++k2) c->color_off[k2 + 1] += c->color_off[k2];
+        std::vector<int32_t> cf(c->n_faces);
+        std::vector<int64_t> pos(c->color_off.begin(), c->color_off.end() - 1);
+        for (int64_t F = 0; F < c->n_faces; ++F) cf[pos[color[F]]++] = (int32_t)F;
+        TRY(upload(c, &c->d_color, color));
+        TRY(upload(c, &c->d_cfaces, cf));
+    }
     TRY(upload(c, &c->d_bsr_cols, c->bsr_cols_h));
     TRY(upload(c, &c->tab.Sr, c->ref.Sr));
     TRY(upload(c, &c->tab.Mf, c->ref.Mf));
@@ -510,6 +548,7 @@ hdg_status hdg_query(const hdg_ctx* c, int key, int64_t* v) {
         case HDG_Q_M_TRACE: *v = c->m_trace; break;
         case HDG_Q_STEP_GRAPH: *v = c->sg_replayed ? 1 : 0; break;
         case HDG_Q_STEP_GRAPH_ITERS: *v = c->sgexec ? c->sg_nit : 0; break;
+        case HDG_Q_N_COLORS: *v = c->ncolors; break;
         case HDG_Q_SCHEDULE: {
             const int pi = c->precision == HDG_FP64 ? 1 : 0;
             int64_t x = 0;
@@ -596,7 +635,9 @@ hdg_status hdg_trace_solve(hdg_ctx* c, double* lambda, int* iters, double* relre
         EventTimer t(c, &c->tim.solve);
         // mixed precision: K already carries the FP32 factors' error and the refinement's FP64
         // residual removes it, so the products may read the FP32 copy as well
-        r = trace_cg(c, lambda, c->krylov_tol, iters, relres, c->d_bsr32 != nullptr);
+        r = (c->precond == HDG_PC_SSOR && ssor_supported(c))
+                ? trace_cg_ssor(c, lambda, c->krylov_tol, iters, relres)
+                : trace_cg(c, lambda, c->krylov_tol, iters, relres, c->d_bsr32 != nullptr);
     }
     if (r == HDG_E_NOCONV) return fail(c, r, "trace solve did not reach krylov_tol");
     if (r) return fail(c, r, "trace solve failed");
@@ -1234,7 +1275,7 @@ void hdg_destroy(hdg_ctx* c) {
                     c->tab.Tsym32, c->tab.Ef32, c->tab.Tfull, c->tab.Tfull32, c->tab.SrT, c->tab.EfT, c->d_eframe, c->d_xscratch, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
                     c->d_bsr, c->d_bsr32, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
                     c->d_scal, c->d_f_saved, c->d_lbnd_saved, c->d_su, c->d_slam, c->d_du, c->d_dlam,
-                    c->d_re64, c->d_sq, c->d_cgflags,
+                    c->d_re64, c->d_sq, c->d_cgflags, c->d_color, c->d_cfaces, c->d_ss,
                     c->d_stage, c->d_ustar, c->d_fstage, c->d_loc_off, c->d_efnf, c->d_face_nf, c->d_edeg,
                     c->d_cls[1], c->d_cls[2], c->d_cls[3], c->d_cls[4], c->d_cls[5]};
     if (c->stream || c->d_geom) (void)hipStreamSynchronize(c->stream);

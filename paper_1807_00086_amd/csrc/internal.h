@@ -207,6 +207,14 @@ struct hdg_ctx {
     int sg_nit = 0;             // CG iterations per stage in the captured graph
     bool sg_replayed = false;   // the last hdg_step ran as a graph replay
 
+    // multicolour block SSOR preconditioner of the trace CG (options.precond): face colours
+    // (faces sharing an element differ), the faces of each colour, and work vectors
+    int precond = 0;
+    int ncolors = 0;
+    std::vector<int64_t> color_off;   // [ncolors + 1] offsets into d_cfaces
+    int8_t* d_color = nullptr;        // [nf]
+    int32_t* d_cfaces = nullptr;      // [nf] faces grouped by colour
+    double* d_ss = nullptr;           // [3][ntr]: t, u, y of the transformed CG
     // device memory of the workspaces (options.dev_alloc / dev_free; null: hipMalloc / hipFree)
     void* (*dev_alloc)(void*, size_t) = nullptr;
     void (*dev_free)(void*, void*) = nullptr;
@@ -246,6 +254,9 @@ int trace_cg(hdg_ctx* c, double* lambda, double tol, int* iters, double* relres,
 // graph capture): flags [2] = done, iterations; relres_dev = largest relative residual.
 int trace_cg_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, double* relres_dev);
 int launch_zero_ints(hdg_ctx* c, int* p, int n);
+// multicolour block SSOR (Eisenstat form) CG; returns HDG_OK / HDG_E_NOCONV / a HIP error
+int trace_cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres);
+bool ssor_supported(const hdg_ctx* c);
 int launch_bsr_f32(hdg_ctx* c);
 // trace solve with the CG work vectors and reduction scratch in the library's static device
 // array (no allocation); static_scratch_setup looks up the array's address on the current device

@@ -788,6 +788,294 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
 }
 
 namespace {
+// ------------------------------------------------------------------ multicolour block SSOR
+// One sweep of a colour: for every face F of colour c (faces of one colour share no element, so
+// they are independent), one group of BS lanes of a wavefront (lane a = row a of the face
+// block; 64 / BS faces per wavefront, the remaining lanes idle):
+//   s = v_F [- D_F t_F]  - sum over the neighbour slots of lower (forward) or higher (backward)
+//       colour of A_{F,G} y_G,        y_F = D_F^{-1} s      [, q_F = t_F + y_F]
+// (HAT: the forward sweep of Eisenstat's product, whose right-hand side is p - D t and whose
+// output is q = t + (D + L)^{-1} (p - D t)).  D_F^{-1} s mixes the rows of the face: the lanes
+// exchange s through shuffles within the group.  Blocks are column-major (entry (a, b) at
+// b BS + a), slot 0 of a block row the diagonal block.
+template <int BS, bool UP, bool HAT>
+__global__ __launch_bounds__(NT) void ssor_sweep_kernel(int64_t nfc, const int32_t* __restrict__ flist,
+                                                        const int8_t* __restrict__ color, int c,
+                                                        const int32_t* __restrict__ cols,
+                                                        const double* __restrict__ bsr,
+                                                        const double* __restrict__ dinv,
+                                                        const double* __restrict__ v,
+                                                        const double* __restrict__ t, double* __restrict__ y,
+                                                        double* __restrict__ q) {
+    constexpr int FPW = 64 / BS, NS = 7;
+    const int lane = threadIdx.x & 63, fw = min(lane / BS, FPW), a = lane - fw * BS;
+    const int64_t g = ((int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * FPW + fw;
+    const bool ok = fw < FPW && g < nfc;
+    const int64_t F = ok ? flist[g] : 0;
+    double sv = 0.0;
+    if (ok) {
+        sv = v[F * BS + a];
+        if (HAT) {
+            const double* Dd = bsr + (size_t)F * NS * BS * BS + a;
+            const double* tf = t + F * BS;
+            double dt = 0.0;
+#pragma unroll
+            for (int b = 0; b < BS; ++b) dt += Dd[b * BS] * tf[b];
+            sv -= dt;
+        }
+#pragma unroll
+        for (int s = 1; s < NS; ++s) {
+            const int32_t cF = cols[F * NS + s];
+            if (cF < 0) continue;
+            const int cc = color[cF];
+            if (UP ? cc <= c : cc >= c) continue;
+            const double* B = bsr + ((size_t)F * NS + s) * BS * BS + a;
+            const double* yv = y + (size_t)cF * BS;
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b < BS; ++b) acc += B[b * BS] * yv[b];
+            sv -= acc;
+        }
+    }
+    // y_F = D_F^{-1} s: row a needs all of s (held by the group's BS lanes)
+    const double* Di = dinv + (size_t)F * BS * BS + min(a, BS - 1);
+    const int base = min(lane - a, 64 - BS);
+    double out = 0.0;
+#pragma unroll
+    for (int b = 0; b < BS; ++b) out += Di[b * BS] * __shfl(sv, base + b, 64);
+    if (ok) {
+        y[F * BS + a] = out;
+        if (HAT) q[F * BS + a] = t[F * BS + a] + out;
+    }
+}
+
+// z_F = D_F r_F (the diagonal blocks of the assembled matrix: slot 0 of each block row)
+template <int BS>
+__global__ __launch_bounds__(NT) void diag_block_apply_kernel(int64_t nf, const double* __restrict__ bsr,
+                                                              const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nf * BS) return;
+    const int64_t F = gid / BS;
+    const int a = (int)(gid % BS);
+    const double* Dd = bsr + (size_t)F * 7 * BS * BS + a;
+    const double* xv = x + F * BS;
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < BS; ++b) acc += Dd[b * BS] * xv[b];
+    y[gid] = acc;
+}
+}  // namespace
+
+namespace {
+// CG update of the transformed system fused with its preconditioner product: y += alpha p,
+// r -= alpha q, z = D r (diagonal block of the face, rows exchanged by shuffles), and the partial
+// sums of r.z per workgroup (part[blk], reduced by dot_final_kernel); groups of BS lanes per face
+// as in the sweeps.
+template <int BS>
+__global__ __launch_bounds__(NT) void ssor_update_kernel(int64_t nf, const double* __restrict__ num,
+                                                         const double* __restrict__ den,
+                                                         const double* __restrict__ p, const double* __restrict__ q,
+                                                         double* __restrict__ y, double* __restrict__ r,
+                                                         double* __restrict__ z, const double* __restrict__ bsr,
+                                                         double* __restrict__ part) {
+    constexpr int FPW = 64 / BS;
+    __shared__ double sh[NT / 64];
+    const int lane = threadIdx.x & 63, fw = min(lane / BS, FPW), a = lane - fw * BS;
+    const int64_t F = ((int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * FPW + fw;
+    const bool ok = fw < FPW && F < nf;
+    const double dd = den[0];
+    const double al = dd != 0.0 ? num[0] / dd : 0.0;
+    double rn = 0.0;
+    if (ok) {
+        const int64_t k = F * BS + a;
+        y[k] += al * p[k];
+        rn = r[k] - al * q[k];
+        r[k] = rn;
+    }
+    const double* Dd = bsr + (size_t)(ok ? F : 0) * 7 * BS * BS + min(a, BS - 1);
+    const int base = min(lane - a, 64 - BS);
+    double zr = 0.0;
+#pragma unroll
+    for (int b = 0; b < BS; ++b) zr += Dd[b * BS] * __shfl(rn, base + b, 64);
+    double acc = 0.0;
+    if (ok) {
+        z[F * BS + a] = zr;
+        acc = rn * zr;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t += sh[w];
+        part[blockIdx.x] = t;
+    }
+}
+}  // namespace
+
+bool ssor_supported(const hdg_ctx* c) {
+    if (c->nrhs != 1 || c->nslot != 7 || c->ncolors == 0 || !c->d_cfaces) return false;
+#define HDG_BS(B) \
+    if (c->bs == B) return true;
+    HDG_BS_CASES(HDG_BS)
+#undef HDG_BS
+    return false;
+}
+
+namespace {
+#define HIPCHK_INT(call)                          \
+    do {                                          \
+        if ((call) != hipSuccess) return HDG_E_HIP; \
+    } while (0)
+
+// one sweep over all colours (forward: colour 0 first; backward: the last colour first)
+template <int BS, bool UP, bool HAT>
+void ssor_sweep(hdg_ctx* c, const double* v, const double* t, double* y, double* q) {
+    constexpr int FPB = (64 / BS) * (NT / 64);   // faces per workgroup
+    for (int k = 0; k < c->ncolors; ++k) {
+        const int col = UP ? c->ncolors - 1 - k : k;
+        const int64_t f0 = c->color_off[col], nfc = c->color_off[col + 1] - f0;
+        if (nfc == 0) continue;
+        hipLaunchKernelGGL((ssor_sweep_kernel<BS, UP, HAT>), dim3((unsigned)((nfc + FPB - 1) / FPB)), dim3(NT), 0, c->stream, nfc,
+                           c->d_cfaces + f0, c->d_color, col, c->d_bsr_cols, c->d_bsr, c->d_pinv, v, t, y, q);
+    }
+}
+
+// CG on the transformed system  Ahat y = Lt^{-1} r0,  Ahat = Lt^{-1} K Ut^{-1}  (Lt = D + L,
+// Ut = D + U = Lt^T), with the product z = D r as its preconditioner: the iterates are those of
+// PCG on K with the SSOR preconditioner M = Lt D^{-1} Ut.  Eisenstat's form of the product:
+// t = Ut^{-1} p,  Ahat p = t + Lt^{-1} (p - D t).  The correction of the initial guess x0 is
+// x - x0 = Ut^{-1} y.  r.z (the residual in the M^{-1} norm) drives the iteration; when its
+// relative value drops below the tolerance, the true relative residual |b - K x| / |b| is
+// formed and decides (a failed check tightens the estimate's threshold tenfold).
+template <int BS>
+int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
+    const int64_t n = c->n_faces * BS;
+    double* rr = c->d_cg_r;
+    double* zz = c->d_cg_z;
+    double* pp = c->d_cg_p;
+    double* qq = c->d_cg_q;
+    double* tt = c->d_ss;
+    double* uu = c->d_ss + n;
+    double* yy = c->d_ss + 2 * n;
+    double* s_rz = c->d_scal;
+    double* s_rz_new = c->d_scal + 32;
+    double* s_pq = c->d_scal + 64;
+    double* s_bb = c->d_scal + 128;
+    double* s_rr = c->d_scal + 96;
+    auto diag = [&](const double* in, double* out) {
+        hipLaunchKernelGGL((diag_block_apply_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->d_bsr,
+                           in, out);
+    };
+    auto true_residual = [&](double* hres) -> int {   // x_try = x0 + Ut^{-1} y into zz; |b - K x_try|^2
+        ssor_sweep<BS, true, false>(c, yy, nullptr, tt, nullptr);
+        launch_lincomb(c, n, 1.0, x, 1.0, tt, zz);
+        spmv(c, zz, qq);
+        launch_lincomb(c, n, 1.0, c->d_rhs, -1.0, qq, uu);
+        dot(c, uu, uu, s_rr);
+        HIPCHK_INT(hipMemcpyAsync(hres, s_rr, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK_INT(hipStreamSynchronize(c->stream));
+        return 0;
+    };
+    // initial guess: Dirichlet entries are the boundary values (identity rows)
+    hipLaunchKernelGGL(copy_bnd_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, BS, 1, c->d_face_bnd,
+                       c->d_rhs, x);
+    spmv(c, x, qq);
+    launch_lincomb(c, n, 1.0, c->d_rhs, -1.0, qq, uu);             // r0 = b - K x0
+    ssor_sweep<BS, false, false>(c, uu, nullptr, rr, nullptr);     // rhat = Lt^{-1} r0
+    hipMemsetAsync(yy, 0, n * sizeof(double), c->stream);
+    diag(rr, zz);
+    launch_lincomb(c, n, 1.0, zz, 0.0, nullptr, pp);
+    dot(c, rr, zz, s_rz);
+    dot(c, c->d_rhs, c->d_rhs, s_bb);
+    // the scale of r.z: (Lt^{-1} b)^T D (Lt^{-1} b)
+    ssor_sweep<BS, false, false>(c, c->d_rhs, nullptr, uu, nullptr);
+    diag(uu, tt);
+    dot(c, uu, tt, s_pq);
+    double h[3];
+    HIPCHK_INT(hipMemcpyAsync(&h[0], s_bb, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK_INT(hipMemcpyAsync(&h[1], s_pq, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK_INT(hipStreamSynchronize(c->stream));
+    const double bnorm = h[0] > 0 ? std::sqrt(h[0]) : 1.0;
+    const double bm = h[1] > 0 ? h[1] : 1.0;
+    double thresh = tol;
+    double worst = std::numeric_limits<double>::quiet_NaN();
+    int it = 0;
+    double* hrz = c->h_rr;
+    for (it = 0; it <= c->krylov_maxit; ++it) {
+        if (hipMemcpyAsync(hrz, s_rz, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipEventRecord(c->ev_rr, c->stream) != hipSuccess)
+            return HDG_E_HIP;
+        // queue the next product (writes t, u, q and p.q only) before waiting for r.z
+        if (it < c->krylov_maxit) {
+            ssor_sweep<BS, true, false>(c, pp, nullptr, tt, nullptr);
+            ssor_sweep<BS, false, true>(c, pp, tt, uu, qq);
+            dot(c, pp, qq, s_pq);
+        }
+        if (hipEventSynchronize(c->ev_rr) != hipSuccess) return HDG_E_HIP;
+        const double est = std::sqrt(std::fabs(hrz[0]) / bm);
+        if (!(est - est == 0.0)) {
+            worst = std::numeric_limits<double>::quiet_NaN();
+            break;
+        }
+        if (est <= thresh || it == c->krylov_maxit) {
+            double hres = 0.0;
+            if (true_residual(&hres)) return HDG_E_HIP;
+            worst = std::sqrt(hres) / bnorm;
+            if (!(worst - worst == 0.0) || worst <= tol || it == c->krylov_maxit) {
+                launch_lincomb(c, n, 1.0, zz, 0.0, nullptr, x);   // x = x0 + Ut^{-1} y
+                break;
+            }
+            thresh *= 0.1;
+            // the check overwrote t and q: queue the product of this iteration again
+            ssor_sweep<BS, true, false>(c, pp, nullptr, tt, nullptr);
+            ssor_sweep<BS, false, true>(c, pp, tt, uu, qq);
+            dot(c, pp, qq, s_pq);
+        }
+        {
+            constexpr int FPB = (64 / BS) * (NT / 64);
+            const int grid = (int)((c->n_faces + FPB - 1) / FPB);
+            if (grid <= RED_MAX * 32) {
+                hipLaunchKernelGGL((ssor_update_kernel<BS>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, s_rz,
+                                   s_pq, pp, qq, yy, rr, zz, c->d_bsr, c->d_red);
+                hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, grid, 1, c->d_red, s_rz_new,
+                                   (const int*)nullptr);
+            } else {
+                hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, 1, s_rz, s_pq,
+                                   pp, qq, yy, rr, c->d_red, (const int*)nullptr, (int*)nullptr);
+                diag(rr, zz);
+                dot(c, rr, zz, s_rz_new);
+            }
+        }
+        hipLaunchKernelGGL(xpby_cols_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, n, 1, s_rz_new, s_rz, zz, pp,
+                           (const int*)nullptr);
+        std::swap(s_rz, s_rz_new);
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = worst;
+    c->last_iters = it;
+    if (!(worst <= tol)) return HDG_E_NOCONV;
+    return HDG_OK;
+}
+}  // namespace
+
+int trace_cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
+    if (!c->d_ss) {
+        void* p = nullptr;
+        const int e = dev_malloc(c, &p, (size_t)3 * c->n_faces * c->bs * sizeof(double));
+        if (e) return e;
+        c->d_ss = (double*)p;
+    }
+#define HDG_BS(B) \
+    if (c->bs == B) return cg_ssor<B>(c, x, tol, iters, relres);
+    HDG_BS_CASES(HDG_BS)
+#undef HDG_BS
+    return HDG_E_UNSUPPORTED;
+}
+#undef HIPCHK_INT
+
+namespace {
 // Device-side convergence test of the captured CG: done = 1 once every column meets the
 // tolerance, 2 on a non-finite residual; relres = the largest relative residual.
 __global__ void cg_check_kernel(int R, const double* __restrict__ s_rr, const double* __restrict__ s_bb,

@@ -24,7 +24,8 @@ STATUS = {0: "HDG_OK", 1: "HDG_E_ARG", 2: "HDG_E_MESH", 3: "HDG_E_ALLOC", 4: "HD
           5: "HDG_E_SINGULAR", 6: "HDG_E_NOCONV", 7: "HDG_E_STATE", 8: "HDG_E_UNSUPPORTED"}
 Q = dict(n_elem=0, n_faces=1, n_bfaces=2, n_local_dofs=3, n_trace_dofs=4, n_vol_points=5,
          n_bnd_points=6, last_iters=7, last_refine=8, m_local=9, m_trace=10, schedule=11,
-         step_graph=12, step_graph_iters=13)
+         step_graph=12, step_graph_iters=13, n_colors=14)
+PRECOND = {"jacobi": 0, "ssor": 1}
 
 # every function declared in include/hdg.h
 EXPORTS = ["hdg_init_mesh", "hdg_query", "hdg_condense", "hdg_condense_rhs", "hdg_trace_solve", "hdg_recover",
@@ -62,7 +63,7 @@ class Options(C.Structure):
                 ("refine_inner_tol", C.c_double), ("cache_factors", C.c_int),
                 ("autotune", C.c_int), ("autotune_table", C.c_char_p), ("use_graph", C.c_int),
                 ("graph_step", C.c_int), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_user", C.c_void_p)]
+                ("alloc_user", C.c_void_p), ("precond", C.c_int)]
 
 
 class TorchAllocator:
@@ -202,7 +203,7 @@ class Solver:
                  nrhs=1, stab_scale=1.0, krylov_tol=1e-13, krylov_maxit=5000, refine_tol=1e-13,
                  refine_maxit=10, refine_inner_tol=1e-6, cache_factors=False, autotune=False,
                  autotune_table=None, use_graph=False, graph_step=False, bface_tag=None, allocator=None,
-                 stream=None):
+                 precond="jacobi", stream=None):
         self.lib = load_library()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self._ev = np.ascontiguousarray(elem_vert, dtype=np.int64)
@@ -234,6 +235,7 @@ class Solver:
         if self.allocator is not None:
             od.dev_alloc = self.allocator.alloc_fn
             od.dev_free = self.allocator.free_fn
+        od.precond = PRECOND[precond] if isinstance(precond, str) else int(precond)
         if stream is None:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
