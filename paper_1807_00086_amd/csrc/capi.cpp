@@ -396,8 +396,18 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
         std::vector<int32_t> cf(c->n_faces);
         std::vector<int64_t> pos(c->color_off.begin(), c->color_off.end() - 1);
         for (int64_t F = 0; F < c->n_faces; ++F) cf[pos[color[F]]++] = (int32_t)F;
+        // per face: bit s of the slot mask set when the block-row slot s holds a neighbour of
+        // a lower colour (the forward sweep's slots); the backward sweep takes the other
+        // occupied slots
+        std::vector<uint8_t> lower(c->n_faces, 0);
+        for (int64_t F = 0; F < c->n_faces; ++F)
+            for (int sl = 1; sl < c->nslot; ++sl) {
+                const int32_t G = c->bsr_cols_h[F * c->nslot + sl];
+                if (G >= 0 && color[G] < color[F]) lower[F] |= (uint8_t)(1u << sl);
+            }
         TRY(upload(c, &c->d_color, color));
         TRY(upload(c, &c->d_cfaces, cf));
+        TRY(upload(c, &c->d_lmask, lower));
     }
     TRY(upload(c, &c->d_bsr_cols, c->bsr_cols_h));
     TRY(upload(c, &c->tab.Sr, c->ref.Sr));
@@ -1275,7 +1285,7 @@ void hdg_destroy(hdg_ctx* c) {
                     c->tab.Tsym32, c->tab.Ef32, c->tab.Tfull, c->tab.Tfull32, c->tab.SrT, c->tab.EfT, c->d_eframe, c->d_xscratch, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
                     c->d_bsr, c->d_bsr32, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
                     c->d_scal, c->d_f_saved, c->d_lbnd_saved, c->d_su, c->d_slam, c->d_du, c->d_dlam,
-                    c->d_re64, c->d_sq, c->d_cgflags, c->d_color, c->d_cfaces, c->d_ss,
+                    c->d_re64, c->d_sq, c->d_cgflags, c->d_color, c->d_cfaces, c->d_lmask, c->d_ss,
                     c->d_stage, c->d_ustar, c->d_fstage, c->d_loc_off, c->d_efnf, c->d_face_nf, c->d_edeg,
                     c->d_cls[1], c->d_cls[2], c->d_cls[3], c->d_cls[4], c->d_cls[5]};
     if (c->stream || c->d_geom) (void)hipStreamSynchronize(c->stream);

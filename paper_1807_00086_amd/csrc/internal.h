@@ -214,6 +214,7 @@ struct hdg_ctx {
     std::vector<int64_t> color_off;   // [ncolors + 1] offsets into d_cfaces
     int8_t* d_color = nullptr;        // [nf]
     int32_t* d_cfaces = nullptr;      // [nf] faces grouped by colour
+    uint8_t* d_lmask = nullptr;       // [nf] bit s: block-row slot s is a lower-colour neighbour
     double* d_ss = nullptr;           // [3][ntr]: t, u, y of the transformed CG
     // device memory of the workspaces (options.dev_alloc / dev_free; null: hipMalloc / hipFree)
     void* (*dev_alloc)(void*, size_t) = nullptr;

@@ -800,7 +800,7 @@ namespace {
 // b BS + a), slot 0 of a block row the diagonal block.
 template <int BS, bool UP, bool HAT>
 __global__ __launch_bounds__(NT) void ssor_sweep_kernel(int64_t nfc, const int32_t* __restrict__ flist,
-                                                        const int8_t* __restrict__ color, int c,
+                                                        const uint8_t* __restrict__ lmask,
                                                         const int32_t* __restrict__ cols,
                                                         const double* __restrict__ bsr,
                                                         const double* __restrict__ dinv,
@@ -814,6 +814,8 @@ __global__ __launch_bounds__(NT) void ssor_sweep_kernel(int64_t nfc, const int32
     const int64_t F = ok ? flist[g] : 0;
     double sv = 0.0;
     if (ok) {
+        // slots of this sweep: the lower-colour neighbours (forward) or the other occupied ones
+        const unsigned lo = lmask[F];
         sv = v[F * BS + a];
         if (HAT) {
             const double* Dd = bsr + (size_t)F * NS * BS * BS + a;
@@ -825,10 +827,9 @@ __global__ __launch_bounds__(NT) void ssor_sweep_kernel(int64_t nfc, const int32
         }
 #pragma unroll
         for (int s = 1; s < NS; ++s) {
+            if (((lo >> s) & 1u) == (UP ? 1u : 0u)) continue;
             const int32_t cF = cols[F * NS + s];
             if (cF < 0) continue;
-            const int cc = color[cF];
-            if (UP ? cc <= c : cc >= c) continue;
             const double* B = bsr + ((size_t)F * NS + s) * BS * BS + a;
             const double* yv = y + (size_t)cF * BS;
             double acc = 0.0;
@@ -915,7 +916,7 @@ __global__ __launch_bounds__(NT) void ssor_update_kernel(int64_t nf, const doubl
 }  // namespace
 
 bool ssor_supported(const hdg_ctx* c) {
-    if (c->nrhs != 1 || c->nslot != 7 || c->ncolors == 0 || !c->d_cfaces) return false;
+    if (c->nrhs != 1 || c->nslot != 7 || c->ncolors == 0 || !c->d_cfaces || !c->d_lmask) return false;
 #define HDG_BS(B) \
     if (c->bs == B) return true;
     HDG_BS_CASES(HDG_BS)
@@ -938,7 +939,7 @@ void ssor_sweep(hdg_ctx* c, const double* v, const double* t, double* y, double*
         const int64_t f0 = c->color_off[col], nfc = c->color_off[col + 1] - f0;
         if (nfc == 0) continue;
         hipLaunchKernelGGL((ssor_sweep_kernel<BS, UP, HAT>), dim3((unsigned)((nfc + FPB - 1) / FPB)), dim3(NT), 0, c->stream, nfc,
-                           c->d_cfaces + f0, c->d_color, col, c->d_bsr_cols, c->d_bsr, c->d_pinv, v, t, y, q);
+                           c->d_cfaces + f0, c->d_lmask, c->d_bsr_cols, c->d_bsr, c->d_pinv, v, t, y, q);
     }
 }
 
