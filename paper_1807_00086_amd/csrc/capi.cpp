@@ -389,6 +389,78 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
             color[F] = (int8_t)col;
             nc = std::max(nc, col + 1);
         }
+        // the colouring is a proper edge colouring of the element graph (elements joined by their
+        // faces); greedy leaves a few faces in colour nv (one above the element degree).  Each
+        // such face F between elements u and v misses one colour al at u and one colour be at v;
+        // swapping al and be along the chain of faces coloured al, be that starts at v frees al at
+        // v unless the chain ends at u (Kempe's interchange).  When every face leaves colour nv,
+        // one sweep launch per direction goes.
+        if (nc == nv + 1) {
+            auto other = [&](int32_t G, int32_t e) {
+                const int32_t e0 = c->face_elem[2 * G], e1 = c->face_elem[2 * G + 1];
+                return e0 == e ? e1 : e0;
+            };
+            auto face_of = [&](int32_t e, int col) -> int32_t {
+                for (int q = 0; q < nv; ++q) {
+                    const int32_t G = c->elem_face[(int64_t)e * nv + q];
+                    if (color[G] == col) return G;
+                }
+                return -1;
+            };
+            auto missing = [&](int32_t e, int32_t F) {
+                unsigned used = 0;
+                for (int q = 0; q < nv; ++q) {
+                    const int32_t G = c->elem_face[(int64_t)e * nv + q];
+                    if (G != F) used |= 1u << color[G];
+                }
+                int col = 0;
+                while (used & (1u << col)) ++col;
+                return col;
+            };
+            bool left = false;
+            std::vector<int32_t> chain;
+            for (int64_t F = 0; F < c->n_faces; ++F) {
+                if (color[F] != nv) continue;
+                const int32_t u = c->face_elem[2 * F], v = c->face_elem[2 * F + 1];
+                if (u < 0 || v < 0) {
+                    left = true;
+                    continue;
+                }
+                const int al = missing(u, (int32_t)F), be = missing(v, (int32_t)F);
+                if (al >= nv || be >= nv) {   // cannot happen for interior faces of simplices
+                    left = true;
+                    continue;
+                }
+                if (al == be) {
+                    color[F] = (int8_t)al;
+                    continue;
+                }
+                // chain from v: its al-face, then the be-face of the next element, ...
+                chain.clear();
+                int32_t e = v;
+                int col = al;
+                bool hits_u = false;
+                for (int64_t len = 0; len < c->n_faces; ++len) {   // a path: it ends
+                    const int32_t G = face_of(e, col);
+                    if (G < 0) break;
+                    chain.push_back(G);
+                    e = other(G, e);
+                    if (e < 0) break;
+                    if (e == u) {
+                        hits_u = true;
+                        break;
+                    }
+                    col = col == al ? be : al;
+                }
+                if (hits_u) {
+                    left = true;
+                    continue;
+                }
+                for (int32_t G : chain) color[G] = (int8_t)(color[G] == al ? be : al);
+                color[F] = (int8_t)al;
+            }
+            if (!left) nc = nv;
+        }
         c->ncolors = nc;
         c->color_off.assign(nc + 1, 0);
         for (int64_t F = 0; F < c->n_faces; ++F) ++c->color_off[color[F] + 1];
@@ -396,18 +468,32 @@ hdg_status hdg_init_mesh(hdg_ctx** out, const hdg_mesh_desc* m, const hdg_phys_d
         std::vector<int32_t> cf(c->n_faces);
         std::vector<int64_t> pos(c->color_off.begin(), c->color_off.end() - 1);
         for (int64_t F = 0; F < c->n_faces; ++F) cf[pos[color[F]]++] = (int32_t)F;
-        // per face: bit s of the slot mask set when the block-row slot s holds a neighbour of
-        // a lower colour (the forward sweep's slots); the backward sweep takes the other
-        // occupied slots
-        std::vector<uint8_t> lower(c->n_faces, 0);
-        for (int64_t F = 0; F < c->n_faces; ++F)
-            for (int sl = 1; sl < c->nslot; ++sl) {
-                const int32_t G = c->bsr_cols_h[F * c->nslot + sl];
-                if (G >= 0 && color[G] < color[F]) lower[F] |= (uint8_t)(1u << sl);
+        // the off-diagonal blocks in sweep order: for every position of the colour order the
+        // blocks of its lower-colour neighbours (the forward sweep's), then, after all of those,
+        // the blocks of the higher-colour neighbours (the backward sweep's).  A sweep launch over
+        // the faces of one colour then streams one contiguous range of blocks.
+        const int ns1 = c->nslot - 1;
+        std::vector<int32_t> off(2 * (c->n_faces + 1)), nb, dst(c->n_faces * ns1, -1);
+        nb.reserve(c->n_faces * ns1);
+        for (int dir = 0; dir < 2; ++dir) {
+            int32_t* o = off.data() + dir * (c->n_faces + 1);
+            for (int64_t p = 0; p < c->n_faces; ++p) {
+                const int32_t F = cf[p];
+                o[p] = (int32_t)nb.size();
+                for (int sl = 1; sl < c->nslot; ++sl) {
+                    const int32_t G = c->bsr_cols_h[F * c->nslot + sl];
+                    if (G < 0 || (color[G] < color[F]) != (dir == 0)) continue;
+                    dst[F * ns1 + sl - 1] = (int32_t)nb.size();
+                    nb.push_back(G);
+                }
             }
-        TRY(upload(c, &c->d_color, color));
+            o[c->n_faces] = (int32_t)nb.size();
+        }
+        c->ss_nblk = (int64_t)nb.size();
         TRY(upload(c, &c->d_cfaces, cf));
-        TRY(upload(c, &c->d_lmask, lower));
+        TRY(upload(c, &c->d_ssoff, off));
+        TRY(upload(c, &c->d_ssdst, dst));
+        if (!nb.empty()) TRY(upload(c, &c->d_ssnb, nb));
     }
     TRY(upload(c, &c->d_bsr_cols, c->bsr_cols_h));
     TRY(upload(c, &c->tab.Sr, c->ref.Sr));
@@ -594,7 +680,10 @@ hdg_status hdg_condense(hdg_ctx* c, double a, const double* f_loc, const double*
     {
         EventTimer t(c, &c->tim.assemble);
         e = launch_assemble(c, lam_bnd);
-        if (!e) e = launch_block_inverse(c);
+        // the FP64 solve with block SSOR does not use the block-Jacobi inverses (a later Jacobi
+        // solve forms them itself)
+        if (!e && !(c->precond == HDG_PC_SSOR && ssor_supported(c) && c->precision == HDG_FP64))
+            e = launch_block_inverse(c);
         if (!e) e = launch_bsr_f32(c);
     }
     if (e) return fail(c, HDG_E_HIP, "assembly kernel launch failed");
@@ -1285,7 +1374,7 @@ void hdg_destroy(hdg_ctx* c) {
                     c->tab.Tsym32, c->tab.Ef32, c->tab.Tfull, c->tab.Tfull32, c->tab.SrT, c->tab.EfT, c->d_eframe, c->d_xscratch, c->d_Ke, c->d_re, c->d_Zt, c->d_z, c->d_LU, c->d_status,
                     c->d_bsr, c->d_bsr32, c->d_rhs, c->d_pinv, c->d_cg_r, c->d_cg_z, c->d_cg_p, c->d_cg_q, c->d_red,
                     c->d_scal, c->d_f_saved, c->d_lbnd_saved, c->d_su, c->d_slam, c->d_du, c->d_dlam,
-                    c->d_re64, c->d_sq, c->d_cgflags, c->d_color, c->d_cfaces, c->d_lmask, c->d_ss,
+                    c->d_re64, c->d_sq, c->d_cgflags, c->d_cfaces, c->d_ssoff, c->d_ssnb, c->d_ssdst, c->d_ss, c->d_ssA, c->d_rinv,
                     c->d_stage, c->d_ustar, c->d_fstage, c->d_loc_off, c->d_efnf, c->d_face_nf, c->d_edeg,
                     c->d_cls[1], c->d_cls[2], c->d_cls[3], c->d_cls[4], c->d_cls[5]};
     if (c->stream || c->d_geom) (void)hipStreamSynchronize(c->stream);

@@ -212,10 +212,17 @@ struct hdg_ctx {
     int precond = 0;
     int ncolors = 0;
     std::vector<int64_t> color_off;   // [ncolors + 1] offsets into d_cfaces
-    int8_t* d_color = nullptr;        // [nf]
-    int32_t* d_cfaces = nullptr;      // [nf] faces grouped by colour
-    uint8_t* d_lmask = nullptr;       // [nf] bit s: block-row slot s is a lower-colour neighbour
+    int32_t* d_cfaces = nullptr;      // [nf] faces grouped by colour (colour-order positions)
+    int32_t* d_ssoff = nullptr;       // [2][nf + 1] first sweep block of each position: forward, backward
+    int32_t* d_ssnb = nullptr;        // [ss_nblk] neighbour face of each sweep block
+    int32_t* d_ssdst = nullptr;       // [nf][nslot - 1] sweep block of block-row slot s >= 1, or -1
+    int64_t ss_nblk = 0;              // sweep blocks: the forward ones (lower colours) first
     double* d_ss = nullptr;           // [3][ntr]: t, u, y of the transformed CG
+    double* d_ssA = nullptr;          // [ss_nblk][bs][bs] R_F^{-1} K_FG R_G^{-T} in sweep order
+    double* d_rinv = nullptr;         // [nf][bs][bs] R_F^{-1}, D_F = R_F R_F^T (Cholesky)
+    int64_t mat_version = 0;          // counts assemblies of the trace matrix
+    int64_t ss_version = -1;          // assembly the scaled copy was built from
+    int64_t pinv_version = -1;        // assembly the block-Jacobi inverses were built from
     // device memory of the workspaces (options.dev_alloc / dev_free; null: hipMalloc / hipFree)
     void* (*dev_alloc)(void*, size_t) = nullptr;
     void (*dev_free)(void*, void*) = nullptr;

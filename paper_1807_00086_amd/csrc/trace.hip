@@ -137,6 +137,10 @@ __global__ __launch_bounds__(NT) void assemble_rhs64_kernel(int64_t nf, int bs, 
     rhs[gid] = v;
 }
 
+// block sizes of the built 3D configurations (m_trace * N_F: acoustic k = 1..5, Maxwell
+// k = 3, elastic k = 4) get the fixed-size kernels
+#define HDG_BS_CASES(X) X(3) X(6) X(10) X(15) X(20) X(21) X(45)
+
 // inverse of each diagonal block by Gauss-Jordan without pivoting (the blocks are SPD):
 // one wavefront per face, the block and its inverse in LDS (bs <= 48)
 constexpr int BI_MAX = 48;
@@ -176,6 +180,49 @@ __global__ __launch_bounds__(64) void block_inverse_kernel(int64_t nf, int nslot
         double* Inv = pinv + (size_t)F * bs * bs;
         for (int i = lane; i < bs * bs; i += 64) Inv[i] = V[i];
         __syncthreads();
+    }
+}
+
+// The same inverse for the built block sizes with the rows of a block in registers: a group of
+// BS lanes per face (lane a holds row a of the block and of its inverse; 64 / BS faces per
+// wavefront, the remaining lanes idle), the pivot row of each step broadcast by shuffles.  No LDS
+// and no barriers.
+template <int BS>
+__global__ __launch_bounds__(NT) void block_inverse_rows_kernel(int64_t nf, int nslot, const double* __restrict__ bsr,
+                                                                double* __restrict__ pinv) {
+    constexpr int FPW = 64 / BS;
+    const int lane = threadIdx.x & 63, fw = min(lane / BS, FPW), a = lane - fw * BS;
+    const int64_t F = ((int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * FPW + fw;
+    const bool ok = fw < FPW && F < nf;
+    const int base = min(lane - a, 64 - BS);   // first lane of the group (idle lanes: any full group)
+    const double* A = bsr + (size_t)(ok ? F : 0) * nslot * BS * BS + min(a, BS - 1);
+    double m[BS], v[BS];
+#pragma unroll
+    for (int b = 0; b < BS; ++b) {
+        m[b] = A[b * BS];
+        v[b] = b == a ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < BS; ++j) {
+        const int src = base + j;
+        const double ip = 1.0 / __shfl(m[j], src, 64);
+        const double f = m[j] * ip;
+        const bool piv = a == j;
+#pragma unroll
+        for (int b = j + 1; b < BS; ++b) {
+            const double pb = __shfl(m[b], src, 64);
+            m[b] = piv ? pb * ip : m[b] - f * pb;
+        }
+#pragma unroll
+        for (int b = 0; b < BS; ++b) {
+            const double pb = __shfl(v[b], src, 64);
+            v[b] = piv ? pb * ip : v[b] - f * pb;
+        }
+    }
+    if (ok) {
+        double* out = pinv + (size_t)F * BS * BS + a;
+#pragma unroll
+        for (int b = 0; b < BS; ++b) out[b * BS] = v[b];
     }
 }
 
@@ -411,6 +458,24 @@ __global__ __launch_bounds__(NT) void dot_final_kernel(int nb, int R, const doub
     }
 }
 
+// out = sum of nb partial sums (one column): 1024 threads, so that a few thousand partials take
+// a few loads per thread
+__global__ __launch_bounds__(1024) void sum_partials_kernel(int nb, const double* __restrict__ part,
+                                                            double* __restrict__ out) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 1024) acc += part[b];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += sh[w];
+        *out = t;
+    }
+}
+
 // CG update of one iteration in a single pass: x += alpha p, r -= alpha q (alpha = num/den per
 // column), and the partial sums of the new r squared per column, in the thread layout of
 // dot_partial_kernel (part[blk][r], reduced by dot_final_kernel)
@@ -526,6 +591,7 @@ int resident_groups(const void* kernel, int block) {
 
 template <bool MAT>
 static int launch_asm(hdg_ctx* c, const double* lam_bnd) {
+    if (MAT) ++c->mat_version;
     int grid = (int)std::min<int64_t>(c->n_faces, 65536);
     if (c->precision == HDG_FP64)
         hipLaunchKernelGGL((assemble_kernel<double, MAT>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
@@ -552,15 +618,22 @@ int launch_assemble_rhs64(hdg_ctx* c, const double* re64, const double* lam_bnd)
 
 int launch_block_inverse(hdg_ctx* c) {
     if (c->bs > BI_MAX) return -1;
+    c->pinv_version = c->mat_version;
+#define HDG_BS(B)                                                                                             \
+    if (c->bs == B) {                                                                                         \
+        constexpr int64_t FPB = (64 / B) * (NT / 64);                                                         \
+        hipLaunchKernelGGL((block_inverse_rows_kernel<B>), dim3((unsigned)((c->n_faces + FPB - 1) / FPB)),     \
+                           dim3(NT), 0, c->stream, c->n_faces, c->nslot, c->d_bsr, c->d_pinv);                 \
+        return (int)hipGetLastError();                                                                        \
+    }
+    HDG_BS_CASES(HDG_BS)
+#undef HDG_BS
     int grid = (int)std::min<int64_t>(c->n_faces, 65536);
     hipLaunchKernelGGL(block_inverse_kernel, dim3(grid), dim3(64), 0, c->stream, c->n_faces, c->nslot, c->bs,
                        c->d_bsr, c->d_pinv);
     return (int)hipGetLastError();
 }
 
-// block sizes of the built 3D configurations (m_trace * N_F: acoustic k = 1..5, Maxwell
-// k = 3, elastic k = 4) get the fixed-size kernels
-#define HDG_BS_CASES(X) X(3) X(6) X(10) X(15) X(20) X(21) X(45)
 
 static int64_t nblk_faces(const hdg_ctx* c) { return (c->n_faces + 3) / 4; }
 
@@ -733,6 +806,7 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
     double* s_pq = c->d_scal + 64;       // [R]
     double* s_rr = c->d_scal + 96;       // [R]
     double* s_bb = c->d_scal + 128;      // [R]
+    if (c->pinv_version != c->mat_version && launch_block_inverse(c)) return HDG_E_HIP;
     // boundary entries of x are the Dirichlet values (identity rows)
     hipLaunchKernelGGL(copy_bnd_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, c->n_faces, c->bs, R,
                        c->d_face_bnd, c->d_rhs, x);
@@ -789,134 +863,272 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
 
 namespace {
 // ------------------------------------------------------------------ multicolour block SSOR
-// One sweep of a colour: for every face F of colour c (faces of one colour share no element, so
-// they are independent), one group of BS lanes of a wavefront (lane a = row a of the face
-// block; 64 / BS faces per wavefront, the remaining lanes idle):
-//   s = v_F [- D_F t_F]  - sum over the neighbour slots of lower (forward) or higher (backward)
-//       colour of A_{F,G} y_G,        y_F = D_F^{-1} s      [, q_F = t_F + y_F]
-// (HAT: the forward sweep of Eisenstat's product, whose right-hand side is p - D t and whose
-// output is q = t + (D + L)^{-1} (p - D t)).  D_F^{-1} s mixes the rows of the face: the lanes
-// exchange s through shuffles within the group.  Blocks are column-major (entry (a, b) at
-// b BS + a), slot 0 of a block row the diagonal block.
-template <int BS, bool UP, bool HAT>
-__global__ __launch_bounds__(NT) void ssor_sweep_kernel(int64_t nfc, const int32_t* __restrict__ flist,
-                                                        const uint8_t* __restrict__ lmask,
-                                                        const int32_t* __restrict__ cols,
-                                                        const double* __restrict__ bsr,
-                                                        const double* __restrict__ dinv,
-                                                        const double* __restrict__ v,
-                                                        const double* __restrict__ t, double* __restrict__ y,
-                                                        double* __restrict__ q) {
-    constexpr int FPW = 64 / BS, NS = 7;
+// The preconditioner works on the block-diagonally scaled matrix  Kt = W K W^T,  W = diag(R_F^{-1}),
+// D_F = R_F R_F^T the Cholesky factor of the diagonal block of face F.  Kt has identity diagonal
+// blocks, and block SSOR on Kt is block SSOR on K carried over by W (W (D+L) D^{-1} (D+U) W^T =
+// (I + Lt)(I + Ut) for the strict block triangles Lt, Ut of Kt), so the iterates are the same; but
+// the sweeps need no diagonal block or its inverse and the preconditioner of the transformed CG
+// (z = D r) becomes the identity.  Per CG iteration the matrix traffic is one read of the
+// off-diagonal blocks of Kt, against four more reads of the diagonal blocks without the scaling.
+
+// R_F^{-1} of each diagonal block, D_F = R_F R_F^T (Cholesky, R_F lower triangular): a group of
+// BS lanes per face, lane a holding row a of the block, then row a of R_F^{-1} (64 / BS faces per
+// wavefront, the remaining lanes idle).  Right-looking factorisation, then the rows of R_F^{-1} in
+// order, Y_a = (e_a - sum_{i<a} R(a,i) Y_i) / R(a,a), each finished row broadcast by shuffles.
+// Blocks column-major (entry (r, c) at c BS + r).  A block that is not positive definite gives
+// NaN, which the CG reports as not converged.
+template <int BS>
+__global__ __launch_bounds__(NT) void chol_rinv_kernel(int64_t nf, const double* __restrict__ bsr,
+                                                       double* __restrict__ rinv) {
+    constexpr int FPW = 64 / BS;
     const int lane = threadIdx.x & 63, fw = min(lane / BS, FPW), a = lane - fw * BS;
-    const int64_t g = ((int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * FPW + fw;
-    const bool ok = fw < FPW && g < nfc;
-    const int64_t F = ok ? flist[g] : 0;
-    double sv = 0.0;
+    const int64_t F = ((int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * FPW + fw;
+    const bool ok = fw < FPW && F < nf;
+    const int base = min(lane - a, 64 - BS);
+    const double* A = bsr + (size_t)(ok ? F : 0) * 7 * BS * BS + min(a, BS - 1);
+    double m[BS];
+#pragma unroll
+    for (int b = 0; b < BS; ++b) m[b] = A[b * BS];
+    // m[j] becomes R(a, j) at step j; ri = 1 / R(a, a).  Lanes a < cc also update their upper
+    // entry m[cc], which step cc then sets to zero.
+    double ri = 0.0;
+#pragma unroll
+    for (int j = 0; j < BS; ++j) {
+        const double d = sqrt(__shfl(m[j], base + j, 64));
+        const double rd = 1.0 / d;
+        const double l = a == j ? d : (a > j ? m[j] * rd : 0.0);
+        if (a == j) ri = rd;
+        m[j] = l;
+#pragma unroll
+        for (int cc = j + 1; cc < BS; ++cc) m[cc] -= l * __shfl(l, base + cc, 64);
+    }
+    double y[BS];
+#pragma unroll
+    for (int b = 0; b < BS; ++b) y[b] = b == a ? ri : 0.0;
+    // row i of R^{-1} is final once steps 0..i-1 have been subtracted; broadcast it to the rows below
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+        const double mi = a > i ? m[i] * ri : 0.0;
+#pragma unroll
+        for (int b = 0; b <= i; ++b) y[b] -= mi * __shfl(y[b], base + i, 64);
+    }
     if (ok) {
-        // slots of this sweep: the lower-colour neighbours (forward) or the other occupied ones
-        const unsigned lo = lmask[F];
-        sv = v[F * BS + a];
-        if (HAT) {
-            const double* Dd = bsr + (size_t)F * NS * BS * BS + a;
-            const double* tf = t + F * BS;
-            double dt = 0.0;
+        double* out = rinv + (size_t)F * BS * BS + a;
 #pragma unroll
-            for (int b = 0; b < BS; ++b) dt += Dd[b * BS] * tf[b];
-            sv -= dt;
+        for (int b = 0; b < BS; ++b) out[b * BS] = y[b];
+    }
+}
+
+// The same factor for larger blocks (whose register form would not fit): one wavefront per face,
+// the block in LDS (column-major), right-looking Cholesky, then the columns of R_F^{-1} by forward
+// substitution (one lane per column).
+template <int BS>
+__global__ __launch_bounds__(64) void chol_rinv_lds_kernel(int64_t nf, const double* __restrict__ bsr,
+                                                           double* __restrict__ rinv) {
+    __shared__ double M[BS * BS];
+    __shared__ double V[BS * BS];
+    const int lane = threadIdx.x;
+    for (int64_t F = blockIdx.x; F < nf; F += gridDim.x) {
+        const double* A = bsr + (size_t)F * 7 * BS * BS;
+        for (int i = lane; i < BS * BS; i += 64) M[i] = A[i];
+        __syncthreads();
+        for (int j = 0; j < BS; ++j) {
+            const double d = sqrt(M[j * BS + j]);
+            __syncthreads();
+            for (int r = j + lane; r < BS; r += 64) M[j * BS + r] = r == j ? d : M[j * BS + r] / d;
+            __syncthreads();
+            // trailing lower triangle: M(r, c) -= R(r, j) R(c, j) for j < c <= r
+            for (int idx = lane; idx < BS * BS; idx += 64) {
+                const int cc = idx / BS, r = idx - cc * BS;
+                if (cc > j && r >= cc) M[cc * BS + r] -= M[j * BS + r] * M[j * BS + cc];
+            }
+            __syncthreads();
         }
+        for (int cc = lane; cc < BS; cc += 64) {
+            // R x = e_cc: x_i = 0 above the diagonal, then forward substitution
+            for (int i = 0; i < BS; ++i) {
+                double v = 0.0;
+                if (i >= cc) {
+                    v = i == cc ? 1.0 : 0.0;
+                    for (int j = cc; j < i; ++j) v -= M[j * BS + i] * V[cc * BS + j];
+                    v /= M[i * BS + i];
+                }
+                V[cc * BS + i] = v;
+            }
+        }
+        __syncthreads();
+        double* out = rinv + (size_t)F * BS * BS;
+        for (int i = lane; i < BS * BS; i += 64) out[i] = V[i];
+        __syncthreads();
+    }
+}
+
+// Off-diagonal blocks of Kt: Kt_{F,s} = R_F^{-1} K_{F,s} R_G^{-T} for the neighbour G of slot s
+// (slots 1..6 of the block row), written to block dst[F][s-1] of the sweep order.  A group of BS
+// lanes per face as in the factor kernel, one wavefront per workgroup: the group stages K_{F,s}
+// and R_G^{-1} in LDS (each lane loads one row of both), then lane a forms
+// u = (row a of R_F^{-1}) K_{F,s} and Kt(a, b) = u . (row b of R_G^{-1}).
+template <int BS>
+__global__ __launch_bounds__(64) void ssor_scale_kernel(int64_t nf, const int32_t* __restrict__ cols,
+                                                        const int32_t* __restrict__ dst,
+                                                        const double* __restrict__ bsr,
+                                                        const double* __restrict__ rinv, double* __restrict__ out) {
+    constexpr int FPW = 64 / BS;
+    __shared__ double Ks[FPW][BS * BS];
+    __shared__ double Rs[FPW][BS * BS];
+    const int lane = threadIdx.x, fw = min(lane / BS, FPW), a = lane - fw * BS;
+    const int64_t F = (int64_t)blockIdx.x * FPW + fw;
+    const bool ok = fw < FPW && F < nf;
+    const int g = min(fw, FPW - 1);
+    double rf[BS];
+    const double* RF = rinv + (size_t)(ok ? F : 0) * BS * BS + a;
 #pragma unroll
-        for (int s = 1; s < NS; ++s) {
-            if (((lo >> s) & 1u) == (UP ? 1u : 0u)) continue;
-            const int32_t cF = cols[F * NS + s];
-            if (cF < 0) continue;
-            const double* B = bsr + ((size_t)F * NS + s) * BS * BS + a;
-            const double* yv = y + (size_t)cF * BS;
+    for (int i = 0; i < BS; ++i) rf[i] = RF[i * BS];
+    for (int s = 1; s < 7; ++s) {
+        const int32_t G = ok ? cols[F * 7 + s] : -1;
+        const int32_t D = G >= 0 ? dst[F * 6 + s - 1] : -1;   // every neighbour has its sweep block
+        if (D >= 0) {
+            const double* K = bsr + ((size_t)F * 7 + s) * BS * BS + a;
+            const double* RG = rinv + (size_t)G * BS * BS + a;
+#pragma unroll
+            for (int j = 0; j < BS; ++j) {
+                Ks[g][j * BS + a] = K[j * BS];
+                Rs[g][j * BS + a] = RG[j * BS];
+            }
+        }
+        __syncthreads();
+        if (D >= 0) {
+            double u[BS];
+#pragma unroll
+            for (int j = 0; j < BS; ++j) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < BS; ++i) acc += rf[i] * Ks[g][j * BS + i];
+                u[j] = acc;
+            }
+            double* O = out + (size_t)D * BS * BS + a;
+#pragma unroll
+            for (int b = 0; b < BS; ++b) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < BS; ++j) acc += u[j] * Rs[g][j * BS + b];
+                O[b * BS] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One sweep of a colour on Kt (unit diagonal blocks): for every face F of colour c (faces of one
+// colour share no element, so they are independent), one thread per row a of the face:
+//   y_Fa = v_Fa [- t_Fa] - sum over the neighbours G of lower (forward) or higher (backward)
+//          colour of (Kt_{F,G} y_G)_a                                   [, q_Fa = t_Fa + y_Fa]
+// HAT: the forward sweep of Eisenstat's product, whose right-hand side is p - t and whose output
+// is q = t + (I + Lt)^{-1} (p - t).  The blocks of the sweep are stored in its order: those of
+// colour-order position P are off[P] .. off[P+1]-1, with neighbours nbr[k]; the faces of one
+// colour read one contiguous range.
+//
+// Fusions of the product sweeps (the CG's other vector work on the same rows):
+//   PX (backward sweep of the product, v = p): p_F = r_F + beta p_F first when num is given
+//      (beta = num/den, the CG's direction update);
+//   C0 (backward sweep of colour 0, the last one): also the forward sweep's colour-0 rows, which
+//      have no lower neighbours: u_F = p_F - t_F, q_F = t_F + u_F;
+//   with part: partial sums of p.q per workgroup (HAT, and C0 for the colour-0 rows).
+struct SweepArgs {
+    const int32_t* cfaces;
+    const int32_t* off;
+    const int32_t* nbr;
+    const double* sa;
+    const double* v;
+    const double* t;
+    double* y;
+    double* q;
+    const double* r;     // PX
+    const double* num;   // PX: null, no direction update
+    const double* den;
+    double* u0;          // C0
+    double* part;        // p.q partials (HAT, C0), or null
+};
+
+template <int BS, bool HAT, bool PX, bool C0>
+__global__ __launch_bounds__(NT) void ssor_sweep_kernel(int64_t p0, int64_t nfc, SweepArgs A) {
+    const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const bool act = gid < nfc * BS;
+    double pq = 0.0;
+    if (act) {
+        const int64_t P = p0 + gid / BS;
+        const int a = (int)(gid % BS);
+        const int64_t F = A.cfaces[P];
+        const int32_t k0 = A.off[P], k1 = A.off[P + 1];
+        const int64_t k = F * BS + a;
+        double sv = A.v[k];
+        if constexpr (PX) {
+            if (A.num) {
+                const double dd = A.den[0];
+                sv = A.r[k] + (dd != 0.0 ? A.num[0] / dd : 0.0) * sv;
+                const_cast<double*>(A.v)[k] = sv;
+            }
+        }
+        const double pk = sv;
+        double tk = 0.0;
+        if constexpr (HAT) {
+            tk = A.t[k];
+            sv -= tk;
+        }
+        for (int32_t kb = k0; kb < k1; ++kb) {
+            const double* B = A.sa + (size_t)kb * BS * BS + a;
+            const double* yv = A.y + (size_t)A.nbr[kb] * BS;
             double acc = 0.0;
 #pragma unroll
             for (int b = 0; b < BS; ++b) acc += B[b * BS] * yv[b];
             sv -= acc;
         }
+        A.y[k] = sv;
+        if constexpr (HAT) {
+            A.q[k] = tk + sv;
+            pq = pk * (tk + sv);
+        }
+        if constexpr (C0) {
+            A.u0[k] = pk - sv;
+            A.q[k] = pk;
+            pq = pk * pk;
+        }
     }
-    // y_F = D_F^{-1} s: row a needs all of s (held by the group's BS lanes)
-    const double* Di = dinv + (size_t)F * BS * BS + min(a, BS - 1);
-    const int base = min(lane - a, 64 - BS);
-    double out = 0.0;
+    if constexpr (HAT || C0) {
+        if (!A.part) return;
+        __shared__ double sh[NT / 64];
 #pragma unroll
-    for (int b = 0; b < BS; ++b) out += Di[b * BS] * __shfl(sv, base + b, 64);
-    if (ok) {
-        y[F * BS + a] = out;
-        if (HAT) q[F * BS + a] = t[F * BS + a] + out;
+        for (int o = 32; o > 0; o >>= 1) pq += __shfl_xor(pq, o, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = pq;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tsum = 0.0;
+            for (int w = 0; w < NT / 64; ++w) tsum += sh[w];
+            A.part[blockIdx.x] = tsum;
+        }
     }
 }
 
-// z_F = D_F r_F (the diagonal blocks of the assembled matrix: slot 0 of each block row)
+// out = x + W^T t  (W^T = diag(R_F^{-T}): row a of R_F^{-T} is column a of R_F^{-1})
 template <int BS>
-__global__ __launch_bounds__(NT) void diag_block_apply_kernel(int64_t nf, const double* __restrict__ bsr,
-                                                              const double* __restrict__ x, double* __restrict__ y) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(NT) void rinvt_axpy_kernel(int64_t nf, const double* __restrict__ rinv,
+                                                        const double* __restrict__ x, const double* __restrict__ t,
+                                                        double* __restrict__ out) {
+    const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (gid >= nf * BS) return;
     const int64_t F = gid / BS;
     const int a = (int)(gid % BS);
-    const double* Dd = bsr + (size_t)F * 7 * BS * BS + a;
-    const double* xv = x + F * BS;
+    const double* Rc = rinv + (size_t)F * BS * BS + (size_t)a * BS;
+    const double* tv = t + F * BS;
     double acc = 0.0;
 #pragma unroll
-    for (int b = 0; b < BS; ++b) acc += Dd[b * BS] * xv[b];
-    y[gid] = acc;
-}
-}  // namespace
-
-namespace {
-// CG update of the transformed system fused with its preconditioner product: y += alpha p,
-// r -= alpha q, z = D r (diagonal block of the face, rows exchanged by shuffles), and the partial
-// sums of r.z per workgroup (part[blk], reduced by dot_final_kernel); groups of BS lanes per face
-// as in the sweeps.
-template <int BS>
-__global__ __launch_bounds__(NT) void ssor_update_kernel(int64_t nf, const double* __restrict__ num,
-                                                         const double* __restrict__ den,
-                                                         const double* __restrict__ p, const double* __restrict__ q,
-                                                         double* __restrict__ y, double* __restrict__ r,
-                                                         double* __restrict__ z, const double* __restrict__ bsr,
-                                                         double* __restrict__ part) {
-    constexpr int FPW = 64 / BS;
-    __shared__ double sh[NT / 64];
-    const int lane = threadIdx.x & 63, fw = min(lane / BS, FPW), a = lane - fw * BS;
-    const int64_t F = ((int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6)) * FPW + fw;
-    const bool ok = fw < FPW && F < nf;
-    const double dd = den[0];
-    const double al = dd != 0.0 ? num[0] / dd : 0.0;
-    double rn = 0.0;
-    if (ok) {
-        const int64_t k = F * BS + a;
-        y[k] += al * p[k];
-        rn = r[k] - al * q[k];
-        r[k] = rn;
-    }
-    const double* Dd = bsr + (size_t)(ok ? F : 0) * 7 * BS * BS + min(a, BS - 1);
-    const int base = min(lane - a, 64 - BS);
-    double zr = 0.0;
-#pragma unroll
-    for (int b = 0; b < BS; ++b) zr += Dd[b * BS] * __shfl(rn, base + b, 64);
-    double acc = 0.0;
-    if (ok) {
-        z[F * BS + a] = zr;
-        acc = rn * zr;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) sh[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < NT / 64; ++w) t += sh[w];
-        part[blockIdx.x] = t;
-    }
+    for (int b = 0; b < BS; ++b) acc += Rc[b] * tv[b];
+    out[gid] = x[gid] + acc;
 }
 }  // namespace
 
 bool ssor_supported(const hdg_ctx* c) {
-    if (c->nrhs != 1 || c->nslot != 7 || c->ncolors == 0 || !c->d_cfaces || !c->d_lmask) return false;
+    if (c->nrhs != 1 || c->nslot != 7 || c->ncolors == 0 || !c->d_cfaces || !c->d_ssoff) return false;
 #define HDG_BS(B) \
     if (c->bs == B) return true;
     HDG_BS_CASES(HDG_BS)
@@ -931,25 +1143,69 @@ namespace {
     } while (0)
 
 // one sweep over all colours (forward: colour 0 first; backward: the last colour first)
-template <int BS, bool UP, bool HAT>
-void ssor_sweep(hdg_ctx* c, const double* v, const double* t, double* y, double* q) {
-    constexpr int FPB = (64 / BS) * (NT / 64);   // faces per workgroup
+template <int BS, bool UP>
+void ssor_sweep(hdg_ctx* c, const double* v, double* y) {
+    SweepArgs A{c->d_cfaces, c->d_ssoff + (UP ? c->n_faces + 1 : 0), c->d_ssnb, c->d_ssA, v, nullptr, y,
+                nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     for (int k = 0; k < c->ncolors; ++k) {
         const int col = UP ? c->ncolors - 1 - k : k;
-        const int64_t f0 = c->color_off[col], nfc = c->color_off[col + 1] - f0;
+        const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
         if (nfc == 0) continue;
-        hipLaunchKernelGGL((ssor_sweep_kernel<BS, UP, HAT>), dim3((unsigned)((nfc + FPB - 1) / FPB)), dim3(NT), 0, c->stream, nfc,
-                           c->d_cfaces + f0, c->d_lmask, c->d_bsr_cols, c->d_bsr, c->d_pinv, v, t, y, q);
+        hipLaunchKernelGGL((ssor_sweep_kernel<BS, false, false, false>), dim3(nblk(nfc * BS)), dim3(NT), 0,
+                           c->stream, p0, nfc, A);
     }
 }
 
-// CG on the transformed system  Ahat y = Lt^{-1} r0,  Ahat = Lt^{-1} K Ut^{-1}  (Lt = D + L,
-// Ut = D + U = Lt^T), with the product z = D r as its preconditioner: the iterates are those of
-// PCG on K with the SSOR preconditioner M = Lt D^{-1} Ut.  Eisenstat's form of the product:
-// t = Ut^{-1} p,  Ahat p = t + Lt^{-1} (p - D t).  The correction of the initial guess x0 is
-// x - x0 = Ut^{-1} y.  r.z (the residual in the M^{-1} norm) drives the iteration; when its
-// relative value drops below the tolerance, the true relative residual |b - K x| / |b| is
-// formed and decides (a failed check tightens the estimate's threshold tenfold).
+// q = Ahat p = t + Lh^{-1} (p - t), t = Uh^{-1} p, and s_pq = p.q; with num/den first
+// p = r + (num/den) p.  The backward sweep's colour-0 launch also forms the forward sweep's
+// colour-0 rows; the p.q partials of all launches go to d_red when they fit (else a separate dot).
+template <int BS>
+void ssor_product(hdg_ctx* c, double* p, const double* r, const double* num, const double* den, double* t,
+                  double* u, double* q, double* s_pq) {
+    const int nc = c->ncolors;
+    int64_t nparts = 0;
+    for (int k = 0; k < nc; ++k) nparts += nblk((c->color_off[k + 1] - c->color_off[k]) * BS);
+    const bool fuse = nparts <= (int64_t)RED_MAX * 32;
+    int64_t po = 0;
+    SweepArgs B{c->d_cfaces, c->d_ssoff + c->n_faces + 1, c->d_ssnb, c->d_ssA, p, nullptr, t, q, r, num, den,
+                u, nullptr};
+    for (int k = 0; k < nc; ++k) {
+        const int col = nc - 1 - k;
+        const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
+        if (nfc == 0) continue;
+        if (col == 0) {
+            B.part = fuse ? c->d_red + po : nullptr;
+            po += nblk(nfc * BS);
+            hipLaunchKernelGGL((ssor_sweep_kernel<BS, false, true, true>), dim3(nblk(nfc * BS)), dim3(NT), 0,
+                               c->stream, p0, nfc, B);
+        } else {
+            hipLaunchKernelGGL((ssor_sweep_kernel<BS, false, true, false>), dim3(nblk(nfc * BS)), dim3(NT), 0,
+                               c->stream, p0, nfc, B);
+        }
+    }
+    SweepArgs H{c->d_cfaces, c->d_ssoff, c->d_ssnb, c->d_ssA, p, t, u, q, nullptr, nullptr, nullptr, nullptr,
+                nullptr};
+    for (int col = 1; col < nc; ++col) {
+        const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
+        if (nfc == 0) continue;
+        H.part = fuse ? c->d_red + po : nullptr;
+        po += nblk(nfc * BS);
+        hipLaunchKernelGGL((ssor_sweep_kernel<BS, true, false, false>), dim3(nblk(nfc * BS)), dim3(NT), 0,
+                           c->stream, p0, nfc, H);
+    }
+    if (fuse)
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, c->stream, (int)po, c->d_red, s_pq);
+    else
+        dot(c, p, q, s_pq);
+}
+
+// CG on the transformed system  Ahat y = Lh^{-1} W r0,  Ahat = Lh^{-1} Kt Uh^{-1}  (Lh = I + Lt,
+// Uh = I + Ut = Lh^T): the iterates are those of PCG on K with the block SSOR preconditioner
+// M = (D + L) D^{-1} (D + U).  Eisenstat's form of the product: t = Uh^{-1} p,
+// Ahat p = t + Lh^{-1} (p - t).  The correction of the initial guess x0 is x - x0 = W^T Uh^{-1} y.
+// r.r of the transformed residual (the residual of K in the M^{-1} norm) drives the iteration;
+// when its relative value drops below the tolerance, the true relative residual |b - K x| / |b|
+// is formed and decides (a failed check tightens the estimate's threshold tenfold).
 template <int BS>
 int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
     const int64_t n = c->n_faces * BS;
@@ -965,13 +1221,29 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
     double* s_pq = c->d_scal + 64;
     double* s_bb = c->d_scal + 128;
     double* s_rr = c->d_scal + 96;
-    auto diag = [&](const double* in, double* out) {
-        hipLaunchKernelGGL((diag_block_apply_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->d_bsr,
-                           in, out);
+    if (c->ss_version != c->mat_version) {   // the scaled copy belongs to an earlier assembly
+        if constexpr (BS <= 21) {
+            constexpr int64_t FPB = (64 / BS) * (NT / 64);   // faces per workgroup of the factor kernel
+            hipLaunchKernelGGL((chol_rinv_kernel<BS>), dim3((unsigned)((c->n_faces + FPB - 1) / FPB)), dim3(NT),
+                               0, c->stream, c->n_faces, c->d_bsr, c->d_rinv);
+        } else {
+            hipLaunchKernelGGL((chol_rinv_lds_kernel<BS>), dim3((unsigned)std::min<int64_t>(c->n_faces, 65536)),
+                               dim3(64), 0, c->stream, c->n_faces, c->d_bsr, c->d_rinv);
+        }
+        hipLaunchKernelGGL((ssor_scale_kernel<BS>), dim3((unsigned)((c->n_faces + 64 / BS - 1) / (64 / BS))),
+                           dim3(64), 0, c->stream, c->n_faces, c->d_bsr_cols, c->d_ssdst, c->d_bsr, c->d_rinv,
+                           c->d_ssA);
+        HIPCHK_INT(hipGetLastError());
+        c->ss_version = c->mat_version;
+    }
+    auto wapply = [&](const double* in, double* out) {   // out = W in
+        hipLaunchKernelGGL((block_apply_fixed_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, 1,
+                           c->d_rinv, in, out, (const int*)nullptr);
     };
-    auto true_residual = [&](double* hres) -> int {   // x_try = x0 + Ut^{-1} y into zz; |b - K x_try|^2
-        ssor_sweep<BS, true, false>(c, yy, nullptr, tt, nullptr);
-        launch_lincomb(c, n, 1.0, x, 1.0, tt, zz);
+    auto true_residual = [&](double* hres) -> int {   // x_try = x0 + W^T Uh^{-1} y into zz; |b - K x_try|^2
+        ssor_sweep<BS, true>(c, yy, tt);
+        hipLaunchKernelGGL((rinvt_axpy_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->d_rinv,
+                           x, tt, zz);
         spmv(c, zz, qq);
         launch_lincomb(c, n, 1.0, c->d_rhs, -1.0, qq, uu);
         dot(c, uu, uu, s_rr);
@@ -984,17 +1256,17 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
                        c->d_rhs, x);
     spmv(c, x, qq);
     launch_lincomb(c, n, 1.0, c->d_rhs, -1.0, qq, uu);             // r0 = b - K x0
-    ssor_sweep<BS, false, false>(c, uu, nullptr, rr, nullptr);     // rhat = Lt^{-1} r0
+    wapply(uu, tt);
+    ssor_sweep<BS, false>(c, tt, rr);                              // rhat = Lh^{-1} W r0
     hipMemsetAsync(yy, 0, n * sizeof(double), c->stream);
-    diag(rr, zz);
-    launch_lincomb(c, n, 1.0, zz, 0.0, nullptr, pp);
-    dot(c, rr, zz, s_rz);
+    launch_lincomb(c, n, 1.0, rr, 0.0, nullptr, pp);
+    dot(c, rr, rr, s_rz);
     dot(c, c->d_rhs, c->d_rhs, s_bb);
-    // the scale of r.z: (Lt^{-1} b)^T D (Lt^{-1} b)
-    ssor_sweep<BS, false, false>(c, c->d_rhs, nullptr, uu, nullptr);
-    diag(uu, tt);
-    dot(c, uu, tt, s_pq);
-    double h[3];
+    // the scale of r.r: |Lh^{-1} W b|^2
+    wapply(c->d_rhs, tt);
+    ssor_sweep<BS, false>(c, tt, uu);
+    dot(c, uu, uu, s_pq);
+    double h[2];
     HIPCHK_INT(hipMemcpyAsync(&h[0], s_bb, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK_INT(hipMemcpyAsync(&h[1], s_pq, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK_INT(hipStreamSynchronize(c->stream));
@@ -1004,16 +1276,17 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
     double worst = std::numeric_limits<double>::quiet_NaN();
     int it = 0;
     double* hrz = c->h_rr;
+    // q = Ahat p, p.q (writes t, u, q; with beta also p = r + beta p first, beta = s_rz / s_rz_new
+    // after the swap at the end of an iteration)
+    auto product = [&](bool beta) {
+        ssor_product<BS>(c, pp, rr, beta ? s_rz : nullptr, s_rz_new, tt, uu, qq, s_pq);
+    };
     for (it = 0; it <= c->krylov_maxit; ++it) {
         if (hipMemcpyAsync(hrz, s_rz, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipEventRecord(c->ev_rr, c->stream) != hipSuccess)
             return HDG_E_HIP;
-        // queue the next product (writes t, u, q and p.q only) before waiting for r.z
-        if (it < c->krylov_maxit) {
-            ssor_sweep<BS, true, false>(c, pp, nullptr, tt, nullptr);
-            ssor_sweep<BS, false, true>(c, pp, tt, uu, qq);
-            dot(c, pp, qq, s_pq);
-        }
+        // queue the next product before waiting for r.r
+        if (it < c->krylov_maxit) product(it > 0);
         if (hipEventSynchronize(c->ev_rr) != hipSuccess) return HDG_E_HIP;
         const double est = std::sqrt(std::fabs(hrz[0]) / bm);
         if (!(est - est == 0.0)) {
@@ -1025,33 +1298,16 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
             if (true_residual(&hres)) return HDG_E_HIP;
             worst = std::sqrt(hres) / bnorm;
             if (!(worst - worst == 0.0) || worst <= tol || it == c->krylov_maxit) {
-                launch_lincomb(c, n, 1.0, zz, 0.0, nullptr, x);   // x = x0 + Ut^{-1} y
+                launch_lincomb(c, n, 1.0, zz, 0.0, nullptr, x);   // x = x0 + W^T Uh^{-1} y
                 break;
             }
             thresh *= 0.1;
-            // the check overwrote t and q: queue the product of this iteration again
-            ssor_sweep<BS, true, false>(c, pp, nullptr, tt, nullptr);
-            ssor_sweep<BS, false, true>(c, pp, tt, uu, qq);
-            dot(c, pp, qq, s_pq);
+            product(false);   // the check overwrote t, u and q: this iteration's product again (p is new)
         }
-        {
-            constexpr int FPB = (64 / BS) * (NT / 64);
-            const int grid = (int)((c->n_faces + FPB - 1) / FPB);
-            if (grid <= RED_MAX * 32) {
-                hipLaunchKernelGGL((ssor_update_kernel<BS>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, s_rz,
-                                   s_pq, pp, qq, yy, rr, zz, c->d_bsr, c->d_red);
-                hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, grid, 1, c->d_red, s_rz_new,
-                                   (const int*)nullptr);
-            } else {
-                hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, 1, s_rz, s_pq,
-                                   pp, qq, yy, rr, c->d_red, (const int*)nullptr, (int*)nullptr);
-                diag(rr, zz);
-                dot(c, rr, zz, s_rz_new);
-            }
-        }
-        hipLaunchKernelGGL(xpby_cols_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, n, 1, s_rz_new, s_rz, zz, pp,
-                           (const int*)nullptr);
-        std::swap(s_rz, s_rz_new);
+        hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, 1, s_rz, s_pq, pp, qq,
+                           yy, rr, c->d_red, (const int*)nullptr, (int*)nullptr);
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, c->stream, c->red_blocks, c->d_red, s_rz_new);
+        std::swap(s_rz, s_rz_new);   // the next product forms p = r + (s_rz / s_rz_new) p
     }
     if (iters) *iters = it;
     if (relres) *relres = worst;
@@ -1062,11 +1318,14 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
 }  // namespace
 
 int trace_cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
-    if (!c->d_ss) {
-        void* p = nullptr;
-        const int e = dev_malloc(c, &p, (size_t)3 * c->n_faces * c->bs * sizeof(double));
+    const size_t nt = (size_t)c->n_faces * c->bs;
+    void** bufs[3] = {(void**)&c->d_ss, (void**)&c->d_rinv, (void**)&c->d_ssA};
+    const size_t sizes[3] = {3 * nt, nt * c->bs, (size_t)std::max<int64_t>(c->ss_nblk, 1) * c->bs * c->bs};
+    for (int i = 0; i < 3; ++i) {
+        if (*bufs[i]) continue;
+        const int e = dev_malloc(c, bufs[i], sizes[i] * sizeof(double));
         if (e) return e;
-        c->d_ss = (double*)p;
+        c->ss_version = -1;
     }
 #define HDG_BS(B) \
     if (c->bs == B) return cg_ssor<B>(c, x, tol, iters, relres);
@@ -1125,6 +1384,7 @@ int trace_cg_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, doub
     double* s_rr = c->d_scal + 96;
     double* s_bb = c->d_scal + 128;
     double* s_res = relres_dev;
+    if (c->pinv_version != c->mat_version && launch_block_inverse(c)) return HDG_E_HIP;
     launch_zero_ints(c, flags, 2);
     hipLaunchKernelGGL(copy_bnd_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, c->n_faces, c->bs, R,
                        c->d_face_bnd, c->d_rhs, x);
