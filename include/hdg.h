@@ -170,8 +170,10 @@ typedef struct {
     void* alloc_user;
     int precond;                /* trace-solve preconditioner (enum hdg_precond).  HDG_PC_SSOR
                                    applies to one right-hand side in 3D (the block sizes of the
-                                   built configurations); elsewhere, and inside the step graph,
-                                   block Jacobi is used.                                      */
+                                   built configurations), in hdg_trace_solve and in the
+                                   correction solves of the mixed-precision refinement;
+                                   elsewhere, inside the step graph and in
+                                   hdg_trace_solve_static, block Jacobi is used.              */
 } hdg_options;
 
 /* Preconditioners of the trace CG (section 2.4.2 uses BILU(0) inside RAS; K is symmetric
@@ -181,11 +183,14 @@ enum hdg_precond {
     HDG_PC_SSOR = 1             /* block symmetric Gauss-Seidel in a multicolour face order
                                    (faces that share an element get different colours):
                                    M = (D + L) D^-1 (D + U), applied through Eisenstat's form
-                                   (CG on (D + L)^-1 K (D + U)^-1 with the product D r as its
-                                   preconditioner), so an iteration costs one forward and one
-                                   backward colour sweep instead of a product and a Jacobi
-                                   step; convergence is confirmed on the same relative
-                                   residual |b - K x| / |b| as with block Jacobi            */
+                                   on the block-diagonally scaled matrix W K W^T (W = R^-1 per
+                                   face, D_F = R R^T), whose diagonal blocks are the identity:
+                                   plain CG on (I + Lt)^-1 W K W^T (I + Ut)^-1, so an
+                                   iteration costs one backward and one forward colour sweep
+                                   and no diagonal block; convergence is confirmed on the
+                                   same relative residual |b - K x| / |b| as with block
+                                   Jacobi.  The scaled matrix (about 6 face blocks per face) is
+                                   formed at the first solve after each assembly.           */
 };
 
 /* Query keys for hdg_query. */
@@ -266,13 +271,13 @@ hdg_status hdg_condense_rhs(hdg_ctx* ctx, double a, const double* f_loc, const d
 /*
  * hdg_trace_solve -- solve the assembled trace system K lam = r in FP64 (section 2.4.2;
  * K is symmetric and definite for every physics here, so preconditioned conjugate
- * gradients replace GMRES; block-Jacobi preconditioner).
+ * gradients replace GMRES; block-Jacobi or block-SSOR preconditioner, options.precond).
  *   lambda   device [n_trace_dofs][nrhs] in: initial guess (boundary entries are reset to
  *            the Dirichlet values), out: solution
  *   iters    host, may be NULL: iterations used
  *   relres   host, may be NULL: final max over rhs of ||r - K lam|| / ||r||
- * In HDG_MIXED_FP32 mode on 3D meshes with 1 or 32 right-hand sides the matrix products
- * read an FP32 copy of K (K is assembled from the FP32 factors and hdg_recover's refinement
+ * With block Jacobi in HDG_MIXED_FP32 mode on 3D meshes with 1 or 32 right-hand sides the
+ * matrix products read an FP32 copy of K (K is assembled from the FP32 factors and hdg_recover's refinement
  * evaluates the residual in FP64 from the element operators, so this changes the solve only
  * at the level of error the refinement removes); relres then refers to that copy.
  * Synchronises the stream.  HDG_E_NOCONV if krylov_tol is not met within krylov_maxit.

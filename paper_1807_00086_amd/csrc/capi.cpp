@@ -680,11 +680,12 @@ hdg_status hdg_condense(hdg_ctx* c, double a, const double* f_loc, const double*
     {
         EventTimer t(c, &c->tim.assemble);
         e = launch_assemble(c, lam_bnd);
-        // the FP64 solve with block SSOR does not use the block-Jacobi inverses (a later Jacobi
-        // solve forms them itself)
-        if (!e && !(c->precond == HDG_PC_SSOR && ssor_supported(c) && c->precision == HDG_FP64))
-            e = launch_block_inverse(c);
-        if (!e) e = launch_bsr_f32(c);
+        // block SSOR (the trace solve and the refinement's correction solves) uses neither the
+        // block-Jacobi inverses nor the FP32 copy of K; a later Jacobi solve forms them itself
+        if (!(c->precond == HDG_PC_SSOR && ssor_supported(c))) {
+            if (!e) e = launch_block_inverse(c);
+            if (!e) e = launch_bsr_f32(c);
+        }
     }
     if (e) return fail(c, HDG_E_HIP, "assembly kernel launch failed");
     c->last_a = a;
@@ -839,7 +840,11 @@ static int refine_trace_step(hdg_ctx* c, double* lambda, float* t_sol) {
         HIPCHK(hipMemsetAsync(c->d_dlam, 0, nt * sizeof(double), c->stream));
         int its;
         double rr;
-        r = trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr, true);
+        // block SSOR when configured (the FP64 scaled matrix of the first solve), else block
+        // Jacobi with the products on the FP32 copy of K
+        r = (c->precond == HDG_PC_SSOR && ssor_supported(c))
+                ? trace_cg_ssor(c, c->d_dlam, c->refine_inner_tol, &its, &rr)
+                : trace_cg(c, c->d_dlam, c->refine_inner_tol, &its, &rr, true);
     }
     if (r && r != HDG_E_NOCONV) return fail(c, r, "refinement trace solve failed");
     if (launch_axpy(c, nt, 1.0, c->d_dlam, lambda)) return fail(c, HDG_E_HIP, "refinement update launch failed");
@@ -1129,6 +1134,8 @@ hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, doub
     if (c->graph_step && c->sgexec && c->sg_key == key &&
         (!c->sg_reuse || (c->factors_cached && c->condensed && c->last_a == a))) {
         HIPCHK(hipGraphLaunch(c->sgexec, c->stream));
+        // a graph that condenses assembles K again: copies derived from K are out of date
+        if (!c->sg_reuse) ++c->mat_version;
         int h[8] = {}, st = 0;
         HIPCHK(hipMemcpyAsync(h, c->d_cgflags, 2 * ns * sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));

@@ -223,6 +223,7 @@ struct hdg_ctx {
     int64_t mat_version = 0;          // counts assemblies of the trace matrix
     int64_t ss_version = -1;          // assembly the scaled copy was built from
     int64_t pinv_version = -1;        // assembly the block-Jacobi inverses were built from
+    int64_t bsr32_version = -1;       // assembly the FP32 copy of K was made from
     // device memory of the workspaces (options.dev_alloc / dev_free; null: hipMalloc / hipFree)
     void* (*dev_alloc)(void*, size_t) = nullptr;
     void (*dev_free)(void*, void*) = nullptr;

@@ -789,6 +789,7 @@ int launch_col_sq(hdg_ctx* c, int64_t n, int R, const double* x, double* host_ou
 // together with their own scalars.  Convergence is checked on the host every iteration.
 int launch_bsr_f32(hdg_ctx* c) {
     if (!c->d_bsr32) return 0;
+    c->bsr32_version = c->mat_version;
     const int64_t n = c->n_faces * c->nslot * c->bs * c->bs;
     hipLaunchKernelGGL(to_f32_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, n, c->d_bsr, c->d_bsr32);
     return (int)hipGetLastError();
@@ -807,6 +808,7 @@ int trace_cg(hdg_ctx* c, double* x, double tol, int* iters, double* relres, bool
     double* s_rr = c->d_scal + 96;       // [R]
     double* s_bb = c->d_scal + 128;      // [R]
     if (c->pinv_version != c->mat_version && launch_block_inverse(c)) return HDG_E_HIP;
+    if (lowp && c->bsr32_version != c->mat_version && launch_bsr_f32(c)) return HDG_E_HIP;
     // boundary entries of x are the Dirichlet values (identity rows)
     hipLaunchKernelGGL(copy_bnd_kernel, dim3(nblk(n * R)), dim3(NT), 0, c->stream, c->n_faces, c->bs, R,
                        c->d_face_bnd, c->d_rhs, x);

@@ -199,7 +199,8 @@ def test_full_size_acoustic_mixed_bench_settings_sampled():
     d = ohdg.make_discretisation(p)
     a = 1.0 / (GAMMA * p.dt)
     from paper_1807_00086_amd import Solver
-    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=3, precision="mixed_fp32", **bench.MIXED_OPTS)
+    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=3, precision="mixed_fp32",
+               precond=bench.STAGE_PRECOND, **bench.MIXED_OPTS)
     nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
     f = random_vector(nl, 2, 31)[:, None]
     lb = (random_vector(nt, 2, 32) * ohdg.boundary_trace_mask(d))[:, None]
@@ -209,6 +210,32 @@ def test_full_size_acoustic_mixed_bench_settings_sampled():
     s.close()
     assert np.all(res <= bench.MIXED_OPTS["refine_tol"]), res
     _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, np.arange(nt), 60, 40, 2)
+
+
+def test_full_size_acoustic_fp64_bench_settings_sampled():
+    """The benchmark workload in FP64 exactly as the benchmark runs it (its trace preconditioner,
+    multicolour block SSOR, to krylov_tol 1e-13): sampled local and trace equations against the
+    oracle's element systems, the trace solve converged on the true residual."""
+    _need_gpu()
+    import bench
+    from oracle import hdg as ohdg
+    _T0[0] = time.time()
+    p = make_problem(2)
+    print(f"case fullsize acoustic fp64 bench settings n_elem={p.n_elem} {bench.STAGE_PRECOND}", flush=True)
+    d = ohdg.make_discretisation(p)
+    a = 1.0 / (GAMMA * p.dt)
+    from paper_1807_00086_amd import Solver
+    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=3, precision="fp64", krylov_tol=1e-13,
+               precond=bench.STAGE_PRECOND)
+    assert s.query("n_colors") == 4
+    nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+    f = random_vector(nl, 2, 33)[:, None]
+    lb = (random_vector(nt, 2, 34) * ohdg.boundary_trace_mask(d))[:, None]
+    u, lam, rr = _stage(s, a, f, lb)
+    _step(f"FP64 stage done ({s.query('last_iters')} trace iterations, relres {rr:.2e})")
+    s.close()
+    assert rr <= 1e-13
+    _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, np.arange(nt), 60, 40, 3)
 
 
 def test_full_size_pvar_mixed_sampled():

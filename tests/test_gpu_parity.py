@@ -167,9 +167,10 @@ def test_stage_parity_mixed(cfg, kw):
 
 @pytest.mark.parametrize("cfg,kw", [(2, dict(n=3, k=3)), (2, dict(n=4, k=3)), (1, dict())])
 def test_stage_parity_mixed_bench_settings(cfg, kw):
-    """The mixed-precision path exactly as the benchmark runs it (first trace solve to its
-    krylov_tol, the refinement stopping on the FP64 residual at its refine_tol) matches the FP64
-    oracle to 1e-10 per field, and the reported residual meets refine_tol."""
+    """The mixed-precision path exactly as the benchmark runs it (its trace preconditioner, the
+    first trace solve to its krylov_tol, the refinement stopping on the FP64 residual at its
+    refine_tol) matches the FP64 oracle to 1e-10 per field, and the reported residual meets
+    refine_tol."""
     _need_gpu()
     import bench
     ohdg = _oracle()
@@ -180,7 +181,7 @@ def test_stage_parity_mixed_bench_settings(cfg, kw):
     f = random_vector(d.loc_off[-1], cfg, 5)
     lb = random_vector(d.tr_off[-1], cfg, 6) * ohdg.boundary_trace_mask(d)
     u_ref, lam_ref, _ = ohdg.solve_stage(d, a, f, lb)
-    s = _solver(p, precision="mixed_fp32", **bench.MIXED_OPTS)
+    s = _solver(p, precision="mixed_fp32", precond=bench.STAGE_PRECOND, **bench.MIXED_OPTS)
     u, lam, it, rr = _gpu_stage(s, a, f, lb)
     errs = _rel_field_errors(ohdg, d, u, u_ref)
     res = s.last_residual()
