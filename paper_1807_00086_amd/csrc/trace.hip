@@ -29,6 +29,10 @@ __device__ __forceinline__ double kget(const T* K, int tt, int r, int c, int kti
 }
 
 // MAT = false: the right-hand side only (the matrix of an earlier assembly is kept)
+// One workgroup per face (grid-stride).  The face's neighbour slots are resolved once per face
+// into an LDS table (element, row and column offsets in K_e, valid columns, whether the
+// neighbour is a Dirichlet face), so every matrix entry is one load of K_e after the table:
+// the chain of dependent loads (neighbour face, its flag, then K_e) is not repeated per entry.
 template <typename T, bool MAT>
 __global__ __launch_bounds__(NT) void assemble_kernel(
     int64_t nf, int d, int bs, int tt, int R, double sign, int ktile, const int32_t* __restrict__ face_elem,
@@ -40,44 +44,63 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
     // identity rows with a zero right-hand side.  face_bnd: 1 Dirichlet (identity rows, the
     // values moved to the neighbours' right-hand sides), 2 Neumann (the one element's flux rows
     // with lam_bnd, the tested flux datum, added to the right-hand side)
+    constexpr int MS = 7;                       // slots of a block row (3D; 2D uses 5)
+    __shared__ int32_t s_e[MS], s_r0[MS], s_c0[MS], s_nc[MS], s_F2[MS], s_dir[MS];
     const int nslot = 1 + 2 * d, nv = d + 1;
     for (int64_t F = blockIdx.x; F < nf; F += gridDim.x) {
         const bool bnd = face_bnd[F] == 1;
         const int nfF = face_nf ? (int)face_nf[F] : bs;
-        int32_t es[2] = {face_elem[2 * F], face_elem[2 * F + 1]};
-        int32_t ls[2] = {face_lf[2 * F], face_lf[2 * F + 1]};
+        const int32_t es[2] = {face_elem[2 * F], face_elem[2 * F + 1]};
+        const int32_t ls[2] = {face_lf[2 * F], face_lf[2 * F + 1]};
+        if (threadIdx.x >= 1 && threadIdx.x < nslot) {
+            // slot 1 + s d + m: the m-th other face of the element on side s
+            const int sl = threadIdx.x, sd = (sl - 1) / d, m = (sl - 1) % d;
+            const int32_t e = es[sd];
+            int32_t ee = -1, r0 = 0, c0 = 0, nc = 0, F2 = -1, dir = 0;
+            if (e >= 0) {
+                const int lf = ls[sd];
+                const int q = (m < lf) ? m : m + 1;
+                F2 = eface[(size_t)e * nv + q];
+                dir = face_bnd[F2] == 1;
+                ee = e;
+                r0 = lf * bs;
+                c0 = q * bs;
+                nc = face_nf ? (int)face_nf[F2] : bs;
+            }
+            s_e[sl] = ee;
+            s_r0[sl] = r0;
+            s_c0[sl] = c0;
+            s_nc[sl] = nc;
+            s_F2[sl] = F2;
+            s_dir[sl] = dir;
+        }
+        __syncthreads();
         double* B = bsr + (size_t)F * nslot * bs * bs;
         for (int idx = threadIdx.x; MAT && idx < nslot * bs * bs; idx += NT) {
-            int slot = idx / (bs * bs), rem = idx % (bs * bs);
-            int b = rem / bs, a = rem % bs;   // column-major block
+            const int slot = idx / (bs * bs), rem = idx - slot * (bs * bs);
+            const int b = rem / bs, a = rem - b * bs;   // column-major block
             double v = 0.0;
             if (slot == 0) {
                 if (bnd || a >= nfF || b >= nfF) {
                     v = (a == b) ? 1.0 : 0.0;
                 } else {
-                    for (int s = 0; s < 2; ++s) {
-                        if (es[s] < 0) continue;
-                        const T* K = Ke + (size_t)es[s] * tt * tt;
-                        v += kget(K, tt, ls[s] * bs + a, ls[s] * bs + b, ktile);
+#pragma unroll
+                    for (int sd = 0; sd < 2; ++sd) {
+                        if (es[sd] < 0) continue;
+                        const T* K = Ke + (size_t)es[sd] * tt * tt;
+                        v += kget(K, tt, ls[sd] * bs + a, ls[sd] * bs + b, ktile);
                     }
                     v *= sign;
                 }
             } else if (!bnd) {
-                int s = (slot - 1) / d, m = (slot - 1) % d;
-                int32_t e = es[s];
-                if (e >= 0) {
-                    int lf = ls[s];
-                    int q = (m < lf) ? m : m + 1;
-                    int32_t F2 = eface[(size_t)e * nv + q];
-                    const int nf2 = face_nf ? (int)face_nf[F2] : bs;
-                    if (face_bnd[F2] != 1 && a < nfF && b < nf2)
-                        v = sign * kget(Ke + (size_t)e * tt * tt, tt, lf * bs + a, q * bs + b, ktile);
-                }
+                const int32_t e = s_e[slot];
+                if (e >= 0 && !s_dir[slot] && a < nfF && b < s_nc[slot])
+                    v = sign * kget(Ke + (size_t)e * tt * tt, tt, s_r0[slot] + a, s_c0[slot] + b, ktile);
             }
             B[idx] = v;
         }
         for (int idx = threadIdx.x; idx < bs * R; idx += NT) {
-            int a = idx / R, r = idx % R;
+            const int a = idx / R, r = idx - a * R;
             double v;
             if (bnd) {
                 v = a < nfF ? lam_bnd[((size_t)F * bs + a) * R + r] : 0.0;
@@ -85,20 +108,20 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
                 v = 0.0;
             } else {
                 v = face_bnd[F] == 2 ? lam_bnd[((size_t)F * bs + a) * R + r] : 0.0;
-                for (int s = 0; s < 2; ++s) {
-                    int32_t e = es[s];
+                for (int sd = 0; sd < 2; ++sd) {
+                    const int32_t e = es[sd];
                     if (e < 0) continue;
-                    int lf = ls[s];
+                    const int lf = ls[sd];
                     const T* K = Ke + (size_t)e * tt * tt;
                     double acc = (double)re[((size_t)e * tt + lf * bs + a) * R + r];
-                    for (int q = 0; q < nv; ++q) {
-                        if (q == lf) continue;
-                        int32_t F2 = eface[(size_t)e * nv + q];
-                        if (face_bnd[F2] != 1) continue;
-                        const int nf2 = face_nf ? (int)face_nf[F2] : bs;
+                    // Dirichlet neighbours of this element: their values move to this row
+                    for (int m = 0; m < d; ++m) {
+                        const int sl = 1 + sd * d + m;
+                        if (!s_dir[sl]) continue;
+                        const int32_t F2 = s_F2[sl];
+                        const int c0 = s_c0[sl], nf2 = s_nc[sl];
                         for (int b = 0; b < nf2; ++b)
-                            acc -= kget(K, tt, lf * bs + a, q * bs + b, ktile) *
-                                   lam_bnd[((size_t)F2 * bs + b) * R + r];
+                            acc -= kget(K, tt, lf * bs + a, c0 + b, ktile) * lam_bnd[((size_t)F2 * bs + b) * R + r];
                     }
                     v += acc;
                 }
@@ -106,6 +129,115 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
             }
             rhs[((size_t)F * bs + a) * R + r] = v;
         }
+        __syncthreads();   // the slot table is rewritten for the next face
+    }
+}
+
+// Element-centric assembly of the matrix and the right-hand side (3D, uniform degree, one
+// right-hand side, trace blocks of BS <= 10): the face-centric kernel reads each K_e once per
+// face of the element, strips of rows whose lower tiles come from the mirrored upper tiles, so
+// its loads fetch K_e more than twice over.  Here a wavefront reads its element's stored tiles
+// once into LDS and scatters them: the off-diagonal blocks K_{F,G} (F, G faces of one element)
+// belong to that element alone and are stored; a face's diagonal block and right-hand side
+// receive one contribution per element of the face, added atomically onto what
+// assemble_init_kernel wrote.  At most two contributions meet in one place (onto zero, or onto
+// the Neumann datum of a face with one element) and IEEE addition is commutative, so the sums do
+// not depend on the order of the atomics: every run gives the same bits.
+template <int BS>
+__global__ __launch_bounds__(NT) void assemble_init_kernel(int64_t nf, double sign, const int32_t* __restrict__ face_elem,
+                                                           const uint8_t* __restrict__ face_bnd,
+                                                           const double* __restrict__ lam_bnd,
+                                                           double* __restrict__ bsr, double* __restrict__ rhs) {
+    constexpr int BB = BS * BS, NS = 7;
+    const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (gid >= nf * BB) return;
+    const int64_t F = gid / BB;
+    const int rem = (int)(gid - F * BB), b = rem / BS, a = rem - b * BS;
+    const int fb = face_bnd[F];
+    const bool dir = fb == 1;
+    double* B = bsr + (size_t)F * NS * BB + rem;
+    B[0] = dir && a == b ? 1.0 : 0.0;
+    // blocks no element writes: all of a Dirichlet row, the slots of a missing side
+    const bool z0 = dir || face_elem[2 * F] < 0, z1 = dir || face_elem[2 * F + 1] < 0;
+#pragma unroll
+    for (int sl = 1; sl < NS; ++sl)
+        if (sl <= 3 ? z0 : z1) B[(size_t)sl * BB] = 0.0;
+    if (rem < BS) {
+        const double lb = fb ? lam_bnd[(size_t)F * BS + rem] : 0.0;
+        rhs[(size_t)F * BS + rem] = dir ? lb : sign * lb;
+    }
+}
+
+template <typename T, int BS>
+__global__ __launch_bounds__(64) void assemble_elem_kernel(int64_t ne, int ktile, double sign,
+                                                           const int32_t* __restrict__ face_elem,
+                                                           const uint8_t* __restrict__ face_bnd,
+                                                           const int32_t* __restrict__ eface,
+                                                           const T* __restrict__ Ke, const T* __restrict__ re,
+                                                           const double* __restrict__ lam_bnd,
+                                                           double* __restrict__ bsr, double* __restrict__ rhs) {
+    constexpr int NV = 4, TT = NV * BS, BB = BS * BS, NS = 7, LD = TT + 1, NL = (TT * TT + 63) / 64;
+    __shared__ double Ks[TT * LD];   // odd row stride: a column read by consecutive rows spreads over the banks
+    __shared__ int32_t sF[NV], sSide[NV], sDir[NV];
+    const int lane = threadIdx.x;
+    // K_e(r, c) as stored: row-major, only the tiles on and above the diagonal when ktile > 0
+    auto kl = [&](int r, int c) -> double {
+        return (ktile > 0 && r / ktile > c / ktile) ? Ks[c * LD + r] : Ks[r * LD + c];
+    };
+    for (int64_t e = blockIdx.x; e < ne; e += gridDim.x) {
+        if (lane < NV) {
+            const int32_t F = eface[(size_t)e * NV + lane];
+            sF[lane] = F;
+            sSide[lane] = face_elem[2 * (size_t)F] == (int32_t)e ? 0 : 1;
+            sDir[lane] = face_bnd[F] == 1;
+        }
+        // the whole TT x TT region in one batch of loads (the entries below the stored tiles are
+        // read and never used), so that every load of the element is in flight at once
+        const T* K = Ke + (size_t)e * TT * TT;
+        T kv[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int idx = lane + 64 * u;
+            kv[u] = idx < TT * TT ? K[idx] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int idx = lane + 64 * u;
+            if (idx < TT * TT) {
+                const int r = idx / TT, c = idx - r * TT;
+                Ks[r * LD + c] = (double)kv[u];
+            }
+        }
+        __syncthreads();
+        // matrix: block (i, q) of K_e goes to row F_i, the slot of face q (q == i: the diagonal)
+        for (int idx = lane; idx < NV * NV * BB; idx += 64) {
+            const int iq = idx / BB, rem = idx - iq * BB;
+            const int i = iq / NV, q = iq - i * NV;
+            if (sDir[i]) continue;
+            const int b = rem / BS, a = rem - b * BS;
+            const double v = sign * kl(i * BS + a, q * BS + b);
+            double* Brow = bsr + (size_t)sF[i] * NS * BB + rem;
+            if (q == i) {
+                unsafeAtomicAdd(Brow, v);
+            } else {
+                const int sl = 1 + sSide[i] * 3 + (q < i ? q : q - 1);
+                Brow[(size_t)sl * BB] = sDir[q] ? 0.0 : v;
+            }
+        }
+        // right-hand side: r_e rows of face i, minus the couplings to Dirichlet faces times their
+        // values
+        for (int idx = lane; idx < NV * BS; idx += 64) {
+            const int i = idx / BS, a = idx - i * BS;
+            if (sDir[i]) continue;
+            double acc = (double)re[(size_t)e * TT + i * BS + a];
+            for (int q = 0; q < NV; ++q) {
+                if (q == i || !sDir[q]) continue;
+                const double* lb = lam_bnd + (size_t)sF[q] * BS;
+                for (int b = 0; b < BS; ++b) acc -= kl(i * BS + a, q * BS + b) * lb[b];
+            }
+            unsafeAtomicAdd(rhs + (size_t)sF[i] * BS + a, sign * acc);
+        }
+        __syncthreads();   // Ks and the face table are rewritten for the next element
     }
 }
 
@@ -592,6 +724,27 @@ int resident_groups(const void* kernel, int block) {
 template <bool MAT>
 static int launch_asm(hdg_ctx* c, const double* lam_bnd) {
     if (MAT) ++c->mat_version;
+    if (MAT && c->dim == 3 && !c->d_face_nf && c->nrhs == 1 && c->n_tr == 4 * c->bs) {
+        const int eg = (int)std::min<int64_t>(c->n_elem, 262144);
+#define HDG_ASM_ELEM(B)                                                                                         \
+        if (c->bs == B) {                                                                                      \
+            hipLaunchKernelGGL((assemble_init_kernel<B>), dim3(nblk(c->n_faces * B * B)), dim3(NT), 0, c->stream,  \
+                               c->n_faces, c->K_sign, c->d_face_elem, c->d_face_bnd, lam_bnd, c->d_bsr, c->d_rhs); \
+            if (c->precision == HDG_FP64)                                                                      \
+                hipLaunchKernelGGL((assemble_elem_kernel<double, B>), dim3(eg), dim3(64), 0, c->stream, c->n_elem, \
+                                   c->ke_tile, c->K_sign, c->d_face_elem, c->d_face_bnd, c->d_eface,            \
+                                   (const double*)c->d_Ke, (const double*)c->d_re, lam_bnd, c->d_bsr, c->d_rhs); \
+            else                                                                                               \
+                hipLaunchKernelGGL((assemble_elem_kernel<float, B>), dim3(eg), dim3(64), 0, c->stream, c->n_elem, \
+                                   c->ke_tile, c->K_sign, c->d_face_elem, c->d_face_bnd, c->d_eface,            \
+                                   (const float*)c->d_Ke, (const float*)c->d_re, lam_bnd, c->d_bsr, c->d_rhs);  \
+            return (int)hipGetLastError();                                                                     \
+        }
+        HDG_ASM_ELEM(3)
+        HDG_ASM_ELEM(6)
+        HDG_ASM_ELEM(10)
+#undef HDG_ASM_ELEM
+    }
     int grid = (int)std::min<int64_t>(c->n_faces, 65536);
     if (c->precision == HDG_FP64)
         hipLaunchKernelGGL((assemble_kernel<double, MAT>), dim3(grid), dim3(NT), 0, c->stream, c->n_faces, c->dim,
