@@ -143,32 +143,35 @@ __global__ __launch_bounds__(NT) void assemble_kernel(
 // assemble_init_kernel wrote.  At most two contributions meet in one place (onto zero, or onto
 // the Neumann datum of a face with one element) and IEEE addition is commutative, so the sums do
 // not depend on the order of the atomics: every run gives the same bits.
-template <int BS>
+template <int BS, bool MAT>
 __global__ __launch_bounds__(NT) void assemble_init_kernel(int64_t nf, double sign, const int32_t* __restrict__ face_elem,
                                                            const uint8_t* __restrict__ face_bnd,
                                                            const double* __restrict__ lam_bnd,
                                                            double* __restrict__ bsr, double* __restrict__ rhs) {
-    constexpr int BB = BS * BS, NS = 7;
+    constexpr int BB = BS * BS, NS = 7, W = MAT ? BB : BS;   // threads per face
     const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (gid >= nf * BB) return;
-    const int64_t F = gid / BB;
-    const int rem = (int)(gid - F * BB), b = rem / BS, a = rem - b * BS;
+    if (gid >= nf * W) return;
+    const int64_t F = gid / W;
+    const int rem = (int)(gid - F * W);
     const int fb = face_bnd[F];
     const bool dir = fb == 1;
-    double* B = bsr + (size_t)F * NS * BB + rem;
-    B[0] = dir && a == b ? 1.0 : 0.0;
-    // blocks no element writes: all of a Dirichlet row, the slots of a missing side
-    const bool z0 = dir || face_elem[2 * F] < 0, z1 = dir || face_elem[2 * F + 1] < 0;
+    if (MAT) {
+        const int b = rem / BS, a = rem - b * BS;
+        double* B = bsr + (size_t)F * NS * BB + rem;
+        B[0] = dir && a == b ? 1.0 : 0.0;
+        // blocks no element writes: all of a Dirichlet row, the slots of a missing side
+        const bool z0 = dir || face_elem[2 * F] < 0, z1 = dir || face_elem[2 * F + 1] < 0;
 #pragma unroll
-    for (int sl = 1; sl < NS; ++sl)
-        if (sl <= 3 ? z0 : z1) B[(size_t)sl * BB] = 0.0;
+        for (int sl = 1; sl < NS; ++sl)
+            if (sl <= 3 ? z0 : z1) B[(size_t)sl * BB] = 0.0;
+    }
     if (rem < BS) {
         const double lb = fb ? lam_bnd[(size_t)F * BS + rem] : 0.0;
         rhs[(size_t)F * BS + rem] = dir ? lb : sign * lb;
     }
 }
 
-template <typename T, int BS>
+template <typename T, int BS, bool MAT>
 __global__ __launch_bounds__(64) void assemble_elem_kernel(int64_t ne, int ktile, double sign,
                                                            const int32_t* __restrict__ face_elem,
                                                            const uint8_t* __restrict__ face_bnd,
@@ -191,26 +194,31 @@ __global__ __launch_bounds__(64) void assemble_elem_kernel(int64_t ne, int ktile
             sSide[lane] = face_elem[2 * (size_t)F] == (int32_t)e ? 0 : 1;
             sDir[lane] = face_bnd[F] == 1;
         }
+        __syncthreads();
+        // the right-hand side alone reads K_e only next to Dirichlet faces
+        const bool needK = MAT || sDir[0] || sDir[1] || sDir[2] || sDir[3];
         // the whole TT x TT region in one batch of loads (the entries below the stored tiles are
         // read and never used), so that every load of the element is in flight at once
         const T* K = Ke + (size_t)e * TT * TT;
         T kv[NL];
+        if (needK) {
 #pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            const int idx = lane + 64 * u;
-            kv[u] = idx < TT * TT ? K[idx] : T(0);
-        }
+            for (int u = 0; u < NL; ++u) {
+                const int idx = lane + 64 * u;
+                kv[u] = idx < TT * TT ? K[idx] : T(0);
+            }
 #pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            const int idx = lane + 64 * u;
-            if (idx < TT * TT) {
-                const int r = idx / TT, c = idx - r * TT;
-                Ks[r * LD + c] = (double)kv[u];
+            for (int u = 0; u < NL; ++u) {
+                const int idx = lane + 64 * u;
+                if (idx < TT * TT) {
+                    const int r = idx / TT, c = idx - r * TT;
+                    Ks[r * LD + c] = (double)kv[u];
+                }
             }
         }
         __syncthreads();
         // matrix: block (i, q) of K_e goes to row F_i, the slot of face q (q == i: the diagonal)
-        for (int idx = lane; idx < NV * NV * BB; idx += 64) {
+        for (int idx = lane; MAT && idx < NV * NV * BB; idx += 64) {
             const int iq = idx / BB, rem = idx - iq * BB;
             const int i = iq / NV, q = iq - i * NV;
             if (sDir[i]) continue;
@@ -724,19 +732,20 @@ int resident_groups(const void* kernel, int block) {
 template <bool MAT>
 static int launch_asm(hdg_ctx* c, const double* lam_bnd) {
     if (MAT) ++c->mat_version;
-    if (MAT && c->dim == 3 && !c->d_face_nf && c->nrhs == 1 && c->n_tr == 4 * c->bs) {
+    if (c->dim == 3 && !c->d_face_nf && c->nrhs == 1 && c->n_tr == 4 * c->bs) {
         const int eg = (int)std::min<int64_t>(c->n_elem, 262144);
 #define HDG_ASM_ELEM(B)                                                                                         \
         if (c->bs == B) {                                                                                      \
-            hipLaunchKernelGGL((assemble_init_kernel<B>), dim3(nblk(c->n_faces * B * B)), dim3(NT), 0, c->stream,  \
-                               c->n_faces, c->K_sign, c->d_face_elem, c->d_face_bnd, lam_bnd, c->d_bsr, c->d_rhs); \
+            hipLaunchKernelGGL((assemble_init_kernel<B, MAT>), dim3(nblk(c->n_faces * (MAT ? B * B : B))), dim3(NT), \
+                               0, c->stream, c->n_faces, c->K_sign, c->d_face_elem, c->d_face_bnd, lam_bnd,     \
+                               c->d_bsr, c->d_rhs);                                                            \
             if (c->precision == HDG_FP64)                                                                      \
-                hipLaunchKernelGGL((assemble_elem_kernel<double, B>), dim3(eg), dim3(64), 0, c->stream, c->n_elem, \
-                                   c->ke_tile, c->K_sign, c->d_face_elem, c->d_face_bnd, c->d_eface,            \
+                hipLaunchKernelGGL((assemble_elem_kernel<double, B, MAT>), dim3(eg), dim3(64), 0, c->stream,   \
+                                   c->n_elem, c->ke_tile, c->K_sign, c->d_face_elem, c->d_face_bnd, c->d_eface, \
                                    (const double*)c->d_Ke, (const double*)c->d_re, lam_bnd, c->d_bsr, c->d_rhs); \
             else                                                                                               \
-                hipLaunchKernelGGL((assemble_elem_kernel<float, B>), dim3(eg), dim3(64), 0, c->stream, c->n_elem, \
-                                   c->ke_tile, c->K_sign, c->d_face_elem, c->d_face_bnd, c->d_eface,            \
+                hipLaunchKernelGGL((assemble_elem_kernel<float, B, MAT>), dim3(eg), dim3(64), 0, c->stream,    \
+                                   c->n_elem, c->ke_tile, c->K_sign, c->d_face_elem, c->d_face_bnd, c->d_eface, \
                                    (const float*)c->d_Ke, (const float*)c->d_re, lam_bnd, c->d_bsr, c->d_rhs);  \
             return (int)hipGetLastError();                                                                     \
         }
