@@ -392,18 +392,19 @@ def run_step_graph(p, steps, warmup):
     """Secondary figure: whole DIRK(3,3) steps (hdg_step, FP64, factors kept across the stages)
     run eagerly, with a host synchronisation per CG iteration, against the same steps replayed
     as one hipGraph with the CG convergence test on the device (options.graph_step), both with
-    the block-Jacobi trace CG; the final states agree to the last bits.  Also the eager steps
-    with the block-SSOR trace CG (eager_ssor)."""
+    the block-Jacobi trace CG (the final states agree to the last bits), and the same pair with
+    the block-SSOR trace CG (eager_ssor, graph_ssor: equal to the CG tolerance, the captured CG
+    stops on its estimate and checks the true residual at the end)."""
     import torch
 
     from paper_1807_00086_amd import Solver
     k = int(p.degree[0])
     out = {}
     finals = {}
-    for mode in ("eager", "graph", "eager_ssor"):
+    for mode in ("eager", "graph", "eager_ssor", "graph_ssor"):
         s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=k, precision="fp64", krylov_tol=1e-13,
-                   cache_factors=True, graph_step=(mode == "graph"),
-                   precond="ssor" if mode == "eager_ssor" else "jacobi")
+                   cache_factors=True, graph_step=mode.startswith("graph"),
+                   precond="ssor" if mode.endswith("ssor") else "jacobi")
         nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
         vp = s.volume_points()
         p0 = np.sin(2 * np.pi * vp[:, 0])
@@ -423,9 +424,9 @@ def run_step_graph(p, steps, warmup):
         torch.cuda.synchronize()
         out[f"{mode}_ms_step"] = 1e3 * (time.perf_counter() - t0) / steps
         out[f"{mode}_iters_last_stage"] = s.query("last_iters")
-        if mode == "graph":
-            out["graph_replays"] = replays
-            out["graph_cg_iters_per_stage"] = s.query("step_graph_iters")
+        if mode.startswith("graph"):
+            out[f"{mode}_replays"] = replays
+            out[f"{mode}_cg_iters_per_stage"] = s.query("step_graph_iters")
         finals[mode] = u.cpu().numpy()
         s.close()
         del u, lbs, lam
@@ -436,6 +437,8 @@ def run_step_graph(p, steps, warmup):
     # the CG tolerance
     out["eager_ssor_vs_eager_max_rel"] = float(np.abs(finals["eager_ssor"] - finals["eager"]).max() /
                                                np.abs(finals["eager"]).max())
+    out["graph_ssor_vs_eager_ssor_max_rel"] = float(np.abs(finals["graph_ssor"] - finals["eager_ssor"]).max() /
+                                                    np.abs(finals["eager_ssor"]).max())
     out["speedup"] = out["eager_ms_step"] / out["graph_ms_step"]
     return out
 
@@ -671,11 +674,12 @@ def main():
     print(f"trace solve: jacobi {jj['solve']:.2f} ms ({jj['iters']:.0f} it), ssor "
           f"{out['trace_solve_jacobi']['ssor_solve_ms']} ms", file=sys.stderr, flush=True)
     out["step_graph"] = {"basis": "secondary: whole DIRK(3,3) steps (hdg_step, FP64, cached factors) eager "
-                                  "against one hipGraph replay per step (block Jacobi), and eager with "
+                                  "against one hipGraph replay per step, with block Jacobi and with "
                                   "block SSOR", **run_step_graph(p, 3, 1)}
     print(f"step graph: {out['step_graph']['eager_ms_step']:.2f} ms eager, "
           f"{out['step_graph']['graph_ms_step']:.2f} ms graph, "
-          f"{out['step_graph']['eager_ssor_ms_step']:.2f} ms eager with SSOR", file=sys.stderr, flush=True)
+          f"{out['step_graph']['eager_ssor_ms_step']:.2f} ms eager with SSOR, "
+          f"{out['step_graph']['graph_ssor_ms_step']:.2f} ms graph with SSOR", file=sys.stderr, flush=True)
     if not args.no_workloads:
         # the other workloads at full size, element kernels of one stage (secondary figures)
         out["other_workloads"] = {}

@@ -170,10 +170,11 @@ typedef struct {
     void* alloc_user;
     int precond;                /* trace-solve preconditioner (enum hdg_precond).  HDG_PC_SSOR
                                    applies to one right-hand side in 3D (the block sizes of the
-                                   built configurations), in hdg_trace_solve and in the
-                                   correction solves of the mixed-precision refinement;
-                                   elsewhere, inside the step graph and in
-                                   hdg_trace_solve_static, block Jacobi is used.              */
+                                   built configurations), in hdg_trace_solve, hdg_step (also
+                                   inside the step graph, with the convergence test on the
+                                   device) and the correction solves of the mixed-precision
+                                   refinement; elsewhere and in hdg_trace_solve_static, block
+                                   Jacobi is used.                                            */
 } hdg_options;
 
 /* Preconditioners of the trace CG (section 2.4.2 uses BILU(0) inside RAS; K is symmetric

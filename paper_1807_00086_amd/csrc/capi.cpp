@@ -1062,9 +1062,13 @@ int step_launches(hdg_ctx* c, int ns, const double Dm[3][3], double dt, const do
         } else {
             e = c->fast_ac ? launch_condense_acoustic(c, a, c->d_fstage) : launch_condense_general(c, a, c->d_fstage);
             if (!e) e = launch_assemble(c, lb);
-            if (!e) e = launch_block_inverse(c);
         }
-        if (!e) e = trace_cg_device(c, lambda, c->krylov_tol, nit, c->d_cgflags + 2 * i, c->d_scal + 160 + i);
+        // the preconditioner's data (block-Jacobi inverses, or the scaled SSOR matrix) are formed
+        // by the solve after each assembly
+        if (!e)
+            e = (c->precond == HDG_PC_SSOR && ssor_supported(c))
+                    ? trace_cg_ssor_device(c, lambda, c->krylov_tol, nit, c->d_cgflags + 2 * i, c->d_scal + 160 + i)
+                    : trace_cg_device(c, lambda, c->krylov_tol, nit, c->d_cgflags + 2 * i, c->d_scal + 160 + i);
         if (!e) e = launch_recover_any(c, lambda, c->d_stage + i * nl);
     }
     return e;
@@ -1184,6 +1188,10 @@ hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, doub
         // stage took here plus a margin (iterations past convergence return at once)
         const bool reuse = c->cache_factors && c->factors_cached && c->condensed && a == c->last_a;
         const int nit = std::min(c->krylov_maxit, std::max(retry_nit, max_it + max_it / 4 + 8));
+        if (c->precond == HDG_PC_SSOR && ssor_supported(c)) {
+            const int s = trace_ssor_alloc(c);   // no allocation inside the capture
+            if (s) return fail(c, s, "allocation of the SSOR buffers failed");
+        }
         if (capture_step(c, ns, Dm, dt, u, lambda, lam_bnd, src, reuse, nit))
             return fail(c, HDG_E_HIP, "capture of the step graph failed");
         c->sg_key = key;

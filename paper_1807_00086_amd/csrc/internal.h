@@ -265,6 +265,10 @@ int trace_cg_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, doub
 int launch_zero_ints(hdg_ctx* c, int* p, int n);
 // multicolour block SSOR (Eisenstat form) CG; returns HDG_OK / HDG_E_NOCONV / a HIP error
 int trace_cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres);
+// the SSOR CG for graph capture (see trace_cg_device); its buffers come from trace_ssor_alloc,
+// which must run before the capture
+int trace_cg_ssor_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, double* relres_dev);
+int trace_ssor_alloc(hdg_ctx* c);
 bool ssor_supported(const hdg_ctx* c);
 int launch_bsr_f32(hdg_ctx* c);
 // trace solve with the CG work vectors and reduction scratch in the library's static device

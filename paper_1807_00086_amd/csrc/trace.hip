@@ -601,7 +601,9 @@ __global__ __launch_bounds__(NT) void dot_final_kernel(int nb, int R, const doub
 // out = sum of nb partial sums (one column): 1024 threads, so that a few thousand partials take
 // a few loads per thread
 __global__ __launch_bounds__(1024) void sum_partials_kernel(int nb, const double* __restrict__ part,
-                                                            double* __restrict__ out) {
+                                                            double* __restrict__ out,
+                                                            const int* __restrict__ done = nullptr) {
+    if (done && *done) return;
     __shared__ double sh[16];
     double acc = 0.0;
     for (int b = threadIdx.x; b < nb; b += 1024) acc += part[b];
@@ -1212,10 +1214,12 @@ struct SweepArgs {
     const double* den;
     double* u0;          // C0
     double* part;        // p.q partials (HAT, C0), or null
+    const int* done;     // the device-side CG's flag: every launch returns once it is set, or null
 };
 
 template <int BS, bool HAT, bool PX, bool C0>
 __global__ __launch_bounds__(NT) void ssor_sweep_kernel(int64_t p0, int64_t nfc, SweepArgs A) {
+    if (A.done && *A.done) return;
     const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
     const bool act = gid < nfc * BS;
     double pq = 0.0;
@@ -1310,7 +1314,7 @@ namespace {
 template <int BS, bool UP>
 void ssor_sweep(hdg_ctx* c, const double* v, double* y) {
     SweepArgs A{c->d_cfaces, c->d_ssoff + (UP ? c->n_faces + 1 : 0), c->d_ssnb, c->d_ssA, v, nullptr, y,
-                nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+                nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     for (int k = 0; k < c->ncolors; ++k) {
         const int col = UP ? c->ncolors - 1 - k : k;
         const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
@@ -1332,7 +1336,7 @@ void ssor_product(hdg_ctx* c, double* p, const double* r, const double* num, con
     const bool fuse = nparts <= (int64_t)RED_MAX * 32;
     int64_t po = 0;
     SweepArgs B{c->d_cfaces, c->d_ssoff + c->n_faces + 1, c->d_ssnb, c->d_ssA, p, nullptr, t, q, r, num, den,
-                u, nullptr};
+                u, nullptr, c->cg_done};
     for (int k = 0; k < nc; ++k) {
         const int col = nc - 1 - k;
         const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
@@ -1348,7 +1352,7 @@ void ssor_product(hdg_ctx* c, double* p, const double* r, const double* num, con
         }
     }
     SweepArgs H{c->d_cfaces, c->d_ssoff, c->d_ssnb, c->d_ssA, p, t, u, q, nullptr, nullptr, nullptr, nullptr,
-                nullptr};
+                nullptr, c->cg_done};
     for (int col = 1; col < nc; ++col) {
         const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
         if (nfc == 0) continue;
@@ -1358,9 +1362,29 @@ void ssor_product(hdg_ctx* c, double* p, const double* r, const double* num, con
                            c->stream, p0, nfc, H);
     }
     if (fuse)
-        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, c->stream, (int)po, c->d_red, s_pq);
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, c->stream, (int)po, c->d_red, s_pq,
+                           (const int*)c->cg_done);
     else
         dot(c, p, q, s_pq);
+}
+
+// R_F^{-1} and the scaled off-diagonal blocks, when the trace matrix has been assembled since they
+// were formed
+template <int BS>
+hipError_t ssor_prepare(hdg_ctx* c) {
+    if (c->ss_version == c->mat_version) return hipSuccess;
+    if constexpr (BS <= 21) {
+        constexpr int64_t FPB = (64 / BS) * (NT / 64);   // faces per workgroup of the factor kernel
+        hipLaunchKernelGGL((chol_rinv_kernel<BS>), dim3((unsigned)((c->n_faces + FPB - 1) / FPB)), dim3(NT), 0,
+                           c->stream, c->n_faces, c->d_bsr, c->d_rinv);
+    } else {
+        hipLaunchKernelGGL((chol_rinv_lds_kernel<BS>), dim3((unsigned)std::min<int64_t>(c->n_faces, 65536)),
+                           dim3(64), 0, c->stream, c->n_faces, c->d_bsr, c->d_rinv);
+    }
+    hipLaunchKernelGGL((ssor_scale_kernel<BS>), dim3((unsigned)((c->n_faces + 64 / BS - 1) / (64 / BS))), dim3(64),
+                       0, c->stream, c->n_faces, c->d_bsr_cols, c->d_ssdst, c->d_bsr, c->d_rinv, c->d_ssA);
+    c->ss_version = c->mat_version;
+    return hipGetLastError();
 }
 
 // CG on the transformed system  Ahat y = Lh^{-1} W r0,  Ahat = Lh^{-1} Kt Uh^{-1}  (Lh = I + Lt,
@@ -1385,21 +1409,7 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
     double* s_pq = c->d_scal + 64;
     double* s_bb = c->d_scal + 128;
     double* s_rr = c->d_scal + 96;
-    if (c->ss_version != c->mat_version) {   // the scaled copy belongs to an earlier assembly
-        if constexpr (BS <= 21) {
-            constexpr int64_t FPB = (64 / BS) * (NT / 64);   // faces per workgroup of the factor kernel
-            hipLaunchKernelGGL((chol_rinv_kernel<BS>), dim3((unsigned)((c->n_faces + FPB - 1) / FPB)), dim3(NT),
-                               0, c->stream, c->n_faces, c->d_bsr, c->d_rinv);
-        } else {
-            hipLaunchKernelGGL((chol_rinv_lds_kernel<BS>), dim3((unsigned)std::min<int64_t>(c->n_faces, 65536)),
-                               dim3(64), 0, c->stream, c->n_faces, c->d_bsr, c->d_rinv);
-        }
-        hipLaunchKernelGGL((ssor_scale_kernel<BS>), dim3((unsigned)((c->n_faces + 64 / BS - 1) / (64 / BS))),
-                           dim3(64), 0, c->stream, c->n_faces, c->d_bsr_cols, c->d_ssdst, c->d_bsr, c->d_rinv,
-                           c->d_ssA);
-        HIPCHK_INT(hipGetLastError());
-        c->ss_version = c->mat_version;
-    }
+    HIPCHK_INT(ssor_prepare<BS>(c));
     auto wapply = [&](const double* in, double* out) {   // out = W in
         hipLaunchKernelGGL((block_apply_fixed_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, 1,
                            c->d_rinv, in, out, (const int*)nullptr);
@@ -1481,7 +1491,99 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
 }
 }  // namespace
 
-int trace_cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
+namespace {
+__global__ __launch_bounds__(NT) void fill_zero_kernel(int64_t n, double* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// device-side test of the SSOR CG's estimate: done = 1 once sqrt(r.r / bm) <= thresh, 2 when
+// it is not finite
+__global__ void ssor_check_kernel(const double* __restrict__ s_rz, const double* __restrict__ s_bm, double thresh,
+                                  int* __restrict__ flags) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || flags[0]) return;
+    const double bm = *s_bm > 0.0 ? *s_bm : 1.0;
+    const double est = sqrt(fabs(*s_rz) / bm);
+    if (!(est - est == 0.0)) flags[0] = 2;
+    else if (est <= thresh) flags[0] = 1;
+}
+
+// after the iterations: relres = |b - K x| / |b| decides (done = 1 only when it meets tol)
+__global__ void ssor_final_kernel(const double* __restrict__ s_rr, const double* __restrict__ s_bb, double tol,
+                                  int* __restrict__ flags, double* __restrict__ relres) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double b = sqrt(*s_bb);
+    const double v = sqrt(*s_rr) / (b > 0.0 ? b : 1.0);
+    *relres = v;
+    flags[0] = !(v - v == 0.0) ? 2 : (v <= tol ? 1 : 0);
+}
+
+// The SSOR CG of cg_ssor with a fixed number of iterations and the test on the device, for
+// capture into a graph (no host synchronisation, no memset): the estimate stops the iterations
+// at a tenth of the tolerance (the host version confirms at the tolerance and tightens on a
+// failed check), then x = x0 + W^T Uh^{-1} y and its true relative residual, which alone sets
+// flags[0] (1 converged, 0 not, 2 non-finite); flags[1] counts the iterations.
+template <int BS>
+int cg_ssor_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, double* relres_dev) {
+    const int64_t n = c->n_faces * BS;
+    double* rr = c->d_cg_r;
+    double* zz = c->d_cg_z;
+    double* pp = c->d_cg_p;
+    double* qq = c->d_cg_q;
+    double* tt = c->d_ss;
+    double* uu = c->d_ss + n;
+    double* yy = c->d_ss + 2 * n;
+    double* s_rz = c->d_scal;
+    double* s_rz_new = c->d_scal + 32;
+    double* s_pq = c->d_scal + 64;
+    double* s_rr = c->d_scal + 96;
+    double* s_bb = c->d_scal + 128;
+    double* s_bm = c->d_scal + 192;
+    if (ssor_prepare<BS>(c) != hipSuccess) return HDG_E_HIP;
+    auto wapply = [&](const double* in, double* out) {   // out = W in
+        hipLaunchKernelGGL((block_apply_fixed_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, 1,
+                           c->d_rinv, in, out, (const int*)nullptr);
+    };
+    launch_zero_ints(c, flags, 2);
+    hipLaunchKernelGGL(copy_bnd_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, BS, 1, c->d_face_bnd,
+                       c->d_rhs, x);
+    spmv(c, x, qq);
+    launch_lincomb(c, n, 1.0, c->d_rhs, -1.0, qq, uu);             // r0 = b - K x0
+    wapply(uu, tt);
+    ssor_sweep<BS, false>(c, tt, rr);                              // rhat = Lh^{-1} W r0
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, n, yy);
+    launch_lincomb(c, n, 1.0, rr, 0.0, nullptr, pp);
+    dot(c, rr, rr, s_rz);
+    dot(c, c->d_rhs, c->d_rhs, s_bb);
+    wapply(c->d_rhs, tt);
+    ssor_sweep<BS, false>(c, tt, uu);
+    dot(c, uu, uu, s_bm);                                          // the scale of r.r
+    const double thresh = 0.1 * tol;
+    hipLaunchKernelGGL(ssor_check_kernel, dim3(1), dim3(64), 0, c->stream, s_rz, s_bm, thresh, flags);
+    c->cg_done = flags;   // from here on every launch of the loop returns once the estimate is met
+    for (int it = 0; it < nit; ++it) {
+        ssor_product<BS>(c, pp, rr, it > 0 ? s_rz : nullptr, s_rz_new, tt, uu, qq, s_pq);
+        hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, 1, s_rz, s_pq, pp, qq,
+                           yy, rr, c->d_red, (const int*)flags, flags + 1);
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, c->stream, c->red_blocks, c->d_red,
+                           s_rz_new, (const int*)flags);
+        hipLaunchKernelGGL(ssor_check_kernel, dim3(1), dim3(64), 0, c->stream, s_rz_new, s_bm, thresh, flags);
+        std::swap(s_rz, s_rz_new);
+    }
+    c->cg_done = nullptr;
+    ssor_sweep<BS, true>(c, yy, tt);
+    hipLaunchKernelGGL((rinvt_axpy_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->d_rinv, x, tt,
+                       zz);
+    spmv(c, zz, qq);
+    launch_lincomb(c, n, 1.0, c->d_rhs, -1.0, qq, uu);
+    dot(c, uu, uu, s_rr);
+    launch_lincomb(c, n, 1.0, zz, 0.0, nullptr, x);                // x = x0 + W^T Uh^{-1} y
+    hipLaunchKernelGGL(ssor_final_kernel, dim3(1), dim3(64), 0, c->stream, s_rr, s_bb, tol, flags, relres_dev);
+    return (int)hipGetLastError();
+}
+}  // namespace
+
+int trace_ssor_alloc(hdg_ctx* c) {
     const size_t nt = (size_t)c->n_faces * c->bs;
     void** bufs[3] = {(void**)&c->d_ss, (void**)&c->d_rinv, (void**)&c->d_ssA};
     const size_t sizes[3] = {3 * nt, nt * c->bs, (size_t)std::max<int64_t>(c->ss_nblk, 1) * c->bs * c->bs};
@@ -1491,8 +1593,23 @@ int trace_cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres)
         if (e) return e;
         c->ss_version = -1;
     }
+    return HDG_OK;
+}
+
+int trace_cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
+    const int e = trace_ssor_alloc(c);
+    if (e) return e;
 #define HDG_BS(B) \
     if (c->bs == B) return cg_ssor<B>(c, x, tol, iters, relres);
+    HDG_BS_CASES(HDG_BS)
+#undef HDG_BS
+    return HDG_E_UNSUPPORTED;
+}
+
+int trace_cg_ssor_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, double* relres_dev) {
+    if (!c->d_ss || !c->d_rinv || !c->d_ssA) return HDG_E_STATE;   // trace_ssor_alloc first (not under capture)
+#define HDG_BS(B) \
+    if (c->bs == B) return cg_ssor_device<B>(c, x, tol, nit, flags, relres_dev);
     HDG_BS_CASES(HDG_BS)
 #undef HDG_BS
     return HDG_E_UNSUPPORTED;
