@@ -186,6 +186,18 @@ def measured_mfma_busy(kernel):
     return None if rec is None else rec["busy"]
 
 
+def ssor_iteration_bytes(n_elem, n_faces, bs):
+    """Algorithmic HBM bytes of one iteration of the block-SSOR trace CG on a tetrahedral mesh:
+    every off-diagonal block of the scaled matrix once (one per ordered pair of distinct faces of
+    an element: 12 per element, bs x bs FP64), the gathers of the neighbours' bs-vectors (one per
+    block), and 14 passes over a trace vector (backward sweeps: p and r read, p and t written;
+    their colour-0 launch: u and q written; forward sweeps: p and t read, u and q written; CG
+    update: y, p, r, q read, y and r written)."""
+    nblk = 12 * n_elem
+    nt = n_faces * bs
+    return nblk * bs * bs * 8 + nblk * bs * 8 + 14 * nt * 8
+
+
 def cpu_baseline(problem, a, budget_s=15.0):
     """The oracle's per-element condense + recover (quadrature forming, dense solve, Schur
     complement, recovery) on a seeded sample of elements, single BLAS thread."""
@@ -322,7 +334,7 @@ def run_precision(p, prec, steps, warmup, keep_solution=False, precond=STAGE_PRE
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     out = dict(ms_step=1e3 * wall / steps, iters=float(np.mean(iters)), refine=float(np.mean(refs)),
-               elem_ms_median=float(np.median(elem_ms)), elem_ms_min=float(np.min(elem_ms)),
+               elem_ms_median=float(np.median(elem_ms)), elem_ms_min=float(np.min(elem_ms)), n_trace_dofs=nt,
                **{k2: v / steps for k2, v in tm.items()})
     if res:
         out["refine_residual_max"] = max(res)
@@ -664,6 +676,19 @@ def main():
                  "(right-hand-side condensation + recover [+ refinement element passes]); "
                  "one factorisation per dt, not per stage",
         **{pr: run_cached(p, pr, args.steps, args.warmup) for pr in precs}}
+    if "fp64" in res:
+        # whole FP64 solves (setup, the scaled matrix, the final true residual included) against
+        # the iterations' algorithmic bytes: a lower bound of the sweeps' own rate
+        r64 = res["fp64"]
+        bs = (k + 1) * (k + 2) // 2
+        it_bytes = ssor_iteration_bytes(p.n_elem, r64["n_trace_dofs"] // bs, bs)
+        gbs = it_bytes * r64["iters"] / (r64["solve"] * 1e-3) / 1e9
+        out["trace_solve_roofline"] = {
+            "basis": "secondary: FP64 block-SSOR trace solve of the timed stage, algorithmic bytes of its "
+                     "iterations over the whole solve time (setup, scaling and final residual included)",
+            "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "bytes_per_iteration": it_bytes, "iters": r64["iters"], "solve_ms": r64["solve"],
+            "kernel": "ssor_sweep_kernel<10, ...>, cg_update_kernel"}
     jj = run_precision(p, "fp64", args.steps, args.warmup, precond="jacobi")
     out["trace_solve_jacobi"] = {
         "basis": "secondary: the FP64 stage with block Jacobi in the trace CG instead of the multicolour "
