@@ -21,10 +21,11 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _condensed(p, prec, seed):
+def _condensed(p, prec, seed, precond="jacobi"):
     from paper_1807_00086_amd import Solver
     kw = dict(krylov_tol=1e-13) if prec == "fp64" else dict(krylov_tol=1e-9, refine_tol=1e-12)
-    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=int(p.degree[0]), precision=prec, **kw)
+    s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=int(p.degree[0]), precision=prec, precond=precond,
+               **kw)
     nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
     fd = torch.as_tensor(random_vector(nl, p.cfg_id, seed), device="cuda")
     lbd = torch.as_tensor(random_vector(nt, p.cfg_id, seed + 1), device="cuda")
@@ -47,6 +48,28 @@ def test_trace_solve_static_equals_trace_solve_two_calls(prec):
         assert it == it_ref and rr == rr_ref, (it, it_ref, rr, rr_ref)
         assert torch.equal(lam, lam_ref)
         s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fp32"])
+def test_trace_solve_static_in_an_ssor_context(prec):
+    """A context configured for block SSOR skips the block-Jacobi inverses (and the FP32 copy of
+    K) at condensation; the static solve, which runs block Jacobi, forms them itself and equals a
+    block-Jacobi context's hdg_trace_solve on the same system to the last bit."""
+    _need_gpu()
+    p = make_problem(2, n=3, k=3)
+    print(f"case no-alloc in an ssor context {prec} n_elem={p.n_elem}", flush=True)
+    sj, _, lbd = _condensed(p, prec, 70)
+    lam_ref = torch.zeros_like(lbd)
+    it_ref, rr_ref = sj.trace_solve(lam_ref)
+    ss, _, _ = _condensed(p, prec, 70, precond="ssor")
+    assert ss.query("n_colors") > 0
+    lam = torch.zeros_like(lbd)
+    it, rr = ss.trace_solve_static(lam)
+    torch.cuda.synchronize()
+    assert it == it_ref and rr == rr_ref, (it, it_ref, rr, rr_ref)
+    assert torch.equal(lam, lam_ref)
+    sj.close()
+    ss.close()
 
 
 def test_trace_solve_static_rejects_a_system_beyond_its_scratch():
