@@ -169,12 +169,13 @@ typedef struct {
     void (*dev_free)(void* alloc_user, void* ptr);
     void* alloc_user;
     int precond;                /* trace-solve preconditioner (enum hdg_precond).  HDG_PC_SSOR
-                                   applies to one right-hand side in 3D (the block sizes of the
-                                   built configurations), in hdg_trace_solve, hdg_step (also
-                                   inside the step graph, with the convergence test on the
-                                   device) and the correction solves of the mixed-precision
-                                   refinement; elsewhere and in hdg_trace_solve_static, block
-                                   Jacobi is used.                                            */
+                                   applies in 3D to the block sizes of the built
+                                   configurations with one or 32 right-hand sides, in
+                                   hdg_trace_solve, hdg_step and the correction solves of the
+                                   mixed-precision refinement; inside the step graph (with the
+                                   convergence test on the device) with one right-hand side;
+                                   elsewhere and in hdg_trace_solve_static, block Jacobi is
+                                   used.                                                      */
 } hdg_options;
 
 /* Preconditioners of the trace CG (section 2.4.2 uses BILU(0) inside RAS; K is symmetric

@@ -1066,7 +1066,7 @@ int step_launches(hdg_ctx* c, int ns, const double Dm[3][3], double dt, const do
         // the preconditioner's data (block-Jacobi inverses, or the scaled SSOR matrix) are formed
         // by the solve after each assembly
         if (!e)
-            e = (c->precond == HDG_PC_SSOR && ssor_supported(c))
+            e = (c->precond == HDG_PC_SSOR && ssor_supported(c) && c->nrhs == 1)
                     ? trace_cg_ssor_device(c, lambda, c->krylov_tol, nit, c->d_cgflags + 2 * i, c->d_scal + 160 + i)
                     : trace_cg_device(c, lambda, c->krylov_tol, nit, c->d_cgflags + 2 * i, c->d_scal + 160 + i);
         if (!e) e = launch_recover_any(c, lambda, c->d_stage + i * nl);
@@ -1188,7 +1188,7 @@ hdg_status hdg_step(hdg_ctx* c, double t, double dt, int scheme, double* u, doub
         // stage took here plus a margin (iterations past convergence return at once)
         const bool reuse = c->cache_factors && c->factors_cached && c->condensed && a == c->last_a;
         const int nit = std::min(c->krylov_maxit, std::max(retry_nit, max_it + max_it / 4 + 8));
-        if (c->precond == HDG_PC_SSOR && ssor_supported(c)) {
+        if (c->precond == HDG_PC_SSOR && ssor_supported(c) && c->nrhs == 1) {
             const int s = trace_ssor_alloc(c);   // no allocation inside the capture
             if (s) return fail(c, s, "allocation of the SSOR buffers failed");
         }

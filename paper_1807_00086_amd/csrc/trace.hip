@@ -1277,6 +1277,106 @@ __global__ __launch_bounds__(NT) void ssor_sweep_kernel(int64_t p0, int64_t nfc,
     }
 }
 
+// The sweep of one colour with 32 right-hand sides: one face per wavefront, the sum over the
+// face's sweep blocks as 16x16x4 FP64 MFMA tiles (A: the block Kt_{F,G}, B: the neighbour's bs x 32
+// vector block), as in the block products of the 32-column CG, then the same row updates and
+// fusions as the one-column sweep, per column (PX: p = r + beta_col p).  No p.q partial sums (a
+// separate dot forms them).
+template <int BS, bool HAT, bool PX, bool C0>
+__global__ __launch_bounds__(256) void ssor_sweep32_kernel(int64_t p0, int64_t nfc, SweepArgs A) {
+    if (A.done && *A.done) return;
+    constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4, R = 32;
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int64_t q = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (q >= nfc) return;   // whole wavefronts
+    const int64_t P = p0 + q;
+    const int64_t F = __builtin_amdgcn_readfirstlane(A.cfaces[P]);
+    const int32_t k0 = __builtin_amdgcn_readfirstlane(A.off[P]), k1 = __builtin_amdgcn_readfirstlane(A.off[P + 1]);
+    mf64x4 acc[MT][2];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = mf64x4{0.0, 0.0, 0.0, 0.0};
+    for (int32_t kb = k0; kb < k1; ++kb) {
+        const int32_t G = __builtin_amdgcn_readfirstlane(A.nbr[kb]);
+        const double* B = A.sa + (size_t)kb * BS * BS;
+        const double* yv = A.y + (size_t)G * BS * R;
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            const int b = min(4 * kk + lg, BS - 1);
+            const bool bok = 4 * kk + lg < BS;
+            double xb[2];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const double t = yv[b * R + 16 * nt + lr];
+                xb[nt] = bok ? t : 0.0;
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const double av = B[b * BS + min(16 * mt + lr, BS - 1)];
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xb[nt], acc[mt][nt], 0, 0, 0);
+            }
+        }
+    }
+    double be[2] = {0.0, 0.0};
+    if constexpr (PX) {
+        if (A.num)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                const double dd = A.den[16 * nt + lr];
+                be[nt] = dd != 0.0 ? A.num[16 * nt + lr] / dd : 0.0;
+            }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = 16 * mt + lg + 4 * v;   // accumulator row of element v of this lane
+                if (a >= BS) continue;
+                const size_t o = ((size_t)F * BS + a) * R + 16 * nt + lr;
+                double sv = A.v[o];
+                if constexpr (PX) {
+                    if (A.num) {
+                        sv = A.r[o] + be[nt] * sv;
+                        const_cast<double*>(A.v)[o] = sv;
+                    }
+                }
+                const double pk = sv;
+                double tk = 0.0;
+                if constexpr (HAT) {
+                    tk = A.t[o];
+                    sv -= tk;
+                }
+                sv -= acc[mt][nt][v];
+                A.y[o] = sv;
+                if constexpr (HAT) A.q[o] = tk + sv;
+                if constexpr (C0) {
+                    A.u0[o] = pk - sv;
+                    A.q[o] = pk;
+                }
+            }
+}
+
+// out = x + W^T t with R right-hand sides (thread per entry (F, a, r))
+template <int BS>
+__global__ __launch_bounds__(NT) void rinvt_axpy_cols_kernel(int64_t nf, int R, const double* __restrict__ rinv,
+                                                             const double* __restrict__ x,
+                                                             const double* __restrict__ t, double* __restrict__ out) {
+    const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (gid >= nf * BS * R) return;
+    const int r = (int)(gid % R);
+    const int64_t Fa = gid / R, F = Fa / BS;
+    const int a = (int)(Fa % BS);
+    const double* Rc = rinv + (size_t)F * BS * BS + (size_t)a * BS;
+    const double* tv = t + (size_t)F * BS * R + r;
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < BS; ++b) acc += Rc[b] * tv[(size_t)b * R];
+    out[gid] = x[gid] + acc;
+}
+
 // out = x + W^T t  (W^T = diag(R_F^{-T}): row a of R_F^{-T} is column a of R_F^{-1})
 template <int BS>
 __global__ __launch_bounds__(NT) void rinvt_axpy_kernel(int64_t nf, const double* __restrict__ rinv,
@@ -1296,7 +1396,8 @@ __global__ __launch_bounds__(NT) void rinvt_axpy_kernel(int64_t nf, const double
 }  // namespace
 
 bool ssor_supported(const hdg_ctx* c) {
-    if (c->nrhs != 1 || c->nslot != 7 || c->ncolors == 0 || !c->d_cfaces || !c->d_ssoff) return false;
+    if ((c->nrhs != 1 && c->nrhs != 32) || c->nslot != 7 || c->ncolors == 0 || !c->d_cfaces || !c->d_ssoff)
+        return false;
 #define HDG_BS(B) \
     if (c->bs == B) return true;
     HDG_BS_CASES(HDG_BS)
@@ -1310,8 +1411,15 @@ namespace {
         if ((call) != hipSuccess) return HDG_E_HIP; \
     } while (0)
 
+// launch of one colour's sweep with 32 right-hand sides (one face per wavefront, four per workgroup)
+template <int BS, bool HAT, bool PX, bool C0>
+void sweep32_launch(hdg_ctx* c, int64_t p0, int64_t nfc, const SweepArgs& A) {
+    hipLaunchKernelGGL((ssor_sweep32_kernel<BS, HAT, PX, C0>), dim3((unsigned)((nfc + 3) / 4)), dim3(256), 0,
+                       c->stream, p0, nfc, A);
+}
+
 // one sweep over all colours (forward: colour 0 first; backward: the last colour first)
-template <int BS, bool UP>
+template <int BS, bool UP, int R = 1>
 void ssor_sweep(hdg_ctx* c, const double* v, double* y) {
     SweepArgs A{c->d_cfaces, c->d_ssoff + (UP ? c->n_faces + 1 : 0), c->d_ssnb, c->d_ssA, v, nullptr, y,
                 nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -1319,9 +1427,36 @@ void ssor_sweep(hdg_ctx* c, const double* v, double* y) {
         const int col = UP ? c->ncolors - 1 - k : k;
         const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
         if (nfc == 0) continue;
-        hipLaunchKernelGGL((ssor_sweep_kernel<BS, false, false, false>), dim3(nblk(nfc * BS)), dim3(NT), 0,
-                           c->stream, p0, nfc, A);
+        if constexpr (R == 1)
+            hipLaunchKernelGGL((ssor_sweep_kernel<BS, false, false, false>), dim3(nblk(nfc * BS)), dim3(NT), 0,
+                               c->stream, p0, nfc, A);
+        else
+            sweep32_launch<BS, false, false, false>(c, p0, nfc, A);
     }
+}
+
+// the product of ssor_product with 32 right-hand sides; p.q per column by a separate dot
+template <int BS>
+void ssor_product32(hdg_ctx* c, double* p, const double* r, const double* num, const double* den, double* t,
+                    double* u, double* q, double* s_pq) {
+    const int nc = c->ncolors;
+    SweepArgs B{c->d_cfaces, c->d_ssoff + c->n_faces + 1, c->d_ssnb, c->d_ssA, p, nullptr, t, q, r, num, den,
+                u, nullptr, c->cg_done};
+    for (int k = 0; k < nc; ++k) {
+        const int col = nc - 1 - k;
+        const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
+        if (nfc == 0) continue;
+        if (col == 0) sweep32_launch<BS, false, true, true>(c, p0, nfc, B);
+        else sweep32_launch<BS, false, true, false>(c, p0, nfc, B);
+    }
+    SweepArgs H{c->d_cfaces, c->d_ssoff, c->d_ssnb, c->d_ssA, p, t, u, q, nullptr, nullptr, nullptr, nullptr,
+                nullptr, c->cg_done};
+    for (int col = 1; col < nc; ++col) {
+        const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
+        if (nfc == 0) continue;
+        sweep32_launch<BS, true, false, false>(c, p0, nfc, H);
+    }
+    dot(c, p, q, s_pq);
 }
 
 // q = Ahat p = t + Lh^{-1} (p - t), t = Uh^{-1} p, and s_pq = p.q; with num/den first
@@ -1394,93 +1529,118 @@ hipError_t ssor_prepare(hdg_ctx* c) {
 // r.r of the transformed residual (the residual of K in the M^{-1} norm) drives the iteration;
 // when its relative value drops below the tolerance, the true relative residual |b - K x| / |b|
 // is formed and decides (a failed check tightens the estimate's threshold tenfold).
-template <int BS>
+template <int BS, int R>
 int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
-    const int64_t n = c->n_faces * BS;
+    static_assert(R == 1 || R == 32, "one or 32 right-hand sides");
+    const int64_t n = c->n_faces * BS, nR = n * R;
     double* rr = c->d_cg_r;
     double* zz = c->d_cg_z;
     double* pp = c->d_cg_p;
     double* qq = c->d_cg_q;
     double* tt = c->d_ss;
-    double* uu = c->d_ss + n;
-    double* yy = c->d_ss + 2 * n;
-    double* s_rz = c->d_scal;
+    double* uu = c->d_ss + nR;
+    double* yy = c->d_ss + 2 * nR;
+    double* s_rz = c->d_scal;            // [R] each
     double* s_rz_new = c->d_scal + 32;
     double* s_pq = c->d_scal + 64;
     double* s_bb = c->d_scal + 128;
     double* s_rr = c->d_scal + 96;
     HIPCHK_INT(ssor_prepare<BS>(c));
     auto wapply = [&](const double* in, double* out) {   // out = W in
-        hipLaunchKernelGGL((block_apply_fixed_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, 1,
+        hipLaunchKernelGGL((block_apply_fixed_kernel<BS>), dim3(nblk(nR)), dim3(NT), 0, c->stream, c->n_faces, R,
                            c->d_rinv, in, out, (const int*)nullptr);
     };
     auto true_residual = [&](double* hres) -> int {   // x_try = x0 + W^T Uh^{-1} y into zz; |b - K x_try|^2
-        ssor_sweep<BS, true>(c, yy, tt);
-        hipLaunchKernelGGL((rinvt_axpy_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->d_rinv,
-                           x, tt, zz);
+        ssor_sweep<BS, true, R>(c, yy, tt);
+        if constexpr (R == 1)
+            hipLaunchKernelGGL((rinvt_axpy_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->d_rinv,
+                               x, tt, zz);
+        else
+            hipLaunchKernelGGL((rinvt_axpy_cols_kernel<BS>), dim3(nblk(nR)), dim3(NT), 0, c->stream, c->n_faces, R,
+                               c->d_rinv, x, tt, zz);
         spmv(c, zz, qq);
-        launch_lincomb(c, n, 1.0, c->d_rhs, -1.0, qq, uu);
+        launch_lincomb(c, nR, 1.0, c->d_rhs, -1.0, qq, uu);
         dot(c, uu, uu, s_rr);
-        HIPCHK_INT(hipMemcpyAsync(hres, s_rr, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK_INT(hipMemcpyAsync(hres, s_rr, R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK_INT(hipStreamSynchronize(c->stream));
         return 0;
     };
     // initial guess: Dirichlet entries are the boundary values (identity rows)
-    hipLaunchKernelGGL(copy_bnd_kernel, dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, BS, 1, c->d_face_bnd,
+    hipLaunchKernelGGL(copy_bnd_kernel, dim3(nblk(nR)), dim3(NT), 0, c->stream, c->n_faces, BS, R, c->d_face_bnd,
                        c->d_rhs, x);
     spmv(c, x, qq);
-    launch_lincomb(c, n, 1.0, c->d_rhs, -1.0, qq, uu);             // r0 = b - K x0
+    launch_lincomb(c, nR, 1.0, c->d_rhs, -1.0, qq, uu);            // r0 = b - K x0
     wapply(uu, tt);
-    ssor_sweep<BS, false>(c, tt, rr);                              // rhat = Lh^{-1} W r0
-    hipMemsetAsync(yy, 0, n * sizeof(double), c->stream);
-    launch_lincomb(c, n, 1.0, rr, 0.0, nullptr, pp);
+    ssor_sweep<BS, false, R>(c, tt, rr);                           // rhat = Lh^{-1} W r0
+    hipMemsetAsync(yy, 0, nR * sizeof(double), c->stream);
+    launch_lincomb(c, nR, 1.0, rr, 0.0, nullptr, pp);
     dot(c, rr, rr, s_rz);
     dot(c, c->d_rhs, c->d_rhs, s_bb);
-    // the scale of r.r: |Lh^{-1} W b|^2
+    // the scale of r.r per column: |Lh^{-1} W b|^2
     wapply(c->d_rhs, tt);
-    ssor_sweep<BS, false>(c, tt, uu);
+    ssor_sweep<BS, false, R>(c, tt, uu);
     dot(c, uu, uu, s_pq);
-    double h[2];
-    HIPCHK_INT(hipMemcpyAsync(&h[0], s_bb, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK_INT(hipMemcpyAsync(&h[1], s_pq, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    double hb[R], hm[R];
+    HIPCHK_INT(hipMemcpyAsync(hb, s_bb, R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK_INT(hipMemcpyAsync(hm, s_pq, R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK_INT(hipStreamSynchronize(c->stream));
-    const double bnorm = h[0] > 0 ? std::sqrt(h[0]) : 1.0;
-    const double bm = h[1] > 0 ? h[1] : 1.0;
+    double bnorm[R], bm[R];
+    for (int r = 0; r < R; ++r) {
+        bnorm[r] = hb[r] > 0 ? std::sqrt(hb[r]) : 1.0;
+        bm[r] = hm[r] > 0 ? hm[r] : 1.0;
+    }
     double thresh = tol;
     double worst = std::numeric_limits<double>::quiet_NaN();
     int it = 0;
-    double* hrz = c->h_rr;
+    double* hrz = c->h_rr;   // pinned, 32 values
     // q = Ahat p, p.q (writes t, u, q; with beta also p = r + beta p first, beta = s_rz / s_rz_new
     // after the swap at the end of an iteration)
     auto product = [&](bool beta) {
-        ssor_product<BS>(c, pp, rr, beta ? s_rz : nullptr, s_rz_new, tt, uu, qq, s_pq);
+        if constexpr (R == 1) ssor_product<BS>(c, pp, rr, beta ? s_rz : nullptr, s_rz_new, tt, uu, qq, s_pq);
+        else ssor_product32<BS>(c, pp, rr, beta ? s_rz : nullptr, s_rz_new, tt, uu, qq, s_pq);
     };
     for (it = 0; it <= c->krylov_maxit; ++it) {
-        if (hipMemcpyAsync(hrz, s_rz, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        if (hipMemcpyAsync(hrz, s_rz, R * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipEventRecord(c->ev_rr, c->stream) != hipSuccess)
             return HDG_E_HIP;
         // queue the next product before waiting for r.r
         if (it < c->krylov_maxit) product(it > 0);
         if (hipEventSynchronize(c->ev_rr) != hipSuccess) return HDG_E_HIP;
-        const double est = std::sqrt(std::fabs(hrz[0]) / bm);
-        if (!(est - est == 0.0)) {
+        double est = 0.0;
+        bool nonfinite = false;
+        for (int r = 0; r < R; ++r) {
+            const double v = std::sqrt(std::fabs(hrz[r]) / bm[r]);
+            if (!(v - v == 0.0)) nonfinite = true;
+            else est = std::max(est, v);
+        }
+        if (nonfinite) {
             worst = std::numeric_limits<double>::quiet_NaN();
             break;
         }
         if (est <= thresh || it == c->krylov_maxit) {
-            double hres = 0.0;
-            if (true_residual(&hres)) return HDG_E_HIP;
-            worst = std::sqrt(hres) / bnorm;
+            double hres[R];
+            if (true_residual(hres)) return HDG_E_HIP;
+            worst = 0.0;
+            for (int r = 0; r < R; ++r) {
+                const double v = std::sqrt(hres[r]) / bnorm[r];
+                worst = (v - v == 0.0) ? std::max(worst, v) : std::numeric_limits<double>::quiet_NaN();
+                if (!(worst - worst == 0.0)) break;
+            }
             if (!(worst - worst == 0.0) || worst <= tol || it == c->krylov_maxit) {
-                launch_lincomb(c, n, 1.0, zz, 0.0, nullptr, x);   // x = x0 + W^T Uh^{-1} y
+                launch_lincomb(c, nR, 1.0, zz, 0.0, nullptr, x);   // x = x0 + W^T Uh^{-1} y
                 break;
             }
             thresh *= 0.1;
             product(false);   // the check overwrote t, u and q: this iteration's product again (p is new)
         }
-        hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, 1, s_rz, s_pq, pp, qq,
+        hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, pp, qq,
                            yy, rr, c->d_red, (const int*)nullptr, (int*)nullptr);
-        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, c->stream, c->red_blocks, c->d_red, s_rz_new);
+        if constexpr (R == 1)
+            hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, c->stream, c->red_blocks, c->d_red,
+                               s_rz_new);
+        else
+            hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, R, c->d_red,
+                               s_rz_new, (const int*)nullptr);
         std::swap(s_rz, s_rz_new);   // the next product forms p = r + (s_rz / s_rz_new) p
     }
     if (iters) *iters = it;
@@ -1586,7 +1746,7 @@ int cg_ssor_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, doubl
 int trace_ssor_alloc(hdg_ctx* c) {
     const size_t nt = (size_t)c->n_faces * c->bs;
     void** bufs[3] = {(void**)&c->d_ss, (void**)&c->d_rinv, (void**)&c->d_ssA};
-    const size_t sizes[3] = {3 * nt, nt * c->bs, (size_t)std::max<int64_t>(c->ss_nblk, 1) * c->bs * c->bs};
+    const size_t sizes[3] = {3 * nt * c->nrhs, nt * c->bs, (size_t)std::max<int64_t>(c->ss_nblk, 1) * c->bs * c->bs};
     for (int i = 0; i < 3; ++i) {
         if (*bufs[i]) continue;
         const int e = dev_malloc(c, bufs[i], sizes[i] * sizeof(double));
@@ -1599,14 +1759,16 @@ int trace_ssor_alloc(hdg_ctx* c) {
 int trace_cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
     const int e = trace_ssor_alloc(c);
     if (e) return e;
-#define HDG_BS(B) \
-    if (c->bs == B) return cg_ssor<B>(c, x, tol, iters, relres);
+#define HDG_BS(B)                                                                  \
+    if (c->bs == B)                                                                \
+        return c->nrhs == 32 ? cg_ssor<B, 32>(c, x, tol, iters, relres) : cg_ssor<B, 1>(c, x, tol, iters, relres);
     HDG_BS_CASES(HDG_BS)
 #undef HDG_BS
     return HDG_E_UNSUPPORTED;
 }
 
 int trace_cg_ssor_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, double* relres_dev) {
+    if (c->nrhs != 1) return HDG_E_UNSUPPORTED;
     if (!c->d_ss || !c->d_rinv || !c->d_ssA) return HDG_E_STATE;   // trace_ssor_alloc first (not under capture)
 #define HDG_BS(B) \
     if (c->bs == B) return cg_ssor_device<B>(c, x, tol, nit, flags, relres_dev);
