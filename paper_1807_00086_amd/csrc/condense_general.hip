@@ -878,13 +878,16 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int aa = a0 + MF::row(lane, v);
-                        if (aa >= TT) continue;
+                        // a diagonal tile keeps its upper triangle and mirrors it, so K_e is
+                        // symmetric to the last bit also where the two triangles' products round
+                        // differently (the split-BF16 products)
+                        if (aa >= TT || (ta == tb && aa > bb)) continue;
                         const int fca = aa / NF;
                         const T sa = (T)geo[1 + D * D + fca / MT];
                         T val = -j1 * invJ * sa * sb * (T)cf.g1[fca][fcb] * ee[v] - j2 * (w0[v] + w1[v]);
                         if (aa == bb) val += (T)cf.dface * sa;
                         Kee[aa * TT + bb] = val;
-                        if (ta != tb) Kee[bb * TT + aa] = val;
+                        if (aa != bb) Kee[bb * TT + aa] = val;
                     }
                 }
             }

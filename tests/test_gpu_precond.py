@@ -34,6 +34,7 @@ CASES = [
     (3, dict(n=1, k=4), "elastic", "fp64", False),       # 45
     (5, dict(n=2, k=3), "maxwell", "fp64", False),       # 20
     (5, dict(n=2, k=3), "maxwell_glm", "fp64", False),
+    (3, dict(n=1, k=4), "elastic", "mixed_bf16", False),   # split-BF16 products, symmetric K_e
 ]
 
 
@@ -80,6 +81,28 @@ def test_ssor_stage_parity_and_iterations(cfg, kw, phys, prec, neumann):
         assert num <= tol * den, (g, num / den)
     assert np.linalg.norm(lam - lam_ref) <= tol * np.linalg.norm(lam_ref)
     print(f"iterations jacobi {res['jacobi'][2]} ssor {it}", flush=True)
+
+
+@pytest.mark.parametrize("cfg,kw,phys,t", [(3, dict(n=1, k=4), "elastic", 180), (5, dict(n=1, k=3), "maxwell", 80)])
+def test_element_matrices_exactly_symmetric_in_every_precision(cfg, kw, phys, t):
+    """Eisenstat's form takes the scaled diagonal blocks as the identity, so the assembled K must
+    be symmetric to the last bit: K_e is, in FP64, mixed FP32 and mixed BF16 (where the two
+    triangles of a diagonal tile would round differently; the tile's upper triangle is mirrored)."""
+    _need_gpu()
+    from paper_1807_00086_amd import Solver
+    p = make_problem(cfg, **kw)
+    p.physics = phys
+    a = 1.0 / (GAMMA * p.dt)
+    for prec in ("fp64", "mixed_fp32", "mixed_bf16"):
+        s = Solver(p.xyz, p.elem_vert, phys, p.elem_par, k=kw["k"], precision=prec)
+        nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
+        s.condense(a, torch.as_tensor(random_vector(nl, cfg, 89), device="cuda"),
+                   torch.zeros(nt, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        for e in (0, p.n_elem // 2, p.n_elem - 1):
+            K = s.element_data("K", e, 1, t * t).reshape(t, t)
+            assert np.array_equal(K, K.T), (prec, e)
+        s.close()
 
 
 def test_ssor_variable_degree_single_rhs():
