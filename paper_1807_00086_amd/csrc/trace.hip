@@ -1036,6 +1036,8 @@ namespace {
 // the sweeps need no diagonal block or its inverse and the preconditioner of the transformed CG
 // (z = D r) becomes the identity.  Per CG iteration the matrix traffic is one read of the
 // off-diagonal blocks of Kt, against four more reads of the diagonal blocks without the scaling.
+// The sweeps take the scaled diagonal blocks as the identity and the upper blocks as stored, so K
+// must be symmetric to the last bit: every condensation path stores a symmetric K_e.
 
 // R_F^{-1} of each diagonal block, D_F = R_F R_F^T (Cholesky, R_F lower triangular): a group of
 // BS lanes per face, lane a holding row a of the block, then row a of R_F^{-1} (64 / BS faces per
