@@ -150,15 +150,16 @@ def test_ssor_variable_degree_single_rhs():
 
 
 SSOR32_CASES = [
-    (2, dict(n=2, k=2), "fp64"),                  # face blocks of 6
-    (2, dict(n=2, k=3), "fp64"),                  # 10
-    (2, dict(n=2, k=3), "mixed_fp32"),            # correction solves with SSOR too
-    (4, dict(nxyz=(2, 2, 1)), "fp64"),            # variable degree: padded blocks of 21
+    (2, dict(n=2, k=2), "fp64", False),           # face blocks of 6
+    (2, dict(n=2, k=3), "fp64", False),           # 10
+    (2, dict(n=2, k=3), "mixed_fp32", False),     # correction solves with SSOR too
+    (2, dict(n=2, k=3), "fp64", True),            # with Neumann faces
+    (4, dict(nxyz=(2, 2, 1)), "fp64", False),     # variable degree: padded blocks of 21
 ]
 
 
-@pytest.mark.parametrize("cfg,kw,prec", SSOR32_CASES)
-def test_ssor_32_rhs_parity_and_iterations(cfg, kw, prec):
+@pytest.mark.parametrize("cfg,kw,prec,neumann", SSOR32_CASES)
+def test_ssor_32_rhs_parity_and_iterations(cfg, kw, prec, neumann):
     """32 right-hand sides: the sweeps run the face blocks on the FP64 matrix cores (one face
     per wavefront, the 32 columns as the MFMA's N dimension) and the CG keeps per-column
     scalars; every column matches the oracle (FP64 1e-12, mixed 1e-10 relative per field) with
@@ -168,19 +169,22 @@ def test_ssor_32_rhs_parity_and_iterations(cfg, kw, prec):
     from paper_1807_00086_amd import Solver
     from test_gpu_pvar import _pad, _unpad
     p = make_problem(cfg, **kw)
+    if neumann:
+        tag_box_faces(p, [(0, 0.0), (2, 1.0)])
     R = 32
     var = p.uniform_k is None
-    print(f"case ssor 32 rhs cfg={cfg} {kw} {prec} n_elem={p.n_elem}", flush=True)
+    print(f"case ssor 32 rhs cfg={cfg} {kw} {prec} neumann={neumann} n_elem={p.n_elem}", flush=True)
     d = ohdg.make_discretisation(p)
     a = 1.0 / (GAMMA * p.dt)
+    mask = ohdg.boundary_trace_mask(d) | ohdg.neumann_trace_mask(d)
     F = random_vector(d.loc_off[-1] * R, cfg, 87).reshape(-1, R)
-    LB = random_vector(d.tr_off[-1] * R, cfg, 88).reshape(-1, R) * ohdg.boundary_trace_mask(d)[:, None]
+    LB = random_vector(d.tr_off[-1] * R, cfg, 88).reshape(-1, R) * mask[:, None]
     u_ref, lam_ref, _ = ohdg.solve_stage(d, a, F, LB)
     opts = dict(krylov_tol=1e-13) if prec == "fp64" else dict(krylov_tol=1e-9, refine_tol=1e-12)
     res = {}
     for pc in ("jacobi", "ssor"):
         s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=p.uniform_k, degree=p.degree if var else None,
-                   precision=prec, nrhs=R, precond=pc, **opts)
+                   precision=prec, nrhs=R, precond=pc, bface_tag=p.bface_tag, **opts)
         fd = torch.as_tensor(np.ascontiguousarray(F), device="cuda")
         lbd = torch.as_tensor(np.ascontiguousarray(_pad(d, LB) if var else LB), device="cuda")
         s.condense(a, fd, lbd)
