@@ -217,7 +217,7 @@ struct hdg_ctx {
     int32_t* d_ssnb = nullptr;        // [ss_nblk] neighbour face of each sweep block
     int32_t* d_ssdst = nullptr;       // [nf][nslot - 1] sweep block of block-row slot s >= 1, or -1
     int64_t ss_nblk = 0;              // sweep blocks: the forward ones (lower colours) first
-    double* d_ss = nullptr;           // [3][ntr]: t, u, y of the transformed CG
+    double* d_ss = nullptr;           // [3][ntr]: t, u, y of the transformed CG (+ [n_faces][32] p.q partials with 32 rhs)
     double* d_ssA = nullptr;          // [ss_nblk][bs][bs] R_F^{-1} K_FG R_G^{-T} in sweep order
     double* d_rinv = nullptr;         // [nf][bs][bs] R_F^{-1}, D_F = R_F R_F^T (Cholesky)
     int64_t mat_version = 0;          // counts assemblies of the trace matrix

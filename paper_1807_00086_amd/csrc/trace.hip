@@ -580,10 +580,43 @@ __global__ __launch_bounds__(NT) void dot_partial_kernel(int64_t n, int R, const
     }
 }
 
+// partial column sums of the per-face partials part[F][32] of the 32-column sweeps: out[blk][r], in
+// the thread layout of dot_partial_kernel
+__global__ __launch_bounds__(NT) void colsum32_kernel(int64_t nf, const double* __restrict__ part,
+                                                      double* __restrict__ out, const int* __restrict__ done) {
+    if (done && *done) return;
+    constexpr int R = 32, T = NT / R;
+    __shared__ double sh[NT];
+    const int t = threadIdx.x, r = t % R;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * T + t / R; i < nf; i += (int64_t)gridDim.x * T) acc += part[i * R + r];
+    sh[t] = acc;
+    __syncthreads();
+    if (t < R) {
+        double s = 0.0;
+        for (int k = 0; k < T; ++k) s += sh[k * R + t];
+        out[(size_t)blockIdx.x * R + t] = s;
+    }
+}
+
 __global__ __launch_bounds__(NT) void dot_final_kernel(int nb, int R, const double* __restrict__ part,
                                                        double* __restrict__ out, const int* __restrict__ done) {
     if (done && *done) return;
     __shared__ double sh[NT];
+    if (R > 1) {   // thread t sums column t % R of rows t / R, t / R + NT / R, ...: coalesced reads
+        const int T = NT / R, t = threadIdx.x;
+        double acc = 0.0;
+        if (t < T * R)
+            for (int b = t / R; b < nb; b += T) acc += part[(size_t)b * R + t % R];
+        sh[t] = acc;
+        __syncthreads();
+        if (t < R) {
+            double s = 0.0;
+            for (int k = 0; k < T; ++k) s += sh[k * R + t];
+            out[t] = s;
+        }
+        return;
+    }
     for (int r = 0; r < R; ++r) {
         double acc = 0.0;
         for (int b = threadIdx.x; b < nb; b += NT) acc += part[(size_t)b * R + r];
@@ -618,15 +651,15 @@ __global__ __launch_bounds__(1024) void sum_partials_kernel(int nb, const double
     }
 }
 
-// CG update of one iteration in a single pass: x += alpha p, r -= alpha q (alpha = num/den per
+// CG update of one iteration in a single pass: x += alpha p (X), r -= alpha q (alpha = num/den per
 // column), and the partial sums of the new r squared per column, in the thread layout of
 // dot_partial_kernel (part[blk][r], reduced by dot_final_kernel)
-__global__ __launch_bounds__(NT) void cg_update_kernel(int64_t n, int R, const double* __restrict__ num,
-                                                       const double* __restrict__ den,
-                                                       const double* __restrict__ p, const double* __restrict__ q,
-                                                       double* __restrict__ x, double* __restrict__ rv,
-                                                       double* __restrict__ part, const int* __restrict__ done,
-                                                       int* __restrict__ iters) {
+template <bool X>
+__device__ __forceinline__ void cg_update_body(int64_t n, int R, const double* __restrict__ num,
+                                               const double* __restrict__ den, const double* __restrict__ p,
+                                               const double* __restrict__ q, double* __restrict__ x,
+                                               double* __restrict__ rv, double* __restrict__ part,
+                                               const int* __restrict__ done, int* __restrict__ iters) {
     if (done && *done) return;
     if (iters && blockIdx.x == 0 && threadIdx.x == 0) ++*iters;
     __shared__ double sh[NT];
@@ -639,7 +672,7 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(int64_t n, int R, const d
 #pragma unroll 4
         for (int64_t i = (int64_t)blockIdx.x * T + t / R; i < n; i += (int64_t)gridDim.x * T) {
             const int64_t k = i * R + r;
-            x[k] += al * p[k];
+            if constexpr (X) x[k] += al * p[k];
             const double rn = rv[k] - al * q[k];
             rv[k] = rn;
             acc += rn * rn;
@@ -658,6 +691,34 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(int64_t n, int R, const d
         for (int k = 0; k < T; ++k) s += sh[k * R + t];
         part[(size_t)blockIdx.x * R + t] = s;
     }
+}
+
+__global__ __launch_bounds__(NT) void cg_update_kernel(int64_t n, int R, const double* __restrict__ num,
+                                                       const double* __restrict__ den,
+                                                       const double* __restrict__ p, const double* __restrict__ q,
+                                                       double* __restrict__ x, double* __restrict__ rv,
+                                                       double* __restrict__ part, const int* __restrict__ done,
+                                                       int* __restrict__ iters) {
+    cg_update_body<true>(n, R, num, den, p, q, x, rv, part, done, iters);
+}
+
+// the same without x (the 32-column SSOR CG applies x += alpha p in the next direction update)
+__global__ __launch_bounds__(NT) void cg_resid_update_kernel(int64_t n, int R, const double* __restrict__ num,
+                                                             const double* __restrict__ den,
+                                                             const double* __restrict__ q, double* __restrict__ rv,
+                                                             double* __restrict__ part) {
+    cg_update_body<false>(n, R, num, den, nullptr, q, nullptr, rv, part, nullptr, nullptr);
+}
+
+// y += (num/den) x per column
+__global__ __launch_bounds__(NT) void axpy_ratio_cols_kernel(int64_t n, int R, const double* __restrict__ num,
+                                                             const double* __restrict__ den,
+                                                             const double* __restrict__ x, double* __restrict__ y) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n * R) return;
+    const int r = (int)(gid % R);
+    const double dd = den[r];
+    y[gid] += (dd != 0.0 ? num[r] / dd : 0.0) * x[gid];
 }
 
 // p = z + beta p, beta = num/den per column
@@ -1217,6 +1278,8 @@ struct SweepArgs {
     double* u0;          // C0
     double* part;        // p.q partials (HAT, C0), or null
     const int* done;     // the device-side CG's flag: every launch returns once it is set, or null
+    double* xs;          // PX with num, 32 columns: xs += (den / pqp) v before the direction update
+    const double* pqp;   // (the previous iteration's solution update), or null
 };
 
 template <int BS, bool HAT, bool PX, bool C0>
@@ -1282,8 +1345,9 @@ __global__ __launch_bounds__(NT) void ssor_sweep_kernel(int64_t p0, int64_t nfc,
 // The sweep of one colour with 32 right-hand sides: one face per wavefront, the sum over the
 // face's sweep blocks as 16x16x4 FP64 MFMA tiles (A: the block Kt_{F,G}, B: the neighbour's bs x 32
 // vector block), as in the block products of the 32-column CG, then the same row updates and
-// fusions as the one-column sweep, per column (PX: p = r + beta_col p).  No p.q partial sums (a
-// separate dot forms them).
+// fusions as the one-column sweep, per column (PX: p = r + beta_col p, after y += alpha_col p of
+// the previous iteration when xs is given).  With part, the p.q sums of the face's rows per
+// column go to part[F][32] (a column sum over the faces follows).
 template <int BS, bool HAT, bool PX, bool C0>
 __global__ __launch_bounds__(256) void ssor_sweep32_kernel(int64_t p0, int64_t nfc, SweepArgs A) {
     if (A.done && *A.done) return;
@@ -1320,13 +1384,17 @@ __global__ __launch_bounds__(256) void ssor_sweep32_kernel(int64_t p0, int64_t n
             }
         }
     }
-    double be[2] = {0.0, 0.0};
+    double be[2] = {0.0, 0.0}, al[2] = {0.0, 0.0}, pq[2] = {0.0, 0.0};
     if constexpr (PX) {
         if (A.num)
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) {
                 const double dd = A.den[16 * nt + lr];
                 be[nt] = dd != 0.0 ? A.num[16 * nt + lr] / dd : 0.0;
+                if (A.xs) {
+                    const double pp = A.pqp[16 * nt + lr];
+                    al[nt] = pp != 0.0 ? dd / pp : 0.0;
+                }
             }
     }
 #pragma unroll
@@ -1341,6 +1409,7 @@ __global__ __launch_bounds__(256) void ssor_sweep32_kernel(int64_t p0, int64_t n
                 double sv = A.v[o];
                 if constexpr (PX) {
                     if (A.num) {
+                        if (A.xs) A.xs[o] += al[nt] * sv;
                         sv = A.r[o] + be[nt] * sv;
                         const_cast<double*>(A.v)[o] = sv;
                     }
@@ -1353,12 +1422,29 @@ __global__ __launch_bounds__(256) void ssor_sweep32_kernel(int64_t p0, int64_t n
                 }
                 sv -= acc[mt][nt][v];
                 A.y[o] = sv;
-                if constexpr (HAT) A.q[o] = tk + sv;
+                if constexpr (HAT) {
+                    A.q[o] = tk + sv;
+                    pq[nt] += pk * (tk + sv);
+                }
                 if constexpr (C0) {
                     A.u0[o] = pk - sv;
                     A.q[o] = pk;
+                    pq[nt] += pk * pk;
                 }
             }
+    if constexpr (HAT || C0) {
+        if (!A.part) return;
+        // the four row groups of a column (lanes lr, lr + 16, lr + 32, lr + 48)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            pq[nt] += __shfl_xor(pq[nt], 16, 64);
+            pq[nt] += __shfl_xor(pq[nt], 32, 64);
+        }
+        if (lg == 0) {
+            A.part[(size_t)F * R + lr] = pq[0];
+            A.part[(size_t)F * R + 16 + lr] = pq[1];
+        }
+    }
 }
 
 // out = x + W^T t with R right-hand sides (thread per entry (F, a, r))
@@ -1437,13 +1523,16 @@ void ssor_sweep(hdg_ctx* c, const double* v, double* y) {
     }
 }
 
-// the product of ssor_product with 32 right-hand sides; p.q per column by a separate dot
+// the product of ssor_product with 32 right-hand sides; p.q per face and column from the launches
+// that form q (`part`, n_faces x 32), then summed over the faces.  With xs (and num), the backward
+// sweep first adds (den / s_pq) p to xs: the previous iteration's solution update, deferred from
+// its CG update so that p is read once
 template <int BS>
 void ssor_product32(hdg_ctx* c, double* p, const double* r, const double* num, const double* den, double* t,
-                    double* u, double* q, double* s_pq) {
+                    double* u, double* q, double* s_pq, double* part, double* xs) {
     const int nc = c->ncolors;
     SweepArgs B{c->d_cfaces, c->d_ssoff + c->n_faces + 1, c->d_ssnb, c->d_ssA, p, nullptr, t, q, r, num, den,
-                u, nullptr, c->cg_done};
+                u, part, c->cg_done, num ? xs : nullptr, s_pq};
     for (int k = 0; k < nc; ++k) {
         const int col = nc - 1 - k;
         const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
@@ -1452,13 +1541,16 @@ void ssor_product32(hdg_ctx* c, double* p, const double* r, const double* num, c
         else sweep32_launch<BS, false, true, false>(c, p0, nfc, B);
     }
     SweepArgs H{c->d_cfaces, c->d_ssoff, c->d_ssnb, c->d_ssA, p, t, u, q, nullptr, nullptr, nullptr, nullptr,
-                nullptr, c->cg_done};
+                part, c->cg_done};
     for (int col = 1; col < nc; ++col) {
         const int64_t p0 = c->color_off[col], nfc = c->color_off[col + 1] - p0;
         if (nfc == 0) continue;
         sweep32_launch<BS, true, false, false>(c, p0, nfc, H);
     }
-    dot(c, p, q, s_pq);
+    hipLaunchKernelGGL(colsum32_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, c->n_faces, part, c->d_red,
+                       (const int*)c->cg_done);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(NT), 0, c->stream, c->red_blocks, 32, c->d_red, s_pq,
+                       (const int*)c->cg_done);
 }
 
 // q = Ahat p = t + Lh^{-1} (p - t), t = Uh^{-1} p, and s_pq = p.q; with num/den first
@@ -1599,14 +1691,18 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
     // after the swap at the end of an iteration)
     auto product = [&](bool beta) {
         if constexpr (R == 1) ssor_product<BS>(c, pp, rr, beta ? s_rz : nullptr, s_rz_new, tt, uu, qq, s_pq);
-        else ssor_product32<BS>(c, pp, rr, beta ? s_rz : nullptr, s_rz_new, tt, uu, qq, s_pq);
+        else ssor_product32<BS>(c, pp, rr, beta ? s_rz : nullptr, s_rz_new, tt, uu, qq, s_pq, c->d_ss + 3 * nR, yy);
     };
     for (it = 0; it <= c->krylov_maxit; ++it) {
         if (hipMemcpyAsync(hrz, s_rz, R * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipEventRecord(c->ev_rr, c->stream) != hipSuccess)
             return HDG_E_HIP;
-        // queue the next product before waiting for r.r
+        // queue the next product before waiting for r.r (with 32 columns it also applies the
+        // previous iteration's y += alpha p; at the iteration limit that update is launched alone)
         if (it < c->krylov_maxit) product(it > 0);
+        else if (R == 32 && it > 0)
+            hipLaunchKernelGGL(axpy_ratio_cols_kernel, dim3(nblk(nR)), dim3(NT), 0, c->stream, n, R, s_rz_new, s_pq,
+                               pp, yy);
         if (hipEventSynchronize(c->ev_rr) != hipSuccess) return HDG_E_HIP;
         double est = 0.0;
         bool nonfinite = false;
@@ -1635,8 +1731,12 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
             thresh *= 0.1;
             product(false);   // the check overwrote t, u and q: this iteration's product again (p is new)
         }
-        hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, pp, qq,
-                           yy, rr, c->d_red, (const int*)nullptr, (int*)nullptr);
+        if constexpr (R == 1)
+            hipLaunchKernelGGL(cg_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, s_rz, s_pq, pp,
+                               qq, yy, rr, c->d_red, (const int*)nullptr, (int*)nullptr);
+        else   // y += alpha p in the next product
+            hipLaunchKernelGGL(cg_resid_update_kernel, dim3(c->red_blocks), dim3(NT), 0, c->stream, n, R, s_rz, s_pq,
+                               qq, rr, c->d_red);
         if constexpr (R == 1)
             hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(1024), 0, c->stream, c->red_blocks, c->d_red,
                                s_rz_new);
@@ -1748,7 +1848,9 @@ int cg_ssor_device(hdg_ctx* c, double* x, double tol, int nit, int* flags, doubl
 int trace_ssor_alloc(hdg_ctx* c) {
     const size_t nt = (size_t)c->n_faces * c->bs;
     void** bufs[3] = {(void**)&c->d_ss, (void**)&c->d_rinv, (void**)&c->d_ssA};
-    const size_t sizes[3] = {3 * nt * c->nrhs, nt * c->bs, (size_t)std::max<int64_t>(c->ss_nblk, 1) * c->bs * c->bs};
+    // d_ss: t, u, y of the transformed CG, and with 32 right-hand sides the per-face p.q partials
+    const size_t sizes[3] = {3 * nt * c->nrhs + (c->nrhs == 32 ? (size_t)c->n_faces * 32 : 0), nt * c->bs,
+                             (size_t)std::max<int64_t>(c->ss_nblk, 1) * c->bs * c->bs};
     for (int i = 0; i < 3; ++i) {
         if (*bufs[i]) continue;
         const int e = dev_malloc(c, bufs[i], sizes[i] * sizeof(double));

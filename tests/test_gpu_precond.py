@@ -209,3 +209,45 @@ def test_ssor_32_rhs_parity_and_iterations(cfg, kw, prec, neumann):
             assert num <= tol * den, (q, g, num / den)
         assert np.linalg.norm(lam[:, q] - lam_ref[:, q]) <= tol * np.linalg.norm(lam_ref[:, q]), q
     print(f"iterations jacobi {res['jacobi'][2]} ssor {it}", flush=True)
+
+
+@pytest.mark.parametrize("R", [1, 32])
+def test_ssor_iteration_limit_energy_decreases(R):
+    """Stopped at the iteration limit m (HDG_E_NOCONV), the returned trace is the m-th CG iterate:
+    its error in the energy norm of K (|e^T K e|, which CG minimises over a growing Krylov space) strictly
+    decreases from m = 2 to 3 to 4 in every column.  With 32 columns the solution update of the
+    last iteration is applied on its own at the limit (otherwise it rides on the next direction
+    update), so a lost update would repeat the previous iterate."""
+    _need_gpu()
+    from oracle import hdg as ohdg
+    from paper_1807_00086_amd import HDGError, Solver
+    p = make_problem(2, n=2, k=3)
+    print(f"case ssor iteration limit R={R} n_elem={p.n_elem}", flush=True)
+    d = ohdg.make_discretisation(p)
+    a = 1.0 / (GAMMA * p.dt)
+    mask = ohdg.boundary_trace_mask(d)
+    F = random_vector(d.loc_off[-1] * R, 2, 91).reshape(-1, R)
+    LB = random_vector(d.tr_off[-1] * R, 2, 92).reshape(-1, R) * mask[:, None]
+    cond = ohdg.condense(d, a, F)
+    lam_ref = ohdg.trace_solve(d, cond, LB)
+    K = cond.K.tocsr()
+    energies = []
+    for m in (2, 3, 4):
+        s = Solver(p.xyz, p.elem_vert, p.physics, p.elem_par, k=3, precision="fp64", nrhs=R, precond="ssor",
+                   krylov_tol=1e-30, krylov_maxit=m)
+        s.condense(a, torch.as_tensor(np.ascontiguousarray(F), device="cuda"),
+                   torch.as_tensor(np.ascontiguousarray(LB), device="cuda"))
+        lam = torch.zeros(d.tr_off[-1] * R, dtype=torch.float64, device="cuda")
+        with pytest.raises(HDGError):
+            s.trace_solve(lam)
+        torch.cuda.synchronize()
+        e = lam.cpu().numpy().reshape(-1, R) - lam_ref
+        assert np.all(e[mask] == 0.0)   # Dirichlet values are set, not iterated
+        energies.append(np.einsum("ir,ir->r", e, K @ e))
+        s.close()
+    # K is definite with the sign of its physics (negative for acoustics): compare |e^T K e|
+    sgn = np.sign(energies[0][0])
+    E2, E3, E4 = (sgn * E for E in energies)
+    assert np.all(E2 > 0.0)
+    assert np.all(E3 < E2) and np.all(E4 < E3), (E2, E3, E4)
+    print(f"energy error m=2..4, worst ratio {np.max(E3 / E2):.3f} {np.max(E4 / E3):.3f}", flush=True)
