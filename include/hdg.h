@@ -127,14 +127,15 @@ typedef struct {
                                    built for it on the mesh's own elements (where the element
                                    buffers live: LDS only, or part of them in per-workgroup
                                    global scratch; reference tables in LDS or read through the
-                                   caches: trading LDS for workgroups per CU), keeps the
+                                   caches: trading LDS for workgroups per CU; four or eight
+                                   wavefronts per element workgroup), keeps the
                                    fastest for the life of the context and synchronises once
                                    to read the timers.  Zero: the built-in default.          */
     const char* autotune_table; /* NULL, or a text file of tuned schedules: read at
                                    hdg_init_mesh (entries for this physics, nrhs, precision
                                    and device replace the defaults), rewritten after tuning.
                                    One line per class: device physics k kF nrhs precision
-                                   schedule ms_0 ms_1 ms_2 (lines starting with '#' are
+                                   schedule ms_0 .. ms_3 (lines starting with '#' are
                                    comments; 0 ms: schedule not built for the class)        */
     int use_graph;              /* nonzero, mesh of variable degree: hdg_condense runs its
                                    per-degree-class launches as one hipGraph whose class

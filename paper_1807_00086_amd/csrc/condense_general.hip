@@ -54,8 +54,7 @@ namespace hdg {
 
 namespace {
 
-constexpr int NTG = 256;
-constexpr int NWG = NTG / 64;   // wavefronts per workgroup
+constexpr int NWG_DEF = 4;   // wavefronts per element workgroup of the condensation (schedules 0-2)
 constexpr int PH_ACOUSTIC = 0, PH_ELASTIC = 1, PH_MAXWELL = 2, PH_GLM = 3;
 // GLM coefficients alpha_1, alpha_2, alpha_3 of (dmax3): section 5.4 runs all three at 1
 constexpr double GLM_A1 = 1.0, GLM_A2 = 1.0, GLM_A3 = 1.0;
@@ -325,9 +324,11 @@ constexpr int64_t gen_gstride(int SG) {
 // TBL: the Sr tables staged in LDS once per workgroup (true) or read through L1/L2 (false, which
 // leaves more LDS for workgroups per CU).  BF (T = float): the matrix-core products (B~2 tiles,
 // the strip updates of the triangular solves, the K_e tiles) run as split-BF16 products on the
-// BF16 matrix cores with FP32 accumulation (bf16x3_mac16); the factorisation stays FP32.
-template <int PHYS, int K, int KF, int R, typename T, int SG, bool TBL, bool BF = false>
-__global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void condense_general_kernel(
+// BF16 matrix cores with FP32 accumulation (bf16x3_mac16); the factorisation stays FP32.  NW:
+// wavefronts per workgroup (one element per workgroup); the tile loops spread over all of them,
+// the pivot steps stay on wavefront 0.
+template <int PHYS, int K, int KF, int R, typename T, int SG, bool TBL, bool BF = false, int NW = NWG_DEF>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void condense_general_kernel(
     int64_t ne, double a, const double* __restrict__ geom, const double* __restrict__ eframe,
     const int32_t* __restrict__ eperm, const T* __restrict__ Sr, const T* __restrict__ Mf,
     const T* __restrict__ Tfull, const T* __restrict__ Ef, const double* __restrict__ f_loc,
@@ -337,6 +338,8 @@ __global__ __launch_bounds__(NTG) __attribute__((amdgpu_waves_per_eu(2))) void c
     constexpr int N = Dm::N, NF = Dm::NF, NFACE = Dm::NFACE, NPERM = Dm::NPERM, D = Dm::D;
     constexpr int M1 = Dm::M1, M2 = Dm::M2, MT = Dm::MT, N1 = Dm::N1, N2 = Dm::N2, NLOC = Dm::NLOC;
     constexpr int NFC = Dm::NFC, TT = Dm::TT, C = Dm::C;
+    constexpr int NTG = 64 * NW, NWG = NW;   // threads and wavefronts of the workgroup
+    static_assert(NW >= 2 && 64 * NW >= GEOM_STRIDE, "the loads assume at least two wavefronts");
 
     __shared__ T Srl[TBL ? D * N * N : 1];
     const T* Srs = TBL ? Srl : Sr;
@@ -1411,16 +1414,21 @@ constexpr int gen_fit(size_t cap, bool tbl) {
 // schedule 0 (default): tables in LDS and at most 75 KB of LDS per workgroup, so that two
 // workgroups share a CU, the element buffers that do not fit in global scratch (L2-resident);
 // schedule 1: tables in LDS and the fewest buffers in global scratch that fit a whole CU's LDS
-// (one workgroup per CU); schedule 2: tables through L1/L2 and the 75 KB rule.  A schedule that
-// repeats an earlier placement is not built.
+// (one workgroup per CU); schedule 2: tables through L1/L2 and the 75 KB rule; schedule 3:
+// schedule 1's placement with eight wavefronts per workgroup instead of four (one element per
+// CU, its tile work spread over two wavefronts per SIMD).  Schedules 0-2 run four wavefronts per
+// workgroup.  A schedule that repeats an earlier placement and shape is not built.
 template <int PHYS, int K, int KF, int R, typename T>
 constexpr int gen_sg(int sched) {
     return sched == 0 ? gen_fit<PHYS, K, KF, R, T>(LDS_SHARE, true)
-                      : (sched == 1 ? gen_fit<PHYS, K, KF, R, T>(LDS_CU, true) : gen_fit<PHYS, K, KF, R, T>(LDS_SHARE, false));
+                      : (sched == 1 || sched == 3 ? gen_fit<PHYS, K, KF, R, T>(LDS_CU, true)
+                                                  : gen_fit<PHYS, K, KF, R, T>(LDS_SHARE, false));
 }
+constexpr int gen_waves(int sched) { return sched == 3 ? 8 : NWG_DEF; }
 template <int PHYS, int K, int KF, int R, typename T>
 constexpr bool gen_built(int sched) {
-    return sched == 0 || (sched == 1 && gen_sg<PHYS, K, KF, R, T>(1) != gen_sg<PHYS, K, KF, R, T>(0)) || sched == 2;
+    return sched == 0 || (sched == 1 && gen_sg<PHYS, K, KF, R, T>(1) != gen_sg<PHYS, K, KF, R, T>(0)) || sched == 2 ||
+           sched == 3;
 }
 template <int PHYS, int K, int KF, int R>
 int gen_grid(int64_t n) {
@@ -1432,19 +1440,19 @@ size_t gen_scratch(int64_t n, int sched) {
     return (size_t)gen_grid<PHYS, K, KF, R>(n) * gen_gstride<PHYS, K, KF, R>(gen_sg<PHYS, K, KF, R, T>(sched)) * sizeof(T);
 }
 
-template <int PHYS, int K, int KF, int R, typename T, int SG, bool TBL, bool BF>
+template <int PHYS, int K, int KF, int R, typename T, int SG, bool TBL, bool BF, int NW = NWG_DEF>
 int launch_gen_sg(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist,
                   int64_t n, T* scratch, hipStream_t st) {
     using TB = TabOf<T>;
-    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, KF, R, T, SG, TBL, BF>), dim3(gen_grid<PHYS, K, KF, R>(n)),
-                       dim3(NTG), 0, st, n, a, c->d_geom, c->d_eframe, c->d_eperm, TB::Sr(tb), TB::Mf(tb), TB::Tf(tb),
+    hipLaunchKernelGGL((condense_general_kernel<PHYS, K, KF, R, T, SG, TBL, BF, NW>),
+                       dim3(gen_grid<PHYS, K, KF, R>(n)), dim3(64 * NW), 0, st, n, a, c->d_geom, c->d_eframe, c->d_eperm, TB::Sr(tb), TB::Mf(tb), TB::Tf(tb),
                        TB::Ef(tb), f_loc, (T*)c->d_Ke, (T*)c->d_re, (T*)c->d_Zt, (T*)c->d_z,
                        (T*)c->d_LU, scratch, c->d_status,
                        var_args(c, elist));
     return (int)hipGetLastError();
 }
 
-// schedule `sched` (0..2) of a class; a schedule that is not built falls back to 0
+// schedule `sched` (0..3) of a class; a schedule that is not built falls back to 0
 template <int PHYS, int K, int KF, int R, typename T, bool BF>
 int launch_gen(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist, int64_t n,
                int sched, T* scratch, hipStream_t st) {
@@ -1452,6 +1460,8 @@ int launch_gen(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb
     if constexpr (gen_built<PHYS, K, KF, R, T>(1))
         if (sched == 1) return launch_gen_sg<PHYS, K, KF, R, T, S1, true, BF>(c, a, f_loc, tb, elist, n, scratch, st);
     if (sched == 2) return launch_gen_sg<PHYS, K, KF, R, T, S2, false, BF>(c, a, f_loc, tb, elist, n, scratch, st);
+    if (sched == 3)
+        return launch_gen_sg<PHYS, K, KF, R, T, S1, true, BF, gen_waves(3)>(c, a, f_loc, tb, elist, n, scratch, st);
     return launch_gen_sg<PHYS, K, KF, R, T, S0, true, BF>(c, a, f_loc, tb, elist, n, scratch, st);
 }
 
@@ -1503,7 +1513,7 @@ int launch_gen_ref(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int
     X(0, 1, 5, 32) X(0, 2, 5, 32) X(0, 3, 5, 32) X(0, 4, 5, 32) X(0, 5, 5, 32)
 
 constexpr int VAR_KF = 5;
-constexpr int NSCHED = 3;   // launch schedules of the condensation (see gen_sg)
+constexpr int NSCHED = 4;   // launch schedules of the condensation (see gen_sg)
 
 // Calls `fn(K, KF, tables, list, count)` for every launch of the current mesh: one per degree
 // class on a mesh of variable degree, one for all elements otherwise.
@@ -1541,7 +1551,7 @@ int gen_class(hdg_ctx* c, int K, int KF, const DeviceTables& tb, const int32_t* 
         }                                                                                                \
         if (g.op == 2) {                                                                                 \
             g.out = std::max({gen_scratch<PP, KK, FF, RR, T>(n, 0), gen_scratch<PP, KK, FF, RR, T>(n, 1),  \
-                              gen_scratch<PP, KK, FF, RR, T>(n, 2)});                                    \
+                              gen_scratch<PP, KK, FF, RR, T>(n, 2), gen_scratch<PP, KK, FF, RR, T>(n, 3)}); \
             return 0;                                                                                    \
         }                                                                                                \
         if constexpr (BF && (PP == 0 || sizeof(T) != 4)) return -1;                                     \
