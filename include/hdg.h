@@ -135,7 +135,7 @@ typedef struct {
                                    hdg_init_mesh (entries for this physics, nrhs, precision
                                    and device replace the defaults), rewritten after tuning.
                                    One line per class: device physics k kF nrhs precision
-                                   schedule ms_0 .. ms_3 (lines starting with '#' are
+                                   schedule ms_0 .. ms_4 (lines starting with '#' are
                                    comments; 0 ms: schedule not built for the class)        */
     int use_graph;              /* nonzero, mesh of variable degree: hdg_condense runs its
                                    per-degree-class launches as one hipGraph whose class

@@ -43,7 +43,7 @@ void dev_release(hdg_ctx* c, void* p) {
 }
 
 // Autotune table: one line per tuned class, "device physics k kF nrhs precision schedule ms_0
-// ms_1 ms_2 ms_3" (0: schedule not built for the class); '#' starts a comment line.
+// ms_1 ms_2 ms_3 ms_4" (0: schedule not built for the class); '#' starts a comment line.
 namespace {
 bool tune_key_matches(const hdg_ctx* c, const std::string& dev, int phys, int k, int kf, int nrhs, int prec) {
     const int kf_c = c->vardeg ? var_face_degree() : k;
@@ -62,7 +62,7 @@ void read_tune_table(hdg_ctx* c) {
         char dev[128];
         int phys, k, kf, nrhs, prec, sch;
         if (std::sscanf(line, "%127s %d %d %d %d %d %d", dev, &phys, &k, &kf, &nrhs, &prec, &sch) != 7) continue;
-        if (sch < 0 || sch > 3 || !tune_key_matches(c, dev, phys, k, kf, nrhs, prec)) continue;
+        if (sch < 0 || sch > 4 || !tune_key_matches(c, dev, phys, k, kf, nrhs, prec)) continue;
         c->sched[pi][k] = (int8_t)sch;
     }
     std::fclose(fp);
@@ -91,15 +91,15 @@ void write_tune_table(const hdg_ctx* c) {
     FILE* fp = std::fopen(tmp.c_str(), "w");
     if (!fp) return;
     if (keep.empty())
-        std::fprintf(fp, "# device physics k kF nrhs precision schedule ms_0 ms_1 ms_2 ms_3 (0: not built)\n");
+        std::fprintf(fp, "# device physics k kF nrhs precision schedule ms_0 ms_1 ms_2 ms_3 ms_4 (0: not built)\n");
     for (const auto& l : keep) std::fputs(l.c_str(), fp);
     for (int k = 1; k <= 5; ++k) {
         if (!timed(k) || !tune_key_matches(c, c->device_name, c->physics, k, c->vardeg ? var_face_degree() : k,
                                                      c->nrhs, c->precision))
             continue;
-        std::fprintf(fp, "%s %d %d %d %d %d %d %.4f %.4f %.4f %.4f\n", c->device_name.c_str(), c->physics, k,
+        std::fprintf(fp, "%s %d %d %d %d %d %d %.4f %.4f %.4f %.4f %.4f\n", c->device_name.c_str(), c->physics, k,
                      c->vardeg ? var_face_degree() : k, c->nrhs, c->precision, c->sched[pi][k], c->sched_ms[pi][k][0],
-                     c->sched_ms[pi][k][1], c->sched_ms[pi][k][2], c->sched_ms[pi][k][3]);
+                     c->sched_ms[pi][k][1], c->sched_ms[pi][k][2], c->sched_ms[pi][k][3], c->sched_ms[pi][k][4]);
     }
     std::fclose(fp);
     std::rename(tmp.c_str(), c->tune_path.c_str());

@@ -1414,21 +1414,24 @@ constexpr int gen_fit(size_t cap, bool tbl) {
 // schedule 0 (default): tables in LDS and at most 75 KB of LDS per workgroup, so that two
 // workgroups share a CU, the element buffers that do not fit in global scratch (L2-resident);
 // schedule 1: tables in LDS and the fewest buffers in global scratch that fit a whole CU's LDS
-// (one workgroup per CU); schedule 2: tables through L1/L2 and the 75 KB rule; schedule 3:
-// schedule 1's placement with eight wavefronts per workgroup instead of four (one element per
-// CU, its tile work spread over two wavefronts per SIMD).  Schedules 0-2 run four wavefronts per
-// workgroup.  A schedule that repeats an earlier placement and shape is not built.
+// (one workgroup per CU); schedule 2: tables through L1/L2 and the 75 KB rule; schedules 3 and 4:
+// eight wavefronts per workgroup instead of four (one element per CU, its tile work spread over
+// two wavefronts per SIMD) with the tables in LDS (schedule 1's placement) or through L1/L2 and
+// the element buffers in a whole CU's LDS.  Schedules 0-2 run four wavefronts per workgroup.
+// Schedule 1 is not built where it repeats schedule 0's placement.
+constexpr int GEN_NSCHED = 5;
 template <int PHYS, int K, int KF, int R, typename T>
 constexpr int gen_sg(int sched) {
     return sched == 0 ? gen_fit<PHYS, K, KF, R, T>(LDS_SHARE, true)
                       : (sched == 1 || sched == 3 ? gen_fit<PHYS, K, KF, R, T>(LDS_CU, true)
-                                                  : gen_fit<PHYS, K, KF, R, T>(LDS_SHARE, false));
+                                                  : (sched == 4 ? gen_fit<PHYS, K, KF, R, T>(LDS_CU, false)
+                                                                : gen_fit<PHYS, K, KF, R, T>(LDS_SHARE, false)));
 }
-constexpr int gen_waves(int sched) { return sched == 3 ? 8 : NWG_DEF; }
+constexpr int gen_waves(int sched) { return sched >= 3 ? 8 : NWG_DEF; }
 template <int PHYS, int K, int KF, int R, typename T>
 constexpr bool gen_built(int sched) {
-    return sched == 0 || (sched == 1 && gen_sg<PHYS, K, KF, R, T>(1) != gen_sg<PHYS, K, KF, R, T>(0)) || sched == 2 ||
-           sched == 3;
+    return sched == 0 || (sched == 1 && gen_sg<PHYS, K, KF, R, T>(1) != gen_sg<PHYS, K, KF, R, T>(0)) ||
+           (sched >= 2 && sched < GEN_NSCHED);
 }
 template <int PHYS, int K, int KF, int R>
 int gen_grid(int64_t n) {
@@ -1452,16 +1455,19 @@ int launch_gen_sg(hdg_ctx* c, double a, const double* f_loc, const DeviceTables&
     return (int)hipGetLastError();
 }
 
-// schedule `sched` (0..3) of a class; a schedule that is not built falls back to 0
+// schedule `sched` (0..4) of a class; a schedule that is not built falls back to 0
 template <int PHYS, int K, int KF, int R, typename T, bool BF>
 int launch_gen(hdg_ctx* c, double a, const double* f_loc, const DeviceTables& tb, const int32_t* elist, int64_t n,
                int sched, T* scratch, hipStream_t st) {
-    constexpr int S0 = gen_sg<PHYS, K, KF, R, T>(0), S1 = gen_sg<PHYS, K, KF, R, T>(1), S2 = gen_sg<PHYS, K, KF, R, T>(2);
+    constexpr int S0 = gen_sg<PHYS, K, KF, R, T>(0), S1 = gen_sg<PHYS, K, KF, R, T>(1), S2 = gen_sg<PHYS, K, KF, R, T>(2),
+                  S4 = gen_sg<PHYS, K, KF, R, T>(4);
     if constexpr (gen_built<PHYS, K, KF, R, T>(1))
         if (sched == 1) return launch_gen_sg<PHYS, K, KF, R, T, S1, true, BF>(c, a, f_loc, tb, elist, n, scratch, st);
     if (sched == 2) return launch_gen_sg<PHYS, K, KF, R, T, S2, false, BF>(c, a, f_loc, tb, elist, n, scratch, st);
     if (sched == 3)
         return launch_gen_sg<PHYS, K, KF, R, T, S1, true, BF, gen_waves(3)>(c, a, f_loc, tb, elist, n, scratch, st);
+    if (sched == 4)
+        return launch_gen_sg<PHYS, K, KF, R, T, S4, false, BF, gen_waves(4)>(c, a, f_loc, tb, elist, n, scratch, st);
     return launch_gen_sg<PHYS, K, KF, R, T, S0, true, BF>(c, a, f_loc, tb, elist, n, scratch, st);
 }
 
@@ -1513,7 +1519,7 @@ int launch_gen_ref(hdg_ctx* c, const DeviceTables& tb, const int32_t* elist, int
     X(0, 1, 5, 32) X(0, 2, 5, 32) X(0, 3, 5, 32) X(0, 4, 5, 32) X(0, 5, 5, 32)
 
 constexpr int VAR_KF = 5;
-constexpr int NSCHED = 4;   // launch schedules of the condensation (see gen_sg)
+constexpr int NSCHED = GEN_NSCHED;   // launch schedules of the condensation (see gen_sg)
 
 // Calls `fn(K, KF, tables, list, count)` for every launch of the current mesh: one per degree
 // class on a mesh of variable degree, one for all elements otherwise.
@@ -1551,7 +1557,8 @@ int gen_class(hdg_ctx* c, int K, int KF, const DeviceTables& tb, const int32_t* 
         }                                                                                                \
         if (g.op == 2) {                                                                                 \
             g.out = std::max({gen_scratch<PP, KK, FF, RR, T>(n, 0), gen_scratch<PP, KK, FF, RR, T>(n, 1),  \
-                              gen_scratch<PP, KK, FF, RR, T>(n, 2), gen_scratch<PP, KK, FF, RR, T>(n, 3)}); \
+                              gen_scratch<PP, KK, FF, RR, T>(n, 2), gen_scratch<PP, KK, FF, RR, T>(n, 3),     \
+                              gen_scratch<PP, KK, FF, RR, T>(n, 4)});                                    \
             return 0;                                                                                    \
         }                                                                                                \
         if constexpr (BF && (PP == 0 || sizeof(T) != 4)) return -1;                                     \

@@ -169,7 +169,7 @@ struct hdg_ctx {
     bool autotune = false;
     std::string tune_path, device_name;
     int8_t sched[2][6] = {{-1, -1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1, -1}};
-    float sched_ms[2][6][4] = {};
+    float sched_ms[2][6][5] = {};   // per precision, degree, launch schedule
     size_t xs_off[6] = {0, 0, 0, 0, 0, 0};   // per-class offsets into d_xscratch (bytes)
     // one hipGraph per condensation of a mesh of variable degree: class launches on side
     // streams forked from and joined into side[0]

@@ -94,7 +94,7 @@ def test_autotuned_schedules_match_default(cfg, kw, prec, tmp_path):
     u1b, _ = _stage(s1, a, f, lb)          # second stage: the tuned schedules, no timing
     s1.close()
     assert set(sch1) == set(sch0)
-    assert all(v in (0, 1, 2, 3) for v in sch1.values())
+    assert all(v in (0, 1, 2, 3, 4) for v in sch1.values())
     assert _rel(u1, u0) <= 1e-13 and _rel(lam1, lam0) <= 1e-13
     assert _rel(u1b, u0) <= 1e-13
     if p.uniform_k:
@@ -202,11 +202,12 @@ WAVE8_CASES = [
 ]
 
 
+@pytest.mark.parametrize("sched", [3, 4])
 @pytest.mark.parametrize("cfg,kw,prec", WAVE8_CASES)
-def test_eight_wavefront_schedule_matches_default(cfg, kw, prec, tmp_path):
-    """Schedule 3 (eight wavefronts per element workgroup, a whole CU's LDS) read from a tune
-    table for every class: the same result as the default schedule (relative 1e-13) and the
-    oracle's tolerance on uniform meshes."""
+def test_eight_wavefront_schedule_matches_default(cfg, kw, prec, sched, tmp_path):
+    """Schedules 3 and 4 (eight wavefronts per element workgroup, a whole CU's LDS; reference
+    tables in LDS or through the caches) read from a tune table for every class: the same result
+    as the default schedule (relative 1e-13) and the oracle's tolerance on uniform meshes."""
     _need_gpu()
     from paper_1807_00086_amd.hdg import PHYSICS, PRECISION
     phys = None
@@ -216,7 +217,7 @@ def test_eight_wavefront_schedule_matches_default(cfg, kw, prec, tmp_path):
     if phys:
         p.physics = phys
     dev = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
-    print(f"case eight wavefronts cfg={cfg} {kw} {p.physics} {prec} n_elem={p.n_elem}", flush=True)
+    print(f"case schedule {sched} cfg={cfg} {kw} {p.physics} {prec} n_elem={p.n_elem}", flush=True)
     a = 1.0 / p.dt
     opts = dict(krylov_tol=1e-13) if prec == "fp64" else dict(krylov_tol=1e-9, refine_tol=1e-12)
     s0 = _solver(p, prec, **opts)
@@ -226,11 +227,11 @@ def test_eight_wavefront_schedule_matches_default(cfg, kw, prec, tmp_path):
     s0.close()
     kf = 5 if p.uniform_k is None else p.uniform_k
     table = tmp_path / "tune8.txt"
-    table.write_text("".join(f"{dev} {PHYSICS[p.physics]} {k} {kf} {p.nrhs} {PRECISION[prec]} 3 1 1 1 1\n"
+    table.write_text("".join(f"{dev} {PHYSICS[p.physics]} {k} {kf} {p.nrhs} {PRECISION[prec]} {sched} 1 1 1 1 1\n"
                              for k in classes))
     s3 = _solver(p, prec, autotune_table=str(table), **opts)
     u3, lam3 = _stage(s3, a, f, lb)
-    assert s3.schedules() == {k: 3 for k in classes}, s3.schedules()
+    assert s3.schedules() == {k: sched for k in classes}, s3.schedules()
     u3b, _ = _stage(s3, a, f, lb)
     s3.close()
     assert _rel(u3, u0) <= 1e-13 and _rel(lam3, lam0) <= 1e-13, (_rel(u3, u0), _rel(lam3, lam0))
