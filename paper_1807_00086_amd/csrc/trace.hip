@@ -1248,6 +1248,88 @@ __global__ __launch_bounds__(64) void ssor_scale_kernel(int64_t nf, const int32_
     }
 }
 
+// The same blocks on the FP64 matrix cores, for the larger face blocks: one face per wavefront, its
+// six slots in turn, the products as 16x16x4 tiles.  With X(r, c) stored at X[c * BS + r]:
+//   U^T  = K_{F,s}^T R_F^{-T}   (rows j, columns a, sum over i),
+//   Kt^T = R_G^{-1} U^T        (rows b, columns a, sum over j),
+// and Kt(a, b) = Kt^T(b, a) is stored at b * BS + a.  Element v of accumulator tile (mt, nt) of U^T
+// is the B operand of k-step 4 mt + v of the second product, so U stays in registers.  Padding
+// rows and columns of the operands are zero (the clamped loads only keep the addresses in range).
+template <int BS>
+__global__ __launch_bounds__(256) void ssor_scale_mfma_kernel(int64_t nf, const int32_t* __restrict__ cols,
+                                                              const int32_t* __restrict__ dst,
+                                                              const double* __restrict__ bsr,
+                                                              const double* __restrict__ rinv,
+                                                              double* __restrict__ out) {
+    constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4;
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int64_t F = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (F >= nf) return;   // whole wavefronts
+    const double* RF = rinv + (size_t)F * BS * BS;
+    for (int s = 1; s < 7; ++s) {
+        const int32_t G = __builtin_amdgcn_readfirstlane(cols[F * 7 + s]);
+        if (G < 0) continue;
+        const int32_t D = __builtin_amdgcn_readfirstlane(dst[F * 6 + s - 1]);
+        if (D < 0) continue;
+        const double* K = bsr + ((size_t)F * 7 + s) * BS * BS;
+        const double* RG = rinv + (size_t)G * BS * BS;
+        mf64x4 u[MT][MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < MT; ++nt) u[mt][nt] = mf64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            const int i = 4 * kk + lg, ic = min(i, BS - 1);
+            double bv[MT];
+#pragma unroll
+            for (int nt = 0; nt < MT; ++nt) {
+                const int a = 16 * nt + lr;
+                const double t = RF[ic * BS + min(a, BS - 1)];
+                bv[nt] = (i < BS && a < BS) ? t : 0.0;
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int j = 16 * mt + lr;
+                const double t = K[min(j, BS - 1) * BS + ic];
+                const double av = j < BS ? t : 0.0;
+#pragma unroll
+                for (int nt = 0; nt < MT; ++nt)
+                    u[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[nt], u[mt][nt], 0, 0, 0);
+            }
+        }
+        mf64x4 kt[MT][MT];
+#pragma unroll
+        for (int mb = 0; mb < MT; ++mb)
+#pragma unroll
+            for (int na = 0; na < MT; ++na) kt[mb][na] = mf64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (16 * mt + 4 * v >= BS) continue;   // k-steps of padding rows of U^T only
+                const int jc = min(16 * mt + 4 * v + lg, BS - 1);
+#pragma unroll
+                for (int mb = 0; mb < MT; ++mb) {
+                    const double av = RG[jc * BS + min(16 * mb + lr, BS - 1)];
+#pragma unroll
+                    for (int na = 0; na < MT; ++na)
+                        kt[mb][na] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, u[mt][na][v], kt[mb][na], 0, 0, 0);
+                }
+            }
+        double* O = out + (size_t)D * BS * BS;
+#pragma unroll
+        for (int mb = 0; mb < MT; ++mb)
+#pragma unroll
+            for (int na = 0; na < MT; ++na)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int b = 16 * mb + lg + 4 * v, a = 16 * na + lr;
+                    if (b < BS && a < BS) O[b * BS + a] = kt[mb][na][v];
+                }
+    }
+}
+
 // One sweep of a colour on Kt (unit diagonal blocks): for every face F of colour c (faces of one
 // colour share no element, so they are independent), one thread per row a of the face:
 //   y_Fa = v_Fa [- t_Fa] - sum over the neighbours G of lower (forward) or higher (backward)
@@ -1610,8 +1692,13 @@ hipError_t ssor_prepare(hdg_ctx* c) {
         hipLaunchKernelGGL((chol_rinv_lds_kernel<BS>), dim3((unsigned)std::min<int64_t>(c->n_faces, 65536)),
                            dim3(64), 0, c->stream, c->n_faces, c->d_bsr, c->d_rinv);
     }
-    hipLaunchKernelGGL((ssor_scale_kernel<BS>), dim3((unsigned)((c->n_faces + 64 / BS - 1) / (64 / BS))), dim3(64),
-                       0, c->stream, c->n_faces, c->d_bsr_cols, c->d_ssdst, c->d_bsr, c->d_rinv, c->d_ssA);
+    if constexpr (BS >= 20)   // blocks of 20 and more: matrix cores, a face per wavefront
+        hipLaunchKernelGGL((ssor_scale_mfma_kernel<BS>), dim3((unsigned)((c->n_faces + 3) / 4)), dim3(256), 0,
+                           c->stream, c->n_faces, c->d_bsr_cols, c->d_ssdst, c->d_bsr, c->d_rinv, c->d_ssA);
+    else
+        hipLaunchKernelGGL((ssor_scale_kernel<BS>), dim3((unsigned)((c->n_faces + 64 / BS - 1) / (64 / BS))),
+                           dim3(64), 0, c->stream, c->n_faces, c->d_bsr_cols, c->d_ssdst, c->d_bsr, c->d_rinv,
+                           c->d_ssA);
     c->ss_version = c->mat_version;
     return hipGetLastError();
 }
