@@ -1149,46 +1149,45 @@ __global__ __launch_bounds__(NT) void chol_rinv_kernel(int64_t nf, const double*
 }
 
 // The same factor for larger blocks (whose register form would not fit): one wavefront per face,
-// the block in LDS (column-major), right-looking Cholesky, then the columns of R_F^{-1} by forward
-// substitution (one lane per column).
+// the block in LDS (column-major), right-looking Cholesky with lane r updating row r of the
+// trailing triangle, then lane cc forms column cc of R_F^{-1} in registers by forward
+// substitution, x_i = (delta_{i,cc} - sum_{j<i} R(i,j) x_j) / R(i,i): x_j = 0 for j < cc, so the
+// fully unrolled sums need no lane-dependent bounds and read R(i, j) as one broadcast per step.
 template <int BS>
 __global__ __launch_bounds__(64) void chol_rinv_lds_kernel(int64_t nf, const double* __restrict__ bsr,
                                                            double* __restrict__ rinv) {
     __shared__ double M[BS * BS];
-    __shared__ double V[BS * BS];
     const int lane = threadIdx.x;
     for (int64_t F = blockIdx.x; F < nf; F += gridDim.x) {
         const double* A = bsr + (size_t)F * 7 * BS * BS;
+        __syncthreads();   // the previous face's reads of M are done
         for (int i = lane; i < BS * BS; i += 64) M[i] = A[i];
         __syncthreads();
         for (int j = 0; j < BS; ++j) {
             const double d = sqrt(M[j * BS + j]);
             __syncthreads();
-            for (int r = j + lane; r < BS; r += 64) M[j * BS + r] = r == j ? d : M[j * BS + r] / d;
+            if (lane >= j && lane < BS) M[j * BS + lane] = lane == j ? d : M[j * BS + lane] / d;
             __syncthreads();
-            // trailing lower triangle: M(r, c) -= R(r, j) R(c, j) for j < c <= r
-            for (int idx = lane; idx < BS * BS; idx += 64) {
-                const int cc = idx / BS, r = idx - cc * BS;
-                if (cc > j && r >= cc) M[cc * BS + r] -= M[j * BS + r] * M[j * BS + cc];
+            // trailing lower triangle: M(r, c) -= R(r, j) R(c, j) for j < c <= r, r = lane
+            if (lane > j && lane < BS) {
+                const double lr = M[j * BS + lane];
+                for (int c = j + 1; c <= lane; ++c) M[c * BS + lane] -= lr * M[j * BS + c];
             }
             __syncthreads();
         }
-        for (int cc = lane; cc < BS; cc += 64) {
-            // R x = e_cc: x_i = 0 above the diagonal, then forward substitution
-            for (int i = 0; i < BS; ++i) {
-                double v = 0.0;
-                if (i >= cc) {
-                    v = i == cc ? 1.0 : 0.0;
-                    for (int j = cc; j < i; ++j) v -= M[j * BS + i] * V[cc * BS + j];
-                    v /= M[i * BS + i];
-                }
-                V[cc * BS + i] = v;
-            }
+        double x[BS];
+#pragma unroll
+        for (int i = 0; i < BS; ++i) {
+            double v = i == lane ? 1.0 : 0.0;
+#pragma unroll
+            for (int j = 0; j < i; ++j) v -= M[j * BS + i] * x[j];
+            x[i] = v / M[i * BS + i];
         }
-        __syncthreads();
-        double* out = rinv + (size_t)F * BS * BS;
-        for (int i = lane; i < BS * BS; i += 64) out[i] = V[i];
-        __syncthreads();
+        if (lane < BS) {
+            double* out = rinv + (size_t)F * BS * BS + (size_t)lane * BS;
+#pragma unroll
+            for (int i = 0; i < BS; ++i) out[i] = x[i];
+        }
     }
 }
 
