@@ -1528,22 +1528,51 @@ __global__ __launch_bounds__(256) void ssor_sweep32_kernel(int64_t p0, int64_t n
     }
 }
 
-// out = x + W^T t with R right-hand sides (thread per entry (F, a, r))
+// out = x + W^T t with 32 right-hand sides on the matrix cores: one face per wavefront,
+// (R_F^{-T} t_F)(a, r) = sum_b R_F^{-1}(b, a) t_F(b, r) as 16x16x4 FP64 tiles (the A operand reads
+// R_F^{-1} transposed, the B operands are 16 consecutive right-hand sides of a row of t)
 template <int BS>
-__global__ __launch_bounds__(NT) void rinvt_axpy_cols_kernel(int64_t nf, int R, const double* __restrict__ rinv,
-                                                             const double* __restrict__ x,
-                                                             const double* __restrict__ t, double* __restrict__ out) {
-    const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (gid >= nf * BS * R) return;
-    const int r = (int)(gid % R);
-    const int64_t Fa = gid / R, F = Fa / BS;
-    const int a = (int)(Fa % BS);
-    const double* Rc = rinv + (size_t)F * BS * BS + (size_t)a * BS;
-    const double* tv = t + (size_t)F * BS * R + r;
-    double acc = 0.0;
+__global__ __launch_bounds__(256) void rinvt_axpy32_kernel(int64_t nf, const double* __restrict__ rinv,
+                                                           const double* __restrict__ x,
+                                                           const double* __restrict__ t, double* __restrict__ out) {
+    constexpr int MT = (BS + 15) / 16, KS = (BS + 3) / 4, R = 32;
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    const int64_t F = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (F >= nf) return;   // whole wavefronts
+    const double* Rb = rinv + (size_t)F * BS * BS;
+    const double* tv = t + (size_t)F * BS * R;
+    mf64x4 acc[MT][2];
 #pragma unroll
-    for (int b = 0; b < BS; ++b) acc += Rc[b] * tv[(size_t)b * R];
-    out[gid] = x[gid] + acc;
+    for (int mt = 0; mt < MT; ++mt) acc[mt][0] = acc[mt][1] = mf64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+        const int b = min(4 * kk + lg, BS - 1);
+        const bool bok = 4 * kk + lg < BS;
+        double xb[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const double v = tv[b * R + 16 * nt + lr];
+            xb[nt] = bok ? v : 0.0;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const double av = Rb[min(16 * mt + lr, BS - 1) * BS + b];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, xb[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = 16 * mt + lg + 4 * v;
+                if (a >= BS) continue;
+                const size_t o = ((size_t)F * BS + a) * R + 16 * nt + lr;
+                out[o] = x[o] + acc[mt][nt][v];
+            }
 }
 
 // out = x + W^T t  (W^T = diag(R_F^{-T}): row a of R_F^{-T} is column a of R_F^{-1})
@@ -1727,8 +1756,11 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
     double* s_rr = c->d_scal + 96;
     HIPCHK_INT(ssor_prepare<BS>(c));
     auto wapply = [&](const double* in, double* out) {   // out = W in
-        hipLaunchKernelGGL((block_apply_fixed_kernel<BS>), dim3(nblk(nR)), dim3(NT), 0, c->stream, c->n_faces, R,
-                           c->d_rinv, in, out, (const int*)nullptr);
+        if constexpr (R == 32)   // the block-diagonal product of the 32-column CG (matrix cores)
+            launch_spmm32<BS, 1, double>(c, (const int32_t*)nullptr, c->d_rinv, in, out, nullptr);
+        else
+            hipLaunchKernelGGL((block_apply_fixed_kernel<BS>), dim3(nblk(nR)), dim3(NT), 0, c->stream, c->n_faces,
+                               R, c->d_rinv, in, out, (const int*)nullptr);
     };
     auto true_residual = [&](double* hres) -> int {   // x_try = x0 + W^T Uh^{-1} y into zz; |b - K x_try|^2
         ssor_sweep<BS, true, R>(c, yy, tt);
@@ -1736,8 +1768,8 @@ int cg_ssor(hdg_ctx* c, double* x, double tol, int* iters, double* relres) {
             hipLaunchKernelGGL((rinvt_axpy_kernel<BS>), dim3(nblk(n)), dim3(NT), 0, c->stream, c->n_faces, c->d_rinv,
                                x, tt, zz);
         else
-            hipLaunchKernelGGL((rinvt_axpy_cols_kernel<BS>), dim3(nblk(nR)), dim3(NT), 0, c->stream, c->n_faces, R,
-                               c->d_rinv, x, tt, zz);
+            hipLaunchKernelGGL((rinvt_axpy32_kernel<BS>), dim3((unsigned)((c->n_faces + 3) / 4)), dim3(256), 0,
+                               c->stream, c->n_faces, c->d_rinv, x, tt, zz);
         spmv(c, zz, qq);
         launch_lincomb(c, nR, 1.0, c->d_rhs, -1.0, qq, uu);
         dot(c, uu, uu, s_rr);
