@@ -1148,6 +1148,56 @@ __global__ __launch_bounds__(NT) void chol_rinv_kernel(int64_t nf, const double*
     }
 }
 
+// Broadcast of lane `src`'s value to the wavefront (src uniform)
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __hiloint2double(hi, lo);
+}
+
+// The same factor for blocks of 33..64 unknowns: one face per wavefront, lane a holding row a of
+// the block and then of R_F^{-1} as in chol_rinv_kernel, the pivot columns and finished rows
+// broadcast by readlane (the source lane is uniform) instead of shuffles.  Lanes past BS repeat
+// the last row; nothing reads or stores their values.
+template <int BS>
+__global__ __launch_bounds__(256) void chol_rinv_wave_kernel(int64_t nf, const double* __restrict__ bsr,
+                                                             double* __restrict__ rinv) {
+    static_assert(BS > 32 && BS <= 64, "one face per wavefront");
+    const int lane = threadIdx.x & 63, a = min(lane, BS - 1);
+    const int64_t F = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (F >= nf) return;   // whole wavefronts
+    const double* A = bsr + (size_t)F * 7 * BS * BS + a;
+    double m[BS];
+#pragma unroll
+    for (int b = 0; b < BS; ++b) m[b] = A[b * BS];
+    double ri = 0.0;
+#pragma unroll
+    for (int j = 0; j < BS; ++j) {
+        const double d = sqrt(lane_bcast(m[j], j));
+        const double rd = 1.0 / d;
+        const double l = a == j ? d : (a > j ? m[j] * rd : 0.0);
+        if (a == j) ri = rd;
+        m[j] = l;
+#pragma unroll
+        for (int cc = j + 1; cc < BS; ++cc) m[cc] -= l * lane_bcast(l, cc);
+    }
+    double y[BS];
+#pragma unroll
+    for (int b = 0; b < BS; ++b) y[b] = b == a ? ri : 0.0;
+#pragma unroll
+    for (int i = 0; i < BS; ++i) {
+        const double mi = a > i ? m[i] * ri : 0.0;
+#pragma unroll
+        for (int b = 0; b <= i; ++b) y[b] -= mi * lane_bcast(y[b], i);
+    }
+    if (lane < BS) {
+        double* out = rinv + (size_t)F * BS * BS + lane;
+#pragma unroll
+        for (int b = 0; b < BS; ++b) out[b * BS] = y[b];
+    }
+}
+
 // The same factor for larger blocks (whose register form would not fit): one wavefront per face,
 // the block in LDS (column-major), right-looking Cholesky with lane r updating row r of the
 // trailing triangle, then lane cc forms column cc of R_F^{-1} in registers by forward
@@ -1712,6 +1762,9 @@ hipError_t ssor_prepare(hdg_ctx* c) {
     if constexpr (BS <= 21) {
         constexpr int64_t FPB = (64 / BS) * (NT / 64);   // faces per workgroup of the factor kernel
         hipLaunchKernelGGL((chol_rinv_kernel<BS>), dim3((unsigned)((c->n_faces + FPB - 1) / FPB)), dim3(NT), 0,
+                           c->stream, c->n_faces, c->d_bsr, c->d_rinv);
+    } else if constexpr (BS > 32 && BS <= 64) {
+        hipLaunchKernelGGL((chol_rinv_wave_kernel<BS>), dim3((unsigned)((c->n_faces + 3) / 4)), dim3(256), 0,
                            c->stream, c->n_faces, c->d_bsr, c->d_rinv);
     } else {
         hipLaunchKernelGGL((chol_rinv_lds_kernel<BS>), dim3((unsigned)std::min<int64_t>(c->n_faces, 65536)),
