@@ -1198,7 +1198,7 @@ __global__ __launch_bounds__(256) void chol_rinv_wave_kernel(int64_t nf, const d
     }
 }
 
-// The same factor for larger blocks (whose register form would not fit): one wavefront per face,
+// The same factor for the other block sizes above 21 (22..32, or above 64): one wavefront per face,
 // the block in LDS (column-major), right-looking Cholesky with lane r updating row r of the
 // trailing triangle, then lane cc forms column cc of R_F^{-1} in registers by forward
 // substitution, x_i = (delta_{i,cc} - sum_{j<i} R(i,j) x_j) / R(i,i): x_j = 0 for j < cc, so the
