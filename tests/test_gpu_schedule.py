@@ -2,10 +2,11 @@
 the hipGraph that runs the degree classes of a variable-degree mesh as one launch.
 
 A schedule only moves element buffers between LDS and per-workgroup global scratch (and the
-reference tables between LDS and the caches), and the
-graph only changes how the class kernels are launched, so every variant must give the
-default's result (relative 1e-13 here; in practice bitwise) and stay within the oracle
-tolerances (FP64 1e-12, mixed FP32 + FP64 refinement 1e-10, relative L2 per field).
+reference tables between LDS and the caches) and sets how many wavefronts share an element's
+tile work (four or eight), and the graph only changes how the class kernels are launched, so
+every variant must give the default's result (relative 1e-13 here; in practice bitwise) and
+stay within the oracle tolerances (FP64 1e-12, mixed FP32 + FP64 refinement 1e-10, relative L2
+per field).
 """
 import numpy as np
 import pytest
