@@ -1305,7 +1305,7 @@ __global__ __launch_bounds__(64) void ssor_scale_kernel(int64_t nf, const int32_
 // is the B operand of k-step 4 mt + v of the second product, so U stays in registers.  Padding
 // rows and columns of the operands are zero (the clamped loads only keep the addresses in range).
 template <int BS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void ssor_scale_mfma_kernel(int64_t nf, const int32_t* __restrict__ cols,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BS > 32 ? 2 : 1))) void ssor_scale_mfma_kernel(int64_t nf, const int32_t* __restrict__ cols,
                                                               const int32_t* __restrict__ dst,
                                                               const double* __restrict__ bsr,
                                                               const double* __restrict__ rinv,
@@ -1347,31 +1347,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void s
                     u[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[nt], u[mt][nt], 0, 0, 0);
             }
         }
-        // one row tile of Kt^T at a time (fewer live accumulators: two wavefronts per SIMD)
+        // MB row tiles of Kt^T at a time: all of them for two tile rows (more independent MFMA
+        // chains), one for three (fewer live accumulators: two wavefronts per SIMD)
+        constexpr int MB = MT <= 2 ? MT : 1;
         double* O = out + (size_t)D * BS * BS;
 #pragma unroll
-        for (int mb = 0; mb < MT; ++mb) {
-            mf64x4 kt[MT];
+        for (int m0 = 0; m0 < MT; m0 += MB) {
+            mf64x4 kt[MB][MT];
 #pragma unroll
-            for (int na = 0; na < MT; ++na) kt[na] = mf64x4{0.0, 0.0, 0.0, 0.0};
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int na = 0; na < MT; ++na) kt[mb][na] = mf64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     if (16 * mt + 4 * v >= BS) continue;   // k-steps of padding rows of U^T only
                     const int jc = min(16 * mt + 4 * v + lg, BS - 1);
-                    const double av = RG[jc * BS + min(16 * mb + lr, BS - 1)];
 #pragma unroll
-                    for (int na = 0; na < MT; ++na)
-                        kt[na] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, u[mt][na][v], kt[na], 0, 0, 0);
+                    for (int mb = 0; mb < MB; ++mb) {
+                        const double av = RG[jc * BS + min(16 * (m0 + mb) + lr, BS - 1)];
+#pragma unroll
+                        for (int na = 0; na < MT; ++na)
+                            kt[mb][na] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, u[mt][na][v], kt[mb][na], 0, 0, 0);
+                    }
                 }
 #pragma unroll
-            for (int na = 0; na < MT; ++na)
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int b = 16 * mb + lg + 4 * v, a = 16 * na + lr;
-                    if (b < BS && a < BS) O[b * BS + a] = kt[na][v];
-                }
+                for (int na = 0; na < MT; ++na)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int b = 16 * (m0 + mb) + lg + 4 * v, a = 16 * na + lr;
+                        if (b < BS && a < BS) O[b * BS + a] = kt[mb][na][v];
+                    }
         }
     }
 }
