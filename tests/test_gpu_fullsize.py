@@ -96,18 +96,21 @@ def _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, tmap, n_elem_sample, n_
         assert np.abs(acc).max() <= 1e-10 * scale, int(F)
 
 
+@pytest.mark.parametrize("precond", ["jacobi", "ssor"])
 @pytest.mark.parametrize("cfg", [3, 5])
-def test_full_size_uniform_sampled(cfg):
-    """Elastic k = 4 (24,576 tets) and Maxwell k = 3 (196,608 tets), FP64 and mixed."""
+def test_full_size_uniform_sampled(cfg, precond):
+    """Elastic k = 4 (24,576 tets) and Maxwell k = 3 (196,608 tets), FP64 and mixed, with either
+    trace preconditioner (the benchmark runs these workloads with block SSOR and the autotuned
+    launch schedules)."""
     _need_gpu()
     from oracle import hdg as ohdg
     _T0[0] = time.time()
     p = make_problem(cfg)
-    print(f"case fullsize cfg={cfg} n_elem={p.n_elem}", flush=True)
+    print(f"case fullsize cfg={cfg} precond={precond} n_elem={p.n_elem}", flush=True)
     d = ohdg.make_discretisation(p)
     a = 1.0 / (GAMMA * p.dt)
     _step("oracle discretisation built")
-    s = _solver(p, "fp64", krylov_tol=1e-12, krylov_maxit=4000)
+    s = _solver(p, "fp64", krylov_tol=1e-12, krylov_maxit=4000, precond=precond)
     nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
     assert nl == d.loc_off[-1] and nt == d.tr_off[-1]
     f = random_vector(nl, cfg, 11)[:, None]
@@ -127,7 +130,7 @@ def test_full_size_uniform_sampled(cfg):
     _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, np.arange(nt), 60, 40, cfg)
 
     # mixed precision at equal error: within 1e-10 of the FP64 path, per field
-    sm = _solver(p, "mixed_fp32", krylov_tol=1e-12, krylov_maxit=4000, refine_tol=1e-11)
+    sm = _solver(p, "mixed_fp32", krylov_tol=1e-12, krylov_maxit=4000, refine_tol=1e-11, precond=precond)
     um, lamm, _ = _stage(sm, a, f, lb)
     _step(f"mixed stage done ({sm.query('last_refine')} refinement passes)")
     sm.close()
@@ -148,8 +151,9 @@ def test_full_size_uniform_sampled(cfg):
 
 def test_full_size_pvar_sampled():
     """p-heterogeneous acoustics (200,000 tets, k_e in 1..5, 32 point-source right-hand sides),
-    FP64 with the degree classes as one graph."""
+    FP64 with the degree classes as one graph and the benchmark's trace preconditioner."""
     _need_gpu()
+    import bench
     from oracle import hdg as ohdg
     _T0[0] = time.time()
     p = make_problem(4)
@@ -157,7 +161,7 @@ def test_full_size_pvar_sampled():
     d = ohdg.make_discretisation(p)
     a = 1.0 / p.dt
     _step("oracle discretisation built")
-    s = _solver(p, "fp64", krylov_tol=1e-12, krylov_maxit=4000)
+    s = _solver(p, "fp64", krylov_tol=1e-12, krylov_maxit=4000, precond=bench.STAGE_PRECOND)
     nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
     assert nl == d.loc_off[-1] and nt == d.skel.n_faces * BS_VAR
     f = s.point_sources(p.sources)
@@ -243,6 +247,7 @@ def test_full_size_pvar_mixed_sampled():
     precision with the degree classes as one graph: per-column residuals at or below refine_tol
     and the local and trace equations of the source elements against the oracle."""
     _need_gpu()
+    import bench
     from oracle import hdg as ohdg
     _T0[0] = time.time()
     p = make_problem(4)
@@ -250,7 +255,8 @@ def test_full_size_pvar_mixed_sampled():
     d = ohdg.make_discretisation(p)
     a = 1.0 / p.dt
     tol_res = 1e-12
-    s = _solver(p, "mixed_fp32", krylov_tol=1e-10, krylov_maxit=4000, refine_tol=tol_res)
+    s = _solver(p, "mixed_fp32", krylov_tol=1e-10, krylov_maxit=4000, refine_tol=tol_res,
+                precond=bench.STAGE_PRECOND)
     nt = s.query("n_trace_dofs")
     f = s.point_sources(p.sources)
     lb = np.zeros((nt, p.nrhs))
@@ -280,11 +286,12 @@ def test_full_size_elastic_bf16_equals_fp64():
     refinement: within 1e-10 of the FP64 path per field (the FP64 path is checked against the
     oracle above), residual at or below refine_tol."""
     _need_gpu()
+    import bench
     _T0[0] = time.time()
     p = make_problem(3)
     print(f"case fullsize elastic bf16 n_elem={p.n_elem}", flush=True)
     a = 1.0 / (GAMMA * p.dt)
-    s = _solver(p, "fp64", krylov_tol=1e-12, krylov_maxit=4000)
+    s = _solver(p, "fp64", krylov_tol=1e-12, krylov_maxit=4000, precond=bench.STAGE_PRECOND)
     nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
     f = random_vector(nl, 3, 11)[:, None]
     from oracle import hdg as ohdg
@@ -292,7 +299,8 @@ def test_full_size_elastic_bf16_equals_fp64():
     lb = (random_vector(nt, 3, 12) * ohdg.boundary_trace_mask(d))[:, None]
     u, lam, _ = _stage(s, a, f, lb)
     s.close()
-    sb = _solver(p, "mixed_bf16", krylov_tol=1e-12, krylov_maxit=4000, refine_tol=1e-11)
+    sb = _solver(p, "mixed_bf16", krylov_tol=1e-12, krylov_maxit=4000, refine_tol=1e-11,
+                 precond=bench.STAGE_PRECOND)
     ub, lamb, _ = _stage(sb, a, f, lb)
     res = sb.last_residual()
     _step(f"bf16 stage done ({sb.query('last_refine')} corrections, residual {res[0]:.2e})")
