@@ -96,17 +96,20 @@ def _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, tmap, n_elem_sample, n_
         assert np.abs(acc).max() <= 1e-10 * scale, int(F)
 
 
-@pytest.mark.parametrize("precond", ["jacobi", "ssor"])
-@pytest.mark.parametrize("cfg", [3, 5])
+@pytest.mark.parametrize("cfg,precond", [(3, "jacobi"), (3, "ssor"), (5, "jacobi"), (5, "ssor"), ("glm", "ssor")])
 def test_full_size_uniform_sampled(cfg, precond):
-    """Elastic k = 4 (24,576 tets) and Maxwell k = 3 (196,608 tets), FP64 and mixed, with either
-    trace preconditioner (the benchmark runs these workloads with block SSOR and the autotuned
-    launch schedules)."""
+    """Elastic k = 4 (24,576 tets), Maxwell and GLM-Maxwell k = 3 (196,608 tets), FP64 and
+    mixed, with either trace preconditioner (the benchmark runs these workloads with block SSOR
+    and the autotuned launch schedules)."""
     _need_gpu()
     from oracle import hdg as ohdg
     _T0[0] = time.time()
+    glm = cfg == "glm"
+    cfg = 5 if glm else cfg
     p = make_problem(cfg)
-    print(f"case fullsize cfg={cfg} precond={precond} n_elem={p.n_elem}", flush=True)
+    if glm:
+        p.physics = "maxwell_glm"
+    print(f"case fullsize cfg={cfg} {p.physics} precond={precond} n_elem={p.n_elem}", flush=True)
     d = ohdg.make_discretisation(p)
     a = 1.0 / (GAMMA * p.dt)
     _step("oracle discretisation built")
@@ -136,7 +139,8 @@ def test_full_size_uniform_sampled(cfg, precond):
     sm.close()
     # relative L2(Omega) error per field: with the orthonormal basis and affine elements the
     # |J|-weighted coefficient 2-norm (the oracle's l2_norm_fields, vectorised over elements)
-    groups = {"elastic": [list(range(6)), [6, 7, 8]], "maxwell": [[0, 1, 2], [3, 4, 5]]}[d.physics]
+    groups = {"elastic": [list(range(6)), [6, 7, 8]], "maxwell": [[0, 1, 2], [3, 4, 5]],
+              "maxwell_glm": [[0, 1, 2], [3, 4, 5], [6]]}[d.physics]
     X = p.xyz[p.elem_vert]
     dj = np.abs(np.linalg.det(np.transpose(X[:, 1:, :] - X[:, :1, :], (0, 2, 1))))[:, None, None]
     m = len(sum(groups, []))
@@ -281,22 +285,27 @@ def test_full_size_pvar_mixed_sampled():
     _check_local_and_trace(ohdg, d, p, a, u, lam, f, lb, tmap, 0, 0, 4, faces=faces, elems=[])
 
 
-def test_full_size_elastic_bf16_equals_fp64():
-    """Elastic k = 4 at full size (24,576 tets) with split-BF16 condensation products and FP64
-    refinement: within 1e-10 of the FP64 path per field (the FP64 path is checked against the
-    oracle above), residual at or below refine_tol."""
+@pytest.mark.parametrize("cfg", [3, 5, "glm"])
+def test_full_size_bf16_equals_fp64(cfg):
+    """Elastic k = 4 (24,576 tets), Maxwell and GLM-Maxwell k = 3 (196,608 tets) at full size with
+    split-BF16 condensation products and FP64 refinement: within 1e-10 of the FP64 path per field
+    (the FP64 path is checked against the oracle above), residual at or below refine_tol."""
     _need_gpu()
     import bench
     _T0[0] = time.time()
-    p = make_problem(3)
-    print(f"case fullsize elastic bf16 n_elem={p.n_elem}", flush=True)
+    glm = cfg == "glm"
+    cfg = 5 if glm else cfg
+    p = make_problem(cfg)
+    if glm:
+        p.physics = "maxwell_glm"
+    print(f"case fullsize bf16 cfg={cfg} {p.physics} n_elem={p.n_elem}", flush=True)
     a = 1.0 / (GAMMA * p.dt)
     s = _solver(p, "fp64", krylov_tol=1e-12, krylov_maxit=4000, precond=bench.STAGE_PRECOND)
     nl, nt = s.query("n_local_dofs"), s.query("n_trace_dofs")
-    f = random_vector(nl, 3, 11)[:, None]
+    f = random_vector(nl, cfg, 11)[:, None]
     from oracle import hdg as ohdg
     d = ohdg.make_discretisation(p)
-    lb = (random_vector(nt, 3, 12) * ohdg.boundary_trace_mask(d))[:, None]
+    lb = (random_vector(nt, cfg, 12) * ohdg.boundary_trace_mask(d))[:, None]
     u, lam, _ = _stage(s, a, f, lb)
     s.close()
     sb = _solver(p, "mixed_bf16", krylov_tol=1e-12, krylov_maxit=4000, refine_tol=1e-11,
@@ -306,10 +315,13 @@ def test_full_size_elastic_bf16_equals_fp64():
     _step(f"bf16 stage done ({sb.query('last_refine')} corrections, residual {res[0]:.2e})")
     sb.close()
     assert np.all(res <= 1e-11)
+    groups = {"elastic": [list(range(6)), [6, 7, 8]], "maxwell": [[0, 1, 2], [3, 4, 5]],
+              "maxwell_glm": [[0, 1, 2], [3, 4, 5], [6]]}[p.physics]
+    m = len(sum(groups, []))
     X = p.xyz[p.elem_vert]
     dj = np.abs(np.linalg.det(np.transpose(X[:, 1:, :] - X[:, :1, :], (0, 2, 1))))[:, None, None]
-    uf, ubf = u[:, 0].reshape(p.n_elem, 9, -1), ub[:, 0].reshape(p.n_elem, 9, -1)
-    for g in (list(range(6)), [6, 7, 8]):
+    uf, ubf = u[:, 0].reshape(p.n_elem, m, -1), ub[:, 0].reshape(p.n_elem, m, -1)
+    for g in groups:
         num = np.sqrt(np.sum(dj * (ubf[:, g] - uf[:, g]) ** 2))
         den = np.sqrt(np.sum(dj * uf[:, g] ** 2))
         assert num <= 1e-10 * den, (g, num / den)
