@@ -556,8 +556,8 @@ def main():
         print(json.dumps({"calibration_copy_bytes_read": 8 * n, "calibration_copy_bytes_written": 8 * n}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only (the element kernels shard by "
-                                   "element partition; nothing here uses a second GPU)",
+        print(json.dumps({"error": "the benchmark runs on one GPU only: the library has no multi-GPU "
+                                   "path (the element kernels would shard by element partition)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
